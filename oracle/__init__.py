@@ -1,0 +1,279 @@
+"""covox reference checker -- TEST INFRASTRUCTURE ONLY.
+
+A thin ctypes wrapper around ``covox_oracle.c``: a plain, slow CPU
+implementation of projective TSDF integration, the exact truncated ESDF and
+the correspondence-free ESDF alignment (Hoss and De Cristoforis, coVoxSLAM,
+arXiv 2410.21149: Sec. III-C, III-D, III-E, III-F, Eq. 1).  Only the tests,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` use it;
+the GPU library never imports or links it, and it imports nothing from the
+GPU library.
+
+Build flags: gcc -O2 -ffp-contract=off (no FMA contraction, no fast-math), so
+that the binary32 mode follows the pinned operation order.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "covox_oracle.c")
+_LIB = os.path.join(_HERE, "_covox_oracle.so")
+_lib = None
+
+OK, EINVAL, EDEGENERATE, NOT_CONVERGED = 0, -1, -5, 1
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("vs", ctypes.c_double), ("trunc_vox", ctypes.c_int), ("max_range", ctypes.c_double),
+                ("d_max", ctypes.c_double), ("w_reg", ctypes.c_double), ("fp64", ctypes.c_int),
+                ("fp16", ctypes.c_int), ("max_iter", ctypes.c_int), ("n_min", ctypes.c_int)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        L.orc_submap_create.restype = _vp
+        L.orc_submap_create.argtypes = [ctypes.POINTER(_Params), _dp]
+        L.orc_submap_destroy.restype = None
+        L.orc_submap_destroy.argtypes = [_vp]
+        L.orc_integrate.restype = ctypes.c_int
+        L.orc_integrate.argtypes = [_vp, _fp, ctypes.c_int, ctypes.c_int, _fp, _dp, _i64p]
+        L.orc_update_esdf.restype = ctypes.c_int
+        L.orc_update_esdf.argtypes = [_vp]
+        L.orc_n_blocks.restype = ctypes.c_int64
+        L.orc_n_blocks.argtypes = [_vp]
+        L.orc_export.restype = None
+        L.orc_export.argtypes = [_vp, _u64p, _dp, _dp, _dp, _i32p]
+        L.orc_import.restype = ctypes.c_int
+        L.orc_import.argtypes = [_vp, ctypes.c_int64, _u64p, _dp, _dp]
+        L.orc_iso_points.restype = ctypes.c_int64
+        L.orc_iso_points.argtypes = [_vp, _vp, ctypes.c_int64]
+        L.orc_normal_eq.restype = None
+        L.orc_normal_eq.argtypes = [_vp, _vp, ctypes.c_int64, _dp, _dp]
+        L.orc_align_points.restype = ctypes.c_int
+        L.orc_align_points.argtypes = [_vp, _vp, ctypes.c_int64, _dp, _dp, _dp, _i64p]
+        L.orc_align_multistart.restype = ctypes.c_int
+        L.orc_align_multistart.argtypes = [_vp, _vp, ctypes.c_int64, _dp, ctypes.c_int, _dp, _dp, _i64p,
+                                           ctypes.POINTER(ctypes.c_int), _dp]
+        L.orc_se3_exp.restype = None
+        L.orc_se3_exp.argtypes = [_dp, _dp]
+        L.orc_solve6.restype = ctypes.c_int
+        L.orc_solve6.argtypes = [_dp, _dp]
+        L.orc_mix64.restype = ctypes.c_uint64
+        L.orc_mix64.argtypes = [ctypes.c_uint64]
+        L.orc_f2h.restype = ctypes.c_uint16
+        L.orc_f2h.argtypes = [ctypes.c_float]
+        L.orc_h2f.restype = ctypes.c_float
+        L.orc_h2f.argtypes = [ctypes.c_uint16]
+        L.orc_pose_cam_sub.restype = None
+        L.orc_pose_cam_sub.argtypes = [_dp, _dp, _dp]
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _mat(T):
+    return np.ascontiguousarray(np.asarray(T, np.float64).reshape(16))
+
+
+class Params:
+    """Map and solver parameters (metres)."""
+
+    def __init__(self, vs=0.05, trunc_vox=4, max_range=5.0, d_max=2.0, w_reg=2.0, fp64=False, fp16=False,
+                 max_iter=30, n_min=100):
+        self.vs, self.trunc_vox, self.max_range, self.d_max = vs, trunc_vox, max_range, d_max
+        self.w_reg, self.fp64, self.fp16, self.max_iter, self.n_min = w_reg, fp64, fp16, max_iter, n_min
+
+    def _c(self):
+        return _Params(self.vs, self.trunc_vox, self.max_range, self.d_max, self.w_reg, int(self.fp64),
+                       int(self.fp16), self.max_iter, self.n_min)
+
+
+class Submap:
+    """A submap of 8^3-voxel blocks with TSDF (D, W) and ESDF (phi) state."""
+
+    def __init__(self, params: Params, T_world_submap=None):
+        self.params = params
+        L = _load()
+        T = _mat(np.eye(4) if T_world_submap is None else T_world_submap)
+        self._cp = params._c()
+        self._h = L.orc_submap_create(ctypes.byref(self._cp), _p(T, _dp))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orc_submap_destroy(h)
+            self._h = None
+
+    @property
+    def n_blocks(self) -> int:
+        return int(_load().orc_n_blocks(self._h))
+
+    def integrate(self, depth, K, T_world_cam):
+        d = np.ascontiguousarray(depth, np.float32)
+        k = np.ascontiguousarray(K, np.float32)
+        st = np.zeros(3, np.int64)
+        rc = _load().orc_integrate(self._h, _p(d, _fp), d.shape[0], d.shape[1], _p(k, _fp),
+                                   _p(_mat(T_world_cam), _dp), _p(st, _i64p))
+        if rc != OK:
+            raise ValueError("oracle integrate: status %d" % rc)
+        return {"n_new": int(st[0]), "n_touched": int(st[1]), "n_valid": int(st[2])}
+
+    def update_esdf(self):
+        _load().orc_update_esdf(self._h)
+
+    def export(self) -> dict:
+        n = self.n_blocks
+        keys = np.zeros(n, np.uint64)
+        D = np.zeros(n * 512, np.float64)
+        W = np.zeros(n * 512, np.float64)
+        phi = np.zeros(n * 512, np.float64)
+        ksq = np.zeros(n * 512, np.int32)
+        _load().orc_export(self._h, _p(keys, _u64p), _p(D, _dp), _p(W, _dp), _p(phi, _dp), _p(ksq, _i32p))
+        return {"keys": keys, "D": D.reshape(n, 512), "W": W.reshape(n, 512),
+                "phi": phi.reshape(n, 512), "ksq": ksq.reshape(n, 512)}
+
+    def import_blocks(self, keys, D, W):
+        keys = np.ascontiguousarray(keys, np.uint64)
+        D = np.ascontiguousarray(D, np.float64).reshape(-1)
+        W = np.ascontiguousarray(W, np.float64).reshape(-1)
+        _load().orc_import(self._h, len(keys), _p(keys, _u64p), _p(D, _dp), _p(W, _dp))
+
+    def iso_points(self) -> np.ndarray:
+        L = _load()
+        n = int(L.orc_iso_points(self._h, None, 0))
+        dt = np.float64 if self.params.fp64 else np.float32
+        out = np.zeros((max(n, 1), 3), dt)
+        L.orc_iso_points(self._h, out.ctypes.data_as(_vp), n)
+        return out[:n]
+
+
+def _pts(A: Submap, pts):
+    dt = np.float64 if A.params.fp64 else np.float32
+    return np.ascontiguousarray(np.asarray(pts, dt).reshape(-1, 3))
+
+
+def normal_eq(A: Submap, pts, T):
+    """(H 6x6, b 6, c, n) at pose T (points of B in B coordinates)."""
+    p = _pts(A, pts)
+    out = np.zeros(29)
+    _load().orc_normal_eq(A._h, p.ctypes.data_as(_vp), len(p), _p(_mat(T), _dp), _p(out, _dp))
+    H = np.zeros((6, 6))
+    m = 0
+    for a in range(6):
+        for b in range(a, 6):
+            H[a, b] = H[b, a] = out[m]
+            m += 1
+    return H, out[21:27].copy(), float(out[27]), int(out[28]), out
+
+
+def align(A: Submap, pts, T_init):
+    p = _pts(A, pts)
+    T = np.zeros(16)
+    cost = np.zeros(1)
+    info = np.zeros(2, np.int64)
+    st = _load().orc_align_points(A._h, p.ctypes.data_as(_vp), len(p), _p(_mat(T_init), _dp), _p(T, _dp),
+                                  _p(cost, _dp), _p(info, _i64p))
+    return {"T": T.reshape(4, 4), "cost": float(cost[0]), "status": int(st), "iters": int(info[0]),
+            "n": int(info[1])}
+
+
+def align_multistart(A: Submap, pts, T_init, n_starts=8):
+    p = _pts(A, pts)
+    T = np.zeros(16)
+    cost = np.zeros(1)
+    info = np.zeros(2, np.int64)
+    best = ctypes.c_int(-1)
+    starts = np.zeros(16 * n_starts)
+    st = _load().orc_align_multistart(A._h, p.ctypes.data_as(_vp), len(p), _p(_mat(T_init), _dp), n_starts,
+                                      _p(T, _dp), _p(cost, _dp), _p(info, _i64p), ctypes.byref(best),
+                                      _p(starts, _dp))
+    return {"T": T.reshape(4, 4), "cost": float(cost[0]), "status": int(st), "iters": int(info[0]),
+            "n": int(info[1]), "best": best.value, "starts": starts.reshape(n_starts, 4, 4)}
+
+
+def se3_exp(xi) -> np.ndarray:
+    x = np.ascontiguousarray(xi, np.float64)
+    E = np.zeros(16)
+    _load().orc_se3_exp(_p(x, _dp), _p(E, _dp))
+    return E.reshape(4, 4)
+
+
+def solve6(ne29):
+    ne = np.ascontiguousarray(ne29, np.float64)
+    x = np.zeros(6)
+    rc = _load().orc_solve6(_p(ne, _dp), _p(x, _dp))
+    return (x if rc == 0 else None)
+
+
+def mix64(k: int) -> int:
+    return int(_load().orc_mix64(ctypes.c_uint64(k & 0xFFFFFFFFFFFFFFFF)))
+
+
+def f2h(x: float) -> int:
+    return int(_load().orc_f2h(ctypes.c_float(x)))
+
+
+def h2f(h: int) -> float:
+    return float(_load().orc_h2f(ctypes.c_uint16(h)))
+
+
+def pose_cam_sub(T_world_cam, T_world_sub) -> np.ndarray:
+    out = np.zeros(16)
+    _load().orc_pose_cam_sub(_p(_mat(T_world_cam), _dp), _p(_mat(T_world_sub), _dp), _p(out, _dp))
+    return out.reshape(4, 4)
+
+
+def pack_key(bx, by, bz) -> np.ndarray:
+    """Packed block key ((bx + 2^20) << 42) | ((by + 2^20) << 21) | (bz + 2^20)."""
+    off = np.int64(1 << 20)
+    bx, by, bz = (np.asarray(v, np.int64) + off for v in (bx, by, bz))
+    return ((bx.astype(np.uint64) << np.uint64(42)) | (by.astype(np.uint64) << np.uint64(21))
+            | bz.astype(np.uint64))
+
+
+def unpack_key(k) -> np.ndarray:
+    k = np.asarray(k, np.uint64)
+    m = np.uint64(0x1FFFFF)
+    off = 1 << 20
+    return np.stack([((k >> np.uint64(42)) & m).astype(np.int64) - off,
+                     ((k >> np.uint64(21)) & m).astype(np.int64) - off,
+                     (k & m).astype(np.int64) - off], axis=-1)
+
+
+def voxel_coords(keys) -> np.ndarray:
+    """(n, 512, 3) integer voxel indices of every voxel of the given blocks."""
+    b = unpack_key(keys)
+    l = np.arange(512)
+    off = np.stack([l & 7, (l >> 3) & 7, l >> 6], axis=1)
+    return 8 * b[:, None, :] + off[None, :, :]
+
+
+def home_bucket(keys, table_cap: int) -> np.ndarray:
+    return np.array([mix64(int(k)) & (table_cap - 1) for k in np.asarray(keys, np.uint64)], np.int64)
