@@ -1,0 +1,260 @@
+/*
+ * covox -- projective TSDF integration, exact ESDF and correspondence-free
+ * ESDF submap alignment on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Hoss and De Cristoforis, "coVoxSLAM: GPU accelerated globally
+ * consistent dense SLAM" (arXiv 2410.21149).  The map is a collection of
+ * submaps; each submap is a sparse set of 8^3-voxel blocks indexed through an
+ * open-addressing hash table whose "activate" step hands out buffer indices
+ * (Sec. III-B, III-C).  Depth frames are fused by projection mapping
+ * (Sec. III-C), the ESDF is derived from the TSDF (Sec. I, III-E), and two
+ * submaps are aligned by the correspondence-free ESDF registration term of
+ * Eq. (1) (Sec. III-F).
+ *
+ * Conventions
+ *   - Lengths in metres.  Poses are 4x4 row-major binary64 matrices
+ *     [R t; 0 0 0 1]; T_a_b maps coordinates in frame b to frame a.
+ *   - Cameras: pinhole, x right, y down, z forward; K = {fx, fy, cx, cy};
+ *     integer pixel coordinates are pixel centres; a depth image stores the
+ *     z coordinate, 0 (or any value outside (0, max_range]) = no measurement.
+ *   - Voxel i (int32 x3) of a submap has centre (i + 0.5) * voxel_size in the
+ *     submap frame; block b = i >> 3; in-block index l = (x&7) + 8(y&7) +
+ *     64(z&7); packed block key ((bx+2^20)<<42) | ((by+2^20)<<21) | (bz+2^20).
+ *   - Device pointers are HIP device (or managed) memory on the current
+ *     device; host pointers are ordinary host memory.  The library never frees
+ *     caller memory.
+ *
+ * Threading and streams: a context is used by one host thread at a time.  All
+ * device work of a context is enqueued on the stream given to
+ * covox_set_stream (default: the null stream).  Calls marked "asynchronous"
+ * return before the device work finishes; callers keep their device inputs
+ * alive until the stream has passed the work.
+ *
+ * Errors: every call returns a status code (below).  On an error the call
+ * leaves the submap unchanged unless stated otherwise; covox_last_error()
+ * returns a message for the last failing call of a context.
+ */
+#ifndef COVOX_H
+#define COVOX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define COVOX_OK 0
+#define COVOX_EINVAL (-1)        /* bad argument: null pointer, size, non-rigid pose, K */
+#define COVOX_EPOOL_FULL (-2)    /* block capacity of the submap would be exceeded */
+#define COVOX_ETABLE_FULL (-3)   /* hash-table load would exceed 85 % */
+#define COVOX_EHIP (-4)          /* HIP runtime error (message kept) */
+#define COVOX_EDEGENERATE (-5)   /* alignment: fewer than n_min residuals or H not PD */
+#define COVOX_NOT_CONVERGED 1    /* alignment: iteration cap reached (result valid) */
+
+/* Storage precision of the TSDF distance D and weight W. */
+#define COVOX_FP32 0
+#define COVOX_FP16 1 /* binary16 storage, binary32 arithmetic */
+
+typedef struct covox_ctx covox_ctx;
+typedef struct covox_submap covox_submap;
+
+typedef struct {
+    double voxel_size;       /* voxel edge (m), e.g. 0.05 */
+    int32_t trunc_vox;       /* truncation distance tau in voxels (tau = trunc_vox * voxel_size) */
+    double max_range;        /* depth values above this are ignored (m) */
+    double d_max;            /* ESDF range (m); R = round(d_max / voxel_size) <= 56 */
+    double w_reg;            /* minimum weight of both endpoints of a registration edge */
+    int64_t block_capacity;  /* blocks per submap (pre-allocated, Sec. III-D) */
+    int32_t precision;       /* COVOX_FP32 or COVOX_FP16 */
+    int32_t max_iter;        /* Gauss-Newton iteration cap */
+    int32_t n_min;           /* minimum number of residuals for a solve */
+    double tol_rho;          /* stop when |delta_rho| < tol_rho (m) ... */
+    double tol_theta;        /* ... and |delta_theta| < tol_theta (rad) */
+} covox_params;
+
+/* Fills p with the defaults: 0.05 m voxels, tau = 4 voxels, 5 m range, 2 m
+ * ESDF, w_reg = 2, 65536 blocks, FP32, 30 iterations, n_min = 100,
+ * tolerances 1e-7 m and 1e-8 rad. */
+void covox_default_params(covox_params *p);
+
+/* Creates a context on the current HIP device.  *out receives the handle.
+ * Returns EINVAL for an invalid parameter set, EHIP on a runtime failure. */
+int covox_create(covox_ctx **out, const covox_params *p);
+void covox_destroy(covox_ctx *ctx);
+
+/* All later device work of ctx goes to `hip_stream` (a hipStream_t). */
+int covox_set_stream(covox_ctx *ctx, void *hip_stream);
+
+/* Blocks until all work of ctx has finished.  Returns EHIP on a device
+ * error and reports a sticky capacity error of an earlier asynchronous
+ * integration as EPOOL_FULL / ETABLE_FULL (once). */
+int covox_sync(covox_ctx *ctx);
+
+/* Human-readable status name; never NULL. */
+const char *covox_status_string(int status);
+/* Message of the last failing call of ctx ("" if none); owned by ctx. */
+const char *covox_last_error(const covox_ctx *ctx);
+
+/* ---------------------------------------------------------------- submaps */
+
+/* A submap with pose T_world_submap (16 binary64, host).  Pre-allocates
+ * block_capacity blocks and a hash table of the next power of two >= 2 x
+ * block_capacity slots (load <= 50 %, Sec. IV hash-table discussion). */
+int covox_submap_create(covox_ctx *ctx, const double T_world_submap[16], covox_submap **out);
+void covox_submap_destroy(covox_submap *s);
+/* Empties a submap (no blocks), asynchronously. */
+int covox_submap_reset(covox_ctx *ctx, covox_submap *s);
+
+/*
+ * Fuses one depth frame into submap s by projection mapping (Sec. III-C;
+ * count / allocate / update of Sec. III-D):
+ *   T_cam_submap = T_world_cam^-1 T_world_submap in binary64, rounded once
+ *   to binary32; voxel i is valid when its centre projects in front of the
+ *   camera onto a pixel (nearest, floor(u + 0.5)) whose depth d lies in
+ *   (0, max_range] and sdf = d - z >= -tau; blocks holding a valid voxel
+ *   and not yet allocated get buffer indices n_blocks + rank in ascending
+ *   packed-key order; every valid voxel takes t = min(sdf, tau),
+ *   W' = W + 1, D' = (D W + t) / W' (binary32, no FMA contraction).
+ * depth_dev: device, H x W binary32, row-major, metres.  K: host, 4 floats.
+ * T_world_cam: host, 16 doubles.  Asynchronous.  On EPOOL_FULL / ETABLE_FULL
+ * the frame is dropped and the submap is unchanged; the condition is
+ * reported by this call when the library cannot rule it out beforehand,
+ * otherwise by the next covox_sync.
+ */
+int covox_integrate_depth(covox_ctx *ctx, covox_submap *s, const float *depth_dev, int32_t H,
+                          int32_t W, const float K[4], const double T_world_cam[16]);
+
+/* F frames in order: depths_dev is F x H x W (device), T_world_cam is F x 16
+ * doubles (host).  Identical results to F sequential calls. */
+int covox_integrate_depth_batch(covox_ctx *ctx, covox_submap *s, const float *depths_dev, int32_t F,
+                                int32_t H, int32_t W, const float K[4], const double *T_world_cam);
+
+/*
+ * Recomputes the ESDF phi of submap s (Sec. I, III-E): with Obs = {W > 0},
+ * Band = Obs and |D| < tau, Sites = Obs and |D| <= voxel_size and
+ * R = round(d_max / voxel_size):
+ *   Band voxels: phi = D;
+ *   other observed voxels: k = min over sites of the squared voxel distance
+ *   (exact), phi = sign(D) * min(d_max, voxel_size * sqrt(k)) for k <= R^2,
+ *   else sign(D) * d_max (sign = +1 for D > 0, else -1);
+ *   unobserved voxels: phi = NaN.
+ * Asynchronous.
+ */
+int covox_update_esdf(covox_ctx *ctx, covox_submap *s);
+
+/* ---------------------------------------------------------------- align */
+
+typedef struct {
+    int64_t n_points;     /* registration points of B */
+    int64_t n_used;       /* residuals used at the returned pose */
+    int32_t iterations;   /* pose updates applied */
+    int32_t status;       /* COVOX_OK, COVOX_NOT_CONVERGED or COVOX_EDEGENERATE */
+    int32_t best_start;   /* multi-start: the chosen start, else 0 */
+    int32_t reserved;
+} covox_align_stats;
+
+/*
+ * Aligns submap B to submap A (Sec. III-F, Eq. 1 registration term):
+ * registration points of B are the zero crossings of D_B along voxel edges
+ * whose endpoints are both in the band with W >= w_reg; the residual of a
+ * point p is the trilinear ESDF of A at T p, its Jacobian [g ; (T p) x g]
+ * for T <- Exp(xi) T.  Gauss-Newton with binary64 6x6 Cholesky solves and
+ * SE(3) updates on the device; stops when |delta_rho| < tol_rho and
+ * |delta_theta| < tol_theta, or after max_iter updates.
+ * T_init_A_B, T_out (host, 16 doubles) map B coordinates into A's frame.
+ * cost (host) = mean squared residual at T_out.  stats: nullable.
+ * Requires covox_update_esdf(A) after A's last integration.  Synchronous.
+ * Returns the alignment status (OK, NOT_CONVERGED, EDEGENERATE) or an error.
+ */
+int covox_align_submaps(covox_ctx *ctx, const covox_submap *A, covox_submap *B,
+                        const double T_init_A_B[16], double T_out[16], double *cost,
+                        covox_align_stats *stats);
+
+/* Multi-start variant: start k of n_starts is T_init Trans(pbar)
+ * Rz(2 pi k / n_starts) Trans(-pbar), pbar the centroid of B's points; the
+ * result is the least-cost start among those with status != EDEGENERATE and
+ * n_used >= max n_used / 2 (ties: smallest k).  Synchronous. */
+int covox_align_multistart(covox_ctx *ctx, const covox_submap *A, covox_submap *B,
+                           const double T_init_A_B[16], int32_t n_starts, double T_out[16],
+                           double *cost, covox_align_stats *stats);
+
+typedef struct {
+    const covox_submap *A;
+    covox_submap *B;
+    double T_init_A_B[16];
+} covox_pair;
+
+/* n pairs, each with n_starts starts (1 = plain, 8 = multi-start), solved
+ * in one persistent launch (one workgroup per pair-start, longest first).
+ * Outputs (host): T_out n x 16, cost n, stats n (nullable).  Results equal
+ * those of the per-pair calls.  Synchronous. */
+int covox_align_batch(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_t n_starts,
+                      double *T_out, double *cost, covox_align_stats *stats);
+
+/* ------------------------------------------------------------ inspection */
+
+typedef struct {
+    int64_t n_blocks;
+    int64_t block_capacity;
+    int64_t table_capacity;
+    int32_t bbox_min[3];  /* allocated block coordinates, inclusive */
+    int32_t bbox_max[3];
+    int32_t precision;
+    int32_t reserved;
+} covox_submap_info;
+
+/* Synchronous. */
+int covox_submap_info_get(covox_ctx *ctx, const covox_submap *s, covox_submap_info *out);
+
+/* Copies the first min(n_blocks, cap) blocks in buffer order to host arrays
+ * (any may be NULL): keys (u64), home bucket mix64(key) & (table_capacity-1)
+ * (u32, SplitMix64 finaliser), D, W, phi (binary32, 512 per block; FP16
+ * storage is widened).  Returns the number of blocks copied (>= 0) or an
+ * error (< 0).  Synchronous. */
+int64_t covox_export_blocks(covox_ctx *ctx, const covox_submap *s, uint64_t *keys, uint32_t *home,
+                            float *D, float *W, float *phi, int64_t cap);
+
+/* Registration points of B (3 floats each, order: block buffer index,
+ * in-block index, axis) copied to host, up to cap points.  Returns the total
+ * count or an error.  Synchronous. */
+int64_t covox_export_points(covox_ctx *ctx, covox_submap *B, float *pts, int64_t cap);
+
+/* One evaluation of the normal equations of the pair at T (host, 16
+ * doubles): out[0..20] upper triangle of H row by row, out[21..26] b,
+ * out[27] sum r^2, out[28] n.  Synchronous. */
+int covox_normal_equations(covox_ctx *ctx, const covox_submap *A, covox_submap *B,
+                           const double T_A_B[16], double out[29]);
+
+/* ---------------------------------------------------------------- timing */
+
+enum {
+    COVOX_K_PROBE = 0,     /* block candidates: projective any-valid test + hash find */
+    COVOX_K_SCAN,          /* compaction, capacity check, index assignment */
+    COVOX_K_INTEGRATE,     /* projective TSDF update (+ activate of new blocks) */
+    COVOX_K_ESDF_PAGE,     /* dense block page of the submap's box */
+    COVOX_K_ESDF_SITES,    /* site bit masks */
+    COVOX_K_EDT_X,         /* nearest site along x */
+    COVOX_K_EDT_Y,         /* lower envelope along y */
+    COVOX_K_EDT_Z,         /* lower envelope along z + phi */
+    COVOX_K_ISO,           /* registration points */
+    COVOX_K_ALIGN,         /* Gauss-Newton (persistent) */
+    COVOX_K_COUNT
+};
+
+typedef struct {
+    double ms[COVOX_K_COUNT];       /* summed kernel time (HIP events on the ctx stream) */
+    int64_t launches[COVOX_K_COUNT];
+} covox_timing;
+
+/* Enables (1) or disables (0) per-kernel HIP-event timing and clears it. */
+int covox_timing_enable(covox_ctx *ctx, int32_t on);
+/* Synchronizes and returns the accumulated timing. */
+int covox_timing_get(covox_ctx *ctx, covox_timing *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COVOX_H */

@@ -1,0 +1,13 @@
+"""covox on MI355X: projective TSDF integration into a voxel-hashed block grid,
+the exact ESDF derived from it, and correspondence-free ESDF submap alignment
+(Hoss and De Cristoforis, coVoxSLAM, arXiv 2410.21149), as hand-written HIP
+kernels for gfx950 behind the C ABI in include/covox.h.
+
+``Context`` wraps a library context; importing this package fails when the
+HIP library has not been built.
+"""
+from .covox import (FP16, FP32, KERNELS, OK, EINVAL, EPOOL_FULL, ETABLE_FULL, EHIP, EDEGENERATE, NOT_CONVERGED,
+                    Context, CovoxError, Submap, default_params, LIB_PATH)
+
+__all__ = ["Context", "Submap", "CovoxError", "default_params", "FP32", "FP16", "KERNELS", "OK", "EINVAL",
+           "EPOOL_FULL", "ETABLE_FULL", "EHIP", "EDEGENERATE", "NOT_CONVERGED", "LIB_PATH"]

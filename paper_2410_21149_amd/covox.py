@@ -1,0 +1,282 @@
+"""Python binding of libcovox.so (include/covox.h): argument marshalling only.
+
+Every computation runs in the HIP library; PyTorch provides device memory
+(depth frames are torch CUDA/HIP tensors) and the stream the library
+enqueues its work on.  If the library has not been built this module raises
+at import time -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime the library then shares
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcovox.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libcovox.so is not built: run __graft_entry__.build() (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, EPOOL_FULL, ETABLE_FULL, EHIP, EDEGENERATE, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1
+FP32, FP16 = 0, 1
+KERNELS = ["probe", "scan", "integrate", "esdf_page", "esdf_sites", "edt_x", "edt_y", "edt_z", "iso", "align"]
+
+
+class CovoxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_lib.covox_status_string(code).decode(), msg))
+        self.code = code
+
+
+class covox_params(ctypes.Structure):
+    _fields_ = [("voxel_size", ctypes.c_double), ("trunc_vox", ctypes.c_int32), ("max_range", ctypes.c_double),
+                ("d_max", ctypes.c_double), ("w_reg", ctypes.c_double), ("block_capacity", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("n_min", ctypes.c_int32),
+                ("tol_rho", ctypes.c_double), ("tol_theta", ctypes.c_double)]
+
+
+class covox_align_stats(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_used", ctypes.c_int64), ("iterations", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("best_start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class covox_pair(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("T_init_A_B", ctypes.c_double * 16)]
+
+
+class covox_submap_info(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int64), ("block_capacity", ctypes.c_int64), ("table_capacity", ctypes.c_int64),
+                ("bbox_min", ctypes.c_int32 * 3), ("bbox_max", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class covox_timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 10), ("launches", ctypes.c_int64 * 10)]
+
+
+_vp, _dp, _fp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)
+_sig = {
+    "covox_default_params": (None, [ctypes.POINTER(covox_params)]),
+    "covox_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(covox_params)]),
+    "covox_destroy": (None, [_vp]),
+    "covox_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "covox_sync": (ctypes.c_int, [_vp]),
+    "covox_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "covox_last_error": (ctypes.c_char_p, [_vp]),
+    "covox_submap_create": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(_vp)]),
+    "covox_submap_destroy": (None, [_vp]),
+    "covox_submap_reset": (ctypes.c_int, [_vp, _vp]),
+    "covox_integrate_depth": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _fp, _dp]),
+    "covox_integrate_depth_batch": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                   _fp, _dp]),
+    "covox_update_esdf": (ctypes.c_int, [_vp, _vp]),
+    "covox_align_submaps": (ctypes.c_int, [_vp, _vp, _vp, _dp, _dp, _dp, ctypes.POINTER(covox_align_stats)]),
+    "covox_align_multistart": (ctypes.c_int, [_vp, _vp, _vp, _dp, ctypes.c_int32, _dp, _dp,
+                                              ctypes.POINTER(covox_align_stats)]),
+    "covox_align_batch": (ctypes.c_int, [_vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_int32, _dp, _dp,
+                                         ctypes.POINTER(covox_align_stats)]),
+    "covox_submap_info_get": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_submap_info)]),
+    "covox_export_blocks": (ctypes.c_int64, [_vp, _vp, _vp, _vp, _fp, _fp, _fp, ctypes.c_int64]),
+    "covox_export_points": (ctypes.c_int64, [_vp, _vp, _fp, ctypes.c_int64]),
+    "covox_normal_equations": (ctypes.c_int, [_vp, _vp, _vp, _dp, _dp]),
+    "covox_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "covox_timing_get": (ctypes.c_int, [_vp, ctypes.POINTER(covox_timing)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _mat(T) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(T, np.float64).reshape(16))
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def default_params(**kw) -> covox_params:
+    p = covox_params()
+    _lib.covox_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = FP16 if v.lower() in ("fp16", "half") else FP32
+        setattr(p, k, v)
+    return p
+
+
+class Submap:
+    def __init__(self, ctx: "Context", handle):
+        self.ctx, self.handle = ctx, handle
+
+    def destroy(self):
+        if self.handle:
+            _lib.covox_submap_destroy(self.handle)
+            self.handle = None
+
+
+class Context:
+    """A covox context bound to the current device and a torch stream."""
+
+    def __init__(self, params: covox_params | None = None, stream: torch.cuda.Stream | None = None, **kw):
+        self.params = params if params is not None else default_params(**kw)
+        h = _vp()
+        rc = _lib.covox_create(ctypes.byref(h), ctypes.byref(self.params))
+        if rc != OK:
+            raise CovoxError(rc, "covox_create")
+        self.handle = h
+        self.set_stream(stream if stream is not None else torch.cuda.current_stream())
+        self._subs = []
+
+    # -- plumbing
+    def _check(self, rc, what, ok=(OK,)):
+        if rc not in ok:
+            raise CovoxError(rc, "%s: %s" % (what, _lib.covox_last_error(self.handle).decode()))
+        return rc
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self.stream = stream
+        self._check(_lib.covox_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)), "set_stream")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            for s in self._subs:
+                s.handle = None
+            _lib.covox_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        self._check(_lib.covox_sync(self.handle), "sync")
+
+    # -- submaps
+    def submap_create(self, T_world_submap=None) -> Submap:
+        T = _mat(np.eye(4) if T_world_submap is None else T_world_submap)
+        h = _vp()
+        self._check(_lib.covox_submap_create(self.handle, _p(T, _dp), ctypes.byref(h)), "submap_create")
+        s = Submap(self, h)
+        self._subs.append(s)
+        return s
+
+    def submap_reset(self, s: Submap):
+        self._check(_lib.covox_submap_reset(self.handle, s.handle), "submap_reset")
+
+    def submap_info(self, s: Submap) -> dict:
+        info = covox_submap_info()
+        self._check(_lib.covox_submap_info_get(self.handle, s.handle, ctypes.byref(info)), "submap_info")
+        return {"n_blocks": info.n_blocks, "block_capacity": info.block_capacity,
+                "table_capacity": info.table_capacity, "bbox_min": tuple(info.bbox_min),
+                "bbox_max": tuple(info.bbox_max), "precision": info.precision}
+
+    # -- hot path
+    @staticmethod
+    def _depth_ptr(depth: torch.Tensor, ndim: int):
+        if not (isinstance(depth, torch.Tensor) and depth.is_cuda and depth.dtype == torch.float32
+                and depth.dim() == ndim and depth.is_contiguous()):
+            raise ValueError("depth must be a contiguous float32 device tensor with %d dims" % ndim)
+        return ctypes.c_void_p(depth.data_ptr())
+
+    def integrate_depth(self, s: Submap, depth: torch.Tensor, K, T_world_cam):
+        k = np.ascontiguousarray(K, np.float32)
+        T = _mat(T_world_cam)
+        H, W = depth.shape
+        return self._check(_lib.covox_integrate_depth(self.handle, s.handle, self._depth_ptr(depth, 2), H, W,
+                                                      _p(k, _fp), _p(T, _dp)), "integrate_depth")
+
+    def integrate_depth_batch(self, s: Submap, depths: torch.Tensor, K, T_world_cam):
+        k = np.ascontiguousarray(K, np.float32)
+        T = np.ascontiguousarray(np.asarray(T_world_cam, np.float64).reshape(-1, 16))
+        F, H, W = depths.shape
+        assert len(T) == F
+        return self._check(_lib.covox_integrate_depth_batch(self.handle, s.handle, self._depth_ptr(depths, 3), F, H,
+                                                            W, _p(k, _fp), _p(T, _dp)), "integrate_depth_batch")
+
+    def update_esdf(self, s: Submap):
+        return self._check(_lib.covox_update_esdf(self.handle, s.handle), "update_esdf")
+
+    def align_submaps(self, A: Submap, B: Submap, T_init):
+        T0 = _mat(T_init)
+        T = np.zeros(16)
+        cost = ctypes.c_double()
+        st = covox_align_stats()
+        rc = _lib.covox_align_submaps(self.handle, A.handle, B.handle, _p(T0, _dp), _p(T, _dp), ctypes.byref(cost),
+                                      ctypes.byref(st))
+        self._check(rc, "align_submaps", ok=(OK, NOT_CONVERGED, EDEGENERATE))
+        return T.reshape(4, 4), cost.value, _stats(st)
+
+    def align_multistart(self, A: Submap, B: Submap, T_init, n_starts=8):
+        T0 = _mat(T_init)
+        T = np.zeros(16)
+        cost = ctypes.c_double()
+        st = covox_align_stats()
+        rc = _lib.covox_align_multistart(self.handle, A.handle, B.handle, _p(T0, _dp), n_starts, _p(T, _dp),
+                                         ctypes.byref(cost), ctypes.byref(st))
+        self._check(rc, "align_multistart", ok=(OK, NOT_CONVERGED, EDEGENERATE))
+        return T.reshape(4, 4), cost.value, _stats(st)
+
+    def align_batch(self, pairs, n_starts=1):
+        n = len(pairs)
+        arr = (covox_pair * max(n, 1))()
+        for i, (A, B, T0) in enumerate(pairs):
+            arr[i].A = A.handle
+            arr[i].B = B.handle
+            arr[i].T_init_A_B[:] = list(_mat(T0))
+        T = np.zeros(16 * max(n, 1))
+        cost = np.zeros(max(n, 1))
+        st = (covox_align_stats * max(n, 1))()
+        self._check(_lib.covox_align_batch(self.handle, arr, n, n_starts, _p(T, _dp), _p(cost, _dp), st),
+                    "align_batch")
+        return T.reshape(-1, 4, 4)[:n], cost[:n], [_stats(st[i]) for i in range(n)]
+
+    def normal_equations(self, A: Submap, B: Submap, T) -> np.ndarray:
+        out = np.zeros(29)
+        Tm = _mat(T)
+        self._check(_lib.covox_normal_equations(self.handle, A.handle, B.handle, _p(Tm, _dp), _p(out, _dp)),
+                    "normal_equations")
+        return out
+
+    # -- inspection
+    def export_blocks(self, s: Submap) -> dict:
+        n = self.submap_info(s)["n_blocks"]
+        keys = np.zeros(max(n, 1), np.uint64)
+        home = np.zeros(max(n, 1), np.uint32)
+        D = np.zeros((max(n, 1), 512), np.float32)
+        W = np.zeros((max(n, 1), 512), np.float32)
+        phi = np.zeros((max(n, 1), 512), np.float32)
+        got = _lib.covox_export_blocks(self.handle, s.handle, keys.ctypes.data_as(_vp), home.ctypes.data_as(_vp),
+                                       _p(D, _fp), _p(W, _fp), _p(phi, _fp), n)
+        if got < 0:
+            self._check(int(got), "export_blocks")
+        return {"keys": keys[:got], "home": home[:got], "D": D[:got], "W": W[:got], "phi": phi[:got]}
+
+    def export_points(self, B: Submap) -> np.ndarray:
+        n = _lib.covox_export_points(self.handle, B.handle, None, 0)
+        if n < 0:
+            self._check(int(n), "export_points")
+        pts = np.zeros((max(n, 1), 3), np.float32)
+        _lib.covox_export_points(self.handle, B.handle, _p(pts, _fp), n)
+        return pts[:n]
+
+    # -- timing
+    def timing_enable(self, on=True):
+        self._check(_lib.covox_timing_enable(self.handle, int(on)), "timing_enable")
+
+    def timing_get(self) -> dict:
+        t = covox_timing()
+        self._check(_lib.covox_timing_get(self.handle, ctypes.byref(t)), "timing_get")
+        return {k: (t.ms[i], t.launches[i]) for i, k in enumerate(KERNELS)}
+
+
+def _stats(st: covox_align_stats) -> dict:
+    return {"n_points": st.n_points, "n_used": st.n_used, "iterations": st.iterations, "status": st.status,
+            "best_start": st.best_start}

@@ -1,0 +1,612 @@
+// C ABI of the covox library (include/covox.h): contexts, submaps, the
+// integrate / ESDF / align entry points, inspection and kernel timing.
+#include "covox_impl.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+namespace covox {
+
+namespace {
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+unsigned fill_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
+
+}  // namespace
+
+void fill_u64(hipStream_t s, uint64_t *p, uint64_t v, int64_t n)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+}
+
+void fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid(n)), dim3(256), 0, s, p, v, n);
+}
+
+int fail(covox_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->last_error = msg;
+    return code;
+}
+
+int hip_check(covox_ctx *ctx, hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return COVOX_OK;
+    return fail(ctx, COVOX_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+TimedLaunch::TimedLaunch(covox_ctx *c, int k) : ctx(c), kind(k)
+{
+    if (!ctx->timing) return;
+    for (hipEvent_t *e : {&a, &b}) {
+        if (!ctx->ev_pool.empty()) {
+            *e = ctx->ev_pool.back();
+            ctx->ev_pool.pop_back();
+        } else if (hipEventCreate(e) != hipSuccess) {
+            *e = nullptr;
+        }
+    }
+    if (a) (void)hipEventRecord(a, ctx->stream);
+}
+
+TimedLaunch::~TimedLaunch()
+{
+    if (!ctx->timing) return;
+    if (a && b) {
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->ev_used.push_back({kind, {a, b}});
+    } else {
+        if (a) ctx->ev_pool.push_back(a);
+        if (b) ctx->ev_pool.push_back(b);
+    }
+}
+
+int ensure_buffer(covox_ctx *ctx, void **ptr, int64_t *cap, int64_t need, size_t elem, const char *what)
+{
+    if (need <= *cap && *ptr) return COVOX_OK;
+    int64_t nc = std::max<int64_t>(need, *cap + *cap / 2);
+    if (*ptr) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return hip_check(ctx, e, "sync before reallocation");
+        (void)hipFree(*ptr);
+        *ptr = nullptr;
+        *cap = 0;
+    }
+    hipError_t e = hipMalloc(ptr, (size_t)nc * elem);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(ctx, COVOX_EHIP, std::string("allocating ") + what + ": " + hipGetErrorString(e));
+    }
+    *cap = nc;
+    return COVOX_OK;
+}
+
+}  // namespace covox
+
+using namespace covox;
+
+namespace {
+
+std::vector<covox_submap *> &submaps_of(covox_ctx *ctx) { return ctx->subs; }
+
+bool valid_params(const covox_params *p, std::string &why)
+{
+    if (!(p->voxel_size > 0) || !std::isfinite(p->voxel_size)) { why = "voxel_size must be positive"; return false; }
+    if (p->trunc_vox < 1) { why = "trunc_vox must be >= 1"; return false; }
+    if (!(p->max_range > 0)) { why = "max_range must be positive"; return false; }
+    if (!(p->d_max > 0)) { why = "d_max must be positive"; return false; }
+    const long long R = llround(p->d_max / p->voxel_size);
+    if (R < 1 || R > 8 * kMaxHalo) { why = "d_max / voxel_size must round to 1..56"; return false; }
+    if (p->block_capacity < 1 || p->block_capacity > (1ll << 30)) { why = "block_capacity out of range"; return false; }
+    if (p->precision != COVOX_FP32 && p->precision != COVOX_FP16) { why = "precision must be FP32 or FP16"; return false; }
+    if (p->max_iter < 0) { why = "max_iter must be >= 0"; return false; }
+    if (p->n_min < 1) { why = "n_min must be >= 1"; return false; }
+    return true;
+}
+
+int read_meta(covox_ctx *ctx, const covox_submap *s, SubmapMeta *m)
+{
+    int rc = hip_check(ctx, hipMemcpyAsync(m, s->meta, sizeof(*m), hipMemcpyDeviceToHost, ctx->stream), "meta copy");
+    if (rc) return rc;
+    return hip_check(ctx, hipStreamSynchronize(ctx->stream), "meta sync");
+}
+
+__global__ void k_clear_status(SubmapMeta *m) { m->status = 0; }
+
+__global__ void k_reset_meta(SubmapMeta *m)
+{
+    m->n_blocks = 0;
+    for (int a = 0; a < 3; ++a) { m->bmin[a] = 0; m->bmax[a] = -1; m->dom_min[a] = 0; m->dom_dim[a] = 0; }
+    m->status = 0;
+    m->n_new = 0;
+    m->n_touched = 0;
+    m->dom_valid = 0;
+    m->n_points = 0;
+    m->pbar[0] = m->pbar[1] = m->pbar[2] = 0.0;
+}
+
+int check_status_after_sync(covox_ctx *ctx, covox_submap *s)
+{
+    SubmapMeta m;
+    int rc = read_meta(ctx, s, &m);
+    if (rc) return rc;
+    s->nb_upper = m.n_blocks;
+    if (m.status != 0) {
+        hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, ctx->stream, s->meta);
+        return fail(ctx, m.status, m.status == COVOX_EPOOL_FULL ? "integrate: block capacity exceeded"
+                                                                : "integrate: hash table load limit exceeded");
+    }
+    return COVOX_OK;
+}
+
+bool rigid_pose(const double *T)
+{
+    for (int k = 0; k < 16; ++k)
+        if (!std::isfinite(T[k])) return false;
+    if (T[12] != 0 || T[13] != 0 || T[14] != 0 || T[15] != 1) return false;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += T[4 * k + r] * T[4 * k + c];
+            if (std::fabs(s - (r == c ? 1.0 : 0.0)) > 1e-6) return false;
+        }
+    return true;
+}
+
+void mat_mul4(const double *A, const double *B, double *O)
+{
+    double t[16];
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) t[4 * r + c] = A[4 * r] * B[c] + A[4 * r + 1] * B[4 + c] + A[4 * r + 2] * B[8 + c] + A[4 * r + 3] * B[12 + c];
+    memcpy(O, t, sizeof(t));
+}
+
+int prepare_pair(covox_ctx *ctx, const covox_submap *A, covox_submap *B)
+{
+    if (!A || !B) return fail(ctx, COVOX_EINVAL, "align: null submap");
+    if (A->esdf_version != A->version)
+        return fail(ctx, COVOX_EINVAL, "align: the ESDF of A is out of date (call covox_update_esdf)");
+    return extract_points(ctx, B);
+}
+
+AlignProblem make_problem(covox_ctx *ctx, const covox_submap *A, const covox_submap *B, const double *T, int max_iter)
+{
+    AlignProblem pr;
+    memset(&pr, 0, sizeof(pr));
+    pr.phi = A->phi;
+    pr.page = A->page;
+    pr.metaA = A->meta;
+    pr.pts = B->pts;
+    pr.n_pts = B->n_pts;
+    memcpy(pr.T, T, sizeof(pr.T));
+    pr.max_iter = max_iter;
+    (void)ctx;
+    return pr;
+}
+
+void start_pose(const double *T_init, const double pbar[3], int k, int n, double *out)
+{
+    const double a = 2.0 * M_PI * (double)k / (double)n;
+    const double P[16] = {1, 0, 0, pbar[0], 0, 1, 0, pbar[1], 0, 0, 1, pbar[2], 0, 0, 0, 1};
+    const double Pm[16] = {1, 0, 0, -pbar[0], 0, 1, 0, -pbar[1], 0, 0, 1, -pbar[2], 0, 0, 0, 1};
+    const double Rz[16] = {cos(a), -sin(a), 0, 0, sin(a), cos(a), 0, 0, 0, 0, 1, 0, 0, 0, 0, 1};
+    double S[16];
+    mat_mul4(T_init, P, S);
+    mat_mul4(S, Rz, S);
+    mat_mul4(S, Pm, out);
+    out[12] = 0; out[13] = 0; out[14] = 0; out[15] = 1;
+}
+
+// Picks the least-cost start among those not degenerate with
+// n_used >= max n_used / 2 (ties: smallest k).
+int select_start(const AlignResult *r, int n)
+{
+    int64_t nmax = 0;
+    for (int k = 0; k < n; ++k)
+        if (r[k].status != COVOX_EDEGENERATE) nmax = std::max(nmax, r[k].n_used);
+    int best = -1;
+    for (int k = 0; k < n; ++k) {
+        if (r[k].status == COVOX_EDEGENERATE) continue;
+        if (2 * r[k].n_used < nmax) continue;
+        if (best < 0 || r[k].cost < r[best].cost) best = k;
+    }
+    return best;
+}
+
+void fill_stats(covox_align_stats *st, const covox_submap *B, const AlignResult &r, int best)
+{
+    if (!st) return;
+    st->n_points = B->n_pts;
+    st->n_used = r.n_used;
+    st->iterations = r.iters;
+    st->status = r.status;
+    st->best_start = best;
+    st->reserved = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void covox_default_params(covox_params *p)
+{
+    if (!p) return;
+    p->voxel_size = 0.05;
+    p->trunc_vox = 4;
+    p->max_range = 5.0;
+    p->d_max = 2.0;
+    p->w_reg = 2.0;
+    p->block_capacity = 65536;
+    p->precision = COVOX_FP32;
+    p->max_iter = 30;
+    p->n_min = 100;
+    p->tol_rho = 1e-7;
+    p->tol_theta = 1e-8;
+}
+
+const char *covox_status_string(int s)
+{
+    switch (s) {
+    case COVOX_OK: return "COVOX_OK";
+    case COVOX_EINVAL: return "COVOX_EINVAL";
+    case COVOX_EPOOL_FULL: return "COVOX_EPOOL_FULL";
+    case COVOX_ETABLE_FULL: return "COVOX_ETABLE_FULL";
+    case COVOX_EHIP: return "COVOX_EHIP";
+    case COVOX_EDEGENERATE: return "COVOX_EDEGENERATE";
+    case COVOX_NOT_CONVERGED: return "COVOX_NOT_CONVERGED";
+    default: return "COVOX_UNKNOWN";
+    }
+}
+
+const char *covox_last_error(const covox_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int covox_create(covox_ctx **out, const covox_params *p)
+{
+    if (!out || !p) return COVOX_EINVAL;
+    *out = nullptr;
+    std::string why;
+    if (!valid_params(p, why)) return COVOX_EINVAL;
+    covox_ctx *ctx = new covox_ctx();
+    ctx->p = *p;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return COVOX_EHIP;
+    }
+    *out = ctx;
+    return COVOX_OK;
+}
+
+void covox_destroy(covox_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    auto &subs = submaps_of(ctx);
+    for (covox_submap *s : std::vector<covox_submap *>(subs)) covox_submap_destroy(s);
+    for (void *ptr : {(void *)ctx->cand, (void *)ctx->t_key, (void *)ctx->t_idx, (void *)ctx->sites, (void *)ctx->g1,
+                      (void *)ctx->g2, (void *)ctx->cnt, (void *)ctx->psum, ctx->prob_dev, ctx->res_dev})
+        if (ptr) (void)hipFree(ptr);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (auto &u : ctx->ev_used) {
+        (void)hipEventDestroy(u.second.first);
+        (void)hipEventDestroy(u.second.second);
+    }
+    delete ctx;
+}
+
+int covox_set_stream(covox_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return COVOX_EINVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return COVOX_OK;
+}
+
+int covox_sync(covox_ctx *ctx)
+{
+    if (!ctx) return COVOX_EINVAL;
+    int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync");
+    if (rc) return rc;
+    for (covox_submap *s : submaps_of(ctx)) {
+        rc = check_status_after_sync(ctx, s);
+        if (rc) return rc;
+    }
+    return COVOX_OK;
+}
+
+int covox_submap_create(covox_ctx *ctx, const double T_world_submap[16], covox_submap **out)
+{
+    if (!ctx || !T_world_submap || !out) return fail(ctx, COVOX_EINVAL, "submap_create: null argument");
+    if (!rigid_pose(T_world_submap)) return fail(ctx, COVOX_EINVAL, "submap_create: pose is not rigid");
+    *out = nullptr;
+    covox_submap *s = new covox_submap();
+    s->ctx = ctx;
+    memcpy(s->T_ws, T_world_submap, sizeof(s->T_ws));
+    s->cap = ctx->p.block_capacity;
+    int64_t t = 1;
+    while (t < 2 * s->cap) t <<= 1;
+    s->tcap = t;
+    const size_t es = ctx->p.precision == COVOX_FP16 ? 2 : 4;
+    const size_t nvox = (size_t)s->cap * 512;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMalloc((void **)&s->keys, sizeof(uint64_t) * s->cap);
+    if (e == hipSuccess) e = hipMalloc(&s->D, es * nvox);
+    if (e == hipSuccess) e = hipMalloc(&s->W, es * nvox);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->phi, sizeof(float) * nvox);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->tkeys, sizeof(uint64_t) * s->tcap);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->tvals, sizeof(uint32_t) * s->tcap);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->meta, sizeof(SubmapMeta));
+    if (e != hipSuccess) {
+        covox_submap_destroy(s);
+        return fail(ctx, COVOX_EHIP, std::string("submap_create: ") + hipGetErrorString(e));
+    }
+    submaps_of(ctx).push_back(s);
+    int rc = covox_submap_reset(ctx, s);
+    if (rc) {
+        covox_submap_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return COVOX_OK;
+}
+
+void covox_submap_destroy(covox_submap *s)
+{
+    if (!s) return;
+    if (s->ctx) {
+        (void)hipStreamSynchronize(s->ctx->stream);
+        auto &subs = submaps_of(s->ctx);
+        subs.erase(std::remove(subs.begin(), subs.end(), s), subs.end());
+    }
+    for (void *p : {(void *)s->keys, s->D, s->W, (void *)s->phi, (void *)s->tkeys, (void *)s->tvals, (void *)s->meta,
+                    (void *)s->page, (void *)s->pts})
+        if (p) (void)hipFree(p);
+    delete s;
+}
+
+int covox_submap_reset(covox_ctx *ctx, covox_submap *s)
+{
+    if (!ctx || !s) return fail(ctx, COVOX_EINVAL, "submap_reset: null argument");
+    fill_u64(ctx->stream, s->tkeys, kEmpty, s->tcap);
+    hipLaunchKernelGGL(k_reset_meta, dim3(1), dim3(1), 0, ctx->stream, s->meta);
+    int rc = hip_check(ctx, hipGetLastError(), "submap_reset");
+    if (rc) return rc;
+    s->nb_upper = 0;
+    s->bound_valid = false;
+    s->version++;
+    s->n_pts = 0;
+    return COVOX_OK;
+}
+
+int covox_integrate_depth(covox_ctx *ctx, covox_submap *s, const float *depth_dev, int32_t H, int32_t W,
+                          const float K[4], const double T_world_cam[16])
+{
+    if (!ctx || !s) return fail(ctx, COVOX_EINVAL, "integrate: null argument");
+    bool maybe_full = false;
+    int rc = integrate_frame(ctx, s, depth_dev, H, W, K, T_world_cam, &maybe_full);
+    if (rc) return rc;
+    if (maybe_full) return check_status_after_sync(ctx, s);
+    return COVOX_OK;
+}
+
+int covox_integrate_depth_batch(covox_ctx *ctx, covox_submap *s, const float *depths_dev, int32_t F, int32_t H,
+                                int32_t W, const float K[4], const double *T_world_cam)
+{
+    if (!ctx || !s || !depths_dev || !T_world_cam || F < 0) return fail(ctx, COVOX_EINVAL, "integrate_batch: bad argument");
+    for (int32_t f = 0; f < F; ++f) {
+        int rc = covox_integrate_depth(ctx, s, depths_dev + (size_t)f * H * W, H, W, K, T_world_cam + 16 * f);
+        if (rc) return rc;
+    }
+    return COVOX_OK;
+}
+
+int covox_update_esdf(covox_ctx *ctx, covox_submap *s)
+{
+    if (!ctx || !s) return fail(ctx, COVOX_EINVAL, "update_esdf: null argument");
+    return update_esdf(ctx, s);
+}
+
+int covox_align_submaps(covox_ctx *ctx, const covox_submap *A, covox_submap *B, const double T_init_A_B[16],
+                        double T_out[16], double *cost, covox_align_stats *stats)
+{
+    if (!ctx || !T_init_A_B || !T_out || !cost) return fail(ctx, COVOX_EINVAL, "align: null argument");
+    if (!rigid_pose(T_init_A_B)) return fail(ctx, COVOX_EINVAL, "align: T_init is not rigid");
+    int rc = prepare_pair(ctx, A, B);
+    if (rc) return rc;
+    AlignProblem pr = make_problem(ctx, A, B, T_init_A_B, ctx->p.max_iter);
+    AlignResult res;
+    if ((rc = run_alignment(ctx, &pr, 1, &res))) return rc;
+    memcpy(T_out, res.T, sizeof(res.T));
+    *cost = res.cost;
+    fill_stats(stats, B, res, 0);
+    return res.status;
+}
+
+int covox_align_multistart(covox_ctx *ctx, const covox_submap *A, covox_submap *B, const double T_init_A_B[16],
+                           int32_t n_starts, double T_out[16], double *cost, covox_align_stats *stats)
+{
+    if (!ctx || !T_init_A_B || !T_out || !cost || n_starts < 1) return fail(ctx, COVOX_EINVAL, "align: bad argument");
+    if (!rigid_pose(T_init_A_B)) return fail(ctx, COVOX_EINVAL, "align: T_init is not rigid");
+    int rc = prepare_pair(ctx, A, B);
+    if (rc) return rc;
+    std::vector<AlignProblem> prs(n_starts);
+    for (int k = 0; k < n_starts; ++k) {
+        double S[16];
+        start_pose(T_init_A_B, B->pbar, k, n_starts, S);
+        prs[k] = make_problem(ctx, A, B, S, ctx->p.max_iter);
+    }
+    std::vector<AlignResult> res(n_starts);
+    if ((rc = run_alignment(ctx, prs.data(), n_starts, res.data()))) return rc;
+    const int best = select_start(res.data(), n_starts);
+    if (best < 0) {
+        memcpy(T_out, T_init_A_B, sizeof(double) * 16);
+        *cost = INFINITY;
+        if (stats) { memset(stats, 0, sizeof(*stats)); stats->n_points = B->n_pts; stats->status = COVOX_EDEGENERATE; stats->best_start = -1; }
+        return COVOX_EDEGENERATE;
+    }
+    memcpy(T_out, res[best].T, sizeof(double) * 16);
+    *cost = res[best].cost;
+    fill_stats(stats, B, res[best], best);
+    return res[best].status;
+}
+
+int covox_align_batch(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_t n_starts, double *T_out,
+                      double *cost, covox_align_stats *stats)
+{
+    if (!ctx || !pairs || n < 0 || n_starts < 1 || !T_out || !cost) return fail(ctx, COVOX_EINVAL, "align_batch: bad argument");
+    int rc;
+    for (int i = 0; i < n; ++i) {
+        if (!rigid_pose(pairs[i].T_init_A_B)) return fail(ctx, COVOX_EINVAL, "align_batch: T_init is not rigid");
+        if ((rc = prepare_pair(ctx, pairs[i].A, pairs[i].B))) return rc;
+    }
+    std::vector<AlignProblem> prs((size_t)n * n_starts);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n_starts; ++k) {
+            double S[16];
+            if (n_starts == 1) memcpy(S, pairs[i].T_init_A_B, sizeof(S));
+            else start_pose(pairs[i].T_init_A_B, pairs[i].B->pbar, k, n_starts, S);
+            prs[(size_t)i * n_starts + k] = make_problem(ctx, pairs[i].A, pairs[i].B, S, ctx->p.max_iter);
+        }
+    std::vector<AlignResult> res(prs.size());
+    if ((rc = run_alignment(ctx, prs.data(), (int)prs.size(), res.data()))) return rc;
+    for (int i = 0; i < n; ++i) {
+        const AlignResult *r = &res[(size_t)i * n_starts];
+        const int best = n_starts == 1 ? (r[0].status == COVOX_EDEGENERATE ? -1 : 0) : select_start(r, n_starts);
+        if (best < 0) {
+            memcpy(T_out + 16 * i, pairs[i].T_init_A_B, sizeof(double) * 16);
+            if (n_starts == 1) memcpy(T_out + 16 * i, r[0].T, sizeof(double) * 16);
+            cost[i] = n_starts == 1 ? r[0].cost : INFINITY;
+            if (stats) {
+                if (n_starts == 1) fill_stats(stats + i, pairs[i].B, r[0], 0);
+                else { memset(stats + i, 0, sizeof(*stats)); stats[i].n_points = pairs[i].B->n_pts; }
+                stats[i].status = COVOX_EDEGENERATE;
+                stats[i].best_start = n_starts == 1 ? 0 : -1;
+            }
+            continue;
+        }
+        memcpy(T_out + 16 * i, r[best].T, sizeof(double) * 16);
+        cost[i] = r[best].cost;
+        fill_stats(stats ? stats + i : nullptr, pairs[i].B, r[best], best);
+    }
+    return COVOX_OK;
+}
+
+int covox_normal_equations(covox_ctx *ctx, const covox_submap *A, covox_submap *B, const double T_A_B[16],
+                           double out[29])
+{
+    if (!ctx || !T_A_B || !out) return fail(ctx, COVOX_EINVAL, "normal_equations: null argument");
+    int rc = prepare_pair(ctx, A, B);
+    if (rc) return rc;
+    AlignProblem pr = make_problem(ctx, A, B, T_A_B, 0);
+    AlignResult res;
+    if ((rc = run_alignment(ctx, &pr, 1, &res))) return rc;
+    memcpy(out, res.ne, sizeof(res.ne));
+    return COVOX_OK;
+}
+
+int covox_submap_info_get(covox_ctx *ctx, const covox_submap *s, covox_submap_info *out)
+{
+    if (!ctx || !s || !out) return fail(ctx, COVOX_EINVAL, "submap_info: null argument");
+    SubmapMeta m;
+    int rc = read_meta(ctx, s, &m);
+    if (rc) return rc;
+    out->n_blocks = m.n_blocks;
+    out->block_capacity = s->cap;
+    out->table_capacity = s->tcap;
+    for (int a = 0; a < 3; ++a) { out->bbox_min[a] = m.bmin[a]; out->bbox_max[a] = m.bmax[a]; }
+    out->precision = ctx->p.precision;
+    out->reserved = m.status;
+    return COVOX_OK;
+}
+
+int64_t covox_export_blocks(covox_ctx *ctx, const covox_submap *s, uint64_t *keys, uint32_t *home, float *D, float *W,
+                            float *phi, int64_t cap)
+{
+    if (!ctx || !s || cap < 0) return fail(ctx, COVOX_EINVAL, "export_blocks: bad argument");
+    SubmapMeta m;
+    int rc = read_meta(ctx, s, &m);
+    if (rc) return rc;
+    const int64_t n = std::min<int64_t>(m.n_blocks, cap);
+    if (n <= 0) return 0;
+    std::vector<uint64_t> k(n);
+    if ((rc = hip_check(ctx, hipMemcpy(k.data(), s->keys, sizeof(uint64_t) * n, hipMemcpyDeviceToHost), "keys copy")))
+        return rc;
+    if (keys) memcpy(keys, k.data(), sizeof(uint64_t) * n);
+    if (home)
+        for (int64_t j = 0; j < n; ++j) home[j] = (uint32_t)(mix64(k[j]) & (uint64_t)(s->tcap - 1));
+    const size_t nv = (size_t)n * 512;
+    auto copy_field = [&](const void *src, float *dst) -> int {
+        if (!dst) return COVOX_OK;
+        if (ctx->p.precision == COVOX_FP16) {
+            std::vector<__half> h(nv);
+            int r = hip_check(ctx, hipMemcpy(h.data(), src, sizeof(__half) * nv, hipMemcpyDeviceToHost), "field copy");
+            if (r) return r;
+            for (size_t i = 0; i < nv; ++i) dst[i] = __half2float(h[i]);
+            return COVOX_OK;
+        }
+        return hip_check(ctx, hipMemcpy(dst, src, sizeof(float) * nv, hipMemcpyDeviceToHost), "field copy");
+    };
+    if ((rc = copy_field(s->D, D))) return rc;
+    if ((rc = copy_field(s->W, W))) return rc;
+    if (phi && (rc = hip_check(ctx, hipMemcpy(phi, s->phi, sizeof(float) * nv, hipMemcpyDeviceToHost), "phi copy")))
+        return rc;
+    return n;
+}
+
+int64_t covox_export_points(covox_ctx *ctx, covox_submap *B, float *pts, int64_t cap)
+{
+    if (!ctx || !B || cap < 0) return fail(ctx, COVOX_EINVAL, "export_points: bad argument");
+    int rc = extract_points(ctx, B);
+    if (rc) return rc;
+    const int64_t n = std::min(cap, B->n_pts);
+    if (pts && n > 0 &&
+        (rc = hip_check(ctx, hipMemcpy(pts, B->pts, sizeof(float) * 3 * n, hipMemcpyDeviceToHost), "points copy")))
+        return rc;
+    return B->n_pts;
+}
+
+int covox_timing_enable(covox_ctx *ctx, int32_t on)
+{
+    if (!ctx) return COVOX_EINVAL;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &u : ctx->ev_used) {
+        ctx->ev_pool.push_back(u.second.first);
+        ctx->ev_pool.push_back(u.second.second);
+    }
+    ctx->ev_used.clear();
+    for (int k = 0; k < COVOX_K_COUNT; ++k) { ctx->ms[k] = 0; ctx->launches[k] = 0; }
+    ctx->timing = on != 0;
+    return COVOX_OK;
+}
+
+int covox_timing_get(covox_ctx *ctx, covox_timing *out)
+{
+    if (!ctx || !out) return COVOX_EINVAL;
+    int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "timing sync");
+    if (rc) return rc;
+    for (auto &u : ctx->ev_used) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, u.second.first, u.second.second) == hipSuccess) ctx->ms[u.first] += ms;
+        ctx->launches[u.first] += 1;
+        ctx->ev_pool.push_back(u.second.first);
+        ctx->ev_pool.push_back(u.second.second);
+    }
+    ctx->ev_used.clear();
+    for (int k = 0; k < COVOX_K_COUNT; ++k) { out->ms[k] = ctx->ms[k]; out->launches[k] = ctx->launches[k]; }
+    return COVOX_OK;
+}
+
+}  // extern "C"

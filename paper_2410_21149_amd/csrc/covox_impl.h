@@ -1,0 +1,242 @@
+// Internal declarations of the covox HIP library (gfx950).  Not installed;
+// the public interface is include/covox.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/covox.h"
+
+namespace covox {
+
+// ------------------------------------------------------------------ keys
+
+constexpr int64_t kKeyOff = 1 << 20;
+constexpr uint64_t kEmpty = ~0ull;   // empty hash slot
+constexpr int kMaxHalo = 7;          // halo blocks of the EDT passes (R <= 56)
+
+__host__ __device__ inline uint64_t pack_key(int32_t bx, int32_t by, int32_t bz)
+{
+    return ((uint64_t)(int64_t)(bx + kKeyOff) << 42) | ((uint64_t)(int64_t)(by + kKeyOff) << 21) |
+           (uint64_t)(int64_t)(bz + kKeyOff);
+}
+
+__host__ __device__ inline void unpack_key(uint64_t k, int32_t &bx, int32_t &by, int32_t &bz)
+{
+    bx = (int32_t)((k >> 42) & 0x1FFFFF) - (int32_t)kKeyOff;
+    by = (int32_t)((k >> 21) & 0x1FFFFF) - (int32_t)kKeyOff;
+    bz = (int32_t)(k & 0x1FFFFF) - (int32_t)kKeyOff;
+}
+
+// SplitMix64 finaliser (Steele, Lea, Flood, OOPSLA 2014): the home bucket
+// of a key is mix64(key) & (capacity - 1).
+__host__ __device__ inline uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Lookup in an open-addressing table with linear probing.  The table is
+// never more than 85 % full, so the probe ends at the key or an empty slot.
+__device__ inline int64_t hash_find(const uint64_t *tkeys, const uint32_t *tvals, uint64_t mask,
+                                    uint64_t key)
+{
+    uint64_t h = mix64(key) & mask;
+    for (;;) {
+        uint64_t k = tkeys[h];
+        if (k == key) return (int64_t)tvals[h];
+        if (k == kEmpty) return -1;
+        h = (h + 1) & mask;
+    }
+}
+
+// Inserts a key known to be absent ("activate": the caller already owns
+// its buffer index).
+__device__ inline void hash_insert(uint64_t *tkeys, uint32_t *tvals, uint64_t mask, uint64_t key,
+                                   uint32_t val)
+{
+    uint64_t h = mix64(key) & mask;
+    for (;;) {
+        unsigned long long prev = atomicCAS((unsigned long long *)&tkeys[h], (unsigned long long)kEmpty,
+                                            (unsigned long long)key);
+        if (prev == kEmpty) {
+            tvals[h] = val;
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// ----------------------------------------------------------- submap state
+
+// Device-resident bookkeeping of one submap.
+struct SubmapMeta {
+    int64_t n_blocks;       // allocated blocks
+    int32_t bmin[3];        // allocated block box (inclusive); valid when n_blocks > 0
+    int32_t bmax[3];
+    int32_t status;         // sticky capacity error of an asynchronous integration
+    int32_t n_new;          // last frame: new blocks
+    int32_t n_touched;      // last frame: touched blocks
+    int32_t dom_valid;      // page below describes dom_min / dom_dim
+    int32_t dom_min[3];     // ESDF / page domain (block coordinates)
+    int32_t dom_dim[3];
+    int64_t n_points;       // registration points
+    double pbar[3];         // their centroid (binary64)
+};
+
+// Per-frame projection parameters (kernel argument).
+struct FrameArgs {
+    float R[9];
+    float t[3];
+    float K[4];
+    int32_t H, W;
+    int32_t blo[3];    // frustum block box origin
+    int32_t bdim[3];   // and extent (z fastest in the linear order)
+    const float *depth;
+};
+
+}  // namespace covox
+
+struct covox_submap {
+    covox_ctx *ctx = nullptr;
+    double T_ws[16];
+    int64_t cap = 0;         // block capacity
+    int64_t tcap = 0;        // hash slots (power of two)
+    uint64_t *keys = nullptr;
+    void *D = nullptr;       // float or __half, cap * 512
+    void *W = nullptr;
+    float *phi = nullptr;
+    uint64_t *tkeys = nullptr;
+    uint32_t *tvals = nullptr;
+    covox::SubmapMeta *meta = nullptr;
+    // host-side upper bounds (no device round trip needed)
+    int64_t nb_upper = 0;            // >= n_blocks
+    bool bound_valid = false;        // box containing every allocated block
+    int32_t bound_lo[3] = {0, 0, 0};
+    int32_t bound_hi[3] = {0, 0, 0};
+    // dense block page of the bounding box (ESDF, points, alignment field)
+    int32_t *page = nullptr;
+    int64_t page_cap = 0;
+    uint64_t version = 1;            // bumped by every state change
+    uint64_t page_version = 0;       // version the page was built from
+    uint64_t esdf_version = 0;
+    // registration points
+    float *pts = nullptr;
+    int64_t pts_cap = 0;
+    uint64_t pts_version = 0;
+    int64_t n_pts = 0;
+    double pbar[3] = {0, 0, 0};
+};
+
+struct covox_ctx {
+    covox_params p;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    std::vector<covox_submap *> subs;  // live submaps of this context
+    // integration scratch
+    uint32_t *cand = nullptr;
+    int64_t cand_cap = 0;
+    uint64_t *t_key = nullptr;
+    int64_t t_key_cap = 0;
+    uint32_t *t_idx = nullptr;
+    int64_t t_idx_cap = 0;
+    // EDT scratch over a dense block box
+    uint64_t *sites = nullptr;  // 8 words per dense block
+    int64_t sites_cap = 0;      // dense blocks
+    uint8_t *g1 = nullptr;      // 512 per dense block
+    int64_t g1_cap = 0;
+    uint16_t *g2 = nullptr;     // 512 per dense block
+    int64_t g2_cap = 0;
+    // registration-point scratch
+    uint32_t *cnt = nullptr;    // per-block counts, then offsets
+    int64_t cnt_cap = 0;
+    double *psum = nullptr;     // per-block point sums
+    int64_t psum_cap = 0;
+    // alignment scratch
+    void *prob_dev = nullptr;
+    int64_t prob_cap = 0;
+    void *res_dev = nullptr;
+    int64_t res_cap = 0;
+    // pinned host staging for small copies
+    void *host_pin = nullptr;
+    size_t host_pin_cap = 0;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+    double ms[COVOX_K_COUNT] = {0};
+    int64_t launches[COVOX_K_COUNT] = {0};
+};
+
+namespace covox {
+
+// Status helpers (api.hip).
+int fail(covox_ctx *ctx, int code, const std::string &msg);
+int hip_check(covox_ctx *ctx, hipError_t e, const char *what);
+
+// Event timing around one kernel launch (api.hip).
+struct TimedLaunch {
+    covox_ctx *ctx;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(covox_ctx *c, int k);
+    ~TimedLaunch();
+};
+
+// Device allocation helpers (api.hip): grow-only buffers.
+int ensure_buffer(covox_ctx *ctx, void **ptr, int64_t *cap, int64_t need, size_t elem, const char *what);
+
+// Orders the LDS accesses of one wave (the per-wave LDS regions need no
+// workgroup barrier).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Fill kernels (no hipMemsetAsync, so that callers may capture the work in
+// a graph).
+void fill_u64(hipStream_t s, uint64_t *p, uint64_t v, int64_t n);
+void fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n);
+
+// k_integrate.hip
+int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H, int32_t W,
+                    const float K[4], const double T_wc[16], bool *maybe_full);
+
+// k_esdf.hip
+int build_page(covox_ctx *ctx, covox_submap *s);   // page + site masks of the bounding box
+int update_esdf(covox_ctx *ctx, covox_submap *s);
+
+// k_align.hip
+int extract_points(covox_ctx *ctx, covox_submap *B);  // synchronous (count read back)
+
+struct AlignProblem {
+    const float *phi;            // field of A
+    const int32_t *page;         // A's page
+    const SubmapMeta *metaA;     // A's domain
+    const float *pts;            // points of B
+    int64_t n_pts;
+    double T[16];                // initial pose (B -> A)
+    int32_t max_iter;
+    int32_t pad;
+};
+
+struct AlignResult {
+    double T[16];
+    double ne[29];
+    double cost;
+    int64_t n_used;
+    int32_t iters;
+    int32_t status;
+};
+
+int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult *res);
+
+}  // namespace covox

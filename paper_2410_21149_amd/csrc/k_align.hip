@@ -1,0 +1,535 @@
+// Correspondence-free ESDF alignment of two submaps (paper Sec. I and
+// Sec. III-F: the registration term of Eq. (1); registration points chosen
+// by weight; residuals, Jacobians and the least-squares solve on the GPU).
+//
+// Registration points of B: zero crossings of D_B along voxel edges whose
+// endpoints are both in the band with W >= w_reg (k_iso_count, k_iso_scan,
+// k_iso_write; order = block buffer index, in-block index, axis).
+//
+// k_align: one workgroup per (pair, start), persistent over the
+// Gauss-Newton iterations.  Per point (binary32): q = T p, trilinear ESDF of
+// A and its gradient g, J = [g ; q x g]; exact binary64 products summed per
+// lane in binary64, then a fixed-order wave / workgroup reduction into the
+// 21 + 6 + 1 + 1 sums of the normal equations.  Lane 0 solves the 6x6 system
+// by binary64 Cholesky and applies T <- Exp(delta) T.
+#include "covox_impl.h"
+
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+namespace covox {
+
+namespace {
+
+template <typename S> __device__ __forceinline__ float ldw(const S *p);
+template <> __device__ __forceinline__ float ldw<float>(const float *p) { return *p; }
+template <> __device__ __forceinline__ float ldw<__half>(const __half *p) { return __half2float(*p); }
+
+struct DomArgs {
+    int32_t lo[3], dim[3];
+};
+
+__device__ __forceinline__ DomArgs dom_of(const SubmapMeta *m)
+{
+    DomArgs d;
+    for (int a = 0; a < 3; ++a) { d.lo[a] = m->dom_min[a]; d.dim[a] = m->dom_dim[a]; }
+    return d;
+}
+
+// Buffer index of block (bx, by, bz) through a dense page, -1 when absent.
+__device__ __forceinline__ int64_t page_lookup(const int32_t *page, const DomArgs &d, int bx, int by, int bz)
+{
+    const int x = bx - d.lo[0], y = by - d.lo[1], z = bz - d.lo[2];
+    if (x < 0 || y < 0 || z < 0 || x >= d.dim[0] || y >= d.dim[1] || z >= d.dim[2]) return -1;
+    return page[((int64_t)z * d.dim[1] + y) * d.dim[0] + x];
+}
+
+// The three +x, +y, +z edges of voxel lane + 64 z of block `idx`.
+template <typename S>
+__device__ __forceinline__ void edge_tests(const S *D, const S *W, int64_t idx, const int64_t nb[3], int lane, int z,
+                                           float tau, float wreg, bool ok[3], float Di_out[1], float Dn_out[3])
+{
+    const int x = lane & 7, y = lane >> 3;
+    const int64_t o = idx * 512 + lane + 64 * z;
+    const float Di = ldw(D + o), Wi = ldw(W + o);
+    Di_out[0] = Di;
+    const bool base = Wi >= wreg && fabsf(Di) < tau;
+    const int c[3] = {x, y, z};
+    const int step[3] = {1, 8, 64};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int64_t on;
+        if (c[a] < 7) on = o + step[a];
+        else on = nb[a] >= 0 ? nb[a] * 512 + (lane + 64 * z) - 7 * step[a] : -1;
+        ok[a] = false;
+        Dn_out[a] = 0.0f;
+        if (!base || on < 0) continue;
+        const float Dn = ldw(D + on), Wn = ldw(W + on);
+        Dn_out[a] = Dn;
+        ok[a] = Wn >= wreg && fabsf(Dn) < tau && ((Di < 0.0f) != (Dn < 0.0f));
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_iso(const SubmapMeta *__restrict__ meta, const uint64_t *__restrict__ keys,
+                                             const int32_t *__restrict__ page, const S *__restrict__ D,
+                                             const S *__restrict__ W, float vs, float tau, float wreg, int write,
+                                             uint32_t *__restrict__ cnt, float *__restrict__ pts,
+                                             double *__restrict__ psum)
+{
+    const int64_t nbk = meta->n_blocks;
+    const DomArgs dm = dom_of(meta);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t j = wave; j < nbk; j += nwaves) {
+        int bx, by, bz;
+        unpack_key(keys[j], bx, by, bz);
+        int64_t nb[3];
+        nb[0] = page_lookup(page, dm, bx + 1, by, bz);
+        nb[1] = page_lookup(page, dm, bx, by + 1, bz);
+        nb[2] = page_lookup(page, dm, bx, by, bz + 1);
+        int64_t base = write ? (int64_t)cnt[j] : 0;
+        uint32_t total = 0;
+        double s0 = 0, s1 = 0, s2 = 0;
+        for (int z = 0; z < 8; ++z) {
+            bool ok[3];
+            float Di, Dn[3];
+            edge_tests(D, W, j, nb, lane, z, tau, wreg, ok, &Di, Dn);
+            const int c = (int)ok[0] + (int)ok[1] + (int)ok[2];
+            // wave exclusive prefix of c (ascending lane = ascending l)
+            int incl = c;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y2 = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y2;
+            }
+            const int wtot = __shfl(incl, 63, 64);
+            if (write && c) {
+                int64_t at = base + (incl - c);
+                const int ix = 8 * bx + (lane & 7), iy = 8 * by + (lane >> 3), iz = 8 * bz + z;
+                const float cx = ((float)ix + 0.5f) * vs, cy = ((float)iy + 0.5f) * vs, cz = ((float)iz + 0.5f) * vs;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (!ok[a]) continue;
+                    const float sfr = Di / (Di - Dn[a]);
+                    float p[3] = {cx, cy, cz};
+                    p[a] = p[a] + sfr * vs;
+                    pts[3 * at + 0] = p[0];
+                    pts[3 * at + 1] = p[1];
+                    pts[3 * at + 2] = p[2];
+                    s0 += (double)p[0];
+                    s1 += (double)p[1];
+                    s2 += (double)p[2];
+                    ++at;
+                }
+            }
+            base += wtot;
+            total += (uint32_t)wtot;
+        }
+        if (!write) {
+            if (lane == 0) cnt[j] = total;
+        } else {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                s0 += __shfl_xor(s0, o, 64);
+                s1 += __shfl_xor(s1, o, 64);
+                s2 += __shfl_xor(s2, o, 64);
+            }
+            if (lane == 0) {
+                psum[3 * j + 0] = s0;
+                psum[3 * j + 1] = s1;
+                psum[3 * j + 2] = s2;
+            }
+        }
+    }
+}
+
+// Exclusive scan of cnt[0, n) in place (one 1024-lane workgroup, each lane a
+// contiguous chunk), total into meta->n_points.
+__global__ __launch_bounds__(1024) void k_iso_scan(SubmapMeta *meta, uint32_t *cnt)
+{
+    __shared__ int64_t lds[16];
+    const int64_t n = meta->n_blocks;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+    const int64_t C = (n + blockDim.x - 1) / blockDim.x;
+    const int64_t beg = std::min<int64_t>((int64_t)tid * C, n), end = std::min<int64_t>(beg + C, n);
+    int64_t s = 0;
+    for (int64_t j = beg; j < end; ++j) s += cnt[j];
+    int64_t x = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int64_t w = lane < nw ? lds[lane] : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(w, o, 64);
+            if (lane >= o) w += y;
+        }
+        if (lane < nw) lds[lane] = w;
+    }
+    __syncthreads();
+    int64_t run = (wid > 0 ? lds[wid - 1] : 0) + x - s;
+    for (int64_t j = beg; j < end; ++j) {
+        const uint32_t c = cnt[j];
+        cnt[j] = (uint32_t)run;
+        run += c;
+    }
+    if (tid == 0) meta->n_points = lds[nw - 1];
+}
+
+// Centroid of the points from per-block sums, summed in block order.
+__global__ void k_pbar(SubmapMeta *meta, const double *psum)
+{
+    if (threadIdx.x != 0) return;
+    const int64_t n = meta->n_blocks;
+    double s[3] = {0, 0, 0};
+    for (int64_t j = 0; j < n; ++j)
+        for (int a = 0; a < 3; ++a) s[a] += psum[3 * j + a];
+    const double np = (double)(meta->n_points > 0 ? meta->n_points : 1);
+    for (int a = 0; a < 3; ++a) meta->pbar[a] = s[a] / np;
+}
+
+// ------------------------------------------------------------ alignment
+
+__device__ __forceinline__ float phi_at(const float *phi, const int32_t *page, const DomArgs &d, int jx, int jy,
+                                        int jz)
+{
+    const int64_t idx = page_lookup(page, d, jx >> 3, jy >> 3, jz >> 3);
+    if (idx < 0) return __builtin_nanf("");
+    return phi[idx * 512 + (jx & 7) + 8 * (jy & 7) + 64 * (jz & 7)];
+}
+
+// Residual and Jacobian of one point; false when a cell corner is
+// unobserved (or the point is far outside A).
+__device__ __forceinline__ bool residual(const float *Tf, const float *p, float vs, const float *phi,
+                                         const int32_t *page, const DomArgs &d, float J[6], float &r)
+{
+    float q[3], f[3];
+    int j0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        q[a] = ((Tf[4 * a + 0] * p[0] + Tf[4 * a + 1] * p[1]) + Tf[4 * a + 2] * p[2]) + Tf[4 * a + 3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float g = (q[a] / vs) - 0.5f;
+        if (!(fabsf(g) < 1.0e8f)) return false;
+        const float fl = floorf(g);
+        j0[a] = (int)fl;
+        f[a] = g - fl;
+    }
+    float c[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        c[k] = phi_at(phi, page, d, j0[0] + (k & 1), j0[1] + ((k >> 1) & 1), j0[2] + ((k >> 2) & 1));
+    }
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ok = ok && !isnan(c[k]);
+    if (!ok) return false;
+    const float wx0 = 1.0f - f[0], wx1 = f[0], wy0 = 1.0f - f[1], wy1 = f[1], wz0 = 1.0f - f[2], wz1 = f[2];
+    const float c00 = c[0] * wx0 + c[1] * wx1, c10 = c[2] * wx0 + c[3] * wx1;
+    const float c01 = c[4] * wx0 + c[5] * wx1, c11 = c[6] * wx0 + c[7] * wx1;
+    const float c0 = c00 * wy0 + c10 * wy1, c1 = c01 * wy0 + c11 * wy1;
+    r = c0 * wz0 + c1 * wz1;
+    const float dx = ((c[1] - c[0]) * wy0 + (c[3] - c[2]) * wy1) * wz0 + ((c[5] - c[4]) * wy0 + (c[7] - c[6]) * wy1) * wz1;
+    const float dy = (c10 - c00) * wz0 + (c11 - c01) * wz1;
+    const float dz = c1 - c0;
+    const float g0 = dx / vs, g1 = dy / vs, g2 = dz / vs;
+    J[0] = g0;
+    J[1] = g1;
+    J[2] = g2;
+    J[3] = q[1] * g2 - q[2] * g1;
+    J[4] = q[2] * g0 - q[0] * g2;
+    J[5] = q[0] * g1 - q[1] * g0;
+    return true;
+}
+
+// 6x6 Cholesky solve of H x = -b (H from the packed upper triangle).
+__device__ bool solve6(const double *ne, double x[6])
+{
+    double L[6][6];
+    for (int j = 0; j < 6; ++j) {
+        for (int i = 0; i < 6; ++i) L[j][i] = 0.0;
+    }
+    auto Hat = [&](int a, int b) {
+        if (a > b) { const int t = a; a = b; b = t; }
+        return ne[a * 6 - a * (a - 1) / 2 + (b - a)];
+    };
+    for (int j = 0; j < 6; ++j) {
+        double s = Hat(j, j);
+        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+        if (!(s > 0.0)) return false;
+        L[j][j] = sqrt(s);
+        for (int i = j + 1; i < 6; ++i) {
+            double t = Hat(i, j);
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t / L[j][j];
+        }
+    }
+    double y[6];
+    for (int i = 0; i < 6; ++i) {
+        double t = -ne[21 + i];
+        for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
+        y[i] = t / L[i][i];
+    }
+    for (int i = 5; i >= 0; --i) {
+        double t = y[i];
+        for (int k = i + 1; k < 6; ++k) t -= L[k][i] * x[k];
+        x[i] = t / L[i][i];
+    }
+    return true;
+}
+
+// T <- Exp(xi) T for xi = (rho, theta); T is the top 3x4 of a rigid
+// transform, row-major.
+__device__ void se3_left_update(const double xi[6], double T[12])
+{
+    const double *w = xi + 3;
+    const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    const double th = sqrt(th2);
+    double A, B, C;
+    if (th < 1e-4) {
+        A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+        B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+        C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+    } else {
+        const double sh = sin(0.5 * th);
+        A = sin(th) / th;
+        B = 2.0 * sh * sh / th2;
+        C = (th - sin(th)) / (th2 * th);
+    }
+    const double K[3][3] = {{0, -w[2], w[1]}, {w[2], 0, -w[0]}, {-w[1], w[0], 0}};
+    double K2[3][3], Rm[3][3], V[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) K2[r][c] = K[r][0] * K[0][c] + K[r][1] * K[1][c] + K[r][2] * K[2][c];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            const double I = r == c ? 1.0 : 0.0;
+            Rm[r][c] = I + A * K[r][c] + B * K2[r][c];
+            V[r][c] = I + B * K[r][c] + C * K2[r][c];
+        }
+    double tE[3];
+    for (int r = 0; r < 3; ++r) tE[r] = V[r][0] * xi[0] + V[r][1] * xi[1] + V[r][2] * xi[2];
+    double O[12];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) O[4 * r + c] = (Rm[r][0] * T[c] + Rm[r][1] * T[4 + c]) + Rm[r][2] * T[8 + c];
+        O[4 * r + 3] = ((Rm[r][0] * T[3] + Rm[r][1] * T[7]) + Rm[r][2] * T[11]) + tE[r];
+    }
+    for (int k = 0; k < 12; ++k) T[k] = O[k];
+}
+
+constexpr int kAlignThreads = 256;
+
+__global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__restrict__ probs,
+                                                         const int32_t *__restrict__ order, AlignResult *res,
+                                                         float vs, double tol_rho, double tol_theta, int n_min)
+{
+    __shared__ double sT[12];
+    __shared__ float sTf[12];
+    __shared__ double red[kAlignThreads / 64][29];
+    __shared__ double tot[29];
+    __shared__ int s_state[3];  // final flag, iterations, status
+    const int pid = order[blockIdx.x];
+    const AlignProblem &P = probs[pid];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const DomArgs d = dom_of(P.metaA);
+    if (tid < 12) {
+        sT[tid] = P.T[tid];
+        sTf[tid] = (float)P.T[tid];
+    }
+    if (tid == 0) {
+        s_state[0] = 0;
+        s_state[1] = 0;
+        s_state[2] = COVOX_NOT_CONVERGED;
+    }
+    __syncthreads();
+    for (;;) {
+        double acc[29];
+#pragma unroll
+        for (int k = 0; k < 29; ++k) acc[k] = 0.0;
+        float Tf[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) Tf[k] = sTf[k];
+        for (int64_t i = tid; i < P.n_pts; i += kAlignThreads) {
+            const float p[3] = {P.pts[3 * i], P.pts[3 * i + 1], P.pts[3 * i + 2]};
+            float J[6], r;
+            if (!residual(Tf, p, vs, P.phi, P.page, d, J, r)) continue;
+            double Jd[6];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) Jd[a] = (double)J[a];
+            const double rd = (double)r;
+            int m = 0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+#pragma unroll
+                for (int b = a; b < 6; ++b) acc[m++] += Jd[a] * Jd[b];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) acc[21 + a] += Jd[a] * rd;
+            acc[27] += rd * rd;
+            acc[28] += 1.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 29; ++k) {
+            double v = acc[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) red[wid][k] = v;
+        }
+        __syncthreads();
+        if (tid < 29) {
+            double v = 0.0;
+            for (int w = 0; w < kAlignThreads / 64; ++w) v += red[w][tid];
+            tot[tid] = v;
+        }
+        __syncthreads();
+        bool stop = false;
+        if (tid == 0) {
+            if (s_state[0] || s_state[1] >= P.max_iter) {
+                stop = true;
+            } else if (tot[28] < (double)n_min) {
+                s_state[2] = COVOX_EDEGENERATE;
+                stop = true;
+            } else {
+                double dl[6];
+                if (!solve6(tot, dl)) {
+                    s_state[2] = COVOX_EDEGENERATE;
+                    stop = true;
+                } else {
+                    double T[12];
+                    for (int k = 0; k < 12; ++k) T[k] = sT[k];
+                    se3_left_update(dl, T);
+                    for (int k = 0; k < 12; ++k) {
+                        sT[k] = T[k];
+                        sTf[k] = (float)T[k];
+                    }
+                    s_state[1] += 1;
+                    const double nr = sqrt(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
+                    const double nt = sqrt(dl[3] * dl[3] + dl[4] * dl[4] + dl[5] * dl[5]);
+                    if (nr < tol_rho && nt < tol_theta) {
+                        s_state[2] = COVOX_OK;
+                        s_state[0] = 1;  // one more evaluation at the final pose
+                    }
+                }
+            }
+            red[0][0] = stop ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        stop = red[0][0] != 0.0;
+        __syncthreads();
+        if (stop) break;
+    }
+    if (tid == 0) {
+        AlignResult &R = res[pid];
+        for (int k = 0; k < 12; ++k) R.T[k] = sT[k];
+        R.T[12] = 0; R.T[13] = 0; R.T[14] = 0; R.T[15] = 1;
+        for (int k = 0; k < 29; ++k) R.ne[k] = tot[k];
+        R.n_used = (int64_t)tot[28];
+        R.cost = tot[28] > 0 ? tot[27] / tot[28] : __builtin_inf();
+        R.iters = s_state[1];
+        R.status = s_state[2];
+    }
+}
+
+unsigned grid_waves(int64_t waves)
+{
+    const int64_t g = (waves + 3) / 4;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+}  // namespace
+
+int extract_points(covox_ctx *ctx, covox_submap *B)
+{
+    if (B->pts_version == B->version) return COVOX_OK;
+    int rc;
+    if ((rc = build_page(ctx, B))) return rc;
+    const int64_t nbk = std::max<int64_t>(1, std::min(B->nb_upper, B->cap));
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->cnt, &ctx->cnt_cap, nbk, sizeof(uint32_t), "point counts"))) return rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->psum, &ctx->psum_cap, nbk, 3 * sizeof(double), "point sums")))
+        return rc;
+    const covox_params &p = ctx->p;
+    const float vs = (float)p.voxel_size, tau = (float)(p.trunc_vox * p.voxel_size), wreg = (float)p.w_reg;
+    const bool h = p.precision == COVOX_FP16;
+    {
+        TimedLaunch tl(ctx, COVOX_K_ISO);
+        if (h)
+            hipLaunchKernelGGL(k_iso<__half>, dim3(grid_waves(nbk)), dim3(256), 0, ctx->stream, B->meta, B->keys,
+                               B->page, (const __half *)B->D, (const __half *)B->W, vs, tau, wreg, 0, ctx->cnt,
+                               (float *)nullptr, (double *)nullptr);
+        else
+            hipLaunchKernelGGL(k_iso<float>, dim3(grid_waves(nbk)), dim3(256), 0, ctx->stream, B->meta, B->keys,
+                               B->page, (const float *)B->D, (const float *)B->W, vs, tau, wreg, 0, ctx->cnt,
+                               (float *)nullptr, (double *)nullptr);
+        hipLaunchKernelGGL(k_iso_scan, dim3(1), dim3(1024), 0, ctx->stream, B->meta, ctx->cnt);
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "point count launch"))) return rc;
+    SubmapMeta m;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(&m, B->meta, sizeof(m), hipMemcpyDeviceToHost, ctx->stream), "meta copy")))
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "point count sync"))) return rc;
+    const int64_t n = m.n_points;
+    if ((rc = ensure_buffer(ctx, (void **)&B->pts, &B->pts_cap, std::max<int64_t>(n, 1), 3 * sizeof(float), "points")))
+        return rc;
+    {
+        TimedLaunch tl(ctx, COVOX_K_ISO);
+        if (h)
+            hipLaunchKernelGGL(k_iso<__half>, dim3(grid_waves(nbk)), dim3(256), 0, ctx->stream, B->meta, B->keys,
+                               B->page, (const __half *)B->D, (const __half *)B->W, vs, tau, wreg, 1, ctx->cnt, B->pts,
+                               ctx->psum);
+        else
+            hipLaunchKernelGGL(k_iso<float>, dim3(grid_waves(nbk)), dim3(256), 0, ctx->stream, B->meta, B->keys,
+                               B->page, (const float *)B->D, (const float *)B->W, vs, tau, wreg, 1, ctx->cnt, B->pts,
+                               ctx->psum);
+        hipLaunchKernelGGL(k_pbar, dim3(1), dim3(64), 0, ctx->stream, B->meta, ctx->psum);
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "point write launch"))) return rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(&m, B->meta, sizeof(m), hipMemcpyDeviceToHost, ctx->stream), "meta copy")))
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "point write sync"))) return rc;
+    B->n_pts = n;
+    for (int a = 0; a < 3; ++a) B->pbar[a] = m.pbar[a];
+    B->pts_version = B->version;
+    return COVOX_OK;
+}
+
+int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult *res)
+{
+    if (n <= 0) return COVOX_OK;
+    int rc;
+    const size_t pbytes = sizeof(AlignProblem) * n + sizeof(int32_t) * n;
+    if ((rc = ensure_buffer(ctx, &ctx->prob_dev, &ctx->prob_cap, (int64_t)pbytes, 1, "problems"))) return rc;
+    if ((rc = ensure_buffer(ctx, &ctx->res_dev, &ctx->res_cap, (int64_t)(sizeof(AlignResult) * n), 1, "results")))
+        return rc;
+    // longest problems first so that the hardware dispatches them early
+    std::vector<int32_t> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].n_pts > probs[b].n_pts; });
+    std::vector<char> stage(pbytes);
+    ::memcpy(stage.data(), probs, sizeof(AlignProblem) * n);
+    ::memcpy(stage.data() + sizeof(AlignProblem) * n, order.data(), sizeof(int32_t) * n);
+    if ((rc = hip_check(ctx, hipMemcpyAsync(ctx->prob_dev, stage.data(), pbytes, hipMemcpyHostToDevice, ctx->stream),
+                        "problem upload")))
+        return rc;
+    const AlignProblem *dprob = (const AlignProblem *)ctx->prob_dev;
+    const int32_t *dorder = (const int32_t *)((const char *)ctx->prob_dev + sizeof(AlignProblem) * n);
+    {
+        TimedLaunch tl(ctx, COVOX_K_ALIGN);
+        hipLaunchKernelGGL(k_align, dim3(n), dim3(kAlignThreads), 0, ctx->stream, dprob, dorder,
+                           (AlignResult *)ctx->res_dev, (float)ctx->p.voxel_size, ctx->p.tol_rho, ctx->p.tol_theta,
+                           ctx->p.n_min);
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "align launch"))) return rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(res, ctx->res_dev, sizeof(AlignResult) * n, hipMemcpyDeviceToHost,
+                                            ctx->stream),
+                        "result copy")))
+        return rc;
+    return hip_check(ctx, hipStreamSynchronize(ctx->stream), "align sync");
+}
+
+}  // namespace covox

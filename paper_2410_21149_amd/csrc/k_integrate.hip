@@ -1,0 +1,394 @@
+// Projective TSDF integration (paper Sec. III-C projection mapping; the
+// count / allocate / update phases of Sec. III-D).
+//
+// One frame is three launches on the context stream:
+//   k_probe      one wave64 per block of the frustum's block box: the 512
+//                voxels are tested for validity (lane = (x, y), z in a loop),
+//                a ballot gives "any valid", lane 0 looks the key up in the
+//                hash table (existing buffer index, or NEW);
+//   k_scan       one 1024-lane workgroup compacts the probe results in box
+//                order -- which is ascending packed-key order -- so new
+//                blocks receive n_blocks + rank deterministically; it checks
+//                capacity before anything is committed;
+//   k_integrate  one wave64 per touched block: activates new blocks (key
+//                store + hash insert, zero-initialised voxels) and applies
+//                the running-average update to every valid voxel.
+// Parity-relevant arithmetic is binary32 in a fixed operation order (the
+// library is built with -ffp-contract=off; division is correctly rounded).
+#include "covox_impl.h"
+
+#include <math.h>
+
+#include <algorithm>
+
+namespace covox {
+
+namespace {
+
+constexpr uint32_t kNew = 0xFFFFFFFFu;
+
+template <typename S> __device__ __forceinline__ float ld(const S *p);
+template <> __device__ __forceinline__ float ld<float>(const float *p) { return *p; }
+template <> __device__ __forceinline__ float ld<__half>(const __half *p) { return __half2float(*p); }
+template <typename S> __device__ __forceinline__ void st(S *p, float v);
+template <> __device__ __forceinline__ void st<float>(float *p, float v) { *p = v; }
+template <> __device__ __forceinline__ void st<__half>(__half *p, float v) { *p = __float2half_rn(v); }
+
+// Validity of voxel (ix, iy, iz) under the frame's projection and its
+// signed distance (depth minus voxel depth).
+__device__ __forceinline__ bool proj_valid(const FrameArgs &f, float vs, float tau, float maxr, int ix,
+                                           int iy, int iz, float &sdf)
+{
+    const float cx = ((float)ix + 0.5f) * vs;
+    const float cy = ((float)iy + 0.5f) * vs;
+    const float cz = ((float)iz + 0.5f) * vs;
+    const float px = ((f.R[0] * cx + f.R[1] * cy) + f.R[2] * cz) + f.t[0];
+    const float py = ((f.R[3] * cx + f.R[4] * cy) + f.R[5] * cz) + f.t[1];
+    const float pz = ((f.R[6] * cx + f.R[7] * cy) + f.R[8] * cz) + f.t[2];
+    if (!(pz > 0.0f)) return false;
+    const float u = ((f.K[0] * px) / pz) + f.K[2];
+    const float v = ((f.K[1] * py) / pz) + f.K[3];
+    const float uf = floorf(u + 0.5f);
+    const float vf = floorf(v + 0.5f);
+    if (!(uf >= 0.0f && uf < (float)f.W && vf >= 0.0f && vf < (float)f.H)) return false;
+    const float d = f.depth[(int64_t)(int)vf * f.W + (int)uf];
+    if (!(d > 0.0f && d <= maxr)) return false;
+    sdf = d - pz;
+    return sdf >= -tau;
+}
+
+__device__ __forceinline__ void box_block(const FrameArgs &f, int64_t j, int &bx, int &by, int &bz)
+{
+    const int64_t nz = f.bdim[2], ny = f.bdim[1];
+    bz = f.blo[2] + (int)(j % nz);
+    by = f.blo[1] + (int)((j / nz) % ny);
+    bx = f.blo[0] + (int)(j / (nz * ny));
+}
+
+__global__ __launch_bounds__(256) void k_probe(FrameArgs f, float vs, float tau, float maxr,
+                                               const uint64_t *__restrict__ tkeys,
+                                               const uint32_t *__restrict__ tvals, uint64_t tmask,
+                                               uint32_t *__restrict__ cand, int64_t n_box)
+{
+    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (j >= n_box) return;  // uniform across the wave
+    int bx, by, bz;
+    box_block(f, j, bx, by, bz);
+    const int ix = 8 * bx + (lane & 7);
+    const int iy = 8 * by + (lane >> 3);
+    bool any = false;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        float sdf;
+        any |= proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf);
+    }
+    const uint64_t m = __ballot(any);
+    if (lane == 0) {
+        uint32_t out = 0;
+        if (m) {
+            const int64_t idx = hash_find(tkeys, tvals, tmask, pack_key(bx, by, bz));
+            out = idx >= 0 ? (uint32_t)idx + 1u : kNew;
+        }
+        cand[j] = out;
+    }
+}
+
+// Exclusive scan of one int64 per thread over a 1024-thread workgroup.
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t *lds, int64_t *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int64_t w = lane < nw ? lds[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int64_t y = __shfl_up(w, o, 64);
+            if (lane >= o) w += y;
+        }
+        if (lane < nw) lds[lane] = w;  // inclusive wave totals
+    }
+    __syncthreads();
+    const int64_t before = (wid > 0 ? lds[wid - 1] : 0) + x - v;
+    *total = lds[nw - 1];
+    __syncthreads();
+    return before;
+}
+
+__global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand, int64_t n_box, FrameArgs f,
+                                               SubmapMeta *meta, int64_t cap, int64_t table_limit,
+                                               uint64_t *__restrict__ t_key, uint32_t *__restrict__ t_idx)
+{
+    __shared__ int64_t lds[16];
+    __shared__ int32_t red[6][16];
+    const int tid = threadIdx.x;
+    const int64_t C = (n_box + blockDim.x - 1) / blockDim.x;
+    const int64_t beg = std::min<int64_t>((int64_t)tid * C, n_box);
+    const int64_t end = std::min<int64_t>(beg + C, n_box);
+    int64_t nt = 0, nn = 0;
+    for (int64_t j = beg; j < end; ++j) {
+        const uint32_t v = cand[j];
+        nt += v != 0;
+        nn += v == kNew;
+    }
+    int64_t tot_t, tot_n;
+    int64_t off_t = block_exclusive_scan(nt, lds, &tot_t);
+    int64_t off_n = block_exclusive_scan(nn, lds, &tot_n);
+    const int64_t n0 = meta->n_blocks;
+    __syncthreads();  // every thread has read n_blocks before it changes
+    const bool pool_full = n0 + tot_n > cap;
+    const bool table_full = n0 + tot_n > table_limit;
+    if (pool_full || table_full) {
+        if (tid == 0) {
+            meta->status = pool_full ? COVOX_EPOOL_FULL : COVOX_ETABLE_FULL;
+            meta->n_new = 0;
+            meta->n_touched = 0;
+        }
+        return;
+    }
+    int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int64_t j = beg; j < end; ++j) {
+        const uint32_t v = cand[j];
+        if (!v) continue;
+        int bx, by, bz;
+        box_block(f, j, bx, by, bz);
+        uint32_t idx;
+        if (v == kNew) {
+            idx = (uint32_t)(n0 + off_n++) | 0x80000000u;
+            lo[0] = min(lo[0], bx); lo[1] = min(lo[1], by); lo[2] = min(lo[2], bz);
+            hi[0] = max(hi[0], bx); hi[1] = max(hi[1], by); hi[2] = max(hi[2], bz);
+        } else {
+            idx = v - 1u;
+        }
+        t_key[off_t] = pack_key(bx, by, bz);
+        t_idx[off_t] = idx;
+        ++off_t;
+    }
+    // box of the new blocks: wave reduction, then across waves
+    const int lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
+            hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
+        }
+        if (lane == 0) { red[a][wid] = lo[a]; red[3 + a][wid] = hi[a]; }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int32_t L[3], Hh[3];
+        for (int a = 0; a < 3; ++a) {
+            L[a] = INT32_MAX; Hh[a] = INT32_MIN;
+            for (int w = 0; w < nw; ++w) { L[a] = min(L[a], red[a][w]); Hh[a] = max(Hh[a], red[3 + a][w]); }
+        }
+        if (tot_n > 0) {
+            for (int a = 0; a < 3; ++a) {
+                if (n0 == 0) { meta->bmin[a] = L[a]; meta->bmax[a] = Hh[a]; }
+                else { meta->bmin[a] = min(meta->bmin[a], L[a]); meta->bmax[a] = max(meta->bmax[a], Hh[a]); }
+            }
+        }
+        meta->n_blocks = n0 + tot_n;
+        meta->n_new = (int32_t)tot_n;
+        meta->n_touched = (int32_t)tot_t;
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float tau, float maxr,
+                                                   const SubmapMeta *__restrict__ meta,
+                                                   const uint64_t *__restrict__ t_key,
+                                                   const uint32_t *__restrict__ t_idx, uint64_t *keys, S *D, S *W,
+                                                   uint64_t *tkeys, uint32_t *tvals, uint64_t tmask)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t n_t = meta->n_touched;
+    for (int64_t t = wave; t < n_t; t += nwaves) {
+        const uint64_t key = t_key[t];
+        const uint32_t v = t_idx[t];
+        const bool is_new = (v >> 31) != 0;
+        const int64_t idx = v & 0x7FFFFFFFu;
+        int bx, by, bz;
+        unpack_key(key, bx, by, bz);
+        if (is_new && lane == 0) {
+            keys[idx] = key;
+            hash_insert(tkeys, tvals, tmask, key, (uint32_t)idx);
+        }
+        const int ix = 8 * bx + (lane & 7);
+        const int iy = 8 * by + (lane >> 3);
+        S *Db = D + idx * 512 + lane;
+        S *Wb = W + idx * 512 + lane;
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+            float sdf;
+            const bool ok = proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf);
+            if (ok) {
+                const float Dv = is_new ? 0.0f : ld(Db + 64 * z);
+                const float Wv = is_new ? 0.0f : ld(Wb + 64 * z);
+                const float tr = fminf(sdf, tau);
+                const float Wn = Wv + 1.0f;
+                const float Dn = ((Dv * Wv) + (tr * 1.0f)) / Wn;
+                st(Db + 64 * z, Dn);
+                st(Wb + 64 * z, Wn);
+            } else if (is_new) {
+                st(Db + 64 * z, 0.0f);
+                st(Wb + 64 * z, 0.0f);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host
+
+void rigid_inverse(const double *T, double *O)
+{
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) O[4 * r + c] = T[4 * c + r];
+    for (int r = 0; r < 3; ++r)
+        O[4 * r + 3] = -((O[4 * r + 0] * T[3] + O[4 * r + 1] * T[7]) + O[4 * r + 2] * T[11]);
+    O[12] = 0; O[13] = 0; O[14] = 0; O[15] = 1;
+}
+
+void rigid_mul(const double *A, const double *B, double *O)
+{
+    double t[16];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c)
+            t[4 * r + c] = (A[4 * r + 0] * B[c] + A[4 * r + 1] * B[4 + c]) + A[4 * r + 2] * B[8 + c];
+        t[4 * r + 3] = ((A[4 * r + 0] * B[3] + A[4 * r + 1] * B[7]) + A[4 * r + 2] * B[11]) + A[4 * r + 3];
+    }
+    t[12] = 0; t[13] = 0; t[14] = 0; t[15] = 1;
+    for (int k = 0; k < 16; ++k) O[k] = t[k];
+}
+
+bool is_rigid(const double *T)
+{
+    for (int k = 0; k < 16; ++k)
+        if (!std::isfinite(T[k])) return false;
+    if (T[12] != 0 || T[13] != 0 || T[14] != 0 || T[15] != 1) return false;
+    double e = 0;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k) s += T[4 * k + r] * T[4 * k + c];
+            e = std::max(e, std::fabs(s - (r == c ? 1.0 : 0.0)));
+        }
+    const double det = T[0] * (T[5] * T[10] - T[6] * T[9]) - T[1] * (T[4] * T[10] - T[6] * T[8]) +
+                       T[2] * (T[4] * T[9] - T[5] * T[8]);
+    return e <= 1e-6 && det > 0;
+}
+
+}  // namespace
+
+int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H, int32_t W,
+                    const float K[4], const double T_wc[16], bool *maybe_full)
+{
+    const covox_params &p = ctx->p;
+    if (!depth || H <= 0 || W <= 0 || !K || !T_wc) return fail(ctx, COVOX_EINVAL, "integrate: bad argument");
+    if (!(K[0] > 0) || !(K[1] > 0) || !std::isfinite(K[2]) || !std::isfinite(K[3]))
+        return fail(ctx, COVOX_EINVAL, "integrate: fx and fy must be positive");
+    if (!is_rigid(T_wc)) return fail(ctx, COVOX_EINVAL, "integrate: T_world_cam is not a rigid transform");
+
+    // camera <- submap, binary64, rounded once to binary32
+    double inv_wc[16], T_cs[16];
+    rigid_inverse(T_wc, inv_wc);
+    rigid_mul(inv_wc, s->T_ws, T_cs);
+    FrameArgs f;
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) f.R[3 * r + c] = (float)T_cs[4 * r + c];
+        f.t[r] = (float)T_cs[4 * r + 3];
+    }
+    for (int k = 0; k < 4; ++k) f.K[k] = K[k];
+    f.H = H;
+    f.W = W;
+    f.depth = depth;
+
+    // Block box containing every voxel centre of the frustum cut at
+    // max_range + tau (conservative; validity decides exactly).
+    double inv_ws[16], T_sc[16];
+    rigid_inverse(s->T_ws, inv_ws);
+    rigid_mul(inv_ws, T_wc, T_sc);
+    const double tau = p.trunc_vox * p.voxel_size;
+    const double zf = p.max_range + tau;
+    double mn[3], mx[3];
+    for (int a = 0; a < 3; ++a) mn[a] = mx[a] = T_sc[4 * a + 3];
+    const double us[2] = {-0.5, W - 0.5}, vv[2] = {-0.5, H - 0.5};
+    for (double u : us)
+        for (double v : vv) {
+            const double pc[3] = {(u - K[2]) / K[0] * zf, (v - K[3]) / K[1] * zf, zf};
+            for (int a = 0; a < 3; ++a) {
+                const double w = T_sc[4 * a] * pc[0] + T_sc[4 * a + 1] * pc[1] + T_sc[4 * a + 2] * pc[2] + T_sc[4 * a + 3];
+                mn[a] = std::min(mn[a], w);
+                mx[a] = std::max(mx[a], w);
+            }
+        }
+    int64_t n_box = 1;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t ilo = (int64_t)std::floor(mn[a] / p.voxel_size - 0.5) - 1;
+        const int64_t ihi = (int64_t)std::ceil(mx[a] / p.voxel_size - 0.5) + 1;
+        const int64_t blo = ilo >= 0 ? ilo / 8 : -((-ilo + 7) / 8);
+        const int64_t bhi = ihi >= 0 ? ihi / 8 : -((-ihi + 7) / 8);
+        if (blo < -kKeyOff + 1 || bhi > kKeyOff - 2)
+            return fail(ctx, COVOX_EINVAL, "integrate: frustum outside the addressable block range");
+        f.blo[a] = (int32_t)blo;
+        f.bdim[a] = (int32_t)(bhi - blo + 1);
+        n_box *= f.bdim[a];
+    }
+
+    int rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->cand, &ctx->cand_cap, n_box, sizeof(uint32_t), "candidates")))
+        return rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->t_key, &ctx->t_key_cap, n_box, sizeof(uint64_t), "touched keys")))
+        return rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->t_idx, &ctx->t_idx_cap, n_box, sizeof(uint32_t), "touched index")))
+        return rc;
+
+    const float vs = (float)p.voxel_size, tau_f = (float)tau, maxr = (float)p.max_range;
+    const uint64_t tmask = (uint64_t)s->tcap - 1;
+    const int64_t table_limit = (int64_t)(0.85 * (double)s->tcap);
+    const unsigned grid = (unsigned)((n_box + 3) / 4);
+    {
+        TimedLaunch tl(ctx, COVOX_K_PROBE);
+        hipLaunchKernelGGL(k_probe, dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau_f, maxr, s->tkeys, s->tvals,
+                           tmask, ctx->cand, n_box);
+    }
+    {
+        TimedLaunch tl(ctx, COVOX_K_SCAN);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, ctx->stream, ctx->cand, n_box, f, s->meta, s->cap,
+                           table_limit, ctx->t_key, ctx->t_idx);
+    }
+    {
+        TimedLaunch tl(ctx, COVOX_K_INTEGRATE);
+        if (p.precision == COVOX_FP16)
+            hipLaunchKernelGGL(k_integrate<__half>, dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau_f, maxr,
+                               s->meta, ctx->t_key, ctx->t_idx, s->keys, (__half *)s->D, (__half *)s->W,
+                               s->tkeys, s->tvals, tmask);
+        else
+            hipLaunchKernelGGL(k_integrate<float>, dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau_f, maxr,
+                               s->meta, ctx->t_key, ctx->t_idx, s->keys, (float *)s->D, (float *)s->W, s->tkeys,
+                               s->tvals, tmask);
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "integrate launch"))) return rc;
+
+    // host-side bounds
+    s->nb_upper += n_box;
+    for (int a = 0; a < 3; ++a) {
+        const int32_t lo = f.blo[a], hi = f.blo[a] + f.bdim[a] - 1;
+        if (!s->bound_valid) { s->bound_lo[a] = lo; s->bound_hi[a] = hi; }
+        else { s->bound_lo[a] = std::min(s->bound_lo[a], lo); s->bound_hi[a] = std::max(s->bound_hi[a], hi); }
+    }
+    s->bound_valid = true;
+    s->version++;
+    *maybe_full = s->nb_upper > s->cap || s->nb_upper > table_limit;
+    return COVOX_OK;
+}
+
+}  // namespace covox

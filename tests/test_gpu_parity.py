@@ -1,0 +1,286 @@
+"""GPU parity: the HIP library (through the C ABI) against the reference
+checker on the same seeded inputs.
+
+Bars: allocated block set, buffer indices and home buckets bit-exact; TSDF D
+and W within 1e-4 m (binary32 storage; bit-exact expected, same pinned
+operation order); ESDF phi within 1e-4 m with identical unobserved sets;
+poses within 1e-6 (translation in m, rotation angle in rad)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def cv():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_21149_amd as cv
+    return cv
+
+
+def _ctx(cv, **kw):
+    base = dict(voxel_size=0.05, trunc_vox=4, max_range=5.0, d_max=2.0, block_capacity=8192)
+    base.update(kw)
+    return cv.Context(**base)
+
+
+def _oracle_params(**kw):
+    base = dict(vs=0.05, trunc_vox=4, max_range=5.0, d_max=2.0)
+    base.update(kw)
+    return orc.Params(**base)
+
+
+def _compare_blocks(g, r, table_cap, fp16=False):
+    assert np.array_equal(g["keys"], r["keys"]), "block keys / buffer order differ"
+    assert np.array_equal(g["home"].astype(np.int64), orc.home_bucket(r["keys"], table_cap)), "home buckets differ"
+    dD = np.abs(g["D"].astype(np.float64) - r["D"])
+    dW = np.abs(g["W"].astype(np.float64) - r["W"])
+    assert dD.max(initial=0) <= TOL and dW.max(initial=0) <= TOL
+    return int(np.count_nonzero(dD)), int(np.count_nonzero(dW))
+
+
+def _compare_phi(g, r):
+    gp, rp = g["phi"].astype(np.float64), r["phi"]
+    assert np.array_equal(np.isnan(gp), np.isnan(rp)), "unobserved sets differ"
+    m = ~np.isnan(rp)
+    d = np.abs(gp[m] - rp[m])
+    assert d.max(initial=0) <= TOL, d.max()
+    return int(np.count_nonzero(d))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_tiny_integration_and_esdf_parity(cv, precision):
+    import torch
+    w = sg.tiny()
+    fr = w.frames()
+    fp16 = precision == "fp16"
+    ctx = _ctx(cv, precision=cv.FP16 if fp16 else cv.FP32)
+    s = ctx.submap_create()
+    ref = orc.Submap(_oracle_params(fp16=fp16))
+    dev = torch.from_numpy(fr).cuda()
+    tcap = ctx.submap_info(s)["table_capacity"]
+    for f in range(w.n_frames):
+        ctx.integrate_depth(s, dev[f], w.cam.K, w.poses[f])
+        ref.integrate(fr[f], w.cam.K, w.poses[f])
+        if f in (0, 1, 7, 19):
+            nd, nw = _compare_blocks(ctx.export_blocks(s), ref.export(), tcap, fp16)
+            assert nd == 0 and nw == 0, "expected bit-exact TSDF (frame %d)" % f
+    ctx.update_esdf(s)
+    ref.update_esdf()
+    assert _compare_phi(ctx.export_blocks(s), ref.export()) == 0
+    ctx.close()
+
+
+def test_room_full_sequence_parity(cv):
+    """The 300-frame 640x480 room sequence (the benchmark workload),
+    integrated with an ESDF update after every frame as the benchmark does;
+    full comparison at the end and at frame 40."""
+    import torch
+    w = sg.room()
+    ctx = _ctx(cv, block_capacity=16384)
+    s = ctx.submap_create()
+    ref = orc.Submap(_oracle_params())
+    tcap = ctx.submap_info(s)["table_capacity"]
+    for f0 in range(0, w.n_frames, 50):
+        fr = w.frames(f0, min(f0 + 50, w.n_frames))
+        dev = torch.from_numpy(fr).cuda()
+        for k in range(len(fr)):
+            ctx.integrate_depth(s, dev[k], w.cam.K, w.poses[f0 + k])
+            ctx.update_esdf(s)
+            ref.integrate(fr[k], w.cam.K, w.poses[f0 + k])
+            if f0 + k == 40:
+                ref.update_esdf()
+                g = ctx.export_blocks(s)
+                r = ref.export()
+                assert _compare_blocks(g, r, tcap) == (0, 0)
+                assert _compare_phi(g, r) == 0
+    ref.update_esdf()
+    g, r = ctx.export_blocks(s), ref.export()
+    assert _compare_blocks(g, r, tcap) == (0, 0)
+    assert _compare_phi(g, r) == 0
+    assert len(g["keys"]) > 1000
+    ctx.close()
+
+
+def test_determinism_two_runs(cv):
+    import torch
+    w = sg.tiny()
+    dev = torch.from_numpy(w.frames()).cuda()
+    outs = []
+    for _ in range(2):
+        ctx = _ctx(cv)
+        s = ctx.submap_create()
+        for f in range(w.n_frames):
+            ctx.integrate_depth(s, dev[f], w.cam.K, w.poses[f])
+        ctx.update_esdf(s)
+        outs.append(ctx.export_blocks(s))
+        ctx.close()
+    for k in ("keys", "home", "D", "W"):
+        assert np.array_equal(outs[0][k], outs[1][k])
+    assert np.array_equal(outs[0]["phi"], outs[1]["phi"], equal_nan=True)
+
+
+def test_batch_integration_equals_sequential(cv):
+    import torch
+    w = sg.tiny()
+    dev = torch.from_numpy(w.frames()).cuda()
+    ctx = _ctx(cv)
+    a = ctx.submap_create()
+    b = ctx.submap_create()
+    for f in range(w.n_frames):
+        ctx.integrate_depth(a, dev[f], w.cam.K, w.poses[f])
+    ctx.integrate_depth_batch(b, dev, w.cam.K, w.poses)
+    ea, eb = ctx.export_blocks(a), ctx.export_blocks(b)
+    for k in ("keys", "home", "D", "W"):
+        assert np.array_equal(ea[k], eb[k])
+    ctx.close()
+
+
+def test_empty_and_invalid_frames(cv):
+    import torch
+    K = np.array([11.0, 12.5, 7.37, 5.61], np.float32)
+    ctx = _ctx(cv)
+    s = ctx.submap_create()
+    for v in (0.0, float("nan"), 5.5, -1.0):
+        ctx.integrate_depth(s, torch.full((12, 16), v, device="cuda"), K, np.eye(4))
+    assert ctx.submap_info(s)["n_blocks"] == 0
+    ctx.update_esdf(s)  # an empty submap is a no-op
+    with pytest.raises(cv.CovoxError):
+        ctx.integrate_depth(s, torch.zeros((12, 16), device="cuda"), np.array([0, 1, 1, 1], np.float32), np.eye(4))
+    bad = np.eye(4)
+    bad[0, 0] = 2.0
+    with pytest.raises(cv.CovoxError):
+        ctx.integrate_depth(s, torch.zeros((12, 16), device="cuda"), K, bad)
+    ctx.close()
+
+
+def test_pool_full_leaves_submap_unchanged(cv):
+    """A frame that needs more blocks than remain is dropped whole and the
+    call reports EPOOL_FULL; a frame that fits still integrates."""
+    import torch
+    w = sg.tiny()
+    fr = w.frames(0, 3)
+    dev = torch.from_numpy(fr).cuda()
+    ref = orc.Submap(_oracle_params())
+    st0 = ref.integrate(fr[0], w.cam.K, w.poses[0])
+    cap = st0["n_new"] + 5
+    ctx = _ctx(cv, block_capacity=cap)
+    s = ctx.submap_create()
+    ctx.integrate_depth(s, dev[0], w.cam.K, w.poses[0])
+    before = ctx.export_blocks(s)
+    with pytest.raises(cv.CovoxError) as e:
+        ctx.integrate_depth(s, torch.from_numpy(w.frame(10)).cuda(), w.cam.K, w.poses[10])
+    assert e.value.code == cv.EPOOL_FULL
+    after = ctx.export_blocks(s)
+    for k in ("keys", "D", "W"):
+        assert np.array_equal(before[k], after[k])
+    ctx.integrate_depth(s, dev[0], w.cam.K, w.poses[0])  # re-observing fits
+    assert ctx.submap_info(s)["n_blocks"] == len(before["keys"])
+    ctx.close()
+
+
+# ------------------------------------------------------------------ align
+
+def _pair_from_tiny(cv, ctx):
+    """A: frames 0-9, B: frames 10-19 of the tiny room, both in the world
+    frame, so the true transform is the identity."""
+    import torch
+    w = sg.tiny()
+    fr = w.frames()
+    dev = torch.from_numpy(fr).cuda()
+    A, B = ctx.submap_create(), ctx.submap_create()
+    rA, rB = orc.Submap(_oracle_params()), orc.Submap(_oracle_params())
+    for f in range(20):
+        for _ in range(2):  # each frame twice: weights >= 2 for registration points
+            ctx.integrate_depth(A if f < 10 else B, dev[f], w.cam.K, w.poses[f])
+            (rA if f < 10 else rB).integrate(fr[f], w.cam.K, w.poses[f])
+    for f in range(20):  # overlap: both submaps also see a few frames of the other half
+        if f % 5 == 0:
+            ctx.integrate_depth(B if f < 10 else A, dev[f], w.cam.K, w.poses[f])
+            (rB if f < 10 else rA).integrate(fr[f], w.cam.K, w.poses[f])
+    ctx.update_esdf(A)
+    ctx.update_esdf(B)
+    rA.update_esdf()
+    rB.update_esdf()
+    return A, B, rA, rB
+
+
+def _pose_err(T1, T2):
+    dt = np.linalg.norm(T1[:3, 3] - T2[:3, 3])
+    c = (np.trace(T1[:3, :3] @ T2[:3, :3].T) - 1) / 2
+    return dt, math.acos(max(-1.0, min(1.0, c)))
+
+
+def test_registration_points_and_normal_equations_parity(cv):
+    ctx = _ctx(cv)
+    A, B, rA, rB = _pair_from_tiny(cv, ctx)
+    pg = ctx.export_points(B)
+    pr = rB.iso_points()
+    assert pg.shape == pr.shape and len(pg) > 1000
+    assert np.array_equal(pg, pr), "registration points differ"
+    T = orc.se3_exp(np.array([0.01, -0.02, 0.005, 0.01, 0.02, -0.015]))
+    ne_g = ctx.normal_equations(A, B, T)
+    ne_r = orc.normal_eq(rA, pr, T)[4]
+    assert ne_g[28] == ne_r[28]  # identical residual set
+    assert np.allclose(ne_g, ne_r, rtol=1e-12, atol=1e-9)
+    ctx.close()
+
+
+def test_alignment_pose_parity_and_recovery(cv):
+    ctx = _ctx(cv)
+    A, B, rA, rB = _pair_from_tiny(cv, ctx)
+    pts = rB.iso_points()
+    for xi in ([0.03, -0.02, 0.01, 0.02, -0.01, 0.03], [-0.05, 0.04, 0.0, 0.0, 0.0, 0.08]):
+        T0 = orc.se3_exp(np.array(xi))
+        Tg, cg, st = ctx.align_submaps(A, B, T0)
+        r = orc.align(rA, pts, T0)
+        assert st["status"] == r["status"] and st["iterations"] == r["iters"] and st["n_used"] == r["n"]
+        dt, dr = _pose_err(Tg, r["T"])
+        assert dt <= 1e-6 and dr <= 1e-6, (dt, dr)
+        assert abs(cg - r["cost"]) <= 1e-9 + 1e-9 * r["cost"]
+        et, er = _pose_err(Tg, np.eye(4))
+        assert et < 0.01 and er < math.radians(0.1), (et, er)
+    ctx.close()
+
+
+def test_multistart_and_batch_match_single_calls(cv):
+    ctx = _ctx(cv)
+    A, B, rA, rB = _pair_from_tiny(cv, ctx)
+    pts = rB.iso_points()
+    T0 = orc.se3_exp(np.array([0.02, 0.01, -0.01, 0.0, 0.0, 0.5]))
+    Tm, cm, sm = ctx.align_multistart(A, B, T0, 8)
+    rm = orc.align_multistart(rA, pts, T0, 8)
+    assert sm["best_start"] == rm["best"]
+    dt, dr = _pose_err(Tm, rm["T"])
+    assert dt <= 1e-6 and dr <= 1e-6
+    pairs = [(A, B, T0), (A, B, orc.se3_exp(np.array([0.01, 0, 0, 0, 0, 0.01])))]
+    Tb, cb, sb = ctx.align_batch(pairs, n_starts=8)
+    assert np.array_equal(Tb[0], Tm) and cb[0] == cm
+    T1, c1, s1 = ctx.align_submaps(A, B, pairs[1][2])
+    Tb1, cb1, _ = ctx.align_batch(pairs[1:], n_starts=1)
+    assert np.array_equal(Tb1[0], T1) and cb1[0] == c1
+    ctx.close()
+
+
+def test_alignment_needs_current_esdf_and_enough_points(cv):
+    import torch
+    ctx = _ctx(cv)
+    A, B, rA, rB = _pair_from_tiny(cv, ctx)
+    w = sg.tiny()
+    ctx.integrate_depth(A, torch.from_numpy(w.frame(3)).cuda(), w.cam.K, w.poses[3])
+    with pytest.raises(cv.CovoxError):
+        ctx.align_submaps(A, B, np.eye(4))
+    ctx.update_esdf(A)
+    empty = ctx.submap_create()
+    T, c, st = ctx.align_submaps(A, empty, np.eye(4))
+    assert st["status"] == cv.EDEGENERATE and st["iterations"] == 0
+    ctx.close()
