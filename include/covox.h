@@ -131,6 +131,14 @@ int covox_integrate_depth(covox_ctx *ctx, covox_submap *s, const float *depth_de
 int covox_integrate_depth_batch(covox_ctx *ctx, covox_submap *s, const float *depths_dev, int32_t F,
                                 int32_t H, int32_t W, const float K[4], const double *T_world_cam);
 
+/* Mapping loop in one call: integrates F frames in order and updates the
+ * ESDF after every esdf_every-th frame and after the last frame
+ * (esdf_every <= 0: only after the last).  Identical results to the
+ * equivalent sequence of covox_integrate_depth / covox_update_esdf calls.
+ * Arguments as covox_integrate_depth_batch.  Asynchronous. */
+int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev, int32_t F, int32_t H,
+                       int32_t W, const float K[4], const double *T_world_cam, int32_t esdf_every);
+
 /*
  * Recomputes the ESDF phi of submap s (Sec. I, III-E): with Obs = {W > 0},
  * Band = Obs and |D| < tau, Sites = Obs and |D| <= voxel_size and
@@ -199,10 +207,11 @@ typedef struct {
     int64_t n_blocks;
     int64_t block_capacity;
     int64_t table_capacity;
+    int64_t n_updates;    /* voxel updates applied since creation / reset */
     int32_t bbox_min[3];  /* allocated block coordinates, inclusive */
     int32_t bbox_max[3];
     int32_t precision;
-    int32_t reserved;
+    int32_t status;       /* pending sticky capacity error (0 if none) */
 } covox_submap_info;
 
 /* Synchronous. */
@@ -248,8 +257,11 @@ typedef struct {
     int64_t launches[COVOX_K_COUNT];
 } covox_timing;
 
-/* Enables (1) or disables (0) per-kernel HIP-event timing and clears it. */
-int covox_timing_enable(covox_ctx *ctx, int32_t on);
+/* Clears the accumulated timing and enables HIP-event timing for the
+ * kernel kinds whose bit (1 << COVOX_K_*) is set in `mask` (0 disables,
+ * -1 enables all).  Each timed launch is bracketed by two events on the
+ * context stream. */
+int covox_timing_enable(covox_ctx *ctx, int32_t mask);
 /* Synchronizes and returns the accumulated timing. */
 int covox_timing_get(covox_ctx *ctx, covox_timing *out);
 

@@ -50,8 +50,8 @@ class covox_pair(ctypes.Structure):
 
 class covox_submap_info(ctypes.Structure):
     _fields_ = [("n_blocks", ctypes.c_int64), ("block_capacity", ctypes.c_int64), ("table_capacity", ctypes.c_int64),
-                ("bbox_min", ctypes.c_int32 * 3), ("bbox_max", ctypes.c_int32 * 3), ("precision", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("n_updates", ctypes.c_int64), ("bbox_min", ctypes.c_int32 * 3), ("bbox_max", ctypes.c_int32 * 3),
+                ("precision", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
 class covox_timing(ctypes.Structure):
@@ -74,6 +74,8 @@ _sig = {
     "covox_integrate_depth_batch": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                    _fp, _dp]),
     "covox_update_esdf": (ctypes.c_int, [_vp, _vp]),
+    "covox_map_sequence": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _fp, _dp,
+                                          ctypes.c_int32]),
     "covox_align_submaps": (ctypes.c_int, [_vp, _vp, _vp, _dp, _dp, _dp, ctypes.POINTER(covox_align_stats)]),
     "covox_align_multistart": (ctypes.c_int, [_vp, _vp, _vp, _dp, ctypes.c_int32, _dp, _dp,
                                               ctypes.POINTER(covox_align_stats)]),
@@ -175,8 +177,9 @@ class Context:
         info = covox_submap_info()
         self._check(_lib.covox_submap_info_get(self.handle, s.handle, ctypes.byref(info)), "submap_info")
         return {"n_blocks": info.n_blocks, "block_capacity": info.block_capacity,
-                "table_capacity": info.table_capacity, "bbox_min": tuple(info.bbox_min),
-                "bbox_max": tuple(info.bbox_max), "precision": info.precision}
+                "table_capacity": info.table_capacity, "n_updates": info.n_updates,
+                "bbox_min": tuple(info.bbox_min), "bbox_max": tuple(info.bbox_max), "precision": info.precision,
+                "status": info.status}
 
     # -- hot path
     @staticmethod
@@ -200,6 +203,14 @@ class Context:
         assert len(T) == F
         return self._check(_lib.covox_integrate_depth_batch(self.handle, s.handle, self._depth_ptr(depths, 3), F, H,
                                                             W, _p(k, _fp), _p(T, _dp)), "integrate_depth_batch")
+
+    def map_sequence(self, s: Submap, depths: torch.Tensor, K, T_world_cam, esdf_every=1):
+        k = np.ascontiguousarray(K, np.float32)
+        T = np.ascontiguousarray(np.asarray(T_world_cam, np.float64).reshape(-1, 16))
+        F, H, W = depths.shape
+        assert len(T) == F
+        return self._check(_lib.covox_map_sequence(self.handle, s.handle, self._depth_ptr(depths, 3), F, H, W,
+                                                   _p(k, _fp), _p(T, _dp), esdf_every), "map_sequence")
 
     def update_esdf(self, s: Submap):
         return self._check(_lib.covox_update_esdf(self.handle, s.handle), "update_esdf")
@@ -268,8 +279,10 @@ class Context:
         return pts[:n]
 
     # -- timing
-    def timing_enable(self, on=True):
-        self._check(_lib.covox_timing_enable(self.handle, int(on)), "timing_enable")
+    def timing_enable(self, kinds=None):
+        """Time the given kernel kinds (names from KERNELS; None = all, [] = off)."""
+        mask = -1 if kinds is None else sum(1 << KERNELS.index(k) for k in kinds)
+        self._check(_lib.covox_timing_enable(self.handle, mask), "timing_enable")
 
     def timing_get(self) -> dict:
         t = covox_timing()

@@ -52,7 +52,7 @@ int hip_check(covox_ctx *ctx, hipError_t e, const char *what)
 
 TimedLaunch::TimedLaunch(covox_ctx *c, int k) : ctx(c), kind(k)
 {
-    if (!ctx->timing) return;
+    if (!(ctx->timing & (1 << kind))) return;
     for (hipEvent_t *e : {&a, &b}) {
         if (!ctx->ev_pool.empty()) {
             *e = ctx->ev_pool.back();
@@ -66,7 +66,7 @@ TimedLaunch::TimedLaunch(covox_ctx *c, int k) : ctx(c), kind(k)
 
 TimedLaunch::~TimedLaunch()
 {
-    if (!ctx->timing) return;
+    if (!(ctx->timing & (1 << kind))) return;
     if (a && b) {
         (void)hipEventRecord(b, ctx->stream);
         ctx->ev_used.push_back({kind, {a, b}});
@@ -138,6 +138,7 @@ __global__ void k_reset_meta(SubmapMeta *m)
     m->dom_valid = 0;
     m->n_points = 0;
     m->pbar[0] = m->pbar[1] = m->pbar[2] = 0.0;
+    m->n_updates = 0;
 }
 
 int check_status_after_sync(covox_ctx *ctx, covox_submap *s)
@@ -413,6 +414,21 @@ int covox_integrate_depth_batch(covox_ctx *ctx, covox_submap *s, const float *de
     return COVOX_OK;
 }
 
+int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev, int32_t F, int32_t H, int32_t W,
+                       const float K[4], const double *T_world_cam, int32_t esdf_every)
+{
+    if (!ctx || !s || !depths_dev || !T_world_cam || F < 0) return fail(ctx, COVOX_EINVAL, "map_sequence: bad argument");
+    for (int32_t f = 0; f < F; ++f) {
+        int rc = covox_integrate_depth(ctx, s, depths_dev + (size_t)f * H * W, H, W, K, T_world_cam + 16 * f);
+        if (rc) return rc;
+        if ((esdf_every > 0 && (f + 1) % esdf_every == 0) || f == F - 1) {
+            rc = update_esdf(ctx, s);
+            if (rc) return rc;
+        }
+    }
+    return COVOX_OK;
+}
+
 int covox_update_esdf(covox_ctx *ctx, covox_submap *s)
 {
     if (!ctx || !s) return fail(ctx, COVOX_EINVAL, "update_esdf: null argument");
@@ -526,9 +542,10 @@ int covox_submap_info_get(covox_ctx *ctx, const covox_submap *s, covox_submap_in
     out->n_blocks = m.n_blocks;
     out->block_capacity = s->cap;
     out->table_capacity = s->tcap;
+    out->n_updates = (int64_t)m.n_updates;
     for (int a = 0; a < 3; ++a) { out->bbox_min[a] = m.bmin[a]; out->bbox_max[a] = m.bmax[a]; }
     out->precision = ctx->p.precision;
-    out->reserved = m.status;
+    out->status = m.status;
     return COVOX_OK;
 }
 
@@ -578,7 +595,7 @@ int64_t covox_export_points(covox_ctx *ctx, covox_submap *B, float *pts, int64_t
     return B->n_pts;
 }
 
-int covox_timing_enable(covox_ctx *ctx, int32_t on)
+int covox_timing_enable(covox_ctx *ctx, int32_t mask)
 {
     if (!ctx) return COVOX_EINVAL;
     (void)hipStreamSynchronize(ctx->stream);
@@ -588,7 +605,7 @@ int covox_timing_enable(covox_ctx *ctx, int32_t on)
     }
     ctx->ev_used.clear();
     for (int k = 0; k < COVOX_K_COUNT; ++k) { ctx->ms[k] = 0; ctx->launches[k] = 0; }
-    ctx->timing = on != 0;
+    ctx->timing = mask;
     return COVOX_OK;
 }
 

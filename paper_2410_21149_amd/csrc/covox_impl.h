@@ -87,6 +87,7 @@ struct SubmapMeta {
     int32_t dom_dim[3];
     int64_t n_points;       // registration points
     double pbar[3];         // their centroid (binary64)
+    unsigned long long n_updates;  // voxel updates since creation / reset
 };
 
 // Per-frame projection parameters (kernel argument).
@@ -167,7 +168,7 @@ struct covox_ctx {
     void *host_pin = nullptr;
     size_t host_pin_cap = 0;
     // timing
-    bool timing = false;
+    int32_t timing = 0;         // bit mask of timed kernel kinds
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
     double ms[COVOX_K_COUNT] = {0};

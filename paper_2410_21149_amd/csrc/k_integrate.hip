@@ -202,7 +202,7 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand
 
 template <typename S>
 __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float tau, float maxr,
-                                                   const SubmapMeta *__restrict__ meta,
+                                                   SubmapMeta *__restrict__ meta,
                                                    const uint64_t *__restrict__ t_key,
                                                    const uint32_t *__restrict__ t_idx, uint64_t *keys, S *D, S *W,
                                                    uint64_t *tkeys, uint32_t *tvals, uint64_t tmask)
@@ -226,10 +226,12 @@ __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float 
         const int iy = 8 * by + (lane >> 3);
         S *Db = D + idx * 512 + lane;
         S *Wb = W + idx * 512 + lane;
+        int n_ok = 0;
 #pragma unroll
         for (int z = 0; z < 8; ++z) {
             float sdf;
             const bool ok = proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf);
+            n_ok += __popcll(__ballot(ok));
             if (ok) {
                 const float Dv = is_new ? 0.0f : ld(Db + 64 * z);
                 const float Wv = is_new ? 0.0f : ld(Wb + 64 * z);
@@ -243,6 +245,7 @@ __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float 
                 st(Wb + 64 * z, 0.0f);
             }
         }
+        if (lane == 0) atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
     }
 }
 
