@@ -3,6 +3,7 @@
 #include "covox_impl.h"
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -284,6 +285,10 @@ int covox_create(covox_ctx **out, const covox_params *p)
     if (!valid_params(p, why)) return COVOX_EINVAL;
     covox_ctx *ctx = new covox_ctx();
     ctx->p = *p;
+    if (const char *m = getenv("COVOX_EDT_MODE")) {
+        if (!strcmp(m, "window")) ctx->edt_mode = 1;
+        else if (!strcmp(m, "envelope")) ctx->edt_mode = 2;
+    }
     if (hipGetDevice(&ctx->device) != hipSuccess) {
         delete ctx;
         return COVOX_EHIP;

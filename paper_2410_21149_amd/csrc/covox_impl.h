@@ -154,6 +154,8 @@ struct covox_ctx {
     int64_t g1_cap = 0;
     uint16_t *g2 = nullptr;     // 512 per dense block
     int64_t g2_cap = 0;
+    int32_t edt_mode = 0;           // 0 auto, 1 voxel-parallel window, 2 per-line envelope
+    int32_t edt_env_min_cols = 2048;  // auto: envelopes when both line passes have this many columns
     // registration-point scratch
     uint32_t *cnt = nullptr;    // per-block counts, then offsets
     int64_t cnt_cap = 0;

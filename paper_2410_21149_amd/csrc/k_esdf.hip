@@ -19,6 +19,7 @@
 // and z in registers; neighbours along an axis are whole blocks, staged in
 // LDS per wave.  Site masks are 8 64-bit words per block (word z, bit x+8y).
 #include "covox_impl.h"
+#include "edt_envelope.h"
 
 #include <algorithm>
 
@@ -121,153 +122,281 @@ __device__ __forceinline__ int nearest_bit(uint64_t lo, uint64_t hi, int p)
     return min(dl, dr);
 }
 
-__global__ __launch_bounds__(256) void k_edt_x(const SubmapMeta *meta, const uint64_t *__restrict__ sites,
-                                               uint8_t *__restrict__ g1, int R, int HB)
+// ------------------------------------------------------------------------
+// y and z passes: lower envelope of parabolas per line (Felzenszwalb and
+// Huttenlocher).  One wave per block column; lane = one line.  A line longer
+// than kWin voxels is cut into output segments that each carry C = 8 HB >= R
+// voxels of context on both sides, which is exact because only k <= R^2 is
+// kept.  Breakpoints s(p, q) = ((f_q - f_p) + (q - p)(q + p)) / (2 (q - p))
+// are compared by integer cross-multiplication (|N| < 2^18, D <= 2 kWin), so
+// the envelope is exact.
+
+constexpr int kWin = 256;  // window positions (u8 stack entries)
+
+__device__ __forceinline__ void segment(int L, int C, int seg, int S, int &y0, int &y1, int &w0, int &w1)
 {
-    __shared__ uint64_t wl[4][(2 * kMaxHalo + 1) * 8];
+    y0 = seg * S;
+    y1 = min(y0 + S, L);
+    w0 = max(0, y0 - C);
+    w1 = min(L, y1 + C);
+}
+
+// g2(x, y, z) = min_y' g1(x, y', z)^2 + (y - y')^2, kept when <= R^2.
+// Lane = x + 8 z within the block column (bx, *, bz).
+__global__ __launch_bounds__(64) void k_edt_y_env(const SubmapMeta *meta, const uint8_t *__restrict__ g1,
+                                              uint16_t *__restrict__ g2, int R, int HB)
+{
+    __shared__ __align__(16) uint8_t col[kWin * 64];   // [position][lane]
+    __shared__ __align__(16) uint8_t stk[kWin * 64];   // [entry][lane]
+    __shared__ __align__(16) uint16_t ost[8 * 64];     // one block of outputs [y][lane]
     const Dom d = read_dom(meta);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    const int nb = 2 * HB + 1;
-    const int x = lane & 7, y = lane >> 3;
-    uint64_t *w = wl[wid];
-    for (int64_t db = wave; db < d.n; db += nwaves) {
-        int bx, by, bz;
-        dom_coords(d, db, bx, by, bz);
-        for (int e = lane; e < nb * 8; e += 64) {
-            const int i = e >> 3, z = e & 7;
-            const int nx = bx + i - HB;
-            w[e] = (nx >= 0 && nx < d.dim[0]) ? sites[(db + (i - HB)) * 8 + z] : 0ull;
+    const int lane = threadIdx.x;
+    const int C = 8 * HB;
+    const int S = kWin - 2 * C;
+    const int L = 8 * d.dim[1];
+    const int nseg = L > 0 ? (L + S - 1) / S : 0;
+    const int64_t ncol = (int64_t)d.dim[0] * d.dim[2] * nseg;
+    const int R2 = R * R;
+    auto getf = [&](int q) {
+        const int a = col[q * 64 + lane];
+        return a * a;
+    };
+    for (int64_t c = blockIdx.x; c < ncol; c += gridDim.x) {
+        const int seg = (int)(c % nseg);
+        const int64_t cc = c / nseg;
+        const int bx = (int)(cc % d.dim[0]), bz = (int)(cc / d.dim[0]);
+        int y0, y1, w0, w1;
+        segment(L, C, seg, S, y0, y1, w0, w1);
+        // stage the window: block j holds bytes (x = 0..7) for (y = lane & 7, z = lane >> 3)
+        for (int j = w0 / 8; j < w1 / 8; ++j) {
+            const int64_t db = dom_index(d, bx, j, bz);
+            const uint64_t v = ((const uint64_t *)(g1 + db * 512))[lane];
+            *(uint64_t *)&col[(8 * (j - w0 / 8) + (lane & 7)) * 64 + 8 * (lane >> 3)] = v;
         }
         wave_sync();
-        uint8_t out[8];
+        Envelope e;
+        e.k = -1;
+        e.p = e.fp = e.pp = e.fpp = 0;
+        const int W = w1 - w0;
+        for (int q = 0; q < W; ++q) {
+            const int a = col[q * 64 + lane];
+            if (a == 255) continue;
+            env_push(e, stk, 64, lane, q, a * a, getf);
+        }
+        Walker wk;
+        if (e.k >= 0) walk_init(wk, e, stk, 64, lane, getf);
+        for (int yb = y0; yb < y1; yb += 8) {
 #pragma unroll
-        for (int z = 0; z < 8; ++z) {
-            uint64_t lo = 0, hi = 0;
-            for (int i = 0; i < nb; ++i) {
-                const uint64_t byte = (w[i * 8 + z] >> (8 * y)) & 0xFFull;
-                const int pos = 8 * i;
-                if (pos < 64) lo |= byte << pos;
-                else hi |= byte << (pos - 64);
+            for (int t = 0; t < 8; ++t) {
+                int v = 0xFFFF;
+                if (e.k >= 0) {
+                    const int val = walk_at(wk, e, stk, 64, lane, yb + t - w0, getf);
+                    if (val <= R2) v = val;
+                }
+                ost[t * 64 + lane] = (uint16_t)v;
             }
-            const int dist = nearest_bit(lo, hi, 8 * HB + x);
-            out[z] = dist <= R ? (uint8_t)dist : (uint8_t)255;
+            wave_sync();
+            const int64_t db = dom_index(d, bx, yb / 8, bz);
+            const uint4 o = *(const uint4 *)&ost[(lane & 7) * 64 + 8 * (lane >> 3)];
+            *(uint4 *)(g2 + db * 512 + 8 * lane) = o;
+            wave_sync();
         }
-        wave_sync();
-#pragma unroll
-        for (int z = 0; z < 8; ++z) g1[db * 512 + lane + 64 * z] = out[z];
     }
 }
+
+// k(x, y, z) = min_z' g2(x, y, z')  + (z - z')^2 and phi for the allocated
+// blocks of the column (bx, by, *).  Lane = x + 8 y, the in-block layout.
+template <typename S>
+__global__ __launch_bounds__(64) void k_edt_z_env(const SubmapMeta *meta, const int32_t *__restrict__ page,
+                                              const uint16_t *__restrict__ g2, const S *__restrict__ D,
+                                              const S *__restrict__ W, float *__restrict__ phi, int R, int HB,
+                                              float vs, float tau, float dmax)
+{
+    __shared__ __align__(16) uint16_t col[kWin * 64];  // [position][lane]
+    __shared__ __align__(16) uint8_t stk[kWin * 64];
+    const Dom d = read_dom(meta);
+    const int lane = threadIdx.x;
+    const int C = 8 * HB;
+    const int Sg = kWin - 2 * C;
+    const int L = 8 * d.dim[2];
+    const int nseg = L > 0 ? (L + Sg - 1) / Sg : 0;
+    const int64_t ncol = (int64_t)d.dim[0] * d.dim[1] * nseg;
+    const int R2 = R * R;
+    auto getf = [&](int q) { return (int)col[q * 64 + lane]; };
+    for (int64_t c = blockIdx.x; c < ncol; c += gridDim.x) {
+        const int seg = (int)(c % nseg);
+        const int64_t cc = c / nseg;
+        const int bx = (int)(cc % d.dim[0]), by = (int)(cc / d.dim[0]);
+        int z0, z1, w0, w1;
+        segment(L, C, seg, Sg, z0, z1, w0, w1);
+        for (int j = w0 / 8; j < w1 / 8; ++j) {
+            const uint16_t *src = g2 + dom_index(d, bx, by, j) * 512 + lane;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) col[(8 * (j - w0 / 8) + t) * 64 + lane] = src[64 * t];
+        }
+        wave_sync();
+        Envelope e;
+        e.k = -1;
+        e.p = e.fp = e.pp = e.fpp = 0;
+        const int Wn = w1 - w0;
+        for (int q = 0; q < Wn; ++q) {
+            const int a = col[q * 64 + lane];
+            if (a == 0xFFFF) continue;
+            env_push(e, stk, 64, lane, q, a, getf);
+        }
+        Walker wk;
+        if (e.k >= 0) walk_init(wk, e, stk, 64, lane, getf);
+        for (int zb = z0; zb < z1; zb += 8) {
+            const int64_t idx = page[dom_index(d, bx, by, zb / 8)];
+            if (idx < 0) continue;
+            const S *Db = D + idx * 512 + lane;
+            const S *Wb = W + idx * 512 + lane;
+            float *Pb = phi + idx * 512 + lane;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const float Dv = ldv(Db + 64 * t), Wv = ldv(Wb + 64 * t);
+                float out;
+                if (!(Wv > 0.0f)) {
+                    out = __builtin_nanf("");
+                } else if (fabsf(Dv) < tau) {
+                    out = Dv;
+                } else {
+                    int best = kBig;
+                    if (e.k >= 0) best = walk_at(wk, e, stk, 64, lane, zb + t - w0, getf);
+                    const float sg = Dv > 0.0f ? 1.0f : -1.0f;
+                    if (best > R2) out = sg * dmax;
+                    else out = sg * fminf(dmax, vs * sqrtf((float)best));
+                }
+                Pb[64 * t] = out;
+            }
+        }
+        wave_sync();
+    }
+}
+
+// ------------------------------------------------------------------------
+// Voxel-parallel passes: one 512-lane workgroup per block, one lane per
+// voxel (l = x + 8y + 64z), the 2 HB + 1 neighbour blocks along the pass axis
+// staged in LDS.  The min-plus search walks outward from the voxel and stops
+// once d^2 reaches the best value, so it is exact; its cost follows the
+// distance to the nearest site rather than the line length, which suits
+// small domains where per-line envelopes leave the GPU idle.
 
 __device__ __forceinline__ int sq8(uint8_t v) { return v == 255 ? kBig : (int)v * (int)v; }
 __device__ __forceinline__ int inf16(uint16_t v) { return v == 0xFFFF ? kBig : (int)v; }
 
-__global__ __launch_bounds__(256) void k_edt_y(const SubmapMeta *meta, const uint8_t *__restrict__ g1,
-                                               uint16_t *__restrict__ g2, int R, int HB)
+__global__ __launch_bounds__(512) void k_edt_x_vox(const SubmapMeta *meta, const uint64_t *__restrict__ sites,
+                                                   uint8_t *__restrict__ g1, int R, int HB)
 {
-    __shared__ uint64_t col[4][(2 * kMaxHalo + 1) * 64];  // (2HB+1) blocks x 512 bytes per wave
+    __shared__ uint64_t wl[(2 * kMaxHalo + 1) * 8];
     const Dom d = read_dom(meta);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int tid = threadIdx.x;
+    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;
     const int nb = 2 * HB + 1;
-    const int x = lane & 7, y = lane >> 3;
-    const int R2 = R * R;
-    uint8_t *c8 = (uint8_t *)col[wid];
-    const int64_t stride_y = d.dim[0];
-    for (int64_t db = wave; db < d.n; db += nwaves) {
+    for (int64_t db = blockIdx.x; db < d.n; db += gridDim.x) {
         int bx, by, bz;
         dom_coords(d, db, bx, by, bz);
+        if (tid < nb * 8) {
+            const int i = tid >> 3, k = tid & 7;
+            const int nx = bx + i - HB;
+            wl[tid] = (nx >= 0 && nx < d.dim[0]) ? sites[(db + (i - HB)) * 8 + k] : 0ull;
+        }
+        __syncthreads();
+        uint64_t lo = 0, hi = 0;
         for (int i = 0; i < nb; ++i) {
+            const uint64_t byte = (wl[i * 8 + z] >> (8 * y)) & 0xFFull;
+            const int pos = 8 * i;
+            if (pos < 64) lo |= byte << pos;
+            else hi |= byte << (pos - 64);
+        }
+        const int dist = nearest_bit(lo, hi, 8 * HB + x);
+        g1[db * 512 + tid] = dist <= R ? (uint8_t)dist : (uint8_t)255;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(512) void k_edt_y_vox(const SubmapMeta *meta, const uint8_t *__restrict__ g1,
+                                                   uint16_t *__restrict__ g2, int R, int HB)
+{
+    __shared__ __align__(16) uint32_t colw[(2 * kMaxHalo + 1) * 128];
+    const uint8_t *col = (const uint8_t *)colw;
+    const Dom d = read_dom(meta);
+    const int tid = threadIdx.x;
+    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;
+    const int nb = 2 * HB + 1;
+    const int R2 = R * R;
+    const int Y = 8 * HB + y;
+    for (int64_t db = blockIdx.x; db < d.n; db += gridDim.x) {
+        int bx, by, bz;
+        dom_coords(d, db, bx, by, bz);
+        for (int e = tid; e < nb * 128; e += 512) {
+            const int i = e >> 7, w = e & 127;
             const int ny = by + i - HB;
-            uint64_t v = ~0ull;
-            if (ny >= 0 && ny < d.dim[1])
-                v = ((const uint64_t *)(g1 + (db + (int64_t)(i - HB) * stride_y) * 512))[lane];
-            col[wid][i * 64 + lane] = v;
+            colw[e] = (ny >= 0 && ny < d.dim[1]) ? ((const uint32_t *)(g1 + (db + (int64_t)(i - HB) * d.dim[0]) * 512))[w]
+                                                 : 0xFFFFFFFFu;
         }
-        wave_sync();
-        uint16_t out[8];
-#pragma unroll
-        for (int z = 0; z < 8; ++z) {
-            const int Y = 8 * HB + y;
-            auto at = [&](int yy) { return c8[(yy >> 3) * 512 + x + 8 * (yy & 7) + 64 * z]; };
-            int best = sq8(at(Y));
-            for (int dd = 1; dd <= R; ++dd) {
-                const int d2 = dd * dd;
-                if (d2 >= best) break;
-                const int a = sq8(at(Y - dd)), b = sq8(at(Y + dd));
-                best = min(best, min(a, b) + d2);
-            }
-            out[z] = best <= R2 ? (uint16_t)best : (uint16_t)0xFFFF;
+        __syncthreads();
+        auto at = [&](int yy) { return col[(yy >> 3) * 512 + x + 8 * (yy & 7) + 64 * z]; };
+        int best = sq8(at(Y));
+        for (int dd = 1; dd <= R; ++dd) {
+            const int d2 = dd * dd;
+            if (d2 >= best) break;
+            best = min(best, min(sq8(at(Y - dd)), sq8(at(Y + dd))) + d2);
         }
-        wave_sync();
-#pragma unroll
-        for (int z = 0; z < 8; ++z) g2[db * 512 + lane + 64 * z] = out[z];
+        g2[db * 512 + tid] = best <= R2 ? (uint16_t)best : (uint16_t)0xFFFF;
+        __syncthreads();
     }
 }
 
 template <typename S>
-__global__ __launch_bounds__(256) void k_edt_z(const SubmapMeta *meta, const uint64_t *__restrict__ keys,
-                                               const uint16_t *__restrict__ g2, const S *__restrict__ D,
-                                               const S *__restrict__ W, float *__restrict__ phi, int R, int HB,
-                                               float vs, float tau, float dmax)
+__global__ __launch_bounds__(512) void k_edt_z_vox(const SubmapMeta *meta, const uint64_t *__restrict__ keys,
+                                                   const uint16_t *__restrict__ g2, const S *__restrict__ D,
+                                                   const S *__restrict__ W, float *__restrict__ phi, int R, int HB,
+                                                   float vs, float tau, float dmax)
 {
-    __shared__ uint64_t col[4][(2 * kMaxHalo + 1) * 128];  // (2HB+1) blocks x 512 u16 per wave
+    __shared__ __align__(16) uint32_t colw[(2 * kMaxHalo + 1) * 256];
+    const uint16_t *col = (const uint16_t *)colw;
     const Dom d = read_dom(meta);
     const int64_t nbk = meta->n_blocks;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int tid = threadIdx.x;
+    const int z = tid >> 6;
     const int nb = 2 * HB + 1;
     const int R2 = R * R;
-    const uint16_t *c16 = (const uint16_t *)col[wid];
+    const int Z = 8 * HB + z;
     const int64_t stride_z = (int64_t)d.dim[0] * d.dim[1];
-    for (int64_t j = wave; j < nbk; j += nwaves) {
+    for (int64_t j = blockIdx.x; j < nbk; j += gridDim.x) {
         int bx, by, bz;
         unpack_key(keys[j], bx, by, bz);
         bx -= d.lo[0]; by -= d.lo[1]; bz -= d.lo[2];
         const int64_t db = dom_index(d, bx, by, bz);
-        for (int i = 0; i < nb; ++i) {
+        for (int e = tid; e < nb * 256; e += 512) {
+            const int i = e >> 8, w = e & 255;
             const int nz = bz + i - HB;
-            uint64_t v0 = ~0ull, v1 = ~0ull;
-            if (nz >= 0 && nz < d.dim[2]) {
-                const uint64_t *src = (const uint64_t *)(g2 + (db + (int64_t)(i - HB) * stride_z) * 512);
-                v0 = src[2 * lane];
-                v1 = src[2 * lane + 1];
-            }
-            col[wid][i * 128 + 2 * lane] = v0;
-            col[wid][i * 128 + 2 * lane + 1] = v1;
+            colw[e] = (nz >= 0 && nz < d.dim[2]) ? ((const uint32_t *)(g2 + (db + (int64_t)(i - HB) * stride_z) * 512))[w]
+                                                 : 0xFFFFFFFFu;
         }
-        wave_sync();
-        const S *Db = D + j * 512 + lane;
-        const S *Wb = W + j * 512 + lane;
-        float *Pb = phi + j * 512 + lane;
-#pragma unroll
-        for (int z = 0; z < 8; ++z) {
-            const float Dv = ldv(Db + 64 * z), Wv = ldv(Wb + 64 * z);
-            float out;
-            if (!(Wv > 0.0f)) {
-                out = __builtin_nanf("");
-            } else if (fabsf(Dv) < tau) {
-                out = Dv;
-            } else {
-                const int Z = 8 * HB + z;
-                auto at = [&](int zz) { return c16[(zz >> 3) * 512 + lane + 64 * (zz & 7)]; };
-                int best = inf16(at(Z));
-                for (int dd = 1; dd <= R; ++dd) {
-                    const int d2 = dd * dd;
-                    if (d2 >= best) break;
-                    const int a = inf16(at(Z - dd)), b = inf16(at(Z + dd));
-                    best = min(best, min(a, b) + d2);
-                }
-                const float sg = Dv > 0.0f ? 1.0f : -1.0f;
-                if (best > R2) out = sg * dmax;
-                else out = sg * fminf(dmax, vs * sqrtf((float)best));
+        const float Dv = ldv(D + j * 512 + tid), Wv = ldv(W + j * 512 + tid);
+        __syncthreads();
+        float out;
+        if (!(Wv > 0.0f)) {
+            out = __builtin_nanf("");
+        } else if (fabsf(Dv) < tau) {
+            out = Dv;
+        } else {
+            const int base = tid & 63;
+            auto at = [&](int zz) { return col[(zz >> 3) * 512 + base + 64 * (zz & 7)]; };
+            int best = inf16(at(Z));
+            for (int dd = 1; dd <= R; ++dd) {
+                const int d2 = dd * dd;
+                if (d2 >= best) break;
+                best = min(best, min(inf16(at(Z - dd)), inf16(at(Z + dd))) + d2);
             }
-            Pb[64 * z] = out;
+            const float sg = Dv > 0.0f ? 1.0f : -1.0f;
+            if (best > R2) out = sg * dmax;
+            else out = sg * fminf(dmax, vs * sqrtf((float)best));
         }
-        wave_sync();
+        phi[j * 512 + tid] = out;
+        __syncthreads();
     }
 }
 
@@ -278,6 +407,19 @@ unsigned grid_for(int64_t waves)
 }
 
 }  // namespace
+
+// Workgroups for a line pass: the columns (block extents along axes a and b
+// of the host-side bound box) times the segments along the third axis.
+static unsigned grid_cols(const covox_submap *s, int a, int b, int HB)
+{
+    if (!s->bound_valid) return 1;
+    const int c = 3 - a - b;
+    const int64_t L = 8 * (int64_t)(s->bound_hi[c] - s->bound_lo[c] + 1);
+    const int64_t S = kWin - 16 * HB;
+    const int64_t nseg = (L + S - 1) / S;
+    const int64_t n = (int64_t)(s->bound_hi[a] - s->bound_lo[a] + 1) * (s->bound_hi[b] - s->bound_lo[b] + 1) * nseg;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 65536));
+}
 
 static int64_t bound_blocks(const covox_submap *s)
 {
@@ -327,25 +469,41 @@ int update_esdf(covox_ctx *ctx, covox_submap *s)
     if ((rc = ensure_buffer(ctx, (void **)&ctx->g1, &ctx->g1_cap, nd, 512, "edt g1"))) return rc;
     if ((rc = ensure_buffer(ctx, (void **)&ctx->g2, &ctx->g2_cap, nd, 1024, "edt g2"))) return rc;
     const float vs = (float)p.voxel_size, tau = (float)(p.trunc_vox * p.voxel_size), dmax = (float)p.d_max;
+    // Pass shape: per-line envelopes when there are enough lines to fill the
+    // GPU, voxel-parallel windowed search otherwise (or as forced by
+    // COVOX_EDT_MODE = window | envelope).
+    const unsigned cols_y = grid_cols(s, 0, 2, HB), cols_z = grid_cols(s, 0, 1, HB);
+    bool envelope = std::min(cols_y, cols_z) >= (unsigned)ctx->edt_env_min_cols;
+    if (ctx->edt_mode == 1) envelope = false;
+    if (ctx->edt_mode == 2) envelope = true;
+    const unsigned gd = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nd, 65536));
+    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(std::min(s->nb_upper, s->cap), 65536));
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_X);
-        hipLaunchKernelGGL(k_edt_x, dim3(grid_for(nd)), dim3(256), 0, ctx->stream, s->meta, ctx->sites, ctx->g1, R,
-                           HB);
+        hipLaunchKernelGGL(k_edt_x_vox, dim3(gd), dim3(512), 0, ctx->stream, s->meta, ctx->sites, ctx->g1, R, HB);
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Y);
-        hipLaunchKernelGGL(k_edt_y, dim3(grid_for(nd)), dim3(256), 0, ctx->stream, s->meta, ctx->g1, ctx->g2, R,
-                           HB);
+        if (envelope)
+            hipLaunchKernelGGL(k_edt_y_env, dim3(cols_y), dim3(64), 0, ctx->stream, s->meta, ctx->g1, ctx->g2, R, HB);
+        else
+            hipLaunchKernelGGL(k_edt_y_vox, dim3(gd), dim3(512), 0, ctx->stream, s->meta, ctx->g1, ctx->g2, R, HB);
     }
-    const int64_t nbk = std::max<int64_t>(1, std::min(s->nb_upper, s->cap));
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Z);
-        if (p.precision == COVOX_FP16)
-            hipLaunchKernelGGL(k_edt_z<__half>, dim3(grid_for(nbk)), dim3(256), 0, ctx->stream, s->meta, s->keys,
-                               ctx->g2, (const __half *)s->D, (const __half *)s->W, s->phi, R, HB, vs, tau, dmax);
+        const bool h = p.precision == COVOX_FP16;
+        if (envelope && h)
+            hipLaunchKernelGGL(k_edt_z_env<__half>, dim3(cols_z), dim3(64), 0, ctx->stream, s->meta, s->page, ctx->g2,
+                               (const __half *)s->D, (const __half *)s->W, s->phi, R, HB, vs, tau, dmax);
+        else if (envelope)
+            hipLaunchKernelGGL(k_edt_z_env<float>, dim3(cols_z), dim3(64), 0, ctx->stream, s->meta, s->page, ctx->g2,
+                               (const float *)s->D, (const float *)s->W, s->phi, R, HB, vs, tau, dmax);
+        else if (h)
+            hipLaunchKernelGGL(k_edt_z_vox<__half>, dim3(gb), dim3(512), 0, ctx->stream, s->meta, s->keys, ctx->g2,
+                               (const __half *)s->D, (const __half *)s->W, s->phi, R, HB, vs, tau, dmax);
         else
-            hipLaunchKernelGGL(k_edt_z<float>, dim3(grid_for(nbk)), dim3(256), 0, ctx->stream, s->meta, s->keys,
-                               ctx->g2, (const float *)s->D, (const float *)s->W, s->phi, R, HB, vs, tau, dmax);
+            hipLaunchKernelGGL(k_edt_z_vox<float>, dim3(gb), dim3(512), 0, ctx->stream, s->meta, s->keys, ctx->g2,
+                               (const float *)s->D, (const float *)s->W, s->phi, R, HB, vs, tau, dmax);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "esdf launch"))) return rc;
     s->esdf_version = s->version;

@@ -284,3 +284,25 @@ def test_alignment_needs_current_esdf_and_enough_points(cv):
     T, c, st = ctx.align_submaps(A, empty, np.eye(4))
     assert st["status"] == cv.EDEGENERATE and st["iterations"] == 0
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", ["window", "envelope"])
+@pytest.mark.parametrize("workload", ["tiny", "room40"])
+def test_esdf_modes_parity(cv, mode, workload, monkeypatch):
+    """Both pass shapes of the ESDF (voxel-parallel windowed search and
+    per-line lower envelopes) give the checker's phi."""
+    import torch
+    monkeypatch.setenv("COVOX_EDT_MODE", mode)
+    w = sg.tiny() if workload == "tiny" else sg.room(n_frames=40)
+    fr = w.frames()
+    ctx = _ctx(cv, block_capacity=16384)
+    s = ctx.submap_create()
+    ref = orc.Submap(_oracle_params())
+    dev = torch.from_numpy(fr).cuda()
+    for f in range(w.n_frames):
+        ctx.integrate_depth(s, dev[f], w.cam.K, w.poses[f])
+        ref.integrate(fr[f], w.cam.K, w.poses[f])
+    ctx.update_esdf(s)
+    ref.update_esdf()
+    assert _compare_phi(ctx.export_blocks(s), ref.export()) == 0
+    ctx.close()
