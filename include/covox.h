@@ -141,7 +141,9 @@ int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev,
 
 /*
  * Recomputes the ESDF phi of submap s (Sec. I, III-E): with Obs = {W > 0},
- * Band = Obs and |D| < tau, Sites = Obs and |D| <= voxel_size and
+ * Band = Obs and |D| < tau (1 - 2^-10) (voxels clamped to tau in every
+ * observation are not in the band, whatever the rounding of their running
+ * average), Sites = Obs and |D| <= voxel_size and
  * R = round(d_max / voxel_size):
  *   Band voxels: phi = D;
  *   other observed voxels: k = min over sites of the squared voxel distance
@@ -151,6 +153,11 @@ int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev,
  * Asynchronous.
  */
 int covox_update_esdf(covox_ctx *ctx, covox_submap *s);
+
+/* ESDF of n submaps (host array of handles), each pass in one launch over
+ * all of them (up to 32 submaps per launch).  Identical results to n calls
+ * of covox_update_esdf.  Asynchronous. */
+int covox_update_esdf_batch(covox_ctx *ctx, covox_submap *const *subs, int32_t n);
 
 /* ---------------------------------------------------------------- align */
 
@@ -166,7 +173,7 @@ typedef struct {
 /*
  * Aligns submap B to submap A (Sec. III-F, Eq. 1 registration term):
  * registration points of B are the zero crossings of D_B along voxel edges
- * whose endpoints are both in the band with W >= w_reg; the residual of a
+ * whose endpoints are both in the band (as for the ESDF) with W >= w_reg; the residual of a
  * point p is the trilinear ESDF of A at T p, its Jacobian [g ; (T p) x g]
  * for T <- Exp(xi) T.  Gauss-Newton with binary64 6x6 Cholesky solves and
  * SE(3) updates on the device; stops when |delta_rho| < tol_rho and

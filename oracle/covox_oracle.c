@@ -485,13 +485,20 @@ static void edt1d(const int64_t *f, int64_t *d, int n, int *v, double *z)
     }
 }
 
+/* The band: |D| below the truncation distance by more than tau / 1024.  A
+ * voxel that was clamped in every observation holds D = tau up to the
+ * rounding of the running average (and of binary16 storage); it carries no
+ * distance information and must not count as in-band whatever the precision. */
+static double band_limit(const orc_params *p) { return p->trunc_vox * p->vs * (1.0 - 1.0 / 1024.0); }
+
 /* Voxel value helpers for either mode. */
 static double Dval(const orc_submap *s, size_t o) { return s->p.fp64 ? s->D64[o] : (double)s->D[o]; }
 static double Wval(const orc_submap *s, size_t o) { return s->p.fp64 ? s->W64[o] : (double)s->W[o]; }
 
 /*
  * ESDF of the whole submap.
- *   Obs  = {W > 0};  Band = Obs and |D| < tau;  Sites = Obs and |D| <= vs.
+ *   Obs  = {W > 0};  Band = Obs and |D| < tau (1 - 2^-10);  Sites = Obs and
+ *   |D| <= vs.
  *   Band voxels copy D.  Other observed voxels: k = min over sites of the
  *   squared voxel distance (exact EDT on the dense block box);
  *   phi = sign * min(d_max, vs * sqrt(k)) for k <= R^2 with R = round(d_max /
@@ -501,7 +508,7 @@ int orc_update_esdf(orc_submap *s)
 {
     if (s->n == 0) return ORC_OK;
     const int fp64 = s->p.fp64;
-    const double tau = s->p.trunc_vox * s->p.vs;
+    const double tau = band_limit(&s->p);
     const float vs_f = (float)s->p.vs, tau_f = (float)tau, dmax_f = (float)s->p.d_max;
     const int64_t Rv = llround(s->p.d_max / s->p.vs);
     const int64_t R2 = Rv * Rv;
@@ -638,7 +645,7 @@ int orc_import(orc_submap *s, int64_t n, const uint64_t *keys, const double *D, 
 /*
  * Registration points of a submap (Sec. III-F: points chosen by weight):
  * zero crossings of D along voxel edges (i, i + e_a) whose two endpoints are
- * both in the band and both have W >= w_reg.  p = c(i) with
+ * both in the band (|D| < tau (1 - 2^-10)) and both have W >= w_reg.  p = c(i) with
  * p_a = c_a(i) + s vs,  s = D(i) / (D(i) - D(i + e_a)).
  * Order: (block buffer index, in-block index l, axis a).
  * out: 3 floats per point (binary32 mode) or 3 doubles (binary64 mode).
@@ -646,7 +653,7 @@ int orc_import(orc_submap *s, int64_t n, const uint64_t *keys, const double *D, 
  */
 int64_t orc_iso_points(const orc_submap *s, void *out, int64_t cap)
 {
-    const double tau = s->p.trunc_vox * s->p.vs;
+    const double tau = band_limit(&s->p);
     const float vs_f = (float)s->p.vs, tau_f = (float)tau, wreg_f = (float)s->p.w_reg;
     int64_t n = 0;
     for (int64_t j = 0; j < s->n; ++j) {

@@ -74,6 +74,7 @@ _sig = {
     "covox_integrate_depth_batch": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                    _fp, _dp]),
     "covox_update_esdf": (ctypes.c_int, [_vp, _vp]),
+    "covox_update_esdf_batch": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int32]),
     "covox_map_sequence": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _fp, _dp,
                                           ctypes.c_int32]),
     "covox_align_submaps": (ctypes.c_int, [_vp, _vp, _vp, _dp, _dp, _dp, ctypes.POINTER(covox_align_stats)]),
@@ -211,6 +212,10 @@ class Context:
         assert len(T) == F
         return self._check(_lib.covox_map_sequence(self.handle, s.handle, self._depth_ptr(depths, 3), F, H, W,
                                                    _p(k, _fp), _p(T, _dp), esdf_every), "map_sequence")
+
+    def update_esdf_batch(self, subs):
+        arr = (_vp * max(len(subs), 1))(*[s.handle for s in subs])
+        return self._check(_lib.covox_update_esdf_batch(self.handle, arr, len(subs)), "update_esdf_batch")
 
     def update_esdf(self, s: Submap):
         return self._check(_lib.covox_update_esdf(self.handle, s.handle), "update_esdf")

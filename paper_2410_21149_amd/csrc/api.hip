@@ -434,6 +434,14 @@ int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev,
     return COVOX_OK;
 }
 
+int covox_update_esdf_batch(covox_ctx *ctx, covox_submap *const *subs, int32_t n)
+{
+    if (!ctx || (!subs && n > 0) || n < 0) return fail(ctx, COVOX_EINVAL, "update_esdf_batch: bad argument");
+    for (int32_t i = 0; i < n; ++i)
+        if (!subs[i]) return fail(ctx, COVOX_EINVAL, "update_esdf_batch: null submap");
+    return update_esdf_batch(ctx, subs, n);
+}
+
 int covox_update_esdf(covox_ctx *ctx, covox_submap *s)
 {
     if (!ctx || !s) return fail(ctx, COVOX_EINVAL, "update_esdf: null argument");

@@ -179,6 +179,11 @@ struct covox_ctx {
 
 namespace covox {
 
+// Upper limit (exclusive) of |D| for the TSDF band: the truncation distance
+// less tau / 1024, so that voxels clamped in every observation (D = tau up to
+// the rounding of the running average or of binary16 storage) stay outside.
+inline double band_limit(const covox_params &p) { return p.trunc_vox * p.voxel_size * (1.0 - 1.0 / 1024.0); }
+
 // Status helpers (api.hip).
 int fail(covox_ctx *ctx, int code, const std::string &msg);
 int hip_check(covox_ctx *ctx, hipError_t e, const char *what);
@@ -216,6 +221,7 @@ int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t
 // k_esdf.hip
 int build_page(covox_ctx *ctx, covox_submap *s);   // page + site masks of the bounding box
 int update_esdf(covox_ctx *ctx, covox_submap *s);
+int update_esdf_batch(covox_ctx *ctx, covox_submap *const *subs, int n);
 
 // k_align.hip
 int extract_points(covox_ctx *ctx, covox_submap *B);  // synchronous (count read back)

@@ -454,7 +454,7 @@ int extract_points(covox_ctx *ctx, covox_submap *B)
     if ((rc = ensure_buffer(ctx, (void **)&ctx->psum, &ctx->psum_cap, nbk, 3 * sizeof(double), "point sums")))
         return rc;
     const covox_params &p = ctx->p;
-    const float vs = (float)p.voxel_size, tau = (float)(p.trunc_vox * p.voxel_size), wreg = (float)p.w_reg;
+    const float vs = (float)p.voxel_size, tau = (float)band_limit(p), wreg = (float)p.w_reg;
     const bool h = p.precision == COVOX_FP16;
     {
         TimedLaunch tl(ctx, COVOX_K_ISO);

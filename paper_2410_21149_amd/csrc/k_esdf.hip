@@ -21,79 +21,218 @@
 #include "covox_impl.h"
 #include "edt_envelope.h"
 
+#include <string.h>
+
 #include <algorithm>
+#include <vector>
 
 namespace covox {
 
 namespace {
 
 constexpr int kBig = 1 << 24;
+constexpr int kWin = 256;     // envelope window positions (u8 stack entries)
+constexpr int kMaxJobs = 32;  // submaps per launch (the job list is a kernel argument)
 
 template <typename S> __device__ __forceinline__ float ldv(const S *p);
 template <> __device__ __forceinline__ float ldv<float>(const float *p) { return *p; }
 template <> __device__ __forceinline__ float ldv<__half>(const __half *p) { return __half2float(*p); }
 
-struct Dom {
-    int32_t lo[3], dim[3];
-    int64_t n;
+// One submap of an ESDF launch.
+struct EsdfJob {
+    SubmapMeta *meta;
+    const uint64_t *keys;
+    const uint64_t *tkeys;
+    const uint32_t *tvals;
+    uint64_t tmask;
+    const void *D;
+    const void *W;
+    float *phi;
+    int32_t *page;
 };
 
-__device__ __forceinline__ Dom read_dom(const SubmapMeta *m)
+template <int NJ>
+struct JobList {
+    EsdfJob j[NJ];
+    int n;
+};
+
+// Per-workgroup view of a launch, derived from the submaps' device
+// bookkeeping: each submap's domain (its allocated block box) and exclusive
+// prefix sums of the work items of every pass over the submaps.  The dense
+// prefix is also the offset of the submap's blocks in the shared scratch.
+struct JobInfo {
+    int32_t lo[3], dim[3];
+    int64_t nd, nb;           // dense blocks of the box, allocated blocks
+    int64_t od, ob, oy, oz;   // prefixes: dense, allocated, y columns, z columns
+};
+
+struct Plan {
+    JobInfo info[kMaxJobs];
+    int n;
+    int64_t td, tb, ty, tz;   // totals
+};
+
+__device__ __forceinline__ int64_t nsegments(int64_t L, int S) { return L > 0 ? (L + S - 1) / S : 0; }
+
+// Fills the job info of one submap from its device bookkeeping.
+__device__ __forceinline__ void job_info(const SubmapMeta *m, int C, JobInfo &ji, int64_t &cy, int64_t &cz)
 {
-    Dom d;
-    if (m->n_blocks <= 0) {
-        d.n = 0;
-        for (int a = 0; a < 3; ++a) { d.lo[a] = 0; d.dim[a] = 0; }
-        return d;
-    }
-    d.n = 1;
+    for (int a = 0; a < 3; ++a) { ji.lo[a] = 0; ji.dim[a] = 0; }
+    ji.nd = 0;
+    ji.nb = 0;
+    cy = 0;
+    cz = 0;
+    const int64_t nb = m->n_blocks;
+    if (nb <= 0) return;
+    ji.nb = nb;
+    ji.nd = 1;
     for (int a = 0; a < 3; ++a) {
-        d.lo[a] = m->bmin[a];
-        d.dim[a] = m->bmax[a] - m->bmin[a] + 1;
-        d.n *= d.dim[a];
+        ji.lo[a] = m->bmin[a];
+        ji.dim[a] = m->bmax[a] - m->bmin[a] + 1;
+        ji.nd *= ji.dim[a];
     }
-    return d;
+    const int S = kWin - 2 * C;
+    cy = (int64_t)ji.dim[0] * ji.dim[2] * nsegments(8 * (int64_t)ji.dim[1], S);
+    cz = (int64_t)ji.dim[0] * ji.dim[1] * nsegments(8 * (int64_t)ji.dim[2], S);
 }
 
-__device__ __forceinline__ void dom_coords(const Dom &d, int64_t db, int &x, int &y, int &z)
+// The plan of a multi-submap launch: the first wave derives one submap per
+// lane with wave prefix sums, then a workgroup barrier publishes it.  A
+// single-submap launch keeps its one entry in registers instead (PlanView).
+template <int NJ>
+__device__ void make_plan(const JobList<NJ> &jl, int C, Plan &pl)
+{
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        JobInfo ji;
+        int64_t cy = 0, cz = 0;
+        for (int a = 0; a < 3; ++a) { ji.lo[a] = 0; ji.dim[a] = 0; }
+        ji.nd = ji.nb = 0;
+        if (lane < jl.n) job_info(jl.j[lane].meta, C, ji, cy, cz);
+        const int64_t v[4] = {ji.nd, ji.nb, cy, cz};
+        int64_t incl[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int64_t x = v[k];
+            for (int o = 1; o < 64; o <<= 1) {
+                const int64_t y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            incl[k] = x;
+        }
+        if (lane < jl.n) {
+            ji.od = incl[0] - v[0];
+            ji.ob = incl[1] - v[1];
+            ji.oy = incl[2] - v[2];
+            ji.oz = incl[3] - v[3];
+            pl.info[lane] = ji;
+        }
+        if (lane == 63) {
+            pl.n = jl.n;
+            pl.td = incl[0];
+            pl.tb = incl[1];
+            pl.ty = incl[2];
+            pl.tz = incl[3];
+        }
+    }
+    __syncthreads();
+}
+
+// Submap owning global work item w of a pass (largest j with offset <= w).
+template <int64_t JobInfo::*OFF>
+__device__ __forceinline__ int find_job(const Plan &pl, int64_t w)
+{
+    int lo = 0, hi = pl.n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pl.info[mid].*OFF <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Uniform access to the plan: registers for one submap, LDS for several.
+template <int NJ>
+struct PlanView {
+    Plan *pl;
+    JobInfo one;
+    int64_t t[4];  // totals: dense, allocated, y columns, z columns
+
+    __device__ void init(const JobList<NJ> &jl, int C, Plan &lds)
+    {
+        if constexpr (NJ == 1) {
+            int64_t cy, cz;
+            job_info(jl.j[0].meta, C, one, cy, cz);
+            one.od = one.ob = one.oy = one.oz = 0;
+            t[0] = one.nd;
+            t[1] = one.nb;
+            t[2] = cy;
+            t[3] = cz;
+            pl = nullptr;
+        } else {
+            make_plan(jl, C, lds);
+            pl = &lds;
+            t[0] = lds.td;
+            t[1] = lds.tb;
+            t[2] = lds.ty;
+            t[3] = lds.tz;
+        }
+    }
+    template <int64_t JobInfo::*OFF>
+    __device__ int job(int64_t w) const
+    {
+        if constexpr (NJ == 1) return 0;
+        else return find_job<OFF>(*pl, w);
+    }
+    __device__ JobInfo info(int j) const
+    {
+        if constexpr (NJ == 1) return one;
+        else return pl->info[j];
+    }
+};
+
+__device__ __forceinline__ void dom_coords(const JobInfo &d, int64_t db, int &x, int &y, int &z)
 {
     x = (int)(db % d.dim[0]);
     y = (int)((db / d.dim[0]) % d.dim[1]);
     z = (int)(db / ((int64_t)d.dim[0] * d.dim[1]));
 }
 
-__device__ __forceinline__ int64_t dom_index(const Dom &d, int x, int y, int z)
+__device__ __forceinline__ int64_t dom_index(const JobInfo &d, int x, int y, int z)
 {
     return ((int64_t)z * d.dim[1] + y) * d.dim[0] + x;
 }
 
-// Page (dense block -> buffer index, -1 if unallocated) and site masks.
-template <typename S>
-__global__ __launch_bounds__(256) void k_page_sites(SubmapMeta *meta, const uint64_t *__restrict__ tkeys,
-                                                    const uint32_t *__restrict__ tvals, uint64_t tmask,
-                                                    const S *__restrict__ D, const S *__restrict__ W,
-                                                    float vs, int32_t *__restrict__ page,
+// Page (dense block -> buffer index, -1 if unallocated) and site masks, one
+// wave per dense block.
+template <typename S, int NJ>
+__global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C, float vs,
                                                     uint64_t *__restrict__ sites)
 {
-    const Dom d = read_dom(meta);
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    if (wave == 0 && lane == 0) {
-        for (int a = 0; a < 3; ++a) { meta->dom_min[a] = d.lo[a]; meta->dom_dim[a] = d.dim[a]; }
-        meta->dom_valid = 1;
-    }
-    for (int64_t db = wave; db < d.n; db += nwaves) {
+    __shared__ Plan lds;
+    PlanView<NJ> pv;
+    pv.init(jl, C, lds);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int64_t g = (int64_t)blockIdx.x * 4 + wid; g < pv.t[0]; g += (int64_t)gridDim.x * 4) {
+        const int j = pv.template job<&JobInfo::od>(g);
+        const JobInfo d = pv.info(j);
+        const EsdfJob &job = jl.j[j];
+        const int64_t db = g - d.od;
         int x, y, z;
         dom_coords(d, db, x, y, z);
+        if (db == 0 && lane == 0) {
+            for (int a = 0; a < 3; ++a) { job.meta->dom_min[a] = d.lo[a]; job.meta->dom_dim[a] = d.dim[a]; }
+            job.meta->dom_valid = 1;
+        }
         int64_t idx = -1;
-        if (lane == 0) idx = hash_find(tkeys, tvals, tmask, pack_key(d.lo[0] + x, d.lo[1] + y, d.lo[2] + z));
+        if (lane == 0) idx = hash_find(job.tkeys, job.tvals, job.tmask, pack_key(d.lo[0] + x, d.lo[1] + y, d.lo[2] + z));
         idx = __shfl(idx, 0, 64);
-        if (lane == 0) page[db] = (int32_t)idx;
+        if (lane == 0) job.page[db] = (int32_t)idx;
         uint64_t w = 0;
         if (idx >= 0) {
-            const S *Db = D + idx * 512 + lane;
-            const S *Wb = W + idx * 512 + lane;
+            const S *Db = (const S *)job.D + idx * 512 + lane;
+            const S *Wb = (const S *)job.W + idx * 512 + lane;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const float Dv = ldv(Db + 64 * k), Wv = ldv(Wb + 64 * k);
@@ -101,7 +240,7 @@ __global__ __launch_bounds__(256) void k_page_sites(SubmapMeta *meta, const uint
                 if (lane == k) w = m;
             }
         }
-        if (lane < 8) sites[db * 8 + lane] = w;
+        if (lane < 8) sites[g * 8 + lane] = w;
     }
 }
 
@@ -123,15 +262,155 @@ __device__ __forceinline__ int nearest_bit(uint64_t lo, uint64_t hi, int p)
 }
 
 // ------------------------------------------------------------------------
-// y and z passes: lower envelope of parabolas per line (Felzenszwalb and
-// Huttenlocher).  One wave per block column; lane = one line.  A line longer
-// than kWin voxels is cut into output segments that each carry C = 8 HB >= R
-// voxels of context on both sides, which is exact because only k <= R^2 is
-// kept.  Breakpoints s(p, q) = ((f_q - f_p) + (q - p)(q + p)) / (2 (q - p))
-// are compared by integer cross-multiplication (|N| < 2^18, D <= 2 kWin), so
-// the envelope is exact.
+// Voxel-parallel passes: one 512-lane workgroup per block, one lane per
+// voxel (l = x + 8y + 64z), the 2 HB + 1 neighbour blocks along the pass axis
+// staged in LDS.  The min-plus search walks outward from the voxel and stops
+// once d^2 reaches the best value, so it is exact; its cost follows the
+// distance to the nearest site rather than the line length, which suits
+// small domains where per-line envelopes leave the GPU idle.
 
-constexpr int kWin = 256;  // window positions (u8 stack entries)
+__device__ __forceinline__ int sq8(uint8_t v) { return v == 255 ? kBig : (int)v * (int)v; }
+__device__ __forceinline__ int inf16(uint16_t v) { return v == 0xFFFF ? kBig : (int)v; }
+
+template <int NJ>
+__global__ __launch_bounds__(512) void k_edt_x_vox(const JobList<NJ> jl, const uint64_t *__restrict__ sites,
+                                                   uint8_t *__restrict__ g1, int R, int HB)
+{
+    __shared__ Plan lds;
+    __shared__ uint64_t wl[(2 * kMaxHalo + 1) * 8];
+    PlanView<NJ> pv;
+    pv.init(jl, 8 * HB, lds);
+    const int tid = threadIdx.x;
+    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;
+    const int nb = 2 * HB + 1;
+    for (int64_t g = blockIdx.x; g < pv.t[0]; g += gridDim.x) {
+        const JobInfo d = pv.info(pv.template job<&JobInfo::od>(g));
+        int bx, by, bz;
+        dom_coords(d, g - d.od, bx, by, bz);
+        if (tid < nb * 8) {
+            const int i = tid >> 3, k = tid & 7;
+            const int nx = bx + i - HB;
+            wl[tid] = (nx >= 0 && nx < d.dim[0]) ? sites[(g + (i - HB)) * 8 + k] : 0ull;
+        }
+        __syncthreads();
+        uint64_t lo = 0, hi = 0;
+        for (int i = 0; i < nb; ++i) {
+            const uint64_t byte = (wl[i * 8 + z] >> (8 * y)) & 0xFFull;
+            const int pos = 8 * i;
+            if (pos < 64) lo |= byte << pos;
+            else hi |= byte << (pos - 64);
+        }
+        const int dist = nearest_bit(lo, hi, 8 * HB + x);
+        g1[g * 512 + tid] = dist <= R ? (uint8_t)dist : (uint8_t)255;
+        __syncthreads();
+    }
+}
+
+template <int NJ>
+__global__ __launch_bounds__(512) void k_edt_y_vox(const JobList<NJ> jl, const uint8_t *__restrict__ g1,
+                                                   uint16_t *__restrict__ g2, int R, int HB)
+{
+    __shared__ Plan lds;
+    __shared__ __align__(16) uint32_t colw[(2 * kMaxHalo + 1) * 128];
+    PlanView<NJ> pv;
+    pv.init(jl, 8 * HB, lds);
+    const uint8_t *col = (const uint8_t *)colw;
+    const int tid = threadIdx.x;
+    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;
+    const int nb = 2 * HB + 1;
+    const int R2 = R * R;
+    const int Y = 8 * HB + y;
+    for (int64_t g = blockIdx.x; g < pv.t[0]; g += gridDim.x) {
+        const JobInfo d = pv.info(pv.template job<&JobInfo::od>(g));
+        int bx, by, bz;
+        dom_coords(d, g - d.od, bx, by, bz);
+        for (int e = tid; e < nb * 128; e += 512) {
+            const int i = e >> 7, w = e & 127;
+            const int ny = by + i - HB;
+            colw[e] = (ny >= 0 && ny < d.dim[1]) ? ((const uint32_t *)(g1 + (g + (int64_t)(i - HB) * d.dim[0]) * 512))[w]
+                                                 : 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        auto at = [&](int yy) { return col[(yy >> 3) * 512 + x + 8 * (yy & 7) + 64 * z]; };
+        int best = sq8(at(Y));
+        for (int dd = 1; dd <= R; ++dd) {
+            const int d2 = dd * dd;
+            if (d2 >= best) break;
+            best = min(best, min(sq8(at(Y - dd)), sq8(at(Y + dd))) + d2);
+        }
+        g2[g * 512 + tid] = best <= R2 ? (uint16_t)best : (uint16_t)0xFFFF;
+        __syncthreads();
+    }
+}
+
+// phi of one voxel from D, W and the squared distance search result.
+__device__ __forceinline__ float phi_value(float Dv, int best, int R2, float vs, float dmax)
+{
+    const float sg = Dv > 0.0f ? 1.0f : -1.0f;
+    if (best > R2) return sg * dmax;
+    return sg * fminf(dmax, vs * sqrtf((float)best));
+}
+
+template <typename S, int NJ>
+__global__ __launch_bounds__(512) void k_edt_z_vox(const JobList<NJ> jl, const uint16_t *__restrict__ g2, int R,
+                                                   int HB, float vs, float tau, float dmax)
+{
+    __shared__ Plan lds;
+    __shared__ __align__(16) uint32_t colw[(2 * kMaxHalo + 1) * 256];
+    PlanView<NJ> pv;
+    pv.init(jl, 8 * HB, lds);
+    const uint16_t *col = (const uint16_t *)colw;
+    const int tid = threadIdx.x;
+    const int z = tid >> 6;
+    const int nb = 2 * HB + 1;
+    const int R2 = R * R;
+    const int Z = 8 * HB + z;
+    for (int64_t w = blockIdx.x; w < pv.t[1]; w += gridDim.x) {
+        const int jj = pv.template job<&JobInfo::ob>(w);
+        const JobInfo d = pv.info(jj);
+        const EsdfJob &job = jl.j[jj];
+        const int64_t j = w - d.ob;
+        int bx, by, bz;
+        unpack_key(job.keys[j], bx, by, bz);
+        bx -= d.lo[0]; by -= d.lo[1]; bz -= d.lo[2];
+        const int64_t g = d.od + dom_index(d, bx, by, bz);
+        const int64_t stride_z = (int64_t)d.dim[0] * d.dim[1];
+        for (int e = tid; e < nb * 256; e += 512) {
+            const int i = e >> 8, q = e & 255;
+            const int nz = bz + i - HB;
+            colw[e] = (nz >= 0 && nz < d.dim[2]) ? ((const uint32_t *)(g2 + (g + (int64_t)(i - HB) * stride_z) * 512))[q]
+                                                 : 0xFFFFFFFFu;
+        }
+        const float Dv = ldv((const S *)job.D + j * 512 + tid), Wv = ldv((const S *)job.W + j * 512 + tid);
+        __syncthreads();
+        float out;
+        if (!(Wv > 0.0f)) {
+            out = __builtin_nanf("");
+        } else if (fabsf(Dv) < tau) {
+            out = Dv;
+        } else {
+            const int base = tid & 63;
+            auto at = [&](int zz) { return col[(zz >> 3) * 512 + base + 64 * (zz & 7)]; };
+            int best = inf16(at(Z));
+            for (int dd = 1; dd <= R; ++dd) {
+                const int d2 = dd * dd;
+                if (d2 >= best) break;
+                best = min(best, min(inf16(at(Z - dd)), inf16(at(Z + dd))) + d2);
+            }
+            out = phi_value(Dv, best, R2, vs, dmax);
+        }
+        job.phi[j * 512 + tid] = out;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// Per-line passes: lower envelope of parabolas (Felzenszwalb and
+// Huttenlocher, edt_envelope.h).  One wave per block column; lane = one
+// line.  A line longer than kWin voxels is cut into output segments that each
+// carry C = 8 HB >= R voxels of context on both sides, which is exact because
+// only k <= R^2 is kept.  Work per voxel is a few LDS steps whatever the
+// distances, which suits large domains with many lines.
 
 __device__ __forceinline__ void segment(int L, int C, int seg, int S, int &y0, int &y1, int &w0, int &w1)
 {
@@ -141,42 +420,43 @@ __device__ __forceinline__ void segment(int L, int C, int seg, int S, int &y0, i
     w1 = min(L, y1 + C);
 }
 
-// g2(x, y, z) = min_y' g1(x, y', z)^2 + (y - y')^2, kept when <= R^2.
 // Lane = x + 8 z within the block column (bx, *, bz).
-__global__ __launch_bounds__(64) void k_edt_y_env(const SubmapMeta *meta, const uint8_t *__restrict__ g1,
-                                              uint16_t *__restrict__ g2, int R, int HB)
+template <int NJ>
+__global__ __launch_bounds__(64) void k_edt_y_env(const JobList<NJ> jl, const uint8_t *__restrict__ g1,
+                                                  uint16_t *__restrict__ g2, int R, int HB)
 {
+    __shared__ Plan lds;
     __shared__ __align__(16) uint8_t col[kWin * 64];   // [position][lane]
     __shared__ __align__(16) uint8_t stk[kWin * 64];   // [entry][lane]
     __shared__ __align__(16) uint16_t ost[8 * 64];     // one block of outputs [y][lane]
-    const Dom d = read_dom(meta);
-    const int lane = threadIdx.x;
     const int C = 8 * HB;
-    const int S = kWin - 2 * C;
-    const int L = 8 * d.dim[1];
-    const int nseg = L > 0 ? (L + S - 1) / S : 0;
-    const int64_t ncol = (int64_t)d.dim[0] * d.dim[2] * nseg;
+    PlanView<NJ> pv;
+    pv.init(jl, C, lds);
+    const int lane = threadIdx.x;
+    const int Sg = kWin - 2 * C;
     const int R2 = R * R;
     auto getf = [&](int q) {
         const int a = col[q * 64 + lane];
         return a * a;
     };
-    for (int64_t c = blockIdx.x; c < ncol; c += gridDim.x) {
-        const int seg = (int)(c % nseg);
-        const int64_t cc = c / nseg;
+    for (int64_t c = blockIdx.x; c < pv.t[2]; c += gridDim.x) {
+        const JobInfo d = pv.info(pv.template job<&JobInfo::oy>(c));
+        const int L = 8 * d.dim[1];
+        const int nseg = (int)nsegments(L, Sg);
+        const int64_t cl = c - d.oy;
+        const int seg = (int)(cl % nseg);
+        const int64_t cc = cl / nseg;
         const int bx = (int)(cc % d.dim[0]), bz = (int)(cc / d.dim[0]);
         int y0, y1, w0, w1;
-        segment(L, C, seg, S, y0, y1, w0, w1);
-        // stage the window: block j holds bytes (x = 0..7) for (y = lane & 7, z = lane >> 3)
+        segment(L, C, seg, Sg, y0, y1, w0, w1);
         for (int j = w0 / 8; j < w1 / 8; ++j) {
-            const int64_t db = dom_index(d, bx, j, bz);
-            const uint64_t v = ((const uint64_t *)(g1 + db * 512))[lane];
+            const int64_t g = d.od + dom_index(d, bx, j, bz);
+            const uint64_t v = ((const uint64_t *)(g1 + g * 512))[lane];
             *(uint64_t *)&col[(8 * (j - w0 / 8) + (lane & 7)) * 64 + 8 * (lane >> 3)] = v;
         }
         wave_sync();
         Envelope e;
-        e.k = -1;
-        e.p = e.fp = e.pp = e.fpp = 0;
+        env_clear(e);
         const int W = w1 - w0;
         for (int q = 0; q < W; ++q) {
             const int a = col[q * 64 + lane];
@@ -196,48 +476,57 @@ __global__ __launch_bounds__(64) void k_edt_y_env(const SubmapMeta *meta, const 
                 ost[t * 64 + lane] = (uint16_t)v;
             }
             wave_sync();
-            const int64_t db = dom_index(d, bx, yb / 8, bz);
+            const int64_t g = d.od + dom_index(d, bx, yb / 8, bz);
             const uint4 o = *(const uint4 *)&ost[(lane & 7) * 64 + 8 * (lane >> 3)];
-            *(uint4 *)(g2 + db * 512 + 8 * lane) = o;
+            *(uint4 *)(g2 + g * 512 + 8 * lane) = o;
             wave_sync();
         }
     }
 }
 
-// k(x, y, z) = min_z' g2(x, y, z')  + (z - z')^2 and phi for the allocated
-// blocks of the column (bx, by, *).  Lane = x + 8 y, the in-block layout.
-template <typename S>
-__global__ __launch_bounds__(64) void k_edt_z_env(const SubmapMeta *meta, const int32_t *__restrict__ page,
-                                              const uint16_t *__restrict__ g2, const S *__restrict__ D,
-                                              const S *__restrict__ W, float *__restrict__ phi, int R, int HB,
-                                              float vs, float tau, float dmax)
+// Lane = x + 8 y, the in-block layout, within the column (bx, by, *).
+template <typename S, int NJ>
+__global__ __launch_bounds__(64) void k_edt_z_env(const JobList<NJ> jl, const uint16_t *__restrict__ g2, int R,
+                                                  int HB, float vs, float tau, float dmax)
 {
+    __shared__ Plan lds;
     __shared__ __align__(16) uint16_t col[kWin * 64];  // [position][lane]
     __shared__ __align__(16) uint8_t stk[kWin * 64];
-    const Dom d = read_dom(meta);
-    const int lane = threadIdx.x;
     const int C = 8 * HB;
+    PlanView<NJ> pv;
+    pv.init(jl, C, lds);
+    const int lane = threadIdx.x;
     const int Sg = kWin - 2 * C;
-    const int L = 8 * d.dim[2];
-    const int nseg = L > 0 ? (L + Sg - 1) / Sg : 0;
-    const int64_t ncol = (int64_t)d.dim[0] * d.dim[1] * nseg;
     const int R2 = R * R;
     auto getf = [&](int q) { return (int)col[q * 64 + lane]; };
-    for (int64_t c = blockIdx.x; c < ncol; c += gridDim.x) {
-        const int seg = (int)(c % nseg);
-        const int64_t cc = c / nseg;
+    for (int64_t c = blockIdx.x; c < pv.t[3]; c += gridDim.x) {
+        const int jj = pv.template job<&JobInfo::oz>(c);
+        const JobInfo d = pv.info(jj);
+        const EsdfJob &job = jl.j[jj];
+        const int L = 8 * d.dim[2];
+        const int nseg = (int)nsegments(L, Sg);
+        const int64_t cl = c - d.oz;
+        const int seg = (int)(cl % nseg);
+        const int64_t cc = cl / nseg;
         const int bx = (int)(cc % d.dim[0]), by = (int)(cc / d.dim[0]);
         int z0, z1, w0, w1;
         segment(L, C, seg, Sg, z0, z1, w0, w1);
+        // nothing to write when no block of the output range is allocated
+        bool any = false;
+        for (int j0 = z0 / 8; j0 < z1 / 8; j0 += 64) {
+            const int j = j0 + lane;
+            const bool a = j < z1 / 8 && job.page[dom_index(d, bx, by, j)] >= 0;
+            any = any || __ballot(a) != 0;
+        }
+        if (!any) continue;
         for (int j = w0 / 8; j < w1 / 8; ++j) {
-            const uint16_t *src = g2 + dom_index(d, bx, by, j) * 512 + lane;
+            const uint16_t *src = g2 + (d.od + dom_index(d, bx, by, j)) * 512 + lane;
 #pragma unroll
             for (int t = 0; t < 8; ++t) col[(8 * (j - w0 / 8) + t) * 64 + lane] = src[64 * t];
         }
         wave_sync();
         Envelope e;
-        e.k = -1;
-        e.p = e.fp = e.pp = e.fpp = 0;
+        env_clear(e);
         const int Wn = w1 - w0;
         for (int q = 0; q < Wn; ++q) {
             const int a = col[q * 64 + lane];
@@ -247,11 +536,11 @@ __global__ __launch_bounds__(64) void k_edt_z_env(const SubmapMeta *meta, const 
         Walker wk;
         if (e.k >= 0) walk_init(wk, e, stk, 64, lane, getf);
         for (int zb = z0; zb < z1; zb += 8) {
-            const int64_t idx = page[dom_index(d, bx, by, zb / 8)];
+            const int64_t idx = job.page[dom_index(d, bx, by, zb / 8)];
             if (idx < 0) continue;
-            const S *Db = D + idx * 512 + lane;
-            const S *Wb = W + idx * 512 + lane;
-            float *Pb = phi + idx * 512 + lane;
+            const S *Db = (const S *)job.D + idx * 512 + lane;
+            const S *Wb = (const S *)job.W + idx * 512 + lane;
+            float *Pb = job.phi + idx * 512 + lane;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 const float Dv = ldv(Db + 64 * t), Wv = ldv(Wb + 64 * t);
@@ -261,11 +550,8 @@ __global__ __launch_bounds__(64) void k_edt_z_env(const SubmapMeta *meta, const 
                 } else if (fabsf(Dv) < tau) {
                     out = Dv;
                 } else {
-                    int best = kBig;
-                    if (e.k >= 0) best = walk_at(wk, e, stk, 64, lane, zb + t - w0, getf);
-                    const float sg = Dv > 0.0f ? 1.0f : -1.0f;
-                    if (best > R2) out = sg * dmax;
-                    else out = sg * fminf(dmax, vs * sqrtf((float)best));
+                    const int best = e.k >= 0 ? walk_at(wk, e, stk, 64, lane, zb + t - w0, getf) : kBig;
+                    out = phi_value(Dv, best, R2, vs, dmax);
                 }
                 Pb[64 * t] = out;
             }
@@ -274,154 +560,9 @@ __global__ __launch_bounds__(64) void k_edt_z_env(const SubmapMeta *meta, const 
     }
 }
 
-// ------------------------------------------------------------------------
-// Voxel-parallel passes: one 512-lane workgroup per block, one lane per
-// voxel (l = x + 8y + 64z), the 2 HB + 1 neighbour blocks along the pass axis
-// staged in LDS.  The min-plus search walks outward from the voxel and stops
-// once d^2 reaches the best value, so it is exact; its cost follows the
-// distance to the nearest site rather than the line length, which suits
-// small domains where per-line envelopes leave the GPU idle.
+unsigned clamp_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 65536)); }
 
-__device__ __forceinline__ int sq8(uint8_t v) { return v == 255 ? kBig : (int)v * (int)v; }
-__device__ __forceinline__ int inf16(uint16_t v) { return v == 0xFFFF ? kBig : (int)v; }
-
-__global__ __launch_bounds__(512) void k_edt_x_vox(const SubmapMeta *meta, const uint64_t *__restrict__ sites,
-                                                   uint8_t *__restrict__ g1, int R, int HB)
-{
-    __shared__ uint64_t wl[(2 * kMaxHalo + 1) * 8];
-    const Dom d = read_dom(meta);
-    const int tid = threadIdx.x;
-    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;
-    const int nb = 2 * HB + 1;
-    for (int64_t db = blockIdx.x; db < d.n; db += gridDim.x) {
-        int bx, by, bz;
-        dom_coords(d, db, bx, by, bz);
-        if (tid < nb * 8) {
-            const int i = tid >> 3, k = tid & 7;
-            const int nx = bx + i - HB;
-            wl[tid] = (nx >= 0 && nx < d.dim[0]) ? sites[(db + (i - HB)) * 8 + k] : 0ull;
-        }
-        __syncthreads();
-        uint64_t lo = 0, hi = 0;
-        for (int i = 0; i < nb; ++i) {
-            const uint64_t byte = (wl[i * 8 + z] >> (8 * y)) & 0xFFull;
-            const int pos = 8 * i;
-            if (pos < 64) lo |= byte << pos;
-            else hi |= byte << (pos - 64);
-        }
-        const int dist = nearest_bit(lo, hi, 8 * HB + x);
-        g1[db * 512 + tid] = dist <= R ? (uint8_t)dist : (uint8_t)255;
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(512) void k_edt_y_vox(const SubmapMeta *meta, const uint8_t *__restrict__ g1,
-                                                   uint16_t *__restrict__ g2, int R, int HB)
-{
-    __shared__ __align__(16) uint32_t colw[(2 * kMaxHalo + 1) * 128];
-    const uint8_t *col = (const uint8_t *)colw;
-    const Dom d = read_dom(meta);
-    const int tid = threadIdx.x;
-    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;
-    const int nb = 2 * HB + 1;
-    const int R2 = R * R;
-    const int Y = 8 * HB + y;
-    for (int64_t db = blockIdx.x; db < d.n; db += gridDim.x) {
-        int bx, by, bz;
-        dom_coords(d, db, bx, by, bz);
-        for (int e = tid; e < nb * 128; e += 512) {
-            const int i = e >> 7, w = e & 127;
-            const int ny = by + i - HB;
-            colw[e] = (ny >= 0 && ny < d.dim[1]) ? ((const uint32_t *)(g1 + (db + (int64_t)(i - HB) * d.dim[0]) * 512))[w]
-                                                 : 0xFFFFFFFFu;
-        }
-        __syncthreads();
-        auto at = [&](int yy) { return col[(yy >> 3) * 512 + x + 8 * (yy & 7) + 64 * z]; };
-        int best = sq8(at(Y));
-        for (int dd = 1; dd <= R; ++dd) {
-            const int d2 = dd * dd;
-            if (d2 >= best) break;
-            best = min(best, min(sq8(at(Y - dd)), sq8(at(Y + dd))) + d2);
-        }
-        g2[db * 512 + tid] = best <= R2 ? (uint16_t)best : (uint16_t)0xFFFF;
-        __syncthreads();
-    }
-}
-
-template <typename S>
-__global__ __launch_bounds__(512) void k_edt_z_vox(const SubmapMeta *meta, const uint64_t *__restrict__ keys,
-                                                   const uint16_t *__restrict__ g2, const S *__restrict__ D,
-                                                   const S *__restrict__ W, float *__restrict__ phi, int R, int HB,
-                                                   float vs, float tau, float dmax)
-{
-    __shared__ __align__(16) uint32_t colw[(2 * kMaxHalo + 1) * 256];
-    const uint16_t *col = (const uint16_t *)colw;
-    const Dom d = read_dom(meta);
-    const int64_t nbk = meta->n_blocks;
-    const int tid = threadIdx.x;
-    const int z = tid >> 6;
-    const int nb = 2 * HB + 1;
-    const int R2 = R * R;
-    const int Z = 8 * HB + z;
-    const int64_t stride_z = (int64_t)d.dim[0] * d.dim[1];
-    for (int64_t j = blockIdx.x; j < nbk; j += gridDim.x) {
-        int bx, by, bz;
-        unpack_key(keys[j], bx, by, bz);
-        bx -= d.lo[0]; by -= d.lo[1]; bz -= d.lo[2];
-        const int64_t db = dom_index(d, bx, by, bz);
-        for (int e = tid; e < nb * 256; e += 512) {
-            const int i = e >> 8, w = e & 255;
-            const int nz = bz + i - HB;
-            colw[e] = (nz >= 0 && nz < d.dim[2]) ? ((const uint32_t *)(g2 + (db + (int64_t)(i - HB) * stride_z) * 512))[w]
-                                                 : 0xFFFFFFFFu;
-        }
-        const float Dv = ldv(D + j * 512 + tid), Wv = ldv(W + j * 512 + tid);
-        __syncthreads();
-        float out;
-        if (!(Wv > 0.0f)) {
-            out = __builtin_nanf("");
-        } else if (fabsf(Dv) < tau) {
-            out = Dv;
-        } else {
-            const int base = tid & 63;
-            auto at = [&](int zz) { return col[(zz >> 3) * 512 + base + 64 * (zz & 7)]; };
-            int best = inf16(at(Z));
-            for (int dd = 1; dd <= R; ++dd) {
-                const int d2 = dd * dd;
-                if (d2 >= best) break;
-                best = min(best, min(inf16(at(Z - dd)), inf16(at(Z + dd))) + d2);
-            }
-            const float sg = Dv > 0.0f ? 1.0f : -1.0f;
-            if (best > R2) out = sg * dmax;
-            else out = sg * fminf(dmax, vs * sqrtf((float)best));
-        }
-        phi[j * 512 + tid] = out;
-        __syncthreads();
-    }
-}
-
-unsigned grid_for(int64_t waves)
-{
-    const int64_t g = (waves + 3) / 4;
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
-}
-
-}  // namespace
-
-// Workgroups for a line pass: the columns (block extents along axes a and b
-// of the host-side bound box) times the segments along the third axis.
-static unsigned grid_cols(const covox_submap *s, int a, int b, int HB)
-{
-    if (!s->bound_valid) return 1;
-    const int c = 3 - a - b;
-    const int64_t L = 8 * (int64_t)(s->bound_hi[c] - s->bound_lo[c] + 1);
-    const int64_t S = kWin - 16 * HB;
-    const int64_t nseg = (L + S - 1) / S;
-    const int64_t n = (int64_t)(s->bound_hi[a] - s->bound_lo[a] + 1) * (s->bound_hi[b] - s->bound_lo[b] + 1) * nseg;
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 65536));
-}
-
-static int64_t bound_blocks(const covox_submap *s)
+int64_t bound_blocks(const covox_submap *s)
 {
     if (!s->bound_valid) return 0;
     int64_t n = 1;
@@ -429,85 +570,134 @@ static int64_t bound_blocks(const covox_submap *s)
     return n;
 }
 
-int build_page(covox_ctx *ctx, covox_submap *s)
+// Columns (times segments) of a line pass over the host-side bound box:
+// axes a and b span the columns, the third axis is the line.
+int64_t bound_cols(const covox_submap *s, int a, int b, int HB)
 {
-    if (s->page_version == s->version) return COVOX_OK;
-    const int64_t nd = std::max<int64_t>(bound_blocks(s), 1);
-    int rc;
-    if ((rc = ensure_buffer(ctx, (void **)&s->page, &s->page_cap, nd, sizeof(int32_t), "page"))) return rc;
-    if ((rc = ensure_buffer(ctx, (void **)&ctx->sites, &ctx->sites_cap, nd, 8 * sizeof(uint64_t), "site masks")))
-        return rc;
-    const float vs = (float)ctx->p.voxel_size;
-    const uint64_t tmask = (uint64_t)s->tcap - 1;
-    {
-        TimedLaunch tl(ctx, COVOX_K_ESDF_PAGE);
-        if (ctx->p.precision == COVOX_FP16)
-            hipLaunchKernelGGL(k_page_sites<__half>, dim3(grid_for(nd)), dim3(256), 0, ctx->stream, s->meta,
-                               s->tkeys, s->tvals, tmask, (const __half *)s->D, (const __half *)s->W, vs, s->page,
-                               ctx->sites);
-        else
-            hipLaunchKernelGGL(k_page_sites<float>, dim3(grid_for(nd)), dim3(256), 0, ctx->stream, s->meta,
-                               s->tkeys, s->tvals, tmask, (const float *)s->D, (const float *)s->W, vs, s->page,
-                               ctx->sites);
-    }
-    if ((rc = hip_check(ctx, hipGetLastError(), "page launch"))) return rc;
-    s->page_version = s->version;
-    return COVOX_OK;
+    if (!s->bound_valid) return 0;
+    const int c = 3 - a - b;
+    const int64_t L = 8 * (int64_t)(s->bound_hi[c] - s->bound_lo[c] + 1);
+    const int64_t S = kWin - 16 * HB;
+    return (int64_t)(s->bound_hi[a] - s->bound_lo[a] + 1) * (s->bound_hi[b] - s->bound_lo[b] + 1) * ((L + S - 1) / S);
 }
 
-int update_esdf(covox_ctx *ctx, covox_submap *s)
+template <int NJ>
+JobList<NJ> make_jobs(covox_submap *const *subs, int n)
 {
-    if (s->esdf_version == s->version) return COVOX_OK;
+    JobList<NJ> jl;
+    memset(&jl, 0, sizeof(jl));
+    jl.n = n;
+    for (int i = 0; i < n; ++i) {
+        covox_submap *s = subs[i];
+        jl.j[i] = EsdfJob{s->meta, s->keys, s->tkeys, s->tvals, (uint64_t)s->tcap - 1, s->D, s->W, s->phi, s->page};
+    }
+    return jl;
+}
+
+// Page + site masks (and, with edt, the three EDT passes) for up to NJ
+// submaps in one launch per kernel.
+template <int NJ>
+int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt)
+{
     const covox_params &p = ctx->p;
     const int R = (int)std::llround(p.d_max / p.voxel_size);
     const int HB = (R + 7) / 8;
-    // the site masks of the page build are consumed here: rebuild them
-    s->page_version = 0;
+    const int C = 8 * HB;
     int rc;
-    if ((rc = build_page(ctx, s))) return rc;
-    const int64_t nd = std::max<int64_t>(bound_blocks(s), 1);
-    if ((rc = ensure_buffer(ctx, (void **)&ctx->g1, &ctx->g1_cap, nd, 512, "edt g1"))) return rc;
-    if ((rc = ensure_buffer(ctx, (void **)&ctx->g2, &ctx->g2_cap, nd, 1024, "edt g2"))) return rc;
-    const float vs = (float)p.voxel_size, tau = (float)(p.trunc_vox * p.voxel_size), dmax = (float)p.d_max;
+    int64_t nd = 0, nb = 0, cy = 0, cz = 0;
+    for (int i = 0; i < n; ++i) {
+        covox_submap *s = subs[i];
+        const int64_t b = std::max<int64_t>(bound_blocks(s), 1);
+        if ((rc = ensure_buffer(ctx, (void **)&s->page, &s->page_cap, b, sizeof(int32_t), "page"))) return rc;
+        nd += b;
+        nb += std::min(s->nb_upper, s->cap);
+        cy += bound_cols(s, 0, 2, HB);
+        cz += bound_cols(s, 0, 1, HB);
+    }
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->sites, &ctx->sites_cap, nd, 8 * sizeof(uint64_t), "site masks")))
+        return rc;
+    if (edt) {
+        if ((rc = ensure_buffer(ctx, (void **)&ctx->g1, &ctx->g1_cap, nd, 512, "edt g1"))) return rc;
+        if ((rc = ensure_buffer(ctx, (void **)&ctx->g2, &ctx->g2_cap, nd, 1024, "edt g2"))) return rc;
+    }
+    const JobList<NJ> jl = make_jobs<NJ>(subs, n);
+    const float vs = (float)p.voxel_size, tau = (float)band_limit(p), dmax = (float)p.d_max;
+    const bool h = p.precision == COVOX_FP16;
+    {
+        TimedLaunch tl(ctx, COVOX_K_ESDF_PAGE);
+        if (h)
+            hipLaunchKernelGGL((k_page_sites<__half, NJ>), dim3(clamp_grid((nd + 3) / 4)), dim3(256), 0, ctx->stream,
+                               jl, C, vs, ctx->sites);
+        else
+            hipLaunchKernelGGL((k_page_sites<float, NJ>), dim3(clamp_grid((nd + 3) / 4)), dim3(256), 0, ctx->stream,
+                               jl, C, vs, ctx->sites);
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "page launch"))) return rc;
+    for (int i = 0; i < n; ++i) subs[i]->page_version = subs[i]->version;
+    if (!edt) return COVOX_OK;
     // Pass shape: per-line envelopes when there are enough lines to fill the
     // GPU, voxel-parallel windowed search otherwise (or as forced by
     // COVOX_EDT_MODE = window | envelope).
-    const unsigned cols_y = grid_cols(s, 0, 2, HB), cols_z = grid_cols(s, 0, 1, HB);
-    bool envelope = std::min(cols_y, cols_z) >= (unsigned)ctx->edt_env_min_cols;
+    bool envelope = std::min(cy, cz) >= (int64_t)ctx->edt_env_min_cols;
     if (ctx->edt_mode == 1) envelope = false;
     if (ctx->edt_mode == 2) envelope = true;
-    const unsigned gd = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nd, 65536));
-    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(std::min(s->nb_upper, s->cap), 65536));
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_X);
-        hipLaunchKernelGGL(k_edt_x_vox, dim3(gd), dim3(512), 0, ctx->stream, s->meta, ctx->sites, ctx->g1, R, HB);
+        hipLaunchKernelGGL((k_edt_x_vox<NJ>), dim3(clamp_grid(nd)), dim3(512), 0, ctx->stream, jl, ctx->sites, ctx->g1,
+                           R, HB);
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Y);
         if (envelope)
-            hipLaunchKernelGGL(k_edt_y_env, dim3(cols_y), dim3(64), 0, ctx->stream, s->meta, ctx->g1, ctx->g2, R, HB);
+            hipLaunchKernelGGL((k_edt_y_env<NJ>), dim3(clamp_grid(cy)), dim3(64), 0, ctx->stream, jl, ctx->g1, ctx->g2,
+                               R, HB);
         else
-            hipLaunchKernelGGL(k_edt_y_vox, dim3(gd), dim3(512), 0, ctx->stream, s->meta, ctx->g1, ctx->g2, R, HB);
+            hipLaunchKernelGGL((k_edt_y_vox<NJ>), dim3(clamp_grid(nd)), dim3(512), 0, ctx->stream, jl, ctx->g1,
+                               ctx->g2, R, HB);
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Z);
-        const bool h = p.precision == COVOX_FP16;
         if (envelope && h)
-            hipLaunchKernelGGL(k_edt_z_env<__half>, dim3(cols_z), dim3(64), 0, ctx->stream, s->meta, s->page, ctx->g2,
-                               (const __half *)s->D, (const __half *)s->W, s->phi, R, HB, vs, tau, dmax);
+            hipLaunchKernelGGL((k_edt_z_env<__half, NJ>), dim3(clamp_grid(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2,
+                               R, HB, vs, tau, dmax);
         else if (envelope)
-            hipLaunchKernelGGL(k_edt_z_env<float>, dim3(cols_z), dim3(64), 0, ctx->stream, s->meta, s->page, ctx->g2,
-                               (const float *)s->D, (const float *)s->W, s->phi, R, HB, vs, tau, dmax);
+            hipLaunchKernelGGL((k_edt_z_env<float, NJ>), dim3(clamp_grid(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2,
+                               R, HB, vs, tau, dmax);
         else if (h)
-            hipLaunchKernelGGL(k_edt_z_vox<__half>, dim3(gb), dim3(512), 0, ctx->stream, s->meta, s->keys, ctx->g2,
-                               (const __half *)s->D, (const __half *)s->W, s->phi, R, HB, vs, tau, dmax);
+            hipLaunchKernelGGL((k_edt_z_vox<__half, NJ>), dim3(clamp_grid(nb)), dim3(512), 0, ctx->stream, jl,
+                               ctx->g2, R, HB, vs, tau, dmax);
         else
-            hipLaunchKernelGGL(k_edt_z_vox<float>, dim3(gb), dim3(512), 0, ctx->stream, s->meta, s->keys, ctx->g2,
-                               (const float *)s->D, (const float *)s->W, s->phi, R, HB, vs, tau, dmax);
+            hipLaunchKernelGGL((k_edt_z_vox<float, NJ>), dim3(clamp_grid(nb)), dim3(512), 0, ctx->stream, jl, ctx->g2,
+                               R, HB, vs, tau, dmax);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "esdf launch"))) return rc;
-    s->esdf_version = s->version;
+    for (int i = 0; i < n; ++i) subs[i]->esdf_version = subs[i]->version;
     return COVOX_OK;
 }
+
+}  // namespace
+
+int build_page(covox_ctx *ctx, covox_submap *s)
+{
+    if (s->page_version == s->version) return COVOX_OK;
+    return esdf_chunk<1>(ctx, &s, 1, false);
+}
+
+int update_esdf_batch(covox_ctx *ctx, covox_submap *const *subs, int n)
+{
+    std::vector<covox_submap *> todo;
+    for (int i = 0; i < n; ++i)
+        if (std::find(todo.begin(), todo.end(), subs[i]) == todo.end()) todo.push_back(subs[i]);
+    if (todo.empty()) return COVOX_OK;
+    if (todo.size() == 1) return esdf_chunk<1>(ctx, todo.data(), 1, true);
+    for (size_t i = 0; i < todo.size(); i += kMaxJobs) {
+        const int m = (int)std::min<size_t>(kMaxJobs, todo.size() - i);
+        const int rc = esdf_chunk<kMaxJobs>(ctx, todo.data() + i, m, true);
+        if (rc) return rc;
+    }
+    return COVOX_OK;
+}
+
+int update_esdf(covox_ctx *ctx, covox_submap *s) { return update_esdf_batch(ctx, &s, 1); }
 
 }  // namespace covox

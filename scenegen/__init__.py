@@ -66,6 +66,14 @@ def _load():
         lib.sg_philox4x32_10.argtypes = [u32p, u32p, u32p]
         lib.sg_pixel_draws.restype = None
         lib.sg_pixel_draws.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, dp]
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lib.sg_render_outdoor.restype = None
+        lib.sg_render_outdoor.argtypes = [
+            dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, i32p, i32p,
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+            ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp,
+            ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32, fp,
+        ]
         lib.sg_hfield_eval.restype = ctypes.c_double
         lib.sg_hfield_eval.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -195,6 +203,8 @@ class Scene:
 
 def render(scene: Scene, cam: Camera, T_world_cam: np.ndarray, seed: int, frame: int) -> np.ndarray:
     """Render one float32 depth frame (H x W, metres, 0 = invalid)."""
+    if isinstance(scene, OutdoorScene):
+        return scene.render(cam, T_world_cam, seed, frame)
     lib = _load()
     out = np.zeros((cam.H, cam.W), np.float32)
     room = np.ascontiguousarray(scene.room if scene.room is not None else np.zeros(6), np.float64)
@@ -219,6 +229,55 @@ def render(scene: Scene, cam: Camera, T_world_cam: np.ndarray, seed: int, frame:
                   frame & 0xFFFFFFFF, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
     del hf
     return out
+
+
+@dataclass
+class OutdoorScene:
+    """Heightfield ground (bilinear on a grid of spacing hs) plus solid boxes
+    (building walls), with a coarse 2-D cell list for the boxes."""
+    hfield: np.ndarray            # (ny, nx)
+    hs: float
+    origin: tuple
+    boxes: np.ndarray             # (n, 6)
+    cell: float = 5.0
+    buildings: list = field(default_factory=list)   # (lo, hi) footprints with base and height
+
+    def __post_init__(self):
+        x0, y0 = self.origin
+        ny, nx = self.hfield.shape
+        self.ncx = int(math.ceil((nx - 1) * self.hs / self.cell))
+        self.ncy = int(math.ceil((ny - 1) * self.hs / self.cell))
+        lists = [[] for _ in range(self.ncx * self.ncy)]
+        for i, b in enumerate(self.boxes):
+            cx0 = max(0, int((b[0] - x0) // self.cell)); cx1 = min(self.ncx - 1, int((b[3] - x0) // self.cell))
+            cy0 = max(0, int((b[1] - y0) // self.cell)); cy1 = min(self.ncy - 1, int((b[4] - y0) // self.cell))
+            for cy in range(cy0, cy1 + 1):
+                for cx in range(cx0, cx1 + 1):
+                    lists[cy * self.ncx + cx].append(i)
+        self._start = np.zeros(len(lists) + 1, np.int32)
+        self._start[1:] = np.cumsum([len(l) for l in lists])
+        self._items = np.array([i for l in lists for i in l] or [0], np.int32)
+        self._hf = np.ascontiguousarray(self.hfield, np.float64)
+        self._box = np.ascontiguousarray(self.boxes.reshape(-1) if len(self.boxes) else np.zeros(6), np.float64)
+
+    def height(self, x, y):
+        lib = _load()
+        ny, nx = self._hf.shape
+        return lib.sg_hfield_eval(_dp(self._hf), nx, ny, self.origin[0], self.origin[1], self.hs, float(x), float(y))
+
+    def render(self, cam, T_world_cam, seed, frame):
+        lib = _load()
+        out = np.zeros((cam.H, cam.W), np.float32)
+        T = np.ascontiguousarray(T_world_cam, np.float64).reshape(16)
+        ny, nx = self._hf.shape
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        lib.sg_render_outdoor(_dp(self._hf), nx, ny, self.origin[0], self.origin[1], self.hs, _dp(self._box),
+                              self._start.ctypes.data_as(i32), self._items.ctypes.data_as(i32), self.ncx, self.ncy,
+                              self.origin[0], self.origin[1], self.cell, cam.H, cam.W, cam.fx, cam.fy, cam.cx, cam.cy,
+                              _dp(T), cam.max_range, cam.noise_model, cam.noise_a, cam.invalid_frac,
+                              seed & 0xFFFFFFFF, frame & 0xFFFFFFFF,
+                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        return out
 
 
 @dataclass
@@ -377,3 +436,182 @@ def wall_scene(z0: float, H: int = 12, W: int = 16, f: float = 12.0) -> tuple[Sc
     scene = Scene(room=np.array([-50.0, -50.0, -50.0, 50.0, 50.0, z0]))
     cam = Camera(H=H, W=W, fx=f, fy=f, cx=(W - 1) / 2.0, cy=(H - 1) / 2.0, max_range=10.0)
     return scene, cam
+
+
+# ------------------------------------------------------------ outdoor (MAV)
+
+def _value_noise(rng, nx, ny, hs, spacing):
+    """Value noise on the sample grid: uniform lattice values every `spacing`
+    metres, smoothstep-bilinear in between."""
+    gx = np.arange(nx) * hs / spacing
+    gy = np.arange(ny) * hs / spacing
+    lat = rng.uniform(-1.0, 1.0, size=(int(gy[-1]) + 2, int(gx[-1]) + 2))
+    ix, iy = np.floor(gx).astype(int), np.floor(gy).astype(int)
+    fx, fy = gx - ix, gy - iy
+    sx, sy = fx * fx * (3 - 2 * fx), fy * fy * (3 - 2 * fy)
+    a = lat[iy][:, ix] * (1 - sx) + lat[iy][:, ix + 1] * sx
+    b = lat[iy + 1][:, ix] * (1 - sx) + lat[iy + 1][:, ix + 1] * sx
+    return a * (1 - sy[:, None]) + b * sy[:, None]
+
+
+def _wall_boxes(lo, hi, axis, door_c, door_w, door_h, z0):
+    """A wall box [lo, hi] with a door opening centred at door_c along `axis`
+    (0: wall runs along x, 1: along y), split into left, right and lintel."""
+    out = []
+    a0, a1 = lo[axis], hi[axis]
+    d0, d1 = door_c - door_w / 2, door_c + door_w / 2
+    for s0, s1 in ((a0, d0), (d1, a1)):
+        if s1 - s0 > 1e-6:
+            l, h = lo.copy(), hi.copy()
+            l[axis], h[axis] = s0, s1
+            out.append(np.concatenate([l, h]))
+    l, h = lo.copy(), hi.copy()
+    l[axis], h[axis] = d0, d1
+    l[2] = z0 + door_h
+    if h[2] > l[2]:
+        out.append(np.concatenate([l, h]))
+    return out
+
+
+def mav(seed: int = 3, n_frames: int = 3000, path_length: float = 400.0, noise: bool = True) -> Workload:
+    """Outdoor 120 x 80 x 20 m scene: rubble heightfield (4 octaves of value
+    noise, 0.5 m samples) plus 15-30 buildings with 0.3 m walls and door
+    openings; a seeded spline at 2-8 m above ground that passes through one
+    building; 640x480 frames, fx = fy = 380, range 10 m, sigma = 0.002 z^2."""
+    rng = np.random.default_rng(seed)
+    hs, X, Y = 0.5, 120.0, 80.0
+    nx, ny = int(X / hs) + 1, int(Y / hs) + 1
+    h = np.zeros((ny, nx))
+    for spacing, amp in ((8.0, 1.4), (4.0, 0.8), (2.0, 0.5), (1.0, 0.3)):
+        h += amp * _value_noise(rng, nx, ny, hs, spacing)
+    h -= h.min()
+    xs, ys = np.arange(nx) * hs, np.arange(ny) * hs
+    boxes, foot = [], []
+    n_b = int(rng.integers(15, 31))
+    corridor = None  # (x0, x1, y0, y1): kept free for the passage through building 0
+    tries = 0
+    while len(foot) < n_b and tries < 4000:
+        tries += 1
+        w, l, ht = rng.uniform(7, 12), rng.uniform(7, 10), rng.uniform(3, 6)
+        if not foot:
+            c = rng.uniform([35, 25], [X - 35, Y - 25])
+        else:
+            c = rng.uniform([12, 12], [X - 12, Y - 12])
+        lo = np.array([c[0] - w / 2, c[1] - l / 2])
+        hi = np.array([c[0] + w / 2, c[1] + l / 2])
+        if any(np.all(lo < f[1] + 4) and np.all(f[0] < hi + 4) for f in foot):
+            continue
+        if corridor is not None and lo[0] < corridor[1] and corridor[0] < hi[0] and lo[1] < corridor[3] \
+                and corridor[2] < hi[1]:
+            continue
+        mx = (xs >= lo[0] - 1) & (xs <= hi[0] + 1)
+        my = (ys >= lo[1] - 1) & (ys <= hi[1] + 1)
+        base = float(h[np.ix_(my, mx)].mean())
+        h[np.ix_(my, mx)] = base
+        if not foot:
+            cyc = (lo[1] + hi[1]) / 2
+            corridor = (lo[0] - 25, hi[0] + 25, cyc - 5, cyc + 5)
+            cx_ = (xs >= corridor[0]) & (xs <= corridor[1])
+            cy_ = (ys >= corridor[2]) & (ys <= corridor[3])
+            h[np.ix_(cy_, cx_)] = np.minimum(h[np.ix_(cy_, cx_)], base)
+        foot.append((lo, hi, base, ht))
+    for k, (lo, hi, base, ht) in enumerate(foot):
+        t, z0, z1 = 0.3, base - 0.5, base + ht
+        dw, dh = 3.0, 3.5
+        # walls at y = lo/hi (running along x) and x = lo/hi (running along y); the
+        # first building gets doors facing each other on its x walls
+        cy = (lo[1] + hi[1]) / 2 if k == 0 else rng.uniform(lo[1] + 2, hi[1] - 2)
+        walls = [
+            (np.array([lo[0], lo[1], z0]), np.array([hi[0], lo[1] + t, z1]), 0, rng.uniform(lo[0] + 2, hi[0] - 2)),
+            (np.array([lo[0], hi[1] - t, z0]), np.array([hi[0], hi[1], z1]), 0, rng.uniform(lo[0] + 2, hi[0] - 2)),
+            (np.array([lo[0], lo[1], z0]), np.array([lo[0] + t, hi[1], z1]), 1, cy),
+            (np.array([hi[0] - t, lo[1], z0]), np.array([hi[0], hi[1], z1]), 1, cy),
+        ]
+        for wlo, whi, axis, dc in walls:
+            boxes.extend(_wall_boxes(wlo, whi, axis, dc, dw, dh, base))
+        boxes.append(np.array([lo[0], lo[1], z1 - t, hi[0], hi[1], z1]))
+    scene = OutdoorScene(hfield=h, hs=hs, origin=(0.0, 0.0), boxes=np.array(boxes), buildings=foot)
+
+    def inside_building(p, margin=0.6):
+        for lo, hi, base, ht in foot:
+            if lo[0] - margin < p[0] < hi[0] + margin and lo[1] - margin < p[1] < hi[1] + margin \
+                    and p[2] < base + ht + margin:
+                return True
+        return False
+
+    # path: cruise waypoints (2-5 m above ground, 1.5 m above roofs within 10 m)
+    # and a passage through building 0 from door to door along +x
+    lo0, hi0, base0, _ = foot[0]
+    cy0 = (lo0[1] + hi0[1]) / 2
+    zin = base0 + 1.75
+    passage = [np.array([x, cy0, zin]) for x in (lo0[0] - 20, lo0[0] - 8, lo0[0] - 1, (lo0[0] + hi0[0]) / 2,
+                                                  hi0[0] + 1, hi0[0] + 8, hi0[0] + 20)]
+
+    def cruise(p):
+        z = scene.height(p[0], p[1]) + rng.uniform(2.0, 5.0)
+        for lo, hi, base, ht in foot:
+            dx = max(lo[0] - p[0], 0.0, p[0] - hi[0])
+            dy = max(lo[1] - p[1], 0.0, p[1] - hi[1])
+            if math.hypot(dx, dy) < 10.0:
+                z = max(z, base + ht + 1.5)
+        return np.array([p[0], p[1], z])
+
+    for attempt in range(1000):
+        n_before = int(rng.integers(3, 7))
+        n_after = 10 - n_before
+        seq = []
+        cur = passage[0].copy()
+        for _ in range(n_before):
+            ang = rng.uniform(-math.pi, math.pi)
+            cur = cur + rng.uniform(25, 45) * np.array([math.cos(ang), math.sin(ang), 0.0])
+            cur[0] = min(max(cur[0], 8.0), X - 8.0)
+            cur[1] = min(max(cur[1], 8.0), Y - 8.0)
+            seq.append(cruise(cur))
+        pts = seq[::-1] + passage
+        cur = passage[-1].copy()
+        for _ in range(n_after):
+            ang = rng.uniform(-math.pi, math.pi)
+            cur = cur + rng.uniform(25, 45) * np.array([math.cos(ang), math.sin(ang), 0.0])
+            cur[0] = min(max(cur[0], 8.0), X - 8.0)
+            cur[1] = min(max(cur[1], 8.0), Y - 8.0)
+            pts.append(cruise(cur))
+        pts = np.array(pts)
+        curve = _catmull_rom(pts, samples_per_seg=400)
+        seg = np.linalg.norm(np.diff(curve, axis=0), axis=1)
+        if seg.sum() < path_length:
+            continue
+        ok = True
+        for q in curve[::20]:
+            if q[2] < scene.height(q[0], q[1]) + 1.0:
+                ok = False
+                break
+            in_corr = corridor[0] < q[0] < corridor[1] and abs(q[1] - cy0) < 1.4
+            if not in_corr and inside_building(q):
+                ok = False
+                break
+        if ok:
+            break
+    else:
+        raise RuntimeError("no collision-free path found")
+    pos, tan = _resample_arclength(curve, path_length / n_frames, n_frames)
+    poses = []
+    for k in range(n_frames):
+        yaw = math.atan2(tan[k, 1], tan[k, 0])
+        inside = lo0[0] - 2 < pos[k, 0] < hi0[0] + 2 and abs(pos[k, 1] - cy0) < 2
+        pitch = 0.0 if inside else math.radians(-30.0)
+        fwd = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
+        poses.append(pose_from_forward(pos[k], fwd))
+    cam = Camera(H=480, W=640, fx=380.0, fy=380.0, cx=319.5, cy=239.5, max_range=10.0,
+                 noise_model=2 if noise else 0, noise_a=0.002)
+    return Workload("mav", scene, cam, np.array(poses), seed, voxel_size=0.10, d_max=3.0, submap_every=100)
+
+
+def gravity_aligned(T: np.ndarray) -> np.ndarray:
+    """Pose with the same position and yaw as T and no roll or pitch (the
+    camera's forward axis projected on the ground plane)."""
+    f = T[:3, 2]
+    yaw = math.atan2(f[1], f[0])
+    G = np.eye(4)
+    G[:3, :3] = rot_z(yaw)
+    G[:3, 3] = T[:3, 3]
+    return G

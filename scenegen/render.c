@@ -270,3 +270,142 @@ double sg_hfield_eval(const double *hf, int nx, int ny, double x0, double y0, do
     hfield_t f = {hf, nx, ny, x0, y0, step, 0.0};
     return hf_eval(&f, x, y);
 }
+
+/* ------------------------------------------------------------ outdoor scene
+ *
+ * Ground: bilinear heightfield on a regular grid (spacing hs, origin x0, y0,
+ * nx * ny samples); a ray is walked cell by cell (2-D DDA) and intersected
+ * exactly with each cell's bilinear patch (a quadratic in the ray
+ * parameter).  Buildings: solid axis-aligned boxes listed in a coarse 2-D
+ * grid (cell gs) that the ray also walks.  Everything in binary64.
+ */
+
+typedef struct {
+    const double *h;
+    int nx, ny;
+    double x0, y0, hs;
+} hgrid_t;
+
+/* smallest root of a + b t + c t^2 = 0 in [t0, t1], or INFINITY */
+static double quad_first_root(double a, double b, double c, double t0, double t1)
+{
+    double r[2];
+    int n = 0;
+    if (fabs(c) < 1e-14) {
+        if (fabs(b) > 1e-300) r[n++] = -a / b;
+    } else {
+        double disc = b * b - 4 * a * c;
+        if (disc >= 0) {
+            double sq = sqrt(disc);
+            double q = -0.5 * (b + (b >= 0 ? sq : -sq));
+            double x1 = q / c;
+            double x2 = q != 0 ? a / q : x1;
+            r[n++] = x1 < x2 ? x1 : x2;
+            r[n++] = x1 < x2 ? x2 : x1;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        if (r[i] >= t0 && r[i] <= t1) return r[i];
+    return INFINITY;
+}
+
+static double hit_hgrid(const hgrid_t *g, const double o[3], const double d[3], double tmax)
+{
+    /* grid coordinates of the ray */
+    double gx = (o[0] - g->x0) / g->hs, gy = (o[1] - g->y0) / g->hs;
+    double dx = d[0] / g->hs, dy = d[1] / g->hs;
+    int ix = (int)floor(gx), iy = (int)floor(gy);
+    int sx = dx > 0 ? 1 : -1, sy = dy > 0 ? 1 : -1;
+    double tdx = dx != 0 ? fabs(1.0 / dx) : INFINITY, tdy = dy != 0 ? fabs(1.0 / dy) : INFINITY;
+    double tnx = dx != 0 ? ((dx > 0 ? (ix + 1 - gx) : (gx - ix)) * tdx) : INFINITY;
+    double tny = dy != 0 ? ((dy > 0 ? (iy + 1 - gy) : (gy - iy)) * tdy) : INFINITY;
+    double t0 = 0.0;
+    while (t0 <= tmax) {
+        double t1 = tnx < tny ? tnx : tny;
+        if (t1 > tmax) t1 = tmax;
+        if (ix >= 0 && iy >= 0 && ix < g->nx - 1 && iy < g->ny - 1) {
+            const double *r0 = g->h + (size_t)iy * g->nx + ix;
+            const double *r1 = r0 + g->nx;
+            double A = r0[0], B = r0[1] - r0[0], C = r1[0] - r0[0], E = r0[0] - r0[1] - r1[0] + r1[1];
+            double u0 = gx - ix, v0 = gy - iy;
+            double a0 = o[2] - A - B * u0 - C * v0 - E * u0 * v0;
+            double a1 = d[2] - B * dx - C * dy - E * (u0 * dy + v0 * dx);
+            double a2 = -E * dx * dy;
+            double t = quad_first_root(a0, a1, a2, t0, t1);
+            if (t < INFINITY) return t;
+        }
+        if (t1 >= tmax) break;
+        t0 = t1;
+        if (tnx < tny) { ix += sx; tnx += tdx; } else { iy += sy; tny += tdy; }
+    }
+    return INFINITY;
+}
+
+typedef struct {
+    const double *box;      /* 6 per box */
+    const int32_t *start;   /* cell -> first entry in items (ncx * ncy + 1) */
+    const int32_t *items;   /* box indices */
+    int ncx, ncy;
+    double x0, y0, gs;
+} bgrid_t;
+
+static double hit_bgrid(const bgrid_t *g, const double o[3], const double d[3], double tmax)
+{
+    double gx = (o[0] - g->x0) / g->gs, gy = (o[1] - g->y0) / g->gs;
+    double dx = d[0] / g->gs, dy = d[1] / g->gs;
+    int ix = (int)floor(gx), iy = (int)floor(gy);
+    int sx = dx > 0 ? 1 : -1, sy = dy > 0 ? 1 : -1;
+    double tdx = dx != 0 ? fabs(1.0 / dx) : INFINITY, tdy = dy != 0 ? fabs(1.0 / dy) : INFINITY;
+    double tnx = dx != 0 ? ((dx > 0 ? (ix + 1 - gx) : (gx - ix)) * tdx) : INFINITY;
+    double tny = dy != 0 ? ((dy > 0 ? (iy + 1 - gy) : (gy - iy)) * tdy) : INFINITY;
+    double best = INFINITY, t0 = 0.0;
+    while (t0 <= tmax && t0 < best) {
+        double t1 = tnx < tny ? tnx : tny;
+        if (ix >= 0 && iy >= 0 && ix < g->ncx && iy < g->ncy) {
+            int c = iy * g->ncx + ix;
+            for (int k = g->start[c]; k < g->start[c + 1]; ++k) {
+                double t = hit_box_solid(o, d, g->box + 6 * g->items[k], g->box + 6 * g->items[k] + 3);
+                if (t < best) best = t;
+            }
+        }
+        if (t1 > tmax) break;
+        t0 = t1;
+        if (tnx < tny) { ix += sx; tnx += tdx; } else { iy += sy; tny += tdy; }
+    }
+    return best;
+}
+
+void sg_render_outdoor(const double *hf, int hnx, int hny, double hx0, double hy0, double hs, const double *box,
+                       const int32_t *bstart, const int32_t *bitems, int ncx, int ncy, double bx0, double by0,
+                       double bgs, int H, int W, double fx, double fy, double cx, double cy, const double *T,
+                       double max_range, int noise_model, double noise_a, double invalid_frac, uint32_t seed,
+                       uint32_t frame, float *out)
+{
+    hgrid_t hg = {hf, hnx, hny, hx0, hy0, hs};
+    bgrid_t bg = {box, bstart, bitems, ncx, ncy, bx0, by0, bgs};
+    const double o[3] = {T[3], T[7], T[11]};
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int r = 0; r < H; ++r) {
+        for (int c = 0; c < W; ++c) {
+            double dc[3] = {((double)c - cx) / fx, ((double)r - cy) / fy, 1.0};
+            double d[3];
+            for (int k = 0; k < 3; ++k)
+                d[k] = T[4 * k + 0] * dc[0] + T[4 * k + 1] * dc[1] + T[4 * k + 2] * dc[2];
+            double s = hit_hgrid(&hg, o, d, max_range);
+            double lim = s < max_range ? s : max_range;
+            double tb = hit_bgrid(&bg, o, d, lim);
+            if (tb < s) s = tb;
+            double z = (s <= max_range) ? s : 0.0;
+            uint32_t pix = (uint32_t)(r * W + c);
+            if (z > 0.0 && (noise_model != 0 || invalid_frac > 0.0)) {
+                double gn, u;
+                pixel_draws(seed, frame, pix, &gn, &u);
+                double sigma = noise_model == 1 ? noise_a : noise_model == 2 ? noise_a * z * z : 0.0;
+                z += sigma * gn;
+                if (z <= 0.0) z = 0.0;
+                if (u < invalid_frac) z = 0.0;
+            }
+            out[(size_t)r * W + c] = (float)z;
+        }
+    }
+}

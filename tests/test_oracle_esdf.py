@@ -36,7 +36,7 @@ def _grid_submap(params, shape_blocks, D, W, origin_block=(0, 0, 0), drop=()):
 def _expected_from_definition(exp, params):
     """phi and k straight from the definition, brute force over all sites."""
     vs_f = np.float32(params.vs)
-    tau_f = np.float32(params.trunc_vox * params.vs)
+    tau_f = np.float32(params.trunc_vox * params.vs * (1.0 - 1.0 / 1024.0))
     dmax_f = np.float32(params.d_max)
     R = int(round(params.d_max / params.vs))
     coords = orc.voxel_coords(exp["keys"]).reshape(-1, 3)
@@ -123,6 +123,23 @@ def test_plane_of_sites_closed_form():
     assert np.array_equal(k[m], (coords[m, 2] - 11) ** 2)
 
 
+def test_band_membership_does_not_depend_on_precision():
+    """Voxels clamped to tau in every observation are outside the band in the
+    binary32, binary64 and binary16 modes alike, although their stored D
+    rounds differently (binary16 0.2 is below 0.2)."""
+    K = np.array([11.0, 12.5, 7.37, 5.61], np.float32)
+    outs = []
+    for kw in (dict(), dict(fp64=True), dict(fp16=True)):
+        s = orc.Submap(orc.Params(**kw))
+        for z in (1.1, 1.13, 1.08):
+            s.integrate(np.full((12, 16), z, np.float32), K, np.eye(4))
+        s.update_esdf()
+        outs.append(s.export())
+    k = [o["ksq"] for o in outs]
+    assert np.array_equal(k[0], k[1]) and np.array_equal(k[0], k[2])
+    assert np.count_nonzero(k[0] > 0) > 500
+
+
 def test_no_sites_gives_dmax_and_unobserved_is_nan():
     shape = (2, 2, 2)
     n = 8 * np.array(shape)
@@ -148,8 +165,11 @@ def test_lipschitz_and_band_copy_on_tiny_workload():
     D = exp["D"].reshape(-1)
     W = exp["W"].reshape(-1)
     phi = exp["phi"].reshape(-1)
-    band = (W > 0) & (np.abs(D) < np.float32(0.2))
+    band = (W > 0) & (np.abs(D) < np.float32(0.2 * (1.0 - 1.0 / 1024.0)))
     assert np.array_equal(phi[band], D[band])
+    # voxels at the truncation limit are outside the band
+    clamped = (W > 0) & (D == np.float32(0.2))
+    assert clamped.sum() > 1000 and np.all(k[clamped] >= 0)
     # 1-Lipschitz between axis neighbours that both carry an exact k
     lut = {tuple(c): kk for c, kk in zip(coords, k) if 0 <= kk <= 1600}
     checked = 0
@@ -182,7 +202,7 @@ def test_esdf_against_analytic_sdf_noise_free():
     D = exp["D"].reshape(-1)
     W = exp["W"].reshape(-1)
     phi = exp["phi"].reshape(-1)
-    m = (W > 0) & (np.abs(D) >= np.float32(0.2)) & (phi > 0) & (phi < 1.9)
+    m = (W > 0) & (np.abs(D) >= np.float32(0.2 * (1.0 - 1.0 / 1024.0))) & (phi > 0) & (phi < 1.9)
     c = (coords[m] + 0.5) * 0.05
     sdf = w.scene.sdf(c)
     assert np.all(phi[m] >= sdf - 1.5 * 0.05)
