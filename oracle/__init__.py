@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "covox_oracle.c")
+_SRC_NET = os.path.join(_HERE, "covox_net.c")
 _LIB = os.path.join(_HERE, "_covox_oracle.so")
 _lib = None
 
@@ -28,10 +29,11 @@ OK, EINVAL, EDEGENERATE, NOT_CONVERGED = 0, -1, -5, 1
 
 
 def build(force: bool = False) -> str:
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in (_SRC, _SRC_NET))
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, _SRC, _SRC_NET, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -40,6 +42,11 @@ class _Params(ctypes.Structure):
     _fields_ = [("vs", ctypes.c_double), ("trunc_vox", ctypes.c_int), ("max_range", ctypes.c_double),
                 ("d_max", ctypes.c_double), ("w_reg", ctypes.c_double), ("fp64", ctypes.c_int),
                 ("fp16", ctypes.c_int), ("max_iter", ctypes.c_int), ("n_min", ctypes.c_int)]
+
+
+class _Conv(ctypes.Structure):
+    _fields_ = [("cin", ctypes.c_int), ("cout", ctypes.c_int), ("din", ctypes.c_int), ("dout", ctypes.c_int),
+                ("stride", ctypes.c_int)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -88,6 +95,18 @@ def _load():
         L.orc_f2h.argtypes = [ctypes.c_float]
         L.orc_h2f.restype = ctypes.c_float
         L.orc_h2f.argtypes = [ctypes.c_uint16]
+        L.orc_net_num_params.restype = ctypes.c_int64
+        L.orc_net_num_params.argtypes = [ctypes.POINTER(_Conv), ctypes.c_int, ctypes.c_int]
+        L.orc_net_forward.restype = ctypes.c_int
+        L.orc_net_forward.argtypes = [ctypes.POINTER(_Conv), ctypes.c_int, ctypes.c_int, _fp, _fp, ctypes.c_int,
+                                      ctypes.c_int, _dp]
+        L.orc_net_loss_grad.restype = ctypes.c_int
+        L.orc_net_loss_grad.argtypes = [ctypes.POINTER(_Conv), ctypes.c_int, ctypes.c_int, _fp, _fp, _fp, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_double, _dp, _dp]
+        L.orc_summary.restype = ctypes.c_int
+        L.orc_summary.argtypes = [_vp, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double, _dp]
+        L.orc_bf16_round.restype = ctypes.c_float
+        L.orc_bf16_round.argtypes = [ctypes.c_float]
         L.orc_pose_cam_sub.restype = None
         L.orc_pose_cam_sub.argtypes = [_dp, _dp, _dp]
         _lib = L
@@ -277,3 +296,55 @@ def voxel_coords(keys) -> np.ndarray:
 
 def home_bucket(keys, table_cap: int) -> np.ndarray:
     return np.array([mix64(int(k)) & (table_cap - 1) for k in np.asarray(keys, np.uint64)], np.int64)
+
+
+# ------------------------------------------------------------ learned proposal
+
+#: The proposal network's layers (cin, cout, din, dout, stride); 64 features.
+NET_LAYERS = [(4, 16, 32, 32, 1), (16, 32, 32, 16, 2), (32, 64, 16, 8, 2), (64, 64, 8, 4, 2)]
+NET_FEAT = 64
+
+
+def _conv_array(layers):
+    arr = (_Conv * len(layers))()
+    for i, (ci, co, di, do, st) in enumerate(layers):
+        arr[i] = _Conv(ci, co, di, do, st)
+    return arr
+
+
+def net_num_params(layers=NET_LAYERS, feat=NET_FEAT) -> int:
+    return int(_load().orc_net_num_params(_conv_array(layers), len(layers), feat))
+
+
+def net_forward(params, x, layers=NET_LAYERS, feat=NET_FEAT, bf16=True) -> np.ndarray:
+    """Outputs (n, 5) of the network for inputs x (n, D, D, D, cin) NDHWC."""
+    p = np.ascontiguousarray(params, np.float32)
+    xx = np.ascontiguousarray(x, np.float32)
+    n = xx.shape[0]
+    out = np.zeros((n, 5))
+    _load().orc_net_forward(_conv_array(layers), len(layers), feat, _p(p, _fp), _p(xx, _fp), n, int(bf16), _p(out, _dp))
+    return out
+
+
+def net_loss_grad(params, x, y, trans_scale, layers=NET_LAYERS, feat=NET_FEAT, bf16=True):
+    """(loss, gradient) of the proposal loss, by backpropagation."""
+    p = np.ascontiguousarray(params, np.float32)
+    xx = np.ascontiguousarray(x, np.float32)
+    yy = np.ascontiguousarray(y, np.float32)
+    n = xx.shape[0]
+    g = np.zeros(len(p))
+    loss = np.zeros(1)
+    _load().orc_net_loss_grad(_conv_array(layers), len(layers), feat, _p(p, _fp), _p(xx, _fp), _p(yy, _fp), n,
+                              int(bf16), float(trans_scale), _p(g, _dp), _p(loss, _dp))
+    return float(loss[0]), g
+
+
+def summary(s: Submap, T_submap_grid, cell) -> np.ndarray:
+    """(32^3, 2) coarse ESDF summary (clamped phi / d_max, mask), binary64."""
+    out = np.zeros((32768, 2))
+    _load().orc_summary(s._h, s.params.vs, s.params.d_max, _p(_mat(T_submap_grid), _dp), float(cell), _p(out, _dp))
+    return out
+
+
+def bf16_round(x: float) -> float:
+    return float(_load().orc_bf16_round(ctypes.c_float(x)))

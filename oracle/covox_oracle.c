@@ -709,6 +709,14 @@ static double phi_at(const orc_submap *A, const int64_t j[3])
     return A->p.fp64 ? A->phi64[o] : (double)A->phi[o];
 }
 
+/* phi of voxel (x, y, z) of submap s, NaN when unallocated (for the
+ * summary checker). */
+double orc_phi_at_voxel(const orc_submap *s, int64_t x, int64_t y, int64_t z)
+{
+    int64_t j[3] = {x, y, z};
+    return phi_at(s, j);
+}
+
 /*
  * Residual r = phi_A(T p) by trilinear interpolation, gradient g of the
  * interpolant, Jacobian J = [g ; q x g] for the left perturbation
