@@ -243,6 +243,63 @@ int64_t covox_export_points(covox_ctx *ctx, covox_submap *B, float *pts, int64_t
 int covox_normal_equations(covox_ctx *ctx, const covox_submap *A, covox_submap *B,
                            const double T_A_B[16], double out[29]);
 
+/* ------------------------------------------------------ learned proposal */
+/* Not part of the paper: a small 3-D CNN proposes the relative pose of a
+ * pair from coarse ESDF summaries; the ESDF alignment above refines it. */
+
+typedef struct covox_net covox_net;
+
+/* One coarse summary: the 32^3 grid of cells of edge `cell` (m) centred on
+ * the grid origin; T_submap_grid maps grid coordinates into the submap
+ * frame.  Writes, for every cell c (x fastest), out_dev[4 c + channel] =
+ * clamp(phi / d_max, -1, 1) and out_dev[4 c + channel + 1] = 1 where the
+ * trilinear ESDF is defined (all 8 corners observed), else 0 and 0.
+ * out_dev: device, 32^3 x 4 floats (NDHWC input block of the network);
+ * channel is 0 or 2.  Requires a current ESDF. */
+typedef struct {
+    const covox_submap *s;
+    double T_submap_grid[16];
+    double cell;
+    float *out_dev;
+    int32_t channel;
+    int32_t reserved;
+} covox_summary_req;
+
+int covox_summaries(covox_ctx *ctx, const covox_summary_req *reqs, int32_t n);
+
+/* Network: conv3d 4->16 (stride 1), 16->32, 32->64, 64->64 (stride 2), all
+ * 3x3x3 with zero padding and ReLU, global mean, fully connected 64 -> 5
+ * (tx, ty, tz, cos yaw, sin yaw).  bf16 weights and activations on the matrix
+ * cores with FP32 accumulation; FP32 master weights, FP32 backward, Adam.
+ * Weights are initialised from `seed` (He-uniform, SplitMix64). */
+int covox_net_create(covox_ctx *ctx, uint64_t seed, covox_net **out);
+void covox_net_destroy(covox_net *net);
+int64_t covox_net_num_params(const covox_net *net);
+int covox_net_get_params(covox_net *net, float *host, int64_t n);
+int covox_net_set_params(covox_net *net, const float *host, int64_t n);
+/* x_dev: device n x 32^3 x 4 floats; out_dev: device n x 5 floats. */
+int covox_net_forward(covox_net *net, const float *x_dev, int32_t n, float *out_dev);
+/* One Adam step (beta 0.9 / 0.999) on the loss mean over the batch of
+ * |t - t*|^2 / trans_scale^2 + |(c, s) - (c*, s*)|^2; y_dev: device n x 5.
+ * loss_host (nullable) receives the loss (synchronous when given). */
+int covox_net_train_step(covox_net *net, const float *x_dev, const float *y_dev, int32_t n, float lr,
+                         float trans_scale, float *loss_host);
+/* Gradient of that loss with respect to the FP32 parameters (host, n_params
+ * floats, same layout as covox_net_get_params) without an update. */
+int covox_net_gradients(covox_net *net, const float *x_dev, const float *y_dev, int32_t n, float trans_scale,
+                        float *grad_host, float *loss_host);
+
+/* Learned alignment of n pairs: A's grid is centred on the centroid c_A of
+ * A's registration points (T_A_grid = Trans(c_A)); B is summarised on the
+ * same grid through the prior T_init (T_B_grid = T_init^-1 T_A_grid).  The
+ * network's correction C = (t, Rz(yaw)) in grid coordinates gives the
+ * proposal T_A_grid C T_A_grid^-1 T_init, refined by single-start alignment;
+ * pairs whose refined cost exceeds cost_thr (or that are degenerate) fall
+ * back to n_starts-start alignment from T_init.  stats[i].best_start = -1
+ * when the refined proposal was kept.  Synchronous. */
+int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell,
+                        double cost_thr, int32_t n_starts, double *T_out, double *cost, covox_align_stats *stats);
+
 /* ---------------------------------------------------------------- timing */
 
 enum {
@@ -256,6 +313,8 @@ enum {
     COVOX_K_EDT_Z,         /* lower envelope along z + phi */
     COVOX_K_ISO,           /* registration points */
     COVOX_K_ALIGN,         /* Gauss-Newton (persistent) */
+    COVOX_K_SUMMARY,       /* coarse ESDF summaries */
+    COVOX_K_NET,           /* proposal network (forward or backward) */
     COVOX_K_COUNT
 };
 

@@ -23,7 +23,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, EPOOL_FULL, ETABLE_FULL, EHIP, EDEGENERATE, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1
 FP32, FP16 = 0, 1
-KERNELS = ["probe", "scan", "integrate", "esdf_page", "esdf_sites", "edt_x", "edt_y", "edt_z", "iso", "align"]
+KERNELS = ["probe", "scan", "integrate", "esdf_page", "esdf_sites", "edt_x", "edt_y", "edt_z", "iso", "align",
+           "summary", "net"]
 
 
 class CovoxError(RuntimeError):
@@ -55,7 +56,12 @@ class covox_submap_info(ctypes.Structure):
 
 
 class covox_timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 10), ("launches", ctypes.c_int64 * 10)]
+    _fields_ = [("ms", ctypes.c_double * 12), ("launches", ctypes.c_int64 * 12)]
+
+
+class covox_summary_req(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_void_p), ("T_submap_grid", ctypes.c_double * 16), ("cell", ctypes.c_double),
+                ("out_dev", ctypes.c_void_p), ("channel", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _vp, _dp, _fp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)
@@ -86,6 +92,18 @@ _sig = {
     "covox_export_blocks": (ctypes.c_int64, [_vp, _vp, _vp, _vp, _fp, _fp, _fp, ctypes.c_int64]),
     "covox_export_points": (ctypes.c_int64, [_vp, _vp, _fp, ctypes.c_int64]),
     "covox_normal_equations": (ctypes.c_int, [_vp, _vp, _vp, _dp, _dp]),
+    "covox_summaries": (ctypes.c_int, [_vp, ctypes.POINTER(covox_summary_req), ctypes.c_int32]),
+    "covox_net_create": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    "covox_net_destroy": (None, [_vp]),
+    "covox_net_num_params": (ctypes.c_int64, [_vp]),
+    "covox_net_get_params": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
+    "covox_net_set_params": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
+    "covox_net_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp]),
+    "covox_net_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, _fp]),
+    "covox_net_gradients": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, _fp, _fp]),
+    "covox_align_learned": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int32, _dp, _dp,
+                                           ctypes.POINTER(covox_align_stats)]),
     "covox_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "covox_timing_get": (ctypes.c_int, [_vp, ctypes.POINTER(covox_timing)]),
 }
@@ -261,6 +279,34 @@ class Context:
                     "normal_equations")
         return out
 
+    # -- learned proposal
+    def summaries(self, reqs):
+        """reqs: list of (submap, T_submap_grid, cell, out tensor (32^3 x 4 floats, device), channel)."""
+        arr = (covox_summary_req * max(len(reqs), 1))()
+        for i, (sm, T, cell, out, ch) in enumerate(reqs):
+            if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.numel() == 32768 * 4):
+                raise ValueError("summary output must be a contiguous float32 device tensor of 32^3 x 4")
+            arr[i].s = sm.handle
+            arr[i].T_submap_grid[:] = list(_mat(T))
+            arr[i].cell = cell
+            arr[i].out_dev = out.data_ptr()
+            arr[i].channel = ch
+        self._check(_lib.covox_summaries(self.handle, arr, len(reqs)), "summaries")
+
+    def align_learned(self, net: "Net", pairs, cell, cost_thr, n_starts=8):
+        n = len(pairs)
+        arr = (covox_pair * max(n, 1))()
+        for i, (A, B, T0) in enumerate(pairs):
+            arr[i].A = A.handle
+            arr[i].B = B.handle
+            arr[i].T_init_A_B[:] = list(_mat(T0))
+        T = np.zeros(16 * max(n, 1))
+        cost = np.zeros(max(n, 1))
+        st = (covox_align_stats * max(n, 1))()
+        self._check(_lib.covox_align_learned(self.handle, net.handle, arr, n, cell, cost_thr, n_starts, _p(T, _dp),
+                                             _p(cost, _dp), st), "align_learned")
+        return T.reshape(-1, 4, 4)[:n], cost[:n], [_stats(st[i]) for i in range(n)]
+
     # -- inspection
     def export_blocks(self, s: Submap) -> dict:
         n = self.submap_info(s)["n_blocks"]
@@ -298,3 +344,65 @@ class Context:
 def _stats(st: covox_align_stats) -> dict:
     return {"n_points": st.n_points, "n_used": st.n_used, "iterations": st.iterations, "status": st.status,
             "best_start": st.best_start}
+
+
+class Net:
+    """The pose-proposal network of a context (weights on the device)."""
+
+    def __init__(self, ctx: Context, seed: int = 1):
+        self.ctx = ctx
+        h = _vp()
+        ctx._check(_lib.covox_net_create(ctx.handle, seed, ctypes.byref(h)), "net_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.covox_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(_lib.covox_net_num_params(self.handle))
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.num_params, np.float32)
+        self.ctx._check(_lib.covox_net_get_params(self.handle, _p(out, _fp), len(out)), "net_get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        self.ctx._check(_lib.covox_net_set_params(self.handle, _p(p, _fp), len(p)), "net_set_params")
+
+    @staticmethod
+    def _x(x: torch.Tensor):
+        if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.dim() == 5 and x.shape[1:] == (32, 32, 32, 4)):
+            raise ValueError("network input must be a contiguous float32 device tensor (n, 32, 32, 32, 4)")
+        return ctypes.c_void_p(x.data_ptr())
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        out = torch.empty((x.shape[0], 5), dtype=torch.float32, device=x.device)
+        self.ctx._check(_lib.covox_net_forward(self.handle, self._x(x), x.shape[0], ctypes.c_void_p(out.data_ptr())),
+                        "net_forward")
+        return out
+
+    def train_step(self, x: torch.Tensor, y: torch.Tensor, lr: float, trans_scale: float = 3.0, want_loss=True):
+        loss = ctypes.c_float(0.0)
+        yy = y.contiguous()
+        self.ctx._check(_lib.covox_net_train_step(self.handle, self._x(x), ctypes.c_void_p(yy.data_ptr()), x.shape[0],
+                                                  lr, trans_scale, ctypes.byref(loss) if want_loss else None),
+                        "net_train_step")
+        return loss.value
+
+    def gradients(self, x: torch.Tensor, y: torch.Tensor, trans_scale: float = 3.0):
+        g = np.zeros(self.num_params, np.float32)
+        loss = ctypes.c_float(0.0)
+        yy = y.contiguous()
+        self.ctx._check(_lib.covox_net_gradients(self.handle, self._x(x), ctypes.c_void_p(yy.data_ptr()), x.shape[0],
+                                                 trans_scale, _p(g, _fp), ctypes.byref(loss)), "net_gradients")
+        return loss.value, g

@@ -170,6 +170,14 @@ bool rigid_pose(const double *T)
     return true;
 }
 
+void rigid_inverse_h(const double *T, double *O)
+{
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) O[4 * r + c] = T[4 * c + r];
+    for (int r = 0; r < 3; ++r) O[4 * r + 3] = -(O[4 * r] * T[3] + O[4 * r + 1] * T[7] + O[4 * r + 2] * T[11]);
+    O[12] = 0; O[13] = 0; O[14] = 0; O[15] = 1;
+}
+
 void mat_mul4(const double *A, const double *B, double *O)
 {
     double t[16];
@@ -304,7 +312,8 @@ void covox_destroy(covox_ctx *ctx)
     auto &subs = submaps_of(ctx);
     for (covox_submap *s : std::vector<covox_submap *>(subs)) covox_submap_destroy(s);
     for (void *ptr : {(void *)ctx->cand, (void *)ctx->t_key, (void *)ctx->t_idx, (void *)ctx->sites, (void *)ctx->g1,
-                      (void *)ctx->g2, (void *)ctx->cnt, (void *)ctx->psum, ctx->prob_dev, ctx->res_dev})
+                      (void *)ctx->g2, (void *)ctx->cnt, (void *)ctx->psum, ctx->prob_dev, ctx->res_dev, ctx->sum_dev,
+                      (void *)ctx->net_in, (void *)ctx->net_out})
         if (ptr) (void)hipFree(ptr);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (auto &u : ctx->ev_used) {
@@ -606,6 +615,179 @@ int64_t covox_export_points(covox_ctx *ctx, covox_submap *B, float *pts, int64_t
         (rc = hip_check(ctx, hipMemcpy(pts, B->pts, sizeof(float) * 3 * n, hipMemcpyDeviceToHost), "points copy")))
         return rc;
     return B->n_pts;
+}
+
+int covox_summaries(covox_ctx *ctx, const covox_summary_req *reqs, int32_t n)
+{
+    if (!ctx || (!reqs && n > 0) || n < 0) return fail(ctx, COVOX_EINVAL, "summaries: bad argument");
+    std::vector<SummaryReq> rq(n);
+    for (int32_t i = 0; i < n; ++i) {
+        const covox_summary_req &r = reqs[i];
+        if (!r.s || !r.out_dev || (r.channel != 0 && r.channel != 2) || !(r.cell > 0) || !rigid_pose(r.T_submap_grid))
+            return fail(ctx, COVOX_EINVAL, "summaries: bad request");
+        if (r.s->esdf_version != r.s->version)
+            return fail(ctx, COVOX_EINVAL, "summaries: the ESDF of a submap is out of date");
+        rq[i].phi = r.s->phi;
+        rq[i].page = r.s->page;
+        rq[i].meta = r.s->meta;
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 4; ++c) rq[i].T[4 * a + c] = (float)r.T_submap_grid[4 * a + c];
+        rq[i].cell = (float)r.cell;
+        rq[i].chan = r.channel;
+        rq[i].out = r.out_dev;
+    }
+    int rc = run_summaries(ctx, rq.data(), n);
+    if (rc) return rc;
+    return hip_check(ctx, hipStreamSynchronize(ctx->stream), "summaries sync");
+}
+
+int covox_net_create(covox_ctx *ctx, uint64_t seed, covox_net **out)
+{
+    if (!ctx || !out) return fail(ctx, COVOX_EINVAL, "net_create: null argument");
+    return net_create(ctx, seed, out);
+}
+
+void covox_net_destroy(covox_net *net) { net_destroy(net); }
+
+int64_t covox_net_num_params(const covox_net *net) { return net ? net_num_params(net) : COVOX_EINVAL; }
+
+int covox_net_get_params(covox_net *net, float *host, int64_t n)
+{
+    if (!net || !host) return COVOX_EINVAL;
+    return net_get_params(net, host, n);
+}
+
+int covox_net_set_params(covox_net *net, const float *host, int64_t n)
+{
+    if (!net || !host) return COVOX_EINVAL;
+    return net_set_params(net, host, n);
+}
+
+int covox_net_forward(covox_net *net, const float *x_dev, int32_t n, float *out_dev)
+{
+    if (!net || !x_dev || !out_dev || n <= 0) return COVOX_EINVAL;
+    return net_forward_api(net, x_dev, n, out_dev);
+}
+
+int covox_net_train_step(covox_net *net, const float *x_dev, const float *y_dev, int32_t n, float lr, float trans_scale,
+                         float *loss_host)
+{
+    if (!net || !x_dev || !y_dev || n <= 0 || !(trans_scale > 0)) return COVOX_EINVAL;
+    return net_train_step(net, x_dev, y_dev, n, lr, trans_scale, loss_host);
+}
+
+int covox_net_gradients(covox_net *net, const float *x_dev, const float *y_dev, int32_t n, float trans_scale,
+                        float *grad_host, float *loss_host)
+{
+    if (!net || !x_dev || !y_dev || !grad_host || n <= 0 || !(trans_scale > 0)) return COVOX_EINVAL;
+    return net_grads(net, x_dev, y_dev, n, trans_scale, grad_host, loss_host);
+}
+
+int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell,
+                        double cost_thr, int32_t n_starts, double *T_out, double *cost, covox_align_stats *stats)
+{
+    if (!ctx || !net || (!pairs && n > 0) || n < 0 || !(cell > 0) || n_starts < 1 || !T_out || !cost)
+        return fail(ctx, COVOX_EINVAL, "align_learned: bad argument");
+    int rc;
+    for (int i = 0; i < n; ++i) {
+        const covox_pair &pr = pairs[i];
+        if (!rigid_pose(pr.T_init_A_B)) return fail(ctx, COVOX_EINVAL, "align_learned: T_init is not rigid");
+        if ((rc = prepare_pair(ctx, pr.A, pr.B))) return rc;
+        if (pr.B->esdf_version != pr.B->version)
+            return fail(ctx, COVOX_EINVAL, "align_learned: the ESDF of B is out of date");
+        if ((rc = extract_points(ctx, const_cast<covox_submap *>(pr.A)))) return rc;
+    }
+    const int chunk = 256;
+    std::vector<AlignResult> res(n);
+    std::vector<float> outs((size_t)chunk * 5);
+    for (int i0 = 0; i0 < n; i0 += chunk) {
+        const int m = std::min(chunk, n - i0);
+        if ((rc = ensure_buffer(ctx, (void **)&ctx->net_in, &ctx->net_in_cap, (int64_t)m * 32768 * 4, sizeof(float),
+                                "net input")))
+            return rc;
+        if ((rc = ensure_buffer(ctx, (void **)&ctx->net_out, &ctx->net_out_cap, (int64_t)m * 5, sizeof(float),
+                                "net output")))
+            return rc;
+        std::vector<SummaryReq> rq(2 * m);
+        std::vector<double> grid((size_t)16 * m);
+        for (int k = 0; k < m; ++k) {
+            const covox_pair &pr = pairs[i0 + k];
+            double *G = &grid[16 * k];  // T_A_grid = Trans(c_A)
+            const double Gv[16] = {1, 0, 0, pr.A->pbar[0], 0, 1, 0, pr.A->pbar[1], 0, 0, 1, pr.A->pbar[2], 0, 0, 0, 1};
+            memcpy(G, Gv, sizeof(Gv));
+            double inv[16], TB[16];
+            rigid_inverse_h(pr.T_init_A_B, inv);
+            mat_mul4(inv, G, TB);
+            const double *Ts[2] = {G, TB};
+            const covox_submap *ss[2] = {pr.A, pr.B};
+            for (int side = 0; side < 2; ++side) {
+                SummaryReq &r = rq[2 * k + side];
+                r.phi = ss[side]->phi;
+                r.page = ss[side]->page;
+                r.meta = ss[side]->meta;
+                for (int a = 0; a < 3; ++a)
+                    for (int c = 0; c < 4; ++c) r.T[4 * a + c] = (float)Ts[side][4 * a + c];
+                r.cell = (float)cell;
+                r.chan = 2 * side;
+                r.out = ctx->net_in + (int64_t)k * 32768 * 4;
+            }
+        }
+        if ((rc = run_summaries(ctx, rq.data(), 2 * m))) return rc;
+        if ((rc = net_forward_api(net, ctx->net_in, m, ctx->net_out))) return rc;
+        if ((rc = hip_check(ctx, hipMemcpyAsync(outs.data(), ctx->net_out, sizeof(float) * 5 * m, hipMemcpyDeviceToHost,
+                                                ctx->stream), "net output copy")))
+            return rc;
+        if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "net sync"))) return rc;
+        std::vector<AlignProblem> prs(m);
+        for (int k = 0; k < m; ++k) {
+            const covox_pair &pr = pairs[i0 + k];
+            const float *o = &outs[5 * k];
+            const double yaw = atan2((double)o[4], (double)o[3]);
+            const double C[16] = {cos(yaw), -sin(yaw), 0, o[0], sin(yaw), cos(yaw), 0, o[1], 0, 0, 1, o[2], 0, 0, 0, 1};
+            const double *G = &grid[16 * k];
+            double Gi[16], A1[16], A2[16], Tp[16];
+            rigid_inverse_h(G, Gi);
+            mat_mul4(G, C, A1);
+            mat_mul4(A1, Gi, A2);
+            mat_mul4(A2, pr.T_init_A_B, Tp);
+            Tp[12] = 0; Tp[13] = 0; Tp[14] = 0; Tp[15] = 1;
+            prs[k] = make_problem(ctx, pr.A, pr.B, Tp, ctx->p.max_iter);
+        }
+        if ((rc = run_alignment(ctx, prs.data(), m, res.data() + i0))) return rc;
+    }
+    // fallback to multi-start from the prior
+    std::vector<int> fb;
+    for (int i = 0; i < n; ++i)
+        if (res[i].status == COVOX_EDEGENERATE || !(res[i].cost <= cost_thr)) fb.push_back(i);
+    std::vector<int> best(n, -1);
+    if (!fb.empty()) {
+        std::vector<AlignProblem> prs((size_t)fb.size() * n_starts);
+        for (size_t j = 0; j < fb.size(); ++j) {
+            const covox_pair &pr = pairs[fb[j]];
+            for (int k = 0; k < n_starts; ++k) {
+                double S[16];
+                if (n_starts == 1) memcpy(S, pr.T_init_A_B, sizeof(S));
+                else start_pose(pr.T_init_A_B, pr.B->pbar, k, n_starts, S);
+                prs[j * n_starts + k] = make_problem(ctx, pr.A, pr.B, S, ctx->p.max_iter);
+            }
+        }
+        std::vector<AlignResult> r2(prs.size());
+        if ((rc = run_alignment(ctx, prs.data(), (int)prs.size(), r2.data()))) return rc;
+        for (size_t j = 0; j < fb.size(); ++j) {
+            const AlignResult *r = &r2[j * n_starts];
+            const int b = n_starts == 1 ? 0 : select_start(r, n_starts);
+            if (b >= 0) {
+                res[fb[j]] = r[b];
+                best[fb[j]] = b;
+            }
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        memcpy(T_out + 16 * i, res[i].T, sizeof(double) * 16);
+        cost[i] = res[i].cost;
+        fill_stats(stats ? stats + i : nullptr, pairs[i].B, res[i], best[i]);
+    }
+    return COVOX_OK;
 }
 
 int covox_timing_enable(covox_ctx *ctx, int32_t mask)

@@ -166,6 +166,12 @@ struct covox_ctx {
     int64_t prob_cap = 0;
     void *res_dev = nullptr;
     int64_t res_cap = 0;
+    void *sum_dev = nullptr;     // summary requests
+    int64_t sum_cap = 0;
+    float *net_in = nullptr;     // learned alignment: summaries and network outputs
+    int64_t net_in_cap = 0;
+    float *net_out = nullptr;
+    int64_t net_out_cap = 0;
     // pinned host staging for small copies
     void *host_pin = nullptr;
     size_t host_pin_cap = 0;
@@ -247,5 +253,30 @@ struct AlignResult {
 };
 
 int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult *res);
+
+// Coarse ESDF summary request (k_align.hip): 32^3 cells of edge `cell`
+// centred on the grid origin, grid frame -> submap frame by T.
+struct SummaryReq {
+    const float *phi;
+    const int32_t *page;
+    const SubmapMeta *meta;
+    float T[12];
+    float cell;
+    int32_t chan;
+    float *out;  // 32^3 x 4 floats (NDHWC)
+};
+int run_summaries(covox_ctx *ctx, const SummaryReq *reqs, int n);
+
+// k_net.hip
+int net_create(covox_ctx *ctx, uint64_t seed, covox_net **out);
+void net_destroy(covox_net *net);
+int64_t net_num_params(const covox_net *net);
+int net_get_params(covox_net *net, float *host, int64_t n);
+int net_set_params(covox_net *net, const float *host, int64_t n);
+int net_forward_api(covox_net *net, const float *x_dev, int n, float *out_dev);
+int net_train_step(covox_net *net, const float *x_dev, const float *y_dev, int n, float lr, float trans_scale,
+                   float *loss_host);
+int net_grads(covox_net *net, const float *x_dev, const float *y_dev, int n, float trans_scale, float *grad_host,
+              float *loss_host);
 
 }  // namespace covox

@@ -436,6 +436,65 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__r
     }
 }
 
+// ---------------------------------------------------------------- summaries
+
+// ESDF value at q by trilinear interpolation of the 8 cell corners (the
+// residual's operation order); false when a corner is unobserved.
+__device__ __forceinline__ bool phi_trilinear(const float q[3], float vs, const float *phi, const int32_t *page,
+                                              const DomArgs &d, float &r)
+{
+    float f[3];
+    int j0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float g = (q[a] / vs) - 0.5f;
+        if (!(fabsf(g) < 1.0e8f)) return false;
+        const float fl = floorf(g);
+        j0[a] = (int)fl;
+        f[a] = g - fl;
+    }
+    float c[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        c[k] = phi_at(phi, page, d, j0[0] + (k & 1), j0[1] + ((k >> 1) & 1), j0[2] + ((k >> 2) & 1));
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (isnan(c[k])) return false;
+    const float wx0 = 1.0f - f[0], wx1 = f[0], wy0 = 1.0f - f[1], wy1 = f[1], wz0 = 1.0f - f[2], wz1 = f[2];
+    const float c00 = c[0] * wx0 + c[1] * wx1, c10 = c[2] * wx0 + c[3] * wx1;
+    const float c01 = c[4] * wx0 + c[5] * wx1, c11 = c[6] * wx0 + c[7] * wx1;
+    const float c0 = c00 * wy0 + c10 * wy1, c1 = c01 * wy0 + c11 * wy1;
+    r = c0 * wz0 + c1 * wz1;
+    return true;
+}
+
+// One lane per cell of a 32^3 grid: cell centre ((i + 0.5) - 16) * cell in the
+// grid frame, mapped to the submap by T (binary32, row-major 3x4); writes
+// (clamp(phi / d_max, -1, 1), 1) or (0, 0) to channels chan, chan + 1 of a
+// 4-channel NDHWC block.
+__global__ __launch_bounds__(256) void k_summary(const SummaryReq *__restrict__ reqs, int n, float vs, float dmax)
+{
+    const int64_t total = (int64_t)n * 32768;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const SummaryReq &R = reqs[i >> 15];
+        const int c = (int)(i & 32767);
+        const int cx = c & 31, cy = (c >> 5) & 31, cz = c >> 10;
+        const float g[3] = {(((float)cx + 0.5f) - 16.0f) * R.cell, (((float)cy + 0.5f) - 16.0f) * R.cell,
+                            (((float)cz + 0.5f) - 16.0f) * R.cell};
+        float q[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) q[a] = ((R.T[4 * a] * g[0] + R.T[4 * a + 1] * g[1]) + R.T[4 * a + 2] * g[2]) + R.T[4 * a + 3];
+        const DomArgs d = dom_of(R.meta);
+        float r, val = 0.0f, msk = 0.0f;
+        if (phi_trilinear(q, vs, R.phi, R.page, d, r)) {
+            val = fminf(1.0f, fmaxf(-1.0f, r / dmax));
+            msk = 1.0f;
+        }
+        R.out[4 * c + R.chan] = val;
+        R.out[4 * c + R.chan + 1] = msk;
+    }
+}
+
 unsigned grid_waves(int64_t waves)
 {
     const int64_t g = (waves + 3) / 4;
@@ -496,6 +555,25 @@ int extract_points(covox_ctx *ctx, covox_submap *B)
     for (int a = 0; a < 3; ++a) B->pbar[a] = m.pbar[a];
     B->pts_version = B->version;
     return COVOX_OK;
+}
+
+int run_summaries(covox_ctx *ctx, const SummaryReq *reqs, int n)
+{
+    if (n <= 0) return COVOX_OK;
+    int rc;
+    const size_t bytes = sizeof(SummaryReq) * n;
+    if ((rc = ensure_buffer(ctx, &ctx->sum_dev, &ctx->sum_cap, (int64_t)bytes, 1, "summary requests"))) return rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(ctx->sum_dev, reqs, bytes, hipMemcpyHostToDevice, ctx->stream),
+                        "summary upload")))
+        return rc;
+    {
+        TimedLaunch tl(ctx, COVOX_K_SUMMARY);
+        const int64_t total = (int64_t)n * 32768;
+        hipLaunchKernelGGL(k_summary, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20)), dim3(256), 0,
+                           ctx->stream, (const SummaryReq *)ctx->sum_dev, n, (float)ctx->p.voxel_size,
+                           (float)ctx->p.d_max);
+    }
+    return hip_check(ctx, hipGetLastError(), "summary launch");
 }
 
 int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult *res)

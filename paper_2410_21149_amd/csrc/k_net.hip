@@ -1,0 +1,570 @@
+// Learned pose proposal for submap alignment: a small 3-D convolutional
+// network on coarse ESDF summaries, trained and run with hand-written
+// kernels.  (Not part of the paper; it proposes the initial pose that the
+// correspondence-free ESDF alignment of Sec. III-F then refines.)
+//
+// Network (input 32^3 x 4 channels, NDHWC):
+//   conv 3x3x3, 4 -> 16, stride 1 (32^3), ReLU
+//   conv 3x3x3, 16 -> 32, stride 2 (16^3), ReLU
+//   conv 3x3x3, 32 -> 64, stride 2 (8^3), ReLU
+//   conv 3x3x3, 64 -> 64, stride 2 (4^3), ReLU
+//   global mean -> fully connected 64 -> 5 (tx, ty, tz, cos yaw, sin yaw)
+// Convolutions (zero padding 1) run as implicit GEMMs on the bf16 matrix
+// cores (v_mfma_f32_16x16x16_bf16): bf16 activations and weights, FP32
+// accumulation, bias and ReLU in FP32, outputs rounded to bf16 (nearest
+// even).  FP32 master weights; the backward pass and Adam run in FP32.
+#include "covox_impl.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+namespace covox {
+
+namespace {
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+// binary32 -> bfloat16, round to nearest even (NaN kept quiet).
+__host__ __device__ inline uint16_t f2bf(float f)
+{
+    uint32_t x;
+    memcpy(&x, &f, 4);
+    if ((x & 0x7F800000u) == 0x7F800000u && (x & 0x7FFFFFu)) return (uint16_t)((x >> 16) | 0x40);
+    const uint32_t lsb = (x >> 16) & 1u;
+    x += 0x7FFFu + lsb;
+    return (uint16_t)(x >> 16);
+}
+
+__host__ __device__ inline float bf2f(uint16_t h)
+{
+    const uint32_t x = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &x, 4);
+    return f;
+}
+
+struct ConvShape {
+    int cin, cout, din, dout, stride;
+    int K() const { return 27 * cin; }
+};
+
+constexpr int kLayers = 4;
+constexpr ConvShape kShapes[kLayers] = {{4, 16, 32, 32, 1}, {16, 32, 32, 16, 2}, {32, 64, 16, 8, 2}, {64, 64, 8, 4, 2}};
+constexpr int kOut = 5;
+constexpr int kFeat = 64;
+
+// ------------------------------------------------------------ forward
+
+__global__ void k_to_bf16(const float *__restrict__ x, uint16_t *__restrict__ y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = f2bf(x[i]);
+}
+
+// One wave computes a 16 (positions) x 16 (output channels) tile; a
+// workgroup holds COUT / 16 waves over the same 16 positions.  MFMA operand
+// layout (16x16x16 bf16): lane l supplies A[m = l % 16][k = 4 (l / 16) + i]
+// and B[k = 4 (l / 16) + i][n = l % 16], i = 0..3, and receives
+// D[m = 4 (l / 16) + i][n = l % 16].
+template <int CIN, int COUT, int DIN, int DOUT, int STRIDE>
+__global__ __launch_bounds__(64 * (COUT / 16)) void k_conv_fwd(const uint16_t *__restrict__ x,
+                                                               const uint16_t *__restrict__ w,
+                                                               const float *__restrict__ bias,
+                                                               uint16_t *__restrict__ y, int64_t n_pos)
+{
+    constexpr int K = 27 * CIN;
+    constexpr int KC = (K + 15) / 16;  // K chunks
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int co = wid * 16 + (lane & 15);  // this lane's B column / D column
+    const int kq = 4 * (lane >> 4);          // first of this lane's 4 k in a chunk
+    for (int64_t tile = blockIdx.x; tile * 16 < n_pos; tile += gridDim.x) {
+        // A row of this lane: output position tile * 16 + lane % 16
+        const int64_t p = tile * 16 + (lane & 15);
+        const bool pin = p < n_pos;
+        const int64_t pp = pin ? p : 0;
+        const int ox = (int)(pp % DOUT), oy = (int)((pp / DOUT) % DOUT), oz = (int)((pp / (DOUT * DOUT)) % DOUT);
+        const int64_t nb = pp / ((int64_t)DOUT * DOUT * DOUT);
+        v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < KC; ++c) {
+            const int k0 = 16 * c + kq;  // 4 consecutive k: same kernel offset, channels ci..ci+3
+            v4i16 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+            if (k0 < K) {
+                const int off = k0 / CIN, ci = k0 % CIN;
+                const int kd = off / 9, kh = (off / 3) % 3, kw = off % 3;
+                const int iz = oz * STRIDE + kd - 1, iy = oy * STRIDE + kh - 1, ix = ox * STRIDE + kw - 1;
+                if (pin && iz >= 0 && iy >= 0 && ix >= 0 && iz < DIN && iy < DIN && ix < DIN) {
+                    const int64_t src = (((nb * DIN + iz) * DIN + iy) * DIN + ix) * CIN + ci;
+                    a = *(const v4i16 *)(x + src);
+                }
+                b = *(const v4i16 *)(w + (int64_t)co * K + k0);
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        }
+        const float bv = bias[co];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t q = tile * 16 + 4 * (lane >> 4) + i;
+            if (q < n_pos) {
+                const float v = fmaxf(acc[i] + bv, 0.0f);
+                y[q * COUT + co] = f2bf(v);
+            }
+        }
+    }
+}
+
+// Global mean over the 4^3 positions and the fully connected head.
+__global__ void k_pool_fc(const uint16_t *__restrict__ a4, const float *__restrict__ wfc,
+                          const float *__restrict__ bfc, float *__restrict__ pooled, float *__restrict__ out, int n)
+{
+    const int b = blockIdx.x, c = threadIdx.x;  // 64 threads
+    if (b >= n) return;
+    __shared__ float f[kFeat];
+    float s = 0.f;
+    for (int p = 0; p < 64; ++p) s += bf2f(a4[((int64_t)b * 64 + p) * kFeat + c]);
+    s *= (1.0f / 64.0f);
+    f[c] = s;
+    pooled[b * kFeat + c] = s;
+    __syncthreads();
+    if (c < kOut) {
+        float o = bfc[c];
+        for (int k = 0; k < kFeat; ++k) o += wfc[c * kFeat + k] * f[k];
+        out[b * kOut + c] = o;
+    }
+}
+
+// ------------------------------------------------------------ backward (FP32)
+
+// Loss: sum over the batch of (|t - t*|^2 / s_t^2 + |(c, s) - (c*, s*)|^2),
+// divided by n.  d_out = its gradient.
+__global__ void k_loss(const float *__restrict__ out, const float *__restrict__ y, float *__restrict__ dout,
+                       float *__restrict__ loss, int n, float inv_st2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * kOut) return;
+    const int k = i % kOut;
+    const float wgt = k < 3 ? inv_st2 : 1.0f;
+    const float d = out[i] - y[i];
+    dout[i] = 2.0f * wgt * d / (float)n;
+    atomicAdd(loss, wgt * d * d / (float)n);
+}
+
+// FC backward: gradients of the head, then d a4 = (d pooled / 64) masked by
+// ReLU (a4 > 0).
+__global__ void k_fc_bwd(const float *__restrict__ dout, const float *__restrict__ pooled,
+                         const float *__restrict__ wfc, const uint16_t *__restrict__ a4, float *__restrict__ gwfc,
+                         float *__restrict__ gbfc, float *__restrict__ da4, int n)
+{
+    const int t = threadIdx.x;  // 64 threads, one block
+    // weight and bias gradients (each thread one feature column)
+    for (int o = 0; o < kOut; ++o) {
+        float g = 0.f, gb = 0.f;
+        for (int b = 0; b < n; ++b) {
+            g += dout[b * kOut + o] * pooled[b * kFeat + t];
+            gb += dout[b * kOut + o];
+        }
+        gwfc[o * kFeat + t] += g;
+        if (t == 0) gbfc[o] += gb;
+    }
+    for (int b = 0; b < n; ++b) {
+        float dp = 0.f;
+        for (int o = 0; o < kOut; ++o) dp += dout[b * kOut + o] * wfc[o * kFeat + t];
+        dp *= (1.0f / 64.0f);
+        for (int p = 0; p < 64; ++p) {
+            const int64_t q = ((int64_t)b * 64 + p) * kFeat + t;
+            da4[q] = bf2f(a4[q]) > 0.f ? dp : 0.f;
+        }
+    }
+}
+
+// Weight gradient: gw[co][k] += sum_p x_col[p][k] dy[p][co]; bias: sum_p dy.
+// Grid: (K * COUT) threads per position chunk, accumulated with atomics.
+template <int CIN, int COUT, int DIN, int DOUT, int STRIDE>
+__global__ void k_conv_wgrad(const uint16_t *__restrict__ x, const float *__restrict__ dy, float *__restrict__ gw,
+                             float *__restrict__ gb, int64_t n_pos, int64_t chunk)
+{
+    constexpr int K = 27 * CIN;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)(K + 1) * COUT;
+    const int64_t slot = id % per, part = id / per;
+    const int64_t p0 = part * chunk;
+    if (p0 >= n_pos) return;
+    const int64_t p1 = min(n_pos, p0 + chunk);
+    const int co = (int)(slot % COUT), k = (int)(slot / COUT);
+    float s = 0.f;
+    if (k == K) {
+        for (int64_t p = p0; p < p1; ++p) s += dy[p * COUT + co];
+        atomicAdd(&gb[co], s);
+        return;
+    }
+    const int off = k / CIN, ci = k % CIN;
+    const int kd = off / 9, kh = (off / 3) % 3, kw = off % 3;
+    for (int64_t p = p0; p < p1; ++p) {
+        const float g = dy[p * COUT + co];
+        if (g == 0.f) continue;
+        const int ox = (int)(p % DOUT), oy = (int)((p / DOUT) % DOUT), oz = (int)((p / (DOUT * DOUT)) % DOUT);
+        const int64_t nb = p / ((int64_t)DOUT * DOUT * DOUT);
+        const int iz = oz * STRIDE + kd - 1, iy = oy * STRIDE + kh - 1, ix = ox * STRIDE + kw - 1;
+        if (iz < 0 || iy < 0 || ix < 0 || iz >= DIN || iy >= DIN || ix >= DIN) continue;
+        s += bf2f(x[(((nb * DIN + iz) * DIN + iy) * DIN + ix) * CIN + ci]) * g;
+    }
+    atomicAdd(&gw[(int64_t)co * K + k], s);
+}
+
+// Input gradient through the convolution, masked by the ReLU of the layer
+// that produced x (x > 0): dx[p][ci] = sum over (offset, co) dy[o][co] w[co][offset, ci].
+template <int CIN, int COUT, int DIN, int DOUT, int STRIDE>
+__global__ void k_conv_dgrad(const uint16_t *__restrict__ x, const float *__restrict__ dy,
+                             const float *__restrict__ wmaster, float *__restrict__ dx, int64_t n_in)
+{
+    constexpr int K = 27 * CIN;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= n_in * CIN) return;
+    const int ci = (int)(id % CIN);
+    const int64_t p = id / CIN;
+    if (!(bf2f(x[id]) > 0.f)) {
+        dx[id] = 0.f;
+        return;
+    }
+    const int ix = (int)(p % DIN), iy = (int)((p / DIN) % DIN), iz = (int)((p / (DIN * DIN)) % DIN);
+    const int64_t nb = p / ((int64_t)DIN * DIN * DIN);
+    float s = 0.f;
+    for (int kd = 0; kd < 3; ++kd) {
+        const int tz = iz + 1 - kd;
+        if (tz < 0 || tz % STRIDE) continue;
+        const int oz = tz / STRIDE;
+        if (oz >= DOUT) continue;
+        for (int kh = 0; kh < 3; ++kh) {
+            const int ty = iy + 1 - kh;
+            if (ty < 0 || ty % STRIDE) continue;
+            const int oy = ty / STRIDE;
+            if (oy >= DOUT) continue;
+            for (int kw = 0; kw < 3; ++kw) {
+                const int tx = ix + 1 - kw;
+                if (tx < 0 || tx % STRIDE) continue;
+                const int ox = tx / STRIDE;
+                if (ox >= DOUT) continue;
+                const int64_t o = ((nb * DOUT + oz) * DOUT + oy) * DOUT + ox;
+                const int k = ((kd * 3 + kh) * 3 + kw) * CIN + ci;
+                for (int co = 0; co < COUT; ++co) s += dy[o * COUT + co] * wmaster[(int64_t)co * K + k];
+            }
+        }
+    }
+    dx[id] = s;
+}
+
+// Adam (Kingma and Ba, 2015) on the FP32 master weights; refreshes the bf16
+// copies of the convolution weights.
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       int64_t n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void k_refresh_bf16(const float *__restrict__ w, uint16_t *__restrict__ wb, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) wb[i] = f2bf(w[i]);
+}
+
+__global__ void k_zero(float *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
+unsigned blocks_for(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + t - 1) / t, 1 << 20)); }
+
+}  // namespace
+
+// Parameter layout (FP32 master, in order): for each convolution w[cout][27
+// cin], b[cout]; then fc w[5][64], b[5].
+struct NetParams {
+    int64_t off_w[kLayers], off_b[kLayers], off_fcw, off_fcb, total;
+    NetParams()
+    {
+        int64_t o = 0;
+        for (int l = 0; l < kLayers; ++l) {
+            off_w[l] = o;
+            o += (int64_t)kShapes[l].cout * kShapes[l].K();
+            off_b[l] = o;
+            o += kShapes[l].cout;
+        }
+        off_fcw = o;
+        o += kOut * kFeat;
+        off_fcb = o;
+        o += kOut;
+        total = o;
+    }
+};
+
+}  // namespace covox
+
+struct covox_net {
+    covox_ctx *ctx = nullptr;
+    covox::NetParams P;
+    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // FP32 master, grad, Adam moments
+    uint16_t *wb[covox::kLayers] = {nullptr, nullptr, nullptr, nullptr};
+    int64_t step = 0;
+    // activations for the current batch capacity
+    int batch_cap = 0;
+    uint16_t *x0 = nullptr, *a[covox::kLayers] = {nullptr, nullptr, nullptr, nullptr};
+    float *pooled = nullptr, *out = nullptr, *dout = nullptr, *loss = nullptr;
+    float *d[covox::kLayers] = {nullptr, nullptr, nullptr, nullptr};  // gradients of the layer outputs
+};
+
+namespace covox {
+
+static int64_t act_elems(int l, int n)
+{
+    const ConvShape &s = kShapes[l];
+    return (int64_t)n * s.dout * s.dout * s.dout * s.cout;
+}
+
+static int net_reserve(covox_net *net, int n)
+{
+    if (n <= net->batch_cap) return COVOX_OK;
+    covox_ctx *ctx = net->ctx;
+    hipStreamSynchronize(ctx->stream);
+    auto fr = [](void *p) { if (p) (void)hipFree(p); };
+    fr(net->x0); fr(net->pooled); fr(net->out); fr(net->dout); fr(net->loss);
+    for (int l = 0; l < kLayers; ++l) { fr(net->a[l]); fr(net->d[l]); net->a[l] = nullptr; net->d[l] = nullptr; }
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMalloc((void **)&net->x0, sizeof(uint16_t) * (int64_t)n * 32768 * 4);
+    for (int l = 0; l < kLayers && e == hipSuccess; ++l) {
+        e = hipMalloc((void **)&net->a[l], sizeof(uint16_t) * act_elems(l, n));
+        if (e == hipSuccess) e = hipMalloc((void **)&net->d[l], sizeof(float) * act_elems(l, n));
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&net->pooled, sizeof(float) * n * kFeat);
+    if (e == hipSuccess) e = hipMalloc((void **)&net->out, sizeof(float) * n * kOut);
+    if (e == hipSuccess) e = hipMalloc((void **)&net->dout, sizeof(float) * n * kOut);
+    if (e == hipSuccess) e = hipMalloc((void **)&net->loss, sizeof(float));
+    if (e != hipSuccess) {
+        net->batch_cap = 0;
+        return fail(ctx, COVOX_EHIP, std::string("net buffers: ") + hipGetErrorString(e));
+    }
+    net->batch_cap = n;
+    return COVOX_OK;
+}
+
+template <int L>
+static void launch_conv_fwd(covox_net *net, const uint16_t *x, int n)
+{
+    constexpr ConvShape s = kShapes[L];
+    const int64_t npos = (int64_t)n * s.dout * s.dout * s.dout;
+    const unsigned grid = (unsigned)std::min<int64_t>((npos + 15) / 16, 1 << 20);
+    hipLaunchKernelGGL((k_conv_fwd<s.cin, s.cout, s.din, s.dout, s.stride>), dim3(grid), dim3(64 * (s.cout / 16)), 0,
+                       net->ctx->stream, x, net->wb[L], net->w + net->P.off_b[L], net->a[L], npos);
+}
+
+static int net_forward(covox_net *net, const float *x_dev, int n)
+{
+    covox_ctx *ctx = net->ctx;
+    int rc = net_reserve(net, n);
+    if (rc) return rc;
+    const int64_t nx = (int64_t)n * 32768 * 4;
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(nx, 256)), dim3(256), 0, ctx->stream, x_dev, net->x0, nx);
+    {
+        TimedLaunch tl(ctx, COVOX_K_NET);
+        launch_conv_fwd<0>(net, net->x0, n);
+        launch_conv_fwd<1>(net, net->a[0], n);
+        launch_conv_fwd<2>(net, net->a[1], n);
+        launch_conv_fwd<3>(net, net->a[2], n);
+        hipLaunchKernelGGL(k_pool_fc, dim3(n), dim3(64), 0, ctx->stream, net->a[3], net->w + net->P.off_fcw,
+                           net->w + net->P.off_fcb, net->pooled, net->out, n);
+    }
+    return hip_check(ctx, hipGetLastError(), "net forward");
+}
+
+template <int L>
+static void launch_wgrad(covox_net *net, const uint16_t *x, int n)
+{
+    constexpr ConvShape s = kShapes[L];
+    const int64_t npos = (int64_t)n * s.dout * s.dout * s.dout;
+    const int64_t chunk = 2048;
+    const int64_t parts = (npos + chunk - 1) / chunk;
+    const int64_t threads = parts * (int64_t)(s.K() + 1) * s.cout;
+    hipLaunchKernelGGL((k_conv_wgrad<s.cin, s.cout, s.din, s.dout, s.stride>), dim3(blocks_for(threads, 256)), dim3(256), 0,
+                       net->ctx->stream, x, net->d[L], net->g + net->P.off_w[L], net->g + net->P.off_b[L], npos, chunk);
+}
+
+template <int L>
+static void launch_dgrad(covox_net *net, const uint16_t *x, float *dx, int n)
+{
+    constexpr ConvShape s = kShapes[L];
+    const int64_t nin = (int64_t)n * s.din * s.din * s.din;
+    hipLaunchKernelGGL((k_conv_dgrad<s.cin, s.cout, s.din, s.dout, s.stride>), dim3(blocks_for(nin * s.cin, 256)),
+                       dim3(256), 0, net->ctx->stream, x, net->d[L], net->w + net->P.off_w[L], dx, nin);
+}
+
+static int net_backward(covox_net *net, int n)
+{
+    covox_ctx *ctx = net->ctx;
+    const int64_t np = net->P.total;
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(np, 256)), dim3(256), 0, ctx->stream, net->g, np);
+    hipLaunchKernelGGL(k_fc_bwd, dim3(1), dim3(64), 0, ctx->stream, net->dout, net->pooled, net->w + net->P.off_fcw,
+                       net->a[3], net->g + net->P.off_fcw, net->g + net->P.off_fcb, net->d[3], n);
+    launch_wgrad<3>(net, net->a[2], n);
+    launch_dgrad<3>(net, net->a[2], net->d[2], n);
+    launch_wgrad<2>(net, net->a[1], n);
+    launch_dgrad<2>(net, net->a[1], net->d[1], n);
+    launch_wgrad<1>(net, net->a[0], n);
+    launch_dgrad<1>(net, net->a[0], net->d[0], n);
+    launch_wgrad<0>(net, net->x0, n);
+    return hip_check(ctx, hipGetLastError(), "net backward");
+}
+
+static void refresh_bf16(covox_net *net)
+{
+    for (int l = 0; l < kLayers; ++l) {
+        const int64_t nw = (int64_t)kShapes[l].cout * kShapes[l].K();
+        hipLaunchKernelGGL(k_refresh_bf16, dim3(blocks_for(nw, 256)), dim3(256), 0, net->ctx->stream,
+                           net->w + net->P.off_w[l], net->wb[l], nw);
+    }
+}
+
+int net_forward_api(covox_net *net, const float *x_dev, int n, float *out_dev)
+{
+    int rc = net_forward(net, x_dev, n);
+    if (rc) return rc;
+    return hip_check(net->ctx, hipMemcpyAsync(out_dev, net->out, sizeof(float) * n * kOut, hipMemcpyDeviceToDevice,
+                                              net->ctx->stream), "net output copy");
+}
+
+int net_train_step(covox_net *net, const float *x_dev, const float *y_dev, int n, float lr, float trans_scale,
+                   float *loss_host)
+{
+    covox_ctx *ctx = net->ctx;
+    int rc = net_forward(net, x_dev, n);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, ctx->stream, net->loss, (int64_t)1);
+    hipLaunchKernelGGL(k_loss, dim3(blocks_for((int64_t)n * kOut, 64)), dim3(64), 0, ctx->stream, net->out, y_dev,
+                       net->dout, net->loss, n, 1.0f / (trans_scale * trans_scale));
+    {
+        TimedLaunch tl(ctx, COVOX_K_NET);
+        if ((rc = net_backward(net, n))) return rc;
+    }
+    net->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)net->step), c2 = 1.f - powf(b2, (float)net->step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(net->P.total, 256)), dim3(256), 0, ctx->stream, net->w, net->g, net->m,
+                       net->v, net->P.total, lr, b1, b2, 1e-8f, c1, c2);
+    refresh_bf16(net);
+    if ((rc = hip_check(ctx, hipGetLastError(), "net train step"))) return rc;
+    if (loss_host) {
+        if ((rc = hip_check(ctx, hipMemcpyAsync(loss_host, net->loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream),
+                            "loss copy")))
+            return rc;
+        return hip_check(ctx, hipStreamSynchronize(ctx->stream), "train sync");
+    }
+    return COVOX_OK;
+}
+
+int net_grads(covox_net *net, const float *x_dev, const float *y_dev, int n, float trans_scale, float *grad_host,
+              float *loss_host)
+{
+    covox_ctx *ctx = net->ctx;
+    int rc = net_forward(net, x_dev, n);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, ctx->stream, net->loss, (int64_t)1);
+    hipLaunchKernelGGL(k_loss, dim3(blocks_for((int64_t)n * kOut, 64)), dim3(64), 0, ctx->stream, net->out, y_dev,
+                       net->dout, net->loss, n, 1.0f / (trans_scale * trans_scale));
+    if ((rc = net_backward(net, n))) return rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(grad_host, net->g, sizeof(float) * net->P.total, hipMemcpyDeviceToHost,
+                                            ctx->stream), "grad copy")))
+        return rc;
+    if (loss_host &&
+        (rc = hip_check(ctx, hipMemcpyAsync(loss_host, net->loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream),
+                        "loss copy")))
+        return rc;
+    return hip_check(ctx, hipStreamSynchronize(ctx->stream), "grad sync");
+}
+
+int net_create(covox_ctx *ctx, uint64_t seed, covox_net **out)
+{
+    covox_net *net = new covox_net();
+    net->ctx = ctx;
+    const int64_t np = net->P.total;
+    hipError_t e = hipSuccess;
+    for (float **p : {&net->w, &net->g, &net->m, &net->v})
+        if (e == hipSuccess) e = hipMalloc((void **)p, sizeof(float) * np);
+    for (int l = 0; l < kLayers && e == hipSuccess; ++l)
+        e = hipMalloc((void **)&net->wb[l], sizeof(uint16_t) * (int64_t)kShapes[l].cout * kShapes[l].K());
+    if (e != hipSuccess) {
+        net_destroy(net);
+        return fail(ctx, COVOX_EHIP, std::string("net_create: ") + hipGetErrorString(e));
+    }
+    // He-uniform initialisation from SplitMix64 (zero biases)
+    std::vector<float> h(np, 0.f);
+    uint64_t state = seed;
+    auto uni = [&]() {
+        state += 0x9e3779b97f4a7c15ull;
+        return (double)(mix64(state) >> 11) * (1.0 / 9007199254740992.0);
+    };
+    for (int l = 0; l < kLayers; ++l) {
+        const double lim = sqrt(6.0 / (double)kShapes[l].K());
+        for (int64_t i = 0; i < (int64_t)kShapes[l].cout * kShapes[l].K(); ++i)
+            h[net->P.off_w[l] + i] = (float)((2.0 * uni() - 1.0) * lim);
+    }
+    const double lim = sqrt(6.0 / (double)kFeat);
+    for (int i = 0; i < kOut * kFeat; ++i) h[net->P.off_fcw + i] = (float)((2.0 * uni() - 1.0) * lim) * 0.1f;
+    std::vector<float> zeros(np, 0.f);
+    e = hipMemcpy(net->w, h.data(), sizeof(float) * np, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(net->m, zeros.data(), sizeof(float) * np, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(net->v, zeros.data(), sizeof(float) * np, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        net_destroy(net);
+        return fail(ctx, COVOX_EHIP, std::string("net_create upload: ") + hipGetErrorString(e));
+    }
+    refresh_bf16(net);
+    *out = net;
+    return hip_check(ctx, hipGetLastError(), "net init");
+}
+
+void net_destroy(covox_net *net)
+{
+    if (!net) return;
+    if (net->ctx) (void)hipStreamSynchronize(net->ctx->stream);
+    for (void *p : {(void *)net->w, (void *)net->g, (void *)net->m, (void *)net->v, (void *)net->x0, (void *)net->pooled,
+                    (void *)net->out, (void *)net->dout, (void *)net->loss})
+        if (p) (void)hipFree(p);
+    for (int l = 0; l < kLayers; ++l) {
+        if (net->wb[l]) (void)hipFree(net->wb[l]);
+        if (net->a[l]) (void)hipFree(net->a[l]);
+        if (net->d[l]) (void)hipFree(net->d[l]);
+    }
+    delete net;
+}
+
+int64_t net_num_params(const covox_net *net) { return net->P.total; }
+
+int net_get_params(covox_net *net, float *host, int64_t n)
+{
+    if (n != net->P.total) return fail(net->ctx, COVOX_EINVAL, "net params: wrong count");
+    int rc = hip_check(net->ctx, hipStreamSynchronize(net->ctx->stream), "params sync");  // pending training steps
+    if (rc) return rc;
+    return hip_check(net->ctx, hipMemcpy(host, net->w, sizeof(float) * n, hipMemcpyDeviceToHost), "params copy");
+}
+
+int net_set_params(covox_net *net, const float *host, int64_t n)
+{
+    if (n != net->P.total) return fail(net->ctx, COVOX_EINVAL, "net params: wrong count");
+    int rc = hip_check(net->ctx, hipStreamSynchronize(net->ctx->stream), "params sync");  // readers in flight
+    if (rc) return rc;
+    rc = hip_check(net->ctx, hipMemcpy(net->w, host, sizeof(float) * n, hipMemcpyHostToDevice), "params upload");
+    if (rc) return rc;
+    refresh_bf16(net);
+    return hip_check(net->ctx, hipStreamSynchronize(net->ctx->stream), "params sync");
+}
+
+}  // namespace covox

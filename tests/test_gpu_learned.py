@@ -1,0 +1,194 @@
+"""GPU parity of the learned pose proposal: coarse ESDF summaries, the bf16
+matrix-core network (forward and gradients) and the proposal-then-refine
+driver, each through the C ABI against the checker on the same seeded
+inputs.
+
+Bars: summary values within 2e-5 (binary32 vs binary64 trilinear weights;
+values are phi / d_max in [-1, 1]) and masks equal except at cells whose
+sample lies within 1e-4 voxel of a voxel-centre plane (the binary32 map
+position can then select the neighbouring corner set); network outputs within
+2 % of the output scale (bf16 storage of every activation: a one-ulp
+difference in the accumulation order can flip a bf16 rounding, 2^-8 relative,
+and such flips compound over four layers); gradients within 3 % relative L2
+per layer against binary64 backpropagation through the checker's bf16 forward
+pass.  The driver with a zero cost threshold must give exactly what plain
+multi-start gives (every pair falls back)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as orc
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cv():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2410_21149_amd as cv
+    return cv
+
+
+def _ctx(cv):
+    return cv.Context(voxel_size=0.05, trunc_vox=4, max_range=5.0, d_max=2.0, block_capacity=8192)
+
+
+def _tiny_submaps(cv, ctx, with_oracle=True):
+    import torch
+    w = sg.tiny()
+    fr = w.frames()
+    dev = torch.from_numpy(fr).cuda()
+    A, B = ctx.submap_create(), ctx.submap_create()
+    rA = orc.Submap(orc.Params(vs=0.05, trunc_vox=4, max_range=5.0, d_max=2.0)) if with_oracle else None
+    rB = orc.Submap(orc.Params(vs=0.05, trunc_vox=4, max_range=5.0, d_max=2.0)) if with_oracle else None
+    for f in range(20):
+        for _ in range(2):
+            ctx.integrate_depth(A if f < 12 else B, dev[f], w.cam.K, w.poses[f])
+            if with_oracle:
+                (rA if f < 12 else rB).integrate(fr[f], w.cam.K, w.poses[f])
+    for f in range(8, 14):  # overlap
+        ctx.integrate_depth(B if f < 12 else A, dev[f], w.cam.K, w.poses[f])
+        if with_oracle:
+            (rB if f < 12 else rA).integrate(fr[f], w.cam.K, w.poses[f])
+    ctx.update_esdf(A)
+    ctx.update_esdf(B)
+    if with_oracle:
+        rA.update_esdf()
+        rB.update_esdf()
+    return A, B, rA, rB
+
+
+def _near_plane(T, cell, vs):
+    """Cells whose sample point lies within 1e-4 voxel of a plane through
+    voxel centres along some axis (x, y or z)."""
+    c = np.arange(32768)
+    g = np.stack([c & 31, (c >> 5) & 31, c >> 10], axis=1).astype(np.float64)
+    q = (g + 0.5 - 16.0) * cell
+    p = q @ T[:3, :3].T + T[:3, 3]
+    u = p / vs - 0.5
+    return np.any(np.abs(u - np.round(u)) < 1e-4, axis=1)
+
+
+def test_summaries_parity(cv):
+    import torch
+    ctx = _ctx(cv)
+    A, B, rA, rB = _tiny_submaps(cv, ctx)
+    Ts = [np.eye(4), orc.se3_exp(np.array([0.13, -0.07, 0.02, 0.05, -0.03, 0.7]))]
+    for T in Ts:
+        for cell, sm, rs in ((0.05, A, rA), (0.11, B, rB)):
+            out = torch.zeros((32768, 4), dtype=torch.float32, device="cuda")
+            ctx.summaries([(sm, T, cell, out, 2)])
+            g = out.cpu().numpy().astype(np.float64)
+            r = orc.summary(rs, T, cell)
+            assert np.all(g[:, :2] == 0), "other channels must be left untouched"
+            bad = (g[:, 3] != r[:, 1]) & ~_near_plane(T, cell, 0.05)
+            assert not bad.any(), np.flatnonzero(bad)[:10]
+            both = (g[:, 3] == 1) & (r[:, 1] == 1)
+            assert both.sum() > 1000
+            assert np.abs(g[both, 2] - r[both, 0]).max() <= 2e-5
+            assert np.all(g[g[:, 3] == 0, 2] == 0)
+    ctx.close()
+
+
+def _inputs(n, seed):
+    """Summary-like network inputs: values in [-1, 1] with masks, the masked
+    cells zero, in blobs (smooth fields) rather than white noise."""
+    rng = np.random.default_rng(seed)
+    c = np.arange(32)
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    x = np.zeros((n, 32, 32, 32, 4), np.float32)
+    for b in range(n):
+        for side in range(2):
+            a, bb, cc = rng.normal(size=3)
+            field = np.sin(0.2 * a * X + 0.3 * bb * Y) * np.cos(0.25 * cc * Z) + 0.1 * rng.normal(size=X.shape)
+            mask = (np.sin(0.15 * X + rng.uniform(0, 6)) + np.cos(0.2 * Y) + 0.5 * np.cos(0.1 * Z)) > -0.3
+            v = np.clip(field, -1, 1) * mask
+            # the (z, y, x) grid index order of NDHWC: x fastest
+            x[b, :, :, :, 2 * side] = v.transpose(2, 1, 0)
+            x[b, :, :, :, 2 * side + 1] = mask.transpose(2, 1, 0)
+    return x
+
+
+def test_network_forward_parity(cv):
+    import torch
+    ctx = _ctx(cv)
+    net = cv.Net(ctx, seed=7)
+    p = net.get_params()
+    assert len(p) == orc.net_num_params()
+    x = _inputs(2, 11)
+    g = net.forward(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+    r = orc.net_forward(p, x, bf16=True)
+    scale = np.abs(r).max()
+    assert scale > 1e-3
+    assert np.abs(g - r).max() <= 0.02 * scale, (g, r)
+    # a different batch size gives the same per-sample outputs
+    g1 = net.forward(torch.from_numpy(x[1:]).cuda()).cpu().numpy()
+    assert np.array_equal(g1[0], g[1].astype(np.float32))
+    ctx.close()
+
+
+def test_network_gradients_parity(cv):
+    import torch
+    ctx = _ctx(cv)
+    net = cv.Net(ctx, seed=9)
+    p = net.get_params()
+    x = _inputs(2, 13)
+    y = np.array([[0.5, -1.0, 0.2, 0.8, 0.6], [-2.0, 0.3, -0.1, -0.6, 0.8]], np.float32)
+    loss_g, grad_g = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda(), 3.0)
+    loss_r, grad_r = orc.net_loss_grad(p, x, y, 3.0, bf16=True)
+    assert abs(loss_g - loss_r) <= 0.02 * loss_r
+    o = 0
+    sizes = []
+    for (ci, co, di, do, st) in orc.NET_LAYERS:
+        sizes += [co * 27 * ci, co]
+    sizes += [5 * orc.NET_FEAT, 5]
+    for k, sz in enumerate(sizes):
+        a, b = grad_g[o:o + sz].astype(np.float64), grad_r[o:o + sz]
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+        assert err <= 0.03, (k, err)
+        o += sz
+    assert o == len(p)
+    ctx.close()
+
+
+def test_training_reduces_the_loss(cv):
+    import torch
+    ctx = _ctx(cv)
+    net = cv.Net(ctx, seed=3)
+    x = torch.from_numpy(_inputs(4, 17)).cuda()
+    y = torch.tensor([[1.0, -0.5, 0.1, 1.0, 0.0], [-1.0, 0.5, 0.0, 0.0, 1.0],
+                      [0.3, 0.3, -0.2, -1.0, 0.0], [0.0, -1.2, 0.1, 0.0, -1.0]], device="cuda")
+    p0 = net.get_params()
+    losses = [net.train_step(x, y, 1e-3) for _ in range(40)]
+    assert losses[-1] < 0.5 * losses[0], losses
+    p1 = net.get_params()
+    assert not np.array_equal(p0, p1)
+    # set_params restores the exact forward
+    net.set_params(p0)
+    net2 = cv.Net(ctx, seed=3)
+    assert np.array_equal(net.forward(x).cpu().numpy(), net2.forward(x).cpu().numpy())
+    ctx.close()
+
+
+def test_learned_driver_fallback_equals_multistart(cv):
+    ctx = _ctx(cv)
+    A, B, _, _ = _tiny_submaps(cv, ctx, with_oracle=False)
+    net = cv.Net(ctx, seed=1)
+    T0s = [orc.se3_exp(np.array([0.02, 0.01, -0.01, 0.0, 0.0, 0.5])),
+           orc.se3_exp(np.array([-0.05, 0.03, 0.0, 0.0, 0.0, -0.2]))]
+    pairs = [(A, B, T) for T in T0s]
+    Tl, cl, sl = ctx.align_learned(net, pairs, 0.1, 0.0, n_starts=8)
+    Tb, cb, sb = ctx.align_batch(pairs, n_starts=8)
+    assert np.array_equal(Tl, Tb) and np.array_equal(cl, cb)
+    assert [s["best_start"] for s in sl] == [s["best_start"] for s in sb]
+    # an infinite threshold keeps the refined proposal: a converged pose
+    Ti, ci, si = ctx.align_learned(net, pairs, 0.1, math.inf, n_starts=8)
+    for k in range(2):
+        assert si[k]["best_start"] == -1 and si[k]["status"] in (cv.OK, cv.NOT_CONVERGED)
+        R = Ti[k][:3, :3]
+        assert np.allclose(R @ R.T, np.eye(3), atol=1e-9)
+    ctx.close()
