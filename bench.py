@@ -286,9 +286,93 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
             errs.append(et)
         align["starts_%d" % n_starts] = {"pairs_per_s": n_pairs / best, "success": ok / n_pairs,
                                           "median_t_err_m": float(np.median(errs)), "ms": best * 1e3}
+    learned = learned_bench(cv, torch, np, ctx, subs, Tws, w.voxel_size)
     ctx.close()
     return {"workload": "outdoor 120x80 m, 3000 frames 640x480 fx=fy=380, 0.1 m voxels, 30 submaps of 100 frames",
-            "build_s": t_build, "esdf_batch": esdf, "align": align}
+            "build_s": t_build, "esdf_batch": esdf, "align": align, "learned": learned}
+
+
+def _success(T, gts, np, bound_t, bound_deg):
+    ok = 0
+    for Tg, Tt in zip(T, gts):
+        et = np.linalg.norm(Tg[:3, 3] - Tt[:3, 3])
+        c = (np.trace(Tg[:3, :3] @ Tt[:3, :3].T) - 1) / 2
+        ok += et <= bound_t and math.degrees(math.acos(max(-1.0, min(1.0, c)))) <= bound_deg
+    return ok / max(1, len(gts))
+
+
+def learned_bench(cv, torch, np, ctx, subs, Tws, vs, n_items=1024, reps=3):
+    """Learned proposal + refinement against plain 8-start on held-out pairs
+    of the outdoor scene (its seed is not among the training seeds): every
+    pair with block overlap >= 0.2 (j = i+1..i+4, both directions), re-framed
+    like the training data (+-3 m x/y, +-0.5 m z, +-180 deg yaw about the
+    summary grid centre, +-2 deg roll/pitch), n_items in total."""
+    import importlib.util
+    path = os.path.join(ROOT, "paper_2410_21149_amd", "data", "proposal_mav.npz")
+    if not os.path.exists(path):
+        return {"skipped": "no trained proposal weights at " + os.path.relpath(path, ROOT)}
+    spec = importlib.util.spec_from_file_location("_train_proposal", os.path.join(ROOT, "paper_2410_21149_amd",
+                                                                                    "train_proposal.py"))
+    tp = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(tp)
+    params, meta = tp.load(path)
+    net = cv.Net(ctx, seed=1)
+    net.set_params(params)
+    cell, c_thr = float(meta["cell"]), float(meta["c_thr"])
+    base = []
+    for i, j, ov in tp.block_pairs(ctx, subs, Tws, vs, min_overlap=0.2):
+        T = np.linalg.inv(Tws[i]) @ Tws[j]
+        base.append((subs[i], subs[j], T))
+        base.append((subs[j], subs[i], np.linalg.inv(T)))
+    cent = {}
+    rng = np.random.default_rng(6)
+    items, gts = [], []
+    for k in range(n_items):
+        A, B, T_gt = base[k % len(base)]
+        if id(A) not in cent:
+            cent[id(A)] = ctx.export_points(A).astype(np.float64).mean(axis=0)
+        G = np.eye(4)
+        G[:3, 3] = cent[id(A)]
+        yaw = rng.uniform(-math.pi, math.pi)
+        C = np.eye(4)
+        C[:3, :3] = [[math.cos(yaw), -math.sin(yaw), 0], [math.sin(yaw), math.cos(yaw), 0], [0, 0, 1]]
+        C[:3, 3] = [rng.uniform(-3, 3), rng.uniform(-3, 3), rng.uniform(-0.5, 0.5)]
+        E = tp.perturbed(rng, np.eye(4), trans=0.0, yaw_deg=0.0, tilt_deg=2.0)
+        items.append((A, B, G @ np.linalg.inv(C) @ np.linalg.inv(G) @ T_gt @ E))
+        gts.append(T_gt)
+    out = {"held_out_pairs": n_items, "distinct_pairs": len(base), "cell_m": cell, "cost_threshold": c_thr,
+           "training": {k: meta[k] for k in ("seeds", "pairs_train", "steps", "batch", "final_loss") if k in meta}}
+    runs = {}
+    for name, fn in (("plain_8start", lambda: ctx.align_batch(items, 8)),
+                     ("learned_refine", lambda: ctx.align_learned(net, items, cell, c_thr, 8))):
+        fn()  # warm (buffers, registration points)
+        best, res = None, None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = fn()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        T, cost, st = res
+        r = {"pairs_per_s": n_items / best, "ms": best * 1e3,
+             "success_1cm_0.1deg": _success(T, gts, np, 0.01, 0.1),
+             "success_5cm_0.5deg": _success(T, gts, np, 0.05, 0.5)}
+        r["aligned_per_s_1cm"] = r["pairs_per_s"] * r["success_1cm_0.1deg"]
+        r["aligned_per_s_5cm"] = r["pairs_per_s"] * r["success_5cm_0.5deg"]
+        if name == "learned_refine":
+            r["fallback_fraction"] = sum(1 for x in st if x["best_start"] >= 0) / n_items
+        runs[name] = r
+    out.update(runs)
+    Tp = ctx.propose(net, items, cell)
+    out["proposal_only_success_0.5m_10deg"] = _success(Tp, gts, np, 0.5, 10.0)
+    pl, le = runs["plain_8start"], runs["learned_refine"]
+    out["ratio_aligned_per_s_1cm"] = (le["aligned_per_s_1cm"] / pl["aligned_per_s_1cm"]
+                                      if pl["aligned_per_s_1cm"] > 0 else None)
+    out["ratio_aligned_per_s_5cm"] = (le["aligned_per_s_5cm"] / pl["aligned_per_s_5cm"]
+                                      if pl["aligned_per_s_5cm"] > 0 else None)
+    out["ratio_pairs_per_s"] = le["pairs_per_s"] / pl["pairs_per_s"]
+    net.close()
+    return out
 
 
 def main():

@@ -300,6 +300,38 @@ int covox_net_gradients(covox_net *net, const float *x_dev, const float *y_dev, 
 int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell,
                         double cost_thr, int32_t n_starts, double *T_out, double *cost, covox_align_stats *stats);
 
+/* The network's proposal alone for n pairs (the first step of
+ * covox_align_learned): T_prop = T_A_grid C T_A_grid^-1 T_init, host n x 16
+ * doubles.  Synchronous. */
+int covox_propose(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell, double *T_prop);
+
+/* Training on re-framings of ground-truth pairs.  Item b of step s draws
+ * (SplitMix64 of seed and the counter s * batch + b) a pair j, a correction
+ * C = (t, Rz(yaw)) with t uniform in [-trans_xy, trans_xy]^2 x [-trans_z,
+ * trans_z] and yaw uniform in [-yaw, yaw], and a tilt E = Rx(roll) Ry(pitch)
+ * with roll, pitch uniform in [-tilt, tilt]; the prior is T_init = T_A_grid
+ * C^-1 T_A_grid^-1 T_gt E and the network is trained (one Adam step per step)
+ * to output C.  The summaries are re-sampled from the existing ESDFs; nothing
+ * is re-integrated. */
+typedef struct {
+    int32_t steps;       /* Adam steps */
+    int32_t batch;       /* items per step, 1..256 */
+    double lr;           /* Adam learning rate */
+    double trans_scale;  /* translation scale of the loss (m) */
+    double cell;         /* summary cell edge (m) */
+    double trans_xy;     /* correction translation range in x and y (m) */
+    double trans_z;      /* correction translation range in z (m) */
+    double yaw;          /* correction yaw range (rad) */
+    double tilt;         /* roll / pitch range of the prior (rad) */
+    uint64_t seed;
+} covox_train_cfg;
+
+/* pairs[i].T_init_A_B holds the ground truth T_A_B of the pair; both ESDFs
+ * must be current.  loss_host (nullable): the loss of every step (steps
+ * floats).  Synchronous. */
+int covox_train_proposal(covox_ctx *ctx, covox_net *net, const covox_train_cfg *cfg, const covox_pair *pairs,
+                         int32_t n, float *loss_host);
+
 /* ---------------------------------------------------------------- timing */
 
 enum {

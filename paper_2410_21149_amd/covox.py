@@ -8,6 +8,7 @@ at import time -- there is no fallback path.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -53,6 +54,13 @@ class covox_submap_info(ctypes.Structure):
     _fields_ = [("n_blocks", ctypes.c_int64), ("block_capacity", ctypes.c_int64), ("table_capacity", ctypes.c_int64),
                 ("n_updates", ctypes.c_int64), ("bbox_min", ctypes.c_int32 * 3), ("bbox_max", ctypes.c_int32 * 3),
                 ("precision", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class covox_train_cfg(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("trans_scale", ctypes.c_double), ("cell", ctypes.c_double), ("trans_xy", ctypes.c_double),
+                ("trans_z", ctypes.c_double), ("yaw", ctypes.c_double), ("tilt", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
 
 
 class covox_timing(ctypes.Structure):
@@ -104,6 +112,9 @@ _sig = {
     "covox_align_learned": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_int32, _dp, _dp,
                                            ctypes.POINTER(covox_align_stats)]),
+    "covox_propose": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_double, _dp]),
+    "covox_train_proposal": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_train_cfg), ctypes.POINTER(covox_pair),
+                                            ctypes.c_int32, _fp]),
     "covox_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "covox_timing_get": (ctypes.c_int, [_vp, ctypes.POINTER(covox_timing)]),
 }
@@ -295,17 +306,41 @@ class Context:
 
     def align_learned(self, net: "Net", pairs, cell, cost_thr, n_starts=8):
         n = len(pairs)
-        arr = (covox_pair * max(n, 1))()
-        for i, (A, B, T0) in enumerate(pairs):
-            arr[i].A = A.handle
-            arr[i].B = B.handle
-            arr[i].T_init_A_B[:] = list(_mat(T0))
+        arr = self._pairs(pairs)
         T = np.zeros(16 * max(n, 1))
         cost = np.zeros(max(n, 1))
         st = (covox_align_stats * max(n, 1))()
         self._check(_lib.covox_align_learned(self.handle, net.handle, arr, n, cell, cost_thr, n_starts, _p(T, _dp),
                                              _p(cost, _dp), st), "align_learned")
         return T.reshape(-1, 4, 4)[:n], cost[:n], [_stats(st[i]) for i in range(n)]
+
+    def propose(self, net: "Net", pairs, cell):
+        """The network's proposals (n x 4 x 4) for (A, B, T_init) pairs."""
+        arr = self._pairs(pairs)
+        n = len(pairs)
+        T = np.zeros(16 * max(n, 1))
+        self._check(_lib.covox_propose(self.handle, net.handle, arr, n, cell, _p(T, _dp)), "propose")
+        return T.reshape(-1, 4, 4)[:n]
+
+    def train_proposal(self, net: "Net", pairs, steps, batch=64, lr=1e-3, trans_scale=3.0, cell=1.0, trans_xy=3.0,
+                       trans_z=0.5, yaw=math.pi, tilt=math.radians(2.0), seed=5):
+        """Trains `net` on re-framings of (A, B, T_gt) pairs; returns the
+        per-step losses."""
+        cfg = covox_train_cfg(steps, batch, lr, trans_scale, cell, trans_xy, trans_z, yaw, tilt, seed)
+        arr = self._pairs(pairs)
+        losses = np.zeros(max(steps, 1), np.float32)
+        self._check(_lib.covox_train_proposal(self.handle, net.handle, ctypes.byref(cfg), arr, len(pairs),
+                                              _p(losses, _fp)), "train_proposal")
+        return losses[:steps]
+
+    @staticmethod
+    def _pairs(pairs):
+        arr = (covox_pair * max(len(pairs), 1))()
+        for i, (A, B, T0) in enumerate(pairs):
+            arr[i].A = A.handle
+            arr[i].B = B.handle
+            arr[i].T_init_A_B[:] = list(_mat(T0))
+        return arr
 
     # -- inspection
     def export_blocks(self, s: Submap) -> dict:

@@ -313,7 +313,7 @@ void covox_destroy(covox_ctx *ctx)
     for (covox_submap *s : std::vector<covox_submap *>(subs)) covox_submap_destroy(s);
     for (void *ptr : {(void *)ctx->cand, (void *)ctx->t_key, (void *)ctx->t_idx, (void *)ctx->sites, (void *)ctx->g1,
                       (void *)ctx->g2, (void *)ctx->cnt, (void *)ctx->psum, ctx->prob_dev, ctx->res_dev, ctx->sum_dev,
-                      (void *)ctx->net_in, (void *)ctx->net_out})
+                      (void *)ctx->net_in, (void *)ctx->net_out, (void *)ctx->train_y, (void *)ctx->loss_hist})
         if (ptr) (void)hipFree(ptr);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (auto &u : ctx->ev_used) {
@@ -683,76 +683,212 @@ int covox_net_gradients(covox_net *net, const float *x_dev, const float *y_dev, 
     return net_grads(net, x_dev, y_dev, n, trans_scale, grad_host, loss_host);
 }
 
+namespace {
+
+// T_A_grid = Trans(c_A): the summary grid of a pair is centred on the
+// centroid of A's registration points.
+void grid_of(const covox_submap *A, double *G)
+{
+    const double Gv[16] = {1, 0, 0, A->pbar[0], 0, 1, 0, A->pbar[1], 0, 0, 1, A->pbar[2], 0, 0, 0, 1};
+    ::memcpy(G, Gv, sizeof(Gv));
+}
+
+// Correction C = (Rz(yaw), t) in grid coordinates.
+void correction(double tx, double ty, double tz, double yaw, double *C)
+{
+    const double c = cos(yaw), s = sin(yaw);
+    const double Cv[16] = {c, -s, 0, tx, s, c, 0, ty, 0, 0, 1, tz, 0, 0, 0, 1};
+    ::memcpy(C, Cv, sizeof(Cv));
+}
+
+// out = G X G^-1 Y for rigid 4x4 matrices (last row exact).
+void conj_mul(const double *G, const double *X, const double *Y, double *out)
+{
+    double Gi[16], A1[16], A2[16];
+    rigid_inverse_h(G, Gi);
+    mat_mul4(G, X, A1);
+    mat_mul4(A1, Gi, A2);
+    mat_mul4(A2, Y, out);
+    out[12] = 0; out[13] = 0; out[14] = 0; out[15] = 1;
+}
+
+// Both ESDFs current, A's registration points (and centroid) extracted.
+int prepare_learned(covox_ctx *ctx, const covox_pair *pairs, int n, const char *what)
+{
+    int rc;
+    for (int i = 0; i < n; ++i) {
+        const covox_pair &pr = pairs[i];
+        if (!pr.A || !pr.B) return fail(ctx, COVOX_EINVAL, std::string(what) + ": null submap");
+        if (!rigid_pose(pr.T_init_A_B)) return fail(ctx, COVOX_EINVAL, std::string(what) + ": pose is not rigid");
+        if ((rc = prepare_pair(ctx, pr.A, pr.B))) return rc;
+        if (pr.B->esdf_version != pr.B->version)
+            return fail(ctx, COVOX_EINVAL, std::string(what) + ": the ESDF of B is out of date");
+        if ((rc = extract_points(ctx, const_cast<covox_submap *>(pr.A)))) return rc;
+    }
+    return COVOX_OK;
+}
+
+// Summaries of m pairs through their priors into the network input block
+// (A on channels 0-1, B on 2-3); G receives the m grid poses T_A_grid.
+int pair_summaries(covox_ctx *ctx, const covox_pair *pairs, int m, double cell, double *G)
+{
+    int rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->net_in, &ctx->net_in_cap, (int64_t)m * 32768 * 4, sizeof(float),
+                            "net input")))
+        return rc;
+    std::vector<SummaryReq> rq(2 * m);
+    for (int k = 0; k < m; ++k) {
+        const covox_pair &pr = pairs[k];
+        double *Gk = G + 16 * k, inv[16], TB[16];
+        grid_of(pr.A, Gk);
+        rigid_inverse_h(pr.T_init_A_B, inv);
+        mat_mul4(inv, Gk, TB);  // T_B_grid = T_init^-1 T_A_grid
+        const double *Ts[2] = {Gk, TB};
+        const covox_submap *ss[2] = {pr.A, pr.B};
+        for (int side = 0; side < 2; ++side) {
+            SummaryReq &r = rq[2 * k + side];
+            r.phi = ss[side]->phi;
+            r.page = ss[side]->page;
+            r.meta = ss[side]->meta;
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 4; ++c) r.T[4 * a + c] = (float)Ts[side][4 * a + c];
+            r.cell = (float)cell;
+            r.chan = 2 * side;
+            r.out = ctx->net_in + (int64_t)k * 32768 * 4;
+        }
+    }
+    return run_summaries(ctx, rq.data(), 2 * m);
+}
+
+// Network proposals T_A_grid C T_A_grid^-1 T_init of m <= 256 pairs
+// (host, m x 16).  Synchronous.
+int propose_chunk(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int m, double cell, double *Tp)
+{
+    int rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->net_out, &ctx->net_out_cap, (int64_t)m * 5, sizeof(float),
+                            "net output")))
+        return rc;
+    std::vector<double> G((size_t)16 * m);
+    if ((rc = pair_summaries(ctx, pairs, m, cell, G.data()))) return rc;
+    if ((rc = net_forward_api(net, ctx->net_in, m, ctx->net_out))) return rc;
+    std::vector<float> outs((size_t)5 * m);
+    if ((rc = hip_check(ctx, hipMemcpyAsync(outs.data(), ctx->net_out, sizeof(float) * 5 * m, hipMemcpyDeviceToHost,
+                                            ctx->stream), "net output copy")))
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "net sync"))) return rc;
+    for (int k = 0; k < m; ++k) {
+        const float *o = &outs[5 * k];
+        double C[16];
+        correction(o[0], o[1], o[2], atan2((double)o[4], (double)o[3]), C);
+        conj_mul(&G[16 * k], C, pairs[k].T_init_A_B, Tp + 16 * k);
+    }
+    return COVOX_OK;
+}
+
+constexpr int kLearnChunk = 256;
+
+// Uniform draw in [0, 1) number k of item `item` (SplitMix64 of the seed
+// and a counter).
+double draw(uint64_t seed, uint64_t item, int k)
+{
+    const uint64_t z = mix64(seed ^ mix64(item * 16u + (uint64_t)k + 1u));
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+}  // namespace
+
+int covox_propose(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell, double *T_prop)
+{
+    if (!ctx || !net || (!pairs && n > 0) || n < 0 || !(cell > 0) || (!T_prop && n > 0))
+        return fail(ctx, COVOX_EINVAL, "propose: bad argument");
+    int rc = prepare_learned(ctx, pairs, n, "propose");
+    if (rc) return rc;
+    for (int i0 = 0; i0 < n; i0 += kLearnChunk)
+        if ((rc = propose_chunk(ctx, net, pairs + i0, std::min(kLearnChunk, n - i0), cell, T_prop + 16 * i0)))
+            return rc;
+    return COVOX_OK;
+}
+
+int covox_train_proposal(covox_ctx *ctx, covox_net *net, const covox_train_cfg *cfg, const covox_pair *pairs,
+                         int32_t n, float *loss_host)
+{
+    if (!ctx || !net || !cfg || !pairs || n <= 0 || cfg->steps < 0 || cfg->batch < 1 || cfg->batch > kLearnChunk ||
+        !(cfg->cell > 0) || !(cfg->trans_scale > 0) || !(cfg->lr >= 0) || !(cfg->trans_xy >= 0) ||
+        !(cfg->trans_z >= 0) || !(cfg->yaw >= 0) || !(cfg->tilt >= 0))
+        return fail(ctx, COVOX_EINVAL, "train_proposal: bad argument");
+    int rc = prepare_learned(ctx, pairs, n, "train_proposal");
+    if (rc) return rc;
+    const int B = cfg->batch;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->train_y, &ctx->train_y_cap, (int64_t)B * 5, sizeof(float),
+                            "training targets")))
+        return rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->loss_hist, &ctx->loss_hist_cap, std::max(1, cfg->steps),
+                            sizeof(float), "training losses")))
+        return rc;
+    std::vector<covox_pair> items(B);
+    std::vector<float> y((size_t)5 * B);
+    std::vector<double> G((size_t)16 * B);
+    for (int32_t st = 0; st < cfg->steps; ++st) {
+        for (int b = 0; b < B; ++b) {
+            const uint64_t item = (uint64_t)st * (uint64_t)B + (uint64_t)b;
+            const int j = std::min(n - 1, (int)(draw(cfg->seed, item, 0) * n));
+            const double tx = (2 * draw(cfg->seed, item, 1) - 1) * cfg->trans_xy;
+            const double ty = (2 * draw(cfg->seed, item, 2) - 1) * cfg->trans_xy;
+            const double tz = (2 * draw(cfg->seed, item, 3) - 1) * cfg->trans_z;
+            const double yaw = (2 * draw(cfg->seed, item, 4) - 1) * cfg->yaw;
+            const double roll = (2 * draw(cfg->seed, item, 5) - 1) * cfg->tilt;
+            const double pitch = (2 * draw(cfg->seed, item, 6) - 1) * cfg->tilt;
+            // prior T_init = G C^-1 G^-1 T_gt E, E = Rx(roll) Ry(pitch) (not predicted)
+            double Gj[16], C[16], Ci[16], E[16], TE[16];
+            grid_of(pairs[j].A, Gj);
+            correction(tx, ty, tz, yaw, C);
+            rigid_inverse_h(C, Ci);
+            const double cr = cos(roll), sr = sin(roll), cp = cos(pitch), sp = sin(pitch);
+            const double Ev[16] = {cp, 0, sp, 0, sr * sp, cr, -sr * cp, 0, -cr * sp, sr, cr * cp, 0, 0, 0, 0, 1};
+            ::memcpy(E, Ev, sizeof(Ev));
+            mat_mul4(pairs[j].T_init_A_B, E, TE);
+            items[b] = pairs[j];
+            conj_mul(Gj, Ci, TE, items[b].T_init_A_B);
+            y[5 * b + 0] = (float)tx;
+            y[5 * b + 1] = (float)ty;
+            y[5 * b + 2] = (float)tz;
+            y[5 * b + 3] = (float)cos(yaw);
+            y[5 * b + 4] = (float)sin(yaw);
+        }
+        if ((rc = pair_summaries(ctx, items.data(), B, cfg->cell, G.data()))) return rc;
+        if ((rc = hip_check(ctx, hipMemcpyAsync(ctx->train_y, y.data(), sizeof(float) * 5 * B, hipMemcpyHostToDevice,
+                                                ctx->stream), "target upload")))
+            return rc;
+        if ((rc = net_train_async(net, ctx->net_in, ctx->train_y, B, (float)cfg->lr, (float)cfg->trans_scale)))
+            return rc;
+        if ((rc = hip_check(ctx, hipMemcpyAsync(ctx->loss_hist + st, net_loss_dev(net), sizeof(float),
+                                                hipMemcpyDeviceToDevice, ctx->stream), "loss copy")))
+            return rc;
+        // the host vectors are refilled next step
+        if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "train sync"))) return rc;
+    }
+    if (loss_host && cfg->steps > 0 &&
+        (rc = hip_check(ctx, hipMemcpy(loss_host, ctx->loss_hist, sizeof(float) * cfg->steps, hipMemcpyDeviceToHost),
+                        "loss history copy")))
+        return rc;
+    return COVOX_OK;
+}
+
 int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell,
                         double cost_thr, int32_t n_starts, double *T_out, double *cost, covox_align_stats *stats)
 {
     if (!ctx || !net || (!pairs && n > 0) || n < 0 || !(cell > 0) || n_starts < 1 || !T_out || !cost)
         return fail(ctx, COVOX_EINVAL, "align_learned: bad argument");
-    int rc;
-    for (int i = 0; i < n; ++i) {
-        const covox_pair &pr = pairs[i];
-        if (!rigid_pose(pr.T_init_A_B)) return fail(ctx, COVOX_EINVAL, "align_learned: T_init is not rigid");
-        if ((rc = prepare_pair(ctx, pr.A, pr.B))) return rc;
-        if (pr.B->esdf_version != pr.B->version)
-            return fail(ctx, COVOX_EINVAL, "align_learned: the ESDF of B is out of date");
-        if ((rc = extract_points(ctx, const_cast<covox_submap *>(pr.A)))) return rc;
-    }
-    const int chunk = 256;
+    int rc = prepare_learned(ctx, pairs, n, "align_learned");
+    if (rc) return rc;
     std::vector<AlignResult> res(n);
-    std::vector<float> outs((size_t)chunk * 5);
-    for (int i0 = 0; i0 < n; i0 += chunk) {
-        const int m = std::min(chunk, n - i0);
-        if ((rc = ensure_buffer(ctx, (void **)&ctx->net_in, &ctx->net_in_cap, (int64_t)m * 32768 * 4, sizeof(float),
-                                "net input")))
-            return rc;
-        if ((rc = ensure_buffer(ctx, (void **)&ctx->net_out, &ctx->net_out_cap, (int64_t)m * 5, sizeof(float),
-                                "net output")))
-            return rc;
-        std::vector<SummaryReq> rq(2 * m);
-        std::vector<double> grid((size_t)16 * m);
-        for (int k = 0; k < m; ++k) {
-            const covox_pair &pr = pairs[i0 + k];
-            double *G = &grid[16 * k];  // T_A_grid = Trans(c_A)
-            const double Gv[16] = {1, 0, 0, pr.A->pbar[0], 0, 1, 0, pr.A->pbar[1], 0, 0, 1, pr.A->pbar[2], 0, 0, 0, 1};
-            memcpy(G, Gv, sizeof(Gv));
-            double inv[16], TB[16];
-            rigid_inverse_h(pr.T_init_A_B, inv);
-            mat_mul4(inv, G, TB);
-            const double *Ts[2] = {G, TB};
-            const covox_submap *ss[2] = {pr.A, pr.B};
-            for (int side = 0; side < 2; ++side) {
-                SummaryReq &r = rq[2 * k + side];
-                r.phi = ss[side]->phi;
-                r.page = ss[side]->page;
-                r.meta = ss[side]->meta;
-                for (int a = 0; a < 3; ++a)
-                    for (int c = 0; c < 4; ++c) r.T[4 * a + c] = (float)Ts[side][4 * a + c];
-                r.cell = (float)cell;
-                r.chan = 2 * side;
-                r.out = ctx->net_in + (int64_t)k * 32768 * 4;
-            }
-        }
-        if ((rc = run_summaries(ctx, rq.data(), 2 * m))) return rc;
-        if ((rc = net_forward_api(net, ctx->net_in, m, ctx->net_out))) return rc;
-        if ((rc = hip_check(ctx, hipMemcpyAsync(outs.data(), ctx->net_out, sizeof(float) * 5 * m, hipMemcpyDeviceToHost,
-                                                ctx->stream), "net output copy")))
-            return rc;
-        if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "net sync"))) return rc;
+    std::vector<double> Tp((size_t)16 * std::min(n, kLearnChunk));
+    for (int i0 = 0; i0 < n; i0 += kLearnChunk) {
+        const int m = std::min(kLearnChunk, n - i0);
+        if ((rc = propose_chunk(ctx, net, pairs + i0, m, cell, Tp.data()))) return rc;
         std::vector<AlignProblem> prs(m);
-        for (int k = 0; k < m; ++k) {
-            const covox_pair &pr = pairs[i0 + k];
-            const float *o = &outs[5 * k];
-            const double yaw = atan2((double)o[4], (double)o[3]);
-            const double C[16] = {cos(yaw), -sin(yaw), 0, o[0], sin(yaw), cos(yaw), 0, o[1], 0, 0, 1, o[2], 0, 0, 0, 1};
-            const double *G = &grid[16 * k];
-            double Gi[16], A1[16], A2[16], Tp[16];
-            rigid_inverse_h(G, Gi);
-            mat_mul4(G, C, A1);
-            mat_mul4(A1, Gi, A2);
-            mat_mul4(A2, pr.T_init_A_B, Tp);
-            Tp[12] = 0; Tp[13] = 0; Tp[14] = 0; Tp[15] = 1;
-            prs[k] = make_problem(ctx, pr.A, pr.B, Tp, ctx->p.max_iter);
-        }
+        for (int k = 0; k < m; ++k)
+            prs[k] = make_problem(ctx, pairs[i0 + k].A, pairs[i0 + k].B, &Tp[16 * k], ctx->p.max_iter);
         if ((rc = run_alignment(ctx, prs.data(), m, res.data() + i0))) return rc;
     }
     // fallback to multi-start from the prior
@@ -766,7 +902,7 @@ int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs,
             const covox_pair &pr = pairs[fb[j]];
             for (int k = 0; k < n_starts; ++k) {
                 double S[16];
-                if (n_starts == 1) memcpy(S, pr.T_init_A_B, sizeof(S));
+                if (n_starts == 1) ::memcpy(S, pr.T_init_A_B, sizeof(S));
                 else start_pose(pr.T_init_A_B, pr.B->pbar, k, n_starts, S);
                 prs[j * n_starts + k] = make_problem(ctx, pr.A, pr.B, S, ctx->p.max_iter);
             }
@@ -783,7 +919,7 @@ int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs,
         }
     }
     for (int i = 0; i < n; ++i) {
-        memcpy(T_out + 16 * i, res[i].T, sizeof(double) * 16);
+        ::memcpy(T_out + 16 * i, res[i].T, sizeof(double) * 16);
         cost[i] = res[i].cost;
         fill_stats(stats ? stats + i : nullptr, pairs[i].B, res[i], best[i]);
     }

@@ -172,6 +172,10 @@ struct covox_ctx {
     int64_t net_in_cap = 0;
     float *net_out = nullptr;
     int64_t net_out_cap = 0;
+    float *train_y = nullptr;    // proposal training: targets and per-step losses
+    int64_t train_y_cap = 0;
+    float *loss_hist = nullptr;
+    int64_t loss_hist_cap = 0;
     // pinned host staging for small copies
     void *host_pin = nullptr;
     size_t host_pin_cap = 0;
@@ -274,6 +278,10 @@ int64_t net_num_params(const covox_net *net);
 int net_get_params(covox_net *net, float *host, int64_t n);
 int net_set_params(covox_net *net, const float *host, int64_t n);
 int net_forward_api(covox_net *net, const float *x_dev, int n, float *out_dev);
+// One training step enqueued on the context stream (no host synchronisation);
+// the step's loss is then at net_loss_dev(net).
+int net_train_async(covox_net *net, const float *x_dev, const float *y_dev, int n, float lr, float trans_scale);
+const float *net_loss_dev(const covox_net *net);
 int net_train_step(covox_net *net, const float *x_dev, const float *y_dev, int n, float lr, float trans_scale,
                    float *loss_host);
 int net_grads(covox_net *net, const float *x_dev, const float *y_dev, int n, float trans_scale, float *grad_host,

@@ -441,8 +441,24 @@ int net_forward_api(covox_net *net, const float *x_dev, int n, float *out_dev)
                                               net->ctx->stream), "net output copy");
 }
 
+const float *net_loss_dev(const covox_net *net) { return net->loss; }
+
 int net_train_step(covox_net *net, const float *x_dev, const float *y_dev, int n, float lr, float trans_scale,
                    float *loss_host)
+{
+    int rc = net_train_async(net, x_dev, y_dev, n, lr, trans_scale);
+    if (rc) return rc;
+    if (loss_host) {
+        covox_ctx *ctx = net->ctx;
+        if ((rc = hip_check(ctx, hipMemcpyAsync(loss_host, net->loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream),
+                            "loss copy")))
+            return rc;
+        return hip_check(ctx, hipStreamSynchronize(ctx->stream), "train sync");
+    }
+    return COVOX_OK;
+}
+
+int net_train_async(covox_net *net, const float *x_dev, const float *y_dev, int n, float lr, float trans_scale)
 {
     covox_ctx *ctx = net->ctx;
     int rc = net_forward(net, x_dev, n);
@@ -460,14 +476,7 @@ int net_train_step(covox_net *net, const float *x_dev, const float *y_dev, int n
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(net->P.total, 256)), dim3(256), 0, ctx->stream, net->w, net->g, net->m,
                        net->v, net->P.total, lr, b1, b2, 1e-8f, c1, c2);
     refresh_bf16(net);
-    if ((rc = hip_check(ctx, hipGetLastError(), "net train step"))) return rc;
-    if (loss_host) {
-        if ((rc = hip_check(ctx, hipMemcpyAsync(loss_host, net->loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream),
-                            "loss copy")))
-            return rc;
-        return hip_check(ctx, hipStreamSynchronize(ctx->stream), "train sync");
-    }
-    return COVOX_OK;
+    return hip_check(ctx, hipGetLastError(), "net train step");
 }
 
 int net_grads(covox_net *net, const float *x_dev, const float *y_dev, int n, float trans_scale, float *grad_host,

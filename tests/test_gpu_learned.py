@@ -192,3 +192,49 @@ def test_learned_driver_fallback_equals_multistart(cv):
         R = Ti[k][:3, :3]
         assert np.allclose(R @ R.T, np.eye(3), atol=1e-9)
     ctx.close()
+
+
+def test_propose_then_refine_equals_driver(cv):
+    """With an infinite threshold the driver's pose is the single-start
+    refinement of the network's proposal."""
+    ctx = _ctx(cv)
+    A, B, _, _ = _tiny_submaps(cv, ctx, with_oracle=False)
+    net = cv.Net(ctx, seed=4)
+    pairs = [(A, B, orc.se3_exp(np.array([0.03, -0.02, 0.0, 0.0, 0.0, 0.3]))),
+             (B, A, orc.se3_exp(np.array([-0.02, 0.01, 0.01, 0.0, 0.0, -0.2])))]
+    Tp = ctx.propose(net, pairs, 0.1)
+    for k in range(2):
+        R = Tp[k][:3, :3]
+        assert np.allclose(R @ R.T, np.eye(3), atol=1e-9) and np.allclose(Tp[k][3], [0, 0, 0, 1])
+    Tl, cl, sl = ctx.align_learned(net, pairs, 0.1, math.inf)
+    Tr, cr, sr = ctx.align_batch([(a, b, Tp[k]) for k, (a, b, _) in enumerate(pairs)], n_starts=1)
+    assert np.array_equal(Tl, Tr) and np.array_equal(cl, cr)
+    ctx.close()
+
+
+def test_training_items_use_the_ground_truth_prior(cv):
+    """With zero re-framing ranges every prior is the ground truth and every
+    target the identity correction, so a step with learning rate 0 reports
+    the loss of the summaries at T_gt against (0, 0, 0, 1, 0)."""
+    import torch
+    ctx = _ctx(cv)
+    A, B, _, _ = _tiny_submaps(cv, ctx, with_oracle=False)
+    net = cv.Net(ctx, seed=2)
+    p0 = net.get_params()
+    T_gt = np.eye(4)
+    L = ctx.train_proposal(net, [(A, B, T_gt)], steps=2, batch=3, lr=0.0, cell=0.1, trans_xy=0.0, trans_z=0.0,
+                           yaw=0.0, tilt=0.0)
+    assert np.array_equal(net.get_params(), p0)  # Adam with lr 0
+    pbar = ctx.export_points(A).astype(np.float64).mean(axis=0)
+    G = np.eye(4)
+    G[:3, 3] = pbar
+    x = torch.zeros((3, 32, 32, 32, 4), dtype=torch.float32, device="cuda")
+    for b in range(3):
+        ctx.summaries([(A, G, 0.1, x[b].view(32768, 4), 0), (B, np.linalg.inv(T_gt) @ G, 0.1, x[b].view(32768, 4), 2)])
+    y = torch.tensor([[0.0, 0.0, 0.0, 1.0, 0.0]] * 3, device="cuda")
+    loss, _ = net.gradients(x, y, 3.0)
+    assert np.allclose(L, loss, rtol=1e-4), (L, loss)
+    # non-zero ranges: the parameters move and the losses stay finite
+    L2 = ctx.train_proposal(net, [(A, B, T_gt), (B, A, T_gt)], steps=3, batch=4, lr=1e-3, cell=0.1)
+    assert np.all(np.isfinite(L2)) and not np.array_equal(net.get_params(), p0)
+    ctx.close()
