@@ -156,6 +156,24 @@ int check_status_after_sync(covox_ctx *ctx, covox_submap *s)
     return COVOX_OK;
 }
 
+// F frames in order: one frame per call through the per-frame kernels,
+// several through batches of up to kMaxBatch frames.
+int integrate_frames(covox_ctx *ctx, covox_submap *s, const float *depths, int32_t F, int32_t H, int32_t W,
+                     const float K[4], const double *T_wc)
+{
+    for (int32_t f0 = 0; f0 < F;) {
+        const int32_t n = std::min<int32_t>(kMaxBatch, F - f0);
+        bool maybe_full = false;
+        const float *d = depths + (size_t)f0 * H * W;
+        int rc = n == 1 ? integrate_frame(ctx, s, d, H, W, K, T_wc + 16 * f0, &maybe_full)
+                        : integrate_batch(ctx, s, d, n, H, W, K, T_wc + 16 * f0, &maybe_full);
+        if (rc) return rc;
+        if (maybe_full && (rc = check_status_after_sync(ctx, s))) return rc;
+        f0 += n;
+    }
+    return COVOX_OK;
+}
+
 bool rigid_pose(const double *T)
 {
     for (int k = 0; k < 16; ++k)
@@ -313,8 +331,13 @@ void covox_destroy(covox_ctx *ctx)
     for (covox_submap *s : std::vector<covox_submap *>(subs)) covox_submap_destroy(s);
     for (void *ptr : {(void *)ctx->cand, (void *)ctx->t_key, (void *)ctx->t_idx, (void *)ctx->sites, (void *)ctx->g1,
                       (void *)ctx->g2, (void *)ctx->cnt, (void *)ctx->psum, ctx->prob_dev, ctx->res_dev, ctx->sum_dev,
-                      (void *)ctx->net_in, (void *)ctx->net_out, (void *)ctx->train_y, (void *)ctx->loss_hist})
+                      (void *)ctx->net_in, (void *)ctx->net_out, (void *)ctx->train_y, (void *)ctx->loss_hist,
+                      (void *)ctx->frames_dev, (void *)ctx->blist})
         if (ptr) (void)hipFree(ptr);
+    for (int k = 0; k < 2; ++k) {
+        if (ctx->frames_pin[k]) (void)hipHostFree(ctx->frames_pin[k]);
+        if (ctx->frames_ev[k]) (void)hipEventDestroy(ctx->frames_ev[k]);
+    }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (auto &u : ctx->ev_used) {
         (void)hipEventDestroy(u.second.first);
@@ -364,6 +387,8 @@ int covox_submap_create(covox_ctx *ctx, const double T_world_submap[16], covox_s
     if (e == hipSuccess) e = hipMalloc((void **)&s->tkeys, sizeof(uint64_t) * s->tcap);
     if (e == hipSuccess) e = hipMalloc((void **)&s->tvals, sizeof(uint32_t) * s->tcap);
     if (e == hipSuccess) e = hipMalloc((void **)&s->meta, sizeof(SubmapMeta));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->pin_nb, sizeof(int64_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->nb_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         covox_submap_destroy(s);
         return fail(ctx, COVOX_EHIP, std::string("submap_create: ") + hipGetErrorString(e));
@@ -389,6 +414,9 @@ void covox_submap_destroy(covox_submap *s)
     for (void *p : {(void *)s->keys, s->D, s->W, (void *)s->phi, (void *)s->tkeys, (void *)s->tvals, (void *)s->meta,
                     (void *)s->page, (void *)s->pts})
         if (p) (void)hipFree(p);
+    if (s->stamp) (void)hipFree(s->stamp);
+    if (s->pin_nb) (void)hipHostFree(s->pin_nb);
+    if (s->nb_ev) (void)hipEventDestroy(s->nb_ev);
     delete s;
 }
 
@@ -421,24 +449,21 @@ int covox_integrate_depth_batch(covox_ctx *ctx, covox_submap *s, const float *de
                                 int32_t W, const float K[4], const double *T_world_cam)
 {
     if (!ctx || !s || !depths_dev || !T_world_cam || F < 0) return fail(ctx, COVOX_EINVAL, "integrate_batch: bad argument");
-    for (int32_t f = 0; f < F; ++f) {
-        int rc = covox_integrate_depth(ctx, s, depths_dev + (size_t)f * H * W, H, W, K, T_world_cam + 16 * f);
-        if (rc) return rc;
-    }
-    return COVOX_OK;
+    return integrate_frames(ctx, s, depths_dev, F, H, W, K, T_world_cam);
 }
 
 int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev, int32_t F, int32_t H, int32_t W,
                        const float K[4], const double *T_world_cam, int32_t esdf_every)
 {
     if (!ctx || !s || !depths_dev || !T_world_cam || F < 0) return fail(ctx, COVOX_EINVAL, "map_sequence: bad argument");
-    for (int32_t f = 0; f < F; ++f) {
-        int rc = covox_integrate_depth(ctx, s, depths_dev + (size_t)f * H * W, H, W, K, T_world_cam + 16 * f);
+    // frames between ESDF updates go through the batched integration
+    const int32_t step = esdf_every > 0 ? esdf_every : F;
+    for (int32_t f0 = 0; f0 < F; f0 += step) {
+        const int32_t n = std::min(step, F - f0);
+        int rc = integrate_frames(ctx, s, depths_dev + (size_t)f0 * H * W, n, H, W, K, T_world_cam + 16 * f0);
         if (rc) return rc;
-        if ((esdf_every > 0 && (f + 1) % esdf_every == 0) || f == F - 1) {
-            rc = update_esdf(ctx, s);
-            if (rc) return rc;
-        }
+        rc = update_esdf(ctx, s);
+        if (rc) return rc;
     }
     return COVOX_OK;
 }

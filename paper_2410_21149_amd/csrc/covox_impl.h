@@ -88,6 +88,9 @@ struct SubmapMeta {
     int64_t n_points;       // registration points
     double pbar[3];         // their centroid (binary64)
     unsigned long long n_updates;  // voxel updates since creation / reset
+    int64_t batch_n0;       // last frame batch: n_blocks before it
+    int32_t batch_frames;   // and its frames committed (a capacity failure stops the batch)
+    int32_t pad0;
 };
 
 // Per-frame projection parameters (kernel argument).
@@ -117,6 +120,12 @@ struct covox_submap {
     covox::SubmapMeta *meta = nullptr;
     // host-side upper bounds (no device round trip needed)
     int64_t nb_upper = 0;            // >= n_blocks
+    int64_t *pin_nb = nullptr;       // pinned copy of n_blocks, refreshed behind the kernels
+    hipEvent_t nb_ev = nullptr;      // completion of that copy
+    bool nb_pending = false;
+    int64_t nb_extra = 0;            // box sizes of the frames enqueued after the copy
+    uint32_t *stamp = nullptr;       // per block: id of the last frame batch that listed it
+    uint32_t batch_id = 0;
     bool bound_valid = false;        // box containing every allocated block
     int32_t bound_lo[3] = {0, 0, 0};
     int32_t bound_hi[3] = {0, 0, 0};
@@ -172,6 +181,13 @@ struct covox_ctx {
     int64_t net_in_cap = 0;
     float *net_out = nullptr;
     int64_t net_out_cap = 0;
+    covox::FrameArgs *frames_dev = nullptr;  // frame batch parameters
+    int64_t frames_cap = 0;
+    covox::FrameArgs *frames_pin[2] = {nullptr, nullptr};  // pinned staging, alternating
+    hipEvent_t frames_ev[2] = {nullptr, nullptr};          // their uploads
+    int frames_slot = 0;
+    uint32_t *blist = nullptr;        // frame batch: blocks to update
+    int64_t blist_cap = 0;
     float *train_y = nullptr;    // proposal training: targets and per-step losses
     int64_t train_y_cap = 0;
     float *loss_hist = nullptr;
@@ -225,6 +241,11 @@ void fill_u64(hipStream_t s, uint64_t *p, uint64_t v, int64_t n);
 void fill_u32(hipStream_t s, uint32_t *p, uint32_t v, int64_t n);
 
 // k_integrate.hip
+// F <= kMaxBatch frames in one probe, one scan and one update launch; the
+// result equals F integrate_frame calls bit for bit.
+constexpr int kMaxBatch = 64;
+int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_t F, int32_t H, int32_t W,
+                    const float K[4], const double *T_wc, bool *maybe_full);
 int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H, int32_t W,
                     const float K[4], const double T_wc[16], bool *maybe_full);
 

@@ -18,8 +18,10 @@
 #include "covox_impl.h"
 
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
+#include <vector>
 
 namespace covox {
 
@@ -65,10 +67,42 @@ __device__ __forceinline__ void box_block(const FrameArgs &f, int64_t j, int &bx
     bx = f.blo[0] + (int)(j / (nz * ny));
 }
 
+// The running-average update of one voxel column (8 z values of a lane) of
+// an allocated block; returns the number of updated voxels of the wave.
+template <typename S>
+__device__ __forceinline__ int update_column(S *Db, S *Wb, const float sdf[8], uint32_t okm, float tau, bool is_new)
+{
+    int n_ok = 0;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const bool ok = (okm >> z) & 1u;
+        n_ok += __popcll(__ballot(ok));
+        if (ok) {
+            const float Dv = is_new ? 0.0f : ld(Db + 64 * z);
+            const float Wv = is_new ? 0.0f : ld(Wb + 64 * z);
+            const float tr = fminf(sdf[z], tau);
+            const float Wn = Wv + 1.0f;
+            const float Dn = ((Dv * Wv) + (tr * 1.0f)) / Wn;
+            st(Db + 64 * z, Dn);
+            st(Wb + 64 * z, Wn);
+        } else if (is_new) {
+            st(Db + 64 * z, 0.0f);
+            st(Wb + 64 * z, 0.0f);
+        }
+    }
+    return n_ok;
+}
+
+// FUSED: blocks that already exist are updated here (their buffer index is
+// known), so only new blocks are left to k_integrate.  Used only when the
+// host bound proves that this frame cannot overflow the pool or the table,
+// so that no capacity failure can follow a partial update.
+template <typename S, bool FUSED>
 __global__ __launch_bounds__(256) void k_probe(FrameArgs f, float vs, float tau, float maxr,
                                                const uint64_t *__restrict__ tkeys,
                                                const uint32_t *__restrict__ tvals, uint64_t tmask,
-                                               uint32_t *__restrict__ cand, int64_t n_box)
+                                               uint32_t *__restrict__ cand, int64_t n_box, S *D, S *W,
+                                               SubmapMeta *meta)
 {
     const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
@@ -77,21 +111,23 @@ __global__ __launch_bounds__(256) void k_probe(FrameArgs f, float vs, float tau,
     box_block(f, j, bx, by, bz);
     const int ix = 8 * bx + (lane & 7);
     const int iy = 8 * by + (lane >> 3);
-    bool any = false;
+    float sdf[8];
+    uint32_t okm = 0;
 #pragma unroll
-    for (int z = 0; z < 8; ++z) {
-        float sdf;
-        any |= proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf);
-    }
-    const uint64_t m = __ballot(any);
-    if (lane == 0) {
-        uint32_t out = 0;
-        if (m) {
-            const int64_t idx = hash_find(tkeys, tvals, tmask, pack_key(bx, by, bz));
-            out = idx >= 0 ? (uint32_t)idx + 1u : kNew;
+    for (int z = 0; z < 8; ++z) okm |= (uint32_t)proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf[z]) << z;
+    const uint64_t m = __ballot(okm != 0);
+    uint32_t out = 0;
+    if (m) {
+        int64_t idx = -1;
+        if (lane == 0) idx = hash_find(tkeys, tvals, tmask, pack_key(bx, by, bz));
+        idx = __shfl(idx, 0, 64);
+        out = idx >= 0 ? (uint32_t)idx + 1u : kNew;
+        if (FUSED && idx >= 0) {
+            const int n_ok = update_column(D + idx * 512 + lane, W + idx * 512 + lane, sdf, okm, tau, false);
+            if (lane == 0) atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
         }
-        cand[j] = out;
     }
+    if (lane == 0) cand[j] = out;
 }
 
 // Exclusive scan of one int64 per thread over a 1024-thread workgroup.
@@ -200,7 +236,8 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand
     }
 }
 
-template <typename S>
+// NEW_ONLY: the probe has already updated the existing blocks (fused path).
+template <typename S, bool NEW_ONLY>
 __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float tau, float maxr,
                                                    SubmapMeta *__restrict__ meta,
                                                    const uint64_t *__restrict__ t_key,
@@ -212,9 +249,10 @@ __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float 
     const int lane = threadIdx.x & 63;
     const int64_t n_t = meta->n_touched;
     for (int64_t t = wave; t < n_t; t += nwaves) {
-        const uint64_t key = t_key[t];
         const uint32_t v = t_idx[t];
         const bool is_new = (v >> 31) != 0;
+        if (NEW_ONLY && !is_new) continue;  // uniform across the wave
+        const uint64_t key = t_key[t];
         const int64_t idx = v & 0x7FFFFFFFu;
         int bx, by, bz;
         unpack_key(key, bx, by, bz);
@@ -224,26 +262,214 @@ __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float 
         }
         const int ix = 8 * bx + (lane & 7);
         const int iy = 8 * by + (lane >> 3);
+        float sdf[8];
+        uint32_t okm = 0;
+#pragma unroll
+        for (int z = 0; z < 8; ++z) okm |= (uint32_t)proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf[z]) << z;
+        const int n_ok = update_column(D + idx * 512 + lane, W + idx * 512 + lane, sdf, okm, tau, is_new);
+        if (lane == 0) atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
+    }
+}
+
+// ------------------------------------------------------- frame batches
+// A batch of F frames takes three launches.  k_probe_batch tests every
+// frame's box blocks against the table as it was before the batch.
+// k_scan_batch walks the frames in order in one workgroup: a candidate
+// marked new that an earlier frame of the batch has created becomes
+// existing; the remaining new blocks of the frame get n_blocks + rank in
+// key order (so indices follow (first frame, key), as with per-frame calls)
+// and are activated at once; every block touched by some frame is listed
+// once.  k_integrate_batch gives each listed block one wave that applies the
+// frames in order in registers and writes D and W once.
+
+__global__ __launch_bounds__(256) void k_probe_batch(const FrameArgs *__restrict__ frames, float vs, float tau,
+                                                     float maxr, const uint64_t *__restrict__ tkeys,
+                                                     const uint32_t *__restrict__ tvals, uint64_t tmask,
+                                                     uint32_t *__restrict__ cand, int64_t stride)
+{
+    const FrameArgs f = frames[blockIdx.y];
+    const int64_t n_box = (int64_t)f.bdim[0] * f.bdim[1] * f.bdim[2];
+    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (j >= n_box) return;  // uniform across the wave
+    int bx, by, bz;
+    box_block(f, j, bx, by, bz);
+    const int ix = 8 * bx + (lane & 7);
+    const int iy = 8 * by + (lane >> 3);
+    bool any = false;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        float sdf;
+        any |= proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf);
+    }
+    const uint64_t m = __ballot(any);
+    if (lane == 0) {
+        uint32_t out = 0;
+        if (m) {
+            const int64_t idx = hash_find(tkeys, tvals, tmask, pack_key(bx, by, bz));
+            out = idx >= 0 ? (uint32_t)idx + 1u : kNew;
+        }
+        cand[(int64_t)blockIdx.y * stride + j] = out;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_batch(const FrameArgs *__restrict__ frames, int F,
+                                                     uint32_t *__restrict__ cand, int64_t stride, SubmapMeta *meta,
+                                                     int64_t cap, int64_t table_limit, uint64_t *keys,
+                                                     uint64_t *tkeys, uint32_t *tvals, uint64_t tmask,
+                                                     uint32_t *stamp, uint32_t batch_id, uint32_t *list)
+{
+    __shared__ int64_t lds[16];
+    __shared__ int32_t red[6][16];
+    const int tid = threadIdx.x;
+    const int64_t n_start = meta->n_blocks;
+    int64_t n0 = n_start, n_list = 0;
+    int committed = F;
+    int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int fi = 0; fi < F; ++fi) {
+        const FrameArgs f = frames[fi];
+        const int64_t n_box = (int64_t)f.bdim[0] * f.bdim[1] * f.bdim[2];
+        uint32_t *cf = cand + (int64_t)fi * stride;
+        const int64_t C = (n_box + blockDim.x - 1) / blockDim.x;
+        const int64_t beg = std::min<int64_t>((int64_t)tid * C, n_box);
+        const int64_t end = std::min<int64_t>(beg + C, n_box);
+        // resolve blocks created by earlier frames of the batch; count
+        int64_t nn = 0, nf = 0;
+        for (int64_t j = beg; j < end; ++j) {
+            uint32_t v = cf[j];
+            if (!v) continue;
+            if (v == kNew) {
+                int bx, by, bz;
+                box_block(f, j, bx, by, bz);
+                const int64_t idx = hash_find(tkeys, tvals, tmask, pack_key(bx, by, bz));
+                if (idx >= 0) {
+                    v = (uint32_t)idx + 1u;
+                    cf[j] = v;
+                }
+            }
+            if (v == kNew) { ++nn; ++nf; }
+            else nf += stamp[v - 1u] != batch_id;
+        }
+        int64_t tot_n, tot_f;
+        int64_t off_n = block_exclusive_scan(nn, lds, &tot_n);
+        int64_t off_f = block_exclusive_scan(nf, lds, &tot_f);
+        if (n0 + tot_n > cap || n0 + tot_n > table_limit) {  // uniform: the frame and the rest are not committed
+            if (tid == 0) meta->status = n0 + tot_n > cap ? COVOX_EPOOL_FULL : COVOX_ETABLE_FULL;
+            committed = fi;
+            break;
+        }
+        for (int64_t j = beg; j < end; ++j) {
+            const uint32_t v = cf[j];
+            if (!v) continue;
+            if (v == kNew) {
+                int bx, by, bz;
+                box_block(f, j, bx, by, bz);
+                const uint64_t key = pack_key(bx, by, bz);
+                const uint32_t idx = (uint32_t)(n0 + off_n++);
+                keys[idx] = key;
+                hash_insert(tkeys, tvals, tmask, key, idx);
+                stamp[idx] = batch_id;
+                list[n_list + off_f++] = idx;
+                lo[0] = min(lo[0], bx); lo[1] = min(lo[1], by); lo[2] = min(lo[2], bz);
+                hi[0] = max(hi[0], bx); hi[1] = max(hi[1], by); hi[2] = max(hi[2], bz);
+            } else if (stamp[v - 1u] != batch_id) {
+                stamp[v - 1u] = batch_id;
+                list[n_list + off_f++] = v - 1u;
+            }
+        }
+        n0 += tot_n;
+        n_list += tot_f;
+        // The next frame reads the table and stamps written here by other
+        // lanes (table slots through device-scope atomics): complete the
+        // writes, then drop any stale copy from this CU's vector cache.
+        __threadfence();
+        __syncthreads();
+        __threadfence();
+    }
+    const int lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
+            hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
+        }
+        if (lane == 0) { red[a][wid] = lo[a]; red[3 + a][wid] = hi[a]; }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        if (n0 > n_start) {
+            for (int a = 0; a < 3; ++a) {
+                int32_t L = INT32_MAX, Hh = INT32_MIN;
+                for (int w = 0; w < nw; ++w) { L = min(L, red[a][w]); Hh = max(Hh, red[3 + a][w]); }
+                if (n_start == 0) { meta->bmin[a] = L; meta->bmax[a] = Hh; }
+                else { meta->bmin[a] = min(meta->bmin[a], L); meta->bmax[a] = max(meta->bmax[a], Hh); }
+            }
+        }
+        meta->n_blocks = n0;
+        meta->n_new = (int32_t)(n0 - n_start);
+        meta->n_touched = (int32_t)n_list;
+        meta->batch_n0 = n_start;
+        meta->batch_frames = committed;
+    }
+}
+
+// Storage rounding of a value kept in registers across frames, so that the
+// batch matches per-frame calls that store after every frame.
+template <typename S> __device__ __forceinline__ float stored(float v);
+template <> __device__ __forceinline__ float stored<float>(float v) { return v; }
+template <> __device__ __forceinline__ float stored<__half>(float v) { return __half2float(__float2half_rn(v)); }
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_integrate_batch(const FrameArgs *__restrict__ frames,
+                                                         SubmapMeta *__restrict__ meta,
+                                                         const uint32_t *__restrict__ list,
+                                                         const uint64_t *__restrict__ keys, S *D, S *W, float vs,
+                                                         float tau, float maxr)
+{
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t n_t = meta->n_touched, n0 = meta->batch_n0;
+    const int F = meta->batch_frames;
+    for (int64_t t = wave; t < n_t; t += nwaves) {
+        const int64_t idx = list[t];
+        const bool is_new = idx >= n0;
+        int bx, by, bz;
+        unpack_key(keys[idx], bx, by, bz);
+        const int ix = 8 * bx + (lane & 7);
+        const int iy = 8 * by + (lane >> 3);
         S *Db = D + idx * 512 + lane;
         S *Wb = W + idx * 512 + lane;
-        int n_ok = 0;
+        float dv[8], wv[8];
 #pragma unroll
         for (int z = 0; z < 8; ++z) {
-            float sdf;
-            const bool ok = proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf);
-            n_ok += __popcll(__ballot(ok));
-            if (ok) {
-                const float Dv = is_new ? 0.0f : ld(Db + 64 * z);
-                const float Wv = is_new ? 0.0f : ld(Wb + 64 * z);
-                const float tr = fminf(sdf, tau);
-                const float Wn = Wv + 1.0f;
-                const float Dn = ((Dv * Wv) + (tr * 1.0f)) / Wn;
-                st(Db + 64 * z, Dn);
-                st(Wb + 64 * z, Wn);
-            } else if (is_new) {
-                st(Db + 64 * z, 0.0f);
-                st(Wb + 64 * z, 0.0f);
+            dv[z] = is_new ? 0.0f : ld(Db + 64 * z);
+            wv[z] = is_new ? 0.0f : ld(Wb + 64 * z);
+        }
+        int n_ok = 0;
+        for (int fi = 0; fi < F; ++fi) {
+            const FrameArgs &f = frames[fi];
+            if (bx < f.blo[0] || bx >= f.blo[0] + f.bdim[0] || by < f.blo[1] || by >= f.blo[1] + f.bdim[1] ||
+                bz < f.blo[2] || bz >= f.blo[2] + f.bdim[2])
+                continue;  // outside the frame's box: no valid voxel
+#pragma unroll
+            for (int z = 0; z < 8; ++z) {
+                float sdf;
+                const bool ok = proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf);
+                n_ok += __popcll(__ballot(ok));
+                if (ok) {
+                    const float tr = fminf(sdf, tau);
+                    const float Wn = wv[z] + 1.0f;
+                    const float Dn = ((dv[z] * wv[z]) + (tr * 1.0f)) / Wn;
+                    dv[z] = stored<S>(Dn);
+                    wv[z] = stored<S>(Wn);
+                }
             }
+        }
+#pragma unroll
+        for (int z = 0; z < 8; ++z) {
+            st(Db + 64 * z, dv[z]);
+            st(Wb + 64 * z, wv[z]);
         }
         if (lane == 0) atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
     }
@@ -289,10 +515,69 @@ bool is_rigid(const double *T)
     return e <= 1e-6 && det > 0;
 }
 
+template <typename S>
+void launch_frame(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, float vs, float tau, float maxr, uint64_t tmask,
+                  int64_t table_limit, int64_t n_box, unsigned grid, bool fused)
+{
+    S *D = (S *)s->D, *W = (S *)s->W;
+    {
+        TimedLaunch tl(ctx, COVOX_K_PROBE);
+        if (fused)
+            hipLaunchKernelGGL((k_probe<S, true>), dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau, maxr, s->tkeys,
+                               s->tvals, tmask, ctx->cand, n_box, D, W, s->meta);
+        else
+            hipLaunchKernelGGL((k_probe<S, false>), dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau, maxr, s->tkeys,
+                               s->tvals, tmask, ctx->cand, n_box, D, W, s->meta);
+    }
+    {
+        TimedLaunch tl(ctx, COVOX_K_SCAN);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, ctx->stream, ctx->cand, n_box, f, s->meta, s->cap,
+                           table_limit, ctx->t_key, ctx->t_idx);
+    }
+    {
+        TimedLaunch tl(ctx, COVOX_K_INTEGRATE);
+        if (fused)
+            hipLaunchKernelGGL((k_integrate<S, true>), dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau, maxr, s->meta,
+                               ctx->t_key, ctx->t_idx, s->keys, D, W, s->tkeys, s->tvals, tmask);
+        else
+            hipLaunchKernelGGL((k_integrate<S, false>), dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau, maxr,
+                               s->meta, ctx->t_key, ctx->t_idx, s->keys, D, W, s->tkeys, s->tvals, tmask);
+    }
+}
+
+// Tightens the host's upper bound on the block count without stalling: the
+// block count is copied to pinned memory behind the frame's kernels, and
+// once that copy has completed the bound becomes that count plus the box
+// sizes of the frames enqueued after it.  A new copy is issued when the
+// bound passes a quarter of the limit.
+void refresh_block_bound(covox_ctx *ctx, covox_submap *s, int64_t n_box, int64_t limit)
+{
+    if (!s->pin_nb) return;
+    if (s->nb_pending) {
+        s->nb_extra += n_box;  // this frame's kernels follow the copy
+        if (hipEventQuery(s->nb_ev) == hipSuccess) {
+            s->nb_upper = std::min(s->nb_upper, *s->pin_nb + s->nb_extra);
+            s->nb_pending = false;
+        }
+    }
+    if (!s->nb_pending && s->nb_upper > limit / 4) {
+        if (hipMemcpyAsync(s->pin_nb, &s->meta->n_blocks, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream) !=
+                hipSuccess ||
+            hipEventRecord(s->nb_ev, ctx->stream) != hipSuccess)
+            return;  // the bound stays valid without the refresh
+        s->nb_pending = true;
+        s->nb_extra = 0;
+    }
+}
+
 }  // namespace
 
-int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H, int32_t W,
-                    const float K[4], const double T_wc[16], bool *maybe_full)
+namespace {
+
+// Frame parameters (pose rounded once from binary64) and the block box of
+// the frustum.
+int prepare_frame(covox_ctx *ctx, const covox_submap *s, const float *depth, int32_t H, int32_t W, const float K[4],
+                  const double T_wc[16], FrameArgs &f, int64_t &n_box)
 {
     const covox_params &p = ctx->p;
     if (!depth || H <= 0 || W <= 0 || !K || !T_wc) return fail(ctx, COVOX_EINVAL, "integrate: bad argument");
@@ -304,7 +589,6 @@ int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t
     double inv_wc[16], T_cs[16];
     rigid_inverse(T_wc, inv_wc);
     rigid_mul(inv_wc, s->T_ws, T_cs);
-    FrameArgs f;
     for (int r = 0; r < 3; ++r) {
         for (int c = 0; c < 3; ++c) f.R[3 * r + c] = (float)T_cs[4 * r + c];
         f.t[r] = (float)T_cs[4 * r + 3];
@@ -333,7 +617,7 @@ int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t
                 mx[a] = std::max(mx[a], w);
             }
         }
-    int64_t n_box = 1;
+    n_box = 1;
     for (int a = 0; a < 3; ++a) {
         const int64_t ilo = (int64_t)std::floor(mn[a] / p.voxel_size - 0.5) - 1;
         const int64_t ihi = (int64_t)std::ceil(mx[a] / p.voxel_size - 0.5) + 1;
@@ -345,8 +629,31 @@ int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t
         f.bdim[a] = (int32_t)(bhi - blo + 1);
         n_box *= f.bdim[a];
     }
+    return COVOX_OK;
+}
 
-    int rc;
+// Host bounds after frames with the given boxes were enqueued.
+void grow_bounds(covox_submap *s, const FrameArgs &f)
+{
+    for (int a = 0; a < 3; ++a) {
+        const int32_t lo = f.blo[a], hi = f.blo[a] + f.bdim[a] - 1;
+        if (!s->bound_valid) { s->bound_lo[a] = lo; s->bound_hi[a] = hi; }
+        else { s->bound_lo[a] = std::min(s->bound_lo[a], lo); s->bound_hi[a] = std::max(s->bound_hi[a], hi); }
+    }
+    s->bound_valid = true;
+}
+
+}  // namespace
+
+int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H, int32_t W,
+                    const float K[4], const double T_wc[16], bool *maybe_full)
+{
+    const covox_params &p = ctx->p;
+    FrameArgs f;
+    int64_t n_box = 0;
+    int rc = prepare_frame(ctx, s, depth, H, W, K, T_wc, f, n_box);
+    if (rc) return rc;
+    const double tau = p.trunc_vox * p.voxel_size;
     if ((rc = ensure_buffer(ctx, (void **)&ctx->cand, &ctx->cand_cap, n_box, sizeof(uint32_t), "candidates")))
         return rc;
     if ((rc = ensure_buffer(ctx, (void **)&ctx->t_key, &ctx->t_key_cap, n_box, sizeof(uint64_t), "touched keys")))
@@ -358,37 +665,108 @@ int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t
     const uint64_t tmask = (uint64_t)s->tcap - 1;
     const int64_t table_limit = (int64_t)(0.85 * (double)s->tcap);
     const unsigned grid = (unsigned)((n_box + 3) / 4);
-    {
-        TimedLaunch tl(ctx, COVOX_K_PROBE);
-        hipLaunchKernelGGL(k_probe, dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau_f, maxr, s->tkeys, s->tvals,
-                           tmask, ctx->cand, n_box);
-    }
-    {
-        TimedLaunch tl(ctx, COVOX_K_SCAN);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, ctx->stream, ctx->cand, n_box, f, s->meta, s->cap,
-                           table_limit, ctx->t_key, ctx->t_idx);
-    }
-    {
-        TimedLaunch tl(ctx, COVOX_K_INTEGRATE);
-        if (p.precision == COVOX_FP16)
-            hipLaunchKernelGGL(k_integrate<__half>, dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau_f, maxr,
-                               s->meta, ctx->t_key, ctx->t_idx, s->keys, (__half *)s->D, (__half *)s->W,
-                               s->tkeys, s->tvals, tmask);
-        else
-            hipLaunchKernelGGL(k_integrate<float>, dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau_f, maxr,
-                               s->meta, ctx->t_key, ctx->t_idx, s->keys, (float *)s->D, (float *)s->W, s->tkeys,
-                               s->tvals, tmask);
-    }
+    // Existing blocks are updated by the probe when no capacity failure is
+    // possible for this frame (every box block new would still fit).
+    const bool fused = s->nb_upper + n_box <= std::min<int64_t>(s->cap, table_limit);
+    if (p.precision == COVOX_FP16)
+        launch_frame<__half>(ctx, s, f, vs, tau_f, maxr, tmask, table_limit, n_box, grid, fused);
+    else
+        launch_frame<float>(ctx, s, f, vs, tau_f, maxr, tmask, table_limit, n_box, grid, fused);
     if ((rc = hip_check(ctx, hipGetLastError(), "integrate launch"))) return rc;
 
     // host-side bounds
     s->nb_upper += n_box;
-    for (int a = 0; a < 3; ++a) {
-        const int32_t lo = f.blo[a], hi = f.blo[a] + f.bdim[a] - 1;
-        if (!s->bound_valid) { s->bound_lo[a] = lo; s->bound_hi[a] = hi; }
-        else { s->bound_lo[a] = std::min(s->bound_lo[a], lo); s->bound_hi[a] = std::max(s->bound_hi[a], hi); }
+    refresh_block_bound(ctx, s, n_box, std::min<int64_t>(s->cap, table_limit));
+    grow_bounds(s, f);
+    s->version++;
+    *maybe_full = s->nb_upper > s->cap || s->nb_upper > table_limit;
+    return COVOX_OK;
+}
+
+int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_t F, int32_t H, int32_t W,
+                    const float K[4], const double *T_wc, bool *maybe_full)
+{
+    if (F <= 0) return COVOX_OK;
+    if (F > kMaxBatch) return fail(ctx, COVOX_EINVAL, "integrate_batch: too many frames in one batch");
+    const covox_params &p = ctx->p;
+    std::vector<FrameArgs> fr(F);
+    int64_t box_max = 0, box_sum = 0;
+    for (int32_t i = 0; i < F; ++i) {
+        int64_t n_box = 0;
+        int rc = prepare_frame(ctx, s, depths + (size_t)i * H * W, H, W, K, T_wc + 16 * i, fr[i], n_box);
+        if (rc) return rc;
+        box_max = std::max(box_max, n_box);
+        box_sum += n_box;
     }
-    s->bound_valid = true;
+    int rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->frames_dev, &ctx->frames_cap, kMaxBatch, sizeof(FrameArgs),
+                            "frame batch")))
+        return rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->cand, &ctx->cand_cap, box_max * F, sizeof(uint32_t), "candidates")))
+        return rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->blist, &ctx->blist_cap, std::max<int64_t>(1, s->cap),
+                            sizeof(uint32_t), "batch block list")))
+        return rc;
+    if (!s->stamp) {
+        if ((rc = hip_check(ctx, hipMalloc((void **)&s->stamp, sizeof(uint32_t) * std::max<int64_t>(1, s->cap)),
+                            "batch stamps")))
+            return rc;
+        fill_u32(ctx->stream, s->stamp, 0u, std::max<int64_t>(1, s->cap));
+        s->batch_id = 0;
+    }
+    if (++s->batch_id == 0) {  // wrapped: clear the stamps
+        fill_u32(ctx->stream, s->stamp, 0u, std::max<int64_t>(1, s->cap));
+        s->batch_id = 1;
+    }
+    // Upload through pinned staging: slot k is reused only once its previous
+    // upload has completed.
+    const int slot = ctx->frames_slot;
+    ctx->frames_slot ^= 1;
+    if (!ctx->frames_pin[slot]) {
+        if ((rc = hip_check(ctx, hipHostMalloc((void **)&ctx->frames_pin[slot], sizeof(FrameArgs) * kMaxBatch,
+                                               hipHostMallocDefault), "frame staging")))
+            return rc;
+        if ((rc = hip_check(ctx, hipEventCreateWithFlags(&ctx->frames_ev[slot], hipEventDisableTiming),
+                            "frame staging event")))
+            return rc;
+    } else if ((rc = hip_check(ctx, hipEventSynchronize(ctx->frames_ev[slot]), "frame staging wait"))) {
+        return rc;
+    }
+    ::memcpy(ctx->frames_pin[slot], fr.data(), sizeof(FrameArgs) * F);
+    if ((rc = hip_check(ctx, hipMemcpyAsync(ctx->frames_dev, ctx->frames_pin[slot], sizeof(FrameArgs) * F,
+                                            hipMemcpyHostToDevice, ctx->stream), "frame batch upload")))
+        return rc;
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->frames_ev[slot], ctx->stream), "frame staging record"))) return rc;
+    const float vs = (float)p.voxel_size, tau_f = (float)(p.trunc_vox * p.voxel_size), maxr = (float)p.max_range;
+    const uint64_t tmask = (uint64_t)s->tcap - 1;
+    const int64_t table_limit = (int64_t)(0.85 * (double)s->tcap);
+    {
+        TimedLaunch tl(ctx, COVOX_K_PROBE);
+        hipLaunchKernelGGL(k_probe_batch, dim3((unsigned)((box_max + 3) / 4), (unsigned)F), dim3(256), 0, ctx->stream,
+                           ctx->frames_dev, vs, tau_f, maxr, s->tkeys, s->tvals, tmask, ctx->cand, box_max);
+    }
+    {
+        TimedLaunch tl(ctx, COVOX_K_SCAN);
+        hipLaunchKernelGGL(k_scan_batch, dim3(1), dim3(1024), 0, ctx->stream, ctx->frames_dev, F, ctx->cand, box_max,
+                           s->meta, s->cap, table_limit, s->keys, s->tkeys, s->tvals, tmask, s->stamp, s->batch_id,
+                           ctx->blist);
+    }
+    {
+        // one wave per listed block (at most min(capacity, sum of the boxes))
+        const int64_t waves = std::max<int64_t>(1, std::min(s->cap, s->nb_upper + box_sum));
+        const unsigned grid = (unsigned)std::min<int64_t>((waves + 3) / 4, 1 << 20);
+        TimedLaunch tl(ctx, COVOX_K_INTEGRATE);
+        if (p.precision == COVOX_FP16)
+            hipLaunchKernelGGL(k_integrate_batch<__half>, dim3(grid), dim3(256), 0, ctx->stream, ctx->frames_dev,
+                               s->meta, ctx->blist, s->keys, (__half *)s->D, (__half *)s->W, vs, tau_f, maxr);
+        else
+            hipLaunchKernelGGL(k_integrate_batch<float>, dim3(grid), dim3(256), 0, ctx->stream, ctx->frames_dev,
+                               s->meta, ctx->blist, s->keys, (float *)s->D, (float *)s->W, vs, tau_f, maxr);
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "integrate batch launch"))) return rc;
+    s->nb_upper += box_sum;
+    refresh_block_bound(ctx, s, box_sum, std::min<int64_t>(s->cap, table_limit));
+    for (int32_t i = 0; i < F; ++i) grow_bounds(s, fr[i]);
     s->version++;
     *maybe_full = s->nb_upper > s->cap || s->nb_upper > table_limit;
     return COVOX_OK;

@@ -145,6 +145,65 @@ def test_batch_integration_equals_sequential(cv):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_batched_integration_matches_checker_and_single_frames(cv, precision):
+    """Frame batches (one probe, one scan and one update launch per batch)
+    against per-frame calls and the checker: blocks in (first frame, key)
+    order, D and W bit for bit, also in binary16 storage where every frame's
+    result is rounded to the stored precision."""
+    import torch
+    w = sg.tiny()
+    fr = w.frames()
+    dev = torch.from_numpy(fr).cuda()
+    fp16 = precision == "fp16"
+    ctx = _ctx(cv, precision=cv.FP16 if fp16 else cv.FP32)
+    a, b = ctx.submap_create(), ctx.submap_create()
+    for f in range(w.n_frames):
+        ctx.integrate_depth(a, dev[f], w.cam.K, w.poses[f])
+    # uneven batches: 7, 1, 12 frames
+    ctx.integrate_depth_batch(b, dev[:7], w.cam.K, w.poses[:7])
+    ctx.integrate_depth_batch(b, dev[7:8], w.cam.K, w.poses[7:8])
+    ctx.integrate_depth_batch(b, dev[8:], w.cam.K, w.poses[8:])
+    ea, eb = ctx.export_blocks(a), ctx.export_blocks(b)
+    for k in ("keys", "home", "D", "W"):
+        assert np.array_equal(ea[k], eb[k]), k
+    assert ctx.submap_info(a)["n_updates"] == ctx.submap_info(b)["n_updates"]
+    ref = orc.Submap(_oracle_params(fp16=fp16))
+    for f in range(w.n_frames):
+        ref.integrate(fr[f], w.cam.K, w.poses[f])
+    nd, nw = _compare_blocks(eb, ref.export(), ctx.submap_info(b)["table_capacity"], fp16)
+    assert nd == 0 and nw == 0
+    ctx.close()
+
+
+def test_batch_stops_at_the_frame_that_overflows(cv):
+    """A batch whose k-th frame needs more blocks than remain commits frames
+    0..k-1 exactly as single calls would, drops the rest and reports
+    EPOOL_FULL."""
+    import torch
+    w = sg.tiny()
+    fr = w.frames(0, 12)
+    dev = torch.from_numpy(fr).cuda()
+    ref = orc.Submap(_oracle_params())
+    n_after = []
+    for f in range(12):
+        ref.integrate(fr[f], w.cam.K, w.poses[f])
+        n_after.append(len(ref.export()["keys"]))
+    k = next(i for i in range(12) if n_after[i] > n_after[0])  # first frame that allocates more
+    cap = n_after[k] - 1
+    ctx = _ctx(cv, block_capacity=cap)
+    a, b = ctx.submap_create(), ctx.submap_create()
+    for f in range(k):
+        ctx.integrate_depth(a, dev[f], w.cam.K, w.poses[f])
+    with pytest.raises(cv.CovoxError) as e:
+        ctx.integrate_depth_batch(b, dev, w.cam.K, w.poses[:12])
+    assert e.value.code == cv.EPOOL_FULL
+    ea, eb = ctx.export_blocks(a), ctx.export_blocks(b)
+    for key in ("keys", "D", "W"):
+        assert np.array_equal(ea[key], eb[key]), key
+    ctx.close()
+
+
 def test_empty_and_invalid_frames(cv):
     import torch
     K = np.array([11.0, 12.5, 7.37, 5.61], np.float32)
