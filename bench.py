@@ -404,7 +404,7 @@ def main():
     dev = torch.from_numpy(frames).cuda()
     prec = cv.FP16 if args.precision == "fp16" else cv.FP32
     ctx = cv.Context(voxel_size=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max,
-                     block_capacity=16384, precision=prec)
+                     block_capacity=131072, precision=prec)
     s = ctx.submap_create()
     K = w.cam.K
 

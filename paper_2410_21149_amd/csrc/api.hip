@@ -387,8 +387,11 @@ int covox_submap_create(covox_ctx *ctx, const double T_world_submap[16], covox_s
     if (e == hipSuccess) e = hipMalloc((void **)&s->tkeys, sizeof(uint64_t) * s->tcap);
     if (e == hipSuccess) e = hipMalloc((void **)&s->tvals, sizeof(uint32_t) * s->tcap);
     if (e == hipSuccess) e = hipMalloc((void **)&s->meta, sizeof(SubmapMeta));
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->pin_nb, sizeof(int64_t), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->nb_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->pin_nb, sizeof(uint64_t), hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+        *s->pin_nb = 0;
+        e = hipHostGetDevicePointer((void **)&s->pin_nb_dev, (void *)s->pin_nb, 0);
+    }
     if (e != hipSuccess) {
         covox_submap_destroy(s);
         return fail(ctx, COVOX_EHIP, std::string("submap_create: ") + hipGetErrorString(e));
@@ -415,8 +418,7 @@ void covox_submap_destroy(covox_submap *s)
                     (void *)s->page, (void *)s->pts})
         if (p) (void)hipFree(p);
     if (s->stamp) (void)hipFree(s->stamp);
-    if (s->pin_nb) (void)hipHostFree(s->pin_nb);
-    if (s->nb_ev) (void)hipEventDestroy(s->nb_ev);
+    if (s->pin_nb) (void)hipHostFree((void *)s->pin_nb);
     delete s;
 }
 

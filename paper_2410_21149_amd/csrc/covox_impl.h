@@ -102,6 +102,13 @@ struct FrameArgs {
     int32_t blo[3];    // frustum block box origin
     int32_t bdim[3];   // and extent (z fastest in the linear order)
     const float *depth;
+    // Conservative block cull (camera frame): unit normals of the four side
+    // planes of the image widened by one pixel, the far limit max_range +
+    // tau, and the radius of a block's voxel centres about its centre
+    // (inflated against rounding).
+    float plane[4][3];
+    float zfar;
+    float cull_r;
 };
 
 }  // namespace covox
@@ -120,10 +127,14 @@ struct covox_submap {
     covox::SubmapMeta *meta = nullptr;
     // host-side upper bounds (no device round trip needed)
     int64_t nb_upper = 0;            // >= n_blocks
-    int64_t *pin_nb = nullptr;       // pinned copy of n_blocks, refreshed behind the kernels
-    hipEvent_t nb_ev = nullptr;      // completion of that copy
-    bool nb_pending = false;
-    int64_t nb_extra = 0;            // box sizes of the frames enqueued after the copy
+    // The scan kernels store (sequence << 40) | n_blocks into pinned host
+    // memory after each integration call; with the box sizes of the calls
+    // enqueued since, it tightens nb_upper without a device round trip.
+    volatile uint64_t *pin_nb = nullptr;
+    uint64_t *pin_nb_dev = nullptr;  // its device address
+    uint64_t seq = 0;                // integration calls enqueued
+    static constexpr int kSeqRing = 256;
+    int64_t box_ring[kSeqRing] = {};  // box sizes of the last calls, by sequence
     uint32_t *stamp = nullptr;       // per block: id of the last frame batch that listed it
     uint32_t batch_id = 0;
     bool bound_valid = false;        // box containing every allocated block

@@ -560,7 +560,14 @@ __global__ __launch_bounds__(64) void k_edt_z_env(const JobList<NJ> jl, const ui
     }
 }
 
-unsigned clamp_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 65536)); }
+// Every ESDF kernel loops over its work items with a grid stride, so the
+// grid only needs to fill the chip: the host's bounds on the dense domain
+// and the block count are loose, and surplus workgroups would each pay
+// their dispatch and set-up for nothing.  2048 workgroups of up to 512
+// lanes keep 256 CUs busy.
+unsigned clamp_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 2048)); }
+// Single-wave workgroups (per-line envelopes): up to 64 waves per CU.
+unsigned clamp_grid_w(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 16384)); }
 
 int64_t bound_blocks(const covox_submap *s)
 {
@@ -649,7 +656,7 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt)
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Y);
         if (envelope)
-            hipLaunchKernelGGL((k_edt_y_env<NJ>), dim3(clamp_grid(cy)), dim3(64), 0, ctx->stream, jl, ctx->g1, ctx->g2,
+            hipLaunchKernelGGL((k_edt_y_env<NJ>), dim3(clamp_grid_w(cy)), dim3(64), 0, ctx->stream, jl, ctx->g1, ctx->g2,
                                R, HB);
         else
             hipLaunchKernelGGL((k_edt_y_vox<NJ>), dim3(clamp_grid(nd)), dim3(512), 0, ctx->stream, jl, ctx->g1,
@@ -658,10 +665,10 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt)
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Z);
         if (envelope && h)
-            hipLaunchKernelGGL((k_edt_z_env<__half, NJ>), dim3(clamp_grid(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2,
+            hipLaunchKernelGGL((k_edt_z_env<__half, NJ>), dim3(clamp_grid_w(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2,
                                R, HB, vs, tau, dmax);
         else if (envelope)
-            hipLaunchKernelGGL((k_edt_z_env<float, NJ>), dim3(clamp_grid(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2,
+            hipLaunchKernelGGL((k_edt_z_env<float, NJ>), dim3(clamp_grid_w(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2,
                                R, HB, vs, tau, dmax);
         else if (h)
             hipLaunchKernelGGL((k_edt_z_vox<__half, NJ>), dim3(clamp_grid(nb)), dim3(512), 0, ctx->stream, jl,

@@ -59,6 +59,23 @@ __device__ __forceinline__ bool proj_valid(const FrameArgs &f, float vs, float t
     return sdf >= -tau;
 }
 
+// False only if no voxel centre of block (bx, by, bz) can pass the validity
+// test in this frame: the sphere holding the centres lies behind the
+// camera, beyond the far limit, or outside a side plane of the image.
+__device__ __forceinline__ bool block_may_be_visible(const FrameArgs &f, float vs, int bx, int by, int bz)
+{
+    const float cx = (float)(8 * bx + 4) * vs, cy = (float)(8 * by + 4) * vs, cz = (float)(8 * bz + 4) * vs;
+    const float px = ((f.R[0] * cx + f.R[1] * cy) + f.R[2] * cz) + f.t[0];
+    const float py = ((f.R[3] * cx + f.R[4] * cy) + f.R[5] * cz) + f.t[1];
+    const float pz = ((f.R[6] * cx + f.R[7] * cy) + f.R[8] * cz) + f.t[2];
+    const float r = f.cull_r;
+    if (pz < -r || pz > f.zfar + r) return false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (f.plane[k][0] * px + f.plane[k][1] * py + f.plane[k][2] * pz < -r) return false;
+    return true;
+}
+
 __device__ __forceinline__ void box_block(const FrameArgs &f, int64_t j, int &bx, int &by, int &bz)
 {
     const int64_t nz = f.bdim[2], ny = f.bdim[1];
@@ -109,6 +126,10 @@ __global__ __launch_bounds__(256) void k_probe(FrameArgs f, float vs, float tau,
     if (j >= n_box) return;  // uniform across the wave
     int bx, by, bz;
     box_block(f, j, bx, by, bz);
+    if (!block_may_be_visible(f, vs, bx, by, bz)) {  // uniform across the wave
+        if (lane == 0) cand[j] = 0;
+        return;
+    }
     const int ix = 8 * bx + (lane & 7);
     const int iy = 8 * by + (lane >> 3);
     float sdf[8];
@@ -158,9 +179,16 @@ __device__ int64_t block_exclusive_scan(int64_t v, int64_t *lds, int64_t *total)
     return before;
 }
 
+// Block count and call sequence for the host's bound (pinned host memory).
+__device__ __forceinline__ void publish_count(uint64_t *host_nb, uint64_t seq, int64_t n_blocks)
+{
+    *(volatile uint64_t *)host_nb = ((seq & 0xFFFFFFull) << 40) | (uint64_t)n_blocks;
+}
+
 __global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand, int64_t n_box, FrameArgs f,
                                                SubmapMeta *meta, int64_t cap, int64_t table_limit,
-                                               uint64_t *__restrict__ t_key, uint32_t *__restrict__ t_idx)
+                                               uint64_t *__restrict__ t_key, uint32_t *__restrict__ t_idx,
+                                               uint64_t *host_nb, uint64_t seq)
 {
     __shared__ int64_t lds[16];
     __shared__ int32_t red[6][16];
@@ -186,6 +214,7 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand
             meta->status = pool_full ? COVOX_EPOOL_FULL : COVOX_ETABLE_FULL;
             meta->n_new = 0;
             meta->n_touched = 0;
+            publish_count(host_nb, seq, n0);
         }
         return;
     }
@@ -233,6 +262,7 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand
         meta->n_blocks = n0 + tot_n;
         meta->n_new = (int32_t)tot_n;
         meta->n_touched = (int32_t)tot_t;
+        publish_count(host_nb, seq, n0 + tot_n);
     }
 }
 
@@ -294,6 +324,10 @@ __global__ __launch_bounds__(256) void k_probe_batch(const FrameArgs *__restrict
     if (j >= n_box) return;  // uniform across the wave
     int bx, by, bz;
     box_block(f, j, bx, by, bz);
+    if (!block_may_be_visible(f, vs, bx, by, bz)) {  // uniform across the wave
+        if (lane == 0) cand[(int64_t)blockIdx.y * stride + j] = 0;
+        return;
+    }
     const int ix = 8 * bx + (lane & 7);
     const int iy = 8 * by + (lane >> 3);
     bool any = false;
@@ -317,7 +351,8 @@ __global__ __launch_bounds__(1024) void k_scan_batch(const FrameArgs *__restrict
                                                      uint32_t *__restrict__ cand, int64_t stride, SubmapMeta *meta,
                                                      int64_t cap, int64_t table_limit, uint64_t *keys,
                                                      uint64_t *tkeys, uint32_t *tvals, uint64_t tmask,
-                                                     uint32_t *stamp, uint32_t batch_id, uint32_t *list)
+                                                     uint32_t *stamp, uint32_t batch_id, uint32_t *list,
+                                                     uint64_t *host_nb, uint64_t seq)
 {
     __shared__ int64_t lds[16];
     __shared__ int32_t red[6][16];
@@ -410,6 +445,7 @@ __global__ __launch_bounds__(1024) void k_scan_batch(const FrameArgs *__restrict
         meta->n_touched = (int32_t)n_list;
         meta->batch_n0 = n_start;
         meta->batch_frames = committed;
+        publish_count(host_nb, seq, n0);
     }
 }
 
@@ -450,8 +486,8 @@ __global__ __launch_bounds__(256) void k_integrate_batch(const FrameArgs *__rest
         for (int fi = 0; fi < F; ++fi) {
             const FrameArgs &f = frames[fi];
             if (bx < f.blo[0] || bx >= f.blo[0] + f.bdim[0] || by < f.blo[1] || by >= f.blo[1] + f.bdim[1] ||
-                bz < f.blo[2] || bz >= f.blo[2] + f.bdim[2])
-                continue;  // outside the frame's box: no valid voxel
+                bz < f.blo[2] || bz >= f.blo[2] + f.bdim[2] || !block_may_be_visible(f, vs, bx, by, bz))
+                continue;  // no valid voxel in this frame
 #pragma unroll
             for (int z = 0; z < 8; ++z) {
                 float sdf;
@@ -532,7 +568,7 @@ void launch_frame(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, float vs,
     {
         TimedLaunch tl(ctx, COVOX_K_SCAN);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, ctx->stream, ctx->cand, n_box, f, s->meta, s->cap,
-                           table_limit, ctx->t_key, ctx->t_idx);
+                           table_limit, ctx->t_key, ctx->t_idx, s->pin_nb_dev, s->seq);
     }
     {
         TimedLaunch tl(ctx, COVOX_K_INTEGRATE);
@@ -546,28 +582,20 @@ void launch_frame(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, float vs,
 }
 
 // Tightens the host's upper bound on the block count without stalling: the
-// block count is copied to pinned memory behind the frame's kernels, and
-// once that copy has completed the bound becomes that count plus the box
-// sizes of the frames enqueued after it.  A new copy is issued when the
-// bound passes a quarter of the limit.
-void refresh_block_bound(covox_ctx *ctx, covox_submap *s, int64_t n_box, int64_t limit)
+// count the scan kernel of call q last published, plus the box sizes of the
+// calls enqueued after q.  Then registers the next call with its box size.
+void refresh_block_bound(covox_submap *s, int64_t next_box)
 {
-    if (!s->pin_nb) return;
-    if (s->nb_pending) {
-        s->nb_extra += n_box;  // this frame's kernels follow the copy
-        if (hipEventQuery(s->nb_ev) == hipSuccess) {
-            s->nb_upper = std::min(s->nb_upper, *s->pin_nb + s->nb_extra);
-            s->nb_pending = false;
-        }
+    const uint64_t v = *s->pin_nb;
+    const uint64_t q = v >> 40, cnt = v & ((1ull << 40) - 1);
+    const uint64_t behind = (s->seq - q) & 0xFFFFFFull;  // calls enqueued after q
+    if (behind < (uint64_t)covox_submap::kSeqRing && behind <= s->seq) {
+        int64_t b = (int64_t)cnt;
+        for (uint64_t k = s->seq - behind + 1; k <= s->seq; ++k) b += s->box_ring[k % covox_submap::kSeqRing];
+        s->nb_upper = std::min(s->nb_upper, b);
     }
-    if (!s->nb_pending && s->nb_upper > limit / 4) {
-        if (hipMemcpyAsync(s->pin_nb, &s->meta->n_blocks, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream) !=
-                hipSuccess ||
-            hipEventRecord(s->nb_ev, ctx->stream) != hipSuccess)
-            return;  // the bound stays valid without the refresh
-        s->nb_pending = true;
-        s->nb_extra = 0;
-    }
+    s->seq++;
+    s->box_ring[s->seq % covox_submap::kSeqRing] = next_box;
 }
 
 }  // namespace
@@ -597,6 +625,18 @@ int prepare_frame(covox_ctx *ctx, const covox_submap *s, const float *depth, int
     f.H = H;
     f.W = W;
     f.depth = depth;
+    {
+        // side planes through the camera centre for u in [-1.5, W + 0.5]
+        // and v in [-1.5, H + 0.5] (one pixel beyond the pixel-centre test)
+        const double fx = K[0], fy = K[1], cx = K[2], cy = K[3];
+        const double n[4][3] = {{fx, 0, cx + 1.5}, {-fx, 0, W + 0.5 - cx}, {0, fy, cy + 1.5}, {0, -fy, H + 0.5 - cy}};
+        for (int k = 0; k < 4; ++k) {
+            const double len = std::sqrt(n[k][0] * n[k][0] + n[k][1] * n[k][1] + n[k][2] * n[k][2]);
+            for (int a = 0; a < 3; ++a) f.plane[k][a] = (float)(n[k][a] / len);
+        }
+        f.zfar = (float)(p.max_range + p.trunc_vox * p.voxel_size);
+        f.cull_r = (float)(1.01 * std::sqrt(3.0) * 3.5 * p.voxel_size + 1e-4);
+    }
 
     // Block box containing every voxel centre of the frustum cut at
     // max_range + tau (conservative; validity decides exactly).
@@ -665,6 +705,7 @@ int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t
     const uint64_t tmask = (uint64_t)s->tcap - 1;
     const int64_t table_limit = (int64_t)(0.85 * (double)s->tcap);
     const unsigned grid = (unsigned)((n_box + 3) / 4);
+    refresh_block_bound(s, n_box);  // s->seq is now this frame's sequence number
     // Existing blocks are updated by the probe when no capacity failure is
     // possible for this frame (every box block new would still fit).
     const bool fused = s->nb_upper + n_box <= std::min<int64_t>(s->cap, table_limit);
@@ -676,7 +717,6 @@ int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t
 
     // host-side bounds
     s->nb_upper += n_box;
-    refresh_block_bound(ctx, s, n_box, std::min<int64_t>(s->cap, table_limit));
     grow_bounds(s, f);
     s->version++;
     *maybe_full = s->nb_upper > s->cap || s->nb_upper > table_limit;
@@ -740,6 +780,7 @@ int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_
     const float vs = (float)p.voxel_size, tau_f = (float)(p.trunc_vox * p.voxel_size), maxr = (float)p.max_range;
     const uint64_t tmask = (uint64_t)s->tcap - 1;
     const int64_t table_limit = (int64_t)(0.85 * (double)s->tcap);
+    refresh_block_bound(s, box_sum);
     {
         TimedLaunch tl(ctx, COVOX_K_PROBE);
         hipLaunchKernelGGL(k_probe_batch, dim3((unsigned)((box_max + 3) / 4), (unsigned)F), dim3(256), 0, ctx->stream,
@@ -749,7 +790,7 @@ int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_
         TimedLaunch tl(ctx, COVOX_K_SCAN);
         hipLaunchKernelGGL(k_scan_batch, dim3(1), dim3(1024), 0, ctx->stream, ctx->frames_dev, F, ctx->cand, box_max,
                            s->meta, s->cap, table_limit, s->keys, s->tkeys, s->tvals, tmask, s->stamp, s->batch_id,
-                           ctx->blist);
+                           ctx->blist, s->pin_nb_dev, s->seq);
     }
     {
         // one wave per listed block (at most min(capacity, sum of the boxes))
@@ -765,7 +806,6 @@ int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "integrate batch launch"))) return rc;
     s->nb_upper += box_sum;
-    refresh_block_bound(ctx, s, box_sum, std::min<int64_t>(s->cap, table_limit));
     for (int32_t i = 0; i < F; ++i) grow_bounds(s, fr[i]);
     s->version++;
     *maybe_full = s->nb_upper > s->cap || s->nb_upper > table_limit;
