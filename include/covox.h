@@ -332,6 +332,32 @@ typedef struct {
 int covox_train_proposal(covox_ctx *ctx, covox_net *net, const covox_train_cfg *cfg, const covox_pair *pairs,
                          int32_t n, float *loss_host);
 
+/* -------------------------------------------------------------- tuning */
+
+/* Launch shapes chosen per call.  Each line pass of the EDT (y, then z) has
+ * two exact implementations: a voxel-parallel windowed search (cost follows
+ * the distance to the nearest site) and per-line lower envelopes (cost
+ * follows the line length; one lane per line segment).  A pass uses the
+ * envelopes when the call has at least *_env_min_cols line segments. */
+typedef struct {
+    int64_t edt_y_env_min_cols;
+    int64_t edt_z_env_min_cols;
+    int64_t reserved[6];
+} covox_tuning;
+
+/* Defaults: y envelopes from 2048 segments up, z always windowed. */
+void covox_default_tuning(covox_tuning *t);
+int covox_tuning_get(const covox_ctx *ctx, covox_tuning *out);
+int covox_tuning_set(covox_ctx *ctx, const covox_tuning *t);
+
+/* Autotuner: recomputes the ESDF of the (up to 32 distinct) submaps with
+ * every combination of pass shapes, times each with HIP events on the
+ * context stream (best of 3), and moves the thresholds so that the fastest
+ * combination is the one chosen for calls of this size.  The ESDF result
+ * is the same for every shape.  out (nullable) receives the new tuning.
+ * Synchronous. */
+int covox_autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int32_t n, covox_tuning *out);
+
 /* ---------------------------------------------------------------- timing */
 
 enum {

@@ -63,6 +63,11 @@ class covox_train_cfg(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+class covox_tuning(ctypes.Structure):
+    _fields_ = [("edt_y_env_min_cols", ctypes.c_int64), ("edt_z_env_min_cols", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 6)]
+
+
 class covox_timing(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * 12), ("launches", ctypes.c_int64 * 12)]
 
@@ -115,6 +120,10 @@ _sig = {
     "covox_propose": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_double, _dp]),
     "covox_train_proposal": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_train_cfg), ctypes.POINTER(covox_pair),
                                             ctypes.c_int32, _fp]),
+    "covox_default_tuning": (None, [ctypes.POINTER(covox_tuning)]),
+    "covox_tuning_get": (ctypes.c_int, [_vp, ctypes.POINTER(covox_tuning)]),
+    "covox_tuning_set": (ctypes.c_int, [_vp, ctypes.POINTER(covox_tuning)]),
+    "covox_autotune_esdf": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(covox_tuning)]),
     "covox_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "covox_timing_get": (ctypes.c_int, [_vp, ctypes.POINTER(covox_timing)]),
 }
@@ -363,6 +372,23 @@ class Context:
         pts = np.zeros((max(n, 1), 3), np.float32)
         _lib.covox_export_points(self.handle, B.handle, _p(pts, _fp), n)
         return pts[:n]
+
+    # -- tuning
+    def tuning(self) -> dict:
+        t = covox_tuning()
+        self._check(_lib.covox_tuning_get(self.handle, ctypes.byref(t)), "tuning_get")
+        return {"edt_y_env_min_cols": t.edt_y_env_min_cols, "edt_z_env_min_cols": t.edt_z_env_min_cols}
+
+    def set_tuning(self, edt_y_env_min_cols, edt_z_env_min_cols):
+        t = covox_tuning()
+        t.edt_y_env_min_cols, t.edt_z_env_min_cols = edt_y_env_min_cols, edt_z_env_min_cols
+        self._check(_lib.covox_tuning_set(self.handle, ctypes.byref(t)), "tuning_set")
+
+    def autotune_esdf(self, subs) -> dict:
+        arr = (_vp * max(len(subs), 1))(*[s.handle for s in subs])
+        t = covox_tuning()
+        self._check(_lib.covox_autotune_esdf(self.handle, arr, len(subs), ctypes.byref(t)), "autotune_esdf")
+        return {"edt_y_env_min_cols": t.edt_y_env_min_cols, "edt_z_env_min_cols": t.edt_z_env_min_cols}
 
     # -- timing
     def timing_enable(self, kinds=None):

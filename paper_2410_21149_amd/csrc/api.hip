@@ -311,6 +311,7 @@ int covox_create(covox_ctx **out, const covox_params *p)
     if (!valid_params(p, why)) return COVOX_EINVAL;
     covox_ctx *ctx = new covox_ctx();
     ctx->p = *p;
+    covox_default_tuning(&ctx->tune);
     if (const char *m = getenv("COVOX_EDT_MODE")) {
         if (!strcmp(m, "window")) ctx->edt_mode = 1;
         else if (!strcmp(m, "envelope")) ctx->edt_mode = 2;
@@ -950,6 +951,44 @@ int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs,
         cost[i] = res[i].cost;
         fill_stats(stats ? stats + i : nullptr, pairs[i].B, res[i], best[i]);
     }
+    return COVOX_OK;
+}
+
+void covox_default_tuning(covox_tuning *t)
+{
+    if (!t) return;
+    memset(t, 0, sizeof(*t));
+    // measured on MI355X: per-line envelopes win the y pass once there are a
+    // few thousand segments; the windowed z pass, which only visits
+    // allocated blocks, won at every size tried
+    t->edt_y_env_min_cols = 2048;
+    t->edt_z_env_min_cols = INT64_MAX;
+}
+
+int covox_tuning_get(const covox_ctx *ctx, covox_tuning *out)
+{
+    if (!ctx || !out) return COVOX_EINVAL;
+    *out = ctx->tune;
+    return COVOX_OK;
+}
+
+int covox_tuning_set(covox_ctx *ctx, const covox_tuning *t)
+{
+    if (!ctx || !t) return COVOX_EINVAL;
+    if (t->edt_y_env_min_cols < 0 || t->edt_z_env_min_cols < 0)
+        return fail(ctx, COVOX_EINVAL, "tuning_set: negative threshold");
+    ctx->tune = *t;
+    return COVOX_OK;
+}
+
+int covox_autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int32_t n, covox_tuning *out)
+{
+    if (!ctx || (!subs && n > 0) || n < 0) return fail(ctx, COVOX_EINVAL, "autotune_esdf: bad argument");
+    for (int32_t i = 0; i < n; ++i)
+        if (!subs[i]) return fail(ctx, COVOX_EINVAL, "autotune_esdf: null submap");
+    int rc = autotune_esdf(ctx, subs, n);
+    if (rc) return rc;
+    if (out) *out = ctx->tune;
     return COVOX_OK;
 }
 

@@ -174,8 +174,8 @@ struct covox_ctx {
     int64_t g1_cap = 0;
     uint16_t *g2 = nullptr;     // 512 per dense block
     int64_t g2_cap = 0;
-    int32_t edt_mode = 0;           // 0 auto, 1 voxel-parallel window, 2 per-line envelope
-    int32_t edt_env_min_cols = 2048;  // auto: envelopes when both line passes have this many columns
+    int32_t edt_mode = 0;           // 0 by the tuning below, 1 voxel-parallel window, 2 per-line envelope
+    covox_tuning tune;              // per-pass shape thresholds (covox_default_tuning, covox_autotune_esdf)
     // registration-point scratch
     uint32_t *cnt = nullptr;    // per-block counts, then offsets
     int64_t cnt_cap = 0;
@@ -263,6 +263,7 @@ int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t
 // k_esdf.hip
 int build_page(covox_ctx *ctx, covox_submap *s);   // page + site masks of the bounding box
 int update_esdf(covox_ctx *ctx, covox_submap *s);
+int autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int n);
 int update_esdf_batch(covox_ctx *ctx, covox_submap *const *subs, int n);
 
 // k_align.hip

@@ -603,8 +603,20 @@ JobList<NJ> make_jobs(covox_submap *const *subs, int n)
 
 // Page + site masks (and, with edt, the three EDT passes) for up to NJ
 // submaps in one launch per kernel.
+// Line segments of the y and z passes over the host bounds of the submaps.
+void chunk_cols(covox_submap *const *subs, int n, int HB, int64_t &cy, int64_t &cz)
+{
+    cy = cz = 0;
+    for (int i = 0; i < n; ++i) {
+        cy += bound_cols(subs[i], 0, 2, HB);
+        cz += bound_cols(subs[i], 0, 1, HB);
+    }
+}
+
+// force < 0: shapes by the tuning (or COVOX_EDT_MODE); else bit 0 = y
+// envelopes, bit 1 = z envelopes.
 template <int NJ>
-int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt)
+int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int force = -1)
 {
     const covox_params &p = ctx->p;
     const int R = (int)std::llround(p.d_max / p.voxel_size);
@@ -618,9 +630,8 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt)
         if ((rc = ensure_buffer(ctx, (void **)&s->page, &s->page_cap, b, sizeof(int32_t), "page"))) return rc;
         nd += b;
         nb += std::min(s->nb_upper, s->cap);
-        cy += bound_cols(s, 0, 2, HB);
-        cz += bound_cols(s, 0, 1, HB);
     }
+    chunk_cols(subs, n, HB, cy, cz);
     if ((rc = ensure_buffer(ctx, (void **)&ctx->sites, &ctx->sites_cap, nd, 8 * sizeof(uint64_t), "site masks")))
         return rc;
     if (edt) {
@@ -645,9 +656,13 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt)
     // Pass shape: per-line envelopes when there are enough lines to fill the
     // GPU, voxel-parallel windowed search otherwise (or as forced by
     // COVOX_EDT_MODE = window | envelope).
-    bool envelope = std::min(cy, cz) >= (int64_t)ctx->edt_env_min_cols;
-    if (ctx->edt_mode == 1) envelope = false;
-    if (ctx->edt_mode == 2) envelope = true;
+    bool env_y = cy >= ctx->tune.edt_y_env_min_cols, env_z = cz >= ctx->tune.edt_z_env_min_cols;
+    if (ctx->edt_mode == 1) env_y = env_z = false;
+    if (ctx->edt_mode == 2) env_y = env_z = true;
+    if (force >= 0) {
+        env_y = (force & 1) != 0;
+        env_z = (force & 2) != 0;
+    }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_X);
         hipLaunchKernelGGL((k_edt_x_vox<NJ>), dim3(clamp_grid(nd)), dim3(512), 0, ctx->stream, jl, ctx->sites, ctx->g1,
@@ -655,7 +670,7 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt)
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Y);
-        if (envelope)
+        if (env_y)
             hipLaunchKernelGGL((k_edt_y_env<NJ>), dim3(clamp_grid_w(cy)), dim3(64), 0, ctx->stream, jl, ctx->g1, ctx->g2,
                                R, HB);
         else
@@ -664,10 +679,10 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt)
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Z);
-        if (envelope && h)
+        if (env_z && h)
             hipLaunchKernelGGL((k_edt_z_env<__half, NJ>), dim3(clamp_grid_w(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2,
                                R, HB, vs, tau, dmax);
-        else if (envelope)
+        else if (env_z)
             hipLaunchKernelGGL((k_edt_z_env<float, NJ>), dim3(clamp_grid_w(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2,
                                R, HB, vs, tau, dmax);
         else if (h)
@@ -706,5 +721,57 @@ int update_esdf_batch(covox_ctx *ctx, covox_submap *const *subs, int n)
 }
 
 int update_esdf(covox_ctx *ctx, covox_submap *s) { return update_esdf_batch(ctx, &s, 1); }
+
+int autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int n)
+{
+    std::vector<covox_submap *> todo;
+    for (int i = 0; i < n && (int)todo.size() < kMaxJobs; ++i)
+        if (std::find(todo.begin(), todo.end(), subs[i]) == todo.end()) todo.push_back(subs[i]);
+    if (todo.empty()) return COVOX_OK;
+    const int m = (int)todo.size();
+    const int R = (int)std::llround(ctx->p.d_max / ctx->p.voxel_size);
+    int64_t cy, cz;
+    chunk_cols(todo.data(), m, (R + 7) / 8, cy, cz);
+    auto run = [&](int force) {
+        return m == 1 ? esdf_chunk<1>(ctx, todo.data(), 1, true, force)
+                      : esdf_chunk<kMaxJobs>(ctx, todo.data(), m, true, force);
+    };
+    hipEvent_t e0, e1;
+    int rc = hip_check(ctx, hipEventCreate(&e0), "autotune event");
+    if (rc) return rc;
+    if ((rc = hip_check(ctx, hipEventCreate(&e1), "autotune event"))) {
+        (void)hipEventDestroy(e0);
+        return rc;
+    }
+    const int32_t saved_timing = ctx->timing;
+    ctx->timing = 0;  // no per-kernel events inside the measured region
+    float best_ms[4];
+    for (int combo = 0; combo < 4 && !rc; ++combo) {
+        best_ms[combo] = 1e30f;
+        rc = run(combo);  // warm-up (buffers, caches)
+        for (int rep = 0; rep < 3 && !rc; ++rep) {
+            rc = hip_check(ctx, hipEventRecord(e0, ctx->stream), "autotune record");
+            if (!rc) rc = run(combo);
+            if (!rc) rc = hip_check(ctx, hipEventRecord(e1, ctx->stream), "autotune record");
+            if (!rc) rc = hip_check(ctx, hipEventSynchronize(e1), "autotune sync");
+            float ms = 0;
+            if (!rc) rc = hip_check(ctx, hipEventElapsedTime(&ms, e0, e1), "autotune elapsed");
+            if (!rc) best_ms[combo] = std::min(best_ms[combo], ms);
+        }
+    }
+    ctx->timing = saved_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    int best = 0;
+    for (int c = 1; c < 4; ++c)
+        if (best_ms[c] < best_ms[best]) best = c;
+    covox_tuning &t = ctx->tune;
+    if (best & 1) t.edt_y_env_min_cols = std::min(t.edt_y_env_min_cols, cy);
+    else t.edt_y_env_min_cols = std::max(t.edt_y_env_min_cols, cy + 1);
+    if (best & 2) t.edt_z_env_min_cols = std::min(t.edt_z_env_min_cols, cz);
+    else t.edt_z_env_min_cols = std::max(t.edt_z_env_min_cols, cz + 1);
+    return COVOX_OK;
+}
 
 }  // namespace covox

@@ -367,6 +367,36 @@ def test_esdf_modes_parity(cv, mode, workload, monkeypatch):
     ctx.close()
 
 
+def test_mixed_pass_shapes_and_autotune_leave_phi_unchanged(cv):
+    """Every combination of y and z pass shapes (chosen through the tuning
+    thresholds) and the autotuner's own runs give the same phi, bit for bit,
+    as the checker; the autotuner returns valid thresholds."""
+    import torch
+    w = sg.room(n_frames=30)
+    fr = w.frames()
+    ctx = _ctx(cv, block_capacity=16384)
+    s = ctx.submap_create()
+    ref = orc.Submap(_oracle_params())
+    dev = torch.from_numpy(fr).cuda()
+    ctx.integrate_depth_batch(s, dev, w.cam.K, w.poses)
+    for f in range(w.n_frames):
+        ref.integrate(fr[f], w.cam.K, w.poses[f])
+    ref.update_esdf()
+    want = ref.export()
+    big = 2 ** 62
+    for y_thr, z_thr in ((0, 0), (0, big), (big, 0), (big, big)):
+        ctx.set_tuning(y_thr, z_thr)
+        ctx.update_esdf(s)
+        assert _compare_phi(ctx.export_blocks(s), want) == 0, (y_thr, z_thr)
+    t = ctx.autotune_esdf([s])
+    assert t["edt_y_env_min_cols"] >= 0 and t["edt_z_env_min_cols"] >= 0
+    assert ctx.tuning() == t
+    assert _compare_phi(ctx.export_blocks(s), want) == 0
+    ctx.update_esdf(s)
+    assert _compare_phi(ctx.export_blocks(s), want) == 0
+    ctx.close()
+
+
 def test_outdoor_submap_parity_and_batched_esdf(cv):
     """An outdoor submap at the large-scale configuration (0.1 m voxels,
     10 m range, ESDF to 3 m) against the checker, and the batched ESDF of
