@@ -6,7 +6,9 @@ Step = the room workload mapped from scratch: 300 depth frames of 640x480
 after every frame -- projective integration (probe / scan / integrate
 kernels) followed by the exact ESDF (page / x / y / z kernels) per frame.
 value = frames per second over the timed steps (inputs already resident in
-device memory).
+device memory).  config.graph_replay_frames_per_s times the same step
+captured once as a HIP graph (covox_graph_*) and replayed (W untimed, K
+timed replays; --no-graph skips it).
 
 Also reported on the same JSON line:
   roofline      the dominant kernel: algorithmic bytes per launch divided by
@@ -68,6 +70,33 @@ def algorithmic_bytes(kind, census, s_dw):
         elif kind == "edt_z":       # g2 of the block columns, D and W in, phi out
             tot += 1024 * nb[f] + s_dw * 512 * nb[f] + 4 * 512 * nb[f]
     return tot / F
+
+
+def measured_traffic(kind, tuning, census):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (profiles/room_hbm_traffic.md: FETCH_SIZE and WRITE_SIZE scaled by
+    a copy of known size), or None when the kernel's source has changed since
+    the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "room_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    table = None
+    for line in open(path):
+        if line.startswith("traffic_json: "):
+            table = json.loads(line[len("traffic_json: "):])
+    if not table:
+        return None
+    symbols = {"probe": "k_probe<float, true>", "scan": "k_scan", "integrate": "k_integrate<float, true>",
+               "esdf_page": "k_page_sites<float, 1>", "edt_x": "k_edt_x<1>", "edt_y": "k_edt_y_vox<1>",
+               "edt_z": "k_edt_z_vox<float, 1>"}
+    ent = table.get(symbols.get(kind, ""))
+    if ent is None:
+        return None
+    src = os.path.join(ROOT, "paper_2410_21149_amd", "csrc", ent["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != ent["sha256"]:
+        return None
+    return ent["bytes_per_dispatch"]
 
 
 def run_census(ctx, s, dev, w, np):
@@ -386,6 +415,7 @@ def main():
     ap.add_argument("--no-align", action="store_true")
     ap.add_argument("--no-mav", action="store_true")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"])
+    ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of graph replays")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -432,24 +462,46 @@ def main():
     dominant = max((k for k in prof if prof[k][1] > 0), key=lambda k: prof[k][0])
     _log("per-kernel ms per step: " + ", ".join("%s %.3f" % (k, v[0]) for k, v in prof.items() if v[1]))
 
-    for _ in range(args.warmup):
+    def eager_step():
         ctx.submap_reset(s)
         ctx.map_sequence(s, dev, K, w.poses, esdf_every=1)
-    torch.cuda.synchronize()
 
-    ctx.timing_enable([dominant])
+    # eager calls: the same steps issued call by call
+    for _ in range(args.warmup):
+        eager_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        ctx.submap_reset(s)
-        ctx.map_sequence(s, dev, K, w.poses, esdf_every=1)
+        eager_step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    eager_fps = w.n_frames * args.steps / (time.perf_counter() - t0)
+
+    # the dominant kernel's launches, bracketed by HIP events (one eager step)
+    ctx.timing_enable([dominant])
+    eager_step()
+    torch.cuda.synchronize()
     tim = ctx.timing_get()
     ctx.timing_enable([])
-    elapsed = t1 - t0
-    ms_per_step = elapsed / args.steps * 1e3
-    fps = w.n_frames * args.steps / elapsed
+
+    # the step captured once as a graph (reset, 300 frames, ESDF after each)
+    # and replayed: W untimed replays, then K timed ones
+    graph_fps = None
+    if not args.no_graph:
+        ctx.graph_begin()
+        eager_step()
+        graph = ctx.graph_end()
+        for _ in range(args.warmup):
+            graph.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.launch()
+        torch.cuda.synchronize()
+        graph_fps = w.n_frames * args.steps / (time.perf_counter() - t0)
+        ctx.sync()  # sticky capacity status of the replays
+        graph.close()
+    fps = eager_fps
+    ms_per_step = w.n_frames / eager_fps * 1e3
 
     s_dw = 4 if prec == cv.FP16 else 8
     ms_k, n_k = tim[dominant]
@@ -457,8 +509,8 @@ def main():
     bytes_launch = algorithmic_bytes(dominant, census, s_dw)
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": bytes_launch,
-                "ms_per_launch": per_launch_ms}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant, room_tuning, census),
+                "bytes_per_launch": bytes_launch, "ms_per_launch": per_launch_ms}
 
     result = {
         "metric": METRIC,
@@ -476,6 +528,7 @@ def main():
         "config": {"workload": "room 8x6x3 m, 300 frames 640x480 fx=fy=525, 5 cm voxels, tau 4 voxels, "
                                "ESDF 2 m after every frame",
                    "frames_per_step": w.n_frames, "voxel_size": w.voxel_size, "blocks": census["n_blocks"][-1],
+                   "graph_replay_frames_per_s": graph_fps,
                    "voxel_updates_per_step": int(sum(census["n_upd"]))},
         "roofline": roofline,
         "kernel_ms_per_step": {k: v[0] for k, v in prof.items() if v[1]},

@@ -332,6 +332,37 @@ typedef struct {
 int covox_train_proposal(covox_ctx *ctx, covox_net *net, const covox_train_cfg *cfg, const covox_pair *pairs,
                          int32_t n, float *loss_host);
 
+/* -------------------------------------------------------------- graphs */
+
+/* Capture of the asynchronous calls of a context into a HIP graph, so that a
+ * launch-bound sequence (a mapping loop: reset, F frames, ESDF updates) is
+ * replayed with one launch.
+ *
+ * Between covox_graph_begin and covox_graph_end only covox_submap_reset,
+ * the integration calls, covox_map_sequence and the ESDF updates may be
+ * called on ctx (every other call returns COVOX_EINVAL), and nothing else
+ * may use the context stream.  Nothing runs during capture, and the host
+ * bookkeeping of every submap is as before covox_graph_begin afterwards.
+ * A submap integrated inside the graph must be reset inside it first
+ * (covox_graph_end fails otherwise).
+ *
+ * covox_graph_launch enqueues the captured kernels on the context stream
+ * with their captured arguments: the same submaps, poses, intrinsics and
+ * depth pointers (the depth contents may change between launches), and
+ * updates the host bookkeeping as the captured calls would.  A submap that
+ * the graph updates without resetting must not have grown since the
+ * capture (COVOX_EINVAL).  Capacity errors of captured integrations are not
+ * reported by the launch: they stay in the submap's sticky status
+ * (covox_submap_info, covox_sync).  While any graph of a context exists,
+ * the context keeps every scratch buffer it replaces until the last graph
+ * is destroyed.  Submaps used by a graph must outlive it, and every graph
+ * of a context must be destroyed before the context. */
+typedef struct covox_graph covox_graph;
+int covox_graph_begin(covox_ctx *ctx);
+int covox_graph_end(covox_ctx *ctx, covox_graph **out);
+int covox_graph_launch(covox_graph *g);
+void covox_graph_destroy(covox_graph *g);
+
 /* -------------------------------------------------------------- tuning */
 
 /* Launch shapes chosen per call.  Each line pass of the EDT (y, then z) has

@@ -7,7 +7,7 @@ kernels for gfx950 behind the C ABI in include/covox.h.
 HIP library has not been built.
 """
 from .covox import (FP16, FP32, KERNELS, OK, EINVAL, EPOOL_FULL, ETABLE_FULL, EHIP, EDEGENERATE, NOT_CONVERGED,
-                    Context, CovoxError, Net, Submap, default_params, LIB_PATH)
+                    Context, CovoxError, Graph, Net, Submap, default_params, LIB_PATH)
 
-__all__ = ["Context", "Net", "Submap", "CovoxError", "default_params", "FP32", "FP16", "KERNELS", "OK", "EINVAL",
+__all__ = ["Context", "Graph", "Net", "Submap", "CovoxError", "default_params", "FP32", "FP16", "KERNELS", "OK", "EINVAL",
            "EPOOL_FULL", "ETABLE_FULL", "EHIP", "EDEGENERATE", "NOT_CONVERGED", "LIB_PATH"]

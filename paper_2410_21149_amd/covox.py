@@ -120,6 +120,10 @@ _sig = {
     "covox_propose": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_double, _dp]),
     "covox_train_proposal": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_train_cfg), ctypes.POINTER(covox_pair),
                                             ctypes.c_int32, _fp]),
+    "covox_graph_begin": (ctypes.c_int, [_vp]),
+    "covox_graph_end": (ctypes.c_int, [_vp, ctypes.POINTER(_vp)]),
+    "covox_graph_launch": (ctypes.c_int, [_vp]),
+    "covox_graph_destroy": (None, [_vp]),
     "covox_default_tuning": (None, [ctypes.POINTER(covox_tuning)]),
     "covox_tuning_get": (ctypes.c_int, [_vp, ctypes.POINTER(covox_tuning)]),
     "covox_tuning_set": (ctypes.c_int, [_vp, ctypes.POINTER(covox_tuning)]),
@@ -186,6 +190,8 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
+            for g in getattr(self, "_graphs", []):
+                g.close()
             for s in self._subs:
                 s.handle = None
             _lib.covox_destroy(self.handle)
@@ -373,6 +379,20 @@ class Context:
         _lib.covox_export_points(self.handle, B.handle, _p(pts, _fp), n)
         return pts[:n]
 
+    # -- graphs
+    def graph_begin(self):
+        """Starts capturing this context's asynchronous calls (see Graph)."""
+        self._check(_lib.covox_graph_begin(self.handle), "graph_begin")
+
+    def graph_end(self) -> "Graph":
+        h = _vp()
+        self._check(_lib.covox_graph_end(self.handle, ctypes.byref(h)), "graph_end")
+        g = Graph(self, h)
+        if not hasattr(self, "_graphs"):
+            self._graphs = []
+        self._graphs.append(g)
+        return g
+
     # -- tuning
     def tuning(self) -> dict:
         t = covox_tuning()
@@ -400,6 +420,28 @@ class Context:
         t = covox_timing()
         self._check(_lib.covox_timing_get(self.handle, ctypes.byref(t)), "timing_get")
         return {k: (t.ms[i], t.launches[i]) for i, k in enumerate(KERNELS)}
+
+
+class Graph:
+    """A captured sequence of calls, replayed by launch()."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.handle = handle
+
+    def launch(self):
+        self.ctx._check(_lib.covox_graph_launch(self.handle), "graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.covox_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _stats(st: covox_align_stats) -> dict:

@@ -82,9 +82,14 @@ int ensure_buffer(covox_ctx *ctx, void **ptr, int64_t *cap, int64_t need, size_t
     if (need <= *cap && *ptr) return COVOX_OK;
     int64_t nc = std::max<int64_t>(need, *cap + *cap / 2);
     if (*ptr) {
-        hipError_t e = hipStreamSynchronize(ctx->stream);
-        if (e != hipSuccess) return hip_check(ctx, e, "sync before reallocation");
-        (void)hipFree(*ptr);
+        if (ctx->capturing || ctx->n_graphs > 0) {
+            // captured kernels may still name the old buffer: keep it
+            ctx->deferred.push_back(*ptr);
+        } else {
+            hipError_t e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) return hip_check(ctx, e, "sync before reallocation");
+            (void)hipFree(*ptr);
+        }
         *ptr = nullptr;
         *cap = 0;
     }
@@ -97,6 +102,51 @@ int ensure_buffer(covox_ctx *ctx, void **ptr, int64_t *cap, int64_t need, size_t
     return COVOX_OK;
 }
 
+SubmapSnap snap(const covox_submap *s)
+{
+    SubmapSnap q;
+    q.nb_upper = s->nb_upper;
+    q.bound_valid = s->bound_valid;
+    for (int a = 0; a < 3; ++a) { q.bound_lo[a] = s->bound_lo[a]; q.bound_hi[a] = s->bound_hi[a]; }
+    q.version = s->version;
+    q.page_version = s->page_version;
+    q.esdf_version = s->esdf_version;
+    q.pts_version = s->pts_version;
+    q.n_pts = s->n_pts;
+    return q;
+}
+
+void restore(covox_submap *s, const SubmapSnap &q)
+{
+    s->nb_upper = q.nb_upper;
+    s->bound_valid = q.bound_valid;
+    for (int a = 0; a < 3; ++a) { s->bound_lo[a] = q.bound_lo[a]; s->bound_hi[a] = q.bound_hi[a]; }
+    s->version = q.version;
+    s->page_version = q.page_version;
+    s->esdf_version = q.esdf_version;
+    s->pts_version = q.pts_version;
+    s->n_pts = q.n_pts;
+}
+
+void capture_touch(covox_ctx *ctx, covox_submap *s, int op)
+{
+    if (!ctx->capturing) return;
+    CaptureEntry *e = nullptr;
+    for (auto &c : ctx->cap_subs)
+        if (c.s == s) e = &c;
+    if (!e) {
+        ctx->cap_subs.push_back(CaptureEntry{s, snap(s), SubmapSnap{}, op == 0, false});
+        e = &ctx->cap_subs.back();
+    }
+    if (op == 1) {
+        e->integrated = true;
+        if (!e->reset_first) {
+            ctx->capture_bad = true;
+            ctx->capture_why = "a submap integrated inside a graph must be reset first inside the same graph";
+        }
+    }
+}
+
 }  // namespace covox
 
 using namespace covox;
@@ -104,6 +154,14 @@ using namespace covox;
 namespace {
 
 std::vector<covox_submap *> &submaps_of(covox_ctx *ctx) { return ctx->subs; }
+
+// Calls that wait for the device or return device results cannot be
+// captured into a graph.
+#define COVOX_NOT_DURING_CAPTURE(ctx, what)                                                  \
+    do {                                                                                   \
+        if ((ctx) && (ctx)->capturing)                                                     \
+            return fail((ctx), COVOX_EINVAL, std::string(what) + ": not allowed while capturing a graph"); \
+    } while (0)
 
 bool valid_params(const covox_params *p, std::string &why)
 {
@@ -144,6 +202,9 @@ __global__ void k_reset_meta(SubmapMeta *m)
 
 int check_status_after_sync(covox_ctx *ctx, covox_submap *s)
 {
+    // Under capture nothing runs yet: the device-side capacity check still
+    // guards every commit, and its sticky status is read after a launch.
+    if (ctx->capturing) return COVOX_OK;
     SubmapMeta m;
     int rc = read_meta(ctx, s, &m);
     if (rc) return rc;
@@ -335,6 +396,8 @@ void covox_destroy(covox_ctx *ctx)
                       (void *)ctx->net_in, (void *)ctx->net_out, (void *)ctx->train_y, (void *)ctx->loss_hist,
                       (void *)ctx->frames_dev, (void *)ctx->blist})
         if (ptr) (void)hipFree(ptr);
+    for (void *p : ctx->deferred) (void)hipFree(p);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (int k = 0; k < 2; ++k) {
         if (ctx->frames_pin[k]) (void)hipHostFree(ctx->frames_pin[k]);
         if (ctx->frames_ev[k]) (void)hipEventDestroy(ctx->frames_ev[k]);
@@ -349,6 +412,7 @@ void covox_destroy(covox_ctx *ctx)
 
 int covox_set_stream(covox_ctx *ctx, void *hip_stream)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "set_stream");
     if (!ctx) return COVOX_EINVAL;
     ctx->stream = (hipStream_t)hip_stream;
     return COVOX_OK;
@@ -356,6 +420,7 @@ int covox_set_stream(covox_ctx *ctx, void *hip_stream)
 
 int covox_sync(covox_ctx *ctx)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "sync");
     if (!ctx) return COVOX_EINVAL;
     int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync");
     if (rc) return rc;
@@ -368,6 +433,7 @@ int covox_sync(covox_ctx *ctx)
 
 int covox_submap_create(covox_ctx *ctx, const double T_world_submap[16], covox_submap **out)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "submap_create");
     if (!ctx || !T_world_submap || !out) return fail(ctx, COVOX_EINVAL, "submap_create: null argument");
     if (!rigid_pose(T_world_submap)) return fail(ctx, COVOX_EINVAL, "submap_create: pose is not rigid");
     *out = nullptr;
@@ -388,6 +454,7 @@ int covox_submap_create(covox_ctx *ctx, const double T_world_submap[16], covox_s
     if (e == hipSuccess) e = hipMalloc((void **)&s->tkeys, sizeof(uint64_t) * s->tcap);
     if (e == hipSuccess) e = hipMalloc((void **)&s->tvals, sizeof(uint32_t) * s->tcap);
     if (e == hipSuccess) e = hipMalloc((void **)&s->meta, sizeof(SubmapMeta));
+    if (e == hipSuccess) e = hipMalloc((void **)&s->stamp, sizeof(uint32_t) * s->cap);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->pin_nb, sizeof(uint64_t), hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) {
         *s->pin_nb = 0;
@@ -398,6 +465,7 @@ int covox_submap_create(covox_ctx *ctx, const double T_world_submap[16], covox_s
         return fail(ctx, COVOX_EHIP, std::string("submap_create: ") + hipGetErrorString(e));
     }
     submaps_of(ctx).push_back(s);
+    fill_u32(ctx->stream, s->stamp, 0u, s->cap);  // frame-batch stamps (never reset)
     int rc = covox_submap_reset(ctx, s);
     if (rc) {
         covox_submap_destroy(s);
@@ -426,6 +494,7 @@ void covox_submap_destroy(covox_submap *s)
 int covox_submap_reset(covox_ctx *ctx, covox_submap *s)
 {
     if (!ctx || !s) return fail(ctx, COVOX_EINVAL, "submap_reset: null argument");
+    capture_touch(ctx, s, 0);
     fill_u64(ctx->stream, s->tkeys, kEmpty, s->tcap);
     hipLaunchKernelGGL(k_reset_meta, dim3(1), dim3(1), 0, ctx->stream, s->meta);
     int rc = hip_check(ctx, hipGetLastError(), "submap_reset");
@@ -441,6 +510,7 @@ int covox_integrate_depth(covox_ctx *ctx, covox_submap *s, const float *depth_de
                           const float K[4], const double T_world_cam[16])
 {
     if (!ctx || !s) return fail(ctx, COVOX_EINVAL, "integrate: null argument");
+    capture_touch(ctx, s, 1);
     bool maybe_full = false;
     int rc = integrate_frame(ctx, s, depth_dev, H, W, K, T_world_cam, &maybe_full);
     if (rc) return rc;
@@ -452,6 +522,7 @@ int covox_integrate_depth_batch(covox_ctx *ctx, covox_submap *s, const float *de
                                 int32_t W, const float K[4], const double *T_world_cam)
 {
     if (!ctx || !s || !depths_dev || !T_world_cam || F < 0) return fail(ctx, COVOX_EINVAL, "integrate_batch: bad argument");
+    capture_touch(ctx, s, 1);
     return integrate_frames(ctx, s, depths_dev, F, H, W, K, T_world_cam);
 }
 
@@ -459,6 +530,7 @@ int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev,
                        const float K[4], const double *T_world_cam, int32_t esdf_every)
 {
     if (!ctx || !s || !depths_dev || !T_world_cam || F < 0) return fail(ctx, COVOX_EINVAL, "map_sequence: bad argument");
+    capture_touch(ctx, s, 1);
     // frames between ESDF updates go through the batched integration
     const int32_t step = esdf_every > 0 ? esdf_every : F;
     for (int32_t f0 = 0; f0 < F; f0 += step) {
@@ -476,18 +548,21 @@ int covox_update_esdf_batch(covox_ctx *ctx, covox_submap *const *subs, int32_t n
     if (!ctx || (!subs && n > 0) || n < 0) return fail(ctx, COVOX_EINVAL, "update_esdf_batch: bad argument");
     for (int32_t i = 0; i < n; ++i)
         if (!subs[i]) return fail(ctx, COVOX_EINVAL, "update_esdf_batch: null submap");
+    for (int32_t i = 0; i < n; ++i) capture_touch(ctx, subs[i], 2);
     return update_esdf_batch(ctx, subs, n);
 }
 
 int covox_update_esdf(covox_ctx *ctx, covox_submap *s)
 {
     if (!ctx || !s) return fail(ctx, COVOX_EINVAL, "update_esdf: null argument");
+    capture_touch(ctx, s, 2);
     return update_esdf(ctx, s);
 }
 
 int covox_align_submaps(covox_ctx *ctx, const covox_submap *A, covox_submap *B, const double T_init_A_B[16],
                         double T_out[16], double *cost, covox_align_stats *stats)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "align_submaps");
     if (!ctx || !T_init_A_B || !T_out || !cost) return fail(ctx, COVOX_EINVAL, "align: null argument");
     if (!rigid_pose(T_init_A_B)) return fail(ctx, COVOX_EINVAL, "align: T_init is not rigid");
     int rc = prepare_pair(ctx, A, B);
@@ -504,6 +579,7 @@ int covox_align_submaps(covox_ctx *ctx, const covox_submap *A, covox_submap *B, 
 int covox_align_multistart(covox_ctx *ctx, const covox_submap *A, covox_submap *B, const double T_init_A_B[16],
                            int32_t n_starts, double T_out[16], double *cost, covox_align_stats *stats)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "align_multistart");
     if (!ctx || !T_init_A_B || !T_out || !cost || n_starts < 1) return fail(ctx, COVOX_EINVAL, "align: bad argument");
     if (!rigid_pose(T_init_A_B)) return fail(ctx, COVOX_EINVAL, "align: T_init is not rigid");
     int rc = prepare_pair(ctx, A, B);
@@ -532,6 +608,7 @@ int covox_align_multistart(covox_ctx *ctx, const covox_submap *A, covox_submap *
 int covox_align_batch(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_t n_starts, double *T_out,
                       double *cost, covox_align_stats *stats)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "align_batch");
     if (!ctx || !pairs || n < 0 || n_starts < 1 || !T_out || !cost) return fail(ctx, COVOX_EINVAL, "align_batch: bad argument");
     int rc;
     for (int i = 0; i < n; ++i) {
@@ -573,6 +650,7 @@ int covox_align_batch(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_
 int covox_normal_equations(covox_ctx *ctx, const covox_submap *A, covox_submap *B, const double T_A_B[16],
                            double out[29])
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "normal_equations");
     if (!ctx || !T_A_B || !out) return fail(ctx, COVOX_EINVAL, "normal_equations: null argument");
     int rc = prepare_pair(ctx, A, B);
     if (rc) return rc;
@@ -585,6 +663,7 @@ int covox_normal_equations(covox_ctx *ctx, const covox_submap *A, covox_submap *
 
 int covox_submap_info_get(covox_ctx *ctx, const covox_submap *s, covox_submap_info *out)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "submap_info_get");
     if (!ctx || !s || !out) return fail(ctx, COVOX_EINVAL, "submap_info: null argument");
     SubmapMeta m;
     int rc = read_meta(ctx, s, &m);
@@ -602,6 +681,7 @@ int covox_submap_info_get(covox_ctx *ctx, const covox_submap *s, covox_submap_in
 int64_t covox_export_blocks(covox_ctx *ctx, const covox_submap *s, uint64_t *keys, uint32_t *home, float *D, float *W,
                             float *phi, int64_t cap)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "export_blocks");
     if (!ctx || !s || cap < 0) return fail(ctx, COVOX_EINVAL, "export_blocks: bad argument");
     SubmapMeta m;
     int rc = read_meta(ctx, s, &m);
@@ -635,6 +715,7 @@ int64_t covox_export_blocks(covox_ctx *ctx, const covox_submap *s, uint64_t *key
 
 int64_t covox_export_points(covox_ctx *ctx, covox_submap *B, float *pts, int64_t cap)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "export_points");
     if (!ctx || !B || cap < 0) return fail(ctx, COVOX_EINVAL, "export_points: bad argument");
     int rc = extract_points(ctx, B);
     if (rc) return rc;
@@ -647,6 +728,7 @@ int64_t covox_export_points(covox_ctx *ctx, covox_submap *B, float *pts, int64_t
 
 int covox_summaries(covox_ctx *ctx, const covox_summary_req *reqs, int32_t n)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "summaries");
     if (!ctx || (!reqs && n > 0) || n < 0) return fail(ctx, COVOX_EINVAL, "summaries: bad argument");
     std::vector<SummaryReq> rq(n);
     for (int32_t i = 0; i < n; ++i) {
@@ -671,6 +753,7 @@ int covox_summaries(covox_ctx *ctx, const covox_summary_req *reqs, int32_t n)
 
 int covox_net_create(covox_ctx *ctx, uint64_t seed, covox_net **out)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "net_create");
     if (!ctx || !out) return fail(ctx, COVOX_EINVAL, "net_create: null argument");
     return net_create(ctx, seed, out);
 }
@@ -681,18 +764,21 @@ int64_t covox_net_num_params(const covox_net *net) { return net ? net_num_params
 
 int covox_net_get_params(covox_net *net, float *host, int64_t n)
 {
+    if (net) COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_get_params");
     if (!net || !host) return COVOX_EINVAL;
     return net_get_params(net, host, n);
 }
 
 int covox_net_set_params(covox_net *net, const float *host, int64_t n)
 {
+    if (net) COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_set_params");
     if (!net || !host) return COVOX_EINVAL;
     return net_set_params(net, host, n);
 }
 
 int covox_net_forward(covox_net *net, const float *x_dev, int32_t n, float *out_dev)
 {
+    if (net) COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_forward");
     if (!net || !x_dev || !out_dev || n <= 0) return COVOX_EINVAL;
     return net_forward_api(net, x_dev, n, out_dev);
 }
@@ -700,6 +786,7 @@ int covox_net_forward(covox_net *net, const float *x_dev, int32_t n, float *out_
 int covox_net_train_step(covox_net *net, const float *x_dev, const float *y_dev, int32_t n, float lr, float trans_scale,
                          float *loss_host)
 {
+    if (net) COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_train_step");
     if (!net || !x_dev || !y_dev || n <= 0 || !(trans_scale > 0)) return COVOX_EINVAL;
     return net_train_step(net, x_dev, y_dev, n, lr, trans_scale, loss_host);
 }
@@ -707,6 +794,7 @@ int covox_net_train_step(covox_net *net, const float *x_dev, const float *y_dev,
 int covox_net_gradients(covox_net *net, const float *x_dev, const float *y_dev, int32_t n, float trans_scale,
                         float *grad_host, float *loss_host)
 {
+    if (net) COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_gradients");
     if (!net || !x_dev || !y_dev || !grad_host || n <= 0 || !(trans_scale > 0)) return COVOX_EINVAL;
     return net_grads(net, x_dev, y_dev, n, trans_scale, grad_host, loss_host);
 }
@@ -827,6 +915,7 @@ double draw(uint64_t seed, uint64_t item, int k)
 
 int covox_propose(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell, double *T_prop)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "propose");
     if (!ctx || !net || (!pairs && n > 0) || n < 0 || !(cell > 0) || (!T_prop && n > 0))
         return fail(ctx, COVOX_EINVAL, "propose: bad argument");
     int rc = prepare_learned(ctx, pairs, n, "propose");
@@ -840,6 +929,7 @@ int covox_propose(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32
 int covox_train_proposal(covox_ctx *ctx, covox_net *net, const covox_train_cfg *cfg, const covox_pair *pairs,
                          int32_t n, float *loss_host)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "train_proposal");
     if (!ctx || !net || !cfg || !pairs || n <= 0 || cfg->steps < 0 || cfg->batch < 1 || cfg->batch > kLearnChunk ||
         !(cfg->cell > 0) || !(cfg->trans_scale > 0) || !(cfg->lr >= 0) || !(cfg->trans_xy >= 0) ||
         !(cfg->trans_z >= 0) || !(cfg->yaw >= 0) || !(cfg->tilt >= 0))
@@ -905,6 +995,7 @@ int covox_train_proposal(covox_ctx *ctx, covox_net *net, const covox_train_cfg *
 int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell,
                         double cost_thr, int32_t n_starts, double *T_out, double *cost, covox_align_stats *stats)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "align_learned");
     if (!ctx || !net || (!pairs && n > 0) || n < 0 || !(cell > 0) || n_starts < 1 || !T_out || !cost)
         return fail(ctx, COVOX_EINVAL, "align_learned: bad argument");
     int rc = prepare_learned(ctx, pairs, n, "align_learned");
@@ -954,6 +1045,117 @@ int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs,
     return COVOX_OK;
 }
 
+int covox_graph_begin(covox_ctx *ctx)
+{
+    if (!ctx) return COVOX_EINVAL;
+    COVOX_NOT_DURING_CAPTURE(ctx, "graph_begin");
+    int rc;
+    if (!ctx->cap_stream &&
+        (rc = hip_check(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking), "capture stream")))
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed), "begin capture")))
+        return rc;
+    ctx->cap_user_stream = ctx->stream;
+    ctx->stream = ctx->cap_stream;
+    ctx->capturing = true;
+    ctx->capture_bad = false;
+    ctx->capture_why.clear();
+    ctx->cap_subs.clear();
+    ctx->cap_host.clear();
+    ctx->cap_saved_timing = ctx->timing;
+    ctx->timing = 0;  // no timing events inside a graph
+    return COVOX_OK;
+}
+
+int covox_graph_end(covox_ctx *ctx, covox_graph **out)
+{
+    if (!ctx || !out) return COVOX_EINVAL;
+    if (!ctx->capturing) return fail(ctx, COVOX_EINVAL, "graph_end: no capture in progress");
+    *out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    ctx->stream = ctx->cap_user_stream;
+    ctx->capturing = false;
+    ctx->timing = ctx->cap_saved_timing;
+    // The captured calls ran their host bookkeeping without running any
+    // work: put every submap back as it was, keep the end state for launches.
+    for (auto &c : ctx->cap_subs) {
+        c.end = snap(c.s);
+        restore(c.s, c.start);
+    }
+    auto drop = [&](const std::string &why, int code) {
+        if (graph) (void)hipGraphDestroy(graph);
+        for (void *h : ctx->cap_host) (void)hipHostFree(h);
+        ctx->cap_host.clear();
+        ctx->cap_subs.clear();
+        return fail(ctx, code, why);
+    };
+    if (e != hipSuccess) return drop(std::string("graph_end: ") + hipGetErrorString(e), COVOX_EHIP);
+    if (ctx->capture_bad) return drop("graph_end: " + ctx->capture_why, COVOX_EINVAL);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return drop(std::string("graph_end: instantiate: ") + hipGetErrorString(e), COVOX_EHIP);
+    covox_graph *g = new covox_graph();
+    g->ctx = ctx;
+    g->graph = graph;
+    g->exec = exec;
+    g->subs = ctx->cap_subs;
+    g->host_bufs = ctx->cap_host;
+    ctx->cap_subs.clear();
+    ctx->cap_host.clear();
+    ctx->n_graphs++;
+    *out = g;
+    return COVOX_OK;
+}
+
+int covox_graph_launch(covox_graph *g)
+{
+    if (!g || !g->ctx) return COVOX_EINVAL;
+    covox_ctx *ctx = g->ctx;
+    COVOX_NOT_DURING_CAPTURE(ctx, "graph_launch");
+    // Scratch and pages were sized for the bounds at capture: a submap used
+    // without a reset in the graph must not have grown since.
+    for (const auto &c : g->subs) {
+        if (c.reset_first) continue;
+        const covox_submap *s = c.s;
+        bool ok = !s->bound_valid || c.start.bound_valid;
+        for (int a = 0; a < 3 && ok && s->bound_valid; ++a)
+            ok = s->bound_lo[a] >= c.start.bound_lo[a] && s->bound_hi[a] <= c.start.bound_hi[a];
+        if (!ok) return fail(ctx, COVOX_EINVAL, "graph_launch: a submap grew beyond its bounds at capture");
+    }
+    int rc = hip_check(ctx, hipGraphLaunch(g->exec, ctx->stream), "graph launch");
+    if (rc) return rc;
+    for (const auto &c : g->subs) {
+        covox_submap *s = c.s;
+        const bool esdf_current = c.end.esdf_version == c.end.version;
+        const bool page_current = c.end.page_version == c.end.version;
+        const uint64_t v = std::max(s->version, c.end.version) + 1;
+        if (c.reset_first) {
+            restore(s, c.end);
+            s->pts_version = 0;
+        }
+        s->version = v;
+        if (esdf_current) s->esdf_version = v;
+        if (page_current) s->page_version = v;
+    }
+    return COVOX_OK;
+}
+
+void covox_graph_destroy(covox_graph *g)
+{
+    if (!g) return;
+    covox_ctx *ctx = g->ctx;
+    if (ctx) (void)hipStreamSynchronize(ctx->stream);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    for (void *h : g->host_bufs) (void)hipHostFree(h);
+    if (ctx && --ctx->n_graphs == 0 && !ctx->capturing) {
+        for (void *p : ctx->deferred) (void)hipFree(p);
+        ctx->deferred.clear();
+    }
+    delete g;
+}
+
 void covox_default_tuning(covox_tuning *t)
 {
     if (!t) return;
@@ -983,6 +1185,7 @@ int covox_tuning_set(covox_ctx *ctx, const covox_tuning *t)
 
 int covox_autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int32_t n, covox_tuning *out)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "autotune_esdf");
     if (!ctx || (!subs && n > 0) || n < 0) return fail(ctx, COVOX_EINVAL, "autotune_esdf: bad argument");
     for (int32_t i = 0; i < n; ++i)
         if (!subs[i]) return fail(ctx, COVOX_EINVAL, "autotune_esdf: null submap");
@@ -994,6 +1197,7 @@ int covox_autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int32_t n, co
 
 int covox_timing_enable(covox_ctx *ctx, int32_t mask)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "timing_enable");
     if (!ctx) return COVOX_EINVAL;
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &u : ctx->ev_used) {
@@ -1008,6 +1212,7 @@ int covox_timing_enable(covox_ctx *ctx, int32_t mask)
 
 int covox_timing_get(covox_ctx *ctx, covox_timing *out)
 {
+    COVOX_NOT_DURING_CAPTURE(ctx, "timing_get");
     if (!ctx || !out) return COVOX_EINVAL;
     int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "timing sync");
     if (rc) return rc;

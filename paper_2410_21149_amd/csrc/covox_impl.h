@@ -154,6 +154,35 @@ struct covox_submap {
     double pbar[3] = {0, 0, 0};
 };
 
+namespace covox {
+
+// Host bookkeeping of a submap (what a graph capture saves and restores).
+struct SubmapSnap {
+    int64_t nb_upper;
+    bool bound_valid;
+    int32_t bound_lo[3], bound_hi[3];
+    uint64_t version, page_version, esdf_version, pts_version;
+    int64_t n_pts;
+};
+
+// A submap used by a graph under capture.
+struct CaptureEntry {
+    covox_submap *s;
+    SubmapSnap start, end;
+    bool reset_first;  // the first captured operation on it was a reset
+    bool integrated;
+};
+
+}  // namespace covox
+
+struct covox_graph {
+    covox_ctx *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<covox::CaptureEntry> subs;
+    std::vector<void *> host_bufs;  // pinned sources of captured copies
+};
+
 struct covox_ctx {
     covox_params p;
     int device = 0;
@@ -206,6 +235,18 @@ struct covox_ctx {
     // pinned host staging for small copies
     void *host_pin = nullptr;
     size_t host_pin_cap = 0;
+    // graph capture (on a stream of the library: the legacy default stream
+    // cannot be captured)
+    hipStream_t cap_stream = nullptr;
+    hipStream_t cap_user_stream = nullptr;
+    bool capturing = false;
+    bool capture_bad = false;
+    std::string capture_why;
+    std::vector<covox::CaptureEntry> cap_subs;
+    std::vector<void *> cap_host;
+    int32_t cap_saved_timing = 0;
+    int n_graphs = 0;                 // live graphs: scratch is never freed while > 0
+    std::vector<void *> deferred;     // scratch replaced while capturing or while graphs live
     // timing
     int32_t timing = 0;         // bit mask of timed kernel kinds
     std::vector<hipEvent_t> ev_pool;
@@ -233,6 +274,10 @@ struct TimedLaunch {
     TimedLaunch(covox_ctx *c, int k);
     ~TimedLaunch();
 };
+
+// Graph capture bookkeeping (api.hip): op 0 = reset, 1 = integration,
+// 2 = ESDF / page.
+void capture_touch(covox_ctx *ctx, covox_submap *s, int op);
 
 // Device allocation helpers (api.hip): grow-only buffers.
 int ensure_buffer(covox_ctx *ctx, void **ptr, int64_t *cap, int64_t need, size_t elem, const char *what);
@@ -306,6 +351,7 @@ int run_summaries(covox_ctx *ctx, const SummaryReq *reqs, int n);
 
 // k_net.hip
 int net_create(covox_ctx *ctx, uint64_t seed, covox_net **out);
+covox_ctx *net_ctx(const covox_net *net);
 void net_destroy(covox_net *net);
 int64_t net_num_params(const covox_net *net);
 int net_get_params(covox_net *net, float *host, int64_t n);

@@ -272,37 +272,40 @@ __device__ __forceinline__ int nearest_bit(uint64_t lo, uint64_t hi, int p)
 __device__ __forceinline__ int sq8(uint8_t v) { return v == 255 ? kBig : (int)v * (int)v; }
 __device__ __forceinline__ int inf16(uint16_t v) { return v == 0xFFFF ? kBig : (int)v; }
 
+// x pass: one wave per dense block, lane = (y, z) line of the block.  The
+// lane gathers byte y of site word z from the 2 HB + 1 blocks along x into a
+// 128-bit mask and stores the 8 distances of its line (x = 0..7, contiguous
+// in the block layout) as one 8-byte word; no LDS and no barriers, so
+// consecutive blocks of a wave overlap their loads.
 template <int NJ>
-__global__ __launch_bounds__(512) void k_edt_x_vox(const JobList<NJ> jl, const uint64_t *__restrict__ sites,
-                                                   uint8_t *__restrict__ g1, int R, int HB)
+__global__ __launch_bounds__(256) void k_edt_x(const JobList<NJ> jl, const uint64_t *__restrict__ sites,
+                                               uint8_t *__restrict__ g1, int R, int HB)
 {
     __shared__ Plan lds;
-    __shared__ uint64_t wl[(2 * kMaxHalo + 1) * 8];
     PlanView<NJ> pv;
     pv.init(jl, 8 * HB, lds);
-    const int tid = threadIdx.x;
-    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;
-    const int nb = 2 * HB + 1;
-    for (int64_t g = blockIdx.x; g < pv.t[0]; g += gridDim.x) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int y = lane & 7, z = lane >> 3;
+    for (int64_t g = (int64_t)blockIdx.x * 4 + wid; g < pv.t[0]; g += (int64_t)gridDim.x * 4) {
         const JobInfo d = pv.info(pv.template job<&JobInfo::od>(g));
         int bx, by, bz;
         dom_coords(d, g - d.od, bx, by, bz);
-        if (tid < nb * 8) {
-            const int i = tid >> 3, k = tid & 7;
-            const int nx = bx + i - HB;
-            wl[tid] = (nx >= 0 && nx < d.dim[0]) ? sites[(g + (i - HB)) * 8 + k] : 0ull;
-        }
-        __syncthreads();
         uint64_t lo = 0, hi = 0;
-        for (int i = 0; i < nb; ++i) {
-            const uint64_t byte = (wl[i * 8 + z] >> (8 * y)) & 0xFFull;
+        for (int i = 0; i < 2 * HB + 1; ++i) {
+            const int nx = bx + i - HB;
+            if (nx < 0 || nx >= d.dim[0]) continue;
+            const uint64_t byte = (sites[(g + (i - HB)) * 8 + z] >> (8 * y)) & 0xFFull;
             const int pos = 8 * i;
             if (pos < 64) lo |= byte << pos;
             else hi |= byte << (pos - 64);
         }
-        const int dist = nearest_bit(lo, hi, 8 * HB + x);
-        g1[g * 512 + tid] = dist <= R ? (uint8_t)dist : (uint8_t)255;
-        __syncthreads();
+        uint64_t out = 0;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const int dist = nearest_bit(lo, hi, 8 * HB + x);
+            out |= (uint64_t)(dist <= R ? dist : 255) << (8 * x);
+        }
+        *(uint64_t *)(g1 + g * 512 + 8 * lane) = out;
     }
 }
 
@@ -665,8 +668,8 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_X);
-        hipLaunchKernelGGL((k_edt_x_vox<NJ>), dim3(clamp_grid(nd)), dim3(512), 0, ctx->stream, jl, ctx->sites, ctx->g1,
-                           R, HB);
+        hipLaunchKernelGGL((k_edt_x<NJ>), dim3(clamp_grid((nd + 3) / 4)), dim3(256), 0, ctx->stream, jl, ctx->sites,
+                           ctx->g1, R, HB);
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Y);

@@ -672,6 +672,33 @@ int prepare_frame(covox_ctx *ctx, const covox_submap *s, const float *depth, int
     return COVOX_OK;
 }
 
+// Batch id reserved for batches captured in a graph.
+constexpr uint32_t kCapturedBatch = 0xFFFFFFFFu;
+
+// Uploads the frame parameters of a batch through pinned staging: slot k is
+// reused only once its previous upload has completed.
+int stage_frames(covox_ctx *ctx, const FrameArgs *fr, int32_t F)
+{
+    int rc;
+    const int slot = ctx->frames_slot;
+    ctx->frames_slot ^= 1;
+    if (!ctx->frames_pin[slot]) {
+        if ((rc = hip_check(ctx, hipHostMalloc((void **)&ctx->frames_pin[slot], sizeof(FrameArgs) * kMaxBatch,
+                                               hipHostMallocDefault), "frame staging")))
+            return rc;
+        if ((rc = hip_check(ctx, hipEventCreateWithFlags(&ctx->frames_ev[slot], hipEventDisableTiming),
+                            "frame staging event")))
+            return rc;
+    } else if ((rc = hip_check(ctx, hipEventSynchronize(ctx->frames_ev[slot]), "frame staging wait"))) {
+        return rc;
+    }
+    ::memcpy(ctx->frames_pin[slot], fr, sizeof(FrameArgs) * F);
+    if ((rc = hip_check(ctx, hipMemcpyAsync(ctx->frames_dev, ctx->frames_pin[slot], sizeof(FrameArgs) * F,
+                                            hipMemcpyHostToDevice, ctx->stream), "frame batch upload")))
+        return rc;
+    return hip_check(ctx, hipEventRecord(ctx->frames_ev[slot], ctx->stream), "frame staging record");
+}
+
 // Host bounds after frames with the given boxes were enqueued.
 void grow_bounds(covox_submap *s, const FrameArgs &f)
 {
@@ -747,36 +774,33 @@ int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_
     if ((rc = ensure_buffer(ctx, (void **)&ctx->blist, &ctx->blist_cap, std::max<int64_t>(1, s->cap),
                             sizeof(uint32_t), "batch block list")))
         return rc;
-    if (!s->stamp) {
-        if ((rc = hip_check(ctx, hipMalloc((void **)&s->stamp, sizeof(uint32_t) * std::max<int64_t>(1, s->cap)),
-                            "batch stamps")))
-            return rc;
+    const bool capture = ctx->capturing;
+    uint32_t batch_id;
+    if (capture) {
+        // A graph replays its batch ids: clear the stamps inside the graph
+        // and use an id that uncaptured batches never take.
         fill_u32(ctx->stream, s->stamp, 0u, std::max<int64_t>(1, s->cap));
-        s->batch_id = 0;
+        batch_id = kCapturedBatch;
+    } else {
+        if (++s->batch_id == kCapturedBatch) {  // wrapped: clear the stamps
+            fill_u32(ctx->stream, s->stamp, 0u, std::max<int64_t>(1, s->cap));
+            s->batch_id = 1;
+        }
+        batch_id = s->batch_id;
     }
-    if (++s->batch_id == 0) {  // wrapped: clear the stamps
-        fill_u32(ctx->stream, s->stamp, 0u, std::max<int64_t>(1, s->cap));
-        s->batch_id = 1;
-    }
-    // Upload through pinned staging: slot k is reused only once its previous
-    // upload has completed.
-    const int slot = ctx->frames_slot;
-    ctx->frames_slot ^= 1;
-    if (!ctx->frames_pin[slot]) {
-        if ((rc = hip_check(ctx, hipHostMalloc((void **)&ctx->frames_pin[slot], sizeof(FrameArgs) * kMaxBatch,
-                                               hipHostMallocDefault), "frame staging")))
+    if (capture) {
+        // the graph keeps its own copy of the frame parameters
+        void *h = nullptr;
+        if ((rc = hip_check(ctx, hipHostMalloc(&h, sizeof(FrameArgs) * F, hipHostMallocDefault), "frame staging")))
             return rc;
-        if ((rc = hip_check(ctx, hipEventCreateWithFlags(&ctx->frames_ev[slot], hipEventDisableTiming),
-                            "frame staging event")))
+        ctx->cap_host.push_back(h);
+        ::memcpy(h, fr.data(), sizeof(FrameArgs) * F);
+        if ((rc = hip_check(ctx, hipMemcpyAsync(ctx->frames_dev, h, sizeof(FrameArgs) * F, hipMemcpyHostToDevice,
+                                                ctx->stream), "frame batch upload")))
             return rc;
-    } else if ((rc = hip_check(ctx, hipEventSynchronize(ctx->frames_ev[slot]), "frame staging wait"))) {
+    } else if ((rc = stage_frames(ctx, fr.data(), F))) {
         return rc;
     }
-    ::memcpy(ctx->frames_pin[slot], fr.data(), sizeof(FrameArgs) * F);
-    if ((rc = hip_check(ctx, hipMemcpyAsync(ctx->frames_dev, ctx->frames_pin[slot], sizeof(FrameArgs) * F,
-                                            hipMemcpyHostToDevice, ctx->stream), "frame batch upload")))
-        return rc;
-    if ((rc = hip_check(ctx, hipEventRecord(ctx->frames_ev[slot], ctx->stream), "frame staging record"))) return rc;
     const float vs = (float)p.voxel_size, tau_f = (float)(p.trunc_vox * p.voxel_size), maxr = (float)p.max_range;
     const uint64_t tmask = (uint64_t)s->tcap - 1;
     const int64_t table_limit = (int64_t)(0.85 * (double)s->tcap);
@@ -789,7 +813,7 @@ int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_
     {
         TimedLaunch tl(ctx, COVOX_K_SCAN);
         hipLaunchKernelGGL(k_scan_batch, dim3(1), dim3(1024), 0, ctx->stream, ctx->frames_dev, F, ctx->cand, box_max,
-                           s->meta, s->cap, table_limit, s->keys, s->tkeys, s->tvals, tmask, s->stamp, s->batch_id,
+                           s->meta, s->cap, table_limit, s->keys, s->tkeys, s->tvals, tmask, s->stamp, batch_id,
                            ctx->blist, s->pin_nb_dev, s->seq);
     }
     {

@@ -557,6 +557,8 @@ void net_destroy(covox_net *net)
 
 int64_t net_num_params(const covox_net *net) { return net->P.total; }
 
+covox_ctx *net_ctx(const covox_net *net) { return net->ctx; }
+
 int net_get_params(covox_net *net, float *host, int64_t n)
 {
     if (n != net->P.total) return fail(net->ctx, COVOX_EINVAL, "net params: wrong count");
