@@ -36,6 +36,7 @@ if ROOT not in sys.path:
 
 METRIC = "TSDF+ESDF frames/s @640x480,5cm; submap-pair aligns/s at ≤1cm/0.1° err"
 HBM_PEAK_GBS = 8000.0
+OUTDOOR_TOL_RHO, OUTDOOR_TOL_THETA = 1e-5, 1e-6  # alignment stopping on the outdoor workload (m, rad)
 
 
 def _log(msg):
@@ -190,6 +191,7 @@ def align_bench(cv, torch, np, w, dev, reps=3):
     out = {"workload": "room submaps of 50 frames, %d pairs (%d distinct), perturbation 0.1 m / 5 deg yaw / 1 deg "
                        "roll-pitch" % (len(pairs), len(pairs_idx))}
     for n_starts in (1, 8):
+        tuning = ctx.autotune_align(pairs, n_starts)  # launch shape for this batch
         best = None
         for _ in range(reps):
             torch.cuda.synchronize()
@@ -241,8 +243,11 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
     w = sg.mav()
     per = w.submap_every
     nsub = w.n_frames // per
+    # Gauss-Newton stops at steps of 10 um / 1 urad here: with sigma = 0.002 z^2
+    # the steps jitter well above the default 1e-7 m / 1e-8 rad at the noise
+    # floor (a few cm), so the default would always run all 30 iterations.
     ctx = cv.Context(voxel_size=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max,
-                     block_capacity=65536)
+                     block_capacity=65536, tol_rho=OUTDOOR_TOL_RHO, tol_theta=OUTDOOR_TOL_THETA)
     subs, Tws = [], []
     for k in range(nsub):
         fr = torch.from_numpy(w.frames(k * per, (k + 1) * per)).cuda()
@@ -298,6 +303,7 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
         gts.append(T_gt)
     ctx.align_batch(pairs[:1], 1)
     align = {"pairs": n_pairs, "distinct_pairs": len(cand),
+             "tol_rho_m": OUTDOOR_TOL_RHO, "tol_theta_rad": OUTDOOR_TOL_THETA,
              "overlap_range": [float(min(c[2] for c in cand)), float(max(c[2] for c in cand))]}
     for n_starts in (1, 8):
         best = None
@@ -315,7 +321,9 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
             ok += et <= 0.01 and er <= 0.1
             errs.append(et)
         align["starts_%d" % n_starts] = {"pairs_per_s": n_pairs / best, "success": ok / n_pairs,
-                                          "median_t_err_m": float(np.median(errs)), "ms": best * 1e3}
+                                          "median_t_err_m": float(np.median(errs)), "ms": best * 1e3,
+                                          "mean_iterations": float(np.mean([x["iterations"] for x in st])),
+                                          "tuning": tuning}
     learned = learned_bench(cv, torch, np, ctx, subs, Tws, w.voxel_size)
     ctx.close()
     return {"workload": "outdoor 120x80 m, 3000 frames 640x480 fx=fy=380, 0.1 m voxels, 30 submaps of 100 frames",
@@ -373,6 +381,7 @@ def learned_bench(cv, torch, np, ctx, subs, Tws, vs, n_items=1024, reps=3):
     out = {"held_out_pairs": n_items, "distinct_pairs": len(base), "cell_m": cell, "cost_threshold": c_thr,
            "training": {k: meta[k] for k in ("seeds", "pairs_train", "steps", "batch", "final_loss") if k in meta}}
     runs = {}
+    out["tuning"] = ctx.autotune_align(items, 8)
     for name, fn in (("plain_8start", lambda: ctx.align_batch(items, 8)),
                      ("learned_refine", lambda: ctx.align_learned(net, items, cell, c_thr, 8))):
         fn()  # warm (buffers, registration points)

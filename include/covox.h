@@ -373,10 +373,19 @@ void covox_graph_destroy(covox_graph *g);
 typedef struct {
     int64_t edt_y_env_min_cols;
     int64_t edt_z_env_min_cols;
-    int64_t reserved[6];
+    /* Lanes of the workgroup that runs one Gauss-Newton problem (256 or
+     * 512).  The FP64 sums are reduced in a fixed order for a given value,
+     * so results are reproducible for a given setting and differ between
+     * settings only by rounding. */
+    int64_t align_threads;
+    /* Points a lane handles per step (1 or 2; their loads overlap).  The
+     * results do not depend on it. */
+    int64_t align_points_per_step;
+    int64_t reserved[4];
 } covox_tuning;
 
-/* Defaults: y envelopes from 2048 segments up, z always windowed. */
+/* Defaults: y envelopes from 2048 segments up, z always windowed, 256
+ * lanes per alignment problem, one point per step. */
 void covox_default_tuning(covox_tuning *t);
 int covox_tuning_get(const covox_ctx *ctx, covox_tuning *out);
 int covox_tuning_set(covox_ctx *ctx, const covox_tuning *t);
@@ -388,6 +397,12 @@ int covox_tuning_set(covox_ctx *ctx, const covox_tuning *t);
  * is the same for every shape.  out (nullable) receives the new tuning.
  * Synchronous. */
 int covox_autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int32_t n, covox_tuning *out);
+
+/* Autotuner of the alignment launch: runs covox_align_batch on these pairs
+ * with 256 and 512 lanes per problem and 1 and 2 points per step (best of 3
+ * each) and keeps the fastest.  out (nullable) receives the new tuning.
+ * Synchronous. */
+int covox_autotune_align(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_t n_starts, covox_tuning *out);
 
 /* ---------------------------------------------------------------- timing */
 

@@ -65,7 +65,8 @@ class covox_train_cfg(ctypes.Structure):
 
 class covox_tuning(ctypes.Structure):
     _fields_ = [("edt_y_env_min_cols", ctypes.c_int64), ("edt_z_env_min_cols", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 6)]
+                ("align_threads", ctypes.c_int64), ("align_points_per_step", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 4)]
 
 
 class covox_timing(ctypes.Structure):
@@ -128,6 +129,8 @@ _sig = {
     "covox_tuning_get": (ctypes.c_int, [_vp, ctypes.POINTER(covox_tuning)]),
     "covox_tuning_set": (ctypes.c_int, [_vp, ctypes.POINTER(covox_tuning)]),
     "covox_autotune_esdf": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(covox_tuning)]),
+    "covox_autotune_align": (ctypes.c_int, [_vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(covox_tuning)]),
     "covox_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "covox_timing_get": (ctypes.c_int, [_vp, ctypes.POINTER(covox_timing)]),
 }
@@ -394,21 +397,41 @@ class Context:
         return g
 
     # -- tuning
+    @staticmethod
+    def _tuning_dict(t) -> dict:
+        return {"edt_y_env_min_cols": t.edt_y_env_min_cols, "edt_z_env_min_cols": t.edt_z_env_min_cols,
+                "align_threads": t.align_threads, "align_points_per_step": t.align_points_per_step}
+
     def tuning(self) -> dict:
         t = covox_tuning()
         self._check(_lib.covox_tuning_get(self.handle, ctypes.byref(t)), "tuning_get")
-        return {"edt_y_env_min_cols": t.edt_y_env_min_cols, "edt_z_env_min_cols": t.edt_z_env_min_cols}
+        return self._tuning_dict(t)
 
-    def set_tuning(self, edt_y_env_min_cols, edt_z_env_min_cols):
+    def set_tuning(self, edt_y_env_min_cols=None, edt_z_env_min_cols=None, align_threads=None,
+                   align_points_per_step=None):
         t = covox_tuning()
-        t.edt_y_env_min_cols, t.edt_z_env_min_cols = edt_y_env_min_cols, edt_z_env_min_cols
+        self._check(_lib.covox_tuning_get(self.handle, ctypes.byref(t)), "tuning_get")
+        if edt_y_env_min_cols is not None:
+            t.edt_y_env_min_cols = edt_y_env_min_cols
+        if edt_z_env_min_cols is not None:
+            t.edt_z_env_min_cols = edt_z_env_min_cols
+        if align_threads is not None:
+            t.align_threads = align_threads
+        if align_points_per_step is not None:
+            t.align_points_per_step = align_points_per_step
         self._check(_lib.covox_tuning_set(self.handle, ctypes.byref(t)), "tuning_set")
 
     def autotune_esdf(self, subs) -> dict:
         arr = (_vp * max(len(subs), 1))(*[s.handle for s in subs])
         t = covox_tuning()
         self._check(_lib.covox_autotune_esdf(self.handle, arr, len(subs), ctypes.byref(t)), "autotune_esdf")
-        return {"edt_y_env_min_cols": t.edt_y_env_min_cols, "edt_z_env_min_cols": t.edt_z_env_min_cols}
+        return self._tuning_dict(t)
+
+    def autotune_align(self, pairs, n_starts=8) -> dict:
+        t = covox_tuning()
+        self._check(_lib.covox_autotune_align(self.handle, self._pairs(pairs), len(pairs), n_starts, ctypes.byref(t)),
+                    "autotune_align")
+        return self._tuning_dict(t)
 
     # -- timing
     def timing_enable(self, kinds=None):

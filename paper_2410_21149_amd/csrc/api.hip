@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <vector>
 
 namespace covox {
@@ -394,7 +395,8 @@ void covox_destroy(covox_ctx *ctx)
     for (void *ptr : {(void *)ctx->cand, (void *)ctx->t_key, (void *)ctx->t_idx, (void *)ctx->sites, (void *)ctx->g1,
                       (void *)ctx->g2, (void *)ctx->cnt, (void *)ctx->psum, ctx->prob_dev, ctx->res_dev, ctx->sum_dev,
                       (void *)ctx->net_in, (void *)ctx->net_out, (void *)ctx->train_y, (void *)ctx->loss_hist,
-                      (void *)ctx->frames_dev, (void *)ctx->blist})
+                      (void *)ctx->frames_dev, (void *)ctx->blist, (void *)ctx->fkeys, (void *)ctx->ffirst,
+                      (void *)ctx->fcount})
         if (ptr) (void)hipFree(ptr);
     for (void *p : ctx->deferred) (void)hipFree(p);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -1165,6 +1167,8 @@ void covox_default_tuning(covox_tuning *t)
     // allocated blocks, won at every size tried
     t->edt_y_env_min_cols = 2048;
     t->edt_z_env_min_cols = INT64_MAX;
+    t->align_threads = 256;
+    t->align_points_per_step = 1;
 }
 
 int covox_tuning_get(const covox_ctx *ctx, covox_tuning *out)
@@ -1179,6 +1183,10 @@ int covox_tuning_set(covox_ctx *ctx, const covox_tuning *t)
     if (!ctx || !t) return COVOX_EINVAL;
     if (t->edt_y_env_min_cols < 0 || t->edt_z_env_min_cols < 0)
         return fail(ctx, COVOX_EINVAL, "tuning_set: negative threshold");
+    if (t->align_threads != 256 && t->align_threads != 512)
+        return fail(ctx, COVOX_EINVAL, "tuning_set: align_threads must be 256 or 512");
+    if (t->align_points_per_step != 1 && t->align_points_per_step != 2)
+        return fail(ctx, COVOX_EINVAL, "tuning_set: align_points_per_step must be 1 or 2");
     ctx->tune = *t;
     return COVOX_OK;
 }
@@ -1191,6 +1199,37 @@ int covox_autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int32_t n, co
         if (!subs[i]) return fail(ctx, COVOX_EINVAL, "autotune_esdf: null submap");
     int rc = autotune_esdf(ctx, subs, n);
     if (rc) return rc;
+    if (out) *out = ctx->tune;
+    return COVOX_OK;
+}
+
+int covox_autotune_align(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_t n_starts, covox_tuning *out)
+{
+    COVOX_NOT_DURING_CAPTURE(ctx, "autotune_align");
+    if (!ctx || !pairs || n <= 0 || n_starts < 1) return fail(ctx, COVOX_EINVAL, "autotune_align: bad argument");
+    std::vector<double> T((size_t)16 * n), cost(n);
+    const covox_tuning saved = ctx->tune;
+    double best_ms = 1e300;
+    covox_tuning best = saved;
+    for (int cfg = 0; cfg < 4; ++cfg) {
+        ctx->tune.align_threads = cfg & 1 ? 512 : 256;
+        ctx->tune.align_points_per_step = cfg & 2 ? 2 : 1;
+        int rc = covox_align_batch(ctx, pairs, n, n_starts, T.data(), cost.data(), nullptr);  // warm
+        for (int rep = 0; rep < 3 && !rc; ++rep) {
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = covox_align_batch(ctx, pairs, n, n_starts, T.data(), cost.data(), nullptr);
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (!rc && ms < best_ms) {
+                best_ms = ms;
+                best = ctx->tune;
+            }
+        }
+        if (rc) {
+            ctx->tune = saved;
+            return rc;
+        }
+    }
+    ctx->tune = best;
     if (out) *out = ctx->tune;
     return COVOX_OK;
 }

@@ -228,6 +228,12 @@ struct covox_ctx {
     int frames_slot = 0;
     uint32_t *blist = nullptr;        // frame batch: blocks to update
     int64_t blist_cap = 0;
+    uint64_t *fkeys = nullptr;        // frame batch: first frame of each new key (temporary table)
+    int64_t fkeys_cap = 0;
+    uint32_t *ffirst = nullptr;
+    int64_t ffirst_cap = 0;
+    int64_t *fcount = nullptr;        // frame batch: new blocks per frame, then frame offsets
+    int64_t fcount_cap = 0;
     float *train_y = nullptr;    // proposal training: targets and per-step losses
     int64_t train_y_cap = 0;
     float *loss_hist = nullptr;

@@ -205,49 +205,83 @@ __device__ __forceinline__ float phi_at(const float *phi, const int32_t *page, c
     return phi[idx * 512 + (jx & 7) + 8 * (jy & 7) + 64 * (jz & 7)];
 }
 
-// Residual and Jacobian of one point; false when a cell corner is
-// unobserved (or the point is far outside A).
-__device__ __forceinline__ bool residual(const float *Tf, const float *p, float vs, const float *phi,
-                                         const int32_t *page, const DomArgs &d, float J[6], float &r)
+// phi at voxel j without branches (NaN when the voxel's block is outside the
+// page or unallocated): the loads go to clamped addresses and the result is
+// selected, so the corner loads of several points can be in flight at once.
+__device__ __forceinline__ float phi_at_nb(const float *phi, const int32_t *page, const DomArgs &d, int jx, int jy,
+                                           int jz)
 {
-    float q[3], f[3];
-    int j0[3];
+    const int x = (jx >> 3) - d.lo[0], y = (jy >> 3) - d.lo[1], z = (jz >> 3) - d.lo[2];
+    const bool in = x >= 0 && y >= 0 && z >= 0 && x < d.dim[0] && y < d.dim[1] && z < d.dim[2];
+    const int64_t pi = in ? ((int64_t)z * d.dim[1] + y) * d.dim[0] + x : 0;
+    const int32_t b = page[pi];
+    const bool ok = in && b >= 0;
+    const float v = phi[(int64_t)(ok ? b : 0) * 512 + (jx & 7) + 8 * (jy & 7) + 64 * (jz & 7)];
+    return ok ? v : __builtin_nanf("");
+}
+
+// Residual and Jacobian of U points (indices i0 + u stride, those beyond n
+// are invalid) with all their loads issued before any is used; ok[u] false
+// when a cell corner is unobserved or the point is far outside A.  Per
+// point: q = T p; g = q / vs - 1/2, j0 = floor(g), f = g - j0; r is the
+// trilinear value of the 8 corners and J = [grad; q x grad] with the
+// gradient of the trilinear patch divided by vs.
+template <int U>
+__device__ __forceinline__ void residual_u(const float *Tf, const float *pts, int64_t i0, int64_t stride, int64_t n,
+                                          float vs, const float *phi, const int32_t *page, const DomArgs &d,
+                                          float J[U][6], float r[U], bool ok[U])
+{
+    float c[U][8], f[U][3], q[U][3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-        q[a] = ((Tf[4 * a + 0] * p[0] + Tf[4 * a + 1] * p[1]) + Tf[4 * a + 2] * p[2]) + Tf[4 * a + 3];
+    for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + u * stride;
+        const bool in = i < n;
+        const int64_t ii = in ? i : 0;
+        const float p[3] = {pts[3 * ii], pts[3 * ii + 1], pts[3 * ii + 2]};
+        int j0[3];
+        bool fin = in;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float g = (q[a] / vs) - 0.5f;
-        if (!(fabsf(g) < 1.0e8f)) return false;
-        const float fl = floorf(g);
-        j0[a] = (int)fl;
-        f[a] = g - fl;
+        for (int a = 0; a < 3; ++a)
+            q[u][a] = ((Tf[4 * a + 0] * p[0] + Tf[4 * a + 1] * p[1]) + Tf[4 * a + 2] * p[2]) + Tf[4 * a + 3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float g = (q[u][a] / vs) - 0.5f;
+            fin = fin && fabsf(g) < 1.0e8f;
+            g = fabsf(g) < 1.0e8f ? g : 0.0f;  // keeps the clamped addresses sane
+            const float fl = floorf(g);
+            j0[a] = (int)fl;
+            f[u][a] = g - fl;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            c[u][k] = phi_at_nb(phi, page, d, j0[0] + (k & 1), j0[1] + ((k >> 1) & 1), j0[2] + ((k >> 2) & 1));
+        ok[u] = fin;
     }
-    float c[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        c[k] = phi_at(phi, page, d, j0[0] + (k & 1), j0[1] + ((k >> 1) & 1), j0[2] + ((k >> 2) & 1));
+    for (int u = 0; u < U; ++u) {
+        bool good = ok[u];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) good = good && !isnan(c[u][k]);
+        ok[u] = good;
+        const float *cc = c[u];
+        const float wx0 = 1.0f - f[u][0], wx1 = f[u][0], wy0 = 1.0f - f[u][1], wy1 = f[u][1], wz0 = 1.0f - f[u][2],
+                    wz1 = f[u][2];
+        const float c00 = cc[0] * wx0 + cc[1] * wx1, c10 = cc[2] * wx0 + cc[3] * wx1;
+        const float c01 = cc[4] * wx0 + cc[5] * wx1, c11 = cc[6] * wx0 + cc[7] * wx1;
+        const float c0 = c00 * wy0 + c10 * wy1, c1 = c01 * wy0 + c11 * wy1;
+        r[u] = c0 * wz0 + c1 * wz1;
+        const float dx = ((cc[1] - cc[0]) * wy0 + (cc[3] - cc[2]) * wy1) * wz0 +
+                         ((cc[5] - cc[4]) * wy0 + (cc[7] - cc[6]) * wy1) * wz1;
+        const float dy = (c10 - c00) * wz0 + (c11 - c01) * wz1;
+        const float dz = c1 - c0;
+        const float g0 = dx / vs, g1 = dy / vs, g2 = dz / vs;
+        J[u][0] = g0;
+        J[u][1] = g1;
+        J[u][2] = g2;
+        J[u][3] = q[u][1] * g2 - q[u][2] * g1;
+        J[u][4] = q[u][2] * g0 - q[u][0] * g2;
+        J[u][5] = q[u][0] * g1 - q[u][1] * g0;
     }
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) ok = ok && !isnan(c[k]);
-    if (!ok) return false;
-    const float wx0 = 1.0f - f[0], wx1 = f[0], wy0 = 1.0f - f[1], wy1 = f[1], wz0 = 1.0f - f[2], wz1 = f[2];
-    const float c00 = c[0] * wx0 + c[1] * wx1, c10 = c[2] * wx0 + c[3] * wx1;
-    const float c01 = c[4] * wx0 + c[5] * wx1, c11 = c[6] * wx0 + c[7] * wx1;
-    const float c0 = c00 * wy0 + c10 * wy1, c1 = c01 * wy0 + c11 * wy1;
-    r = c0 * wz0 + c1 * wz1;
-    const float dx = ((c[1] - c[0]) * wy0 + (c[3] - c[2]) * wy1) * wz0 + ((c[5] - c[4]) * wy0 + (c[7] - c[6]) * wy1) * wz1;
-    const float dy = (c10 - c00) * wz0 + (c11 - c01) * wz1;
-    const float dz = c1 - c0;
-    const float g0 = dx / vs, g1 = dy / vs, g2 = dz / vs;
-    J[0] = g0;
-    J[1] = g1;
-    J[2] = g2;
-    J[3] = q[1] * g2 - q[2] * g1;
-    J[4] = q[2] * g0 - q[0] * g2;
-    J[5] = q[0] * g1 - q[1] * g0;
-    return true;
 }
 
 // 6x6 Cholesky solve of H x = -b (H from the packed upper triangle).
@@ -324,8 +358,9 @@ __device__ void se3_left_update(const double xi[6], double T[12])
     for (int k = 0; k < 12; ++k) T[k] = O[k];
 }
 
-constexpr int kAlignThreads = 256;
-
+// One workgroup of kAlignThreads lanes per problem (pair and start); each
+// lane takes U points per step (same points, same order, for every U).
+template <int kAlignThreads, int U>
 __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__restrict__ probs,
                                                          const int32_t *__restrict__ order, AlignResult *res,
                                                          float vs, double tol_rho, double tol_theta, int n_min)
@@ -356,23 +391,29 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__r
         float Tf[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) Tf[k] = sTf[k];
-        for (int64_t i = tid; i < P.n_pts; i += kAlignThreads) {
-            const float p[3] = {P.pts[3 * i], P.pts[3 * i + 1], P.pts[3 * i + 2]};
-            float J[6], r;
-            if (!residual(Tf, p, vs, P.phi, P.page, d, J, r)) continue;
-            double Jd[6];
+        // each lane takes its points tid, tid + T, tid + 2T, ... in order, U
+        // per step with their loads overlapped
+        for (int64_t i0 = tid; i0 < P.n_pts; i0 += U * kAlignThreads) {
+            float J[U][6], r[U];
+            bool ok[U];
+            residual_u<U>(Tf, P.pts, i0, kAlignThreads, P.n_pts, vs, P.phi, P.page, d, J, r, ok);
 #pragma unroll
-            for (int a = 0; a < 6; ++a) Jd[a] = (double)J[a];
-            const double rd = (double)r;
-            int m = 0;
+            for (int u = 0; u < U; ++u) {
+                if (!ok[u]) continue;
+                double Jd[6];
 #pragma unroll
-            for (int a = 0; a < 6; ++a)
+                for (int a = 0; a < 6; ++a) Jd[a] = (double)J[u][a];
+                const double rd = (double)r[u];
+                int m = 0;
 #pragma unroll
-                for (int b = a; b < 6; ++b) acc[m++] += Jd[a] * Jd[b];
+                for (int a = 0; a < 6; ++a)
 #pragma unroll
-            for (int a = 0; a < 6; ++a) acc[21 + a] += Jd[a] * rd;
-            acc[27] += rd * rd;
-            acc[28] += 1.0;
+                    for (int b = a; b < 6; ++b) acc[m++] += Jd[a] * Jd[b];
+#pragma unroll
+                for (int a = 0; a < 6; ++a) acc[21 + a] += Jd[a] * rd;
+                acc[27] += rd * rd;
+                acc[28] += 1.0;
+            }
         }
 #pragma unroll
         for (int k = 0; k < 29; ++k) {
@@ -598,9 +639,26 @@ int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult 
     const int32_t *dorder = (const int32_t *)((const char *)ctx->prob_dev + sizeof(AlignProblem) * n);
     {
         TimedLaunch tl(ctx, COVOX_K_ALIGN);
-        hipLaunchKernelGGL(k_align, dim3(n), dim3(kAlignThreads), 0, ctx->stream, dprob, dorder,
-                           (AlignResult *)ctx->res_dev, (float)ctx->p.voxel_size, ctx->p.tol_rho, ctx->p.tol_theta,
-                           ctx->p.n_min);
+        AlignResult *dres = (AlignResult *)ctx->res_dev;
+        const float vs = (float)ctx->p.voxel_size;
+        const double tr = ctx->p.tol_rho, tt = ctx->p.tol_theta;
+        const int nm = ctx->p.n_min;
+        const bool two = ctx->tune.align_points_per_step == 2;
+        if (ctx->tune.align_threads == 512) {
+            if (two)
+                hipLaunchKernelGGL((k_align<512, 2>), dim3(n), dim3(512), 0, ctx->stream, dprob, dorder, dres, vs, tr,
+                                   tt, nm);
+            else
+                hipLaunchKernelGGL((k_align<512, 1>), dim3(n), dim3(512), 0, ctx->stream, dprob, dorder, dres, vs, tr,
+                                   tt, nm);
+        } else {
+            if (two)
+                hipLaunchKernelGGL((k_align<256, 2>), dim3(n), dim3(256), 0, ctx->stream, dprob, dorder, dres, vs, tr,
+                                   tt, nm);
+            else
+                hipLaunchKernelGGL((k_align<256, 1>), dim3(n), dim3(256), 0, ctx->stream, dprob, dorder, dres, vs, tr,
+                                   tt, nm);
+        }
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "align launch"))) return rc;
     if ((rc = hip_check(ctx, hipMemcpyAsync(res, ctx->res_dev, sizeof(AlignResult) * n, hipMemcpyDeviceToHost,

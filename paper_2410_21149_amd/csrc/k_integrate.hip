@@ -347,105 +347,145 @@ __global__ __launch_bounds__(256) void k_probe_batch(const FrameArgs *__restrict
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_batch(const FrameArgs *__restrict__ frames, int F,
-                                                     uint32_t *__restrict__ cand, int64_t stride, SubmapMeta *meta,
-                                                     int64_t cap, int64_t table_limit, uint64_t *keys,
-                                                     uint64_t *tkeys, uint32_t *tvals, uint64_t tmask,
-                                                     uint32_t *stamp, uint32_t batch_id, uint32_t *list,
-                                                     uint64_t *host_nb, uint64_t seq)
+// The allocation of a batch in four parallel steps, equal to per-frame
+// calls: a block is new in the first frame of the batch that touches it and
+// not before the batch; new blocks take n_blocks + rank in (first frame, key)
+// order; the frames up to the first one that would overflow the pool or the
+// table are committed, the rest dropped.
+//   k_batch_first     first frame of every new key (temporary table, min)
+//   k_batch_rank      one workgroup per frame: the frame's first-time new
+//                     blocks ranked in box order (= key order)
+//   k_batch_commit    offsets of the frames, capacity check, counts
+//   k_batch_activate  keys, table entries and the list of distinct touched
+//                     blocks of the committed frames
+
+constexpr uint32_t kFirstNew = 0x80000000u;  // candidate: first-time new, low bits = rank in its frame
+
+__global__ __launch_bounds__(256) void k_batch_first(const FrameArgs *__restrict__ frames,
+                                                     const uint32_t *__restrict__ cand, int64_t stride,
+                                                     uint64_t *fkeys, uint32_t *ffirst, uint64_t fmask)
+{
+    const int fi = blockIdx.y;
+    const FrameArgs &f = frames[fi];
+    const int64_t n_box = (int64_t)f.bdim[0] * f.bdim[1] * f.bdim[2];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_box; j += (int64_t)gridDim.x * blockDim.x) {
+        if (cand[(int64_t)fi * stride + j] != kNew) continue;
+        int bx, by, bz;
+        box_block(f, j, bx, by, bz);
+        const uint64_t key = pack_key(bx, by, bz);
+        // the table holds at least twice as many slots as candidates
+        for (uint64_t h = mix64(key) & fmask;; h = (h + 1) & fmask) {
+            const unsigned long long prev =
+                atomicCAS((unsigned long long *)&fkeys[h], (unsigned long long)kEmpty, (unsigned long long)key);
+            if (prev == kEmpty || prev == key) {
+                atomicMin(&ffirst[h], (uint32_t)fi);
+                break;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_batch_rank(const FrameArgs *__restrict__ frames, uint32_t *cand,
+                                                     int64_t stride, const uint64_t *__restrict__ fkeys,
+                                                     const uint32_t *__restrict__ ffirst, uint64_t fmask,
+                                                     int64_t *fcount)
 {
     __shared__ int64_t lds[16];
-    __shared__ int32_t red[6][16];
+    const int fi = blockIdx.x;
+    const FrameArgs &f = frames[fi];
+    const int64_t n_box = (int64_t)f.bdim[0] * f.bdim[1] * f.bdim[2];
+    uint32_t *cf = cand + (int64_t)fi * stride;
     const int tid = threadIdx.x;
-    const int64_t n_start = meta->n_blocks;
-    int64_t n0 = n_start, n_list = 0;
-    int committed = F;
-    int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
-    for (int fi = 0; fi < F; ++fi) {
-        const FrameArgs f = frames[fi];
-        const int64_t n_box = (int64_t)f.bdim[0] * f.bdim[1] * f.bdim[2];
-        uint32_t *cf = cand + (int64_t)fi * stride;
-        const int64_t C = (n_box + blockDim.x - 1) / blockDim.x;
-        const int64_t beg = std::min<int64_t>((int64_t)tid * C, n_box);
-        const int64_t end = std::min<int64_t>(beg + C, n_box);
-        // resolve blocks created by earlier frames of the batch; count
-        int64_t nn = 0, nf = 0;
-        for (int64_t j = beg; j < end; ++j) {
-            uint32_t v = cf[j];
-            if (!v) continue;
-            if (v == kNew) {
-                int bx, by, bz;
-                box_block(f, j, bx, by, bz);
-                const int64_t idx = hash_find(tkeys, tvals, tmask, pack_key(bx, by, bz));
-                if (idx >= 0) {
-                    v = (uint32_t)idx + 1u;
-                    cf[j] = v;
-                }
-            }
-            if (v == kNew) { ++nn; ++nf; }
-            else nf += stamp[v - 1u] != batch_id;
-        }
-        int64_t tot_n, tot_f;
-        int64_t off_n = block_exclusive_scan(nn, lds, &tot_n);
-        int64_t off_f = block_exclusive_scan(nf, lds, &tot_f);
-        if (n0 + tot_n > cap || n0 + tot_n > table_limit) {  // uniform: the frame and the rest are not committed
-            if (tid == 0) meta->status = n0 + tot_n > cap ? COVOX_EPOOL_FULL : COVOX_ETABLE_FULL;
-            committed = fi;
-            break;
-        }
-        for (int64_t j = beg; j < end; ++j) {
-            const uint32_t v = cf[j];
-            if (!v) continue;
-            if (v == kNew) {
-                int bx, by, bz;
-                box_block(f, j, bx, by, bz);
-                const uint64_t key = pack_key(bx, by, bz);
-                const uint32_t idx = (uint32_t)(n0 + off_n++);
-                keys[idx] = key;
-                hash_insert(tkeys, tvals, tmask, key, idx);
-                stamp[idx] = batch_id;
-                list[n_list + off_f++] = idx;
-                lo[0] = min(lo[0], bx); lo[1] = min(lo[1], by); lo[2] = min(lo[2], bz);
-                hi[0] = max(hi[0], bx); hi[1] = max(hi[1], by); hi[2] = max(hi[2], bz);
-            } else if (stamp[v - 1u] != batch_id) {
-                stamp[v - 1u] = batch_id;
-                list[n_list + off_f++] = v - 1u;
-            }
-        }
-        n0 += tot_n;
-        n_list += tot_f;
-        // The next frame reads the table and stamps written here by other
-        // lanes (table slots through device-scope atomics): complete the
-        // writes, then drop any stale copy from this CU's vector cache.
-        __threadfence();
-        __syncthreads();
-        __threadfence();
+    const int64_t C = (n_box + blockDim.x - 1) / blockDim.x;
+    const int64_t beg = std::min<int64_t>((int64_t)tid * C, n_box);
+    const int64_t end = std::min<int64_t>(beg + C, n_box);
+    int64_t nn = 0;
+    for (int64_t j = beg; j < end; ++j) {
+        if (cf[j] != kNew) continue;
+        int bx, by, bz;
+        box_block(f, j, bx, by, bz);
+        const uint64_t key = pack_key(bx, by, bz);
+        uint64_t h = mix64(key) & fmask;
+        while (fkeys[h] != key) h = (h + 1) & fmask;  // present: inserted by this candidate
+        if (ffirst[h] == (uint32_t)fi) ++nn;
+        else cf[j] = 0;  // created by an earlier frame of the batch
     }
-    const int lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        for (int o = 32; o > 0; o >>= 1) {
-            lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
-            hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
-        }
-        if (lane == 0) { red[a][wid] = lo[a]; red[3 + a][wid] = hi[a]; }
+    int64_t tot;
+    int64_t off = block_exclusive_scan(nn, lds, &tot);
+    for (int64_t j = beg; j < end; ++j)
+        if (cf[j] == kNew) cf[j] = kFirstNew | (uint32_t)(off++);
+    if (tid == 0) fcount[fi] = tot;
+}
+
+// One wave: F <= 64 frames.
+__global__ __launch_bounds__(64) void k_batch_commit(int F, const int64_t *__restrict__ fcount, int64_t *foff,
+                                                     SubmapMeta *meta, int64_t cap, int64_t table_limit,
+                                                     uint64_t *host_nb, uint64_t seq)
+{
+    const int lane = threadIdx.x;
+    const int64_t n0 = meta->n_blocks;
+    const int64_t c = lane < F ? fcount[lane] : 0;
+    int64_t incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
     }
-    __syncthreads();
-    if (tid == 0) {
-        if (n0 > n_start) {
-            for (int a = 0; a < 3; ++a) {
-                int32_t L = INT32_MAX, Hh = INT32_MIN;
-                for (int w = 0; w < nw; ++w) { L = min(L, red[a][w]); Hh = max(Hh, red[3 + a][w]); }
-                if (n_start == 0) { meta->bmin[a] = L; meta->bmax[a] = Hh; }
-                else { meta->bmin[a] = min(meta->bmin[a], L); meta->bmax[a] = max(meta->bmax[a], Hh); }
-            }
-        }
-        meta->n_blocks = n0;
-        meta->n_new = (int32_t)(n0 - n_start);
-        meta->n_touched = (int32_t)n_list;
-        meta->batch_n0 = n_start;
+    const bool over = lane < F && (n0 + incl > cap || n0 + incl > table_limit);
+    const uint64_t m = __ballot(over);
+    const int committed = m ? __ffsll((long long)m) - 1 : F;
+    if (lane < F) foff[lane] = n0 + incl - c;
+    // (all lanes take part in the shuffles)
+    const int src = committed < F ? committed : 0;
+    const int64_t before_fail = __shfl(incl - c, src, 64);
+    const int64_t at_fail = __shfl(incl, src, 64);
+    const int64_t total_all = __shfl(incl, 63, 64);
+    if (lane == 0) {
+        const int64_t n_new = committed < F ? before_fail : total_all;
+        if (committed < F) meta->status = n0 + at_fail > cap ? COVOX_EPOOL_FULL : COVOX_ETABLE_FULL;
+        if (n0 == 0 && n_new > 0)
+            for (int a = 0; a < 3; ++a) { meta->bmin[a] = INT32_MAX; meta->bmax[a] = INT32_MIN; }
+        meta->n_blocks = n0 + n_new;
+        meta->n_new = (int32_t)n_new;
+        meta->n_touched = 0;
+        meta->batch_n0 = n0;
         meta->batch_frames = committed;
-        publish_count(host_nb, seq, n0);
+        publish_count(host_nb, seq, n0 + n_new);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_activate(const FrameArgs *__restrict__ frames,
+                                                        const uint32_t *__restrict__ cand, int64_t stride,
+                                                        const int64_t *__restrict__ foff, SubmapMeta *meta,
+                                                        uint64_t *keys, uint64_t *tkeys, uint32_t *tvals,
+                                                        uint64_t tmask, uint32_t *stamp, uint32_t batch_id,
+                                                        uint32_t *list)
+{
+    const int fi = blockIdx.y;
+    if (fi >= meta->batch_frames) return;  // uniform: frame not committed
+    const FrameArgs &f = frames[fi];
+    const int64_t n_box = (int64_t)f.bdim[0] * f.bdim[1] * f.bdim[2];
+    const int64_t base = foff[fi];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_box; j += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = cand[(int64_t)fi * stride + j];
+        if (!v) continue;
+        uint32_t idx;
+        bool listed;
+        if (v & kFirstNew) {
+            int bx, by, bz;
+            box_block(f, j, bx, by, bz);
+            const uint64_t key = pack_key(bx, by, bz);
+            idx = (uint32_t)(base + (v & ~kFirstNew));
+            keys[idx] = key;
+            hash_insert(tkeys, tvals, tmask, key, idx);
+            stamp[idx] = batch_id;
+            listed = true;
+            atomicMin(&meta->bmin[0], bx); atomicMin(&meta->bmin[1], by); atomicMin(&meta->bmin[2], bz);
+            atomicMax(&meta->bmax[0], bx); atomicMax(&meta->bmax[1], by); atomicMax(&meta->bmax[2], bz);
+        } else {
+            idx = v - 1u;  // existed before the batch
+            listed = atomicExch(&stamp[idx], batch_id) != batch_id;
+        }
+        if (listed) list[atomicAdd(&meta->n_touched, 1)] = idx;
     }
 }
 
@@ -774,6 +814,17 @@ int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_
     if ((rc = ensure_buffer(ctx, (void **)&ctx->blist, &ctx->blist_cap, std::max<int64_t>(1, s->cap),
                             sizeof(uint32_t), "batch block list")))
         return rc;
+    // first-frame table: a power of two holding every candidate twice over
+    int64_t fslots = 1;
+    while (fslots < 2 * box_sum) fslots <<= 1;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->fkeys, &ctx->fkeys_cap, fslots, sizeof(uint64_t), "first-frame keys")))
+        return rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->ffirst, &ctx->ffirst_cap, fslots, sizeof(uint32_t),
+                            "first-frame values")))
+        return rc;
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->fcount, &ctx->fcount_cap, 2 * kMaxBatch, sizeof(int64_t),
+                            "frame counts")))
+        return rc;
     const bool capture = ctx->capturing;
     uint32_t batch_id;
     if (capture) {
@@ -812,9 +863,18 @@ int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_
     }
     {
         TimedLaunch tl(ctx, COVOX_K_SCAN);
-        hipLaunchKernelGGL(k_scan_batch, dim3(1), dim3(1024), 0, ctx->stream, ctx->frames_dev, F, ctx->cand, box_max,
-                           s->meta, s->cap, table_limit, s->keys, s->tkeys, s->tvals, tmask, s->stamp, batch_id,
-                           ctx->blist, s->pin_nb_dev, s->seq);
+        const unsigned gx = (unsigned)std::min<int64_t>((box_max + 255) / 256, 256);
+        fill_u64(ctx->stream, ctx->fkeys, kEmpty, fslots);
+        fill_u32(ctx->stream, ctx->ffirst, 0xFFFFFFFFu, fslots);
+        hipLaunchKernelGGL(k_batch_first, dim3(gx, (unsigned)F), dim3(256), 0, ctx->stream, ctx->frames_dev, ctx->cand,
+                           box_max, ctx->fkeys, ctx->ffirst, (uint64_t)fslots - 1);
+        hipLaunchKernelGGL(k_batch_rank, dim3((unsigned)F), dim3(1024), 0, ctx->stream, ctx->frames_dev, ctx->cand,
+                           box_max, ctx->fkeys, ctx->ffirst, (uint64_t)fslots - 1, ctx->fcount);
+        hipLaunchKernelGGL(k_batch_commit, dim3(1), dim3(64), 0, ctx->stream, F, ctx->fcount, ctx->fcount + kMaxBatch,
+                           s->meta, s->cap, table_limit, s->pin_nb_dev, s->seq);
+        hipLaunchKernelGGL(k_batch_activate, dim3(gx, (unsigned)F), dim3(256), 0, ctx->stream, ctx->frames_dev,
+                           ctx->cand, box_max, ctx->fcount + kMaxBatch, s->meta, s->keys, s->tkeys, s->tvals, tmask,
+                           s->stamp, batch_id, ctx->blist);
     }
     {
         // one wave per listed block (at most min(capacity, sum of the boxes))

@@ -330,6 +330,34 @@ def test_multistart_and_batch_match_single_calls(cv):
     ctx.close()
 
 
+def test_alignment_workgroup_sizes_agree_with_checker(cv):
+    """256 and 512 lanes per problem (tuning.align_threads) reduce the FP64
+    sums in different orders: every setting meets the pose bar against the
+    checker; 1 or 2 points per step give identical results; the autotuner
+    keeps one of the settings."""
+    ctx = _ctx(cv)
+    A, B, rA, rB = _pair_from_tiny(cv, ctx)
+    pts = rB.iso_points()
+    T0 = orc.se3_exp(np.array([0.03, -0.02, 0.01, 0.02, -0.01, 0.03]))
+    r = orc.align(rA, pts, T0)
+    for lanes in (256, 512):
+        got = []
+        for per_step in (1, 2):
+            ctx.set_tuning(align_threads=lanes, align_points_per_step=per_step)
+            Tg, cg, st = ctx.align_submaps(A, B, T0)
+            assert st["status"] == r["status"] and st["n_used"] == r["n"]
+            dt, dr = _pose_err(Tg, r["T"])
+            assert dt <= 1e-6 and dr <= 1e-6, (lanes, dt, dr)
+            got.append((Tg, cg))
+        # points per step change nothing, bit for bit
+        assert np.array_equal(got[0][0], got[1][0]) and got[0][1] == got[1][1]
+    with pytest.raises(cv.CovoxError):
+        ctx.set_tuning(align_threads=300)
+    t = ctx.autotune_align([(A, B, T0), (B, A, np.linalg.inv(T0))], n_starts=8)
+    assert t["align_threads"] in (256, 512) and t["align_points_per_step"] in (1, 2)
+    ctx.close()
+
+
 def test_alignment_needs_current_esdf_and_enough_points(cv):
     import torch
     ctx = _ctx(cv)
