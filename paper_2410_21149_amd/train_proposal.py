@@ -58,13 +58,13 @@ def block_pairs(ctx, subs, Tws, vs, min_overlap=0.2, reach=4):
     return out
 
 
-def build_scene(cv, torch, ctx, seed):
+def build_scene(cv, torch, ctx, seed, scale=1.0):
     """Maps one MAV scene into 30 gravity-aligned submaps with current
     ESDFs; returns (submaps, T_world_submap list) or None if the generator
     finds no path for this seed."""
     import scenegen as sg
     try:
-        w = sg.mav(seed=seed)
+        w = sg.mav(seed=seed, scale=scale)
     except RuntimeError:
         return None
     per = w.submap_every
@@ -113,6 +113,9 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--cell", type=float, default=1.0)
     ap.add_argument("--net-seed", type=int, default=1)
+    ap.add_argument("--block-capacity", type=int, default=8192, help="blocks per submap (submaps that overflow are skipped)")
+    ap.add_argument("--render-scale", type=float, default=1.0,
+                    help="render the training scenes at this fraction of 640x480 (same field of view)")
     ap.add_argument("--out", default=DEFAULT_OUT)
     a = ap.parse_args(argv)
     if ROOT not in sys.path:
@@ -121,11 +124,11 @@ def main(argv=None):
 
     import paper_2410_21149_amd as cv
     t0 = time.perf_counter()
-    ctx = cv.Context(voxel_size=0.1, trunc_vox=4, max_range=10.0, d_max=3.0, block_capacity=8192)
+    ctx = cv.Context(voxel_size=0.1, trunc_vox=4, max_range=10.0, d_max=3.0, block_capacity=a.block_capacity)
     scenes, seeds = [], []
     sd = a.seed0
     while len(scenes) < a.scenes:
-        got = build_scene(cv, torch, ctx, sd)
+        got = build_scene(cv, torch, ctx, sd, a.render_scale)
         if got is not None:
             scenes.append(got)
             seeds.append(sd)
@@ -171,6 +174,7 @@ def main(argv=None):
             c_thr = float(np.percentile(ok_cost, 95))
         _log("calibration: %d of %d aligned by plain 8-start, c_thr %.4g" % (len(ok_cost), len(items), c_thr))
     meta = {"seeds": seeds, "calibration_seeds": seeds[len(seeds) - n_cal:], "pairs_train": len(train),
+            "render_scale": a.render_scale,
             "steps": a.steps, "batch": a.batch, "lr": a.lr, "cell": a.cell, "c_thr": c_thr,
             "final_loss": float(np.mean(losses[-100:])), "seconds": time.perf_counter() - t0}
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)

@@ -473,11 +473,14 @@ def _wall_boxes(lo, hi, axis, door_c, door_w, door_h, z0):
     return out
 
 
-def mav(seed: int = 3, n_frames: int = 3000, path_length: float = 400.0, noise: bool = True) -> Workload:
+def mav(seed: int = 3, n_frames: int = 3000, path_length: float = 400.0, noise: bool = True,
+        scale: float = 1.0) -> Workload:
     """Outdoor 120 x 80 x 20 m scene: rubble heightfield (4 octaves of value
     noise, 0.5 m samples) plus 15-30 buildings with 0.3 m walls and door
     openings; a seeded spline at 2-8 m above ground that passes through one
-    building; 640x480 frames, fx = fy = 380, range 10 m, sigma = 0.002 z^2."""
+    building; 640x480 frames, fx = fy = 380, range 10 m, sigma = 0.002 z^2.
+    scale < 1 renders the same views with fewer pixels (same field of view:
+    W, H, fx, fy scaled, pixel-centre principal point)."""
     rng = np.random.default_rng(seed)
     hs, X, Y = 0.5, 120.0, 80.0
     nx, ny = int(X / hs) + 1, int(Y / hs) + 1
@@ -601,8 +604,9 @@ def mav(seed: int = 3, n_frames: int = 3000, path_length: float = 400.0, noise: 
         pitch = 0.0 if inside else math.radians(-30.0)
         fwd = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
         poses.append(pose_from_forward(pos[k], fwd))
-    cam = Camera(H=480, W=640, fx=380.0, fy=380.0, cx=319.5, cy=239.5, max_range=10.0,
-                 noise_model=2 if noise else 0, noise_a=0.002)
+    Wd, Hd = int(round(640 * scale)), int(round(480 * scale))
+    cam = Camera(H=Hd, W=Wd, fx=380.0 * scale, fy=380.0 * scale, cx=(Wd - 1) / 2.0, cy=(Hd - 1) / 2.0,
+                 max_range=10.0, noise_model=2 if noise else 0, noise_a=0.002)
     return Workload("mav", scene, cam, np.array(poses), seed, voxel_size=0.10, d_max=3.0, submap_every=100)
 
 
