@@ -459,6 +459,76 @@ def test_outdoor_submap_parity_and_batched_esdf(cv):
     ctx.close()
 
 
+def test_outdoor_alignment_and_summary_parity(cv):
+    """Two overlapping outdoor submaps (0.1 m voxels, 10 m range, noise
+    0.002 z^2) at full frame size: registration points bit-exact, alignment
+    from perturbed priors within the pose bar of the checker (same status,
+    iterations and residual count), and the proposal's 1 m summaries against
+    the checker's binary64 ones."""
+    import torch
+    w = sg.mav(n_frames=80)
+    K = w.cam.K
+    params = dict(voxel_size=0.1, trunc_vox=4, max_range=10.0, d_max=3.0, block_capacity=16384)
+    ctx = _ctx(cv, **params)
+    fr = w.frames(0, 70)
+    dev = torch.from_numpy(fr).cuda()
+    spans = [(0, 40), (30, 70)]
+    gs, rs, Ts = [], [], []
+    for a, b in spans:
+        T = sg.gravity_aligned(w.poses[a])
+        s = ctx.submap_create(T)
+        ctx.map_sequence(s, dev[a:b], K, w.poses[a:b], esdf_every=0)
+        r = orc.Submap(orc.Params(vs=0.1, trunc_vox=4, max_range=10.0, d_max=3.0), T)
+        for f in range(a, b):
+            r.integrate(fr[f], K, w.poses[f])
+        r.update_esdf()
+        gs.append(s)
+        rs.append(r)
+        Ts.append(T)
+    pts = rs[1].iso_points()
+    assert np.array_equal(ctx.export_points(gs[1]), pts) and len(pts) > 1000
+    T_gt = np.linalg.inv(Ts[0]) @ Ts[1]
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        xi = np.concatenate([rng.uniform(-0.3, 0.3, 3), [0.0, 0.0, rng.uniform(-0.1, 0.1)]])
+        T0 = T_gt @ orc.se3_exp(xi)
+        Tg, cg, st = ctx.align_submaps(gs[0], gs[1], T0)
+        r = orc.align(rs[0], pts, T0)
+        assert st["status"] == r["status"] and st["iterations"] == r["iters"] and st["n_used"] == r["n"]
+        dt, dr = _pose_err(Tg, r["T"])
+        assert dt <= 1e-6 and dr <= 1e-6, (dt, dr)
+    # summaries of A on the proposal grid (1 m cells) and of B through T_gt
+    c = ctx.export_points(gs[0]).astype(np.float64).mean(axis=0)
+    G = np.eye(4)
+    G[:3, 3] = c
+    for sm, rsub, T in ((gs[0], rs[0], G), (gs[1], rs[1], np.linalg.inv(T_gt) @ G)):
+        out = torch.zeros((32768, 4), dtype=torch.float32, device="cuda")
+        ctx.summaries([(sm, T, 1.0, out, 0)])
+        g = out.cpu().numpy().astype(np.float64)
+        want = orc.summary(rsub, T, 1.0)
+        both = (g[:, 1] == 1) & (want[:, 1] == 1)
+        assert both.sum() > 300  # a 40-frame submap covers several hundred 1 m cells
+        assert np.mean(g[:, 1] != want[:, 1]) < 1e-3  # masks: only cells at voxel-centre planes may differ
+        assert np.abs(g[both, 0] - want[both, 0]).max() <= 2e-5
+    ctx.close()
+
+
+def test_frustum_outside_the_key_range_is_rejected(cv):
+    """A camera whose frustum leaves the addressable block range (2^20
+    blocks per axis) is refused before any launch; the submap is unchanged."""
+    import torch
+    w = sg.tiny()
+    ctx = _ctx(cv)
+    s = ctx.submap_create()
+    T = np.array(w.poses[0], np.float64).copy()
+    T[0, 3] = 0.05 * 8 * (2 ** 20)  # beyond the last block along x
+    with pytest.raises(cv.CovoxError) as e:
+        ctx.integrate_depth(s, torch.from_numpy(w.frame(0)).cuda(), w.cam.K, T)
+    assert e.value.code == cv.EINVAL
+    assert ctx.submap_info(s)["n_blocks"] == 0
+    ctx.close()
+
+
 def test_precision_statement_fp16_fp32_vs_fp64(cv):
     """Error of the binary32 and binary16 storage paths against the binary64
     checker on 60 room frames: max / RMS of |D - D64|, |W - W64| and
