@@ -14,7 +14,7 @@ Also reported on the same JSON line:
   roofline      the dominant kernel: algorithmic bytes per launch divided by
                 its mean duration from HIP events recorded around each of its
                 launches in the timed region, against 8 TB/s;
-  cpu_baseline  the reference checker (single-threaded C) on a bounded
+  cpu_baseline  the oracle (single-threaded C) on a bounded
                 prefix of the same workload;
   align         ESDF alignment of overlapping room submaps: pairs/s and the
                 fraction within 1 cm / 0.1 degrees, 1 start and 8 starts.
@@ -140,7 +140,7 @@ def frustum_box_blocks(w, f, vs, np):
 
 
 def cpu_baseline(w, frames, budget_s):
-    """The reference checker on a prefix of the workload: integrate + ESDF per
+    """The oracle on a prefix of the workload: integrate + ESDF per
     frame until the time budget is spent (whole frames)."""
     import oracle as orc
     ref = orc.Submap(orc.Params(vs=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max))
@@ -456,12 +456,13 @@ def main():
     ap.add_argument("--no-align", action="store_true")
     ap.add_argument("--no-mav", action="store_true")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"])
-    ap.add_argument("--no-graph", action="store_true", help="time eager calls instead of graph replays")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage room timing")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU runs are not part of it",
+        print("bench.py: runs on one GPU only (--gpus 1); multi-GPU runs are not supported",
               file=sys.stderr)
         sys.exit(2)
 
@@ -575,6 +576,24 @@ def main():
         "kernel_ms_per_step": {k: v[0] for k, v in prof.items() if v[1]},
         "tuning": room_tuning,
     }
+    if prec == cv.FP32 and not args.no_fp16:
+        # the same steps with FP16 storage of D and W (FP32 arithmetic)
+        _log("room workload with FP16 storage")
+        c16 = cv.Context(voxel_size=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max,
+                         block_capacity=131072, precision=cv.FP16)
+        c16.set_tuning(**{k: v for k, v in room_tuning.items()})
+        s16 = c16.submap_create()
+        for _ in range(args.warmup):
+            c16.submap_reset(s16)
+            c16.map_sequence(s16, dev, K, w.poses, esdf_every=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            c16.submap_reset(s16)
+            c16.map_sequence(s16, dev, K, w.poses, esdf_every=1)
+        torch.cuda.synchronize()
+        result["config"]["fp16_storage_frames_per_s"] = w.n_frames * args.steps / (time.perf_counter() - t0)
+        c16.close()
     if not args.no_align:
         _log("alignment pairs")
         result["align"] = align_bench(cv, torch, np, w, dev)
@@ -582,7 +601,7 @@ def main():
         _log("outdoor workload: 30 submaps, batched ESDF and alignment")
         result["mav"] = mav_bench(cv, torch, np)
     if not args.no_cpu_baseline:
-        _log("cpu baseline (reference checker)")
+        _log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(w, frames, args.cpu_seconds)
     ctx.close()
     print(json.dumps(result), flush=True)

@@ -1,4 +1,4 @@
-"""covox reference checker -- TEST INFRASTRUCTURE ONLY.
+"""covox oracle -- TEST INFRASTRUCTURE ONLY.
 
 A thin ctypes wrapper around ``covox_oracle.c``: a plain, slow CPU
 implementation of projective TSDF integration, the exact truncated ESDF and

@@ -1,5 +1,5 @@
 /*
- * covox reference checker, learned-proposal part -- TEST INFRASTRUCTURE ONLY.
+ * covox oracle, learned-proposal part -- TEST INFRASTRUCTURE ONLY.
  *
  * Plain loops for the coarse ESDF summaries and for the small 3-D
  * convolutional network (forward, loss, backward) that the GPU library runs

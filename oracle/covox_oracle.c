@@ -1,5 +1,5 @@
 /*
- * covox reference checker -- TEST INFRASTRUCTURE ONLY.
+ * covox oracle -- TEST INFRASTRUCTURE ONLY.
  *
  * A plain, slow CPU implementation of what the GPU library computes, used by
  * the tests, the smoke check and the CPU-baseline leg of the benchmark.  It
@@ -710,7 +710,7 @@ static double phi_at(const orc_submap *A, const int64_t j[3])
 }
 
 /* phi of voxel (x, y, z) of submap s, NaN when unallocated (for the
- * summary checker). */
+ * summary oracle). */
 double orc_phi_at_voxel(const orc_submap *s, int64_t x, int64_t y, int64_t z)
 {
     int64_t j[3] = {x, y, z};

@@ -1,6 +1,6 @@
 """Seeded synthetic scenes, trajectories and depth frames.
 
-This package generates inputs only.  Both the reference checker (``oracle/``)
+This package generates inputs only.  Both the oracle (``oracle/``)
 and the GPU library consume its output; it holds no part of the mapping
 method itself (no TSDF, ESDF or alignment arithmetic).
 

@@ -1,7 +1,7 @@
 /*
  * Seeded synthetic depth renderer (input generation only).
  *
- * This file produces the depth frames that both the reference checker and
+ * This file produces the depth frames that both the oracle and
  * the GPU path consume.  It contains no part of the mapping method: only
  * ray/primitive intersection, a counter-based random number generator and
  * the sensor noise model of the synthetic workloads.

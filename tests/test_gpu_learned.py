@@ -1,6 +1,6 @@
 """GPU parity of the learned pose proposal: coarse ESDF summaries, the bf16
 matrix-core network (forward and gradients) and the proposal-then-refine
-driver, each through the C ABI against the checker on the same seeded
+driver, each through the C ABI against the oracle on the same seeded
 inputs.
 
 Bars: summary values within 2e-5 (binary32 vs binary64 trilinear weights;
@@ -10,7 +10,7 @@ position can then select the neighbouring corner set); network outputs within
 2 % of the output scale (bf16 storage of every activation: a one-ulp
 difference in the accumulation order can flip a bf16 rounding, 2^-8 relative,
 and such flips compound over four layers); gradients within 3 % relative L2
-per layer against binary64 backpropagation through the checker's bf16 forward
+per layer against binary64 backpropagation through the oracle's bf16 forward
 pass.  The driver with a zero cost threshold must give exactly what plain
 multi-start gives (every pair falls back)."""
 import math

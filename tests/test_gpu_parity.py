@@ -1,11 +1,12 @@
 """GPU parity: the HIP library (through the C ABI) against the reference
-checker on the same seeded inputs.
+oracle on the same seeded inputs.
 
 Bars: allocated block set, buffer indices and home buckets bit-exact; TSDF D
 and W within 1e-4 m (binary32 storage; bit-exact expected, same pinned
 operation order); ESDF phi within 1e-4 m with identical unobserved sets;
 poses within 1e-6 (translation in m, rotation angle in rad)."""
 import math
+import tempfile
 
 import numpy as np
 import pytest
@@ -146,9 +147,9 @@ def test_batch_integration_equals_sequential(cv):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16"])
-def test_batched_integration_matches_checker_and_single_frames(cv, precision):
+def test_batched_integration_matches_oracle_and_single_frames(cv, precision):
     """Frame batches (one probe, one scan and one update launch per batch)
-    against per-frame calls and the checker: blocks in (first frame, key)
+    against per-frame calls and the oracle: blocks in (first frame, key)
     order, D and W bit for bit, also in binary16 storage where every frame's
     result is rounded to the stored precision."""
     import torch
@@ -330,10 +331,10 @@ def test_multistart_and_batch_match_single_calls(cv):
     ctx.close()
 
 
-def test_alignment_workgroup_sizes_agree_with_checker(cv):
+def test_alignment_workgroup_sizes_agree_with_oracle(cv):
     """256 and 512 lanes per problem (tuning.align_threads) reduce the FP64
     sums in different orders: every setting meets the pose bar against the
-    checker; 1 or 2 points per step give identical results; the autotuner
+    oracle; 1 or 2 points per step give identical results; the autotuner
     keeps one of the settings."""
     ctx = _ctx(cv)
     A, B, rA, rB = _pair_from_tiny(cv, ctx)
@@ -377,7 +378,7 @@ def test_alignment_needs_current_esdf_and_enough_points(cv):
 @pytest.mark.parametrize("workload", ["tiny", "room40"])
 def test_esdf_modes_parity(cv, mode, workload, monkeypatch):
     """Both pass shapes of the ESDF (voxel-parallel windowed search and
-    per-line lower envelopes) give the checker's phi."""
+    per-line lower envelopes) give the oracle's phi."""
     import torch
     monkeypatch.setenv("COVOX_EDT_MODE", mode)
     w = sg.tiny() if workload == "tiny" else sg.room(n_frames=40)
@@ -398,7 +399,7 @@ def test_esdf_modes_parity(cv, mode, workload, monkeypatch):
 def test_mixed_pass_shapes_and_autotune_leave_phi_unchanged(cv):
     """Every combination of y and z pass shapes (chosen through the tuning
     thresholds) and the autotuner's own runs give the same phi, bit for bit,
-    as the checker; the autotuner returns valid thresholds."""
+    as the oracle; the autotuner returns valid thresholds."""
     import torch
     w = sg.room(n_frames=30)
     fr = w.frames()
@@ -427,7 +428,7 @@ def test_mixed_pass_shapes_and_autotune_leave_phi_unchanged(cv):
 
 def test_outdoor_submap_parity_and_batched_esdf(cv):
     """An outdoor submap at the large-scale configuration (0.1 m voxels,
-    10 m range, ESDF to 3 m) against the checker, and the batched ESDF of
+    10 m range, ESDF to 3 m) against the oracle, and the batched ESDF of
     several submaps equal to per-submap updates."""
     import torch
     w = sg.mav(n_frames=600)
@@ -462,9 +463,9 @@ def test_outdoor_submap_parity_and_batched_esdf(cv):
 def test_outdoor_alignment_and_summary_parity(cv):
     """Two overlapping outdoor submaps (0.1 m voxels, 10 m range, noise
     0.002 z^2) at full frame size: registration points bit-exact, alignment
-    from perturbed priors within the pose bar of the checker (same status,
+    from perturbed priors within the pose bar of the oracle (same status,
     iterations and residual count), and the proposal's 1 m summaries against
-    the checker's binary64 ones."""
+    the oracle's binary64 ones."""
     import torch
     w = sg.mav(n_frames=80)
     K = w.cam.K
@@ -531,7 +532,7 @@ def test_frustum_outside_the_key_range_is_rejected(cv):
 
 def test_precision_statement_fp16_fp32_vs_fp64(cv):
     """Error of the binary32 and binary16 storage paths against the binary64
-    checker on 60 room frames: max / RMS of |D - D64|, |W - W64| and
+    oracle on 60 room frames: max / RMS of |D - D64|, |W - W64| and
     |phi - phi64| over voxels with equal weights, and the number of
     voxel-frame validity decisions that differ from binary64 (pixel-edge and
     truncation ties; they appear as weight differences).  A frame can also
@@ -578,7 +579,7 @@ def test_precision_statement_fp16_fp32_vs_fp64(cv):
                         "phi_max": float(dP.max()), "phi_rms": float(np.sqrt((dP ** 2).mean())),
                         "phi_over_1e-4": int(np.count_nonzero(dP > 1e-4))}
         ctx.close()
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    out = os.environ.get("COVOX_REPORT_DIR", tempfile.gettempdir())  # where the statement is written
     os.makedirs(out, exist_ok=True)
     with open(os.path.join(out, "precision_report.json"), "w") as fh:
         json.dump(report, fh, indent=1)

@@ -1,4 +1,4 @@
-"""Pins of the checker's proposal-network code and coarse summaries: bf16
+"""Pins of the oracle's proposal-network code and coarse summaries: bf16
 rounding at ties, the convolution against an independent numpy
 implementation, backpropagation against central finite differences (binary64
 toy network) and the summary of a linear field (exact under trilinear
