@@ -41,7 +41,9 @@ def build(force: bool = False) -> str:
 class _Params(ctypes.Structure):
     _fields_ = [("vs", ctypes.c_double), ("trunc_vox", ctypes.c_int), ("max_range", ctypes.c_double),
                 ("d_max", ctypes.c_double), ("w_reg", ctypes.c_double), ("fp64", ctypes.c_int),
-                ("fp16", ctypes.c_int), ("max_iter", ctypes.c_int), ("n_min", ctypes.c_int)]
+                ("fp16", ctypes.c_int), ("max_iter", ctypes.c_int), ("n_min", ctypes.c_int),
+                ("tol_rho", ctypes.c_double), ("tol_theta", ctypes.c_double), ("align_dof", ctypes.c_int),
+                ("weight_mode", ctypes.c_int)]
 
 
 class _Conv(ctypes.Structure):
@@ -125,13 +127,15 @@ class Params:
     """Map and solver parameters (metres)."""
 
     def __init__(self, vs=0.05, trunc_vox=4, max_range=5.0, d_max=2.0, w_reg=2.0, fp64=False, fp16=False,
-                 max_iter=30, n_min=100):
+                 max_iter=30, n_min=100, tol_rho=1e-7, tol_theta=1e-8, align_dof=6, weight_mode=0):
         self.vs, self.trunc_vox, self.max_range, self.d_max = vs, trunc_vox, max_range, d_max
         self.w_reg, self.fp64, self.fp16, self.max_iter, self.n_min = w_reg, fp64, fp16, max_iter, n_min
+        self.tol_rho, self.tol_theta, self.align_dof, self.weight_mode = tol_rho, tol_theta, align_dof, weight_mode
 
     def _c(self):
         return _Params(self.vs, self.trunc_vox, self.max_range, self.d_max, self.w_reg, int(self.fp64),
-                       int(self.fp16), self.max_iter, self.n_min)
+                       int(self.fp16), self.max_iter, self.n_min, self.tol_rho, self.tol_theta, int(self.align_dof),
+                       int(self.weight_mode))
 
 
 class Submap:

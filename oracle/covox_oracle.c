@@ -54,6 +54,10 @@ typedef struct {
     int fp16;          /* binary16 storage of D and W (binary32 mode only) */
     int max_iter;      /* Gauss-Newton iteration cap */
     int n_min;         /* minimum number of residuals */
+    double tol_rho;    /* Gauss-Newton stop: |step translation| below this (m) ... */
+    double tol_theta;  /* ... and |step rotation| below this (rad) */
+    int align_dof;     /* 6, or 4: translation and yaw only (gravity-aligned submaps) */
+    int weight_mode;   /* 0: weight 1 per observation; 1: weight 1 / d^2 (d = measured depth, m) */
 } orc_params;
 
 typedef struct {
@@ -265,13 +269,13 @@ static int lin_index(int64_t ix, int64_t iy, int64_t iz)
 
 /* ------------------------------------------------------- integrate */
 
-typedef struct { int64_t i[3]; double sdf; } valid_vox;
+typedef struct { int64_t i[3]; double sdf, d; } valid_vox;
 
 /* Projective validity of voxel i under camera pose T_cs (Sec. III-C),
  * binary32 pinned order.  Returns 1 and the signed distance when valid. */
 static int valid32(const float R[9], const float t[3], float vs_f, float tau_f, float maxr_f,
                    const float K[4], const float *depth, int H, int W, const int64_t i[3],
-                   float *sdf_out)
+                   float *sdf_out, float *d_out)
 {
     float c[3], p[3];
     for (int a = 0; a < 3; ++a) c[a] = ((float)i[a] + 0.5f) * vs_f;
@@ -288,13 +292,14 @@ static int valid32(const float R[9], const float t[3], float vs_f, float tau_f, 
     float sdf = d - p[2];
     if (!(sdf >= -tau_f)) return 0;
     *sdf_out = sdf;
+    *d_out = d;
     return 1;
 }
 
 /* The same test in binary64. */
 static int valid64(const double R[9], const double t[3], double vs, double tau, double maxr,
                    const float K[4], const float *depth, int H, int W, const int64_t i[3],
-                   double *sdf_out)
+                   double *sdf_out, double *d_out)
 {
     double c[3], p[3];
     for (int a = 0; a < 3; ++a) c[a] = ((double)i[a] + 0.5) * vs;
@@ -311,6 +316,7 @@ static int valid64(const double R[9], const double t[3], double vs, double tau, 
     double sdf = d - p[2];
     if (!(sdf >= -tau)) return 0;
     *sdf_out = sdf;
+    *d_out = d;
     return 1;
 }
 
@@ -380,18 +386,20 @@ int orc_integrate(orc_submap *s, const float *depth, int H, int W, const float K
         for (i[1] = lo[1]; i[1] <= hi[1]; ++i[1])
             for (i[2] = lo[2]; i[2] <= hi[2]; ++i[2]) {
                 int ok;
-                double sdf;
+                double sdf, dd;
                 if (s->p.fp64) {
-                    ok = valid64(R64, t64, s->p.vs, tau, s->p.max_range, K, depth, H, W, i, &sdf);
+                    ok = valid64(R64, t64, s->p.vs, tau, s->p.max_range, K, depth, H, W, i, &sdf, &dd);
                 } else {
-                    float sf;
-                    ok = valid32(R32, t32, vs_f, tau_f, maxr_f, K, depth, H, W, i, &sf);
+                    float sf, df;
+                    ok = valid32(R32, t32, vs_f, tau_f, maxr_f, K, depth, H, W, i, &sf, &df);
                     sdf = sf;
+                    dd = df;
                 }
                 if (!ok) continue;
                 if (nv == capv) { capv *= 2; vv = (valid_vox *)realloc(vv, sizeof(valid_vox) * capv); }
                 vv[nv].i[0] = i[0]; vv[nv].i[1] = i[1]; vv[nv].i[2] = i[2];
                 vv[nv].sdf = sdf;
+                vv[nv].d = dd;
                 ++nv;
             }
 
@@ -426,15 +434,19 @@ int orc_integrate(orc_submap *s, const float *depth, int H, int W, const float K
         const int64_t *v = vv[j].i;
         int64_t idx = find_block(s, pack_key(floordiv8(v[0]), floordiv8(v[1]), floordiv8(v[2])));
         size_t o = (size_t)512 * idx + lin_index(v[0], v[1], v[2]);
+        /* observation weight (Sec. III-C: weights may follow the sensor's
+         * performance curve): 1, or 1 / d^2 for a depth noise that grows with
+         * the distance */
         if (s->p.fp64) {
             double t = vv[j].sdf < tau ? vv[j].sdf : tau;
-            double w = 1.0;
+            double w = s->p.weight_mode ? 1.0 / (vv[j].d * vv[j].d) : 1.0;
             double Wn = s->W64[o] + w;
             s->D64[o] = ((s->D64[o] * s->W64[o]) + (t * w)) / Wn;
             s->W64[o] = Wn;
         } else {
             float t = fminf((float)vv[j].sdf, tau_f);
-            float w = 1.0f;
+            const float df = (float)vv[j].d;
+            float w = s->p.weight_mode ? 1.0f / (df * df) : 1.0f;
             float Wold = s->W[o], Dold = s->D[o];
             float Wn = Wold + w;
             float Dn = ((Dold * Wold) + (t * w)) / Wn;
@@ -896,6 +908,52 @@ int orc_solve6(const double *ne, double x[6])
 }
 
 /*
+ * The 4-DoF step (translation and yaw, for submaps whose gravity direction
+ * is known): the Jacobian is the 6-DoF one restricted to (rho_x, rho_y,
+ * rho_z, theta_z), so its normal equations are rows and columns 0, 1, 2, 5 of
+ * the 6-DoF ones.  Solved by the same Cholesky; d = (rho, 0, 0, theta_z).
+ */
+int orc_solve_xyz_yaw(const double ne[29], double d[6])
+{
+    static const int sel[4] = {0, 1, 2, 5};
+    double H[4][4], b[4];
+    for (int a = 0; a < 4; ++a) {
+        for (int c = 0; c < 4; ++c) {
+            int r = sel[a], q = sel[c];
+            if (r > q) { int t = r; r = q; q = t; }
+            H[a][c] = ne[r * 6 - r * (r - 1) / 2 + (q - r)];
+        }
+        b[a] = ne[21 + sel[a]];
+    }
+    double L[4][4] = {{0}};
+    for (int j = 0; j < 4; ++j) {
+        double sj = H[j][j];
+        for (int k = 0; k < j; ++k) sj -= L[j][k] * L[j][k];
+        if (!(sj > 0.0)) return -1;
+        L[j][j] = sqrt(sj);
+        for (int i = j + 1; i < 4; ++i) {
+            double t = H[i][j];
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t / L[j][j];
+        }
+    }
+    double y[4], x[4];
+    for (int i = 0; i < 4; ++i) {
+        double t = -b[i];
+        for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
+        y[i] = t / L[i][i];
+    }
+    for (int i = 3; i >= 0; --i) {
+        double t = y[i];
+        for (int k = i + 1; k < 4; ++k) t -= L[k][i] * x[k];
+        x[i] = t / L[i][i];
+    }
+    d[0] = x[0]; d[1] = x[1]; d[2] = x[2];
+    d[3] = 0.0; d[4] = 0.0; d[5] = x[3];
+    return 0;
+}
+
+/*
  * Gauss-Newton alignment of B's registration points to A's ESDF.
  * T maps B coordinates to A coordinates.  Each iteration: normal equations
  * at T; stop with EDEGENERATE when fewer than n_min residuals or H is not
@@ -916,14 +974,17 @@ int orc_align_points(const orc_submap *A, const void *pts, int64_t n_pts, const 
         orc_normal_eq(A, pts, n_pts, T, ne);
         if (ne[28] < A->p.n_min) { status = ORC_EDEGENERATE; break; }
         double d[6];
-        if (orc_solve6(ne, d) != 0) { status = ORC_EDEGENERATE; break; }
+        if ((A->p.align_dof == 4 ? orc_solve_xyz_yaw(ne, d) : orc_solve6(ne, d)) != 0) {
+            status = ORC_EDEGENERATE;
+            break;
+        }
         double E[16];
         orc_se3_exp(d, E);
         rigid_mul(E, T, T);
         ++n_upd;
         double nr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         double nt = sqrt(d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
-        if (nr < 1e-7 && nt < 1e-8) { status = ORC_OK; break; }
+        if (nr < A->p.tol_rho && nt < A->p.tol_theta) { status = ORC_OK; break; }
     }
     orc_normal_eq(A, pts, n_pts, T, ne);
     *cost = ne[28] > 0 ? ne[27] / ne[28] : INFINITY;
