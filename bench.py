@@ -320,23 +320,23 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
             ov = block_overlap(keys[i], Tws[i], keys[j], Tws[j], w.voxel_size, np)
             if 0.3 <= ov <= 0.9:
                 cand.append((i, j, ov))
-    rng = np.random.default_rng(4)
-    pairs, gts = [], []
-    for k in range(n_pairs):
-        i, j, _ = cand[k % len(cand)]
-        T_gt = np.linalg.inv(Tws[i]) @ Tws[j]
-        dR = sg.rot_z(math.radians(rng.uniform(-10, 10))) @ sg.rot_y(math.radians(rng.uniform(-2, 2))) \
-            @ sg.rot_x(math.radians(rng.uniform(-2, 2)))
-        dT = np.eye(4)
-        dT[:3, :3] = dR
-        dT[:3, 3] = rng.uniform(-0.5, 0.5, size=3)
-        pairs.append((subs[i], subs[j], T_gt @ dT))
-        gts.append(T_gt)
-    ctx.align_batch(pairs[:1], 1)
-    align = {"pairs": n_pairs, "distinct_pairs": len(cand),
-             "tol_rho_m": OUTDOOR_TOL_RHO, "tol_theta_rad": OUTDOOR_TOL_THETA,
-             "overlap_range": [float(min(c[2] for c in cand)), float(max(c[2] for c in cand))]}
-    for n_starts in (1, 8):
+    def make_pairs(seed, tilt_deg):
+        rng = np.random.default_rng(seed)
+        pairs, gts = [], []
+        for k in range(n_pairs):
+            i, j, _ = cand[k % len(cand)]
+            T_gt = np.linalg.inv(Tws[i]) @ Tws[j]
+            dR = sg.rot_z(math.radians(rng.uniform(-10, 10))) @ sg.rot_y(math.radians(rng.uniform(-tilt_deg, tilt_deg))) \
+                @ sg.rot_x(math.radians(rng.uniform(-tilt_deg, tilt_deg)))
+            dT = np.eye(4)
+            dT[:3, :3] = dR
+            dT[:3, 3] = rng.uniform(-0.5, 0.5, size=3)
+            pairs.append((subs[i], subs[j], T_gt @ dT))
+            gts.append(T_gt)
+        return pairs, gts
+
+    def run_pairs(pairs, gts, n_starts):
+        tuning = ctx.autotune_align(pairs, n_starts)
         best = None
         for _ in range(reps):
             torch.cuda.synchronize()
@@ -351,10 +351,27 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
             er = math.degrees(math.acos(max(-1.0, min(1.0, c))))
             ok += et <= 0.01 and er <= 0.1
             errs.append(et)
-        align["starts_%d" % n_starts] = {"pairs_per_s": n_pairs / best, "success": ok / n_pairs,
-                                          "median_t_err_m": float(np.median(errs)), "ms": best * 1e3,
-                                          "mean_iterations": float(np.mean([x["iterations"] for x in st])),
-                                          "tuning": tuning}
+        return {"pairs_per_s": n_pairs / best, "success": ok / n_pairs, "median_t_err_m": float(np.median(errs)),
+                "ms": best * 1e3, "mean_iterations": float(np.mean([x["iterations"] for x in st])),
+                "tuning": tuning}
+
+    pairs, gts = make_pairs(4, 2.0)
+    ctx.align_batch(pairs[:1], 1)
+    align = {"pairs": n_pairs, "distinct_pairs": len(cand),
+             "tol_rho_m": OUTDOOR_TOL_RHO, "tol_theta_rad": OUTDOOR_TOL_THETA,
+             "overlap_range": [float(min(c[2] for c in cand)), float(max(c[2] for c in cand))]}
+    for n_starts in (1, 8):
+        align["starts_%d" % n_starts] = run_pairs(pairs, gts, n_starts)
+    # gravity-aligned priors (roll and pitch known, as from an IMU): the
+    # 4-DoF estimate (translation and yaw) beside the 6-DoF one on the same pairs
+    pairs_g, gts_g = make_pairs(5, 0.0)
+    align_4dof = {"prior": "+-0.5 m, +-10 deg yaw, roll/pitch exact"}
+    for dof in (6, 4):
+        ctx.set_params(align_dof=dof)
+        for n_starts in (1, 8):
+            align_4dof["dof%d_starts_%d" % (dof, n_starts)] = run_pairs(pairs_g, gts_g, n_starts)
+    ctx.set_params(align_dof=6)
+    align["gravity_aligned_priors"] = align_4dof
     learned = learned_bench(cv, torch, np, ctx, subs, Tws, w.voxel_size)
     ctx.close()
     return {"workload": "outdoor 120x80 m, 3000 frames 640x480 fx=fy=380, 0.1 m voxels, 30 submaps of 100 frames",

@@ -72,7 +72,15 @@ typedef struct {
     int32_t n_min;           /* minimum number of residuals for a solve */
     double tol_rho;          /* stop when |delta_rho| < tol_rho (m) ... */
     double tol_theta;        /* ... and |delta_theta| < tol_theta (rad) */
+    int32_t align_dof;       /* 6, or 4: translation and yaw only (Sec. III-F: submap poses in
+                                R^3 x SO(2) when gravity is known); the 4-DoF step solves rows and
+                                columns (rho_x, rho_y, rho_z, theta_z) of the normal equations */
+    int32_t weight_mode;     /* observation weight (Sec. III-C, weights after the sensor's noise):
+                                COVOX_WEIGHT_CONSTANT (1) or COVOX_WEIGHT_INV_DEPTH2 (1 / d^2, d = the
+                                pixel's depth in m) */
 } covox_params;
+
+enum { COVOX_WEIGHT_CONSTANT = 0, COVOX_WEIGHT_INV_DEPTH2 = 1 };
 
 /* Fills p with the defaults: 0.05 m voxels, tau = 4 voxels, 5 m range, 2 m
  * ESDF, w_reg = 2, 65536 blocks, FP32, 30 iterations, n_min = 100,
@@ -83,6 +91,13 @@ void covox_default_params(covox_params *p);
  * Returns EINVAL for an invalid parameter set, EHIP on a runtime failure. */
 int covox_create(covox_ctx **out, const covox_params *p);
 void covox_destroy(covox_ctx *ctx);
+
+/* Replaces the parameters that do not shape storage: w_reg, max_iter,
+ * n_min, tol_rho, tol_theta, align_dof and weight_mode (the next
+ * integrations use the new weight).  COVOX_EINVAL if p is invalid or
+ * changes voxel_size, trunc_vox, max_range, d_max, block_capacity or
+ * precision.  Registration points are re-extracted after a w_reg change. */
+int covox_set_params(covox_ctx *ctx, const covox_params *p);
 
 /* All later device work of ctx goes to `hip_stream` (a hipStream_t). */
 int covox_set_stream(covox_ctx *ctx, void *hip_stream);

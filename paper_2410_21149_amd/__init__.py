@@ -6,8 +6,10 @@ kernels for gfx950 behind the C ABI in include/covox.h.
 ``Context`` wraps a library context; importing this package fails when the
 HIP library has not been built.
 """
-from .covox import (FP16, FP32, KERNELS, OK, EINVAL, EPOOL_FULL, ETABLE_FULL, EHIP, EDEGENERATE, NOT_CONVERGED,
-                    Context, CovoxError, Graph, Net, Submap, default_params, LIB_PATH)
+from .covox import (EDEGENERATE, EHIP, EINVAL, EPOOL_FULL, ETABLE_FULL, FP16, FP32, KERNELS, LIB_PATH,
+                    NOT_CONVERGED, OK, WEIGHT_CONSTANT, WEIGHT_INV_DEPTH2, Context, CovoxError, Graph, Net, Submap,
+                    default_params)
 
-__all__ = ["Context", "Graph", "Net", "Submap", "CovoxError", "default_params", "FP32", "FP16", "KERNELS", "OK", "EINVAL",
-           "EPOOL_FULL", "ETABLE_FULL", "EHIP", "EDEGENERATE", "NOT_CONVERGED", "LIB_PATH"]
+__all__ = ["Context", "Graph", "Net", "Submap", "CovoxError", "default_params", "FP32", "FP16", "WEIGHT_CONSTANT",
+           "WEIGHT_INV_DEPTH2", "KERNELS", "OK", "EINVAL", "EPOOL_FULL", "ETABLE_FULL", "EHIP", "EDEGENERATE",
+           "NOT_CONVERGED", "LIB_PATH"]

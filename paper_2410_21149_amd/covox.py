@@ -24,6 +24,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, EPOOL_FULL, ETABLE_FULL, EHIP, EDEGENERATE, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1
 FP32, FP16 = 0, 1
+WEIGHT_CONSTANT, WEIGHT_INV_DEPTH2 = 0, 1
 KERNELS = ["probe", "scan", "integrate", "esdf_page", "esdf_sites", "edt_x", "edt_y", "edt_z", "iso", "align",
            "summary", "net"]
 
@@ -38,7 +39,8 @@ class covox_params(ctypes.Structure):
     _fields_ = [("voxel_size", ctypes.c_double), ("trunc_vox", ctypes.c_int32), ("max_range", ctypes.c_double),
                 ("d_max", ctypes.c_double), ("w_reg", ctypes.c_double), ("block_capacity", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("n_min", ctypes.c_int32),
-                ("tol_rho", ctypes.c_double), ("tol_theta", ctypes.c_double)]
+                ("tol_rho", ctypes.c_double), ("tol_theta", ctypes.c_double), ("align_dof", ctypes.c_int32),
+                ("weight_mode", ctypes.c_int32)]
 
 
 class covox_align_stats(ctypes.Structure):
@@ -84,6 +86,7 @@ _sig = {
     "covox_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(covox_params)]),
     "covox_destroy": (None, [_vp]),
     "covox_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "covox_set_params": (ctypes.c_int, [_vp, ctypes.POINTER(covox_params)]),
     "covox_sync": (ctypes.c_int, [_vp]),
     "covox_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "covox_last_error": (ctypes.c_char_p, [_vp]),
@@ -186,6 +189,15 @@ class Context:
         if rc not in ok:
             raise CovoxError(rc, "%s: %s" % (what, _lib.covox_last_error(self.handle).decode()))
         return rc
+
+    def set_params(self, **kw):
+        """Changes non-storage parameters (w_reg, max_iter, n_min, tol_rho,
+        tol_theta, align_dof, weight_mode)."""
+        p = covox_params.from_buffer_copy(self.params)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        self._check(_lib.covox_set_params(self.handle, ctypes.byref(p)), "set_params")
+        self.params = p
 
     def set_stream(self, stream: torch.cuda.Stream):
         self.stream = stream

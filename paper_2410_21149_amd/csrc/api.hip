@@ -176,6 +176,11 @@ bool valid_params(const covox_params *p, std::string &why)
     if (p->precision != COVOX_FP32 && p->precision != COVOX_FP16) { why = "precision must be FP32 or FP16"; return false; }
     if (p->max_iter < 0) { why = "max_iter must be >= 0"; return false; }
     if (p->n_min < 1) { why = "n_min must be >= 1"; return false; }
+    if (p->align_dof != 6 && p->align_dof != 4) { why = "align_dof must be 6 or 4"; return false; }
+    if (p->weight_mode != COVOX_WEIGHT_CONSTANT && p->weight_mode != COVOX_WEIGHT_INV_DEPTH2) {
+        why = "weight_mode must be COVOX_WEIGHT_CONSTANT or COVOX_WEIGHT_INV_DEPTH2";
+        return false;
+    }
     return true;
 }
 
@@ -347,6 +352,8 @@ void covox_default_params(covox_params *p)
     p->n_min = 100;
     p->tol_rho = 1e-7;
     p->tol_theta = 1e-8;
+    p->align_dof = 6;
+    p->weight_mode = COVOX_WEIGHT_CONSTANT;
 }
 
 const char *covox_status_string(int s)
@@ -410,6 +417,22 @@ void covox_destroy(covox_ctx *ctx)
         (void)hipEventDestroy(u.second.second);
     }
     delete ctx;
+}
+
+int covox_set_params(covox_ctx *ctx, const covox_params *p)
+{
+    if (!ctx || !p) return COVOX_EINVAL;
+    COVOX_NOT_DURING_CAPTURE(ctx, "set_params");
+    std::string why;
+    if (!valid_params(p, why)) return fail(ctx, COVOX_EINVAL, "set_params: " + why);
+    const covox_params &o = ctx->p;
+    if (p->voxel_size != o.voxel_size || p->trunc_vox != o.trunc_vox || p->max_range != o.max_range ||
+        p->d_max != o.d_max || p->block_capacity != o.block_capacity || p->precision != o.precision)
+        return fail(ctx, COVOX_EINVAL, "set_params: storage-shaping parameters cannot change");
+    if (p->w_reg != o.w_reg)
+        for (covox_submap *s : submaps_of(ctx)) s->pts_version = 0;
+    ctx->p = *p;
+    return COVOX_OK;
 }
 
 int covox_set_stream(covox_ctx *ctx, void *hip_stream)

@@ -109,6 +109,7 @@ struct FrameArgs {
     float plane[4][3];
     float zfar;
     float cull_r;
+    int32_t weight_mode;  // COVOX_WEIGHT_*
 };
 
 }  // namespace covox

@@ -284,6 +284,48 @@ __device__ __forceinline__ void residual_u(const float *Tf, const float *pts, in
     }
 }
 
+// 4-DoF step (translation and yaw): rows and columns 0, 1, 2, 5 of the
+// normal equations by Cholesky; x = (rho, 0, 0, theta_z).
+__device__ bool solve_xyz_yaw(const double *ne, double x[6])
+{
+    const int sel[4] = {0, 1, 2, 5};
+    double H[4][4], b[4], L[4][4];
+    for (int a = 0; a < 4; ++a) {
+        for (int c = 0; c < 4; ++c) {
+            int r = sel[a], q = sel[c];
+            if (r > q) { const int t = r; r = q; q = t; }
+            H[a][c] = ne[r * 6 - r * (r - 1) / 2 + (q - r)];
+            L[a][c] = 0.0;
+        }
+        b[a] = ne[21 + sel[a]];
+    }
+    for (int j = 0; j < 4; ++j) {
+        double sj = H[j][j];
+        for (int k = 0; k < j; ++k) sj -= L[j][k] * L[j][k];
+        if (!(sj > 0.0)) return false;
+        L[j][j] = sqrt(sj);
+        for (int i = j + 1; i < 4; ++i) {
+            double t = H[i][j];
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t / L[j][j];
+        }
+    }
+    double y[4], z[4];
+    for (int i = 0; i < 4; ++i) {
+        double t = -b[i];
+        for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
+        y[i] = t / L[i][i];
+    }
+    for (int i = 3; i >= 0; --i) {
+        double t = y[i];
+        for (int k = i + 1; k < 4; ++k) t -= L[k][i] * z[k];
+        z[i] = t / L[i][i];
+    }
+    x[0] = z[0]; x[1] = z[1]; x[2] = z[2];
+    x[3] = 0.0; x[4] = 0.0; x[5] = z[3];
+    return true;
+}
+
 // 6x6 Cholesky solve of H x = -b (H from the packed upper triangle).
 __device__ bool solve6(const double *ne, double x[6])
 {
@@ -363,7 +405,8 @@ __device__ void se3_left_update(const double xi[6], double T[12])
 template <int kAlignThreads, int U>
 __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__restrict__ probs,
                                                          const int32_t *__restrict__ order, AlignResult *res,
-                                                         float vs, double tol_rho, double tol_theta, int n_min)
+                                                         float vs, double tol_rho, double tol_theta, int n_min,
+                                                         int dof)
 {
     __shared__ double sT[12];
     __shared__ float sTf[12];
@@ -438,7 +481,7 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__r
                 stop = true;
             } else {
                 double dl[6];
-                if (!solve6(tot, dl)) {
+                if (!(dof == 4 ? solve_xyz_yaw(tot, dl) : solve6(tot, dl))) {
                     s_state[2] = COVOX_EDEGENERATE;
                     stop = true;
                 } else {
@@ -642,22 +685,22 @@ int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult 
         AlignResult *dres = (AlignResult *)ctx->res_dev;
         const float vs = (float)ctx->p.voxel_size;
         const double tr = ctx->p.tol_rho, tt = ctx->p.tol_theta;
-        const int nm = ctx->p.n_min;
+        const int nm = ctx->p.n_min, dof = ctx->p.align_dof;
         const bool two = ctx->tune.align_points_per_step == 2;
         if (ctx->tune.align_threads == 512) {
             if (two)
                 hipLaunchKernelGGL((k_align<512, 2>), dim3(n), dim3(512), 0, ctx->stream, dprob, dorder, dres, vs, tr,
-                                   tt, nm);
+                                   tt, nm, dof);
             else
                 hipLaunchKernelGGL((k_align<512, 1>), dim3(n), dim3(512), 0, ctx->stream, dprob, dorder, dres, vs, tr,
-                                   tt, nm);
+                                   tt, nm, dof);
         } else {
             if (two)
                 hipLaunchKernelGGL((k_align<256, 2>), dim3(n), dim3(256), 0, ctx->stream, dprob, dorder, dres, vs, tr,
-                                   tt, nm);
+                                   tt, nm, dof);
             else
                 hipLaunchKernelGGL((k_align<256, 1>), dim3(n), dim3(256), 0, ctx->stream, dprob, dorder, dres, vs, tr,
-                                   tt, nm);
+                                   tt, nm, dof);
         }
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "align launch"))) return rc;

@@ -36,10 +36,11 @@ template <typename S> __device__ __forceinline__ void st(S *p, float v);
 template <> __device__ __forceinline__ void st<float>(float *p, float v) { *p = v; }
 template <> __device__ __forceinline__ void st<__half>(__half *p, float v) { *p = __float2half_rn(v); }
 
-// Validity of voxel (ix, iy, iz) under the frame's projection and its
-// signed distance (depth minus voxel depth).
+// Validity of voxel (ix, iy, iz) under the frame's projection, its signed
+// distance (depth minus voxel depth) and the observation weight (1, or
+// 1 / d^2 for the pixel's depth d).
 __device__ __forceinline__ bool proj_valid(const FrameArgs &f, float vs, float tau, float maxr, int ix,
-                                           int iy, int iz, float &sdf)
+                                           int iy, int iz, float &sdf, float &w)
 {
     const float cx = ((float)ix + 0.5f) * vs;
     const float cy = ((float)iy + 0.5f) * vs;
@@ -56,6 +57,7 @@ __device__ __forceinline__ bool proj_valid(const FrameArgs &f, float vs, float t
     const float d = f.depth[(int64_t)(int)vf * f.W + (int)uf];
     if (!(d > 0.0f && d <= maxr)) return false;
     sdf = d - pz;
+    w = f.weight_mode == COVOX_WEIGHT_INV_DEPTH2 ? 1.0f / (d * d) : 1.0f;
     return sdf >= -tau;
 }
 
@@ -87,7 +89,8 @@ __device__ __forceinline__ void box_block(const FrameArgs &f, int64_t j, int &bx
 // The running-average update of one voxel column (8 z values of a lane) of
 // an allocated block; returns the number of updated voxels of the wave.
 template <typename S>
-__device__ __forceinline__ int update_column(S *Db, S *Wb, const float sdf[8], uint32_t okm, float tau, bool is_new)
+__device__ __forceinline__ int update_column(S *Db, S *Wb, const float sdf[8], const float wt[8], uint32_t okm, float tau,
+                                             bool is_new)
 {
     int n_ok = 0;
 #pragma unroll
@@ -98,8 +101,8 @@ __device__ __forceinline__ int update_column(S *Db, S *Wb, const float sdf[8], u
             const float Dv = is_new ? 0.0f : ld(Db + 64 * z);
             const float Wv = is_new ? 0.0f : ld(Wb + 64 * z);
             const float tr = fminf(sdf[z], tau);
-            const float Wn = Wv + 1.0f;
-            const float Dn = ((Dv * Wv) + (tr * 1.0f)) / Wn;
+            const float Wn = Wv + wt[z];
+            const float Dn = ((Dv * Wv) + (tr * wt[z])) / Wn;
             st(Db + 64 * z, Dn);
             st(Wb + 64 * z, Wn);
         } else if (is_new) {
@@ -132,10 +135,11 @@ __global__ __launch_bounds__(256) void k_probe(FrameArgs f, float vs, float tau,
     }
     const int ix = 8 * bx + (lane & 7);
     const int iy = 8 * by + (lane >> 3);
-    float sdf[8];
+    float sdf[8], wt[8];
     uint32_t okm = 0;
 #pragma unroll
-    for (int z = 0; z < 8; ++z) okm |= (uint32_t)proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf[z]) << z;
+    for (int z = 0; z < 8; ++z)
+        okm |= (uint32_t)proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf[z], wt[z]) << z;
     const uint64_t m = __ballot(okm != 0);
     uint32_t out = 0;
     if (m) {
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(256) void k_probe(FrameArgs f, float vs, float tau,
         idx = __shfl(idx, 0, 64);
         out = idx >= 0 ? (uint32_t)idx + 1u : kNew;
         if (FUSED && idx >= 0) {
-            const int n_ok = update_column(D + idx * 512 + lane, W + idx * 512 + lane, sdf, okm, tau, false);
+            const int n_ok = update_column(D + idx * 512 + lane, W + idx * 512 + lane, sdf, wt, okm, tau, false);
             if (lane == 0) atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
         }
     }
@@ -292,11 +296,12 @@ __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float 
         }
         const int ix = 8 * bx + (lane & 7);
         const int iy = 8 * by + (lane >> 3);
-        float sdf[8];
+        float sdf[8], wt[8];
         uint32_t okm = 0;
 #pragma unroll
-        for (int z = 0; z < 8; ++z) okm |= (uint32_t)proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf[z]) << z;
-        const int n_ok = update_column(D + idx * 512 + lane, W + idx * 512 + lane, sdf, okm, tau, is_new);
+        for (int z = 0; z < 8; ++z)
+            okm |= (uint32_t)proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf[z], wt[z]) << z;
+        const int n_ok = update_column(D + idx * 512 + lane, W + idx * 512 + lane, sdf, wt, okm, tau, is_new);
         if (lane == 0) atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
     }
 }
@@ -333,8 +338,8 @@ __global__ __launch_bounds__(256) void k_probe_batch(const FrameArgs *__restrict
     bool any = false;
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
-        float sdf;
-        any |= proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf);
+        float sdf, w;
+        any |= proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf, w);
     }
     const uint64_t m = __ballot(any);
     if (lane == 0) {
@@ -530,13 +535,13 @@ __global__ __launch_bounds__(256) void k_integrate_batch(const FrameArgs *__rest
                 continue;  // no valid voxel in this frame
 #pragma unroll
             for (int z = 0; z < 8; ++z) {
-                float sdf;
-                const bool ok = proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf);
+                float sdf, w;
+                const bool ok = proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf, w);
                 n_ok += __popcll(__ballot(ok));
                 if (ok) {
                     const float tr = fminf(sdf, tau);
-                    const float Wn = wv[z] + 1.0f;
-                    const float Dn = ((dv[z] * wv[z]) + (tr * 1.0f)) / Wn;
+                    const float Wn = wv[z] + w;
+                    const float Dn = ((dv[z] * wv[z]) + (tr * w)) / Wn;
                     dv[z] = stored<S>(Dn);
                     wv[z] = stored<S>(Wn);
                 }
@@ -665,6 +670,7 @@ int prepare_frame(covox_ctx *ctx, const covox_submap *s, const float *depth, int
     f.H = H;
     f.W = W;
     f.depth = depth;
+    f.weight_mode = p.weight_mode;
     {
         // side planes through the camera centre for u in [-1.5, W + 0.5]
         // and v in [-1.5, H + 0.5] (one pixel beyond the pixel-centre test)
