@@ -43,7 +43,7 @@ class _Params(ctypes.Structure):
                 ("d_max", ctypes.c_double), ("w_reg", ctypes.c_double), ("fp64", ctypes.c_int),
                 ("fp16", ctypes.c_int), ("max_iter", ctypes.c_int), ("n_min", ctypes.c_int),
                 ("tol_rho", ctypes.c_double), ("tol_theta", ctypes.c_double), ("align_dof", ctypes.c_int),
-                ("weight_mode", ctypes.c_int)]
+                ("weight_mode", ctypes.c_int), ("integrator", ctypes.c_int), ("ray_carve", ctypes.c_int)]
 
 
 class _Conv(ctypes.Structure):
@@ -109,6 +109,8 @@ def _load():
         L.orc_summary.argtypes = [_vp, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double, _dp]
         L.orc_bf16_round.restype = ctypes.c_float
         L.orc_bf16_round.argtypes = [ctypes.c_float]
+        L.orc_ray_walk32.restype = ctypes.c_int64
+        L.orc_ray_walk32.argtypes = [_fp, _fp, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i64p, ctypes.c_int64]
         L.orc_pose_cam_sub.restype = None
         L.orc_pose_cam_sub.argtypes = [_dp, _dp, _dp]
         _lib = L
@@ -127,15 +129,17 @@ class Params:
     """Map and solver parameters (metres)."""
 
     def __init__(self, vs=0.05, trunc_vox=4, max_range=5.0, d_max=2.0, w_reg=2.0, fp64=False, fp16=False,
-                 max_iter=30, n_min=100, tol_rho=1e-7, tol_theta=1e-8, align_dof=6, weight_mode=0):
+                 max_iter=30, n_min=100, tol_rho=1e-7, tol_theta=1e-8, align_dof=6, weight_mode=0, integrator=0,
+                 ray_carve=True):
         self.vs, self.trunc_vox, self.max_range, self.d_max = vs, trunc_vox, max_range, d_max
         self.w_reg, self.fp64, self.fp16, self.max_iter, self.n_min = w_reg, fp64, fp16, max_iter, n_min
         self.tol_rho, self.tol_theta, self.align_dof, self.weight_mode = tol_rho, tol_theta, align_dof, weight_mode
+        self.integrator, self.ray_carve = integrator, ray_carve  # 0: projection mapping, 1: raycasting
 
     def _c(self):
         return _Params(self.vs, self.trunc_vox, self.max_range, self.d_max, self.w_reg, int(self.fp64),
                        int(self.fp16), self.max_iter, self.n_min, self.tol_rho, self.tol_theta, int(self.align_dof),
-                       int(self.weight_mode))
+                       int(self.weight_mode), int(self.integrator), int(bool(self.ray_carve)))
 
 
 class Submap:
@@ -161,12 +165,14 @@ class Submap:
     def integrate(self, depth, K, T_world_cam):
         d = np.ascontiguousarray(depth, np.float32)
         k = np.ascontiguousarray(K, np.float32)
-        st = np.zeros(3, np.int64)
+        st = np.zeros(4, np.int64)
         rc = _load().orc_integrate(self._h, _p(d, _fp), d.shape[0], d.shape[1], _p(k, _fp),
                                    _p(_mat(T_world_cam), _dp), _p(st, _i64p))
         if rc != OK:
             raise ValueError("oracle integrate: status %d" % rc)
-        return {"n_new": int(st[0]), "n_touched": int(st[1]), "n_valid": int(st[2])}
+        # n_valid: valid voxels (projection) or contributions (raycasting);
+        # n_voxels: voxels updated
+        return {"n_new": int(st[0]), "n_touched": int(st[1]), "n_valid": int(st[2]), "n_voxels": int(st[3])}
 
     def update_esdf(self):
         _load().orc_update_esdf(self._h)
@@ -239,6 +245,18 @@ def align_multistart(A: Submap, pts, T_init, n_starts=8):
                                       _p(starts, _dp))
     return {"T": T.reshape(4, 4), "cost": float(cost[0]), "status": int(st), "iters": int(info[0]),
             "n": int(info[1]), "best": best.value, "starts": starts.reshape(n_starts, 4, 4)}
+
+
+def ray_walk32(o, u, s0, s1, vs) -> np.ndarray:
+    """Voxel indices (n, 3) crossed by the binary32 ray segment o + s u,
+    s in [s0, s1], in walk order."""
+    o = np.ascontiguousarray(o, np.float32)
+    u = np.ascontiguousarray(u, np.float32)
+    s0, s1, vs = np.float32(s0), np.float32(s1), np.float32(vs)
+    cap = 3 * int(np.ceil(np.float32(s1 - s0) / vs)) + 6
+    out = np.zeros((cap, 3), np.int64)
+    n = _load().orc_ray_walk32(_p(o, _fp), _p(u, _fp), s0, s1, vs, _p(out, _i64p), cap)
+    return out[:n]
 
 
 def se3_exp(xi) -> np.ndarray:

@@ -13,6 +13,11 @@
  *               indexed by 3-D position), Sec. III-D (count new blocks,
  *               allocate them from a pre-allocated buffer, then update; the
  *               weight/distance update is commutative).
+ *   raycast     Sec. III-C (rays from the optical centre through every
+ *               observed point; all voxels crossed up to the truncation
+ *               distance behind the point are updated; every point counts),
+ *               Sec. III-D (count and allocate new blocks, then reduce all
+ *               contributions of the frame per voxel in address order).
  *   esdf        Sec. I and Sec. III-E (Euclidean distance to the nearest
  *               obstacle built from the TSDF, reusing the distances inside the
  *               truncation band; exact EDT in the PBA lineage).
@@ -58,6 +63,8 @@ typedef struct {
     double tol_theta;  /* ... and |step rotation| below this (rad) */
     int align_dof;     /* 6, or 4: translation and yaw only (gravity-aligned submaps) */
     int weight_mode;   /* 0: weight 1 per observation; 1: weight 1 / d^2 (d = measured depth, m) */
+    int integrator;    /* 0: projection mapping; 1: raycasting */
+    int ray_carve;     /* raycasting: 1 = rays start at the optical centre; 0 = at tau before the point */
 } orc_params;
 
 typedef struct {
@@ -349,6 +356,38 @@ static void frustum_box(const orc_submap *s, const float K[4], int H, int W, con
     }
 }
 
+/* Blocks touched by a frame: keys tk[0..n) (any order, duplicates allowed)
+ * are sorted and deduplicated in place; blocks not yet allocated get buffer
+ * indices n + rank in ascending key order (Sec. III-D: count, then allocate
+ * from the pre-allocated buffer).  Returns the number of new blocks and sets
+ * *n_touched. */
+static int64_t allocate_touched(orc_submap *s, uint64_t *tk, size_t n, size_t *n_touched)
+{
+    qsort(tk, n, sizeof(uint64_t), cmp_u64);
+    size_t nt = 0;
+    for (size_t j = 0; j < n; ++j)
+        if (nt == 0 || tk[nt - 1] != tk[j]) tk[nt++] = tk[j];
+    int64_t n_new = 0;
+    int64_t n0 = s->n;
+    grow(s, s->n + (int64_t)nt);
+    for (size_t j = 0; j < nt; ++j) {  /* tk is ascending: ranks follow key order */
+        if (find_block(s, tk[j]) >= 0) continue;
+        int64_t idx = n0 + n_new;
+        s->keys[idx] = tk[j];
+        for (int l = 0; l < 512; ++l) {
+            if (s->p.fp64) { s->D64[512 * idx + l] = 0.0; s->W64[512 * idx + l] = 0.0; }
+            else { s->D[512 * idx + l] = 0.0f; s->W[512 * idx + l] = 0.0f; }
+            s->ksq[512 * idx + l] = -1;
+            if (s->p.fp64) s->phi64[512 * idx + l] = NAN; else s->phi[512 * idx + l] = NAN;
+        }
+        ++n_new;
+    }
+    s->n = n0 + n_new;
+    rebuild_sorted(s);
+    *n_touched = nt;
+    return n_new;
+}
+
 /*
  * Integrate one depth frame (Sec. III-C projection mapping; Sec. III-D
  * count / allocate / update).
@@ -357,12 +396,16 @@ static void frustum_box(const orc_submap *s, const float K[4], int H, int W, con
  *      allocated blocks; new blocks get buffer indices n + rank in
  *      ascending packed-key order;
  *   3. each valid voxel: t = min(sdf, tau); W' = W + 1; D' = (D W + t) / W'.
- * stats (nullable): [n_new, n_touched, n_valid].
+ * stats (nullable): [n_new, n_touched, n_valid, n_valid].
  */
+int orc_integrate_raycast(orc_submap *s, const float *depth, int H, int W, const float K[4],
+                          const double *T_wc, int64_t *stats);
+
 int orc_integrate(orc_submap *s, const float *depth, int H, int W, const float K[4],
                   const double *T_wc, int64_t *stats)
 {
     if (H <= 0 || W <= 0 || !(K[0] > 0) || !(K[1] > 0)) return ORC_EINVAL;
+    if (s->p.integrator == 1) return orc_integrate_raycast(s, depth, H, W, K, T_wc, stats);
     double T_cs[16];
     orc_pose_cam_sub(T_wc, s->T_ws, T_cs);
     int64_t lo[3], hi[3];
@@ -407,27 +450,8 @@ int orc_integrate(orc_submap *s, const float *depth, int H, int W, const float K
     uint64_t *tk = (uint64_t *)malloc(sizeof(uint64_t) * (nv ? nv : 1));
     for (size_t j = 0; j < nv; ++j)
         tk[j] = pack_key(floordiv8(vv[j].i[0]), floordiv8(vv[j].i[1]), floordiv8(vv[j].i[2]));
-    qsort(tk, nv, sizeof(uint64_t), cmp_u64);
     size_t nt = 0;
-    for (size_t j = 0; j < nv; ++j)
-        if (nt == 0 || tk[nt - 1] != tk[j]) tk[nt++] = tk[j];
-    int64_t n_new = 0;
-    int64_t n0 = s->n;
-    grow(s, s->n + (int64_t)nt);
-    for (size_t j = 0; j < nt; ++j) {  /* tk is ascending: ranks follow key order */
-        if (find_block(s, tk[j]) >= 0) continue;
-        int64_t idx = n0 + n_new;
-        s->keys[idx] = tk[j];
-        for (int l = 0; l < 512; ++l) {
-            if (s->p.fp64) { s->D64[512 * idx + l] = 0.0; s->W64[512 * idx + l] = 0.0; }
-            else { s->D[512 * idx + l] = 0.0f; s->W[512 * idx + l] = 0.0f; }
-            s->ksq[512 * idx + l] = -1;
-            if (s->p.fp64) s->phi64[512 * idx + l] = NAN; else s->phi[512 * idx + l] = NAN;
-        }
-        ++n_new;
-    }
-    s->n = n0 + n_new;
-    rebuild_sorted(s);
+    const int64_t n_new = allocate_touched(s, tk, nv, &nt);
 
     /* 3. update every valid voxel */
     for (size_t j = 0; j < nv; ++j) {
@@ -454,9 +478,234 @@ int orc_integrate(orc_submap *s, const float *depth, int H, int W, const float K
             s->W[o] = round_store(s, Wn);
         }
     }
-    if (stats) { stats[0] = n_new; stats[1] = (int64_t)nt; stats[2] = (int64_t)nv; }
+    if (stats) { stats[0] = n_new; stats[1] = (int64_t)nt; stats[2] = (int64_t)nv; stats[3] = (int64_t)nv; }
     free(tk);
     free(vv);
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------- raycast */
+
+/*
+ * Voxels crossed by the segment o + s u, s in [s0, s1], of a ray with unit
+ * direction u (binary32): the grid traversal of Amanatides and Woo
+ * (Eurographics 1987).  The start voxel holds o + s0 u; the parameter of the
+ * next boundary along axis a is computed from the voxel index itself,
+ *   s_a = ((i_a + [u_a > 0]) vs - o_a) / u_a   (infinite when u_a = 0),
+ * the smallest s_a (x before y before z on ties) moves that axis by one, and
+ * the walk ends once that smallest s_a is not below s1.  At most max_out
+ * voxels (3 ceil((s1 - s0) / vs) + 6 bounds the walk) are written to out as
+ * (x, y, z) triples; returns the number written.
+ */
+int64_t orc_ray_walk32(const float o[3], const float u[3], float s0, float s1, float vs, int64_t *out,
+                       int64_t max_out)
+{
+    int64_t i[3];
+    int step[3];
+    float sn[3];
+    for (int a = 0; a < 3; ++a) {
+        const float e = o[a] + s0 * u[a];
+        i[a] = (int64_t)floorf(e / vs);
+        step[a] = u[a] > 0.0f ? 1 : (u[a] < 0.0f ? -1 : 0);
+        sn[a] = step[a] ? (((float)(i[a] + (step[a] > 0)) * vs) - o[a]) / u[a] : INFINITY;
+    }
+    int64_t n = 0;
+    while (n < max_out) {
+        out[3 * n + 0] = i[0]; out[3 * n + 1] = i[1]; out[3 * n + 2] = i[2];
+        ++n;
+        int a = 0;
+        if (sn[1] < sn[a]) a = 1;
+        if (sn[2] < sn[a]) a = 2;
+        if (!(sn[a] < s1)) break;
+        i[a] += step[a];
+        sn[a] = (((float)(i[a] + (step[a] > 0)) * vs) - o[a]) / u[a];
+    }
+    return n;
+}
+
+/* The same walk in binary64. */
+static int64_t ray_walk64(const double o[3], const double u[3], double s0, double s1, double vs, int64_t *out,
+                          int64_t max_out)
+{
+    int64_t i[3];
+    int step[3];
+    double sn[3];
+    for (int a = 0; a < 3; ++a) {
+        const double e = o[a] + s0 * u[a];
+        i[a] = (int64_t)floor(e / vs);
+        step[a] = u[a] > 0.0 ? 1 : (u[a] < 0.0 ? -1 : 0);
+        sn[a] = step[a] ? (((double)(i[a] + (step[a] > 0)) * vs) - o[a]) / u[a] : INFINITY;
+    }
+    int64_t n = 0;
+    while (n < max_out) {
+        out[3 * n + 0] = i[0]; out[3 * n + 1] = i[1]; out[3 * n + 2] = i[2];
+        ++n;
+        int a = 0;
+        if (sn[1] < sn[a]) a = 1;
+        if (sn[2] < sn[a]) a = 2;
+        if (!(sn[a] < s1)) break;
+        i[a] += step[a];
+        sn[a] = (((double)(i[a] + (step[a] > 0)) * vs) - o[a]) / u[a];
+    }
+    return n;
+}
+
+typedef struct { uint64_t bkey; int64_t lin, pix; double t, w; } ray_contrib;
+
+static int cmp_contrib(const void *a, const void *b)
+{
+    const ray_contrib *x = (const ray_contrib *)a, *y = (const ray_contrib *)b;
+    if (x->bkey != y->bkey) return x->bkey < y->bkey ? -1 : 1;
+    if (x->lin != y->lin) return x->lin < y->lin ? -1 : 1;
+    return x->pix < y->pix ? -1 : (x->pix > y->pix ? 1 : 0);
+}
+
+/*
+ * Raycast integration of one depth frame (Sec. III-C: a ray from the optical
+ * centre through every observed point updates the voxels it crosses up to the
+ * truncation distance behind the point; Sec. III-D: count and allocate the
+ * new blocks, then merge all of the frame's contributions per voxel, the
+ * weight and distance update being commutative, with the voxels in address
+ * order).
+ *   ray of pixel (col, row) with valid depth z (0 < z <= max_range):
+ *     q = ((col - cx) z / fx, (row - cy) z / fy, z) in the camera frame,
+ *     d = R_sc q, r = |d|, u = d / r, origin o = t_sc (submap frame);
+ *   segment s in [s0, r + tau], s0 = 0 with ray_carve (from the optical
+ *     centre), else max(0, r - tau);
+ *   each crossed voxel (orc_ray_walk32) with centre c: sdf = r - (c - o).u;
+ *     it contributes t = min(sdf, tau) with the weight w (1, or 1/z^2) when
+ *     sdf >= -tau;
+ *   blocks holding a contribution are touched; new ones get buffer indices
+ *     n + rank in ascending key order;
+ *   per voxel, over its contributions in pixel (raster) order:
+ *     sw = sum w, stw = sum t w, both in binary64 (the products of binary32
+ *     t and w are exact there); then in binary32 W' = W + sw,
+ *     D' = (D W + stw) / W' (sw and stw rounded once).
+ * stats (nullable): [n_new, n_touched, n_contributions, n_voxels_updated].
+ */
+int orc_integrate_raycast(orc_submap *s, const float *depth, int H, int W, const float K[4],
+                          const double *T_wc, int64_t *stats)
+{
+    double inv_ws[16], T_sc[16];
+    rigid_inverse(s->T_ws, inv_ws);
+    rigid_mul(inv_ws, T_wc, T_sc);
+    float R32[9], o32[3];
+    double R64[9], o64[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) { R32[3 * r + c] = (float)T_sc[4 * r + c]; R64[3 * r + c] = T_sc[4 * r + c]; }
+        o32[r] = (float)T_sc[4 * r + 3];
+        o64[r] = T_sc[4 * r + 3];
+    }
+    const double tau = s->p.trunc_vox * s->p.vs;
+    const float vs_f = (float)s->p.vs, tau_f = (float)tau, maxr_f = (float)s->p.max_range;
+
+    size_t nc = 0, capc = 1 << 16;
+    ray_contrib *L = (ray_contrib *)malloc(sizeof(ray_contrib) * capc);
+    int64_t walk_cap = 0, *walk = NULL;
+    for (int row = 0; row < H; ++row)
+        for (int col = 0; col < W; ++col) {
+            const float z = depth[(size_t)row * W + col];
+            if (!(z > 0.0f && z <= maxr_f)) continue;
+            const int64_t pix = (int64_t)row * W + col;
+            int64_t nvox, guard;
+            double r, u[3], o[3], w;
+            if (!s->p.fp64) {
+                const float xc = (((float)col - K[2]) * z) / K[0];
+                const float yc = (((float)row - K[3]) * z) / K[1];
+                float d[3], uf[3];
+                for (int k = 0; k < 3; ++k) d[k] = (R32[3 * k] * xc + R32[3 * k + 1] * yc) + R32[3 * k + 2] * z;
+                const float rf = sqrtf((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+                for (int k = 0; k < 3; ++k) uf[k] = d[k] / rf;
+                const float s1 = rf + tau_f;
+                const float s0 = s->p.ray_carve ? 0.0f : fmaxf(rf - tau_f, 0.0f);
+                guard = 3 * (int64_t)ceilf((s1 - s0) / vs_f) + 6;
+                if (guard > walk_cap) { walk_cap = guard; walk = (int64_t *)realloc(walk, sizeof(int64_t) * 3 * walk_cap); }
+                nvox = orc_ray_walk32(o32, uf, s0, s1, vs_f, walk, guard);
+                const float wf = s->p.weight_mode ? 1.0f / (z * z) : 1.0f;
+                for (int64_t k = 0; k < nvox; ++k) {
+                    float c[3];
+                    for (int a = 0; a < 3; ++a) c[a] = ((float)walk[3 * k + a] + 0.5f) * vs_f;
+                    const float proj = ((c[0] - o32[0]) * uf[0] + (c[1] - o32[1]) * uf[1]) + (c[2] - o32[2]) * uf[2];
+                    const float sdf = rf - proj;
+                    if (!(sdf >= -tau_f)) continue;
+                    if (nc == capc) { capc *= 2; L = (ray_contrib *)realloc(L, sizeof(ray_contrib) * capc); }
+                    const int64_t *v = walk + 3 * k;
+                    L[nc].bkey = pack_key(floordiv8(v[0]), floordiv8(v[1]), floordiv8(v[2]));
+                    L[nc].lin = lin_index(v[0], v[1], v[2]);
+                    L[nc].pix = pix;
+                    L[nc].t = fminf(sdf, tau_f);
+                    L[nc].w = wf;
+                    ++nc;
+                }
+            } else {
+                const double zd = z;
+                const double xc = (((double)col - K[2]) * zd) / K[0];
+                const double yc = (((double)row - K[3]) * zd) / K[1];
+                double d[3];
+                for (int k = 0; k < 3; ++k) d[k] = (R64[3 * k] * xc + R64[3 * k + 1] * yc) + R64[3 * k + 2] * zd;
+                r = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+                for (int k = 0; k < 3; ++k) { u[k] = d[k] / r; o[k] = o64[k]; }
+                const double s1 = r + tau;
+                const double s0 = s->p.ray_carve ? 0.0 : fmax(r - tau, 0.0);
+                guard = 3 * (int64_t)ceil((s1 - s0) / s->p.vs) + 6;
+                if (guard > walk_cap) { walk_cap = guard; walk = (int64_t *)realloc(walk, sizeof(int64_t) * 3 * walk_cap); }
+                nvox = ray_walk64(o, u, s0, s1, s->p.vs, walk, guard);
+                w = s->p.weight_mode ? 1.0 / (zd * zd) : 1.0;
+                for (int64_t k = 0; k < nvox; ++k) {
+                    double c[3];
+                    for (int a = 0; a < 3; ++a) c[a] = ((double)walk[3 * k + a] + 0.5) * s->p.vs;
+                    const double proj = ((c[0] - o[0]) * u[0] + (c[1] - o[1]) * u[1]) + (c[2] - o[2]) * u[2];
+                    const double sdf = r - proj;
+                    if (!(sdf >= -tau)) continue;
+                    if (nc == capc) { capc *= 2; L = (ray_contrib *)realloc(L, sizeof(ray_contrib) * capc); }
+                    const int64_t *v = walk + 3 * k;
+                    L[nc].bkey = pack_key(floordiv8(v[0]), floordiv8(v[1]), floordiv8(v[2]));
+                    L[nc].lin = lin_index(v[0], v[1], v[2]);
+                    L[nc].pix = pix;
+                    L[nc].t = sdf < tau ? sdf : tau;
+                    L[nc].w = w;
+                    ++nc;
+                }
+            }
+        }
+    free(walk);
+
+    /* count and allocate */
+    uint64_t *tk = (uint64_t *)malloc(sizeof(uint64_t) * (nc ? nc : 1));
+    for (size_t j = 0; j < nc; ++j) tk[j] = L[j].bkey;
+    size_t nt = 0;
+    const int64_t n_new = allocate_touched(s, tk, nc, &nt);
+    free(tk);
+
+    /* merge per voxel: contributions sorted by (voxel, pixel) */
+    qsort(L, nc, sizeof(ray_contrib), cmp_contrib);
+    int64_t n_vox = 0;
+    for (size_t j = 0; j < nc;) {
+        size_t e = j;
+        while (e < nc && L[e].bkey == L[j].bkey && L[e].lin == L[j].lin) ++e;
+        const size_t o = (size_t)512 * find_block(s, L[j].bkey) + (size_t)L[j].lin;
+        if (s->p.fp64) {
+            double sw = 0.0, stw = 0.0;
+            for (size_t k = j; k < e; ++k) { sw = sw + L[k].w; stw = stw + L[k].t * L[k].w; }
+            const double Wn = s->W64[o] + sw;
+            s->D64[o] = ((s->D64[o] * s->W64[o]) + stw) / Wn;
+            s->W64[o] = Wn;
+        } else {
+            /* t and w are binary32 values; their products are exact in
+             * binary64, and the sums are kept in binary64 */
+            double sw = 0.0, stw = 0.0;
+            for (size_t k = j; k < e; ++k) { sw = sw + L[k].w; stw = stw + L[k].t * L[k].w; }
+            const float Wold = s->W[o], Dold = s->D[o];
+            const float Wn = Wold + (float)sw;
+            const float Dn = ((Dold * Wold) + (float)stw) / Wn;
+            s->D[o] = round_store(s, Dn);
+            s->W[o] = round_store(s, Wn);
+        }
+        ++n_vox;
+        j = e;
+    }
+    free(L);
+    if (stats) { stats[0] = n_new; stats[1] = (int64_t)nt; stats[2] = (int64_t)nc; stats[3] = n_vox; }
     return ORC_OK;
 }
 
