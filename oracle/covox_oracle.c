@@ -491,7 +491,8 @@ int orc_integrate(orc_submap *s, const float *depth, int H, int W, const float K
  * direction u (binary32): the grid traversal of Amanatides and Woo
  * (Eurographics 1987).  The start voxel holds o + s0 u; the parameter of the
  * next boundary along axis a is computed from the voxel index itself,
- *   s_a = ((i_a + [u_a > 0]) vs - o_a) / u_a   (infinite when u_a = 0),
+ *   s_a = ((i_a + [u_a > 0]) vs - o_a) * (1 / u_a)   (infinite when u_a = 0,
+ *   the reciprocal rounded once per ray),
  * the smallest s_a (x before y before z on ties) moves that axis by one, and
  * the walk ends once that smallest s_a is not below s1.  At most max_out
  * voxels (3 ceil((s1 - s0) / vs) + 6 bounds the walk) are written to out as
@@ -502,12 +503,13 @@ int64_t orc_ray_walk32(const float o[3], const float u[3], float s0, float s1, f
 {
     int64_t i[3];
     int step[3];
-    float sn[3];
+    float sn[3], iu[3];
     for (int a = 0; a < 3; ++a) {
         const float e = o[a] + s0 * u[a];
         i[a] = (int64_t)floorf(e / vs);
         step[a] = u[a] > 0.0f ? 1 : (u[a] < 0.0f ? -1 : 0);
-        sn[a] = step[a] ? (((float)(i[a] + (step[a] > 0)) * vs) - o[a]) / u[a] : INFINITY;
+        iu[a] = step[a] ? 1.0f / u[a] : 0.0f;
+        sn[a] = step[a] ? (((float)(i[a] + (step[a] > 0)) * vs) - o[a]) * iu[a] : INFINITY;
     }
     int64_t n = 0;
     while (n < max_out) {
@@ -518,7 +520,7 @@ int64_t orc_ray_walk32(const float o[3], const float u[3], float s0, float s1, f
         if (sn[2] < sn[a]) a = 2;
         if (!(sn[a] < s1)) break;
         i[a] += step[a];
-        sn[a] = (((float)(i[a] + (step[a] > 0)) * vs) - o[a]) / u[a];
+        sn[a] = (((float)(i[a] + (step[a] > 0)) * vs) - o[a]) * iu[a];
     }
     return n;
 }
@@ -529,12 +531,13 @@ static int64_t ray_walk64(const double o[3], const double u[3], double s0, doubl
 {
     int64_t i[3];
     int step[3];
-    double sn[3];
+    double sn[3], iu[3];
     for (int a = 0; a < 3; ++a) {
         const double e = o[a] + s0 * u[a];
         i[a] = (int64_t)floor(e / vs);
         step[a] = u[a] > 0.0 ? 1 : (u[a] < 0.0 ? -1 : 0);
-        sn[a] = step[a] ? (((double)(i[a] + (step[a] > 0)) * vs) - o[a]) / u[a] : INFINITY;
+        iu[a] = step[a] ? 1.0 / u[a] : 0.0;
+        sn[a] = step[a] ? (((double)(i[a] + (step[a] > 0)) * vs) - o[a]) * iu[a] : INFINITY;
     }
     int64_t n = 0;
     while (n < max_out) {
@@ -545,7 +548,7 @@ static int64_t ray_walk64(const double o[3], const double u[3], double s0, doubl
         if (sn[2] < sn[a]) a = 2;
         if (!(sn[a] < s1)) break;
         i[a] += step[a];
-        sn[a] = (((double)(i[a] + (step[a] > 0)) * vs) - o[a]) / u[a];
+        sn[a] = (((double)(i[a] + (step[a] > 0)) * vs) - o[a]) * iu[a];
     }
     return n;
 }
