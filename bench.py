@@ -463,6 +463,47 @@ def learned_bench(cv, torch, np, ctx, subs, Tws, vs, n_items=1024, reps=3):
     return out
 
 
+def integrator_bench(cv, torch, np, w, dev, tuning, reps=2):
+    """Projection mapping against raycasting (carved from the optical centre,
+    and band-only rays) on the room sequence: integration-only frames/s
+    (300 frames, no ESDF), TSDF+ESDF frames/s (ESDF after every frame), and
+    kernel time per frame by kind."""
+    out = {}
+    for name, kw in (("projective", dict(integrator=cv.PROJECTIVE)),
+                     ("raycast_carve", dict(integrator=cv.RAYCAST, ray_carve=1)),
+                     ("raycast_band", dict(integrator=cv.RAYCAST, ray_carve=0))):
+        ctx = cv.Context(voxel_size=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max,
+                         block_capacity=32768, **kw)
+        ctx.set_tuning(**tuning)
+        s = ctx.submap_create()
+        r = {}
+        for label, every in (("integrate_only", 0), ("tsdf_esdf", 1)):
+            best = None
+            for k in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.submap_reset(s)
+                ctx.map_sequence(s, dev, w.cam.K, w.poses, esdf_every=every)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if k > 0:  # the first pass warms up
+                    best = dt if best is None else min(best, dt)
+            r[label + "_frames_per_s"] = w.n_frames / best
+        ctx.timing_enable(None)
+        ctx.submap_reset(s)
+        ctx.map_sequence(s, dev, w.cam.K, w.poses, esdf_every=0)
+        r["kernel_us_per_frame"] = {k: v[0] * 1e3 / w.n_frames for k, v in ctx.timing_get().items() if v[1]}
+        ctx.timing_enable([])
+        info = ctx.submap_info(s)
+        r["blocks"], r["voxel_updates_per_frame"] = info["n_blocks"], info["n_updates"] / w.n_frames
+        out[name] = r
+        ctx.close()
+    p = out["projective"]["integrate_only_frames_per_s"]
+    for name in ("raycast_carve", "raycast_band"):
+        out[name]["integrate_only_speed_vs_projective"] = out[name]["integrate_only_frames_per_s"] / p
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -475,6 +516,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"])
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage room timing")
+    ap.add_argument("--no-raycast", action="store_true", help="skip the projective / raycast comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -611,6 +653,9 @@ def main():
         torch.cuda.synchronize()
         result["config"]["fp16_storage_frames_per_s"] = w.n_frames * args.steps / (time.perf_counter() - t0)
         c16.close()
+    if prec == cv.FP32 and not args.no_raycast:
+        _log("projection mapping against raycasting (room)")
+        result["integrators"] = integrator_bench(cv, torch, np, w, dev, room_tuning)
     if not args.no_align:
         _log("alignment pairs")
         result["align"] = align_bench(cv, torch, np, w, dev)

@@ -78,13 +78,19 @@ typedef struct {
     int32_t weight_mode;     /* observation weight (Sec. III-C, weights after the sensor's noise):
                                 COVOX_WEIGHT_CONSTANT (1) or COVOX_WEIGHT_INV_DEPTH2 (1 / d^2, d = the
                                 pixel's depth in m) */
+    int32_t integrator;      /* COVOX_PROJECTIVE (projection mapping) or COVOX_RAYCAST (Sec. III-C
+                                raycasting: see covox_integrate_depth); raycasting needs FP32 storage */
+    int32_t ray_carve;       /* raycasting: 1 = rays start at the optical centre (free space is
+                                carved, as the paper describes), 0 = at tau before the point */
 } covox_params;
 
 enum { COVOX_WEIGHT_CONSTANT = 0, COVOX_WEIGHT_INV_DEPTH2 = 1 };
+enum { COVOX_PROJECTIVE = 0, COVOX_RAYCAST = 1 };
 
 /* Fills p with the defaults: 0.05 m voxels, tau = 4 voxels, 5 m range, 2 m
  * ESDF, w_reg = 2, 65536 blocks, FP32, 30 iterations, n_min = 100,
- * tolerances 1e-7 m and 1e-8 rad. */
+ * tolerances 1e-7 m and 1e-8 rad, 6 DoF, constant weights, projection
+ * mapping (rays carved from the optical centre when raycasting). */
 void covox_default_params(covox_params *p);
 
 /* Creates a context on the current HIP device.  *out receives the handle.
@@ -93,8 +99,9 @@ int covox_create(covox_ctx **out, const covox_params *p);
 void covox_destroy(covox_ctx *ctx);
 
 /* Replaces the parameters that do not shape storage: w_reg, max_iter,
- * n_min, tol_rho, tol_theta, align_dof and weight_mode (the next
- * integrations use the new weight).  COVOX_EINVAL if p is invalid or
+ * n_min, tol_rho, tol_theta, align_dof, weight_mode, integrator and
+ * ray_carve (the next integrations use them; switching to raycasting
+ * allocates its accumulators, 16 bytes per voxel of block_capacity).  COVOX_EINVAL if p is invalid or
  * changes voxel_size, trunc_vox, max_range, d_max, block_capacity or
  * precision.  Registration points are re-extracted after a w_reg change. */
 int covox_set_params(covox_ctx *ctx, const covox_params *p);
@@ -131,7 +138,18 @@ int covox_submap_reset(covox_ctx *ctx, covox_submap *s);
  *   (0, max_range] and sdf = d - z >= -tau; blocks holding a valid voxel
  *   and not yet allocated get buffer indices n_blocks + rank in ascending
  *   packed-key order; every valid voxel takes t = min(sdf, tau),
- *   W' = W + 1, D' = (D W + t) / W' (binary32, no FMA contraction).
+ *   W' = W + w, D' = (D W + t w) / W' (binary32, no FMA contraction).
+ * With integrator = COVOX_RAYCAST (Sec. III-C raycasting, Sec. III-D merge):
+ *   T_submap_cam = T_world_submap^-1 T_world_cam (binary64, rounded once);
+ *   pixel (c, r) with depth z in (0, max_range] casts the ray q = ((c - cx)
+ *   z / fx, (r - cy) z / fy, z), d = R q, length r = |d|, unit u = d / r,
+ *   from the optical centre o (ray_carve = 1, else from r - tau) to r + tau;
+ *   the voxels it crosses (Amanatides-Woo walk in binary32, each boundary
+ *   parameter ((i + [u > 0]) vs - o) * (1 / u) computed from the index,
+ *   ties x before y before z) with sdf = r - (centre - o).u >= -tau contribute
+ *   t = min(sdf, tau) and w; new blocks are allocated as above; each voxel
+ *   sums w and t w over the frame in binary64, then W' = W + sw,
+ *   D' = (D W + stw) / W' in binary32.  Every valid pixel contributes.
  * depth_dev: device, H x W binary32, row-major, metres.  K: host, 4 floats.
  * T_world_cam: host, 16 doubles.  Asynchronous.  On EPOOL_FULL / ETABLE_FULL
  * the frame is dropped and the submap is unchanged; the condition is
@@ -434,6 +452,9 @@ enum {
     COVOX_K_ALIGN,         /* Gauss-Newton (persistent) */
     COVOX_K_SUMMARY,       /* coarse ESDF summaries */
     COVOX_K_NET,           /* proposal network (forward or backward) */
+    COVOX_K_RAY_MARK,      /* raycasting: clear, walk and flag touched blocks, resolve their index */
+    COVOX_K_RAY_ACCUM,     /* raycasting: walk again and accumulate (w, t w) per voxel */
+    COVOX_K_RAY_APPLY,     /* raycasting: activate new blocks, merge the sums into D and W */
     COVOX_K_COUNT
 };
 

@@ -1,4 +1,4 @@
-"""covox on MI355X: projective TSDF integration into a voxel-hashed block grid,
+"""covox on MI355X: projective or raycast TSDF integration into a voxel-hashed block grid,
 the exact ESDF derived from it, and correspondence-free ESDF submap alignment
 (Hoss and De Cristoforis, coVoxSLAM, arXiv 2410.21149), as hand-written HIP
 kernels for gfx950 behind the C ABI in include/covox.h.
@@ -7,9 +7,9 @@ kernels for gfx950 behind the C ABI in include/covox.h.
 HIP library has not been built.
 """
 from .covox import (EDEGENERATE, EHIP, EINVAL, EPOOL_FULL, ETABLE_FULL, FP16, FP32, KERNELS, LIB_PATH,
-                    NOT_CONVERGED, OK, WEIGHT_CONSTANT, WEIGHT_INV_DEPTH2, Context, CovoxError, Graph, Net, Submap,
-                    default_params)
+                    NOT_CONVERGED, OK, PROJECTIVE, RAYCAST, WEIGHT_CONSTANT, WEIGHT_INV_DEPTH2, Context, CovoxError,
+                    Graph, Net, Submap, default_params)
 
 __all__ = ["Context", "Graph", "Net", "Submap", "CovoxError", "default_params", "FP32", "FP16", "WEIGHT_CONSTANT",
-           "WEIGHT_INV_DEPTH2", "KERNELS", "OK", "EINVAL", "EPOOL_FULL", "ETABLE_FULL", "EHIP", "EDEGENERATE",
+           "WEIGHT_INV_DEPTH2", "PROJECTIVE", "RAYCAST", "KERNELS", "OK", "EINVAL", "EPOOL_FULL", "ETABLE_FULL", "EHIP", "EDEGENERATE",
            "NOT_CONVERGED", "LIB_PATH"]

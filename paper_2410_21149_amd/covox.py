@@ -25,8 +25,9 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, EPOOL_FULL, ETABLE_FULL, EHIP, EDEGENERATE, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1
 FP32, FP16 = 0, 1
 WEIGHT_CONSTANT, WEIGHT_INV_DEPTH2 = 0, 1
+PROJECTIVE, RAYCAST = 0, 1
 KERNELS = ["probe", "scan", "integrate", "esdf_page", "esdf_sites", "edt_x", "edt_y", "edt_z", "iso", "align",
-           "summary", "net"]
+           "summary", "net", "ray_mark", "ray_accum", "ray_apply"]
 
 
 class CovoxError(RuntimeError):
@@ -40,7 +41,7 @@ class covox_params(ctypes.Structure):
                 ("d_max", ctypes.c_double), ("w_reg", ctypes.c_double), ("block_capacity", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("n_min", ctypes.c_int32),
                 ("tol_rho", ctypes.c_double), ("tol_theta", ctypes.c_double), ("align_dof", ctypes.c_int32),
-                ("weight_mode", ctypes.c_int32)]
+                ("weight_mode", ctypes.c_int32), ("integrator", ctypes.c_int32), ("ray_carve", ctypes.c_int32)]
 
 
 class covox_align_stats(ctypes.Structure):
@@ -72,7 +73,7 @@ class covox_tuning(ctypes.Structure):
 
 
 class covox_timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 12), ("launches", ctypes.c_int64 * 12)]
+    _fields_ = [("ms", ctypes.c_double * len(KERNELS)), ("launches", ctypes.c_int64 * len(KERNELS))]
 
 
 class covox_summary_req(ctypes.Structure):
@@ -192,7 +193,7 @@ class Context:
 
     def set_params(self, **kw):
         """Changes non-storage parameters (w_reg, max_iter, n_min, tol_rho,
-        tol_theta, align_dof, weight_mode)."""
+        tol_theta, align_dof, weight_mode, integrator, ray_carve)."""
         p = covox_params.from_buffer_copy(self.params)
         for k, v in kw.items():
             setattr(p, k, v)

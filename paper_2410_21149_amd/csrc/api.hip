@@ -181,6 +181,16 @@ bool valid_params(const covox_params *p, std::string &why)
         why = "weight_mode must be COVOX_WEIGHT_CONSTANT or COVOX_WEIGHT_INV_DEPTH2";
         return false;
     }
+    if (p->integrator != COVOX_PROJECTIVE && p->integrator != COVOX_RAYCAST) {
+        why = "integrator must be COVOX_PROJECTIVE or COVOX_RAYCAST";
+        return false;
+    }
+    if (p->ray_carve != 0 && p->ray_carve != 1) { why = "ray_carve must be 0 or 1"; return false; }
+    if (p->integrator == COVOX_RAYCAST && p->precision != COVOX_FP32) {
+        // a voxel near the camera gains one weight per ray and frame
+        why = "raycasting needs FP32 storage (weights exceed the binary16 range)";
+        return false;
+    }
     return true;
 }
 
@@ -228,8 +238,10 @@ int check_status_after_sync(covox_ctx *ctx, covox_submap *s)
 int integrate_frames(covox_ctx *ctx, covox_submap *s, const float *depths, int32_t F, int32_t H, int32_t W,
                      const float K[4], const double *T_wc)
 {
+    // raycasting runs frame by frame (a capacity failure stops at its frame)
+    const int32_t per_call = ctx->p.integrator == COVOX_RAYCAST ? 1 : kMaxBatch;
     for (int32_t f0 = 0; f0 < F;) {
-        const int32_t n = std::min<int32_t>(kMaxBatch, F - f0);
+        const int32_t n = std::min<int32_t>(per_call, F - f0);
         bool maybe_full = false;
         const float *d = depths + (size_t)f0 * H * W;
         int rc = n == 1 ? integrate_frame(ctx, s, d, H, W, K, T_wc + 16 * f0, &maybe_full)
@@ -354,6 +366,8 @@ void covox_default_params(covox_params *p)
     p->tol_theta = 1e-8;
     p->align_dof = 6;
     p->weight_mode = COVOX_WEIGHT_CONSTANT;
+    p->integrator = COVOX_PROJECTIVE;
+    p->ray_carve = 1;
 }
 
 const char *covox_status_string(int s)
@@ -389,6 +403,10 @@ int covox_create(covox_ctx **out, const covox_params *p)
         delete ctx;
         return COVOX_EHIP;
     }
+    if (p->integrator == COVOX_RAYCAST && ensure_ray_acc(ctx) != COVOX_OK) {
+        delete ctx;
+        return COVOX_EHIP;
+    }
     *out = ctx;
     return COVOX_OK;
 }
@@ -403,7 +421,7 @@ void covox_destroy(covox_ctx *ctx)
                       (void *)ctx->g2, (void *)ctx->cnt, (void *)ctx->psum, ctx->prob_dev, ctx->res_dev, ctx->sum_dev,
                       (void *)ctx->net_in, (void *)ctx->net_out, (void *)ctx->train_y, (void *)ctx->loss_hist,
                       (void *)ctx->frames_dev, (void *)ctx->blist, (void *)ctx->fkeys, (void *)ctx->ffirst,
-                      (void *)ctx->fcount})
+                      (void *)ctx->fcount, (void *)ctx->ray_acc})
         if (ptr) (void)hipFree(ptr);
     for (void *p : ctx->deferred) (void)hipFree(p);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -432,6 +450,7 @@ int covox_set_params(covox_ctx *ctx, const covox_params *p)
     if (p->w_reg != o.w_reg)
         for (covox_submap *s : submaps_of(ctx)) s->pts_version = 0;
     ctx->p = *p;
+    if (p->integrator == COVOX_RAYCAST) return ensure_ray_acc(ctx);
     return COVOX_OK;
 }
 

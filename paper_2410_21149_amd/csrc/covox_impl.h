@@ -110,6 +110,11 @@ struct FrameArgs {
     float zfar;
     float cull_r;
     int32_t weight_mode;  // COVOX_WEIGHT_*
+    // Raycasting: submap <- camera rotation and the optical centre in the
+    // submap frame (binary64 rounded once), and whether rays start there.
+    float Rs[9];
+    float o[3];
+    int32_t ray_carve;
 };
 
 }  // namespace covox
@@ -197,6 +202,8 @@ struct covox_ctx {
     int64_t t_key_cap = 0;
     uint32_t *t_idx = nullptr;
     int64_t t_idx_cap = 0;
+    double *ray_acc = nullptr;  // raycasting: (sum w, sum t w) per voxel, zero between frames
+    int64_t ray_acc_blocks = 0;
     // EDT scratch over a dense block box
     uint64_t *sites = nullptr;  // 8 words per dense block
     int64_t sites_cap = 0;      // dense blocks
@@ -311,6 +318,21 @@ int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_
                     const float K[4], const double *T_wc, bool *maybe_full);
 int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H, int32_t W,
                     const float K[4], const double T_wc[16], bool *maybe_full);
+// Frame parameters and the frustum's block box (validates the arguments).
+int prepare_frame(covox_ctx *ctx, const covox_submap *s, const float *depth, int32_t H, int32_t W, const float K[4],
+                  const double T_wc[16], FrameArgs &f, int64_t &n_box);
+// Host block-count bound: registers the next call and its box size.
+void refresh_block_bound(covox_submap *s, int64_t next_box);
+// Host block-box bound after a frame with box f was enqueued.
+void grow_bounds(covox_submap *s, const FrameArgs &f);
+// Compaction of ctx->cand over the box into ctx->t_key / t_idx, capacity
+// check, new-block indices in key order (k_scan).
+void launch_block_scan(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, int64_t n_box, int64_t table_limit);
+
+// k_raycast.hip
+int raycast_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H, int32_t W, const float K[4],
+                  const double T_wc[16], bool *maybe_full);
+int ensure_ray_acc(covox_ctx *ctx);  // accumulators for block_capacity blocks (not under capture)
 
 // k_esdf.hip
 int build_page(covox_ctx *ctx, covox_submap *s);   // page + site masks of the bounding box

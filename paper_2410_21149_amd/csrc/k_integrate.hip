@@ -626,6 +626,8 @@ void launch_frame(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, float vs,
     }
 }
 
+}  // namespace
+
 // Tightens the host's upper bound on the block count without stalling: the
 // count the scan kernel of call q last published, plus the box sizes of the
 // calls enqueued after q.  Then registers the next call with its box size.
@@ -643,9 +645,13 @@ void refresh_block_bound(covox_submap *s, int64_t next_box)
     s->box_ring[s->seq % covox_submap::kSeqRing] = next_box;
 }
 
-}  // namespace
-
-namespace {
+// The compaction launch shared by both integrators (one workgroup).
+void launch_block_scan(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, int64_t n_box, int64_t table_limit)
+{
+    TimedLaunch tl(ctx, COVOX_K_SCAN);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, ctx->stream, ctx->cand, n_box, f, s->meta, s->cap,
+                       table_limit, ctx->t_key, ctx->t_idx, s->pin_nb_dev, s->seq);
+}
 
 // Frame parameters (pose rounded once from binary64) and the block box of
 // the frustum.
@@ -689,6 +695,12 @@ int prepare_frame(covox_ctx *ctx, const covox_submap *s, const float *depth, int
     double inv_ws[16], T_sc[16];
     rigid_inverse(s->T_ws, inv_ws);
     rigid_mul(inv_ws, T_wc, T_sc);
+    // submap <- camera, rounded once, for raycasting
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) f.Rs[3 * r + c] = (float)T_sc[4 * r + c];
+        f.o[r] = (float)T_sc[4 * r + 3];
+    }
+    f.ray_carve = p.ray_carve;
     const double tau = p.trunc_vox * p.voxel_size;
     const double zf = p.max_range + tau;
     double mn[3], mx[3];
@@ -718,6 +730,8 @@ int prepare_frame(covox_ctx *ctx, const covox_submap *s, const float *depth, int
     return COVOX_OK;
 }
 
+namespace {
+
 // Batch id reserved for batches captured in a graph.
 constexpr uint32_t kCapturedBatch = 0xFFFFFFFFu;
 
@@ -745,6 +759,8 @@ int stage_frames(covox_ctx *ctx, const FrameArgs *fr, int32_t F)
     return hip_check(ctx, hipEventRecord(ctx->frames_ev[slot], ctx->stream), "frame staging record");
 }
 
+}  // namespace
+
 // Host bounds after frames with the given boxes were enqueued.
 void grow_bounds(covox_submap *s, const FrameArgs &f)
 {
@@ -756,12 +772,11 @@ void grow_bounds(covox_submap *s, const FrameArgs &f)
     s->bound_valid = true;
 }
 
-}  // namespace
-
 int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H, int32_t W,
                     const float K[4], const double T_wc[16], bool *maybe_full)
 {
     const covox_params &p = ctx->p;
+    if (p.integrator == COVOX_RAYCAST) return raycast_frame(ctx, s, depth, H, W, K, T_wc, maybe_full);
     FrameArgs f;
     int64_t n_box = 0;
     int rc = prepare_frame(ctx, s, depth, H, W, K, T_wc, f, n_box);

@@ -52,7 +52,9 @@ def test_create_rejects_bad_params(lib):
     spec = importlib.util.spec_from_file_location("_b2", os.path.join(ROOT, "paper_2410_21149_amd", "covox.py"))
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
-    for kw in [dict(voxel_size=-1.0), dict(trunc_vox=0), dict(d_max=10.0), dict(precision=7), dict(n_min=0)]:
+    for kw in [dict(voxel_size=-1.0), dict(trunc_vox=0), dict(d_max=10.0), dict(precision=7), dict(n_min=0),
+               dict(align_dof=5), dict(weight_mode=2), dict(integrator=2), dict(ray_carve=3),
+               dict(integrator=1, precision=1)]:
         p = mod.default_params(**kw)
         h = ctypes.c_void_p()
         assert mod._lib.covox_create(ctypes.byref(h), ctypes.byref(p)) == mod.EINVAL
