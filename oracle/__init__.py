@@ -1,6 +1,7 @@
 """covox oracle -- TEST INFRASTRUCTURE ONLY.
 
-A thin ctypes wrapper around ``covox_oracle.c``: a plain, slow CPU
+A thin ctypes wrapper around ``covox_oracle.c`` (and, in ``pgo.py``, the
+submap pose-graph optimisation in numpy): a plain, slow CPU
 implementation of projective TSDF integration, the exact truncated ESDF and
 the correspondence-free ESDF alignment (Hoss and De Cristoforis, coVoxSLAM,
 arXiv 2410.21149: Sec. III-C, III-D, III-E, III-F, Eq. 1).  Only the tests,
