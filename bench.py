@@ -372,11 +372,19 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
             align_4dof["dof%d_starts_%d" % (dof, n_starts)] = run_pairs(pairs_g, gts_g, n_starts)
     ctx.set_params(align_dof=6)
     align["gravity_aligned_priors"] = align_4dof
+    # pose graph: every pair within three submaps that shares at least 10 % of its blocks
+    cand_pgo = []
+    for i in range(nsub):
+        for j in range(i + 1, min(nsub, i + 4)):
+            ov = block_overlap(keys[i], Tws[i], keys[j], Tws[j], w.voxel_size, np)
+            if ov >= 0.1:
+                cand_pgo.append((i, j, ov))
+    pose_graph = pgo_bench(cv, torch, np, ctx, subs, Tws, cand_pgo, reps)
     learned = learned_bench(cv, torch, np, ctx, subs, Tws, w.voxel_size)
     ctx.close()
     return {"workload": "outdoor 120x80 m, 3000 frames 640x480 fx=fy=380, 0.1 m voxels, 30 submaps of 100 frames",
             "build_s": t_build, "render_s": t_render, "mapping": mapping, "esdf_batch": esdf, "align": align,
-            "learned": learned}
+            "pose_graph": pose_graph, "learned": learned}
 
 
 def _success(T, gts, np, bound_t, bound_deg):
@@ -386,6 +394,59 @@ def _success(T, gts, np, bound_t, bound_deg):
         c = (np.trace(Tg[:3, :3] @ Tt[:3, :3].T) - 1) / 2
         ok += et <= bound_t and math.degrees(math.acos(max(-1.0, min(1.0, c)))) <= bound_deg
     return ok / max(1, len(gts))
+
+
+def pgo_bench(cv, torch, np, ctx, subs, Tws, cand, reps=2):
+    """Submap pose-graph optimisation (Eq. 1) over the 30 outdoor submaps:
+    odometry between consecutive submaps with noise (0.1 m horizontal,
+    0.05 m vertical, 0.3 deg yaw per step, the factor sigmas), poses started
+    at dead reckoning from it, registration terms for every pair within
+    three submaps sharing at least 10 % of its blocks, in both directions.  Reports the position / yaw RMS error against the
+    ground truth before and after, LM iterations and the wall time."""
+    n = len(subs)
+    x_true = np.array([[T[0, 3], T[1, 3], T[2, 3], math.atan2(T[1, 0], T[0, 0])] for T in Tws])
+
+    def rel(xi, xj):
+        c, s = math.cos(xi[3]), math.sin(xi[3])
+        d = xj[:3] - xi[:3]
+        return np.array([c * d[0] + s * d[1], -s * d[0] + c * d[1], d[2], xj[3] - xi[3]])
+
+    rng = np.random.default_rng(7)
+    sig = np.array([0.1, 0.1, 0.05, math.radians(0.3)])
+    facs, x0 = [], np.zeros_like(x_true)
+    x0[0] = x_true[0]
+    for k in range(n - 1):
+        z = rel(x_true[k], x_true[k + 1]) + rng.normal(size=4) * sig
+        facs.append(dict(i=k, j=k + 1, z=z, sigma=sig))
+        c, s = math.cos(x0[k, 3]), math.sin(x0[k, 3])
+        x0[k + 1, :3] = x0[k, :3] + np.array([c * z[0] - s * z[1], s * z[0] + c * z[1], z[2]])
+        x0[k + 1, 3] = x0[k, 3] + z[3]
+    pairs = [(i, j) for (i, j, _) in cand] + [(j, i) for (i, j, _) in cand]
+
+    def err(x):
+        dp = np.linalg.norm(x[:, :3] - x_true[:, :3], axis=1)
+        dy = np.degrees(np.abs(np.angle(np.exp(1j * (x[:, 3] - x_true[:, 3])))))
+        return float(np.sqrt(np.mean(dp ** 2))), float(np.sqrt(np.mean(dy ** 2)))
+
+    ctx.pgo_solve(subs, x0, pairs, facs, max_iter=2)  # registration points extracted once
+    best, out = None, None
+    for _ in range(reps):
+        ctx.timing_enable(["align", "pgo"])
+        t0 = time.perf_counter()
+        x, st = ctx.pgo_solve(subs, x0, pairs, facs, sigma_reg=0.05, max_iter=20)
+        dt = time.perf_counter() - t0
+        tk = ctx.timing_get()
+        ctx.timing_enable([])
+        if best is None or dt < best:
+            best, out = dt, (x, st, tk)
+    x, st, tk = out
+    e0, e1 = err(x0), err(x)
+    return {"submaps": n, "registration_terms": len(pairs), "odometry_terms": len(facs),
+            "rms_position_error_m": {"dead_reckoning": e0[0], "optimised": e1[0]},
+            "rms_yaw_error_deg": {"dead_reckoning": e0[1], "optimised": e1[1]},
+            "lm_iterations": st["iterations"], "accepted": st["accepted"], "cg_iterations": st["cg_iterations"],
+            "ms": best * 1e3, "ms_per_lm_iteration": best * 1e3 / max(st["iterations"], 1),
+            "kernel_ms": {k: v[0] for k, v in tk.items() if v[1]}}
 
 
 def learned_bench(cv, torch, np, ctx, subs, Tws, vs, n_items=1024, reps=3):

@@ -365,6 +365,69 @@ typedef struct {
 int covox_train_proposal(covox_ctx *ctx, covox_net *net, const covox_train_cfg *cfg, const covox_pair *pairs,
                          int32_t n, float *loss_host);
 
+/* --------------------------------------------------- pose graph (Eq. 1) */
+
+/*
+ * Submap pose-graph optimisation (Eq. 1, Sec. III-F backend): the poses of
+ * n submaps minimise
+ *   F = sum_reg c_ij / sigma_reg^2 + sum_factors e^T diag(1 / sigma^2) e
+ * where c_ij is the sum of squared alignment residuals phi_i(T_i^-1 T_j p)
+ * over the registration points p of submap j (the residual of
+ * covox_normal_equations), and e is a 4-DoF relative-pose error.
+ *   pose of submap k: x_k = (t_x, t_y, t_z, yaw), T_k = [Rz(yaw) t; 0 1]
+ *     (R^3 x SO(2): gravity known); x_0 is held fixed;
+ *   factor (i, j) with measured z of T_i^-1 T_j:
+ *     e_t = Rz(-z_yaw) (Rz(-yaw_i) (t_j - t_i) - z_t),
+ *     e_yaw = wrap(yaw_j - yaw_i - z_yaw);
+ *   registration blocks: the 6x6 normal equations of T_ij under the left
+ *     perturbation, chained to x_i and x_j through Ad(T_i^-1) and the
+ *     first-order twist of (dt, dyaw);
+ *   Levenberg-Marquardt: (H + mu diag(H)) delta = -g solved by
+ *     block-Jacobi preconditioned CG on the block-sparse system; a step is
+ *     taken when the gain ratio is positive; mu follows the update of Madsen,
+ *     Nielsen and Tingleff (2004); stops when max |delta| < tol_step.
+ * Odometry and loop-closure factors have the same form (their sigmas
+ * differ).  Every submap of a registration pair needs a current ESDF (the
+ * field side) and registration points (the point side, extracted here).
+ */
+typedef struct {
+    int32_t i, j;         /* submap indices into the pose array */
+    int32_t reserved[2];
+    double z[4];          /* measured T_i^-1 T_j: (t_x, t_y, t_z) in m, yaw in rad */
+    double sigma[4];      /* standard deviations of the four error components (> 0) */
+} covox_pose_factor;
+
+typedef struct {
+    int32_t max_iter;     /* LM solves (20) */
+    int32_t cg_max_iter;  /* PCG iterations per solve; 0 = the system size */
+    double sigma_reg;     /* registration residual standard deviation, m (0.05) */
+    double lambda0;       /* initial damping, relative to diag(H) (1e-4) */
+    double tol_step;      /* stop when max |delta| < tol_step (1e-8) */
+    double cg_tol;        /* PCG stop: |r| <= cg_tol |b| (1e-12) */
+} covox_pgo_cfg;
+
+typedef struct {
+    int32_t iterations;     /* LM solves */
+    int32_t accepted;       /* steps taken */
+    int32_t converged;      /* 1 when max |delta| fell below tol_step */
+    int32_t cg_iterations;  /* PCG iterations over all solves */
+    double cost_init;       /* F at the initial poses */
+    double cost_final;      /* F at the returned poses */
+} covox_pgo_stats;
+
+void covox_default_pgo_cfg(covox_pgo_cfg *cfg);
+
+/* subs: n submaps (n >= 2).  x: host, n x 4 doubles, the initial poses on
+ * entry and the optimised ones on return (x_0 unchanged).  reg_pairs: host,
+ * n_reg x 2 int32 (i = the submap whose ESDF is sampled, j = the submap whose
+ * registration points are moved), i != j.  factors: host, n_fac entries.
+ * cfg: nullable (defaults).  stats: nullable.  Synchronous.  EINVAL for bad
+ * indices, sigmas or sizes, or when the damped system is not positive
+ * definite. */
+int covox_pgo_solve(covox_ctx *ctx, covox_submap *const *subs, int32_t n, double *x, const int32_t *reg_pairs,
+                    int32_t n_reg, const covox_pose_factor *factors, int32_t n_fac, const covox_pgo_cfg *cfg,
+                    covox_pgo_stats *stats);
+
 /* -------------------------------------------------------------- graphs */
 
 /* Capture of the asynchronous calls of a context into a HIP graph, so that a
@@ -455,6 +518,7 @@ enum {
     COVOX_K_RAY_MARK,      /* raycasting: clear, walk and flag touched blocks, resolve their index */
     COVOX_K_RAY_ACCUM,     /* raycasting: walk again and accumulate (w, t w) per voxel */
     COVOX_K_RAY_APPLY,     /* raycasting: activate new blocks, merge the sums into D and W */
+    COVOX_K_PGO,           /* pose graph: term blocks, block-sparse assembly, PCG */
     COVOX_K_COUNT
 };
 

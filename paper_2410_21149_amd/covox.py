@@ -27,7 +27,7 @@ FP32, FP16 = 0, 1
 WEIGHT_CONSTANT, WEIGHT_INV_DEPTH2 = 0, 1
 PROJECTIVE, RAYCAST = 0, 1
 KERNELS = ["probe", "scan", "integrate", "esdf_page", "esdf_sites", "edt_x", "edt_y", "edt_z", "iso", "align",
-           "summary", "net", "ray_mark", "ray_accum", "ray_apply"]
+           "summary", "net", "ray_mark", "ray_accum", "ray_apply", "pgo"]
 
 
 class CovoxError(RuntimeError):
@@ -70,6 +70,21 @@ class covox_tuning(ctypes.Structure):
     _fields_ = [("edt_y_env_min_cols", ctypes.c_int64), ("edt_z_env_min_cols", ctypes.c_int64),
                 ("align_threads", ctypes.c_int64), ("align_points_per_step", ctypes.c_int64),
                 ("reserved", ctypes.c_int64 * 4)]
+
+
+class covox_pose_factor(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_int32), ("j", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2),
+                ("z", ctypes.c_double * 4), ("sigma", ctypes.c_double * 4)]
+
+
+class covox_pgo_cfg(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("cg_max_iter", ctypes.c_int32), ("sigma_reg", ctypes.c_double),
+                ("lambda0", ctypes.c_double), ("tol_step", ctypes.c_double), ("cg_tol", ctypes.c_double)]
+
+
+class covox_pgo_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("accepted", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("cg_iterations", ctypes.c_int32), ("cost_init", ctypes.c_double), ("cost_final", ctypes.c_double)]
 
 
 class covox_timing(ctypes.Structure):
@@ -135,6 +150,10 @@ _sig = {
     "covox_autotune_esdf": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(covox_tuning)]),
     "covox_autotune_align": (ctypes.c_int, [_vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_int32,
                                             ctypes.POINTER(covox_tuning)]),
+    "covox_default_pgo_cfg": (None, [ctypes.POINTER(covox_pgo_cfg)]),
+    "covox_pgo_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int32, _dp, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.c_int32, ctypes.POINTER(covox_pose_factor), ctypes.c_int32,
+                                       ctypes.POINTER(covox_pgo_cfg), ctypes.POINTER(covox_pgo_stats)]),
     "covox_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "covox_timing_get": (ctypes.c_int, [_vp, ctypes.POINTER(covox_timing)]),
 }
@@ -320,6 +339,34 @@ class Context:
         self._check(_lib.covox_normal_equations(self.handle, A.handle, B.handle, _p(Tm, _dp), _p(out, _dp)),
                     "normal_equations")
         return out
+
+    # -- pose graph (Eq. 1)
+    def pgo_solve(self, subs, x0, reg_pairs, factors, **cfg):
+        """Submap pose-graph optimisation.  subs: submaps; x0: (n, 4) poses
+        (t, yaw) of their T_world_submap estimates (x0[0] is held fixed);
+        reg_pairs: (i, j) pairs (ESDF of i, registration points of j);
+        factors: dicts with i, j, z (4), sigma (4); cfg: max_iter,
+        cg_max_iter, sigma_reg, lambda0, tol_step, cg_tol.  Returns the
+        poses and a stats dict."""
+        c = covox_pgo_cfg()
+        _lib.covox_default_pgo_cfg(ctypes.byref(c))
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        n = len(subs)
+        hs = (_vp * n)(*[sm.handle for sm in subs])
+        x = np.ascontiguousarray(np.asarray(x0, np.float64).reshape(n, 4)).copy()
+        rp = np.ascontiguousarray(np.asarray(reg_pairs, np.int32).reshape(-1, 2))
+        fa = (covox_pose_factor * max(len(factors), 1))()
+        for k, f in enumerate(factors):
+            fa[k].i, fa[k].j = int(f["i"]), int(f["j"])
+            for a in range(4):
+                fa[k].z[a] = float(f["z"][a])
+                fa[k].sigma[a] = float(f["sigma"][a])
+        st = covox_pgo_stats()
+        self._check(_lib.covox_pgo_solve(self.handle, hs, n, _p(x, _dp), rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         len(rp), fa, len(factors), ctypes.byref(c), ctypes.byref(st)), "pgo_solve")
+        return x, {"iterations": st.iterations, "accepted": st.accepted, "converged": bool(st.converged),
+                   "cg_iterations": st.cg_iterations, "cost_init": st.cost_init, "cost_final": st.cost_final}
 
     # -- learned proposal
     def summaries(self, reqs):

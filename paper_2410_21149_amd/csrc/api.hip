@@ -705,6 +705,20 @@ int covox_normal_equations(covox_ctx *ctx, const covox_submap *A, covox_submap *
     return COVOX_OK;
 }
 
+void covox_default_pgo_cfg(covox_pgo_cfg *cfg)
+{
+    if (cfg) covox_default_pgo_cfg_impl(cfg);
+}
+
+int covox_pgo_solve(covox_ctx *ctx, covox_submap *const *subs, int32_t n, double *x, const int32_t *reg_pairs,
+                    int32_t n_reg, const covox_pose_factor *factors, int32_t n_fac, const covox_pgo_cfg *cfg,
+                    covox_pgo_stats *stats)
+{
+    if (!ctx) return COVOX_EINVAL;
+    COVOX_NOT_DURING_CAPTURE(ctx, "pgo_solve");
+    return pgo_solve(ctx, subs, n, x, reg_pairs, n_reg, factors, n_fac, cfg, stats);
+}
+
 int covox_submap_info_get(covox_ctx *ctx, const covox_submap *s, covox_submap_info *out)
 {
     COVOX_NOT_DURING_CAPTURE(ctx, "submap_info_get");

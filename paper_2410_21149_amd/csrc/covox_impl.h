@@ -329,6 +329,12 @@ void grow_bounds(covox_submap *s, const FrameArgs &f);
 // check, new-block indices in key order (k_scan).
 void launch_block_scan(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, int64_t n_box, int64_t table_limit);
 
+// k_pgo.hip: submap pose-graph optimisation (covox_pgo_solve)
+void covox_default_pgo_cfg_impl(covox_pgo_cfg *c);
+int pgo_solve(covox_ctx *ctx, covox_submap *const *subs, int32_t n, double *x, const int32_t *reg_pairs,
+              int32_t n_reg, const covox_pose_factor *factors, int32_t n_fac, const covox_pgo_cfg *cfg,
+              covox_pgo_stats *stats);
+
 // k_raycast.hip
 int raycast_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H, int32_t W, const float K[4],
                   const double T_wc[16], bool *maybe_full);

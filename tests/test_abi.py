@@ -68,9 +68,10 @@ def test_struct_layouts_match_header():
     src = r'''
 #include <stdio.h>
 #include "covox.h"
-int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(covox_params), sizeof(covox_align_stats),
+int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu ", sizeof(covox_params), sizeof(covox_align_stats),
  sizeof(covox_pair), sizeof(covox_submap_info), sizeof(covox_timing), sizeof(covox_summary_req),
- sizeof(covox_train_cfg), sizeof(covox_tuning));return 0;}
+ sizeof(covox_train_cfg), sizeof(covox_tuning));
+ printf("%zu %zu %zu\n", sizeof(covox_pose_factor), sizeof(covox_pgo_cfg), sizeof(covox_pgo_stats));return 0;}
 '''
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
@@ -85,4 +86,6 @@ int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(covox_params),
     assert sizes == [ctypes.sizeof(mod.covox_params), ctypes.sizeof(mod.covox_align_stats),
                      ctypes.sizeof(mod.covox_pair), ctypes.sizeof(mod.covox_submap_info),
                      ctypes.sizeof(mod.covox_timing), ctypes.sizeof(mod.covox_summary_req),
-                     ctypes.sizeof(mod.covox_train_cfg), ctypes.sizeof(mod.covox_tuning)]
+                     ctypes.sizeof(mod.covox_train_cfg), ctypes.sizeof(mod.covox_tuning),
+                     ctypes.sizeof(mod.covox_pose_factor), ctypes.sizeof(mod.covox_pgo_cfg),
+                     ctypes.sizeof(mod.covox_pgo_stats)]
