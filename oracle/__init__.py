@@ -44,7 +44,8 @@ class _Params(ctypes.Structure):
                 ("d_max", ctypes.c_double), ("w_reg", ctypes.c_double), ("fp64", ctypes.c_int),
                 ("fp16", ctypes.c_int), ("max_iter", ctypes.c_int), ("n_min", ctypes.c_int),
                 ("tol_rho", ctypes.c_double), ("tol_theta", ctypes.c_double), ("align_dof", ctypes.c_int),
-                ("weight_mode", ctypes.c_int), ("integrator", ctypes.c_int), ("ray_carve", ctypes.c_int)]
+                ("weight_mode", ctypes.c_int), ("integrator", ctypes.c_int), ("ray_carve", ctypes.c_int),
+                ("esdf_mode", ctypes.c_int)]
 
 
 class _Conv(ctypes.Structure):
@@ -110,6 +111,8 @@ def _load():
         L.orc_summary.argtypes = [_vp, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double, _dp]
         L.orc_bf16_round.restype = ctypes.c_float
         L.orc_bf16_round.argtypes = [ctypes.c_float]
+        L.orc_esdf_wavefront.restype = ctypes.c_int
+        L.orc_esdf_wavefront.argtypes = [_vp, _i64p]
         L.orc_ray_walk32.restype = ctypes.c_int64
         L.orc_ray_walk32.argtypes = [_fp, _fp, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i64p, ctypes.c_int64]
         L.orc_pose_cam_sub.restype = None
@@ -131,16 +134,17 @@ class Params:
 
     def __init__(self, vs=0.05, trunc_vox=4, max_range=5.0, d_max=2.0, w_reg=2.0, fp64=False, fp16=False,
                  max_iter=30, n_min=100, tol_rho=1e-7, tol_theta=1e-8, align_dof=6, weight_mode=0, integrator=0,
-                 ray_carve=True):
+                 ray_carve=True, esdf_mode=0):
         self.vs, self.trunc_vox, self.max_range, self.d_max = vs, trunc_vox, max_range, d_max
         self.w_reg, self.fp64, self.fp16, self.max_iter, self.n_min = w_reg, fp64, fp16, max_iter, n_min
         self.tol_rho, self.tol_theta, self.align_dof, self.weight_mode = tol_rho, tol_theta, align_dof, weight_mode
         self.integrator, self.ray_carve = integrator, ray_carve  # 0: projection mapping, 1: raycasting
+        self.esdf_mode = esdf_mode  # 0: exact EDT, 1: incremental wavefront
 
     def _c(self):
         return _Params(self.vs, self.trunc_vox, self.max_range, self.d_max, self.w_reg, int(self.fp64),
                        int(self.fp16), self.max_iter, self.n_min, self.tol_rho, self.tol_theta, int(self.align_dof),
-                       int(self.weight_mode), int(self.integrator), int(bool(self.ray_carve)))
+                       int(self.weight_mode), int(self.integrator), int(bool(self.ray_carve)), int(self.esdf_mode))
 
 
 class Submap:
@@ -177,6 +181,13 @@ class Submap:
 
     def update_esdf(self):
         _load().orc_update_esdf(self._h)
+
+    def esdf_wavefront(self) -> dict:
+        """One incremental (wavefront) ESDF update; returns its round count,
+        block-rounds processed and blocks queued first."""
+        st = np.zeros(3, np.int64)
+        _load().orc_esdf_wavefront(self._h, _p(st, _i64p))
+        return {"rounds": int(st[0]), "block_rounds": int(st[1]), "dirty": int(st[2])}
 
     def export(self) -> dict:
         n = self.n_blocks

@@ -21,6 +21,10 @@
  *   esdf        Sec. I and Sec. III-E (Euclidean distance to the nearest
  *               obstacle built from the TSDF, reusing the distances inside the
  *               truncation band; exact EDT in the PBA lineage).
+ *   wavefront   Sec. III-E (incremental update: newly occupied and freed
+ *               voxels seed per-block work, each block is swept along every
+ *               axis, block faces pass better distances to the neighbours,
+ *               repeated until nothing changes).
  *   align       Sec. I and Sec. III-F, Eq. (1) registration term
  *               (correspondence-free ESDF alignment, registration points
  *               chosen by weight, least squares on residuals/Jacobians).
@@ -65,6 +69,7 @@ typedef struct {
     int weight_mode;   /* 0: weight 1 per observation; 1: weight 1 / d^2 (d = measured depth, m) */
     int integrator;    /* 0: projection mapping; 1: raycasting */
     int ray_carve;     /* raycasting: 1 = rays start at the optical centre; 0 = at tau before the point */
+    int esdf_mode;     /* 0: exact EDT recomputed; 1: incremental wavefront (nearest-site propagation) */
 } orc_params;
 
 typedef struct {
@@ -79,6 +84,11 @@ typedef struct {
     float *phi;
     double *phi64;
     int32_t *ksq;       /* squared EDT distance in voxels^2; -1 in band / unobserved */
+    /* wavefront ESDF state (esdf_mode 1) */
+    int32_t *wk;        /* squared distance to the parent site (voxels^2), or WF_INF */
+    int32_t *wpar;      /* parent site as a packed offset from the voxel, or WF_NONE */
+    uint8_t *wsite;     /* site flag at the last update */
+    int64_t wn;         /* blocks at the last update */
 } orc_submap;
 
 /* ------------------------------------------------------------ keys */
@@ -241,6 +251,7 @@ void orc_submap_destroy(orc_submap *s)
     free(s->keys); free(s->skeys); free(s->sidx);
     free(s->D); free(s->W); free(s->D64); free(s->W64);
     free(s->phi); free(s->phi64); free(s->ksq);
+    free(s->wk); free(s->wpar); free(s->wsite);
     free(s);
 }
 
@@ -262,6 +273,9 @@ static void grow(orc_submap *s, int64_t need)
         s->phi = (float *)realloc(s->phi, sizeof(float) * 512 * nc);
     }
     s->ksq = (int32_t *)realloc(s->ksq, sizeof(int32_t) * 512 * nc);
+    s->wk = (int32_t *)realloc(s->wk, sizeof(int32_t) * 512 * nc);
+    s->wpar = (int32_t *)realloc(s->wpar, sizeof(int32_t) * 512 * nc);
+    s->wsite = (uint8_t *)realloc(s->wsite, 512 * nc);
     s->cap = nc;
 }
 
@@ -768,8 +782,11 @@ static double Wval(const orc_submap *s, size_t o) { return s->p.fp64 ? s->W64[o]
  *   phi = sign * min(d_max, vs * sqrt(k)) for k <= R^2 with R = round(d_max /
  *   vs), else sign * d_max; sign = +1 when D > 0.  Unobserved: NaN.
  */
+int orc_esdf_wavefront(orc_submap *s, int64_t *stats);
+
 int orc_update_esdf(orc_submap *s)
 {
+    if (s->p.esdf_mode == 1) return orc_esdf_wavefront(s, NULL);
     if (s->n == 0) return ORC_OK;
     const int fp64 = s->p.fp64;
     const double tau = band_limit(&s->p);
@@ -869,6 +886,213 @@ int orc_update_esdf(orc_submap *s)
     return ORC_OK;
 }
 
+/* ----------------------------------------------------- ESDF wavefront */
+
+#define WF_INF INT32_MAX
+#define WF_NONE (-1)
+
+static int32_t wf_pack(int dx, int dy, int dz) { return (dx + 128) | ((dy + 128) << 8) | ((dz + 128) << 16); }
+
+static void wf_unpack(int32_t p, int d[3])
+{
+    d[0] = (p & 255) - 128;
+    d[1] = ((p >> 8) & 255) - 128;
+    d[2] = ((p >> 16) & 255) - 128;
+}
+
+/* Voxel v takes the parent site of its face neighbour u (parent offset pu,
+ * e = u - v) when that site is nearer than its own and within R. */
+static int wf_offer(int32_t *kv, int32_t *pv, int32_t ku, int32_t pu, const int e[3], int64_t R2)
+{
+    if (ku == WF_INF) return 0;
+    int d[3];
+    wf_unpack(pu, d);
+    const int o[3] = {d[0] + e[0], d[1] + e[1], d[2] + e[2]};
+    const int64_t k = (int64_t)o[0] * o[0] + (int64_t)o[1] * o[1] + (int64_t)o[2] * o[2];
+    if (k > R2 || k >= *kv) return 0;
+    *kv = (int32_t)k;
+    *pv = wf_pack(o[0], o[1], o[2]);
+    return 1;
+}
+
+/* Buffer index of the block next to block j in direction dir (0 -x, 1 +x,
+ * 2 -y, 3 +y, 4 -z, 5 +z), or -1. */
+static int64_t wf_neighbour(const orc_submap *s, int64_t j, int dir)
+{
+    int64_t b[3];
+    unpack_key(s->keys[j], b);
+    b[dir >> 1] += (dir & 1) ? 1 : -1;
+    return find_block(s, pack_key(b[0], b[1], b[2]));
+}
+
+static int site_of(const orc_submap *s, size_t o)
+{
+    if (s->p.fp64) return s->W64[o] > 0 && fabs(s->D64[o]) <= s->p.vs;
+    return s->W[o] > 0.0f && fabsf(s->D[o]) <= (float)s->p.vs;
+}
+
+/*
+ * Incremental ESDF (Sec. III-E).  Every voxel of an allocated block keeps
+ * its nearest known site (parent, as an offset) and the squared distance k
+ * to it in voxels^2 (k <= R^2, else none), R = round(d_max / vs).
+ *   1. sites: observed voxels with |D| <= vs (as for the exact EDT);
+ *   2. seeds: voxels of new blocks start with no parent; a site takes
+ *      itself (k = 0); a voxel whose parent is no longer a site loses it
+ *      (raise); every block with such a change is queued;
+ *   3. rounds, until the queue is empty; each queued block, from the state
+ *      of the previous round: its face voxels take the parents of the
+ *      neighbouring blocks' face voxels when nearer (faces -x, +x, -y, +y,
+ *      -z, +z in turn), then each axis x, y, z is swept forward and
+ *      backward, every voxel taking its predecessor's parent when nearer;
+ *      a block that changed queues itself and its six neighbours;
+ *   4. phi of every observed voxel as for the exact EDT, with k from 3.
+ * stats (nullable): [rounds, block-rounds processed, blocks queued first].
+ */
+int orc_esdf_wavefront(orc_submap *s, int64_t *stats)
+{
+    const int64_t n = s->n, n0 = s->wn;
+    const int64_t Rv = llround(s->p.d_max / s->p.vs), R2 = Rv * Rv;
+    uint8_t *site = (uint8_t *)malloc((size_t)512 * (n ? n : 1));
+    uint8_t *q = (uint8_t *)calloc((size_t)(n ? n : 1), 1);
+    for (int64_t j = 0; j < n; ++j)
+        for (int l = 0; l < 512; ++l) site[512 * j + l] = (uint8_t)site_of(s, (size_t)512 * j + l);
+    int64_t n_dirty = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t b[3];
+        unpack_key(s->keys[j], b);
+        for (int l = 0; l < 512; ++l) {
+            const size_t o = (size_t)512 * j + l;
+            if (j >= n0) { s->wk[o] = WF_INF; s->wpar[o] = WF_NONE; q[j] = 1; }
+            if (site[o]) {
+                if (s->wk[o] != 0) { s->wk[o] = 0; s->wpar[o] = wf_pack(0, 0, 0); q[j] = 1; }
+            } else if (s->wk[o] != WF_INF) {
+                int d[3];
+                wf_unpack(s->wpar[o], d);
+                const int64_t v[3] = {8 * b[0] + (l & 7), 8 * b[1] + ((l >> 3) & 7), 8 * b[2] + (l >> 6)};
+                const int64_t st[3] = {v[0] + d[0], v[1] + d[1], v[2] + d[2]};
+                const int64_t sb = find_block(s, pack_key(floordiv8(st[0]), floordiv8(st[1]), floordiv8(st[2])));
+                if (sb < 0 || !site[512 * sb + lin_index(st[0], st[1], st[2])]) {
+                    s->wk[o] = WF_INF;
+                    s->wpar[o] = WF_NONE;
+                    q[j] = 1;
+                }
+            }
+        }
+        n_dirty += q[j];
+    }
+    int32_t *nk = (int32_t *)malloc(sizeof(int32_t) * 512 * (n ? n : 1));
+    int32_t *np = (int32_t *)malloc(sizeof(int32_t) * 512 * (n ? n : 1));
+    uint8_t *changed = (uint8_t *)malloc((size_t)(n ? n : 1));
+    int64_t *list = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
+    int64_t rounds = 0, work = 0;
+    for (;;) {
+        int64_t m = 0;
+        for (int64_t j = 0; j < n; ++j)
+            if (q[j]) list[m++] = j;
+        if (m == 0) break;
+        for (int64_t t = 0; t < m; ++t) {
+            const int64_t j = list[t];
+            int32_t *K = nk + 512 * j, *P = np + 512 * j;
+            memcpy(K, s->wk + 512 * j, sizeof(int32_t) * 512);
+            memcpy(P, s->wpar + 512 * j, sizeof(int32_t) * 512);
+            for (int dir = 0; dir < 6; ++dir) {
+                const int64_t nb = wf_neighbour(s, j, dir);
+                if (nb < 0) continue;
+                const int a = dir >> 1, side = (dir & 1) ? 7 : 0;
+                int e[3] = {0, 0, 0};
+                e[a] = (dir & 1) ? 1 : -1;
+                for (int u1 = 0; u1 < 8; ++u1)
+                    for (int u2 = 0; u2 < 8; ++u2) {
+                        int c[3], cn[3];
+                        c[a] = side;
+                        c[a == 0 ? 1 : 0] = u1;
+                        c[a == 2 ? 1 : 2] = u2;
+                        memcpy(cn, c, sizeof(c));
+                        cn[a] = 7 - side;
+                        const int lv = c[0] + 8 * c[1] + 64 * c[2], lu = cn[0] + 8 * cn[1] + 64 * cn[2];
+                        wf_offer(&K[lv], &P[lv], s->wk[512 * nb + lu], s->wpar[512 * nb + lu], e, R2);
+                    }
+            }
+            for (int a = 0; a < 3; ++a)
+                for (int u1 = 0; u1 < 8; ++u1)
+                    for (int u2 = 0; u2 < 8; ++u2) {
+                        int c[3];
+                        c[a == 0 ? 1 : 0] = u1;
+                        c[a == 2 ? 1 : 2] = u2;
+                        int e[3] = {0, 0, 0};
+                        e[a] = -1;
+                        for (int x = 1; x < 8; ++x) {  /* forward: from x - 1 */
+                            c[a] = x;
+                            const int lv = c[0] + 8 * c[1] + 64 * c[2];
+                            c[a] = x - 1;
+                            const int lu = c[0] + 8 * c[1] + 64 * c[2];
+                            wf_offer(&K[lv], &P[lv], K[lu], P[lu], e, R2);
+                        }
+                        e[a] = 1;
+                        for (int x = 6; x >= 0; --x) {  /* backward: from x + 1 */
+                            c[a] = x;
+                            const int lv = c[0] + 8 * c[1] + 64 * c[2];
+                            c[a] = x + 1;
+                            const int lu = c[0] + 8 * c[1] + 64 * c[2];
+                            wf_offer(&K[lv], &P[lv], K[lu], P[lu], e, R2);
+                        }
+                    }
+            changed[j] = memcmp(K, s->wk + 512 * j, sizeof(int32_t) * 512) != 0 ||
+                         memcmp(P, s->wpar + 512 * j, sizeof(int32_t) * 512) != 0;
+        }
+        memset(q, 0, (size_t)n);
+        for (int64_t t = 0; t < m; ++t) {
+            const int64_t j = list[t];
+            memcpy(s->wk + 512 * j, nk + 512 * j, sizeof(int32_t) * 512);
+            memcpy(s->wpar + 512 * j, np + 512 * j, sizeof(int32_t) * 512);
+        }
+        for (int64_t t = 0; t < m; ++t) {
+            const int64_t j = list[t];
+            if (!changed[j]) continue;
+            q[j] = 1;
+            for (int dir = 0; dir < 6; ++dir) {
+                const int64_t nb = wf_neighbour(s, j, dir);
+                if (nb >= 0) q[nb] = 1;
+            }
+        }
+        ++rounds;
+        work += m;
+    }
+    /* phi as for the exact EDT */
+    const double tau = band_limit(&s->p);
+    const float vs_f = (float)s->p.vs, tau_f = (float)tau, dmax_f = (float)s->p.d_max;
+    for (int64_t j = 0; j < n; ++j)
+        for (int l = 0; l < 512; ++l) {
+            const size_t o = (size_t)512 * j + l;
+            const int64_t k = s->wk[o] == WF_INF ? R2 + 1 : s->wk[o];
+            s->ksq[o] = -1;
+            if (s->p.fp64) {
+                double Wv = s->W64[o], Dv = s->D64[o];
+                if (!(Wv > 0)) { s->phi64[o] = NAN; continue; }
+                if (fabs(Dv) < tau) { s->phi64[o] = Dv; continue; }
+                double sg = Dv > 0 ? 1.0 : -1.0;
+                s->ksq[o] = (int32_t)k;
+                if (k > R2) { s->phi64[o] = sg * s->p.d_max; continue; }
+                double r = s->p.vs * sqrt((double)k);
+                s->phi64[o] = sg * (r < s->p.d_max ? r : s->p.d_max);
+            } else {
+                float Wv = s->W[o], Dv = s->D[o];
+                if (!(Wv > 0.0f)) { s->phi[o] = NAN; continue; }
+                if (fabsf(Dv) < tau_f) { s->phi[o] = Dv; continue; }
+                float sg = Dv > 0.0f ? 1.0f : -1.0f;
+                s->ksq[o] = (int32_t)k;
+                if (k > R2) { s->phi[o] = sg * dmax_f; continue; }
+                float r = vs_f * sqrtf((float)k);
+                s->phi[o] = sg * fminf(dmax_f, r);
+            }
+        }
+    memcpy(s->wsite, site, (size_t)512 * n);
+    s->wn = n;
+    if (stats) { stats[0] = rounds; stats[1] = work; stats[2] = n_dirty; }
+    free(site); free(q); free(nk); free(np); free(changed); free(list);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------ export */
 
 void orc_export(const orc_submap *s, uint64_t *keys, double *D, double *W, double *phi, int32_t *ksq)
@@ -900,6 +1124,7 @@ int orc_import(orc_submap *s, int64_t n, const uint64_t *keys, const double *D, 
         }
     }
     s->n = n;
+    s->wn = 0;  /* the wavefront state starts over */
     rebuild_sorted(s);
     return ORC_OK;
 }
