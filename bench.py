@@ -288,6 +288,7 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
                "voxel_updates": int(n_upd), "voxel_updates_per_s": n_upd / best_map, "kernel_ms": map_kernels,
                "algorithmic_bytes": b_map, "achieved_GBs": b_map / best_map / 1e9,
                "frac_hbm": b_map / best_map / 1e9 / HBM_PEAK_GBS}
+    large = large_submap_esdf_bench(cv, torch, np, w, frames[:600], reps)
     del frames
     t_build = time.perf_counter() - t0
     nblk = [ctx.submap_info(s)["n_blocks"] for s in subs]
@@ -383,8 +384,8 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
     learned = learned_bench(cv, torch, np, ctx, subs, Tws, w.voxel_size)
     ctx.close()
     return {"workload": "outdoor 120x80 m, 3000 frames 640x480 fx=fy=380, 0.1 m voxels, 30 submaps of 100 frames",
-            "build_s": t_build, "render_s": t_render, "mapping": mapping, "esdf_batch": esdf, "align": align,
-            "pose_graph": pose_graph, "learned": learned}
+            "build_s": t_build, "render_s": t_render, "mapping": mapping, "esdf_batch": esdf,
+            "esdf_large_submap": large, "align": align, "pose_graph": pose_graph, "learned": learned}
 
 
 def _success(T, gts, np, bound_t, bound_deg):
@@ -394,6 +395,49 @@ def _success(T, gts, np, bound_t, bound_deg):
         c = (np.trace(Tg[:3, :3] @ Tt[:3, :3].T) - 1) / 2
         ok += et <= bound_t and math.degrees(math.acos(max(-1.0, min(1.0, c)))) <= bound_deg
     return ok / max(1, len(gts))
+
+
+def large_submap_esdf_bench(cv, torch, np, w, frames, reps=2, every=20):
+    """One large outdoor submap (the first 600 frames, about 80 m of path)
+    with an ESDF update after every 20 frames: the exact EDT recomputes the
+    whole box each time, the wavefront (Sec. III-E) only what changed.
+    Reports the ESDF time per update (mapping with updates minus mapping
+    without) and the wavefront's error against the exact field at the end."""
+    import scenegen as sg
+    F = len(frames)
+    T_ws = sg.gravity_aligned(w.poses[0])
+    out, fields = {"frames": F, "update_every": every}, {}
+    for name, mode in (("exact", cv.ESDF_EXACT), ("wavefront", cv.ESDF_WAVEFRONT)):
+        ctx = cv.Context(voxel_size=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max,
+                         block_capacity=131072, esdf_mode=mode)
+        s = ctx.submap_create(T_ws)
+        times = {}
+        for label, e in (("map_only", 0), ("map_esdf", every)):
+            best = None
+            for k in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.submap_reset(s)
+                ctx.map_sequence(s, frames, w.cam.K, w.poses[:F], esdf_every=e)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if k > 0:
+                    best = dt if best is None else min(best, dt)
+            times[label] = best
+        n_upd = F // every
+        info = ctx.submap_info(s)
+        out[name] = {"ms_per_update": (times["map_esdf"] - times["map_only"]) * 1e3 / n_upd,
+                     "map_esdf_ms": times["map_esdf"] * 1e3, "map_only_ms": times["map_only"] * 1e3,
+                     "blocks": info["n_blocks"]}
+        fields[name] = ctx.export_blocks(s)
+        ctx.close()
+    a, b = fields["exact"], fields["wavefront"]
+    m = ~np.isnan(a["phi"])
+    d = np.abs(a["phi"][m].astype(np.float64) - b["phi"][m])
+    out["wavefront_vs_exact"] = {"observed_voxels": int(m.sum()), "equal_fraction": float((d == 0).mean()),
+                                 "max_abs_m": float(d.max(initial=0)), "rms_m": float(np.sqrt((d ** 2).mean()))}
+    out["speedup_wavefront"] = out["exact"]["ms_per_update"] / max(out["wavefront"]["ms_per_update"], 1e-9)
+    return out
 
 
 def pgo_bench(cv, torch, np, ctx, subs, Tws, cand, reps=2):
@@ -565,6 +609,47 @@ def integrator_bench(cv, torch, np, w, dev, tuning, reps=2):
     return out
 
 
+def esdf_modes_bench(cv, torch, np, w, dev, tuning, reps=2):
+    """The exact EDT against the incremental wavefront (Sec. III-E) on the
+    room sequence with an ESDF update after every frame: TSDF+ESDF frames/s,
+    ESDF kernel time per update, and the wavefront's error against the exact
+    field on the observed voxels of the final map."""
+    out, fields = {}, {}
+    for name, mode in (("exact", cv.ESDF_EXACT), ("wavefront", cv.ESDF_WAVEFRONT)):
+        ctx = cv.Context(voxel_size=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max,
+                         block_capacity=32768, esdf_mode=mode)
+        ctx.set_tuning(**tuning)
+        s = ctx.submap_create()
+        best = None
+        for k in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.submap_reset(s)
+            ctx.map_sequence(s, dev, w.cam.K, w.poses, esdf_every=1)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if k > 0:
+                best = dt if best is None else min(best, dt)
+        kinds = ["esdf_page", "esdf_sites", "edt_x", "edt_y", "edt_z", "wavefront"]
+        ctx.timing_enable(kinds)
+        ctx.submap_reset(s)
+        ctx.map_sequence(s, dev, w.cam.K, w.poses, esdf_every=1)
+        tk = ctx.timing_get()
+        ctx.timing_enable([])
+        out[name] = {"tsdf_esdf_frames_per_s": w.n_frames / best,
+                     "esdf_kernel_us_per_update": sum(v[0] for k, v in tk.items() if k in kinds) * 1e3 / w.n_frames,
+                     "launches_per_update": sum(v[1] for k, v in tk.items() if k in kinds) / w.n_frames}
+        fields[name] = ctx.export_blocks(s)
+        ctx.close()
+    a, b = fields["exact"], fields["wavefront"]
+    m = ~np.isnan(a["phi"])
+    d = np.abs(a["phi"][m].astype(np.float64) - b["phi"][m])
+    out["wavefront_vs_exact"] = {"observed_voxels": int(m.sum()), "equal_fraction": float((d == 0).mean()),
+                                 "max_abs_m": float(d.max(initial=0)), "rms_m": float(np.sqrt((d ** 2).mean())),
+                                 "same_keys": bool(np.array_equal(a["keys"], b["keys"]))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -578,6 +663,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage room timing")
     ap.add_argument("--no-raycast", action="store_true", help="skip the projective / raycast comparison")
+    ap.add_argument("--no-wavefront", action="store_true", help="skip the exact / wavefront ESDF comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -717,6 +803,9 @@ def main():
     if prec == cv.FP32 and not args.no_raycast:
         _log("projection mapping against raycasting (room)")
         result["integrators"] = integrator_bench(cv, torch, np, w, dev, room_tuning)
+    if prec == cv.FP32 and not args.no_wavefront:
+        _log("exact against wavefront ESDF (room)")
+        result["esdf_modes"] = esdf_modes_bench(cv, torch, np, w, dev, room_tuning)
     if not args.no_align:
         _log("alignment pairs")
         result["align"] = align_bench(cv, torch, np, w, dev)

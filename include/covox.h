@@ -82,10 +82,13 @@ typedef struct {
                                 raycasting: see covox_integrate_depth); raycasting needs FP32 storage */
     int32_t ray_carve;       /* raycasting: 1 = rays start at the optical centre (free space is
                                 carved, as the paper describes), 0 = at tau before the point */
+    int32_t esdf_mode;       /* COVOX_ESDF_EXACT (exact EDT recomputed) or COVOX_ESDF_WAVEFRONT
+                                (Sec. III-E incremental propagation: see covox_update_esdf) */
 } covox_params;
 
 enum { COVOX_WEIGHT_CONSTANT = 0, COVOX_WEIGHT_INV_DEPTH2 = 1 };
 enum { COVOX_PROJECTIVE = 0, COVOX_RAYCAST = 1 };
+enum { COVOX_ESDF_EXACT = 0, COVOX_ESDF_WAVEFRONT = 1 };
 
 /* Fills p with the defaults: 0.05 m voxels, tau = 4 voxels, 5 m range, 2 m
  * ESDF, w_reg = 2, 65536 blocks, FP32, 30 iterations, n_min = 100,
@@ -99,8 +102,8 @@ int covox_create(covox_ctx **out, const covox_params *p);
 void covox_destroy(covox_ctx *ctx);
 
 /* Replaces the parameters that do not shape storage: w_reg, max_iter,
- * n_min, tol_rho, tol_theta, align_dof, weight_mode, integrator and
- * ray_carve (the next integrations use them; switching to raycasting
+ * n_min, tol_rho, tol_theta, align_dof, weight_mode, integrator, ray_carve
+ * and esdf_mode (the next calls use them; switching to raycasting
  * allocates its accumulators, 16 bytes per voxel of block_capacity).  COVOX_EINVAL if p is invalid or
  * changes voxel_size, trunc_vox, max_range, d_max, block_capacity or
  * precision.  Registration points are re-extracted after a w_reg change. */
@@ -184,6 +187,16 @@ int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev,
  *   else sign(D) * d_max (sign = +1 for D > 0, else -1);
  *   unobserved voxels: phi = NaN.
  * Asynchronous.
+ * With esdf_mode = COVOX_ESDF_WAVEFRONT, k comes instead from an
+ * incremental propagation (Sec. III-E) over the allocated blocks: every
+ * voxel keeps a parent site (offset) and its squared distance (<= R^2, else
+ * none); sites take themselves, voxels whose parent is no longer a site
+ * lose it, and the changed blocks are queued; in synchronous rounds each
+ * queued block takes better parents from its neighbours' face voxels (faces
+ * -x, +x, -y, +y, -z, +z), sweeps x, y, z forward and backward, and, if it
+ * changed, queues itself and its neighbours.  Distances never fall below
+ * the exact k; they match it on nearly every voxel.  Synchronous (the round
+ * count is read back), not capturable in a graph.
  */
 int covox_update_esdf(covox_ctx *ctx, covox_submap *s);
 
@@ -519,6 +532,7 @@ enum {
     COVOX_K_RAY_ACCUM,     /* raycasting: walk again and accumulate (w, t w) per voxel */
     COVOX_K_RAY_APPLY,     /* raycasting: activate new blocks, merge the sums into D and W */
     COVOX_K_PGO,           /* pose graph: term blocks, block-sparse assembly, PCG */
+    COVOX_K_WAVEFRONT,     /* incremental ESDF: seeds, rounds (queue, block sweeps, commit), phi */
     COVOX_K_COUNT
 };
 

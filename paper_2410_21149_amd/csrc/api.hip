@@ -191,6 +191,10 @@ bool valid_params(const covox_params *p, std::string &why)
         why = "raycasting needs FP32 storage (weights exceed the binary16 range)";
         return false;
     }
+    if (p->esdf_mode != COVOX_ESDF_EXACT && p->esdf_mode != COVOX_ESDF_WAVEFRONT) {
+        why = "esdf_mode must be COVOX_ESDF_EXACT or COVOX_ESDF_WAVEFRONT";
+        return false;
+    }
     return true;
 }
 
@@ -368,6 +372,7 @@ void covox_default_params(covox_params *p)
     p->weight_mode = COVOX_WEIGHT_CONSTANT;
     p->integrator = COVOX_PROJECTIVE;
     p->ray_carve = 1;
+    p->esdf_mode = COVOX_ESDF_EXACT;
 }
 
 const char *covox_status_string(int s)
@@ -421,10 +426,12 @@ void covox_destroy(covox_ctx *ctx)
                       (void *)ctx->g2, (void *)ctx->cnt, (void *)ctx->psum, ctx->prob_dev, ctx->res_dev, ctx->sum_dev,
                       (void *)ctx->net_in, (void *)ctx->net_out, (void *)ctx->train_y, (void *)ctx->loss_hist,
                       (void *)ctx->frames_dev, (void *)ctx->blist, (void *)ctx->fkeys, (void *)ctx->ffirst,
-                      (void *)ctx->fcount, (void *)ctx->ray_acc})
+                      (void *)ctx->fcount, (void *)ctx->ray_acc, (void *)ctx->wf_nk, (void *)ctx->wf_np,
+                      (void *)ctx->wf_sites, (void *)ctx->wf_flag, (void *)ctx->wf_list, (void *)ctx->wf_cnt})
         if (ptr) (void)hipFree(ptr);
     for (void *p : ctx->deferred) (void)hipFree(p);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->wf_pin) (void)hipHostFree(ctx->wf_pin);
     for (int k = 0; k < 2; ++k) {
         if (ctx->frames_pin[k]) (void)hipHostFree(ctx->frames_pin[k]);
         if (ctx->frames_ev[k]) (void)hipEventDestroy(ctx->frames_ev[k]);
@@ -528,7 +535,7 @@ void covox_submap_destroy(covox_submap *s)
         subs.erase(std::remove(subs.begin(), subs.end(), s), subs.end());
     }
     for (void *p : {(void *)s->keys, s->D, s->W, (void *)s->phi, (void *)s->tkeys, (void *)s->tvals, (void *)s->meta,
-                    (void *)s->page, (void *)s->pts})
+                    (void *)s->page, (void *)s->pts, (void *)s->wf_k, (void *)s->wf_p, (void *)s->wf_wn})
         if (p) (void)hipFree(p);
     if (s->stamp) (void)hipFree(s->stamp);
     if (s->pin_nb) (void)hipHostFree((void *)s->pin_nb);
@@ -547,7 +554,7 @@ int covox_submap_reset(covox_ctx *ctx, covox_submap *s)
     s->bound_valid = false;
     s->version++;
     s->n_pts = 0;
-    return COVOX_OK;
+    return wavefront_reset(ctx, s);
 }
 
 int covox_integrate_depth(covox_ctx *ctx, covox_submap *s, const float *depth_dev, int32_t H, int32_t W,

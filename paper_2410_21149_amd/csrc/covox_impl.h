@@ -158,6 +158,11 @@ struct covox_submap {
     uint64_t pts_version = 0;
     int64_t n_pts = 0;
     double pbar[3] = {0, 0, 0};
+    // wavefront ESDF state (esdf_mode COVOX_ESDF_WAVEFRONT): squared distance
+    // and packed parent offset per voxel, blocks at the last update (device)
+    int32_t *wf_k = nullptr;
+    int32_t *wf_p = nullptr;
+    int64_t *wf_wn = nullptr;
 };
 
 namespace covox {
@@ -204,6 +209,19 @@ struct covox_ctx {
     int64_t t_idx_cap = 0;
     double *ray_acc = nullptr;  // raycasting: (sum w, sum t w) per voxel, zero between frames
     int64_t ray_acc_blocks = 0;
+    // wavefront ESDF scratch: next-round state, site masks, queue flags and list
+    int32_t *wf_nk = nullptr, *wf_np = nullptr;
+    int64_t wf_nk_cap = 0, wf_np_cap = 0;
+    uint64_t *wf_sites = nullptr;
+    int64_t wf_sites_cap = 0;
+    uint32_t *wf_flag = nullptr;
+    int64_t wf_flag_cap = 0;
+    int32_t *wf_list = nullptr;
+    int64_t wf_list_cap = 0;
+    int64_t *wf_cnt = nullptr;  // [queue size of the last list, block-rounds]
+    int64_t wf_cnt_cap = 0;
+    int64_t *wf_pin = nullptr;  // pinned copy of wf_cnt
+    int64_t wf_last_block_rounds = 0;
     // EDT scratch over a dense block box
     uint64_t *sites = nullptr;  // 8 words per dense block
     int64_t sites_cap = 0;      // dense blocks
@@ -334,6 +352,10 @@ void covox_default_pgo_cfg_impl(covox_pgo_cfg *c);
 int pgo_solve(covox_ctx *ctx, covox_submap *const *subs, int32_t n, double *x, const int32_t *reg_pairs,
               int32_t n_reg, const covox_pose_factor *factors, int32_t n_fac, const covox_pgo_cfg *cfg,
               covox_pgo_stats *stats);
+
+// k_wavefront.hip: incremental ESDF (esdf_mode COVOX_ESDF_WAVEFRONT)
+int update_esdf_wavefront(covox_ctx *ctx, covox_submap *s);
+int wavefront_reset(covox_ctx *ctx, covox_submap *s);
 
 // k_raycast.hip
 int raycast_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H, int32_t W, const float K[4],

@@ -714,6 +714,13 @@ int update_esdf_batch(covox_ctx *ctx, covox_submap *const *subs, int n)
     for (int i = 0; i < n; ++i)
         if (std::find(todo.begin(), todo.end(), subs[i]) == todo.end()) todo.push_back(subs[i]);
     if (todo.empty()) return COVOX_OK;
+    if (ctx->p.esdf_mode == COVOX_ESDF_WAVEFRONT) {
+        for (covox_submap *s : todo) {
+            const int rc = update_esdf_wavefront(ctx, s);
+            if (rc) return rc;
+        }
+        return COVOX_OK;
+    }
     if (todo.size() == 1) return esdf_chunk<1>(ctx, todo.data(), 1, true);
     for (size_t i = 0; i < todo.size(); i += kMaxJobs) {
         const int m = (int)std::min<size_t>(kMaxJobs, todo.size() - i);
