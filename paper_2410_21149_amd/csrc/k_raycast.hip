@@ -18,7 +18,9 @@
 //                   voxel: lanes of a wave that reach the same voxel in the
 //                   same step are summed in registers, the workgroup's
 //                   16 x 16 pixel tile sums its voxels in an LDS table, and
-//                   the table is flushed with global FP64 atomics;
+//                   the table is flushed with global FP64 atomics; with
+//                   constant weights, contributions clamped to tau travel as
+//                   integer counts;
 //   k_ray_apply     one wave per touched block: W' = W + sw, D' = (D W + stw)
 //                   / W' where sw > 0, and the accumulators are cleared.
 // The paper orders the merge by sorting the contributions by voxel address;
@@ -233,6 +235,10 @@ __device__ __forceinline__ void add_global(double *acc, int64_t addr, double vw,
     unsafeAtomicAdd(acc + 2 * addr + 1, vtw);
 }
 
+// With constant weights, a contribution clamped to tau (free space: most of
+// them) is (w, t w) = (1, tau), so it is counted instead: an integer per LDS
+// slot, ballot popcounts for a wave's group.  The count c enters the binary64
+// sums as c and c tau, both exact.
 __global__ __launch_bounds__(256) void k_ray_accum(FrameArgs f, float vs, float tau, float maxr,
                                                    const SubmapMeta *__restrict__ meta,
                                                    const uint64_t *__restrict__ tkeys,
@@ -241,13 +247,17 @@ __global__ __launch_bounds__(256) void k_ray_accum(FrameArgs f, float vs, float 
 {
     __shared__ unsigned long long s_key[kAccSlots];
     __shared__ double s_w[kAccSlots], s_tw[kAccSlots];
+    __shared__ uint32_t s_cnt[kAccSlots];
     if (meta->n_touched == 0) return;  // uniform: nothing committed (capacity failure, or no contribution)
     for (int k = threadIdx.x; k < kAccSlots; k += blockDim.x) {
         s_key[k] = kAccEmpty;
         s_w[k] = 0.0;
         s_tw[k] = 0.0;
+        s_cnt[k] = 0u;
     }
     __syncthreads();
+    const bool counted = f.weight_mode == COVOX_WEIGHT_CONSTANT;  // uniform
+    const double tau_d = (double)tau;
     const int lane = threadIdx.x & 63;
     int col, row;
     lane_pixel(col, row);
@@ -261,6 +271,7 @@ __global__ __launch_bounds__(256) void k_ray_accum(FrameArgs f, float vs, float 
         bool has = false;
         int64_t addr = -1;
         double vw = 0.0, vtw = 0.0;
+        uint32_t cnt = 0;  // clamped contributions carried as a count
         if (active) {
             float t;
             if (ray_contrib(R, vs, tau, t)) {
@@ -272,8 +283,12 @@ __global__ __launch_bounds__(256) void k_ray_accum(FrameArgs f, float vs, float 
                 if (base >= 0) {
                     has = true;
                     addr = base * 512 + (R.i[0] & 7) + 8 * (R.i[1] & 7) + 64 * (R.i[2] & 7);
-                    vw = (double)R.w;
-                    vtw = (double)t * (double)R.w;  // exact in binary64
+                    if (counted && t == tau) {
+                        cnt = 1u;
+                    } else {
+                        vw = (double)R.w;
+                        vtw = (double)t * (double)R.w;  // exact in binary64
+                    }
                 }
             }
             active = ray_next(R, vs);
@@ -285,17 +300,24 @@ __global__ __launch_bounds__(256) void k_ray_accum(FrameArgs f, float vs, float 
             const int leader = __ffsll((unsigned long long)m) - 1;
             const int64_t la = __shfl(addr, leader, 64);
             const bool in = has && addr == la;
-            if (__popcll(__ballot(in)) > 1) {
-                double a = in ? vw : 0.0, b = in ? vtw : 0.0;
+            const uint64_t g = __ballot(in);
+            if (__popcll(g) > 1) {
+                const uint32_t gc = (uint32_t)__popcll(__ballot(in && cnt != 0u));
+                double a = 0.0, b = 0.0;
+                if (__ballot(in && cnt == 0u)) {  // some member carries a value
+                    a = in ? vw : 0.0;
+                    b = in ? vtw : 0.0;
 #pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    a += __shfl_xor(a, off, 64);
-                    b += __shfl_xor(b, off, 64);
+                    for (int off = 32; off > 0; off >>= 1) {
+                        a += __shfl_xor(a, off, 64);
+                        b += __shfl_xor(b, off, 64);
+                    }
                 }
                 if (in) {
                     has = lane == leader;
                     vw = a;
                     vtw = b;
+                    cnt = gc;
                 }
             }
         }
@@ -310,17 +332,23 @@ __global__ __launch_bounds__(256) void k_ray_accum(FrameArgs f, float vs, float 
                     if (k == kAccEmpty) k = key;
                 }
                 if (k == key) {
-                    __hip_atomic_fetch_add(&s_w[h], vw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    __hip_atomic_fetch_add(&s_tw[h], vtw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (cnt) atomicAdd(&s_cnt[h], cnt);
+                    if (vw != 0.0) {
+                        __hip_atomic_fetch_add(&s_w[h], vw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_fetch_add(&s_tw[h], vtw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
                     done = true;
                 }
             }
-            if (!done) add_global(acc, addr, vw, vtw);
+            if (!done) add_global(acc, addr, (double)cnt + vw, (double)cnt * tau_d + vtw);
         }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kAccSlots; k += blockDim.x)
-        if (s_key[k] != kAccEmpty) add_global(acc, (int64_t)s_key[k], s_w[k], s_tw[k]);
+        if (s_key[k] != kAccEmpty) {
+            const double c = (double)s_cnt[k];
+            add_global(acc, (int64_t)s_key[k], c + s_w[k], c * tau_d + s_tw[k]);
+        }
 }
 
 __global__ __launch_bounds__(256) void k_ray_apply(SubmapMeta *__restrict__ meta, const uint32_t *__restrict__ t_idx,
