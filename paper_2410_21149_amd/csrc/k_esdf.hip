@@ -270,6 +270,8 @@ __device__ __forceinline__ int nearest_bit(uint64_t lo, uint64_t hi, int p)
 // small domains where per-line envelopes leave the GPU idle.
 
 __device__ __forceinline__ int sq8(uint8_t v) { return v == 255 ? kBig : (int)v * (int)v; }
+
+constexpr int kScanStep = 8;  // offsets per exit test of the windowed y and z passes
 __device__ __forceinline__ int inf16(uint16_t v) { return v == 0xFFFF ? kBig : (int)v; }
 
 // x pass: one wave per dense block, lane = (y, z) line of the block.  The
@@ -336,10 +338,16 @@ __global__ __launch_bounds__(512) void k_edt_y_vox(const JobList<NJ> jl, const u
         __syncthreads();
         auto at = [&](int yy) { return col[(yy >> 3) * 512 + x + 8 * (yy & 7) + 64 * z]; };
         int best = sq8(at(Y));
-        for (int dd = 1; dd <= R; ++dd) {
-            const int d2 = dd * dd;
-            if (d2 >= best) break;
-            best = min(best, min(sq8(at(Y - dd)), sq8(at(Y + dd))) + d2);
+        // outward scan, kScanStep offsets per exit test: the test needs the
+        // previous minimum, so testing less often keeps more LDS reads in
+        // flight; offsets past the exit cannot lower the minimum
+        for (int dd = 1; dd <= R; dd += kScanStep) {
+            if (dd * dd >= best) break;
+#pragma unroll
+            for (int q = 0; q < kScanStep; ++q) {
+                const int e = dd + q;
+                if (e <= R) best = min(best, min(sq8(at(Y - e)), sq8(at(Y + e))) + e * e);
+            }
         }
         g2[g * 512 + tid] = best <= R2 ? (uint16_t)best : (uint16_t)0xFFFF;
         __syncthreads();
@@ -395,10 +403,13 @@ __global__ __launch_bounds__(512) void k_edt_z_vox(const JobList<NJ> jl, const u
             const int base = tid & 63;
             auto at = [&](int zz) { return col[(zz >> 3) * 512 + base + 64 * (zz & 7)]; };
             int best = inf16(at(Z));
-            for (int dd = 1; dd <= R; ++dd) {
-                const int d2 = dd * dd;
-                if (d2 >= best) break;
-                best = min(best, min(inf16(at(Z - dd)), inf16(at(Z + dd))) + d2);
+            for (int dd = 1; dd <= R; dd += kScanStep) {  // as in the y pass
+                if (dd * dd >= best) break;
+#pragma unroll
+                for (int q = 0; q < kScanStep; ++q) {
+                    const int e = dd + q;
+                    if (e <= R) best = min(best, min(inf16(at(Z - e)), inf16(at(Z + e))) + e * e);
+                }
             }
             out = phi_value(Dv, best, R2, vs, dmax);
         }
