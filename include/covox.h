@@ -453,7 +453,10 @@ int covox_pgo_solve(covox_ctx *ctx, covox_submap *const *subs, int32_t n, double
  * may use the context stream.  Nothing runs during capture, and the host
  * bookkeeping of every submap is as before covox_graph_begin afterwards.
  * A submap integrated inside the graph must be reset inside it first
- * (covox_graph_end fails otherwise).
+ * (covox_graph_end fails otherwise).  Both integrators can be captured
+ * (raycasting needs its accumulators, which covox_create / covox_set_params
+ * allocate); the wavefront ESDF cannot (it reads its round count back), and
+ * its update returns COVOX_EINVAL under capture.
  *
  * covox_graph_launch enqueues the captured kernels on the context stream
  * with their captured arguments: the same submaps, poses, intrinsics and

@@ -127,3 +127,34 @@ def test_capture_rules(cv):
         g.launch()
     g.close()
     ctx.close()
+
+
+def test_graph_replays_raycast_mapping(cv):
+    """Raycast integration captured with ESDF updates: every replay equals
+    the eager run (keys and weights bit for bit; D within 1e-6 m, as the
+    per-voxel sums come from atomics in any order)."""
+    import torch
+    w = sg.tiny(n_frames=10)
+    dev = torch.from_numpy(w.frames()).cuda()
+    ref_ctx = _ctx(cv, integrator=cv.RAYCAST)
+    r = ref_ctx.submap_create()
+    ref_ctx.map_sequence(r, dev, w.cam.K, w.poses, esdf_every=3)
+    want = ref_ctx.export_blocks(r)
+    ref_ctx.close()
+
+    ctx = _ctx(cv, integrator=cv.RAYCAST)
+    s = ctx.submap_create()
+    ctx.graph_begin()
+    ctx.submap_reset(s)
+    ctx.map_sequence(s, dev, w.cam.K, w.poses, esdf_every=3)
+    g = ctx.graph_end()
+    for rep in range(3):
+        g.launch()
+        ctx.sync()
+        got = ctx.export_blocks(s)
+        assert np.array_equal(got["keys"], want["keys"]) and np.array_equal(got["W"], want["W"])
+        assert np.abs(got["D"].astype(np.float64) - want["D"]).max() <= 1e-6
+        ctx.integrate_depth(s, dev[0], w.cam.K, w.poses[0])  # eager work between replays
+        ctx.sync()
+    g.close()
+    ctx.close()
