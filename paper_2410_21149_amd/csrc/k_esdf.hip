@@ -311,8 +311,10 @@ __global__ __launch_bounds__(256) void k_edt_x(const JobList<NJ> jl, const uint6
     }
 }
 
+// y pass: 256 lanes per block, each lane two voxels (z and z + 4), so that
+// the whole pass of a room-sized domain is resident at once.
 template <int NJ>
-__global__ __launch_bounds__(512) void k_edt_y_vox(const JobList<NJ> jl, const uint8_t *__restrict__ g1,
+__global__ __launch_bounds__(256) void k_edt_y_vox(const JobList<NJ> jl, const uint8_t *__restrict__ g1,
                                                    uint16_t *__restrict__ g2, int R, int HB)
 {
     __shared__ Plan lds;
@@ -321,7 +323,7 @@ __global__ __launch_bounds__(512) void k_edt_y_vox(const JobList<NJ> jl, const u
     pv.init(jl, 8 * HB, lds);
     const uint8_t *col = (const uint8_t *)colw;
     const int tid = threadIdx.x;
-    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;
+    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;  // z in 0..3; the lane also takes z + 4
     const int nb = 2 * HB + 1;
     const int R2 = R * R;
     const int Y = 8 * HB + y;
@@ -329,27 +331,31 @@ __global__ __launch_bounds__(512) void k_edt_y_vox(const JobList<NJ> jl, const u
         const JobInfo d = pv.info(pv.template job<&JobInfo::od>(g));
         int bx, by, bz;
         dom_coords(d, g - d.od, bx, by, bz);
-        for (int e = tid; e < nb * 128; e += 512) {
+        for (int e = tid; e < nb * 128; e += blockDim.x) {
             const int i = e >> 7, w = e & 127;
             const int ny = by + i - HB;
             colw[e] = (ny >= 0 && ny < d.dim[1]) ? ((const uint32_t *)(g1 + (g + (int64_t)(i - HB) * d.dim[0]) * 512))[w]
                                                  : 0xFFFFFFFFu;
         }
         __syncthreads();
-        auto at = [&](int yy) { return col[(yy >> 3) * 512 + x + 8 * (yy & 7) + 64 * z]; };
-        int best = sq8(at(Y));
+        auto at = [&](int yy, int zz) { return col[(yy >> 3) * 512 + x + 8 * (yy & 7) + 64 * zz]; };
+        int b0 = sq8(at(Y, z)), b1 = sq8(at(Y, z + 4));
         // outward scan, kScanStep offsets per exit test: the test needs the
-        // previous minimum, so testing less often keeps more LDS reads in
-        // flight; offsets past the exit cannot lower the minimum
+        // previous minima, so testing less often keeps more LDS reads in
+        // flight; offsets past a voxel's exit cannot lower its minimum
         for (int dd = 1; dd <= R; dd += kScanStep) {
-            if (dd * dd >= best) break;
+            if (dd * dd >= max(b0, b1)) break;
 #pragma unroll
             for (int q = 0; q < kScanStep; ++q) {
                 const int e = dd + q;
-                if (e <= R) best = min(best, min(sq8(at(Y - e)), sq8(at(Y + e))) + e * e);
+                if (e <= R) {
+                    b0 = min(b0, min(sq8(at(Y - e, z)), sq8(at(Y + e, z))) + e * e);
+                    b1 = min(b1, min(sq8(at(Y - e, z + 4)), sq8(at(Y + e, z + 4))) + e * e);
+                }
             }
         }
-        g2[g * 512 + tid] = best <= R2 ? (uint16_t)best : (uint16_t)0xFFFF;
+        g2[g * 512 + tid] = b0 <= R2 ? (uint16_t)b0 : (uint16_t)0xFFFF;
+        g2[g * 512 + tid + 256] = b1 <= R2 ? (uint16_t)b1 : (uint16_t)0xFFFF;
         __syncthreads();
     }
 }
@@ -688,7 +694,7 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
             hipLaunchKernelGGL((k_edt_y_env<NJ>), dim3(clamp_grid_w(cy)), dim3(64), 0, ctx->stream, jl, ctx->g1, ctx->g2,
                                R, HB);
         else
-            hipLaunchKernelGGL((k_edt_y_vox<NJ>), dim3(clamp_grid(nd)), dim3(512), 0, ctx->stream, jl, ctx->g1,
+            hipLaunchKernelGGL((k_edt_y_vox<NJ>), dim3(clamp_grid(nd)), dim3(256), 0, ctx->stream, jl, ctx->g1,
                                ctx->g2, R, HB);
     }
     {
