@@ -93,6 +93,9 @@ def _load():
         L.orc_se3_exp.argtypes = [_dp, _dp]
         L.orc_solve6.restype = ctypes.c_int
         L.orc_solve6.argtypes = [_dp, _dp]
+        L.orc_hash_insert.restype = None
+        L.orc_hash_insert.argtypes = [_u64p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int64, _u64p, ctypes.c_int64,
+                                      ctypes.c_uint32, _i64p, _i64p]
         L.orc_mix64.restype = ctypes.c_uint64
         L.orc_mix64.argtypes = [ctypes.c_uint64]
         L.orc_f2h.restype = ctypes.c_uint16
@@ -330,6 +333,32 @@ def voxel_coords(keys) -> np.ndarray:
 
 def home_bucket(keys, table_cap: int) -> np.ndarray:
     return np.array([mix64(int(k)) & (table_cap - 1) for k in np.asarray(keys, np.uint64)], np.int64)
+
+
+class HashTable:
+    """Open-addressing table with linear probing (Sec. III-B; the stress test
+    of Sec. IV): keys inserted one after another, sequentially."""
+
+    EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+    def __init__(self, capacity: int):
+        if capacity < 2 or capacity & (capacity - 1):
+            raise ValueError("capacity must be a power of two >= 2")
+        self.keys = np.full(capacity, self.EMPTY, np.uint64)
+        self.vals = np.zeros(capacity, np.uint32)
+        self.stats = np.zeros(3, np.int64)  # max probe, probe sum, failed inserts
+
+    def insert(self, keys, val_base: int = 0) -> np.ndarray:
+        """Inserts keys in order; returns each key's probe length (-1: table full)."""
+        k = np.ascontiguousarray(keys, np.uint64)
+        probe = np.zeros(len(k), np.int64)
+        _load().orc_hash_insert(_p(self.keys, _u64p), self.vals.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                len(self.keys), _p(k, _u64p), len(k), int(val_base) & 0xFFFFFFFF, _p(probe, _i64p),
+                                _p(self.stats, _i64p))
+        return probe
+
+    def occupied(self) -> np.ndarray:
+        return self.keys != self.EMPTY
 
 
 # ------------------------------------------------------------ learned proposal

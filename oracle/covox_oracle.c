@@ -28,6 +28,11 @@
  *   align       Sec. I and Sec. III-F, Eq. (1) registration term
  *               (correspondence-free ESDF alignment, registration points
  *               chosen by weight, least squares on residuals/Jacobians).
+ *   hash        Sec. III-B (blocks indexed by their 3-D position through a
+ *               hash table with open addressing) and the hash-table stress
+ *               test of Sec. IV: keys inserted one after another, each in
+ *               the first empty slot from its home slot upwards (linear
+ *               probing, wrapping at the end).
  *
  * Two numeric modes:
  *   binary32  every arithmetic step rounded to binary32 in the pinned
@@ -1529,4 +1534,39 @@ int orc_align_multistart(const orc_submap *A, const void *pts, int64_t n_pts, co
     if (best_k) *best_k = best;
     free(Ts); free(cs); free(ns); free(its); free(st);
     return status;
+}
+
+/* ------------------------------------------------------------- hash table */
+
+/*
+ * Inserts keys[0..n) in this order into the open-addressing table
+ * tkeys/tvals of `cap` slots (a power of two; empty = all ones): each key
+ * goes to the first empty slot at or after its home slot mix64(key) &
+ * (cap - 1), wrapping at the end; the slot's value becomes val_base + i
+ * (modulo 2^32).  probe[i] (nullable) receives the number of slots passed
+ * over.  stats[0] = max probe, stats[1] += probe sum, stats[2] += keys that
+ * found no empty slot (the table was full).
+ */
+void orc_hash_insert(uint64_t *tkeys, uint32_t *tvals, int64_t cap, const uint64_t *keys, int64_t n,
+                     uint32_t val_base, int64_t *probe, int64_t stats[3])
+{
+    const uint64_t EMPTY = ~(uint64_t)0;
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t h = orc_mix64(keys[i]) & (uint64_t)(cap - 1);
+        int64_t p = 0;
+        while (p < cap && tkeys[h] != EMPTY) {
+            h = (h + 1) & (uint64_t)(cap - 1);
+            ++p;
+        }
+        if (p == cap) {
+            stats[2] += 1;
+            if (probe) probe[i] = -1;
+            continue;
+        }
+        tkeys[h] = keys[i];
+        tvals[h] = val_base + (uint32_t)i;
+        if (probe) probe[i] = p;
+        if (p > stats[0]) stats[0] = p;
+        stats[1] += p;
+    }
 }

@@ -619,3 +619,30 @@ def gravity_aligned(T: np.ndarray) -> np.ndarray:
     G[:3, :3] = rot_z(yaw)
     G[:3, 3] = T[:3, 3]
     return G
+
+
+def _fmix64(k: np.ndarray) -> np.ndarray:
+    """MurmurHash3's 64-bit finaliser (Appleby): a bijection of uint64."""
+    k = k.copy()
+    s = np.uint64(33)
+    k ^= k >> s
+    k *= np.uint64(0xFF51AFD7ED558CCD)
+    k ^= k >> s
+    k *= np.uint64(0xC4CEB9FE1A85EC53)
+    k ^= k >> s
+    return k
+
+
+def hash_keys(n: int, seed: int = 7) -> np.ndarray:
+    """n distinct pseudo-random uint64 keys, none equal to all ones (the empty
+    slot of a table): a bijection of n consecutive counters from a seeded
+    random start, so distinct by construction."""
+    start = np.random.default_rng(seed).integers(0, 2 ** 63, dtype=np.uint64)
+    ctr = np.arange(n + 1, dtype=np.uint64)
+    ctr += start
+    k = _fmix64(ctr)
+    full = np.uint64(0xFFFFFFFFFFFFFFFF)
+    bad = np.flatnonzero(k[:n] == full)
+    if len(bad):
+        k[bad] = k[n]  # the spare counter (all ones appears at most once)
+    return k[:n]
