@@ -13,11 +13,19 @@ timed replays; --no-graph skips it).
 Also reported on the same JSON line:
   roofline      the dominant kernel: algorithmic bytes per launch divided by
                 its mean duration from HIP events recorded around each of its
-                launches in the timed region, against 8 TB/s;
+                launches in the timed region, against 8 TB/s and against a
+                1 GiB device-to-device copy timed in the same run;
+  config.latency_per_frame  one frame integrated plus its ESDF, then a
+                host synchronisation (median, p99, max over the sequence);
   cpu_baseline  the oracle (single-threaded C) on a bounded
                 prefix of the same workload;
   align         ESDF alignment of overlapping room submaps: pairs/s and the
-                fraction within 1 cm / 0.1 degrees, 1 start and 8 starts.
+                fraction within 1 cm / 0.1 degrees, 1 start and 8 starts;
+  mav           the outdoor workload: mapping, batched ESDF, alignment, pose
+                graph, learned proposal, and integration time against the
+                updated-voxel count at five voxel sizes (voxel_sweep);
+  hash_table    the hash-table stress test: inserts per second and probe
+                lengths at load factors 0.25 .. 0.85.
 
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
 """
@@ -289,6 +297,7 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
                "algorithmic_bytes": b_map, "achieved_GBs": b_map / best_map / 1e9,
                "frac_hbm": b_map / best_map / 1e9 / HBM_PEAK_GBS}
     large = large_submap_esdf_bench(cv, torch, np, w, frames[:600], reps)
+    sweep = voxel_sweep_bench(cv, torch, np, w, frames[:per], Tws[0])
     del frames
     t_build = time.perf_counter() - t0
     nblk = [ctx.submap_info(s)["n_blocks"] for s in subs]
@@ -385,7 +394,8 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
     ctx.close()
     return {"workload": "outdoor 120x80 m, 3000 frames 640x480 fx=fy=380, 0.1 m voxels, 30 submaps of 100 frames",
             "build_s": t_build, "render_s": t_render, "mapping": mapping, "esdf_batch": esdf,
-            "esdf_large_submap": large, "align": align, "pose_graph": pose_graph, "learned": learned}
+            "esdf_large_submap": large, "voxel_sweep": sweep, "align": align, "pose_graph": pose_graph,
+            "learned": learned}
 
 
 def _success(T, gts, np, bound_t, bound_deg):
@@ -395,6 +405,118 @@ def _success(T, gts, np, bound_t, bound_deg):
         c = (np.trace(Tg[:3, :3] @ Tt[:3, :3].T) - 1) / 2
         ok += et <= bound_t and math.degrees(math.acos(max(-1.0, min(1.0, c)))) <= bound_deg
     return ok / max(1, len(gts))
+
+
+def _linear_fit(x, y, np):
+    """Least-squares line y = a + b x and its coefficient of determination."""
+    x, y = np.asarray(x, float), np.asarray(y, float)
+    b, a = np.polyfit(x, y, 1)
+    res = y - (a + b * x)
+    r2 = 1.0 - (res @ res) / max(((y - y.mean()) ** 2).sum(), 1e-300)
+    return a, b, r2
+
+
+def voxel_sweep_bench(cv, torch, np, w, frames, T_ws, sizes=(0.20, 0.15, 0.10, 0.075, 0.05), reps=2):
+    """Integration time against the number of updated voxels (Sec. IV, TSDF
+    timings: raycasting scales almost linearly with the voxel count): the
+    first submap's frames of the outdoor sequence integrated at five voxel
+    sizes, by raycasting (carved from the optical centre, as in the paper)
+    and by projection mapping.  Per size: ms per frame (best of reps after a
+    warm-up pass), voxel updates per frame, blocks; per integrator: the
+    least-squares line ms = a + b * updates and its R^2."""
+    out = {}
+    F = frames.shape[0]
+    poses = w.poses[:F]
+    for name, kw in (("raycast_carve", dict(integrator=cv.RAYCAST, ray_carve=1)),
+                     ("projective", dict(integrator=cv.PROJECTIVE))):
+        rows = []
+        for vs in sizes:
+            cap = int(min(1 << 20, max(16384, 16384 * (0.10 / vs) ** 3)))
+            row = {"voxel_size": vs, "block_capacity": cap}
+            try:
+                # no ESDF here; its range is capped at 40 voxels only to keep the
+                # parameters valid at the finest size
+                ctx = cv.Context(voxel_size=vs, trunc_vox=4, max_range=w.cam.max_range,
+                                 d_max=min(w.d_max, 40 * vs), block_capacity=cap, **kw)
+            except cv.CovoxError as e:
+                row["error"] = str(e)
+                rows.append(row)
+                continue
+            s = ctx.submap_create(T_ws)
+            try:
+                best = None
+                for k in range(reps + 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    ctx.submap_reset(s)
+                    ctx.map_sequence(s, frames, w.cam.K, poses, esdf_every=0)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    if k > 0:
+                        best = dt if best is None else min(best, dt)
+                info = ctx.submap_info(s)
+                row.update({"ms_per_frame": best * 1e3 / F, "voxel_updates_per_frame": info["n_updates"] / F,
+                            "blocks": info["n_blocks"],
+                            "ns_per_voxel_update": best * 1e9 / max(info["n_updates"], 1)})
+            except cv.CovoxError as e:
+                row["error"] = str(e)
+            ctx.close()
+            rows.append(row)
+        ok = [r for r in rows if "ms_per_frame" in r]
+        fit = None
+        if len(ok) >= 3:
+            a, b, r2 = _linear_fit([r["voxel_updates_per_frame"] for r in ok], [r["ms_per_frame"] for r in ok], np)
+            fit = {"intercept_ms": a, "ns_per_update": b * 1e6, "r2": r2}
+        out[name] = {"sizes": rows, "linear_fit": fit}
+    out["frames"] = F
+    return out
+
+
+def hash_bench(cv, torch, np, cap_log2=26, loads=(0.25, 0.40, 0.55, 0.70, 0.85), batch=1 << 20):
+    """Hash-table stress test (Sec. IV): a table of 2^26 slots (the capacity
+    is a power of two, so the load factor is set by the key count: 16.8 M to
+    57 M keys) filled from empty to each load factor with distinct random
+    keys (seed 7) in batches of 2^20 keys.  Per load factor: keys per second
+    over the whole fill (kernel time, HIP events), ms of the last batch (the
+    fullest table), the longest and the mean probe."""
+    import scenegen as sg
+    cap = 1 << cap_log2
+    n_max = int(max(loads) * cap)
+    keys = torch.from_numpy(sg.hash_keys(n_max, seed=7).view(np.int64)).cuda()
+    tk = torch.empty(cap, dtype=torch.int64, device="cuda")
+    tv = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ctx = cv.Context(block_capacity=64)
+    out = {"capacity": cap, "batch_keys": batch, "loads": []}
+    for lf in loads:
+        n = int(lf * cap)
+        nb = (n + batch - 1) // batch
+        stats = torch.zeros(nb, 3, dtype=torch.int64, device="cuda")
+        best = None
+        for rep in range(3):
+            tk.fill_(-1)
+            stats.zero_()
+            torch.cuda.synchronize()
+            ctx.timing_enable(["hash"])
+            for j in range(nb):
+                if j == nb - 1:
+                    last = ctx.timing_get()["hash"][0]
+                    ctx.timing_enable(["hash"])
+                b0 = j * batch
+                ctx.hash_insert(tk, tv, b0, keys[b0:min(n, b0 + batch)], stats[j], val_base=b0)
+            ms_last = ctx.timing_get()["hash"][0]
+            ms = last + ms_last if nb > 1 else ms_last
+            ctx.timing_enable([])
+            if best is None or ms < best[0]:
+                best = (ms, ms_last)
+        st = stats.cpu().numpy()
+        out["loads"].append({"load_factor": lf, "keys": n, "mkeys_per_s": n / (best[0] * 1e-3) / 1e6,
+                             "ms_fill": best[0], "ms_last_batch": best[1],
+                             "last_batch_keys": n - (nb - 1) * batch,
+                             "max_probe": int(st[:, 0].max()), "mean_probe": float(st[:, 1].sum()) / n,
+                             "failed": int(st[:, 2].sum())})
+    ctx.close()
+    del keys, tk, tv
+    return out
 
 
 def large_submap_esdf_bench(cv, torch, np, w, frames, reps=2, every=20):
@@ -664,6 +786,8 @@ def main():
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage room timing")
     ap.add_argument("--no-raycast", action="store_true", help="skip the projective / raycast comparison")
     ap.add_argument("--no-wavefront", action="store_true", help="skip the exact / wavefront ESDF comparison")
+    ap.add_argument("--no-hash", action="store_true", help="skip the hash-table stress test")
+    ap.add_argument("--no-copy", action="store_true", help="skip the stream-copy bandwidth measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -751,6 +875,39 @@ def main():
     fps = eager_fps
     ms_per_step = w.n_frames / eager_fps * 1e3
 
+    # per-call latency: one frame integrated and its ESDF updated, then a
+    # host synchronisation, frame by frame through the sequence
+    lat = []
+    ctx.submap_reset(s)
+    torch.cuda.synchronize()
+    for f in range(w.n_frames):
+        t0 = time.perf_counter()
+        ctx.integrate_depth(s, dev[f], K, w.poses[f])
+        ctx.update_esdf(s)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    lat = np.array(lat) * 1e3
+    latency = {"median_ms": float(np.median(lat)), "p99_ms": float(np.percentile(lat, 99)),
+               "max_ms": float(lat.max())}
+
+    # achievable bandwidth: a device-to-device copy of 1 GiB in this run
+    copy_gbs = None
+    if not args.no_copy:
+        n = (1 << 30) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        best = None
+        for _ in range(5):
+            ev[0].record()
+            dst.copy_(src)
+            ev[1].record()
+            torch.cuda.synchronize()
+            t = ev[0].elapsed_time(ev[1])
+            best = t if best is None else min(best, t)
+        copy_gbs = 2 * 4 * n / (best * 1e-3) / 1e9
+        del src, dst
+
     s_dw = 4 if prec == cv.FP16 else 8
     ms_k, n_k = tim[dominant]
     per_launch_ms = ms_k / max(n_k, 1)
@@ -758,7 +915,8 @@ def main():
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant, room_tuning, census),
-                "bytes_per_launch": bytes_launch, "ms_per_launch": per_launch_ms}
+                "bytes_per_launch": bytes_launch, "ms_per_launch": per_launch_ms,
+                "achievable_copy_GBs": copy_gbs, "frac_achievable": (achieved / copy_gbs) if copy_gbs else None}
 
     result = {
         "metric": METRIC,
@@ -777,7 +935,8 @@ def main():
                                "ESDF 2 m after every frame",
                    "frames_per_step": w.n_frames, "voxel_size": w.voxel_size, "blocks": census["n_blocks"][-1],
                    "graph_replay_frames_per_s": graph_fps,
-                   "voxel_updates_per_step": int(sum(census["n_upd"]))},
+                   "voxel_updates_per_step": int(sum(census["n_upd"])),
+                   "latency_per_frame": latency},
         "roofline": roofline,
         "kernel_ms_per_step": {k: v[0] for k, v in prof.items() if v[1]},
         "tuning": room_tuning,
@@ -812,6 +971,9 @@ def main():
     if not args.no_mav:
         _log("outdoor workload: 30 submaps, batched ESDF and alignment")
         result["mav"] = mav_bench(cv, torch, np)
+    if not args.no_hash:
+        _log("hash-table stress test (2^26 slots, load 0.25 .. 0.85)")
+        result["hash_table"] = hash_bench(cv, torch, np)
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(w, frames, args.cpu_seconds)

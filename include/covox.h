@@ -475,6 +475,41 @@ int covox_graph_end(covox_ctx *ctx, covox_graph **out);
 int covox_graph_launch(covox_graph *g);
 void covox_graph_destroy(covox_graph *g);
 
+/* ---------------------------------------------------------- hash table */
+
+/* Hash-table stress test (Sec. IV, hash-table stress testing: insertions
+ * at a range of load factors).  Inserts n keys into a table that the caller
+ * owns, with the routine that maps block coordinates to block indices in
+ * every submap (Sec. III-B): open addressing, home slot = SplitMix64
+ * finaliser of the key masked to the capacity, linear probing towards
+ * higher slots (wrapping), one 64-bit compare-and-swap per probed slot.
+ * Concurrent inserts of one call land in slots that depend on scheduling;
+ * the set of occupied slots and the probe sum do not (linear probing).
+ *
+ *   table_keys  device uint64[capacity]; an empty slot holds UINT64_MAX.
+ *               The caller fills every slot with UINT64_MAX before the
+ *               first insert and keeps the table between calls.
+ *   table_vals  device uint32[capacity]; the slot that receives keys[i]
+ *               gets val_base + i (modulo 2^32).
+ *   capacity    slots: a power of two, 2 .. 2^32.
+ *   n_present   keys already in the table.  After the call at most 15/16
+ *               of the slots may be occupied (n_present + n), else
+ *               COVOX_ETABLE_FULL and nothing runs.
+ *   keys        device uint64[n]: distinct, absent from the table, none
+ *               equal to UINT64_MAX.  A key already present is inserted
+ *               a second time.
+ *   stats       device int64[3], raised by the call (the caller clears it):
+ *               [0] = max over this call's keys of the probe length (slots
+ *               past the home slot), [1] += sum of the probe lengths,
+ *               [2] += keys not inserted because capacity slots in a row
+ *               were occupied (only when n_present understated the load or
+ *               the table was not cleared; such a probe stops there).
+ *
+ * Asynchronous on the context stream.  COVOX_EINVAL for a null pointer, a
+ * capacity that is not a power of two in range, or a negative count. */
+int covox_hash_insert(covox_ctx *ctx, uint64_t *table_keys, uint32_t *table_vals, int64_t capacity,
+                      int64_t n_present, const uint64_t *keys, int64_t n, uint32_t val_base, int64_t *stats);
+
 /* -------------------------------------------------------------- tuning */
 
 /* Launch shapes chosen per call.  Each line pass of the EDT (y, then z) has
@@ -536,6 +571,7 @@ enum {
     COVOX_K_RAY_APPLY,     /* raycasting: activate new blocks, merge the sums into D and W */
     COVOX_K_PGO,           /* pose graph: term blocks, block-sparse assembly, PCG */
     COVOX_K_WAVEFRONT,     /* incremental ESDF: seeds, rounds (queue, block sweeps, commit), phi */
+    COVOX_K_HASH,          /* hash-table stress insertion (covox_hash_insert) */
     COVOX_K_COUNT
 };
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcovox.so")
-SOURCES = ["api.hip", "k_integrate.hip", "k_raycast.hip", "k_pgo.hip", "k_wavefront.hip", "k_esdf.hip", "k_align.hip", "k_net.hip"]
+SOURCES = ["api.hip", "k_integrate.hip", "k_raycast.hip", "k_pgo.hip", "k_wavefront.hip", "k_esdf.hip", "k_align.hip", "k_net.hip", "k_hash.hip"]
 HEADERS = ["covox_impl.h", "edt_envelope.h", os.path.join("..", "..", "include", "covox.h")]
 ARCH = os.environ.get("COVOX_OFFLOAD_ARCH", "gfx950")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

@@ -28,7 +28,7 @@ WEIGHT_CONSTANT, WEIGHT_INV_DEPTH2 = 0, 1
 PROJECTIVE, RAYCAST = 0, 1
 ESDF_EXACT, ESDF_WAVEFRONT = 0, 1
 KERNELS = ["probe", "scan", "integrate", "esdf_page", "esdf_sites", "edt_x", "edt_y", "edt_z", "iso", "align",
-           "summary", "net", "ray_mark", "ray_accum", "ray_apply", "pgo", "wavefront"]
+           "summary", "net", "ray_mark", "ray_accum", "ray_apply", "pgo", "wavefront", "hash"]
 
 
 class CovoxError(RuntimeError):
@@ -156,6 +156,8 @@ _sig = {
     "covox_pgo_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.c_int32, _dp, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.c_int32, ctypes.POINTER(covox_pose_factor), ctypes.c_int32,
                                        ctypes.POINTER(covox_pgo_cfg), ctypes.POINTER(covox_pgo_stats)]),
+    "covox_hash_insert": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64, _vp, ctypes.c_int64,
+                                         ctypes.c_uint32, _vp]),
     "covox_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "covox_timing_get": (ctypes.c_int, [_vp, ctypes.POINTER(covox_timing)]),
 }
@@ -369,6 +371,27 @@ class Context:
                                          len(rp), fa, len(factors), ctypes.byref(c), ctypes.byref(st)), "pgo_solve")
         return x, {"iterations": st.iterations, "accepted": st.accepted, "converged": bool(st.converged),
                    "cg_iterations": st.cg_iterations, "cost_init": st.cost_init, "cost_final": st.cost_final}
+
+    # -- hash-table stress test (Sec. IV)
+    def hash_insert(self, table_keys, table_vals, n_present, keys, stats, val_base=0):
+        """Inserts the device keys (int64 or uint64 tensor, distinct, absent,
+        none equal to all ones) into the caller's table (table_keys:
+        capacity 64-bit slots, empty = all ones; table_vals: capacity 32-bit
+        slots).  stats: int64 device tensor of 3, raised by the call (max
+        probe, probe sum, failures).  Asynchronous on the context stream."""
+        def dev(t, bits, what):
+            if not (t.is_cuda and t.is_contiguous() and t.element_size() * 8 == bits and not t.is_floating_point()):
+                raise ValueError("%s must be a contiguous %d-bit integer device tensor" % (what, bits))
+            return ctypes.c_void_p(t.data_ptr())
+        if table_vals.numel() != table_keys.numel():
+            raise ValueError("table_vals must have one slot per table_keys slot")
+        if stats.dtype != torch.int64 or stats.numel() < 3:
+            raise ValueError("stats must be an int64 device tensor of at least 3 entries")
+        n = keys.numel()
+        return self._check(_lib.covox_hash_insert(self.handle, dev(table_keys, 64, "table_keys"),
+                                                  dev(table_vals, 32, "table_vals"), table_keys.numel(), int(n_present),
+                                                  dev(keys, 64, "keys") if n else None, n, int(val_base) & 0xFFFFFFFF,
+                                                  dev(stats, 64, "stats")), "hash_insert")
 
     # -- learned proposal
     def summaries(self, reqs):

@@ -726,6 +726,14 @@ int covox_pgo_solve(covox_ctx *ctx, covox_submap *const *subs, int32_t n, double
     return pgo_solve(ctx, subs, n, x, reg_pairs, n_reg, factors, n_fac, cfg, stats);
 }
 
+int covox_hash_insert(covox_ctx *ctx, uint64_t *table_keys, uint32_t *table_vals, int64_t capacity,
+                      int64_t n_present, const uint64_t *keys, int64_t n, uint32_t val_base, int64_t *stats)
+{
+    if (!ctx) return COVOX_EINVAL;
+    COVOX_NOT_DURING_CAPTURE(ctx, "hash_insert");
+    return hash_insert_keys(ctx, table_keys, table_vals, capacity, n_present, keys, n, val_base, stats);
+}
+
 int covox_submap_info_get(covox_ctx *ctx, const covox_submap *s, covox_submap_info *out)
 {
     COVOX_NOT_DURING_CAPTURE(ctx, "submap_info_get");

@@ -72,6 +72,26 @@ __device__ inline void hash_insert(uint64_t *tkeys, uint32_t *tvals, uint64_t ma
     }
 }
 
+// The same insertion (home slot, probe order, compare-and-swap) with the
+// probe bounded by `limit` slots, for tables that the caller owns and may
+// have filled: returns the number of slots probed past the home slot, or -1
+// when `limit` slots were occupied.
+__device__ inline int64_t hash_insert_bounded(uint64_t *tkeys, uint32_t *tvals, uint64_t mask, uint64_t key,
+                                              uint32_t val, uint64_t limit)
+{
+    uint64_t h = mix64(key) & mask;
+    for (uint64_t step = 0; step < limit; ++step) {
+        unsigned long long prev = atomicCAS((unsigned long long *)&tkeys[h], (unsigned long long)kEmpty,
+                                            (unsigned long long)key);
+        if (prev == kEmpty) {
+            tvals[h] = val;
+            return (int64_t)step;
+        }
+        h = (h + 1) & mask;
+    }
+    return -1;
+}
+
 // ----------------------------------------------------------- submap state
 
 // Device-resident bookkeeping of one submap.
@@ -352,6 +372,10 @@ void covox_default_pgo_cfg_impl(covox_pgo_cfg *c);
 int pgo_solve(covox_ctx *ctx, covox_submap *const *subs, int32_t n, double *x, const int32_t *reg_pairs,
               int32_t n_reg, const covox_pose_factor *factors, int32_t n_fac, const covox_pgo_cfg *cfg,
               covox_pgo_stats *stats);
+
+// k_hash.hip: stress insertion into a caller-owned table (covox_hash_insert)
+int hash_insert_keys(covox_ctx *ctx, uint64_t *tkeys, uint32_t *tvals, int64_t capacity, int64_t n_present,
+                     const uint64_t *keys, int64_t n, uint32_t val_base, int64_t *stats);
 
 // k_wavefront.hip: incremental ESDF (esdf_mode COVOX_ESDF_WAVEFRONT)
 int update_esdf_wavefront(covox_ctx *ctx, covox_submap *s);
