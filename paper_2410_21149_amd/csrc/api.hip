@@ -215,6 +215,7 @@ __global__ void k_reset_meta(SubmapMeta *m)
     m->n_new = 0;
     m->n_touched = 0;
     m->dom_valid = 0;
+    m->dom_nblocks = 0;
     m->n_points = 0;
     m->pbar[0] = m->pbar[1] = m->pbar[2] = 0.0;
     m->n_updates = 0;
@@ -431,6 +432,12 @@ void covox_destroy(covox_ctx *ctx)
         if (ptr) (void)hipFree(ptr);
     for (void *p : ctx->deferred) (void)hipFree(p);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->esdf_stream) {
+        (void)hipStreamSynchronize(ctx->esdf_stream);
+        (void)hipStreamDestroy(ctx->esdf_stream);
+    }
+    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_integrated, ctx->ev_paged, ctx->ev_join})
+        if (e) (void)hipEventDestroy(e);
     if (ctx->wf_pin) (void)hipHostFree(ctx->wf_pin);
     for (int k = 0; k < 2; ++k) {
         if (ctx->frames_pin[k]) (void)hipHostFree(ctx->frames_pin[k]);
@@ -577,6 +584,22 @@ int covox_integrate_depth_batch(covox_ctx *ctx, covox_submap *s, const float *de
     return integrate_frames(ctx, s, depths_dev, F, H, W, K, T_world_cam);
 }
 
+namespace {
+
+// The second stream and the events of a pipelined map_sequence, created
+// once per context (the stream last, so that its presence means all exist).
+int ensure_pipeline(covox_ctx *ctx)
+{
+    if (ctx->esdf_stream) return COVOX_OK;
+    int rc;
+    for (hipEvent_t *e : {&ctx->ev_fork, &ctx->ev_integrated, &ctx->ev_paged, &ctx->ev_join})
+        if (!*e && (rc = hip_check(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming), "pipeline event")))
+            return rc;
+    return hip_check(ctx, hipStreamCreateWithFlags(&ctx->esdf_stream, hipStreamNonBlocking), "esdf stream");
+}
+
+}  // namespace
+
 int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev, int32_t F, int32_t H, int32_t W,
                        const float K[4], const double *T_world_cam, int32_t esdf_every)
 {
@@ -584,14 +607,53 @@ int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev,
     capture_touch(ctx, s, 1);
     // frames between ESDF updates go through the batched integration
     const int32_t step = esdf_every > 0 ? esdf_every : F;
-    for (int32_t f0 = 0; f0 < F; f0 += step) {
-        const int32_t n = std::min(step, F - f0);
-        int rc = integrate_frames(ctx, s, depths_dev + (size_t)f0 * H * W, n, H, W, K, T_world_cam + 16 * f0);
-        if (rc) return rc;
-        rc = update_esdf(ctx, s);
-        if (rc) return rc;
+    // With an exact ESDF update after every chunk, the update of chunk k runs
+    // on a second stream while chunk k + 1 is integrated on the context
+    // stream: only the update's first kernel reads the TSDF, and the next
+    // integration waits for that kernel alone.  The results are those of the
+    // calls in sequence.
+    const bool pipe = esdf_every > 0 && F > step && ctx->p.esdf_mode == COVOX_ESDF_EXACT &&
+                      (ctx->esdf_stream || !ctx->capturing);
+    if (!pipe) {
+        for (int32_t f0 = 0; f0 < F; f0 += step) {
+            const int32_t n = std::min(step, F - f0);
+            int rc = integrate_frames(ctx, s, depths_dev + (size_t)f0 * H * W, n, H, W, K, T_world_cam + 16 * f0);
+            if (rc) return rc;
+            rc = update_esdf(ctx, s);
+            if (rc) return rc;
+        }
+        return COVOX_OK;
     }
-    return COVOX_OK;
+    int rc = ensure_pipeline(ctx);
+    if (rc) return rc;
+    hipStream_t main = ctx->stream, aux = ctx->esdf_stream;
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->ev_fork, main), "fork")) ||
+        (rc = hip_check(ctx, hipStreamWaitEvent(aux, ctx->ev_fork, 0), "fork wait")))
+        return rc;
+    int rc_loop = COVOX_OK;
+    for (int32_t f0 = 0; f0 < F && !rc_loop; f0 += step) {
+        const int32_t n = std::min(step, F - f0);
+        rc_loop = integrate_frames(ctx, s, depths_dev + (size_t)f0 * H * W, n, H, W, K, T_world_cam + 16 * f0);
+        if (rc_loop) break;
+        if ((rc_loop = hip_check(ctx, hipEventRecord(ctx->ev_integrated, main), "integrated")) ||
+            (rc_loop = hip_check(ctx, hipStreamWaitEvent(aux, ctx->ev_integrated, 0), "integrated wait")))
+            break;
+        ctx->stream = aux;
+        ctx->esdf_page_event = ctx->ev_paged;
+        ctx->esdf_page_recorded = false;
+        rc_loop = update_esdf(ctx, s);
+        if (!rc_loop && !ctx->esdf_page_recorded)  // no page kernel ran: order after the whole update
+            rc_loop = hip_check(ctx, hipEventRecord(ctx->ev_paged, aux), "paged");
+        ctx->esdf_page_event = nullptr;
+        ctx->stream = main;
+        if (!rc_loop) rc_loop = hip_check(ctx, hipStreamWaitEvent(main, ctx->ev_paged, 0), "paged wait");
+    }
+    // join, after an error too: later work on the context stream follows all of it
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->ev_join, aux), "join")) ||
+        (rc = hip_check(ctx, hipStreamWaitEvent(main, ctx->ev_join, 0), "join wait"))) {
+        if (!rc_loop) rc_loop = rc;
+    }
+    return rc_loop;
 }
 
 int covox_update_esdf_batch(covox_ctx *ctx, covox_submap *const *subs, int32_t n)

@@ -110,7 +110,7 @@ struct SubmapMeta {
     unsigned long long n_updates;  // voxel updates since creation / reset
     int64_t batch_n0;       // last frame batch: n_blocks before it
     int32_t batch_frames;   // and its frames committed (a capacity failure stops the batch)
-    int32_t pad0;
+    int32_t dom_nblocks;    // allocated blocks when the page was built (the EDT passes' domain)
 };
 
 // Per-frame projection parameters (kernel argument).
@@ -287,6 +287,14 @@ struct covox_ctx {
     // pinned host staging for small copies
     void *host_pin = nullptr;
     size_t host_pin_cap = 0;
+    // map_sequence: the ESDF of one frame chunk runs on esdf_stream while the
+    // next chunk integrates on the context stream.  esdf_page_event, when
+    // set, is recorded right after the page / site / seed kernel (the last
+    // ESDF kernel that reads the TSDF).
+    hipStream_t esdf_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_integrated = nullptr, ev_paged = nullptr, ev_join = nullptr;
+    hipEvent_t esdf_page_event = nullptr;
+    bool esdf_page_recorded = false;
     // graph capture (on a stream of the library: the legacy default stream
     // cannot be captured)
     hipStream_t cap_stream = nullptr;

@@ -75,7 +75,12 @@ struct Plan {
 
 __device__ __forceinline__ int64_t nsegments(int64_t L, int S) { return L > 0 ? (L + S - 1) / S : 0; }
 
-// Fills the job info of one submap from its device bookkeeping.
+// Fills the job info of one submap from its device bookkeeping: the live
+// block count and block box (SNAP = false: the page kernel, which runs while
+// nothing else changes the submap), or the snapshot the page kernel stored
+// (SNAP = true: the EDT passes, which may run while the next frames are
+// integrated into the same submap).
+template <bool SNAP>
 __device__ __forceinline__ void job_info(const SubmapMeta *m, int C, JobInfo &ji, int64_t &cy, int64_t &cz)
 {
     for (int a = 0; a < 3; ++a) { ji.lo[a] = 0; ji.dim[a] = 0; }
@@ -83,13 +88,13 @@ __device__ __forceinline__ void job_info(const SubmapMeta *m, int C, JobInfo &ji
     ji.nb = 0;
     cy = 0;
     cz = 0;
-    const int64_t nb = m->n_blocks;
+    const int64_t nb = SNAP ? (int64_t)m->dom_nblocks : m->n_blocks;
     if (nb <= 0) return;
     ji.nb = nb;
     ji.nd = 1;
     for (int a = 0; a < 3; ++a) {
-        ji.lo[a] = m->bmin[a];
-        ji.dim[a] = m->bmax[a] - m->bmin[a] + 1;
+        ji.lo[a] = SNAP ? m->dom_min[a] : m->bmin[a];
+        ji.dim[a] = SNAP ? m->dom_dim[a] : m->bmax[a] - m->bmin[a] + 1;
         ji.nd *= ji.dim[a];
     }
     const int S = kWin - 2 * C;
@@ -100,7 +105,7 @@ __device__ __forceinline__ void job_info(const SubmapMeta *m, int C, JobInfo &ji
 // The plan of a multi-submap launch: the first wave derives one submap per
 // lane with wave prefix sums, then a workgroup barrier publishes it.  A
 // single-submap launch keeps its one entry in registers instead (PlanView).
-template <int NJ>
+template <bool SNAP, int NJ>
 __device__ void make_plan(const JobList<NJ> &jl, int C, Plan &pl)
 {
     if (threadIdx.x < 64) {
@@ -109,7 +114,7 @@ __device__ void make_plan(const JobList<NJ> &jl, int C, Plan &pl)
         int64_t cy = 0, cz = 0;
         for (int a = 0; a < 3; ++a) { ji.lo[a] = 0; ji.dim[a] = 0; }
         ji.nd = ji.nb = 0;
-        if (lane < jl.n) job_info(jl.j[lane].meta, C, ji, cy, cz);
+        if (lane < jl.n) job_info<SNAP>(jl.j[lane].meta, C, ji, cy, cz);
         const int64_t v[4] = {ji.nd, ji.nb, cy, cz};
         int64_t incl[4];
 #pragma unroll
@@ -153,7 +158,7 @@ __device__ __forceinline__ int find_job(const Plan &pl, int64_t w)
 }
 
 // Uniform access to the plan: registers for one submap, LDS for several.
-template <int NJ>
+template <int NJ, bool SNAP = true>
 struct PlanView {
     Plan *pl;
     JobInfo one;
@@ -163,7 +168,7 @@ struct PlanView {
     {
         if constexpr (NJ == 1) {
             int64_t cy, cz;
-            job_info(jl.j[0].meta, C, one, cy, cz);
+            job_info<SNAP>(jl.j[0].meta, C, one, cy, cz);
             one.od = one.ob = one.oy = one.oz = 0;
             t[0] = one.nd;
             t[1] = one.nb;
@@ -171,7 +176,7 @@ struct PlanView {
             t[3] = cz;
             pl = nullptr;
         } else {
-            make_plan(jl, C, lds);
+            make_plan<SNAP>(jl, C, lds);
             pl = &lds;
             t[0] = lds.td;
             t[1] = lds.tb;
@@ -205,15 +210,27 @@ __device__ __forceinline__ int64_t dom_index(const JobInfo &d, int x, int y, int
 }
 
 // Page (dense block -> buffer index, -1 if unallocated) and site masks, one
-// wave per dense block.
-template <typename S, int NJ>
-__global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C, float vs,
+// wave per dense block, and the snapshot of each submap's domain (block box
+// and block count) that the later passes work on.  With SEEDS, also the phi
+// seed of every voxel of an allocated block: NaN when unobserved, D inside
+// the band, and otherwise an infinity with the sign of D.  The EDT passes then
+// never read the TSDF, so that the next frames may be integrated while they
+// run.
+template <typename S, int NJ, bool SEEDS>
+__global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C, float vs, float tau,
                                                     uint64_t *__restrict__ sites)
 {
     __shared__ Plan lds;
-    PlanView<NJ> pv;
+    PlanView<NJ, false> pv;
     pv.init(jl, C, lds);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (blockIdx.x == 0 && (int)threadIdx.x < jl.n) {
+        const JobInfo d = pv.info(threadIdx.x);
+        SubmapMeta *m = jl.j[threadIdx.x].meta;
+        for (int a = 0; a < 3; ++a) { m->dom_min[a] = d.lo[a]; m->dom_dim[a] = d.dim[a]; }
+        m->dom_nblocks = (int32_t)d.nb;
+        m->dom_valid = 1;
+    }
     for (int64_t g = (int64_t)blockIdx.x * 4 + wid; g < pv.t[0]; g += (int64_t)gridDim.x * 4) {
         const int j = pv.template job<&JobInfo::od>(g);
         const JobInfo d = pv.info(j);
@@ -221,10 +238,6 @@ __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C,
         const int64_t db = g - d.od;
         int x, y, z;
         dom_coords(d, db, x, y, z);
-        if (db == 0 && lane == 0) {
-            for (int a = 0; a < 3; ++a) { job.meta->dom_min[a] = d.lo[a]; job.meta->dom_dim[a] = d.dim[a]; }
-            job.meta->dom_valid = 1;
-        }
         int64_t idx = -1;
         if (lane == 0) idx = hash_find(job.tkeys, job.tvals, job.tmask, pack_key(d.lo[0] + x, d.lo[1] + y, d.lo[2] + z));
         idx = __shfl(idx, 0, 64);
@@ -238,6 +251,10 @@ __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C,
                 const float Dv = ldv(Db + 64 * k), Wv = ldv(Wb + 64 * k);
                 const uint64_t m = __ballot(Wv > 0.0f && fabsf(Dv) <= vs);
                 if (lane == k) w = m;
+                if constexpr (SEEDS)
+                    job.phi[idx * 512 + lane + 64 * k] =
+                        !(Wv > 0.0f) ? __builtin_nanf("")
+                                     : (fabsf(Dv) < tau ? Dv : (Dv > 0.0f ? __builtin_inff() : -__builtin_inff()));
             }
         }
         if (lane < 8) sites[g * 8 + lane] = w;
@@ -360,17 +377,18 @@ __global__ __launch_bounds__(256) void k_edt_y_vox(const JobList<NJ> jl, const u
     }
 }
 
-// phi of one voxel from D, W and the squared distance search result.
-__device__ __forceinline__ float phi_value(float Dv, int best, int R2, float vs, float dmax)
+// phi of a voxel outside the band from its seed (an infinity with the sign
+// of D) and the squared distance search result.
+__device__ __forceinline__ float phi_value(float seed, int best, int R2, float vs, float dmax)
 {
-    const float sg = Dv > 0.0f ? 1.0f : -1.0f;
+    const float sg = seed > 0.0f ? 1.0f : -1.0f;
     if (best > R2) return sg * dmax;
     return sg * fminf(dmax, vs * sqrtf((float)best));
 }
 
-template <typename S, int NJ>
+template <int NJ>
 __global__ __launch_bounds__(512) void k_edt_z_vox(const JobList<NJ> jl, const uint16_t *__restrict__ g2, int R,
-                                                   int HB, float vs, float tau, float dmax)
+                                                   int HB, float vs, float dmax)
 {
     __shared__ Plan lds;
     __shared__ __align__(16) uint32_t colw[(2 * kMaxHalo + 1) * 256];
@@ -398,14 +416,10 @@ __global__ __launch_bounds__(512) void k_edt_z_vox(const JobList<NJ> jl, const u
             colw[e] = (nz >= 0 && nz < d.dim[2]) ? ((const uint32_t *)(g2 + (g + (int64_t)(i - HB) * stride_z) * 512))[q]
                                                  : 0xFFFFFFFFu;
         }
-        const float Dv = ldv((const S *)job.D + j * 512 + tid), Wv = ldv((const S *)job.W + j * 512 + tid);
+        const float seed = job.phi[j * 512 + tid];  // from k_page_sites
         __syncthreads();
-        float out;
-        if (!(Wv > 0.0f)) {
-            out = __builtin_nanf("");
-        } else if (fabsf(Dv) < tau) {
-            out = Dv;
-        } else {
+        // an unobserved (NaN) or in-band (D) seed is already the result
+        if (__builtin_isinf(seed)) {
             const int base = tid & 63;
             auto at = [&](int zz) { return col[(zz >> 3) * 512 + base + 64 * (zz & 7)]; };
             int best = inf16(at(Z));
@@ -417,9 +431,8 @@ __global__ __launch_bounds__(512) void k_edt_z_vox(const JobList<NJ> jl, const u
                     if (e <= R) best = min(best, min(inf16(at(Z - e)), inf16(at(Z + e))) + e * e);
                 }
             }
-            out = phi_value(Dv, best, R2, vs, dmax);
+            job.phi[j * 512 + tid] = phi_value(seed, best, R2, vs, dmax);
         }
-        job.phi[j * 512 + tid] = out;
         __syncthreads();
     }
 }
@@ -505,9 +518,9 @@ __global__ __launch_bounds__(64) void k_edt_y_env(const JobList<NJ> jl, const ui
 }
 
 // Lane = x + 8 y, the in-block layout, within the column (bx, by, *).
-template <typename S, int NJ>
+template <int NJ>
 __global__ __launch_bounds__(64) void k_edt_z_env(const JobList<NJ> jl, const uint16_t *__restrict__ g2, int R,
-                                                  int HB, float vs, float tau, float dmax)
+                                                  int HB, float vs, float dmax)
 {
     __shared__ Plan lds;
     __shared__ __align__(16) uint16_t col[kWin * 64];  // [position][lane]
@@ -558,22 +571,13 @@ __global__ __launch_bounds__(64) void k_edt_z_env(const JobList<NJ> jl, const ui
         for (int zb = z0; zb < z1; zb += 8) {
             const int64_t idx = job.page[dom_index(d, bx, by, zb / 8)];
             if (idx < 0) continue;
-            const S *Db = (const S *)job.D + idx * 512 + lane;
-            const S *Wb = (const S *)job.W + idx * 512 + lane;
             float *Pb = job.phi + idx * 512 + lane;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const float Dv = ldv(Db + 64 * t), Wv = ldv(Wb + 64 * t);
-                float out;
-                if (!(Wv > 0.0f)) {
-                    out = __builtin_nanf("");
-                } else if (fabsf(Dv) < tau) {
-                    out = Dv;
-                } else {
-                    const int best = e.k >= 0 ? walk_at(wk, e, stk, 64, lane, zb + t - w0, getf) : kBig;
-                    out = phi_value(Dv, best, R2, vs, dmax);
-                }
-                Pb[64 * t] = out;
+                const float seed = Pb[64 * t];  // from k_page_sites
+                if (!__builtin_isinf(seed)) continue;  // unobserved or in the band: the seed stays
+                const int best = e.k >= 0 ? walk_at(wk, e, stk, 64, lane, zb + t - w0, getf) : kBig;
+                Pb[64 * t] = phi_value(seed, best, R2, vs, dmax);
             }
         }
         wave_sync();
@@ -663,14 +667,27 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
     const bool h = p.precision == COVOX_FP16;
     {
         TimedLaunch tl(ctx, COVOX_K_ESDF_PAGE);
-        if (h)
-            hipLaunchKernelGGL((k_page_sites<__half, NJ>), dim3(clamp_grid((nd + 3) / 4)), dim3(256), 0, ctx->stream,
-                               jl, C, vs, ctx->sites);
+        const dim3 grid(clamp_grid((nd + 3) / 4));
+        if (h && edt)
+            hipLaunchKernelGGL((k_page_sites<__half, NJ, true>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
+                               ctx->sites);
+        else if (h)
+            hipLaunchKernelGGL((k_page_sites<__half, NJ, false>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
+                               ctx->sites);
+        else if (edt)
+            hipLaunchKernelGGL((k_page_sites<float, NJ, true>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
+                               ctx->sites);
         else
-            hipLaunchKernelGGL((k_page_sites<float, NJ>), dim3(clamp_grid((nd + 3) / 4)), dim3(256), 0, ctx->stream,
-                               jl, C, vs, ctx->sites);
+            hipLaunchKernelGGL((k_page_sites<float, NJ, false>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
+                               ctx->sites);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "page launch"))) return rc;
+    // the rest of the update reads no TSDF state: a pipelined caller may let
+    // the next integration start here
+    if (ctx->esdf_page_event) {
+        if ((rc = hip_check(ctx, hipEventRecord(ctx->esdf_page_event, ctx->stream), "page event"))) return rc;
+        ctx->esdf_page_recorded = true;
+    }
     for (int i = 0; i < n; ++i) subs[i]->page_version = subs[i]->version;
     if (!edt) return COVOX_OK;
     // Pass shape: per-line envelopes when there are enough lines to fill the
@@ -699,18 +716,12 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Z);
-        if (env_z && h)
-            hipLaunchKernelGGL((k_edt_z_env<__half, NJ>), dim3(clamp_grid_w(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2,
-                               R, HB, vs, tau, dmax);
-        else if (env_z)
-            hipLaunchKernelGGL((k_edt_z_env<float, NJ>), dim3(clamp_grid_w(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2,
-                               R, HB, vs, tau, dmax);
-        else if (h)
-            hipLaunchKernelGGL((k_edt_z_vox<__half, NJ>), dim3(clamp_grid(nb)), dim3(512), 0, ctx->stream, jl,
-                               ctx->g2, R, HB, vs, tau, dmax);
+        if (env_z)
+            hipLaunchKernelGGL((k_edt_z_env<NJ>), dim3(clamp_grid_w(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2, R, HB,
+                               vs, dmax);
         else
-            hipLaunchKernelGGL((k_edt_z_vox<float, NJ>), dim3(clamp_grid(nb)), dim3(512), 0, ctx->stream, jl, ctx->g2,
-                               R, HB, vs, tau, dmax);
+            hipLaunchKernelGGL((k_edt_z_vox<NJ>), dim3(clamp_grid(nb)), dim3(512), 0, ctx->stream, jl, ctx->g2, R, HB,
+                               vs, dmax);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "esdf launch"))) return rc;
     for (int i = 0; i < n; ++i) subs[i]->esdf_version = subs[i]->version;
