@@ -5,10 +5,12 @@ Step = the room workload mapped from scratch: 300 depth frames of 640x480
 (fx = fy = 525), 5 cm voxels, truncation 4 voxels, ESDF (2 m) recomputed
 after every frame -- projective integration (probe / scan / integrate
 kernels) followed by the exact ESDF (page / x / y / z kernels) per frame.
-value = frames per second over the timed steps (inputs already resident in
-device memory).  config.graph_replay_frames_per_s times the same step
-captured once as a HIP graph (covox_graph_*) and replayed (W untimed, K
-timed replays; --no-graph skips it).
+The ESDF of each frame runs on a second stream while the next frame is
+integrated (covox_map_sequence).  The step is captured once as a HIP graph
+(covox_graph_*) and replayed: W untimed, then K timed replays.  value =
+frames per second over the timed replays (inputs already resident in device
+memory).  config.eager_frames_per_s times the same step issued call by call
+(W untimed, K timed); with --no-graph that eager figure is the value.
 
 Also reported on the same JSON line:
   roofline      the dominant kernel: algorithmic bytes per launch divided by
@@ -816,8 +818,12 @@ def main():
     frames = w.frames()
     dev = torch.from_numpy(frames).cuda()
     prec = cv.FP16 if args.precision == "fp16" else cv.FP32
+    # Block capacity 2^21 (12.6 GB of D, W and phi): a captured step cannot
+    # read the block count back, so the host bound grows by each frame's
+    # whole frustum box (1.08 M blocks over the sequence), and updates fold
+    # into the probe kernel only while that bound stays within capacity.
     ctx = cv.Context(voxel_size=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max,
-                     block_capacity=131072, precision=prec)
+                     block_capacity=1 << 21, precision=prec)
     s = ctx.submap_create()
     K = w.cam.K
 
@@ -872,8 +878,11 @@ def main():
         graph_fps = w.n_frames * args.steps / (time.perf_counter() - t0)
         ctx.sync()  # sticky capacity status of the replays
         graph.close()
-    fps = eager_fps
-    ms_per_step = w.n_frames / eager_fps * 1e3
+    # value: the step as a captured graph replayed (the launch-bound frame
+    # loop without per-launch host cost), else the eager calls
+    fps = graph_fps if graph_fps is not None else eager_fps
+    step_mode = "graph_replay" if graph_fps is not None else "eager"
+    ms_per_step = w.n_frames / fps * 1e3
 
     # per-call latency: one frame integrated and its ESDF updated, then a
     # host synchronisation, frame by frame through the sequence
@@ -934,6 +943,7 @@ def main():
         "config": {"workload": "room 8x6x3 m, 300 frames 640x480 fx=fy=525, 5 cm voxels, tau 4 voxels, "
                                "ESDF 2 m after every frame",
                    "frames_per_step": w.n_frames, "voxel_size": w.voxel_size, "blocks": census["n_blocks"][-1],
+                   "step_mode": step_mode, "eager_frames_per_s": eager_fps,
                    "graph_replay_frames_per_s": graph_fps,
                    "voxel_updates_per_step": int(sum(census["n_upd"])),
                    "latency_per_frame": latency},
