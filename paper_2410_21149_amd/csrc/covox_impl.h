@@ -55,6 +55,35 @@ __device__ inline int64_t hash_find(const uint64_t *tkeys, const uint32_t *tvals
     }
 }
 
+// The same lookup in two steps: hash_first reads the home slot (key and
+// value), hash_resolve finishes the lookup, probing on only when the home
+// slot holds another key.  Other reads can be in flight in between.
+struct HashProbe {
+    uint64_t h, k;
+    uint32_t v;
+};
+
+__device__ inline HashProbe hash_first(const uint64_t *tkeys, const uint32_t *tvals, uint64_t mask, uint64_t key)
+{
+    HashProbe p;
+    p.h = mix64(key) & mask;
+    p.k = tkeys[p.h];
+    p.v = tvals[p.h];
+    return p;
+}
+
+__device__ inline int64_t hash_resolve(const HashProbe &p, const uint64_t *tkeys, const uint32_t *tvals,
+                                       uint64_t mask, uint64_t key)
+{
+    if (p.k == key) return (int64_t)p.v;
+    if (p.k == kEmpty) return -1;
+    for (uint64_t h = (p.h + 1) & mask;; h = (h + 1) & mask) {
+        const uint64_t k = tkeys[h];
+        if (k == key) return (int64_t)tvals[h];
+        if (k == kEmpty) return -1;
+    }
+}
+
 // Inserts a key known to be absent ("activate": the caller already owns
 // its buffer index).
 __device__ inline void hash_insert(uint64_t *tkeys, uint32_t *tvals, uint64_t mask, uint64_t key,

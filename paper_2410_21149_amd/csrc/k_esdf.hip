@@ -246,9 +246,16 @@ __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C,
         if (idx >= 0) {
             const S *Db = (const S *)job.D + idx * 512 + lane;
             const S *Wb = (const S *)job.W + idx * 512 + lane;
+            // all reads before the first write (the seeds), so that they overlap
+            float Dk[8], Wk[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const float Dv = ldv(Db + 64 * k), Wv = ldv(Wb + 64 * k);
+                Dk[k] = ldv(Db + 64 * k);
+                Wk[k] = ldv(Wb + 64 * k);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float Dv = Dk[k], Wv = Wk[k];
                 const uint64_t m = __ballot(Wv > 0.0f && fabsf(Dv) <= vs);
                 if (lane == k) w = m;
                 if constexpr (SEEDS)
@@ -289,6 +296,10 @@ __device__ __forceinline__ int nearest_bit(uint64_t lo, uint64_t hi, int p)
 __device__ __forceinline__ int sq8(uint8_t v) { return v == 255 ? kBig : (int)v * (int)v; }
 
 constexpr int kScanStep = 8;  // offsets per exit test of the windowed y and z passes
+// 32-bit words a lane stages into LDS per block in the y pass (256 lanes,
+// 2 HB + 1 blocks of 128 words) and the z pass (512 lanes, 256 words each)
+constexpr int kStageY = ((2 * kMaxHalo + 1) * 128 + 255) / 256;
+constexpr int kStageZ = ((2 * kMaxHalo + 1) * 256 + 511) / 512;
 __device__ __forceinline__ int inf16(uint16_t v) { return v == 0xFFFF ? kBig : (int)v; }
 
 // x pass: one wave per dense block, lane = (y, z) line of the block.  The
@@ -309,11 +320,21 @@ __global__ __launch_bounds__(256) void k_edt_x(const JobList<NJ> jl, const uint6
         const JobInfo d = pv.info(pv.template job<&JobInfo::od>(g));
         int bx, by, bz;
         dom_coords(d, g - d.od, bx, by, bz);
-        uint64_t lo = 0, hi = 0;
-        for (int i = 0; i < 2 * HB + 1; ++i) {
+        // the site words of the 2 HB + 1 blocks along x, read together
+        // (slots past the halo or outside the domain read this block's word
+        // and drop it)
+        uint64_t wv[2 * kMaxHalo + 1];
+#pragma unroll
+        for (int i = 0; i < 2 * kMaxHalo + 1; ++i) {
             const int nx = bx + i - HB;
-            if (nx < 0 || nx >= d.dim[0]) continue;
-            const uint64_t byte = (sites[(g + (i - HB)) * 8 + z] >> (8 * y)) & 0xFFull;
+            const bool ok = i < 2 * HB + 1 && nx >= 0 && nx < d.dim[0];
+            const uint64_t v = sites[(ok ? g + (i - HB) : g) * 8 + z];
+            wv[i] = ok ? v : 0ull;
+        }
+        uint64_t lo = 0, hi = 0;
+#pragma unroll
+        for (int i = 0; i < 2 * kMaxHalo + 1; ++i) {
+            const uint64_t byte = (wv[i] >> (8 * y)) & 0xFFull;
             const int pos = 8 * i;
             if (pos < 64) lo |= byte << pos;
             else hi |= byte << (pos - 64);
@@ -348,12 +369,20 @@ __global__ __launch_bounds__(256) void k_edt_y_vox(const JobList<NJ> jl, const u
         const JobInfo d = pv.info(pv.template job<&JobInfo::od>(g));
         int bx, by, bz;
         dom_coords(d, g - d.od, bx, by, bz);
-        for (int e = tid; e < nb * 128; e += blockDim.x) {
-            const int i = e >> 7, w = e & 127;
+        // stage the column: every read issued before the first LDS write
+        // (entries outside the domain read this block's word and drop it)
+        uint32_t sv[kStageY];
+#pragma unroll
+        for (int q = 0; q < kStageY; ++q) {
+            const int e = tid + 256 * q, i = e >> 7, w = e & 127;
             const int ny = by + i - HB;
-            colw[e] = (ny >= 0 && ny < d.dim[1]) ? ((const uint32_t *)(g1 + (g + (int64_t)(i - HB) * d.dim[0]) * 512))[w]
-                                                 : 0xFFFFFFFFu;
+            const bool ok = e < nb * 128 && ny >= 0 && ny < d.dim[1];
+            sv[q] = ((const uint32_t *)(g1 + (g + (ok ? (int64_t)(i - HB) * d.dim[0] : 0)) * 512))[ok ? w : 0];
+            sv[q] = ok ? sv[q] : 0xFFFFFFFFu;
         }
+#pragma unroll
+        for (int q = 0; q < kStageY; ++q)
+            if (tid + 256 * q < nb * 128) colw[tid + 256 * q] = sv[q];
         __syncthreads();
         auto at = [&](int yy, int zz) { return col[(yy >> 3) * 512 + x + 8 * (yy & 7) + 64 * zz]; };
         int b0 = sq8(at(Y, z)), b1 = sq8(at(Y, z + 4));
@@ -410,13 +439,20 @@ __global__ __launch_bounds__(512) void k_edt_z_vox(const JobList<NJ> jl, const u
         bx -= d.lo[0]; by -= d.lo[1]; bz -= d.lo[2];
         const int64_t g = d.od + dom_index(d, bx, by, bz);
         const int64_t stride_z = (int64_t)d.dim[0] * d.dim[1];
-        for (int e = tid; e < nb * 256; e += 512) {
-            const int i = e >> 8, q = e & 255;
+        // stage the column as in the y pass
+        uint32_t sv[kStageZ];
+#pragma unroll
+        for (int r = 0; r < kStageZ; ++r) {
+            const int e = tid + 512 * r, i = e >> 8, q = e & 255;
             const int nz = bz + i - HB;
-            colw[e] = (nz >= 0 && nz < d.dim[2]) ? ((const uint32_t *)(g2 + (g + (int64_t)(i - HB) * stride_z) * 512))[q]
-                                                 : 0xFFFFFFFFu;
+            const bool ok = e < nb * 256 && nz >= 0 && nz < d.dim[2];
+            sv[r] = ((const uint32_t *)(g2 + (g + (ok ? (int64_t)(i - HB) * stride_z : 0)) * 512))[ok ? q : 0];
+            sv[r] = ok ? sv[r] : 0xFFFFFFFFu;
         }
         const float seed = job.phi[j * 512 + tid];  // from k_page_sites
+#pragma unroll
+        for (int r = 0; r < kStageZ; ++r)
+            if (tid + 512 * r < nb * 256) colw[tid + 512 * r] = sv[r];
         __syncthreads();
         // an unobserved (NaN) or in-band (D) seed is already the result
         if (__builtin_isinf(seed)) {

@@ -36,29 +36,52 @@ template <typename S> __device__ __forceinline__ void st(S *p, float v);
 template <> __device__ __forceinline__ void st<float>(float *p, float v) { *p = v; }
 template <> __device__ __forceinline__ void st<__half>(__half *p, float v) { *p = __float2half_rn(v); }
 
-// Validity of voxel (ix, iy, iz) under the frame's projection, its signed
-// distance (depth minus voxel depth) and the observation weight (1, or
-// 1 / d^2 for the pixel's depth d).
-__device__ __forceinline__ bool proj_valid(const FrameArgs &f, float vs, float tau, float maxr, int ix,
-                                           int iy, int iz, float &sdf, float &w)
+// Validity of the 8 voxels (ix, iy, iz0 + z), z = 0..7, of one lane under
+// the frame's projection: the voxel centre lies in front of the camera, its
+// nearest pixel is inside the image, the pixel's depth d is in (0, max
+// range], and the signed distance sdf = d - (voxel depth) is at least -tau.
+// Sets sdf and the observation weight w (1, or 1 / d^2) of each valid voxel
+// and returns the mask of valid voxels.  The steps run in three passes (the
+// pixel of every voxel, the 8 depth reads, the tests) so that the reads are
+// in flight together; the arithmetic of each voxel is unchanged.
+__device__ __forceinline__ uint32_t proj_column(const FrameArgs &f, float vs, float tau, float maxr, int ix, int iy,
+                                                int iz0, float sdf[8], float w[8])
 {
     const float cx = ((float)ix + 0.5f) * vs;
     const float cy = ((float)iy + 0.5f) * vs;
-    const float cz = ((float)iz + 0.5f) * vs;
-    const float px = ((f.R[0] * cx + f.R[1] * cy) + f.R[2] * cz) + f.t[0];
-    const float py = ((f.R[3] * cx + f.R[4] * cy) + f.R[5] * cz) + f.t[1];
-    const float pz = ((f.R[6] * cx + f.R[7] * cy) + f.R[8] * cz) + f.t[2];
-    if (!(pz > 0.0f)) return false;
-    const float u = ((f.K[0] * px) / pz) + f.K[2];
-    const float v = ((f.K[1] * py) / pz) + f.K[3];
-    const float uf = floorf(u + 0.5f);
-    const float vf = floorf(v + 0.5f);
-    if (!(uf >= 0.0f && uf < (float)f.W && vf >= 0.0f && vf < (float)f.H)) return false;
-    const float d = f.depth[(int64_t)(int)vf * f.W + (int)uf];
-    if (!(d > 0.0f && d <= maxr)) return false;
-    sdf = d - pz;
-    w = f.weight_mode == COVOX_WEIGHT_INV_DEPTH2 ? 1.0f / (d * d) : 1.0f;
-    return sdf >= -tau;
+    float pzv[8];
+    int64_t pix[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        const float cz = ((float)(iz0 + z) + 0.5f) * vs;
+        const float px = ((f.R[0] * cx + f.R[1] * cy) + f.R[2] * cz) + f.t[0];
+        const float py = ((f.R[3] * cx + f.R[4] * cy) + f.R[5] * cz) + f.t[1];
+        const float pz = ((f.R[6] * cx + f.R[7] * cy) + f.R[8] * cz) + f.t[2];
+        pzv[z] = pz;
+        pix[z] = -1;
+        if (pz > 0.0f) {
+            const float u = ((f.K[0] * px) / pz) + f.K[2];
+            const float v = ((f.K[1] * py) / pz) + f.K[3];
+            const float uf = floorf(u + 0.5f);
+            const float vf = floorf(v + 0.5f);
+            if (uf >= 0.0f && uf < (float)f.W && vf >= 0.0f && vf < (float)f.H)
+                pix[z] = (int64_t)(int)vf * f.W + (int)uf;
+        }
+    }
+    float d[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) d[z] = f.depth[pix[z] >= 0 ? pix[z] : 0];  // pixel 0 stands in, unused
+    uint32_t okm = 0;
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        sdf[z] = 0.0f;
+        w[z] = 0.0f;
+        if (pix[z] < 0 || !(d[z] > 0.0f && d[z] <= maxr)) continue;
+        sdf[z] = d[z] - pzv[z];
+        w[z] = f.weight_mode == COVOX_WEIGHT_INV_DEPTH2 ? 1.0f / (d[z] * d[z]) : 1.0f;
+        okm |= (uint32_t)(sdf[z] >= -tau) << z;
+    }
+    return okm;
 }
 
 // False only if no voxel centre of block (bx, by, bz) can pass the validity
@@ -92,23 +115,36 @@ template <typename S>
 __device__ __forceinline__ int update_column(S *Db, S *Wb, const float sdf[8], const float wt[8], uint32_t okm, float tau,
                                              bool is_new)
 {
+    // The whole column is read, updated in registers and written back
+    // (unchanged voxels with their own value, a new block's with zero), in
+    // straight-line code: conditional reads or writes would make the
+    // compiler wait for each one in turn.
+    float Dp[8], Wp[8];
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        Dp[z] = ld(Db + 64 * z);
+        Wp[z] = ld(Wb + 64 * z);
+    }
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        Dp[z] = is_new ? 0.0f : Dp[z];
+        Wp[z] = is_new ? 0.0f : Wp[z];
+    }
     int n_ok = 0;
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
         const bool ok = (okm >> z) & 1u;
         n_ok += __popcll(__ballot(ok));
-        if (ok) {
-            const float Dv = is_new ? 0.0f : ld(Db + 64 * z);
-            const float Wv = is_new ? 0.0f : ld(Wb + 64 * z);
-            const float tr = fminf(sdf[z], tau);
-            const float Wn = Wv + wt[z];
-            const float Dn = ((Dv * Wv) + (tr * wt[z])) / Wn;
-            st(Db + 64 * z, Dn);
-            st(Wb + 64 * z, Wn);
-        } else if (is_new) {
-            st(Db + 64 * z, 0.0f);
-            st(Wb + 64 * z, 0.0f);
-        }
+        const float tr = fminf(sdf[z], tau);
+        const float Wn = Wp[z] + wt[z];
+        const float Dn = ((Dp[z] * Wp[z]) + (tr * wt[z])) / Wn;
+        Dp[z] = ok ? Dn : Dp[z];
+        Wp[z] = ok ? Wn : Wp[z];
+    }
+#pragma unroll
+    for (int z = 0; z < 8; ++z) {
+        st(Db + 64 * z, Dp[z]);
+        st(Wb + 64 * z, Wp[z]);
     }
     return n_ok;
 }
@@ -133,18 +169,20 @@ __global__ __launch_bounds__(256) void k_probe(FrameArgs f, float vs, float tau,
         if (lane == 0) cand[j] = 0;
         return;
     }
+    // the home slot of the block's key is read before the validity test, so
+    // that its latency overlaps the depth reads
+    // (every lane reads the same slot: one request, no branch)
+    const uint64_t key = pack_key(bx, by, bz);
+    const HashProbe hp = hash_first(tkeys, tvals, tmask, key);
     const int ix = 8 * bx + (lane & 7);
     const int iy = 8 * by + (lane >> 3);
     float sdf[8], wt[8];
-    uint32_t okm = 0;
-#pragma unroll
-    for (int z = 0; z < 8; ++z)
-        okm |= (uint32_t)proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf[z], wt[z]) << z;
+    const uint32_t okm = proj_column(f, vs, tau, maxr, ix, iy, 8 * bz, sdf, wt);
     const uint64_t m = __ballot(okm != 0);
     uint32_t out = 0;
     if (m) {
         int64_t idx = -1;
-        if (lane == 0) idx = hash_find(tkeys, tvals, tmask, pack_key(bx, by, bz));
+        if (lane == 0) idx = hash_resolve(hp, tkeys, tvals, tmask, key);
         idx = __shfl(idx, 0, 64);
         out = idx >= 0 ? (uint32_t)idx + 1u : kNew;
         if (FUSED && idx >= 0) {
@@ -297,10 +335,7 @@ __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float 
         const int ix = 8 * bx + (lane & 7);
         const int iy = 8 * by + (lane >> 3);
         float sdf[8], wt[8];
-        uint32_t okm = 0;
-#pragma unroll
-        for (int z = 0; z < 8; ++z)
-            okm |= (uint32_t)proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf[z], wt[z]) << z;
+        const uint32_t okm = proj_column(f, vs, tau, maxr, ix, iy, 8 * bz, sdf, wt);
         const int n_ok = update_column(D + idx * 512 + lane, W + idx * 512 + lane, sdf, wt, okm, tau, is_new);
         if (lane == 0) atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
     }
@@ -335,12 +370,8 @@ __global__ __launch_bounds__(256) void k_probe_batch(const FrameArgs *__restrict
     }
     const int ix = 8 * bx + (lane & 7);
     const int iy = 8 * by + (lane >> 3);
-    bool any = false;
-#pragma unroll
-    for (int z = 0; z < 8; ++z) {
-        float sdf, w;
-        any |= proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf, w);
-    }
+    float sdf[8], w[8];
+    const bool any = proj_column(f, vs, tau, maxr, ix, iy, 8 * bz, sdf, w) != 0;
     const uint64_t m = __ballot(any);
     if (lane == 0) {
         uint32_t out = 0;
@@ -533,15 +564,16 @@ __global__ __launch_bounds__(256) void k_integrate_batch(const FrameArgs *__rest
             if (bx < f.blo[0] || bx >= f.blo[0] + f.bdim[0] || by < f.blo[1] || by >= f.blo[1] + f.bdim[1] ||
                 bz < f.blo[2] || bz >= f.blo[2] + f.bdim[2] || !block_may_be_visible(f, vs, bx, by, bz))
                 continue;  // no valid voxel in this frame
+            float sdf[8], w[8];
+            const uint32_t okm = proj_column(f, vs, tau, maxr, ix, iy, 8 * bz, sdf, w);
 #pragma unroll
             for (int z = 0; z < 8; ++z) {
-                float sdf, w;
-                const bool ok = proj_valid(f, vs, tau, maxr, ix, iy, 8 * bz + z, sdf, w);
+                const bool ok = (okm >> z) & 1u;
                 n_ok += __popcll(__ballot(ok));
                 if (ok) {
-                    const float tr = fminf(sdf, tau);
-                    const float Wn = wv[z] + w;
-                    const float Dn = ((dv[z] * wv[z]) + (tr * w)) / Wn;
+                    const float tr = fminf(sdf[z], tau);
+                    const float Wn = wv[z] + w[z];
+                    const float Dn = ((dv[z] * wv[z]) + (tr * w[z])) / Wn;
                     dv[z] = stored<S>(Dn);
                     wv[z] = stored<S>(Wn);
                 }
