@@ -423,12 +423,14 @@ void covox_destroy(covox_ctx *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     auto &subs = submaps_of(ctx);
     for (covox_submap *s : std::vector<covox_submap *>(subs)) covox_submap_destroy(s);
-    for (void *ptr : {(void *)ctx->cand, (void *)ctx->t_key, (void *)ctx->t_idx, (void *)ctx->sites, (void *)ctx->g1,
+    for (void *ptr : {(void *)ctx->cand, (void *)ctx->t_key, (void *)ctx->t_idx, (void *)ctx->sites[0], (void *)ctx->g1,
                       (void *)ctx->g2, (void *)ctx->cnt, (void *)ctx->psum, ctx->prob_dev, ctx->res_dev, ctx->sum_dev,
                       (void *)ctx->net_in, (void *)ctx->net_out, (void *)ctx->train_y, (void *)ctx->loss_hist,
                       (void *)ctx->frames_dev, (void *)ctx->blist, (void *)ctx->fkeys, (void *)ctx->ffirst,
                       (void *)ctx->fcount, (void *)ctx->ray_acc, (void *)ctx->wf_nk, (void *)ctx->wf_np,
-                      (void *)ctx->wf_sites, (void *)ctx->wf_flag, (void *)ctx->wf_list, (void *)ctx->wf_cnt})
+                      (void *)ctx->wf_sites, (void *)ctx->wf_flag, (void *)ctx->wf_list, (void *)ctx->wf_cnt,
+                      (void *)ctx->sites[1], (void *)ctx->seeds[0], (void *)ctx->seeds[1], (void *)ctx->snap[0],
+                      (void *)ctx->snap[1]})
         if (ptr) (void)hipFree(ptr);
     for (void *p : ctx->deferred) (void)hipFree(p);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -436,7 +438,7 @@ void covox_destroy(covox_ctx *ctx)
         (void)hipStreamSynchronize(ctx->esdf_stream);
         (void)hipStreamDestroy(ctx->esdf_stream);
     }
-    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_integrated, ctx->ev_paged, ctx->ev_join})
+    for (hipEvent_t e : {ctx->ev_fork, ctx->ev_paged, ctx->ev_join, ctx->ev_free[0], ctx->ev_free[1]})
         if (e) (void)hipEventDestroy(e);
     if (ctx->wf_pin) (void)hipHostFree(ctx->wf_pin);
     for (int k = 0; k < 2; ++k) {
@@ -592,7 +594,7 @@ int ensure_pipeline(covox_ctx *ctx)
 {
     if (ctx->esdf_stream) return COVOX_OK;
     int rc;
-    for (hipEvent_t *e : {&ctx->ev_fork, &ctx->ev_integrated, &ctx->ev_paged, &ctx->ev_join})
+    for (hipEvent_t *e : {&ctx->ev_fork, &ctx->ev_paged, &ctx->ev_join, &ctx->ev_free[0], &ctx->ev_free[1]})
         if (!*e && (rc = hip_check(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming), "pipeline event")))
             return rc;
     return hip_check(ctx, hipStreamCreateWithFlags(&ctx->esdf_stream, hipStreamNonBlocking), "esdf stream");
@@ -607,10 +609,12 @@ int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev,
     capture_touch(ctx, s, 1);
     // frames between ESDF updates go through the batched integration
     const int32_t step = esdf_every > 0 ? esdf_every : F;
-    // With an exact ESDF update after every chunk, the update of chunk k runs
-    // on a second stream while chunk k + 1 is integrated on the context
-    // stream: only the update's first kernel reads the TSDF, and the next
-    // integration waits for that kernel alone.  The results are those of the
+    // With an exact ESDF update after every chunk, the page kernel of each
+    // update (the last ESDF kernel that reads the TSDF) runs right after the
+    // chunk's integration on the context stream, and its EDT passes run on a
+    // second stream while the next chunk is integrated.  The page kernels
+    // alternate between two scratch slots, so that the one of chunk k + 1
+    // does not wait for the passes of chunk k.  The results are those of the
     // calls in sequence.
     const bool pipe = esdf_every > 0 && F > step && ctx->p.esdf_mode == COVOX_ESDF_EXACT &&
                       (ctx->esdf_stream || !ctx->capturing);
@@ -626,31 +630,40 @@ int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev,
     }
     int rc = ensure_pipeline(ctx);
     if (rc) return rc;
-    hipStream_t main = ctx->stream, aux = ctx->esdf_stream;
-    if ((rc = hip_check(ctx, hipEventRecord(ctx->ev_fork, main), "fork")) ||
+    hipStream_t base = ctx->stream, aux = ctx->esdf_stream;
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->ev_fork, base), "fork")) ||
         (rc = hip_check(ctx, hipStreamWaitEvent(aux, ctx->ev_fork, 0), "fork wait")))
         return rc;
     int rc_loop = COVOX_OK;
-    for (int32_t f0 = 0; f0 < F && !rc_loop; f0 += step) {
+    bool in_flight[2] = {false, false};  // an update's passes were enqueued on the slot
+    bool prev_read_page = false;         // the last update's passes read the page
+    int k = 0;
+    for (int32_t f0 = 0; f0 < F && !rc_loop; f0 += step, ++k) {
         const int32_t n = std::min(step, F - f0);
         rc_loop = integrate_frames(ctx, s, depths_dev + (size_t)f0 * H * W, n, H, W, K, T_world_cam + 16 * f0);
         if (rc_loop) break;
-        if ((rc_loop = hip_check(ctx, hipEventRecord(ctx->ev_integrated, main), "integrated")) ||
-            (rc_loop = hip_check(ctx, hipStreamWaitEvent(aux, ctx->ev_integrated, 0), "integrated wait")))
+        const int slot = k & 1;
+        // the slot is free once the passes of the update two chunks back are
+        // done; the page, once the last update's passes are, if they read it
+        if (in_flight[slot] && (rc_loop = hip_check(ctx, hipStreamWaitEvent(base, ctx->ev_free[slot], 0), "slot wait")))
             break;
-        ctx->stream = aux;
-        ctx->esdf_page_event = ctx->ev_paged;
-        ctx->esdf_page_recorded = false;
+        if (prev_read_page && in_flight[1 - slot] &&
+            (rc_loop = hip_check(ctx, hipStreamWaitEvent(base, ctx->ev_free[1 - slot], 0), "page wait")))
+            break;
+        ctx->esdf_slot = slot;
+        ctx->esdf_edt_stream = aux;
+        ctx->esdf_used_page = false;
         rc_loop = update_esdf(ctx, s);
-        if (!rc_loop && !ctx->esdf_page_recorded)  // no page kernel ran: order after the whole update
-            rc_loop = hip_check(ctx, hipEventRecord(ctx->ev_paged, aux), "paged");
-        ctx->esdf_page_event = nullptr;
-        ctx->stream = main;
-        if (!rc_loop) rc_loop = hip_check(ctx, hipStreamWaitEvent(main, ctx->ev_paged, 0), "paged wait");
+        ctx->esdf_edt_stream = nullptr;
+        ctx->esdf_slot = 0;
+        if (rc_loop) break;
+        prev_read_page = ctx->esdf_used_page;
+        if ((rc_loop = hip_check(ctx, hipEventRecord(ctx->ev_free[slot], aux), "slot free"))) break;
+        in_flight[slot] = true;
     }
     // join, after an error too: later work on the context stream follows all of it
     if ((rc = hip_check(ctx, hipEventRecord(ctx->ev_join, aux), "join")) ||
-        (rc = hip_check(ctx, hipStreamWaitEvent(main, ctx->ev_join, 0), "join wait"))) {
+        (rc = hip_check(ctx, hipStreamWaitEvent(base, ctx->ev_join, 0), "join wait"))) {
         if (!rc_loop) rc_loop = rc;
     }
     return rc_loop;

@@ -139,8 +139,16 @@ struct SubmapMeta {
     unsigned long long n_updates;  // voxel updates since creation / reset
     int64_t batch_n0;       // last frame batch: n_blocks before it
     int32_t batch_frames;   // and its frames committed (a capacity failure stops the batch)
-    int32_t dom_nblocks;    // allocated blocks when the page was built (the EDT passes' domain)
+    int32_t dom_nblocks;    // allocated blocks when the page was built
 };
+
+// The domain one ESDF update works on (block box and allocated block
+// count), stored by the page kernel and read by the passes after it.
+struct EsdfSnap {
+    int32_t lo[3], dim[3];
+    int32_t nb, pad;
+};
+constexpr int kEsdfMaxJobs = 32;  // submaps per ESDF launch
 
 // Per-frame projection parameters (kernel argument).
 struct FrameArgs {
@@ -272,8 +280,15 @@ struct covox_ctx {
     int64_t *wf_pin = nullptr;  // pinned copy of wf_cnt
     int64_t wf_last_block_rounds = 0;
     // EDT scratch over a dense block box
-    uint64_t *sites = nullptr;  // 8 words per dense block
-    int64_t sites_cap = 0;      // dense blocks
+    // ESDF scratch written by the page kernel, in two slots: a pipelined
+    // map_sequence builds the page of frame k + 1 while the passes of frame
+    // k still read slot k mod 2
+    uint64_t *sites[2] = {nullptr, nullptr};  // 8 words per dense block
+    int64_t sites_cap[2] = {0, 0};            // dense blocks
+    float *seeds[2] = {nullptr, nullptr};     // phi seed per voxel of the dense blocks
+    int64_t seeds_cap[2] = {0, 0};            // dense blocks
+    covox::EsdfSnap *snap[2] = {nullptr, nullptr};  // kEsdfMaxJobs per slot
+    int esdf_slot = 0;
     uint8_t *g1 = nullptr;      // 512 per dense block
     int64_t g1_cap = 0;
     uint16_t *g2 = nullptr;     // 512 per dense block
@@ -316,14 +331,16 @@ struct covox_ctx {
     // pinned host staging for small copies
     void *host_pin = nullptr;
     size_t host_pin_cap = 0;
-    // map_sequence: the ESDF of one frame chunk runs on esdf_stream while the
-    // next chunk integrates on the context stream.  esdf_page_event, when
-    // set, is recorded right after the page / site / seed kernel (the last
-    // ESDF kernel that reads the TSDF).
+    // map_sequence: the page kernel of each update runs on the context
+    // stream right after the integration it reads; the EDT passes run on
+    // esdf_stream (set as esdf_edt_stream for the duration), after
+    // ev_paged, while the next chunk integrates.  ev_free[slot] follows the
+    // passes of the last update that used the slot.
     hipStream_t esdf_stream = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_integrated = nullptr, ev_paged = nullptr, ev_join = nullptr;
-    hipEvent_t esdf_page_event = nullptr;
-    bool esdf_page_recorded = false;
+    hipStream_t esdf_edt_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_paged = nullptr, ev_join = nullptr;
+    hipEvent_t ev_free[2] = {nullptr, nullptr};
+    bool esdf_used_page = false;  // the last update's passes read the page (z envelopes)
     // graph capture (on a stream of the library: the legacy default stream
     // cannot be captured)
     hipStream_t cap_stream = nullptr;

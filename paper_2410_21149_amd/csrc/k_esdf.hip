@@ -32,7 +32,7 @@ namespace {
 
 constexpr int kBig = 1 << 24;
 constexpr int kWin = 256;     // envelope window positions (u8 stack entries)
-constexpr int kMaxJobs = 32;  // submaps per launch (the job list is a kernel argument)
+constexpr int kMaxJobs = kEsdfMaxJobs;  // submaps per launch (the job list is a kernel argument)
 
 template <typename S> __device__ __forceinline__ float ldv(const S *p);
 template <> __device__ __forceinline__ float ldv<float>(const float *p) { return *p; }
@@ -41,6 +41,7 @@ template <> __device__ __forceinline__ float ldv<__half>(const __half *p) { retu
 // One submap of an ESDF launch.
 struct EsdfJob {
     SubmapMeta *meta;
+    EsdfSnap *snap;     // the update's domain (written by the page kernel)
     const uint64_t *keys;
     const uint64_t *tkeys;
     const uint32_t *tvals;
@@ -49,6 +50,7 @@ struct EsdfJob {
     const void *W;
     float *phi;
     int32_t *page;
+    float *seeds;       // phi seed per voxel, by dense block index of the launch
 };
 
 template <int NJ>
@@ -75,26 +77,27 @@ struct Plan {
 
 __device__ __forceinline__ int64_t nsegments(int64_t L, int S) { return L > 0 ? (L + S - 1) / S : 0; }
 
-// Fills the job info of one submap from its device bookkeeping: the live
-// block count and block box (SNAP = false: the page kernel, which runs while
-// nothing else changes the submap), or the snapshot the page kernel stored
-// (SNAP = true: the EDT passes, which may run while the next frames are
-// integrated into the same submap).
+// Fills the job info of one submap: from the live block count and block box
+// (SNAP = false: the page kernel, which runs in order with the integration),
+// or from the snapshot the page kernel stored (SNAP = true: the EDT passes,
+// which may run while the next frames are integrated into the same submap).
 template <bool SNAP>
-__device__ __forceinline__ void job_info(const SubmapMeta *m, int C, JobInfo &ji, int64_t &cy, int64_t &cz)
+__device__ __forceinline__ void job_info(const EsdfJob &job, int C, JobInfo &ji, int64_t &cy, int64_t &cz)
 {
+    const SubmapMeta *m = job.meta;
+    const EsdfSnap *sn = job.snap;
     for (int a = 0; a < 3; ++a) { ji.lo[a] = 0; ji.dim[a] = 0; }
     ji.nd = 0;
     ji.nb = 0;
     cy = 0;
     cz = 0;
-    const int64_t nb = SNAP ? (int64_t)m->dom_nblocks : m->n_blocks;
+    const int64_t nb = SNAP ? (int64_t)sn->nb : m->n_blocks;
     if (nb <= 0) return;
     ji.nb = nb;
     ji.nd = 1;
     for (int a = 0; a < 3; ++a) {
-        ji.lo[a] = SNAP ? m->dom_min[a] : m->bmin[a];
-        ji.dim[a] = SNAP ? m->dom_dim[a] : m->bmax[a] - m->bmin[a] + 1;
+        ji.lo[a] = SNAP ? sn->lo[a] : m->bmin[a];
+        ji.dim[a] = SNAP ? sn->dim[a] : m->bmax[a] - m->bmin[a] + 1;
         ji.nd *= ji.dim[a];
     }
     const int S = kWin - 2 * C;
@@ -114,7 +117,7 @@ __device__ void make_plan(const JobList<NJ> &jl, int C, Plan &pl)
         int64_t cy = 0, cz = 0;
         for (int a = 0; a < 3; ++a) { ji.lo[a] = 0; ji.dim[a] = 0; }
         ji.nd = ji.nb = 0;
-        if (lane < jl.n) job_info<SNAP>(jl.j[lane].meta, C, ji, cy, cz);
+        if (lane < jl.n) job_info<SNAP>(jl.j[lane], C, ji, cy, cz);
         const int64_t v[4] = {ji.nd, ji.nb, cy, cz};
         int64_t incl[4];
 #pragma unroll
@@ -168,7 +171,7 @@ struct PlanView {
     {
         if constexpr (NJ == 1) {
             int64_t cy, cz;
-            job_info<SNAP>(jl.j[0].meta, C, one, cy, cz);
+            job_info<SNAP>(jl.j[0], C, one, cy, cz);
             one.od = one.ob = one.oy = one.oz = 0;
             t[0] = one.nd;
             t[1] = one.nb;
@@ -214,8 +217,8 @@ __device__ __forceinline__ int64_t dom_index(const JobInfo &d, int x, int y, int
 // and block count) that the later passes work on.  With SEEDS, also the phi
 // seed of every voxel of an allocated block: NaN when unobserved, D inside
 // the band, and otherwise an infinity with the sign of D.  The EDT passes then
-// never read the TSDF, so that the next frames may be integrated while they
-// run.
+// never read the TSDF or the submap's bookkeeping, so that the next frames
+// may be integrated while they run.
 template <typename S, int NJ, bool SEEDS>
 __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C, float vs, float tau,
                                                     uint64_t *__restrict__ sites)
@@ -227,8 +230,12 @@ __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C,
     if (blockIdx.x == 0 && (int)threadIdx.x < jl.n) {
         const JobInfo d = pv.info(threadIdx.x);
         SubmapMeta *m = jl.j[threadIdx.x].meta;
-        for (int a = 0; a < 3; ++a) { m->dom_min[a] = d.lo[a]; m->dom_dim[a] = d.dim[a]; }
-        m->dom_nblocks = (int32_t)d.nb;
+        EsdfSnap *sn = jl.j[threadIdx.x].snap;
+        for (int a = 0; a < 3; ++a) {
+            m->dom_min[a] = sn->lo[a] = d.lo[a];
+            m->dom_dim[a] = sn->dim[a] = d.dim[a];
+        }
+        m->dom_nblocks = sn->nb = (int32_t)d.nb;
         m->dom_valid = 1;
     }
     for (int64_t g = (int64_t)blockIdx.x * 4 + wid; g < pv.t[0]; g += (int64_t)gridDim.x * 4) {
@@ -259,7 +266,7 @@ __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C,
                 const uint64_t m = __ballot(Wv > 0.0f && fabsf(Dv) <= vs);
                 if (lane == k) w = m;
                 if constexpr (SEEDS)
-                    job.phi[idx * 512 + lane + 64 * k] =
+                    job.seeds[g * 512 + lane + 64 * k] =
                         !(Wv > 0.0f) ? __builtin_nanf("")
                                      : (fabsf(Dv) < tau ? Dv : (Dv > 0.0f ? __builtin_inff() : -__builtin_inff()));
             }
@@ -449,12 +456,13 @@ __global__ __launch_bounds__(512) void k_edt_z_vox(const JobList<NJ> jl, const u
             sv[r] = ((const uint32_t *)(g2 + (g + (ok ? (int64_t)(i - HB) * stride_z : 0)) * 512))[ok ? q : 0];
             sv[r] = ok ? sv[r] : 0xFFFFFFFFu;
         }
-        const float seed = job.phi[j * 512 + tid];  // from k_page_sites
+        const float seed = job.seeds[g * 512 + tid];  // from k_page_sites
 #pragma unroll
         for (int r = 0; r < kStageZ; ++r)
             if (tid + 512 * r < nb * 256) colw[tid + 512 * r] = sv[r];
         __syncthreads();
-        // an unobserved (NaN) or in-band (D) seed is already the result
+        // an unobserved (NaN) or in-band (D) seed is the result
+        float out = seed;
         if (__builtin_isinf(seed)) {
             const int base = tid & 63;
             auto at = [&](int zz) { return col[(zz >> 3) * 512 + base + 64 * (zz & 7)]; };
@@ -467,8 +475,9 @@ __global__ __launch_bounds__(512) void k_edt_z_vox(const JobList<NJ> jl, const u
                     if (e <= R) best = min(best, min(inf16(at(Z - e)), inf16(at(Z + e))) + e * e);
                 }
             }
-            job.phi[j * 512 + tid] = phi_value(seed, best, R2, vs, dmax);
+            out = phi_value(seed, best, R2, vs, dmax);
         }
+        job.phi[j * 512 + tid] = out;
         __syncthreads();
     }
 }
@@ -607,13 +616,17 @@ __global__ __launch_bounds__(64) void k_edt_z_env(const JobList<NJ> jl, const ui
         for (int zb = z0; zb < z1; zb += 8) {
             const int64_t idx = job.page[dom_index(d, bx, by, zb / 8)];
             if (idx < 0) continue;
+            const float *Sb = job.seeds + (d.od + dom_index(d, bx, by, zb / 8)) * 512 + lane;
             float *Pb = job.phi + idx * 512 + lane;
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
-                const float seed = Pb[64 * t];  // from k_page_sites
-                if (!__builtin_isinf(seed)) continue;  // unobserved or in the band: the seed stays
-                const int best = e.k >= 0 ? walk_at(wk, e, stk, 64, lane, zb + t - w0, getf) : kBig;
-                Pb[64 * t] = phi_value(seed, best, R2, vs, dmax);
+                const float seed = Sb[64 * t];  // from k_page_sites
+                float out = seed;  // unobserved or in the band
+                if (__builtin_isinf(seed)) {
+                    const int best = e.k >= 0 ? walk_at(wk, e, stk, 64, lane, zb + t - w0, getf) : kBig;
+                    out = phi_value(seed, best, R2, vs, dmax);
+                }
+                Pb[64 * t] = out;
             }
         }
         wave_sync();
@@ -649,14 +662,15 @@ int64_t bound_cols(const covox_submap *s, int a, int b, int HB)
 }
 
 template <int NJ>
-JobList<NJ> make_jobs(covox_submap *const *subs, int n)
+JobList<NJ> make_jobs(covox_submap *const *subs, int n, EsdfSnap *snap, float *seeds)
 {
     JobList<NJ> jl;
     memset(&jl, 0, sizeof(jl));
     jl.n = n;
     for (int i = 0; i < n; ++i) {
         covox_submap *s = subs[i];
-        jl.j[i] = EsdfJob{s->meta, s->keys, s->tkeys, s->tvals, (uint64_t)s->tcap - 1, s->D, s->W, s->phi, s->page};
+        jl.j[i] = EsdfJob{s->meta, snap + i, s->keys, s->tkeys, s->tvals, (uint64_t)s->tcap - 1, s->D, s->W,
+                          s->phi, s->page, seeds};
     }
     return jl;
 }
@@ -683,22 +697,47 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
     const int HB = (R + 7) / 8;
     const int C = 8 * HB;
     int rc;
+    // The page kernel runs on the context stream; the passes after it run
+    // on ctx->esdf_edt_stream when a pipelined caller sets one (after
+    // ev_paged, so that the caller may integrate meanwhile), else on the
+    // context stream too.
+    hipStream_t edt_stream = ctx->esdf_edt_stream ? ctx->esdf_edt_stream : ctx->stream;
+    const int slot = ctx->esdf_slot;
     int64_t nd = 0, nb = 0, cy = 0, cz = 0;
+    for (int i = 0; i < n; ++i) {
+        covox_submap *s = subs[i];
+        nd += std::max<int64_t>(bound_blocks(s), 1);
+        nb += std::min(s->nb_upper, s->cap);
+    }
+    chunk_cols(subs, n, HB, cy, cz);
+    // a buffer that grows is freed: the passes of an earlier update on the
+    // other stream may still read it
+    bool grows = ctx->sites_cap[slot] < nd ||
+                 (edt && (ctx->seeds_cap[slot] < nd || ctx->g1_cap < nd || ctx->g2_cap < nd));
+    for (int i = 0; i < n; ++i) grows = grows || subs[i]->page_cap < std::max<int64_t>(bound_blocks(subs[i]), 1);
+    if (grows && edt_stream != ctx->stream && !ctx->capturing &&
+        (rc = hip_check(ctx, hipStreamSynchronize(edt_stream), "esdf stream sync")))
+        return rc;
     for (int i = 0; i < n; ++i) {
         covox_submap *s = subs[i];
         const int64_t b = std::max<int64_t>(bound_blocks(s), 1);
         if ((rc = ensure_buffer(ctx, (void **)&s->page, &s->page_cap, b, sizeof(int32_t), "page"))) return rc;
-        nd += b;
-        nb += std::min(s->nb_upper, s->cap);
     }
-    chunk_cols(subs, n, HB, cy, cz);
-    if ((rc = ensure_buffer(ctx, (void **)&ctx->sites, &ctx->sites_cap, nd, 8 * sizeof(uint64_t), "site masks")))
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->sites[slot], &ctx->sites_cap[slot], nd, 8 * sizeof(uint64_t),
+                            "site masks")))
+        return rc;
+    if (!ctx->snap[slot] && (rc = hip_check(ctx, hipMalloc((void **)&ctx->snap[slot], sizeof(EsdfSnap) * kMaxJobs),
+                                            "esdf snapshot")))
         return rc;
     if (edt) {
+        if ((rc = ensure_buffer(ctx, (void **)&ctx->seeds[slot], &ctx->seeds_cap[slot], nd, 512 * sizeof(float),
+                                "phi seeds")))
+            return rc;
         if ((rc = ensure_buffer(ctx, (void **)&ctx->g1, &ctx->g1_cap, nd, 512, "edt g1"))) return rc;
         if ((rc = ensure_buffer(ctx, (void **)&ctx->g2, &ctx->g2_cap, nd, 1024, "edt g2"))) return rc;
     }
-    const JobList<NJ> jl = make_jobs<NJ>(subs, n);
+    uint64_t *const sites = ctx->sites[slot];
+    const JobList<NJ> jl = make_jobs<NJ>(subs, n, ctx->snap[slot], ctx->seeds[slot]);
     const float vs = (float)p.voxel_size, tau = (float)band_limit(p), dmax = (float)p.d_max;
     const bool h = p.precision == COVOX_FP16;
     {
@@ -706,24 +745,18 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
         const dim3 grid(clamp_grid((nd + 3) / 4));
         if (h && edt)
             hipLaunchKernelGGL((k_page_sites<__half, NJ, true>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               ctx->sites);
+                               sites);
         else if (h)
             hipLaunchKernelGGL((k_page_sites<__half, NJ, false>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               ctx->sites);
+                               sites);
         else if (edt)
             hipLaunchKernelGGL((k_page_sites<float, NJ, true>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               ctx->sites);
+                               sites);
         else
             hipLaunchKernelGGL((k_page_sites<float, NJ, false>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               ctx->sites);
+                               sites);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "page launch"))) return rc;
-    // the rest of the update reads no TSDF state: a pipelined caller may let
-    // the next integration start here
-    if (ctx->esdf_page_event) {
-        if ((rc = hip_check(ctx, hipEventRecord(ctx->esdf_page_event, ctx->stream), "page event"))) return rc;
-        ctx->esdf_page_recorded = true;
-    }
     for (int i = 0; i < n; ++i) subs[i]->page_version = subs[i]->version;
     if (!edt) return COVOX_OK;
     // Pass shape: per-line envelopes when there are enough lines to fill the
@@ -736,9 +769,19 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
         env_y = (force & 1) != 0;
         env_z = (force & 2) != 0;
     }
+    ctx->esdf_used_page = env_z;  // the z envelopes read the page
+    // the passes read nothing the next integration writes: on their own
+    // stream they wait for the page kernel only
+    hipStream_t base = ctx->stream;
+    if (edt_stream != base) {
+        if ((rc = hip_check(ctx, hipEventRecord(ctx->ev_paged, base), "paged")) ||
+            (rc = hip_check(ctx, hipStreamWaitEvent(edt_stream, ctx->ev_paged, 0), "paged wait")))
+            return rc;
+        ctx->stream = edt_stream;  // for the launches and their timing events below
+    }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_X);
-        hipLaunchKernelGGL((k_edt_x<NJ>), dim3(clamp_grid((nd + 3) / 4)), dim3(256), 0, ctx->stream, jl, ctx->sites,
+        hipLaunchKernelGGL((k_edt_x<NJ>), dim3(clamp_grid((nd + 3) / 4)), dim3(256), 0, ctx->stream, jl, sites,
                            ctx->g1, R, HB);
     }
     {
@@ -759,6 +802,7 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
             hipLaunchKernelGGL((k_edt_z_vox<NJ>), dim3(clamp_grid(nb)), dim3(512), 0, ctx->stream, jl, ctx->g2, R, HB,
                                vs, dmax);
     }
+    ctx->stream = base;
     if ((rc = hip_check(ctx, hipGetLastError(), "esdf launch"))) return rc;
     for (int i = 0; i < n; ++i) subs[i]->esdf_version = subs[i]->version;
     return COVOX_OK;

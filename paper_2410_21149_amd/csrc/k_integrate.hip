@@ -238,15 +238,29 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand
     const int64_t C = (n_box + blockDim.x - 1) / blockDim.x;
     const int64_t beg = std::min<int64_t>((int64_t)tid * C, n_box);
     const int64_t end = std::min<int64_t>(beg + C, n_box);
+    // the first kCache entries of the thread's range stay in registers for
+    // the second pass; their reads are issued together
+    constexpr int kCache = 8;
+    uint32_t cv[kCache];
+#pragma unroll
+    for (int q = 0; q < kCache; ++q) cv[q] = beg + q < end ? cand[beg + q] : 0u;
     int64_t nt = 0, nn = 0;
-    for (int64_t j = beg; j < end; ++j) {
+#pragma unroll
+    for (int q = 0; q < kCache; ++q) {
+        nt += cv[q] != 0;
+        nn += cv[q] == kNew;
+    }
+    for (int64_t j = beg + kCache; j < end; ++j) {
         const uint32_t v = cand[j];
         nt += v != 0;
         nn += v == kNew;
     }
-    int64_t tot_t, tot_n;
-    int64_t off_t = block_exclusive_scan(nt, lds, &tot_t);
-    int64_t off_n = block_exclusive_scan(nn, lds, &tot_n);
+    // one scan of both counts (touched in the low, new in the high 32 bits:
+    // each is at most n_box < 2^32, so the fields never carry into each other)
+    int64_t tot;
+    const int64_t off = block_exclusive_scan(nt | (nn << 32), lds, &tot);
+    int64_t off_t = off & 0xFFFFFFFFll, off_n = off >> 32;
+    const int64_t tot_t = tot & 0xFFFFFFFFll, tot_n = tot >> 32;
     const int64_t n0 = meta->n_blocks;
     __syncthreads();  // every thread has read n_blocks before it changes
     const bool pool_full = n0 + tot_n > cap;
@@ -261,9 +275,8 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand
         return;
     }
     int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
-    for (int64_t j = beg; j < end; ++j) {
-        const uint32_t v = cand[j];
-        if (!v) continue;
+    auto emit = [&](int64_t j, uint32_t v) {
+        if (!v) return;
         int bx, by, bz;
         box_block(f, j, bx, by, bz);
         uint32_t idx;
@@ -277,7 +290,11 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand
         t_key[off_t] = pack_key(bx, by, bz);
         t_idx[off_t] = idx;
         ++off_t;
-    }
+    };
+#pragma unroll
+    for (int q = 0; q < kCache; ++q)
+        if (beg + q < end) emit(beg + q, cv[q]);
+    for (int64_t j = beg + kCache; j < end; ++j) emit(j, cand[j]);
     // box of the new blocks: wave reduction, then across waves
     const int lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
 #pragma unroll
