@@ -73,14 +73,14 @@ def algorithmic_bytes(kind, census, s_dw):
             tot += 4 * box[f] + 12 * (census["n_touched"][f])
         elif kind == "integrate":   # init of new blocks, activation (updates are the probe's)
             tot += s_dw * 512 * new[f] + 24 * new[f]
-        elif kind == "esdf_page":   # D, W of every block in, page + site masks out
-            tot += s_dw * 512 * nb[f] + 4 * dense[f] + 64 * dense[f]
+        elif kind == "esdf_page":   # D, W of every block in, page + site masks + phi seeds out
+            tot += s_dw * 512 * nb[f] + 4 * dense[f] + 64 * dense[f] + 4 * 512 * nb[f]
         elif kind == "edt_x":       # site masks in, g1 (1 B / voxel) out
             tot += 64 * dense[f] + 512 * dense[f]
         elif kind == "edt_y":       # g1 in, g2 (2 B / voxel) out
             tot += 512 * dense[f] + 1024 * dense[f]
-        elif kind == "edt_z":       # g2 of the block columns, D and W in, phi out
-            tot += 1024 * nb[f] + s_dw * 512 * nb[f] + 4 * 512 * nb[f]
+        elif kind == "edt_z":       # g2 of the block columns, phi seeds in, phi out
+            tot += 1024 * nb[f] + 4 * 512 * nb[f] + 4 * 512 * nb[f]
     return tot / F
 
 
@@ -100,8 +100,8 @@ def measured_traffic(kind, tuning, census):
     if not table:
         return None
     symbols = {"probe": "k_probe<float, true>", "scan": "k_scan", "integrate": "k_integrate<float, true>",
-               "esdf_page": "k_page_sites<float, 1>", "edt_x": "k_edt_x<1>", "edt_y": "k_edt_y_vox<1>",
-               "edt_z": "k_edt_z_vox<float, 1>"}
+               "esdf_page": "k_page_sites<float, 1, true>", "edt_x": "k_edt_x<1>", "edt_y": "k_edt_y_vox<1, 2>",
+               "edt_z": "k_edt_z_vox<1>"}
     ent = table.get(symbols.get(kind, ""))
     if ent is None:
         return None

@@ -303,10 +303,13 @@ __device__ __forceinline__ int nearest_bit(uint64_t lo, uint64_t hi, int p)
 __device__ __forceinline__ int sq8(uint8_t v) { return v == 255 ? kBig : (int)v * (int)v; }
 
 constexpr int kScanStep = 8;  // offsets per exit test of the windowed y and z passes
-// 32-bit words a lane stages into LDS per block in the y pass (256 lanes,
-// 2 HB + 1 blocks of 128 words) and the z pass (512 lanes, 256 words each)
-constexpr int kStageY = ((2 * kMaxHalo + 1) * 128 + 255) / 256;
+// 32-bit words a lane stages into LDS per block in the z pass (512 lanes,
+// 2 HB + 1 blocks of 256 words)
 constexpr int kStageZ = ((2 * kMaxHalo + 1) * 256 + 511) / 512;
+// Voxels per lane of the windowed y pass, and its grid: one workgroup per
+// dense block up to what the chip holds at once (32 waves per CU).
+constexpr int kYVox = 2;
+constexpr int64_t kYGrid = 256 * 32 / (512 / kYVox / 64);
 __device__ __forceinline__ int inf16(uint16_t v) { return v == 0xFFFF ? kBig : (int)v; }
 
 // x pass: one wave per dense block, lane = (y, z) line of the block.  The
@@ -356,19 +359,23 @@ __global__ __launch_bounds__(256) void k_edt_x(const JobList<NJ> jl, const uint6
     }
 }
 
-// y pass: 256 lanes per block, each lane two voxels (z and z + 4), so that
-// the whole pass of a room-sized domain is resident at once.
-template <int NJ>
-__global__ __launch_bounds__(256) void k_edt_y_vox(const JobList<NJ> jl, const uint8_t *__restrict__ g1,
-                                                   uint16_t *__restrict__ g2, int R, int HB)
+// y pass: 512 / V lanes per block, each lane V voxels (z0, z0 + 8 / V, ...),
+// so that the whole pass of a room-sized domain is resident at once and each
+// lane has V independent scans to overlap.
+template <int NJ, int V>
+__global__ __launch_bounds__(512 / V) void k_edt_y_vox(const JobList<NJ> jl, const uint8_t *__restrict__ g1,
+                                                       uint16_t *__restrict__ g2, int R, int HB)
 {
+    constexpr int T = 512 / V;   // lanes
+    constexpr int ZS = 8 / V;    // z step between a lane's voxels
+    constexpr int kStage = ((2 * kMaxHalo + 1) * 128 + T - 1) / T;  // staged words per lane
     __shared__ Plan lds;
     __shared__ __align__(16) uint32_t colw[(2 * kMaxHalo + 1) * 128];
     PlanView<NJ> pv;
     pv.init(jl, 8 * HB, lds);
     const uint8_t *col = (const uint8_t *)colw;
     const int tid = threadIdx.x;
-    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;  // z in 0..3; the lane also takes z + 4
+    const int x = tid & 7, y = (tid >> 3) & 7, z0 = tid >> 6;  // z0 in 0 .. ZS - 1
     const int nb = 2 * HB + 1;
     const int R2 = R * R;
     const int Y = 8 * HB + y;
@@ -378,37 +385,43 @@ __global__ __launch_bounds__(256) void k_edt_y_vox(const JobList<NJ> jl, const u
         dom_coords(d, g - d.od, bx, by, bz);
         // stage the column: every read issued before the first LDS write
         // (entries outside the domain read this block's word and drop it)
-        uint32_t sv[kStageY];
+        uint32_t sv[kStage];
 #pragma unroll
-        for (int q = 0; q < kStageY; ++q) {
-            const int e = tid + 256 * q, i = e >> 7, w = e & 127;
+        for (int q = 0; q < kStage; ++q) {
+            const int e = tid + T * q, i = e >> 7, w = e & 127;
             const int ny = by + i - HB;
             const bool ok = e < nb * 128 && ny >= 0 && ny < d.dim[1];
             sv[q] = ((const uint32_t *)(g1 + (g + (ok ? (int64_t)(i - HB) * d.dim[0] : 0)) * 512))[ok ? w : 0];
             sv[q] = ok ? sv[q] : 0xFFFFFFFFu;
         }
 #pragma unroll
-        for (int q = 0; q < kStageY; ++q)
-            if (tid + 256 * q < nb * 128) colw[tid + 256 * q] = sv[q];
+        for (int q = 0; q < kStage; ++q)
+            if (tid + T * q < nb * 128) colw[tid + T * q] = sv[q];
         __syncthreads();
         auto at = [&](int yy, int zz) { return col[(yy >> 3) * 512 + x + 8 * (yy & 7) + 64 * zz]; };
-        int b0 = sq8(at(Y, z)), b1 = sq8(at(Y, z + 4));
+        int b[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) b[v] = sq8(at(Y, z0 + ZS * v));
         // outward scan, kScanStep offsets per exit test: the test needs the
         // previous minima, so testing less often keeps more LDS reads in
         // flight; offsets past a voxel's exit cannot lower its minimum
         for (int dd = 1; dd <= R; dd += kScanStep) {
-            if (dd * dd >= max(b0, b1)) break;
+            int bm = b[0];
+#pragma unroll
+            for (int v = 1; v < V; ++v) bm = max(bm, b[v]);
+            if (dd * dd >= bm) break;
 #pragma unroll
             for (int q = 0; q < kScanStep; ++q) {
                 const int e = dd + q;
                 if (e <= R) {
-                    b0 = min(b0, min(sq8(at(Y - e, z)), sq8(at(Y + e, z))) + e * e);
-                    b1 = min(b1, min(sq8(at(Y - e, z + 4)), sq8(at(Y + e, z + 4))) + e * e);
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        b[v] = min(b[v], min(sq8(at(Y - e, z0 + ZS * v)), sq8(at(Y + e, z0 + ZS * v))) + e * e);
                 }
             }
         }
-        g2[g * 512 + tid] = b0 <= R2 ? (uint16_t)b0 : (uint16_t)0xFFFF;
-        g2[g * 512 + tid + 256] = b1 <= R2 ? (uint16_t)b1 : (uint16_t)0xFFFF;
+#pragma unroll
+        for (int v = 0; v < V; ++v) g2[g * 512 + tid + T * v] = b[v] <= R2 ? (uint16_t)b[v] : (uint16_t)0xFFFF;
         __syncthreads();
     }
 }
@@ -790,8 +803,8 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
             hipLaunchKernelGGL((k_edt_y_env<NJ>), dim3(clamp_grid_w(cy)), dim3(64), 0, ctx->stream, jl, ctx->g1, ctx->g2,
                                R, HB);
         else
-            hipLaunchKernelGGL((k_edt_y_vox<NJ>), dim3(clamp_grid(nd)), dim3(256), 0, ctx->stream, jl, ctx->g1,
-                               ctx->g2, R, HB);
+            hipLaunchKernelGGL((k_edt_y_vox<NJ, kYVox>), dim3(std::max<int64_t>(1, std::min<int64_t>(nd, kYGrid))),
+                               dim3(512 / kYVox), 0, ctx->stream, jl, ctx->g1, ctx->g2, R, HB);
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Z);
