@@ -25,10 +25,13 @@
  *     caller memory.
  *
  * Threading and streams: a context is used by one host thread at a time.  All
- * device work of a context is enqueued on the stream given to
- * covox_set_stream (default: the null stream).  Calls marked "asynchronous"
- * return before the device work finishes; callers keep their device inputs
- * alive until the stream has passed the work.
+ * device work of a context is ordered on the stream given to
+ * covox_set_stream (default: the null stream): work that a call runs on a
+ * stream of the library's own (covox_map_sequence) starts after an event
+ * recorded on that stream and ends before an event the stream waits for.
+ * Calls marked "asynchronous" return before the device work finishes;
+ * callers keep their device inputs alive until the stream has passed the
+ * work.
  *
  * Errors: every call returns a status code (below).  On an error the call
  * leaves the submap unchanged unless stated otherwise; covox_last_error()
@@ -171,7 +174,11 @@ int covox_integrate_depth_batch(covox_ctx *ctx, covox_submap *s, const float *de
  * ESDF after every esdf_every-th frame and after the last frame
  * (esdf_every <= 0: only after the last).  Identical results to the
  * equivalent sequence of covox_integrate_depth / covox_update_esdf calls.
- * Arguments as covox_integrate_depth_batch.  Asynchronous. */
+ * With the exact ESDF and more than one update, the EDT passes of each
+ * update run on a second stream of the library while the next frames are
+ * integrated (each update still computes the ESDF of the TSDF after its
+ * own frames); the call joins that stream back into the context stream
+ * before it returns.  Arguments as covox_integrate_depth_batch.  Asynchronous. */
 int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev, int32_t F, int32_t H,
                        int32_t W, const float K[4], const double *T_world_cam, int32_t esdf_every);
 
