@@ -100,7 +100,7 @@ def measured_traffic(kind, tuning, census):
     if not table:
         return None
     symbols = {"probe": "k_probe<float, true>", "scan": "k_scan", "integrate": "k_integrate<float, true>",
-               "esdf_page": "k_page_sites<float, 1, true>", "edt_x": "k_edt_x<1>", "edt_y": "k_edt_y_vox<1, 2>",
+               "esdf_page": "k_page_sites<float, 1, true>", "edt_x": "k_edt_x<1>", "edt_y": "k_edt_y_col<1>",
                "edt_z": "k_edt_z_vox<1>"}
     ent = table.get(symbols.get(kind, ""))
     if ent is None:

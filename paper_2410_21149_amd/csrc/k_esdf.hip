@@ -306,10 +306,7 @@ constexpr int kScanStep = 8;  // offsets per exit test of the windowed y and z p
 // 32-bit words a lane stages into LDS per block in the z pass (512 lanes,
 // 2 HB + 1 blocks of 256 words)
 constexpr int kStageZ = ((2 * kMaxHalo + 1) * 256 + 511) / 512;
-// Voxels per lane of the windowed y pass, and its grid: one workgroup per
-// dense block up to what the chip holds at once (32 waves per CU).
-constexpr int kYVox = 2;
-constexpr int64_t kYGrid = 256 * 32 / (512 / kYVox / 64);
+
 __device__ __forceinline__ int inf16(uint16_t v) { return v == 0xFFFF ? kBig : (int)v; }
 
 // x pass: one wave per dense block, lane = (y, z) line of the block.  The
@@ -359,69 +356,93 @@ __global__ __launch_bounds__(256) void k_edt_x(const JobList<NJ> jl, const uint6
     }
 }
 
-// y pass: 512 / V lanes per block, each lane V voxels (z0, z0 + 8 / V, ...),
-// so that the whole pass of a room-sized domain is resident at once and each
-// lane has V independent scans to overlap.
-template <int NJ, int V>
-__global__ __launch_bounds__(512 / V) void k_edt_y_vox(const JobList<NJ> jl, const uint8_t *__restrict__ g1,
-                                                       uint16_t *__restrict__ g2, int R, int HB)
+// y pass with a column layout in LDS: the staged g1 values of each (x, z)
+// column of the 2 HB + 1 blocks are contiguous (y fastest), so that a lane
+// reads four offsets of its column with one 32-bit LDS read per direction
+// (two dwords, joined by a byte shift where the four rows straddle them).
+// 256 lanes per block, each lane the voxels z and z + 4.  The minimum is the
+// same as the windowed pass's: the same offsets, tested for exit every eight.
+constexpr int kColBytes = 132;  // per column: 4 bytes of margin, 8 (2 kMaxHalo + 1) rows, margin; 33
+                                // dwords, so that the 8 x columns a wave reads fall in different banks
+
+template <int NJ>
+__global__ __launch_bounds__(256) void k_edt_y_col(const JobList<NJ> jl, const uint8_t *__restrict__ g1,
+                                                   uint16_t *__restrict__ g2, int R, int HB)
 {
-    constexpr int T = 512 / V;   // lanes
-    constexpr int ZS = 8 / V;    // z step between a lane's voxels
-    constexpr int kStage = ((2 * kMaxHalo + 1) * 128 + T - 1) / T;  // staged words per lane
+    constexpr int kStage = ((2 * kMaxHalo + 1) * 128 + 255) / 256;  // staged words per lane
     __shared__ Plan lds;
-    __shared__ __align__(16) uint32_t colw[(2 * kMaxHalo + 1) * 128];
+    __shared__ __align__(16) uint32_t colw[64 * kColBytes / 4 + 4];
+    uint8_t *colb = (uint8_t *)colw;
     PlanView<NJ> pv;
     pv.init(jl, 8 * HB, lds);
-    const uint8_t *col = (const uint8_t *)colw;
     const int tid = threadIdx.x;
-    const int x = tid & 7, y = (tid >> 3) & 7, z0 = tid >> 6;  // z0 in 0 .. ZS - 1
+    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;  // z in 0..3; the lane also takes z + 4
     const int nb = 2 * HB + 1;
     const int R2 = R * R;
     const int Y = 8 * HB + y;
+    const int c0 = x + 8 * z, c1 = x + 8 * (z + 4);
+    const uint32_t *cw0 = colw + c0 * (kColBytes / 4), *cw1 = colw + c1 * (kColBytes / 4);
+    // row r of a column is byte 4 + r: the rows Y - 4m - 4 .. Y - 4m - 1 start
+    // in dword (Y >> 2) - m at byte Y & 3, the rows Y + 4m + 1 .. Y + 4m + 4
+    // in dword ((Y + 5) >> 2) + m at byte (Y + 5) & 3
+    const int dn = Y >> 2, sdn = Y & 3, up = (Y + 5) >> 2, sup = (Y + 5) & 3;
     for (int64_t g = blockIdx.x; g < pv.t[0]; g += gridDim.x) {
         const JobInfo d = pv.info(pv.template job<&JobInfo::od>(g));
         int bx, by, bz;
         dom_coords(d, g - d.od, bx, by, bz);
-        // stage the column: every read issued before the first LDS write
-        // (entries outside the domain read this block's word and drop it)
+        // stage: every read issued before the first LDS write (entries outside
+        // the domain read this block's word and drop it)
         uint32_t sv[kStage];
 #pragma unroll
         for (int q = 0; q < kStage; ++q) {
-            const int e = tid + T * q, i = e >> 7, w = e & 127;
+            const int e = tid + 256 * q, i = e >> 7, w = e & 127;
             const int ny = by + i - HB;
             const bool ok = e < nb * 128 && ny >= 0 && ny < d.dim[1];
             sv[q] = ((const uint32_t *)(g1 + (g + (ok ? (int64_t)(i - HB) * d.dim[0] : 0)) * 512))[ok ? w : 0];
             sv[q] = ok ? sv[q] : 0xFFFFFFFFu;
         }
+        // word w of staged block i holds x = 4 (w & 1) + k, y = (w >> 1) & 7,
+        // z = w >> 4 for its bytes k = 0..3: row 8 i + y of column x + 8 z
 #pragma unroll
-        for (int q = 0; q < kStage; ++q)
-            if (tid + T * q < nb * 128) colw[tid + T * q] = sv[q];
+        for (int q = 0; q < kStage; ++q) {
+            const int e = tid + 256 * q;
+            if (e < nb * 128) {
+                const int i = e >> 7, w = e & 127;
+                uint8_t *dst = colb + (4 * (w & 1) + 8 * (w >> 4)) * kColBytes + 4 + 8 * i + ((w >> 1) & 7);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dst[k * kColBytes] = (uint8_t)(sv[q] >> (8 * k));
+            }
+        }
         __syncthreads();
-        auto at = [&](int yy, int zz) { return col[(yy >> 3) * 512 + x + 8 * (yy & 7) + 64 * zz]; };
-        int b[V];
+        int b0 = sq8(colb[c0 * kColBytes + 4 + Y]), b1 = sq8(colb[c1 * kColBytes + 4 + Y]);
+        // sliding dword windows per direction and voxel
+        uint32_t dhi0 = cw0[dn + 1], dhi1 = cw1[dn + 1];  // "-": the dword above the next one
+        uint32_t ulo0 = cw0[up], ulo1 = cw1[up];          // "+": the dword below the next one
+        for (int dd = 1, m = 0; dd <= R; dd += 8) {
+            if (dd * dd >= max(b0, b1)) break;
 #pragma unroll
-        for (int v = 0; v < V; ++v) b[v] = sq8(at(Y, z0 + ZS * v));
-        // outward scan, kScanStep offsets per exit test: the test needs the
-        // previous minima, so testing less often keeps more LDS reads in
-        // flight; offsets past a voxel's exit cannot lower its minimum
-        for (int dd = 1; dd <= R; dd += kScanStep) {
-            int bm = b[0];
+            for (int h = 0; h < 2; ++h, ++m) {
+                const uint32_t dlo0 = cw0[dn - m], dlo1 = cw1[dn - m];
+                const uint32_t uhi0 = cw0[up + m + 1], uhi1 = cw1[up + m + 1];
+                const uint32_t dv0 = __builtin_amdgcn_alignbyte(dhi0, dlo0, sdn);
+                const uint32_t dv1 = __builtin_amdgcn_alignbyte(dhi1, dlo1, sdn);
+                const uint32_t uv0 = __builtin_amdgcn_alignbyte(uhi0, ulo0, sup);
+                const uint32_t uv1 = __builtin_amdgcn_alignbyte(uhi1, ulo1, sup);
+                dhi0 = dlo0; dhi1 = dlo1;
+                ulo0 = uhi0; ulo1 = uhi1;
 #pragma unroll
-            for (int v = 1; v < V; ++v) bm = max(bm, b[v]);
-            if (dd * dd >= bm) break;
-#pragma unroll
-            for (int q = 0; q < kScanStep; ++q) {
-                const int e = dd + q;
-                if (e <= R) {
-#pragma unroll
-                    for (int v = 0; v < V; ++v)
-                        b[v] = min(b[v], min(sq8(at(Y - e, z0 + ZS * v)), sq8(at(Y + e, z0 + ZS * v))) + e * e);
+                for (int k = 0; k < 4; ++k) {
+                    const int e = 4 * m + 1 + k;  // byte 3 - k going down, byte k going up
+                    if (e <= R) {
+                        const int ee = e * e;
+                        b0 = min(b0, min(sq8((uint8_t)(dv0 >> (8 * (3 - k)))), sq8((uint8_t)(uv0 >> (8 * k)))) + ee);
+                        b1 = min(b1, min(sq8((uint8_t)(dv1 >> (8 * (3 - k)))), sq8((uint8_t)(uv1 >> (8 * k)))) + ee);
+                    }
                 }
             }
         }
-#pragma unroll
-        for (int v = 0; v < V; ++v) g2[g * 512 + tid + T * v] = b[v] <= R2 ? (uint16_t)b[v] : (uint16_t)0xFFFF;
+        g2[g * 512 + tid] = b0 <= R2 ? (uint16_t)b0 : (uint16_t)0xFFFF;
+        g2[g * 512 + tid + 256] = b1 <= R2 ? (uint16_t)b1 : (uint16_t)0xFFFF;
         __syncthreads();
     }
 }
@@ -803,8 +824,8 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
             hipLaunchKernelGGL((k_edt_y_env<NJ>), dim3(clamp_grid_w(cy)), dim3(64), 0, ctx->stream, jl, ctx->g1, ctx->g2,
                                R, HB);
         else
-            hipLaunchKernelGGL((k_edt_y_vox<NJ, kYVox>), dim3(std::max<int64_t>(1, std::min<int64_t>(nd, kYGrid))),
-                               dim3(512 / kYVox), 0, ctx->stream, jl, ctx->g1, ctx->g2, R, HB);
+            hipLaunchKernelGGL((k_edt_y_col<NJ>), dim3(clamp_grid(nd)), dim3(256), 0, ctx->stream, jl, ctx->g1,
+                               ctx->g2, R, HB);
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_Z);
