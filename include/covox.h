@@ -535,11 +535,16 @@ typedef struct {
     /* Points a lane handles per step (1 or 2; their loads overlap).  The
      * results do not depend on it. */
     int64_t align_points_per_step;
-    int64_t reserved[4];
+    /* Most workgroups of each EDT pass launch while the passes run beside
+     * an integration (covox_map_sequence): a smaller grid, which the passes
+     * cover with a grid stride, leaves CUs to the integration.  0: no
+     * limit.  The results do not depend on it. */
+    int64_t edt_pipe_max_workgroups;
+    int64_t reserved[3];
 } covox_tuning;
 
 /* Defaults: y envelopes from 2048 segments up, z always windowed, 256
- * lanes per alignment problem, one point per step. */
+ * lanes per alignment problem, one point per step, no workgroup cap. */
 void covox_default_tuning(covox_tuning *t);
 int covox_tuning_get(const covox_ctx *ctx, covox_tuning *out);
 int covox_tuning_set(covox_ctx *ctx, const covox_tuning *t);

@@ -71,7 +71,7 @@ class covox_train_cfg(ctypes.Structure):
 class covox_tuning(ctypes.Structure):
     _fields_ = [("edt_y_env_min_cols", ctypes.c_int64), ("edt_z_env_min_cols", ctypes.c_int64),
                 ("align_threads", ctypes.c_int64), ("align_points_per_step", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 4)]
+                ("edt_pipe_max_workgroups", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
 
 
 class covox_pose_factor(ctypes.Structure):
@@ -485,7 +485,8 @@ class Context:
     @staticmethod
     def _tuning_dict(t) -> dict:
         return {"edt_y_env_min_cols": t.edt_y_env_min_cols, "edt_z_env_min_cols": t.edt_z_env_min_cols,
-                "align_threads": t.align_threads, "align_points_per_step": t.align_points_per_step}
+                "align_threads": t.align_threads, "align_points_per_step": t.align_points_per_step,
+                "edt_pipe_max_workgroups": t.edt_pipe_max_workgroups}
 
     def tuning(self) -> dict:
         t = covox_tuning()
@@ -493,7 +494,7 @@ class Context:
         return self._tuning_dict(t)
 
     def set_tuning(self, edt_y_env_min_cols=None, edt_z_env_min_cols=None, align_threads=None,
-                   align_points_per_step=None):
+                   align_points_per_step=None, edt_pipe_max_workgroups=None):
         t = covox_tuning()
         self._check(_lib.covox_tuning_get(self.handle, ctypes.byref(t)), "tuning_get")
         if edt_y_env_min_cols is not None:
@@ -504,6 +505,8 @@ class Context:
             t.align_threads = align_threads
         if align_points_per_step is not None:
             t.align_points_per_step = align_points_per_step
+        if edt_pipe_max_workgroups is not None:
+            t.edt_pipe_max_workgroups = edt_pipe_max_workgroups
         self._check(_lib.covox_tuning_set(self.handle, ctypes.byref(t)), "tuning_set")
 
     def autotune_esdf(self, subs) -> dict:

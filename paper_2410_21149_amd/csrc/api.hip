@@ -1315,6 +1315,9 @@ void covox_default_tuning(covox_tuning *t)
     t->edt_z_env_min_cols = INT64_MAX;
     t->align_threads = 256;
     t->align_points_per_step = 1;
+    // no cap: on the room step (MI355X) a cap of 512 gave a graph replay about
+    // 5 % faster but eager calls no faster, and made each pass slower
+    t->edt_pipe_max_workgroups = 0;
 }
 
 int covox_tuning_get(const covox_ctx *ctx, covox_tuning *out)
@@ -1333,6 +1336,8 @@ int covox_tuning_set(covox_ctx *ctx, const covox_tuning *t)
         return fail(ctx, COVOX_EINVAL, "tuning_set: align_threads must be 256 or 512");
     if (t->align_points_per_step != 1 && t->align_points_per_step != 2)
         return fail(ctx, COVOX_EINVAL, "tuning_set: align_points_per_step must be 1 or 2");
+    if (t->edt_pipe_max_workgroups < 0)
+        return fail(ctx, COVOX_EINVAL, "tuning_set: edt_pipe_max_workgroups must be >= 0");
     ctx->tune = *t;
     return COVOX_OK;
 }

@@ -673,6 +673,14 @@ __global__ __launch_bounds__(64) void k_edt_z_env(const JobList<NJ> jl, const ui
 // their dispatch and set-up for nothing.  2048 workgroups of up to 512
 // lanes keep 256 CUs busy.
 unsigned clamp_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 2048)); }
+// The passes loop over their work with a grid stride, so a smaller grid is
+// valid; while they run beside an integration (on their own stream), the
+// tuning's cap leaves CUs to it.
+unsigned cap_grid(const covox_ctx *ctx, unsigned g)
+{
+    const int64_t cap = ctx->tune.edt_pipe_max_workgroups;
+    return ctx->esdf_edt_stream && cap > 0 ? (unsigned)std::min<int64_t>(g, cap) : g;
+}
 // Single-wave workgroups (per-line envelopes): up to 64 waves per CU.
 unsigned clamp_grid_w(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 16384)); }
 
@@ -815,7 +823,7 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_X);
-        hipLaunchKernelGGL((k_edt_x<NJ>), dim3(clamp_grid((nd + 3) / 4)), dim3(256), 0, ctx->stream, jl, sites,
+        hipLaunchKernelGGL((k_edt_x<NJ>), dim3(cap_grid(ctx, clamp_grid((nd + 3) / 4))), dim3(256), 0, ctx->stream, jl, sites,
                            ctx->g1, R, HB);
     }
     {
@@ -824,7 +832,7 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
             hipLaunchKernelGGL((k_edt_y_env<NJ>), dim3(clamp_grid_w(cy)), dim3(64), 0, ctx->stream, jl, ctx->g1, ctx->g2,
                                R, HB);
         else
-            hipLaunchKernelGGL((k_edt_y_col<NJ>), dim3(clamp_grid(nd)), dim3(256), 0, ctx->stream, jl, ctx->g1,
+            hipLaunchKernelGGL((k_edt_y_col<NJ>), dim3(cap_grid(ctx, clamp_grid(nd))), dim3(256), 0, ctx->stream, jl, ctx->g1,
                                ctx->g2, R, HB);
     }
     {
@@ -833,7 +841,7 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
             hipLaunchKernelGGL((k_edt_z_env<NJ>), dim3(clamp_grid_w(cz)), dim3(64), 0, ctx->stream, jl, ctx->g2, R, HB,
                                vs, dmax);
         else
-            hipLaunchKernelGGL((k_edt_z_vox<NJ>), dim3(clamp_grid(nb)), dim3(512), 0, ctx->stream, jl, ctx->g2, R, HB,
+            hipLaunchKernelGGL((k_edt_z_vox<NJ>), dim3(cap_grid(ctx, clamp_grid(nb))), dim3(512), 0, ctx->stream, jl, ctx->g2, R, HB,
                                vs, dmax);
     }
     ctx->stream = base;

@@ -96,6 +96,30 @@ def test_pipelined_sequence_equals_calls_in_order(cv, room90, scene, kw, every):
     b.close()
 
 
+@pytest.mark.parametrize("cap", [0, 3, 512])
+def test_pass_grid_cap_does_not_change_the_result(cv, cap):
+    """The EDT passes cover their work with a grid stride, so the workgroup
+    cap of the pipelined passes (tuning edt_pipe_max_workgroups; 0 = none)
+    leaves the result unchanged."""
+    import torch
+    w = sg.tiny()
+    dev = torch.from_numpy(w.frames()).cuda()
+    base = dict(voxel_size=0.05, trunc_vox=4, max_range=5.0, d_max=2.0, block_capacity=8192)
+    a = cv.Context(**base)
+    a.set_tuning(edt_pipe_max_workgroups=cap)
+    assert a.tuning()["edt_pipe_max_workgroups"] == cap
+    sa = a.submap_create()
+    a.map_sequence(sa, dev, w.cam.K, w.poses, esdf_every=1)
+    b = cv.Context(**base)
+    sb = b.submap_create()
+    _in_order(b, sb, dev, w.cam.K, w.poses, 1)
+    _same(a.export_blocks(sa), b.export_blocks(sb))
+    with pytest.raises(cv.CovoxError):
+        a.set_tuning(edt_pipe_max_workgroups=-1)
+    a.close()
+    b.close()
+
+
 def test_captured_pipelined_sequence_replays_to_the_calls_in_order(cv, room90):
     import torch
     w, fr = room90
