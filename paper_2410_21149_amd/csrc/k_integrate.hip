@@ -230,7 +230,7 @@ __device__ __forceinline__ void publish_count(uint64_t *host_nb, uint64_t seq, i
 __global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand, int64_t n_box, FrameArgs f,
                                                SubmapMeta *meta, int64_t cap, int64_t table_limit,
                                                uint64_t *__restrict__ t_key, uint32_t *__restrict__ t_idx,
-                                               uint64_t *host_nb, uint64_t seq)
+                                               uint64_t *__restrict__ t_new, uint64_t *host_nb, uint64_t seq)
 {
     __shared__ int64_t lds[16];
     __shared__ int32_t red[6][16];
@@ -281,6 +281,7 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand
         box_block(f, j, bx, by, bz);
         uint32_t idx;
         if (v == kNew) {
+            t_new[off_n] = pack_key(bx, by, bz);  // the new blocks alone, in index order
             idx = (uint32_t)(n0 + off_n++) | 0x80000000u;
             lo[0] = min(lo[0], bx); lo[1] = min(lo[1], by); lo[2] = min(lo[2], bz);
             hi[0] = max(hi[0], bx); hi[1] = max(hi[1], by); hi[2] = max(hi[2], bz);
@@ -325,23 +326,26 @@ __global__ __launch_bounds__(1024) void k_scan(const uint32_t *__restrict__ cand
     }
 }
 
-// NEW_ONLY: the probe has already updated the existing blocks (fused path).
+// NEW_ONLY: the probe has already updated the existing blocks (fused path),
+// and the waves walk the scan's list of the new blocks alone (t_new; block
+// index n_blocks - n_new + position), so that a small grid suffices.
 template <typename S, bool NEW_ONLY>
 __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float tau, float maxr,
                                                    SubmapMeta *__restrict__ meta,
                                                    const uint64_t *__restrict__ t_key,
-                                                   const uint32_t *__restrict__ t_idx, uint64_t *keys, S *D, S *W,
+                                                   const uint32_t *__restrict__ t_idx,
+                                                   const uint64_t *__restrict__ t_new, uint64_t *keys, S *D, S *W,
                                                    uint64_t *tkeys, uint32_t *tvals, uint64_t tmask)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int lane = threadIdx.x & 63;
-    const int64_t n_t = meta->n_touched;
+    const int64_t n_t = NEW_ONLY ? (int64_t)meta->n_new : (int64_t)meta->n_touched;
+    const int64_t n0 = NEW_ONLY ? meta->n_blocks - n_t : 0;
     for (int64_t t = wave; t < n_t; t += nwaves) {
-        const uint32_t v = t_idx[t];
+        const uint32_t v = NEW_ONLY ? 0x80000000u | (uint32_t)(n0 + t) : t_idx[t];
         const bool is_new = (v >> 31) != 0;
-        if (NEW_ONLY && !is_new) continue;  // uniform across the wave
-        const uint64_t key = t_key[t];
+        const uint64_t key = NEW_ONLY ? t_new[t] : t_key[t];
         const int64_t idx = v & 0x7FFFFFFFu;
         int bx, by, bz;
         unpack_key(key, bx, by, bz);
@@ -645,6 +649,11 @@ bool is_rigid(const double *T)
     return e <= 1e-6 && det > 0;
 }
 
+// Workgroups of the new-block integration after a fused probe: a frame adds a
+// few new blocks, except the first ones; the waves walk the list with a
+// stride.
+constexpr unsigned kNewGrid = 64;
+
 template <typename S>
 void launch_frame(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, float vs, float tau, float maxr, uint64_t tmask,
                   int64_t table_limit, int64_t n_box, unsigned grid, bool fused)
@@ -662,16 +671,18 @@ void launch_frame(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, float vs,
     {
         TimedLaunch tl(ctx, COVOX_K_SCAN);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, ctx->stream, ctx->cand, n_box, f, s->meta, s->cap,
-                           table_limit, ctx->t_key, ctx->t_idx, s->pin_nb_dev, s->seq);
+                           table_limit, ctx->t_key, ctx->t_idx, ctx->t_key + n_box, s->pin_nb_dev, s->seq);
     }
     {
         TimedLaunch tl(ctx, COVOX_K_INTEGRATE);
         if (fused)
-            hipLaunchKernelGGL((k_integrate<S, true>), dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau, maxr, s->meta,
-                               ctx->t_key, ctx->t_idx, s->keys, D, W, s->tkeys, s->tvals, tmask);
+            hipLaunchKernelGGL((k_integrate<S, true>), dim3(std::min(grid, kNewGrid)), dim3(256), 0, ctx->stream, f, vs,
+                               tau, maxr, s->meta, ctx->t_key, ctx->t_idx, ctx->t_key + n_box, s->keys, D, W,
+                               s->tkeys, s->tvals, tmask);
         else
             hipLaunchKernelGGL((k_integrate<S, false>), dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau, maxr,
-                               s->meta, ctx->t_key, ctx->t_idx, s->keys, D, W, s->tkeys, s->tvals, tmask);
+                               s->meta, ctx->t_key, ctx->t_idx, ctx->t_key + n_box, s->keys, D, W, s->tkeys,
+                               s->tvals, tmask);
     }
 }
 
@@ -699,7 +710,7 @@ void launch_block_scan(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, int6
 {
     TimedLaunch tl(ctx, COVOX_K_SCAN);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, ctx->stream, ctx->cand, n_box, f, s->meta, s->cap,
-                       table_limit, ctx->t_key, ctx->t_idx, s->pin_nb_dev, s->seq);
+                       table_limit, ctx->t_key, ctx->t_idx, ctx->t_key + n_box, s->pin_nb_dev, s->seq);
 }
 
 // Frame parameters (pose rounded once from binary64) and the block box of
@@ -833,7 +844,8 @@ int integrate_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t
     const double tau = p.trunc_vox * p.voxel_size;
     if ((rc = ensure_buffer(ctx, (void **)&ctx->cand, &ctx->cand_cap, n_box, sizeof(uint32_t), "candidates")))
         return rc;
-    if ((rc = ensure_buffer(ctx, (void **)&ctx->t_key, &ctx->t_key_cap, n_box, sizeof(uint64_t), "touched keys")))
+    // touched keys, then (from n_box on) the new blocks' keys
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->t_key, &ctx->t_key_cap, 2 * n_box, sizeof(uint64_t), "touched keys")))
         return rc;
     if ((rc = ensure_buffer(ctx, (void **)&ctx->t_idx, &ctx->t_idx_cap, n_box, sizeof(uint32_t), "touched index")))
         return rc;

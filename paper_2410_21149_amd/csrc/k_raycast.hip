@@ -423,7 +423,8 @@ int raycast_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H
     if ((rc = ensure_ray_acc(ctx))) return rc;
     if ((rc = ensure_buffer(ctx, (void **)&ctx->cand, &ctx->cand_cap, n_box, sizeof(uint32_t), "candidates")))
         return rc;
-    if ((rc = ensure_buffer(ctx, (void **)&ctx->t_key, &ctx->t_key_cap, n_box, sizeof(uint64_t), "touched keys")))
+    // touched keys, then (from n_box on) the new blocks' keys (k_scan)
+    if ((rc = ensure_buffer(ctx, (void **)&ctx->t_key, &ctx->t_key_cap, 2 * n_box, sizeof(uint64_t), "touched keys")))
         return rc;
     if ((rc = ensure_buffer(ctx, (void **)&ctx->t_idx, &ctx->t_idx_cap, n_box, sizeof(uint32_t), "touched index")))
         return rc;
