@@ -201,23 +201,27 @@ def align_bench(cv, torch, np, w, dev, reps=3):
     ctx.align_batch(pairs[:2], 1)  # registration points extracted once per submap
     out = {"workload": "room submaps of 50 frames, %d pairs (%d distinct), perturbation 0.1 m / 5 deg yaw / 1 deg "
                        "roll-pitch" % (len(pairs), len(pairs_idx))}
-    for n_starts in (1, 8):
-        tuning = ctx.autotune_align(pairs, n_starts)  # launch shape for this batch
-        best = None
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            T, cost, st = ctx.align_batch(pairs, n_starts)
-            dt = time.perf_counter() - t0
-            best = dt if best is None else min(best, dt)
-        ok = 0
-        for Tg, Tt in zip(T, gts):
-            et = np.linalg.norm(Tg[:3, 3] - Tt[:3, 3])
-            c = (np.trace(Tg[:3, :3] @ Tt[:3, :3].T) - 1) / 2
-            er = math.degrees(math.acos(max(-1.0, min(1.0, c))))
-            ok += et <= 0.01 and er <= 0.1
-        out["starts_%d" % n_starts] = {"pairs_per_s": len(pairs) / best, "success": ok / len(pairs),
-                                        "ms": best * 1e3}
+    # Gauss-Newton (the default), then Levenberg-Marquardt on the same pairs
+    for solver, prefix in ((cv.GAUSS_NEWTON, ""), (cv.LEVENBERG_MARQUARDT, "lm_")):
+        ctx.set_params(align_solver=solver)
+        for n_starts in (1, 8):
+            tuning = ctx.autotune_align(pairs, n_starts)  # launch shape for this batch
+            best = None
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                T, cost, st = ctx.align_batch(pairs, n_starts)
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            ok = 0
+            for Tg, Tt in zip(T, gts):
+                et = np.linalg.norm(Tg[:3, 3] - Tt[:3, 3])
+                c = (np.trace(Tg[:3, :3] @ Tt[:3, :3].T) - 1) / 2
+                er = math.degrees(math.acos(max(-1.0, min(1.0, c))))
+                ok += et <= 0.01 and er <= 0.1
+            out["%sstarts_%d" % (prefix, n_starts)] = {"pairs_per_s": len(pairs) / best, "success": ok / len(pairs),
+                                                        "ms": best * 1e3}
+    ctx.set_params(align_solver=cv.GAUSS_NEWTON)
     ctx.close()
     return out
 
@@ -375,6 +379,10 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
              "overlap_range": [float(min(c[2] for c in cand)), float(max(c[2] for c in cand))]}
     for n_starts in (1, 8):
         align["starts_%d" % n_starts] = run_pairs(pairs, gts, n_starts)
+    ctx.set_params(align_solver=cv.LEVENBERG_MARQUARDT)  # the same pairs under Levenberg-Marquardt
+    for n_starts in (1, 8):
+        align["lm_starts_%d" % n_starts] = run_pairs(pairs, gts, n_starts)
+    ctx.set_params(align_solver=cv.GAUSS_NEWTON)
     # gravity-aligned priors (roll and pitch known, as from an IMU): the
     # 4-DoF estimate (translation and yaw) beside the 6-DoF one on the same pairs
     pairs_g, gts_g = make_pairs(5, 0.0)

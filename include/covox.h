@@ -71,7 +71,8 @@ typedef struct {
     double w_reg;            /* minimum weight of both endpoints of a registration edge */
     int64_t block_capacity;  /* blocks per submap (pre-allocated, Sec. III-D) */
     int32_t precision;       /* COVOX_FP32 or COVOX_FP16 */
-    int32_t max_iter;        /* Gauss-Newton iteration cap */
+    int32_t max_iter;        /* alignment iteration cap: pose updates (Gauss-Newton) or solves
+                                (Levenberg-Marquardt) */
     int32_t n_min;           /* minimum number of residuals for a solve */
     double tol_rho;          /* stop when |delta_rho| < tol_rho (m) ... */
     double tol_theta;        /* ... and |delta_theta| < tol_theta (rad) */
@@ -87,16 +88,19 @@ typedef struct {
                                 carved, as the paper describes), 0 = at tau before the point */
     int32_t esdf_mode;       /* COVOX_ESDF_EXACT (exact EDT recomputed) or COVOX_ESDF_WAVEFRONT
                                 (Sec. III-E incremental propagation: see covox_update_esdf) */
+    int32_t align_solver;    /* COVOX_GAUSS_NEWTON or COVOX_LEVENBERG_MARQUARDT (Sec. III-F: LM with a
+                                trust region); see covox_align_submaps */
 } covox_params;
 
 enum { COVOX_WEIGHT_CONSTANT = 0, COVOX_WEIGHT_INV_DEPTH2 = 1 };
 enum { COVOX_PROJECTIVE = 0, COVOX_RAYCAST = 1 };
 enum { COVOX_ESDF_EXACT = 0, COVOX_ESDF_WAVEFRONT = 1 };
+enum { COVOX_GAUSS_NEWTON = 0, COVOX_LEVENBERG_MARQUARDT = 1 };
 
 /* Fills p with the defaults: 0.05 m voxels, tau = 4 voxels, 5 m range, 2 m
  * ESDF, w_reg = 2, 65536 blocks, FP32, 30 iterations, n_min = 100,
- * tolerances 1e-7 m and 1e-8 rad, 6 DoF, constant weights, projection
- * mapping (rays carved from the optical centre when raycasting). */
+ * tolerances 1e-7 m and 1e-8 rad, 6 DoF, Gauss-Newton, constant weights,
+ * projection mapping (rays carved from the optical centre when raycasting). */
 void covox_default_params(covox_params *p);
 
 /* Creates a context on the current HIP device.  *out receives the handle.
@@ -105,8 +109,8 @@ int covox_create(covox_ctx **out, const covox_params *p);
 void covox_destroy(covox_ctx *ctx);
 
 /* Replaces the parameters that do not shape storage: w_reg, max_iter,
- * n_min, tol_rho, tol_theta, align_dof, weight_mode, integrator, ray_carve
- * and esdf_mode (the next calls use them; switching to raycasting
+ * n_min, tol_rho, tol_theta, align_dof, weight_mode, integrator, ray_carve,
+ * esdf_mode and align_solver (the next calls use them; switching to raycasting
  * allocates its accumulators, 16 bytes per voxel of block_capacity).  COVOX_EINVAL if p is invalid or
  * changes voxel_size, trunc_vox, max_range, d_max, block_capacity or
  * precision.  Registration points are re-extracted after a w_reg change. */
@@ -217,7 +221,7 @@ int covox_update_esdf_batch(covox_ctx *ctx, covox_submap *const *subs, int32_t n
 typedef struct {
     int64_t n_points;     /* registration points of B */
     int64_t n_used;       /* residuals used at the returned pose */
-    int32_t iterations;   /* pose updates applied */
+    int32_t iterations;   /* pose updates applied (Levenberg-Marquardt: steps taken) */
     int32_t status;       /* COVOX_OK, COVOX_NOT_CONVERGED or COVOX_EDEGENERATE */
     int32_t best_start;   /* multi-start: the chosen start, else 0 */
     int32_t reserved;
@@ -231,6 +235,14 @@ typedef struct {
  * for T <- Exp(xi) T.  Gauss-Newton with binary64 6x6 Cholesky solves and
  * SE(3) updates on the device; stops when |delta_rho| < tol_rho and
  * |delta_theta| < tol_theta, or after max_iter updates.
+ * With align_solver = COVOX_LEVENBERG_MARQUARDT each solve is of
+ * (H + mu diag(H)) delta = -b; the trial pose Exp(delta) T is evaluated and
+ * taken when the gain ratio (c/n - c'/n') / L is positive, L = -(2 delta.b +
+ * delta.H.delta) / n the decrease of the mean cost c/n that the linear model
+ * predicts (fewer than n_min residuals at the trial: not taken); then
+ * mu *= max(1/3, 1 - (2 rho - 1)^3), nu = 2, else mu *= nu, nu *= 2 (mu starts
+ * at 1e-4, nu at 2).  A step below the tolerances ends the solve as
+ * converged without being taken; max_iter caps the solves.
  * T_init_A_B, T_out (host, 16 doubles) map B coordinates into A's frame.
  * cost (host) = mean squared residual at T_out.  stats: nullable.
  * Requires covox_update_esdf(A) after A's last integration.  Synchronous.

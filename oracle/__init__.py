@@ -45,7 +45,7 @@ class _Params(ctypes.Structure):
                 ("fp16", ctypes.c_int), ("max_iter", ctypes.c_int), ("n_min", ctypes.c_int),
                 ("tol_rho", ctypes.c_double), ("tol_theta", ctypes.c_double), ("align_dof", ctypes.c_int),
                 ("weight_mode", ctypes.c_int), ("integrator", ctypes.c_int), ("ray_carve", ctypes.c_int),
-                ("esdf_mode", ctypes.c_int)]
+                ("esdf_mode", ctypes.c_int), ("align_solver", ctypes.c_int)]
 
 
 class _Conv(ctypes.Structure):
@@ -68,6 +68,8 @@ def _load():
         L = ctypes.CDLL(_LIB)
         L.orc_submap_create.restype = _vp
         L.orc_submap_create.argtypes = [ctypes.POINTER(_Params), _dp]
+        L.orc_set_solver.restype = None
+        L.orc_set_solver.argtypes = [_vp, ctypes.POINTER(_Params)]
         L.orc_submap_destroy.restype = None
         L.orc_submap_destroy.argtypes = [_vp]
         L.orc_integrate.restype = ctypes.c_int
@@ -93,6 +95,10 @@ def _load():
         L.orc_se3_exp.argtypes = [_dp, _dp]
         L.orc_solve6.restype = ctypes.c_int
         L.orc_solve6.argtypes = [_dp, _dp]
+        L.orc_solve6_damped.restype = ctypes.c_int
+        L.orc_solve6_damped.argtypes = [_dp, ctypes.c_double, _dp]
+        L.orc_solve_xyz_yaw_damped.restype = ctypes.c_int
+        L.orc_solve_xyz_yaw_damped.argtypes = [_dp, ctypes.c_double, _dp]
         L.orc_hash_insert.restype = None
         L.orc_hash_insert.argtypes = [_u64p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int64, _u64p, ctypes.c_int64,
                                       ctypes.c_uint32, _i64p, _i64p]
@@ -137,17 +143,19 @@ class Params:
 
     def __init__(self, vs=0.05, trunc_vox=4, max_range=5.0, d_max=2.0, w_reg=2.0, fp64=False, fp16=False,
                  max_iter=30, n_min=100, tol_rho=1e-7, tol_theta=1e-8, align_dof=6, weight_mode=0, integrator=0,
-                 ray_carve=True, esdf_mode=0):
+                 ray_carve=True, esdf_mode=0, align_solver=0):
         self.vs, self.trunc_vox, self.max_range, self.d_max = vs, trunc_vox, max_range, d_max
         self.w_reg, self.fp64, self.fp16, self.max_iter, self.n_min = w_reg, fp64, fp16, max_iter, n_min
         self.tol_rho, self.tol_theta, self.align_dof, self.weight_mode = tol_rho, tol_theta, align_dof, weight_mode
         self.integrator, self.ray_carve = integrator, ray_carve  # 0: projection mapping, 1: raycasting
         self.esdf_mode = esdf_mode  # 0: exact EDT, 1: incremental wavefront
+        self.align_solver = align_solver  # 0: Gauss-Newton, 1: Levenberg-Marquardt
 
     def _c(self):
         return _Params(self.vs, self.trunc_vox, self.max_range, self.d_max, self.w_reg, int(self.fp64),
                        int(self.fp16), self.max_iter, self.n_min, self.tol_rho, self.tol_theta, int(self.align_dof),
-                       int(self.weight_mode), int(self.integrator), int(bool(self.ray_carve)), int(self.esdf_mode))
+                       int(self.weight_mode), int(self.integrator), int(bool(self.ray_carve)), int(self.esdf_mode),
+                       int(self.align_solver))
 
 
 class Submap:
@@ -159,6 +167,14 @@ class Submap:
         T = _mat(np.eye(4) if T_world_submap is None else T_world_submap)
         self._cp = params._c()
         self._h = L.orc_submap_create(ctypes.byref(self._cp), _p(T, _dp))
+
+    def set_solver(self, params: Params):
+        """Takes the alignment solver's parameters (max_iter, n_min, tol_rho,
+        tol_theta, align_dof, align_solver) from params; the map is kept."""
+        cp = params._c()
+        _load().orc_set_solver(self._h, ctypes.byref(cp))
+        for k in ("max_iter", "n_min", "tol_rho", "tol_theta", "align_dof", "align_solver"):
+            setattr(self.params, k, getattr(params, k))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -281,10 +297,23 @@ def se3_exp(xi) -> np.ndarray:
     return E.reshape(4, 4)
 
 
-def solve6(ne29):
+def solve6(ne29, mu=None):
+    """The step x of H x = -b, or of (H + mu diag(H)) x = -b when mu is given
+    (Levenberg-Marquardt); None when the matrix is not positive definite."""
     ne = np.ascontiguousarray(ne29, np.float64)
     x = np.zeros(6)
-    rc = _load().orc_solve6(_p(ne, _dp), _p(x, _dp))
+    if mu is None:
+        rc = _load().orc_solve6(_p(ne, _dp), _p(x, _dp))
+    else:
+        rc = _load().orc_solve6_damped(_p(ne, _dp), float(mu), _p(x, _dp))
+    return (x if rc == 0 else None)
+
+
+def solve_xyz_yaw(ne29, mu=0.0):
+    """The 4-DoF step (rho, 0, 0, theta_z) with damping mu."""
+    ne = np.ascontiguousarray(ne29, np.float64)
+    x = np.zeros(6)
+    rc = _load().orc_solve_xyz_yaw_damped(_p(ne, _dp), float(mu), _p(x, _dp))
     return (x if rc == 0 else None)
 
 

@@ -27,7 +27,9 @@
  *               repeated until nothing changes).
  *   align       Sec. I and Sec. III-F, Eq. (1) registration term
  *               (correspondence-free ESDF alignment, registration points
- *               chosen by weight, least squares on residuals/Jacobians).
+ *               chosen by weight, least squares on residuals/Jacobians;
+ *               Gauss-Newton, or Levenberg-Marquardt with a trust region
+ *               as Sec. III-F names for the backend).
  *   hash        Sec. III-B (blocks indexed by their 3-D position through a
  *               hash table with open addressing) and the hash-table stress
  *               test of Sec. IV: keys inserted one after another, each in
@@ -75,6 +77,7 @@ typedef struct {
     int integrator;    /* 0: projection mapping; 1: raycasting */
     int ray_carve;     /* raycasting: 1 = rays start at the optical centre; 0 = at tau before the point */
     int esdf_mode;     /* 0: exact EDT recomputed; 1: incremental wavefront (nearest-site propagation) */
+    int align_solver;  /* 0: Gauss-Newton; 1: Levenberg-Marquardt with the gain-ratio trust region */
 } orc_params;
 
 typedef struct {
@@ -248,6 +251,18 @@ orc_submap *orc_submap_create(const orc_params *p, const double *T_ws)
     s->p = *p;
     memcpy(s->T_ws, T_ws, sizeof(s->T_ws));
     return s;
+}
+
+/* Replaces the alignment solver's parameters (max_iter, n_min, tol_rho,
+ * tol_theta, align_dof, align_solver); the map is untouched. */
+void orc_set_solver(orc_submap *s, const orc_params *p)
+{
+    s->p.max_iter = p->max_iter;
+    s->p.n_min = p->n_min;
+    s->p.tol_rho = p->tol_rho;
+    s->p.tol_theta = p->tol_theta;
+    s->p.align_dof = p->align_dof;
+    s->p.align_solver = p->align_solver;
 }
 
 void orc_submap_destroy(orc_submap *s)
@@ -1355,14 +1370,17 @@ void orc_se3_exp(const double xi[6], double *E)
     E[12] = 0; E[13] = 0; E[14] = 0; E[15] = 1;
 }
 
-/* Solve H x = -b for the 6x6 symmetric H (upper triangle packed) by
- * Cholesky.  Returns 0, or -1 when H is not positive definite. */
-int orc_solve6(const double *ne, double x[6])
+/* Solve (H + mu diag(H)) x = -b for the 6x6 symmetric H (upper triangle
+ * packed) by Cholesky; mu = 0 is the Gauss-Newton step.  Returns 0, or -1
+ * when the matrix is not positive definite. */
+int orc_solve6_damped(const double *ne, double mu, double x[6])
 {
     double H[36], L[36];
     int m = 0;
     for (int a = 0; a < 6; ++a)
         for (int b = a; b < 6; ++b) { H[6 * a + b] = ne[m]; H[6 * b + a] = ne[m]; ++m; }
+    if (mu != 0.0)
+        for (int j = 0; j < 6; ++j) H[6 * j + j] = H[6 * j + j] + mu * H[6 * j + j];
     memset(L, 0, sizeof(L));
     for (int j = 0; j < 6; ++j) {
         double s = H[6 * j + j];
@@ -1389,13 +1407,15 @@ int orc_solve6(const double *ne, double x[6])
     return 0;
 }
 
+int orc_solve6(const double *ne, double x[6]) { return orc_solve6_damped(ne, 0.0, x); }
+
 /*
  * The 4-DoF step (translation and yaw, for submaps whose gravity direction
  * is known): the Jacobian is the 6-DoF one restricted to (rho_x, rho_y,
  * rho_z, theta_z), so its normal equations are rows and columns 0, 1, 2, 5 of
  * the 6-DoF ones.  Solved by the same Cholesky; d = (rho, 0, 0, theta_z).
  */
-int orc_solve_xyz_yaw(const double ne[29], double d[6])
+int orc_solve_xyz_yaw_damped(const double ne[29], double mu, double d[6])
 {
     static const int sel[4] = {0, 1, 2, 5};
     double H[4][4], b[4];
@@ -1407,6 +1427,8 @@ int orc_solve_xyz_yaw(const double ne[29], double d[6])
         }
         b[a] = ne[21 + sel[a]];
     }
+    if (mu != 0.0)
+        for (int a = 0; a < 4; ++a) H[a][a] = H[a][a] + mu * H[a][a];
     double L[4][4] = {{0}};
     for (int j = 0; j < 4; ++j) {
         double sj = H[j][j];
@@ -1435,6 +1457,85 @@ int orc_solve_xyz_yaw(const double ne[29], double d[6])
     return 0;
 }
 
+int orc_solve_xyz_yaw(const double ne[29], double d[6]) { return orc_solve_xyz_yaw_damped(ne, 0.0, d); }
+
+/*
+ * Levenberg-Marquardt alignment (Sec. III-F solves the backend's least
+ * squares by LM with a trust region; here the same rule serves one pair).
+ * At the current pose T with normal equations (H, b, c, n), cost c / n:
+ *   solve (H + mu diag(H)) delta = -b (4-DoF: rows and columns 0, 1, 2, 5);
+ *   if |delta_rho| < tol_rho and |delta_theta| < tol_theta: converged, the
+ *     step is not taken;
+ *   trial T' = Exp(delta) T with normal equations (H', b', c', n');
+ *   predicted decrease of the mean cost L = -(2 delta.b + delta.H.delta) / n;
+ *   gain ratio rho = (c / n - c' / n') / L when n' >= n_min and L > 0,
+ *     else -1;
+ *   rho > 0: T = T', mu *= max(1/3, 1 - (2 rho - 1)^3), nu = 2;
+ *   otherwise mu *= nu, nu *= 2.
+ * mu starts at 1e-4 (relative to diag(H), Marquardt's scaling), nu at 2
+ * (the rule of Madsen, Nielsen and Tingleff, 2004).  max_iter caps the
+ * solves; fewer than n_min residuals at the start is EDEGENERATE, as is a
+ * damped matrix that is not positive definite.  info[0] = steps taken.
+ */
+static double lm_predicted(const double *ne, const double d[6])
+{
+    double g = 0.0, q = 0.0;
+    for (int a = 0; a < 6; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < 6; ++b) {
+            const int r = a < b ? a : b, c = a < b ? b : a;
+            s += ne[r * 6 - r * (r - 1) / 2 + (c - r)] * d[b];
+        }
+        q += d[a] * s;
+        g += d[a] * ne[21 + a];
+    }
+    return -(2.0 * g + q);
+}
+
+static int align_lm(const orc_submap *A, const void *pts, int64_t n_pts, const double *T_init, double *T_out,
+                    double *cost, int64_t *info)
+{
+    double T[16], Tt[16], ne[29], nt[29];
+    memcpy(T, T_init, sizeof(T));
+    int status = ORC_NOT_CONVERGED;
+    int64_t taken = 0;
+    orc_normal_eq(A, pts, n_pts, T, ne);
+    if (A->p.max_iter > 0 && ne[28] < A->p.n_min) status = ORC_EDEGENERATE;
+    double mu = 1e-4, nu = 2.0;
+    for (int it = 0; it < A->p.max_iter && status == ORC_NOT_CONVERGED; ++it) {
+        double d[6];
+        if ((A->p.align_dof == 4 ? orc_solve_xyz_yaw_damped(ne, mu, d) : orc_solve6_damped(ne, mu, d)) != 0) {
+            status = ORC_EDEGENERATE;
+            break;
+        }
+        double nr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double nth = sqrt(d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
+        if (nr < A->p.tol_rho && nth < A->p.tol_theta) { status = ORC_OK; break; }
+        double E[16];
+        orc_se3_exp(d, E);
+        rigid_mul(E, T, Tt);
+        orc_normal_eq(A, pts, n_pts, Tt, nt);
+        const double pred = lm_predicted(ne, d);
+        double rho = -1.0;
+        if (nt[28] >= A->p.n_min && pred > 0.0) rho = (ne[27] / ne[28] - nt[27] / nt[28]) / (pred / ne[28]);
+        if (rho > 0.0) {
+            memcpy(T, Tt, sizeof(T));
+            memcpy(ne, nt, sizeof(ne));
+            ++taken;
+            const double s = 2.0 * rho - 1.0, f = 1.0 - s * s * s;
+            mu *= f > 1.0 / 3.0 ? f : 1.0 / 3.0;
+            nu = 2.0;
+        } else {
+            mu *= nu;
+            nu *= 2.0;
+        }
+    }
+    *cost = ne[28] > 0 ? ne[27] / ne[28] : INFINITY;
+    memcpy(T_out, T, sizeof(T));
+    if (info) { info[0] = taken; info[1] = (int64_t)ne[28]; }
+    return status;
+}
+
 /*
  * Gauss-Newton alignment of B's registration points to A's ESDF.
  * T maps B coordinates to A coordinates.  Each iteration: normal equations
@@ -1447,6 +1548,7 @@ int orc_solve_xyz_yaw(const double ne[29], double d[6])
 int orc_align_points(const orc_submap *A, const void *pts, int64_t n_pts, const double *T_init,
                      double *T_out, double *cost, int64_t *info)
 {
+    if (A->p.align_solver == 1) return align_lm(A, pts, n_pts, T_init, T_out, cost, info);
     double T[16];
     memcpy(T, T_init, sizeof(T));
     int status = ORC_NOT_CONVERGED;

@@ -27,6 +27,7 @@ FP32, FP16 = 0, 1
 WEIGHT_CONSTANT, WEIGHT_INV_DEPTH2 = 0, 1
 PROJECTIVE, RAYCAST = 0, 1
 ESDF_EXACT, ESDF_WAVEFRONT = 0, 1
+GAUSS_NEWTON, LEVENBERG_MARQUARDT = 0, 1
 KERNELS = ["probe", "scan", "integrate", "esdf_page", "esdf_sites", "edt_x", "edt_y", "edt_z", "iso", "align",
            "summary", "net", "ray_mark", "ray_accum", "ray_apply", "pgo", "wavefront", "hash"]
 
@@ -43,7 +44,7 @@ class covox_params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("n_min", ctypes.c_int32),
                 ("tol_rho", ctypes.c_double), ("tol_theta", ctypes.c_double), ("align_dof", ctypes.c_int32),
                 ("weight_mode", ctypes.c_int32), ("integrator", ctypes.c_int32), ("ray_carve", ctypes.c_int32),
-                ("esdf_mode", ctypes.c_int32)]
+                ("esdf_mode", ctypes.c_int32), ("align_solver", ctypes.c_int32)]
 
 
 class covox_align_stats(ctypes.Structure):
@@ -216,7 +217,8 @@ class Context:
 
     def set_params(self, **kw):
         """Changes non-storage parameters (w_reg, max_iter, n_min, tol_rho,
-        tol_theta, align_dof, weight_mode, integrator, ray_carve, esdf_mode)."""
+        tol_theta, align_dof, weight_mode, integrator, ray_carve, esdf_mode,
+        align_solver)."""
         p = covox_params.from_buffer_copy(self.params)
         for k, v in kw.items():
             setattr(p, k, v)

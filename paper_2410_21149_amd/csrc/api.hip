@@ -195,6 +195,10 @@ bool valid_params(const covox_params *p, std::string &why)
         why = "esdf_mode must be COVOX_ESDF_EXACT or COVOX_ESDF_WAVEFRONT";
         return false;
     }
+    if (p->align_solver != COVOX_GAUSS_NEWTON && p->align_solver != COVOX_LEVENBERG_MARQUARDT) {
+        why = "align_solver must be COVOX_GAUSS_NEWTON or COVOX_LEVENBERG_MARQUARDT";
+        return false;
+    }
     return true;
 }
 
@@ -374,6 +378,7 @@ void covox_default_params(covox_params *p)
     p->integrator = COVOX_PROJECTIVE;
     p->ray_carve = 1;
     p->esdf_mode = COVOX_ESDF_EXACT;
+    p->align_solver = COVOX_GAUSS_NEWTON;
 }
 
 const char *covox_status_string(int s)

@@ -285,8 +285,9 @@ __device__ __forceinline__ void residual_u(const float *Tf, const float *pts, in
 }
 
 // 4-DoF step (translation and yaw): rows and columns 0, 1, 2, 5 of the
-// normal equations by Cholesky; x = (rho, 0, 0, theta_z).
-__device__ bool solve_xyz_yaw(const double *ne, double x[6])
+// normal equations, diagonal damped by mu (0: Gauss-Newton), by Cholesky;
+// x = (rho, 0, 0, theta_z).
+__device__ bool solve_xyz_yaw(const double *ne, double mu, double x[6])
 {
     const int sel[4] = {0, 1, 2, 5};
     double H[4][4], b[4], L[4][4];
@@ -299,6 +300,8 @@ __device__ bool solve_xyz_yaw(const double *ne, double x[6])
         }
         b[a] = ne[21 + sel[a]];
     }
+    if (mu != 0.0)
+        for (int a = 0; a < 4; ++a) H[a][a] = H[a][a] + mu * H[a][a];
     for (int j = 0; j < 4; ++j) {
         double sj = H[j][j];
         for (int k = 0; k < j; ++k) sj -= L[j][k] * L[j][k];
@@ -326,8 +329,9 @@ __device__ bool solve_xyz_yaw(const double *ne, double x[6])
     return true;
 }
 
-// 6x6 Cholesky solve of H x = -b (H from the packed upper triangle).
-__device__ bool solve6(const double *ne, double x[6])
+// 6x6 Cholesky solve of (H + mu diag(H)) x = -b (H from the packed upper
+// triangle; mu = 0 is the Gauss-Newton step).
+__device__ bool solve6(const double *ne, double mu, double x[6])
 {
     double L[6][6];
     for (int j = 0; j < 6; ++j) {
@@ -339,6 +343,7 @@ __device__ bool solve6(const double *ne, double x[6])
     };
     for (int j = 0; j < 6; ++j) {
         double s = Hat(j, j);
+        if (mu != 0.0) s = s + mu * s;
         for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
         if (!(s > 0.0)) return false;
         L[j][j] = sqrt(s);
@@ -360,6 +365,23 @@ __device__ bool solve6(const double *ne, double x[6])
         x[i] = t / L[i][i];
     }
     return true;
+}
+
+// Decrease of the sum of squares that the linear model predicts for the step
+// d: -(2 d.b + d.H.d), from the packed normal equations.
+__device__ double lm_predicted(const double *ne, const double d[6])
+{
+    double g = 0.0, q = 0.0;
+    for (int a = 0; a < 6; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < 6; ++b) {
+            const int r = a < b ? a : b, c = a < b ? b : a;
+            s += ne[r * 6 - r * (r - 1) / 2 + (c - r)] * d[b];
+        }
+        q += d[a] * s;
+        g += d[a] * ne[21 + a];
+    }
+    return -(2.0 * g + q);
 }
 
 // T <- Exp(xi) T for xi = (rho, theta); T is the top 3x4 of a rigid
@@ -402,7 +424,11 @@ __device__ void se3_left_update(const double xi[6], double T[12])
 
 // One workgroup of kAlignThreads lanes per problem (pair and start); each
 // lane takes U points per step (same points, same order, for every U).
-template <int kAlignThreads, int U>
+// LM = false: Gauss-Newton, every solve taken.  LM = true: Levenberg-
+// Marquardt (the trust-region least squares Sec. III-F names): the solve is
+// damped by mu diag(H), its trial pose is evaluated, and the step is taken
+// when the mean cost falls (gain ratio > 0); max_iter then caps the solves.
+template <int kAlignThreads, int U, bool LM>
 __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__restrict__ probs,
                                                          const int32_t *__restrict__ order, AlignResult *res,
                                                          float vs, double tol_rho, double tol_theta, int n_min,
@@ -412,7 +438,9 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__r
     __shared__ float sTf[12];
     __shared__ double red[kAlignThreads / 64][29];
     __shared__ double tot[29];
-    __shared__ int s_state[3];  // final flag, iterations, status
+    __shared__ int s_state[3];  // final flag, iterations (LM: solves), status
+    __shared__ double sPrev[29], sTt[12], sD[6], sMu[2];  // LM: accepted sums, trial pose, step, mu and nu
+    __shared__ int s_lm[2];                               // LM: accepted sums present, steps taken
     const int pid = order[blockIdx.x];
     const AlignProblem &P = probs[pid];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -425,6 +453,12 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__r
         s_state[0] = 0;
         s_state[1] = 0;
         s_state[2] = COVOX_NOT_CONVERGED;
+        if (LM) {
+            s_lm[0] = 0;
+            s_lm[1] = 0;
+            sMu[0] = 1e-4;
+            sMu[1] = 2.0;
+        }
     }
     __syncthreads();
     for (;;) {
@@ -473,7 +507,65 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__r
         }
         __syncthreads();
         bool stop = false;
-        if (tid == 0) {
+        if (LM && tid == 0) {
+            bool solve = true;
+            if (!s_lm[0]) {  // sums at the start pose
+                if (P.max_iter <= 0) {
+                    stop = true;
+                    solve = false;
+                } else if (tot[28] < (double)n_min) {
+                    s_state[2] = COVOX_EDEGENERATE;
+                    stop = true;
+                    solve = false;
+                } else {
+                    for (int k = 0; k < 29; ++k) sPrev[k] = tot[k];
+                    s_lm[0] = 1;
+                }
+            } else {  // sums at the trial pose: take the step or raise the damping
+                const double pred = lm_predicted(sPrev, sD);
+                double rho = -1.0;
+                if (tot[28] >= (double)n_min && pred > 0.0)
+                    rho = (sPrev[27] / sPrev[28] - tot[27] / tot[28]) / (pred / sPrev[28]);
+                if (rho > 0.0) {
+                    for (int k = 0; k < 12; ++k) sT[k] = sTt[k];
+                    for (int k = 0; k < 29; ++k) sPrev[k] = tot[k];
+                    s_lm[1] += 1;
+                    const double s = 2.0 * rho - 1.0, f = 1.0 - s * s * s;
+                    sMu[0] *= f > 1.0 / 3.0 ? f : 1.0 / 3.0;
+                    sMu[1] = 2.0;
+                } else {
+                    sMu[0] *= sMu[1];
+                    sMu[1] *= 2.0;
+                }
+            }
+            if (solve) {
+                double dl[6];
+                if (s_state[1] >= P.max_iter) {
+                    stop = true;
+                } else if (!(dof == 4 ? solve_xyz_yaw(sPrev, sMu[0], dl) : solve6(sPrev, sMu[0], dl))) {
+                    s_state[2] = COVOX_EDEGENERATE;
+                    stop = true;
+                } else {
+                    s_state[1] += 1;
+                    const double nr = sqrt(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
+                    const double nt = sqrt(dl[3] * dl[3] + dl[4] * dl[4] + dl[5] * dl[5]);
+                    if (nr < tol_rho && nt < tol_theta) {
+                        s_state[2] = COVOX_OK;  // converged; the step is not taken
+                        stop = true;
+                    } else {
+                        double T[12];
+                        for (int k = 0; k < 12; ++k) T[k] = sT[k];
+                        se3_left_update(dl, T);
+                        for (int k = 0; k < 6; ++k) sD[k] = dl[k];
+                        for (int k = 0; k < 12; ++k) {
+                            sTt[k] = T[k];
+                            sTf[k] = (float)T[k];
+                        }
+                    }
+                }
+            }
+            red[0][0] = stop ? 1.0 : 0.0;
+        } else if (tid == 0) {
             if (s_state[0] || s_state[1] >= P.max_iter) {
                 stop = true;
             } else if (tot[28] < (double)n_min) {
@@ -481,7 +573,7 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__r
                 stop = true;
             } else {
                 double dl[6];
-                if (!(dof == 4 ? solve_xyz_yaw(tot, dl) : solve6(tot, dl))) {
+                if (!(dof == 4 ? solve_xyz_yaw(tot, 0.0, dl) : solve6(tot, 0.0, dl))) {
                     s_state[2] = COVOX_EDEGENERATE;
                     stop = true;
                 } else {
@@ -510,12 +602,14 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__r
     }
     if (tid == 0) {
         AlignResult &R = res[pid];
+        const bool acc = LM && s_lm[0];  // LM: the sums of the accepted pose
+        const double *ne = acc ? sPrev : tot;
         for (int k = 0; k < 12; ++k) R.T[k] = sT[k];
         R.T[12] = 0; R.T[13] = 0; R.T[14] = 0; R.T[15] = 1;
-        for (int k = 0; k < 29; ++k) R.ne[k] = tot[k];
-        R.n_used = (int64_t)tot[28];
-        R.cost = tot[28] > 0 ? tot[27] / tot[28] : __builtin_inf();
-        R.iters = s_state[1];
+        for (int k = 0; k < 29; ++k) R.ne[k] = ne[k];
+        R.n_used = (int64_t)ne[28];
+        R.cost = ne[28] > 0 ? ne[27] / ne[28] : __builtin_inf();
+        R.iters = acc ? s_lm[1] : s_state[1];
         R.status = s_state[2];
     }
 }
@@ -685,22 +779,24 @@ int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult 
         AlignResult *dres = (AlignResult *)ctx->res_dev;
         const float vs = (float)ctx->p.voxel_size;
         const double tr = ctx->p.tol_rho, tt = ctx->p.tol_theta;
-        const int nm = ctx->p.n_min, dof = ctx->p.align_dof;
+        const int nm = ctx->p.n_min, dof = ctx->p.align_dof, lm = ctx->p.align_solver == COVOX_LEVENBERG_MARQUARDT;
         const bool two = ctx->tune.align_points_per_step == 2;
-        if (ctx->tune.align_threads == 512) {
-            if (two)
-                hipLaunchKernelGGL((k_align<512, 2>), dim3(n), dim3(512), 0, ctx->stream, dprob, dorder, dres, vs, tr,
-                                   tt, nm, dof);
-            else
-                hipLaunchKernelGGL((k_align<512, 1>), dim3(n), dim3(512), 0, ctx->stream, dprob, dorder, dres, vs, tr,
-                                   tt, nm, dof);
-        } else {
-            if (two)
-                hipLaunchKernelGGL((k_align<256, 2>), dim3(n), dim3(256), 0, ctx->stream, dprob, dorder, dres, vs, tr,
-                                   tt, nm, dof);
-            else
-                hipLaunchKernelGGL((k_align<256, 1>), dim3(n), dim3(256), 0, ctx->stream, dprob, dorder, dres, vs, tr,
-                                   tt, nm, dof);
+        const int shape = (ctx->tune.align_threads == 512 ? 4 : 0) + (two ? 2 : 0) + (lm ? 1 : 0);
+        switch (shape) {
+#define COVOX_ALIGN_LAUNCH(S, NT, U, L)                                                                          \
+    case S:                                                                                                    \
+        hipLaunchKernelGGL((k_align<NT, U, L>), dim3(n), dim3(NT), 0, ctx->stream, dprob, dorder, dres, vs, tr, \
+                           tt, nm, dof);                                                                       \
+        break;
+            COVOX_ALIGN_LAUNCH(0, 256, 1, false)
+            COVOX_ALIGN_LAUNCH(1, 256, 1, true)
+            COVOX_ALIGN_LAUNCH(2, 256, 2, false)
+            COVOX_ALIGN_LAUNCH(3, 256, 2, true)
+            COVOX_ALIGN_LAUNCH(4, 512, 1, false)
+            COVOX_ALIGN_LAUNCH(5, 512, 1, true)
+            COVOX_ALIGN_LAUNCH(6, 512, 2, false)
+            COVOX_ALIGN_LAUNCH(7, 512, 2, true)
+#undef COVOX_ALIGN_LAUNCH
         }
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "align launch"))) return rc;
