@@ -1,8 +1,9 @@
 """GPU parity of the Levenberg-Marquardt alignment mode (align_solver =
 LEVENBERG_MARQUARDT): poses, status, steps taken and residual counts against
 the oracle for plain, multi-start, batched, 4-DoF and far starts (the last
-with rejected steps), on both workgroup sizes; the Gauss-Newton default is
-unchanged after switching back."""
+with rejected steps), on both workgroup sizes; a repeated call gives the
+same result bit for bit; the Gauss-Newton default is unchanged after
+switching back."""
 import math
 
 import numpy as np
@@ -60,6 +61,8 @@ def test_lm_alignment_parity(cv):
             ctx.set_tuning(align_threads=lanes, align_points_per_step=1 if lanes == 256 else 2)
             Tg, cg, st = ctx.align_submaps(A, B, T0)
             _check(st, Tg, cg, r)
+            T2, c2, s2 = ctx.align_submaps(A, B, T0)  # a second call: bit for bit
+            assert np.array_equal(T2, Tg) and c2 == cg and s2["iterations"] == st["iterations"]
         if i < 2:  # near starts recover the identity (near the optimum the rejected
             # steps of binary32 pose noise can use up the solve cap: NOT_CONVERGED)
             assert _pose_err(Tg, np.eye(4))[0] < 0.01
