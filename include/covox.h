@@ -338,6 +338,10 @@ int covox_summaries(covox_ctx *ctx, const covox_summary_req *reqs, int32_t n);
  * cores with FP32 accumulation; FP32 master weights, FP32 backward, Adam.
  * Weights are initialised from `seed` (He-uniform, SplitMix64). */
 int covox_net_create(covox_ctx *ctx, uint64_t seed, covox_net **out);
+/* covox_destroy frees the device memory of every net of the context; such
+ * a net's handle stays valid for covox_net_destroy (which then frees only
+ * the handle) and covox_net_num_params, and every other call on it returns
+ * COVOX_EINVAL. */
 void covox_net_destroy(covox_net *net);
 int64_t covox_net_num_params(const covox_net *net);
 int covox_net_get_params(covox_net *net, float *host, int64_t n);
@@ -360,8 +364,12 @@ int covox_net_gradients(covox_net *net, const float *x_dev, const float *y_dev, 
  * network's correction C = (t, Rz(yaw)) in grid coordinates gives the
  * proposal T_A_grid C T_A_grid^-1 T_init, refined by single-start alignment;
  * pairs whose refined cost exceeds cost_thr (or that are degenerate) fall
- * back to n_starts-start alignment from T_init.  stats[i].best_start = -1
- * when the refined proposal was kept.  Synchronous. */
+ * back to n_starts-start alignment from T_init, and the refined proposal
+ * competes with those starts under the multi-start selection rule (it wins
+ * ties), so a fallback never returns a higher cost than the refined pose.
+ * stats[i].best_start = -1 when the refined proposal was kept, else the
+ * chosen start.  A net whose context was destroyed is rejected (EINVAL), as
+ * is a net of another context.  Synchronous. */
 int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell,
                         double cost_thr, int32_t n_starts, double *T_out, double *cost, covox_align_stats *stats);
 

@@ -8,6 +8,7 @@ at import time -- there is no fallback path.
 from __future__ import annotations
 
 import ctypes
+import weakref
 import math
 import os
 
@@ -208,6 +209,7 @@ class Context:
         self.handle = h
         self.set_stream(stream if stream is not None else torch.cuda.current_stream())
         self._subs = []
+        self._nets = weakref.WeakSet()
 
     # -- plumbing
     def _check(self, rc, what, ok=(OK,)):
@@ -235,6 +237,8 @@ class Context:
                 g.close()
             for s in self._subs:
                 s.handle = None
+            for n in list(getattr(self, "_nets", ())):
+                n.close()
             _lib.covox_destroy(self.handle)
             self.handle = None
 
@@ -570,6 +574,7 @@ class Net:
         h = _vp()
         ctx._check(_lib.covox_net_create(ctx.handle, seed, ctypes.byref(h)), "net_create")
         self.handle = h
+        ctx._nets.add(self)
 
     def close(self):
         if getattr(self, "handle", None):

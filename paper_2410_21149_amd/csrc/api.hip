@@ -428,6 +428,10 @@ void covox_destroy(covox_ctx *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     auto &subs = submaps_of(ctx);
     for (covox_submap *s : std::vector<covox_submap *>(subs)) covox_submap_destroy(s);
+    // Networks outlive nothing of the context: their device memory goes now,
+    // and their handles stay valid for covox_net_destroy alone.
+    for (covox_net *net : ctx->nets) net_detach(net);
+    ctx->nets.clear();
     for (void *ptr : {(void *)ctx->cand, (void *)ctx->t_key, (void *)ctx->t_idx, (void *)ctx->sites[0], (void *)ctx->g1,
                       (void *)ctx->g2, (void *)ctx->cnt, (void *)ctx->psum, ctx->prob_dev, ctx->res_dev, ctx->sum_dev,
                       (void *)ctx->net_in, (void *)ctx->net_out, (void *)ctx->train_y, (void *)ctx->loss_hist,
@@ -917,38 +921,38 @@ int64_t covox_net_num_params(const covox_net *net) { return net ? net_num_params
 
 int covox_net_get_params(covox_net *net, float *host, int64_t n)
 {
-    if (net) COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_get_params");
-    if (!net || !host) return COVOX_EINVAL;
+    if (!net || !net_ctx(net) || !host) return COVOX_EINVAL;
+    COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_get_params");
     return net_get_params(net, host, n);
 }
 
 int covox_net_set_params(covox_net *net, const float *host, int64_t n)
 {
-    if (net) COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_set_params");
-    if (!net || !host) return COVOX_EINVAL;
+    if (!net || !net_ctx(net) || !host) return COVOX_EINVAL;
+    COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_set_params");
     return net_set_params(net, host, n);
 }
 
 int covox_net_forward(covox_net *net, const float *x_dev, int32_t n, float *out_dev)
 {
-    if (net) COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_forward");
-    if (!net || !x_dev || !out_dev || n <= 0) return COVOX_EINVAL;
+    if (!net || !net_ctx(net) || !x_dev || !out_dev || n <= 0) return COVOX_EINVAL;
+    COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_forward");
     return net_forward_api(net, x_dev, n, out_dev);
 }
 
 int covox_net_train_step(covox_net *net, const float *x_dev, const float *y_dev, int32_t n, float lr, float trans_scale,
                          float *loss_host)
 {
-    if (net) COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_train_step");
-    if (!net || !x_dev || !y_dev || n <= 0 || !(trans_scale > 0)) return COVOX_EINVAL;
+    if (!net || !net_ctx(net) || !x_dev || !y_dev || n <= 0 || !(trans_scale > 0)) return COVOX_EINVAL;
+    COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_train_step");
     return net_train_step(net, x_dev, y_dev, n, lr, trans_scale, loss_host);
 }
 
 int covox_net_gradients(covox_net *net, const float *x_dev, const float *y_dev, int32_t n, float trans_scale,
                         float *grad_host, float *loss_host)
 {
-    if (net) COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_gradients");
-    if (!net || !x_dev || !y_dev || !grad_host || n <= 0 || !(trans_scale > 0)) return COVOX_EINVAL;
+    if (!net || !net_ctx(net) || !x_dev || !y_dev || !grad_host || n <= 0 || !(trans_scale > 0)) return COVOX_EINVAL;
+    COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_gradients");
     return net_grads(net, x_dev, y_dev, n, trans_scale, grad_host, loss_host);
 }
 
@@ -1069,7 +1073,7 @@ double draw(uint64_t seed, uint64_t item, int k)
 int covox_propose(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell, double *T_prop)
 {
     COVOX_NOT_DURING_CAPTURE(ctx, "propose");
-    if (!ctx || !net || (!pairs && n > 0) || n < 0 || !(cell > 0) || (!T_prop && n > 0))
+    if (!ctx || !net || net_ctx(net) != ctx || (!pairs && n > 0) || n < 0 || !(cell > 0) || (!T_prop && n > 0))
         return fail(ctx, COVOX_EINVAL, "propose: bad argument");
     int rc = prepare_learned(ctx, pairs, n, "propose");
     if (rc) return rc;
@@ -1083,8 +1087,8 @@ int covox_train_proposal(covox_ctx *ctx, covox_net *net, const covox_train_cfg *
                          int32_t n, float *loss_host)
 {
     COVOX_NOT_DURING_CAPTURE(ctx, "train_proposal");
-    if (!ctx || !net || !cfg || !pairs || n <= 0 || cfg->steps < 0 || cfg->batch < 1 || cfg->batch > kLearnChunk ||
-        !(cfg->cell > 0) || !(cfg->trans_scale > 0) || !(cfg->lr >= 0) || !(cfg->trans_xy >= 0) ||
+    if (!ctx || !net || net_ctx(net) != ctx || !cfg || !pairs || n <= 0 || cfg->steps < 0 || cfg->batch < 1 ||
+        cfg->batch > kLearnChunk || !(cfg->cell > 0) || !(cfg->trans_scale > 0) || !(cfg->lr >= 0) || !(cfg->trans_xy >= 0) ||
         !(cfg->trans_z >= 0) || !(cfg->yaw >= 0) || !(cfg->tilt >= 0))
         return fail(ctx, COVOX_EINVAL, "train_proposal: bad argument");
     int rc = prepare_learned(ctx, pairs, n, "train_proposal");
@@ -1149,7 +1153,8 @@ int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs,
                         double cost_thr, int32_t n_starts, double *T_out, double *cost, covox_align_stats *stats)
 {
     COVOX_NOT_DURING_CAPTURE(ctx, "align_learned");
-    if (!ctx || !net || (!pairs && n > 0) || n < 0 || !(cell > 0) || n_starts < 1 || !T_out || !cost)
+    if (!ctx || !net || net_ctx(net) != ctx || (!pairs && n > 0) || n < 0 || !(cell > 0) || n_starts < 1 || !T_out ||
+        !cost)
         return fail(ctx, COVOX_EINVAL, "align_learned: bad argument");
     int rc = prepare_learned(ctx, pairs, n, "align_learned");
     if (rc) return rc;
@@ -1181,12 +1186,17 @@ int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs,
         }
         std::vector<AlignResult> r2(prs.size());
         if ((rc = run_alignment(ctx, prs.data(), (int)prs.size(), r2.data()))) return rc;
+        // The refined proposal competes with the starts under the start
+        // selection rule (candidate 0; ties keep it), so a fallback never
+        // returns a pose of higher cost than the one it already had.
+        std::vector<AlignResult> cand((size_t)n_starts + 1);
         for (size_t j = 0; j < fb.size(); ++j) {
-            const AlignResult *r = &r2[j * n_starts];
-            const int b = n_starts == 1 ? 0 : select_start(r, n_starts);
-            if (b >= 0) {
-                res[fb[j]] = r[b];
-                best[fb[j]] = b;
+            cand[0] = res[fb[j]];
+            for (int k = 0; k < n_starts; ++k) cand[1 + k] = r2[j * n_starts + k];
+            const int b = select_start(cand.data(), n_starts + 1);
+            if (b >= 1) {
+                res[fb[j]] = cand[b];
+                best[fb[j]] = b - 1;
             }
         }
     }

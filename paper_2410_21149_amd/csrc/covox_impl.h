@@ -257,6 +257,7 @@ struct covox_ctx {
     hipStream_t stream = nullptr;
     std::string last_error;
     std::vector<covox_submap *> subs;  // live submaps of this context
+    std::vector<covox_net *> nets;     // live networks of this context (detached by covox_destroy)
     // integration scratch
     uint32_t *cand = nullptr;
     int64_t cand_cap = 0;
@@ -486,8 +487,11 @@ int run_summaries(covox_ctx *ctx, const SummaryReq *reqs, int n);
 
 // k_net.hip
 int net_create(covox_ctx *ctx, uint64_t seed, covox_net **out);
-covox_ctx *net_ctx(const covox_net *net);
+covox_ctx *net_ctx(const covox_net *net);  // nullptr once the context is destroyed
 void net_destroy(covox_net *net);
+// Frees the device memory of a network whose context is being destroyed and
+// clears its context; the handle stays valid for net_destroy only.
+void net_detach(covox_net *net);
 int64_t net_num_params(const covox_net *net);
 int net_get_params(covox_net *net, float *host, int64_t n);
 int net_set_params(covox_net *net, const float *host, int64_t n);

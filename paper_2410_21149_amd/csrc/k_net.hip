@@ -335,7 +335,8 @@ static int net_reserve(covox_net *net, int n)
 {
     if (n <= net->batch_cap) return COVOX_OK;
     covox_ctx *ctx = net->ctx;
-    hipStreamSynchronize(ctx->stream);
+    int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "net reserve sync");  // readers of the old buffers
+    if (rc) return rc;
     auto fr = [](void *p) { if (p) (void)hipFree(p); };
     fr(net->x0); fr(net->pooled); fr(net->out); fr(net->dout); fr(net->loss);
     for (int l = 0; l < kLayers; ++l) { fr(net->a[l]); fr(net->d[l]); net->a[l] = nullptr; net->d[l] = nullptr; }
@@ -536,22 +537,48 @@ int net_create(covox_ctx *ctx, uint64_t seed, covox_net **out)
         return fail(ctx, COVOX_EHIP, std::string("net_create upload: ") + hipGetErrorString(e));
     }
     refresh_bf16(net);
+    int rc = hip_check(ctx, hipGetLastError(), "net init");
+    if (rc) {
+        net_destroy(net);
+        return rc;
+    }
+    ctx->nets.push_back(net);
     *out = net;
-    return hip_check(ctx, hipGetLastError(), "net init");
+    return COVOX_OK;
+}
+
+static void net_free_device(covox_net *net)
+{
+    for (float **p : {&net->w, &net->g, &net->m, &net->v, &net->pooled, &net->out, &net->dout, &net->loss}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    if (net->x0) (void)hipFree(net->x0);
+    net->x0 = nullptr;
+    for (int l = 0; l < kLayers; ++l) {
+        for (void **p : {(void **)&net->wb[l], (void **)&net->a[l], (void **)&net->d[l]}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+    }
+    net->batch_cap = 0;
+}
+
+void net_detach(covox_net *net)
+{
+    if (!net) return;
+    net_free_device(net);
+    net->ctx = nullptr;
 }
 
 void net_destroy(covox_net *net)
 {
     if (!net) return;
-    if (net->ctx) (void)hipStreamSynchronize(net->ctx->stream);
-    for (void *p : {(void *)net->w, (void *)net->g, (void *)net->m, (void *)net->v, (void *)net->x0, (void *)net->pooled,
-                    (void *)net->out, (void *)net->dout, (void *)net->loss})
-        if (p) (void)hipFree(p);
-    for (int l = 0; l < kLayers; ++l) {
-        if (net->wb[l]) (void)hipFree(net->wb[l]);
-        if (net->a[l]) (void)hipFree(net->a[l]);
-        if (net->d[l]) (void)hipFree(net->d[l]);
+    if (covox_ctx *ctx = net->ctx) {
+        (void)hipStreamSynchronize(ctx->stream);
+        ctx->nets.erase(std::remove(ctx->nets.begin(), ctx->nets.end(), net), ctx->nets.end());
     }
+    net_free_device(net);
     delete net;
 }
 
