@@ -124,6 +124,11 @@ def _load():
         L.orc_esdf_wavefront.argtypes = [_vp, _i64p]
         L.orc_ray_walk32.restype = ctypes.c_int64
         L.orc_ray_walk32.argtypes = [_fp, _fp, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i64p, ctypes.c_int64]
+        L.orc_ray_walk32_fragile.restype = ctypes.c_int64
+        L.orc_ray_walk32_fragile.argtypes = [_fp, _fp, ctypes.c_float, ctypes.c_float, ctypes.c_float, _i64p,
+                                             ctypes.c_int64, _i64p, ctypes.c_int64, _i64p]
+        L.orc_fragile_voxels.restype = ctypes.c_int64
+        L.orc_fragile_voxels.argtypes = [_vp, _i64p, ctypes.c_int64]
         L.orc_pose_cam_sub.restype = None
         L.orc_pose_cam_sub.argtypes = [_dp, _dp, _dp]
         _lib = L
@@ -200,6 +205,16 @@ class Submap:
 
     def update_esdf(self):
         _load().orc_update_esdf(self._h)
+
+    def fragile_voxels(self) -> np.ndarray:
+        """Voxels (n, 3), with repeats, next to the fragile steps of every
+        raycast walk so far: where another faithful rounding of the crossing
+        parameters could visit a different voxel (see ray_walk32)."""
+        L = _load()
+        n = int(L.orc_fragile_voxels(self._h, None, 0))
+        out = np.zeros((max(n, 1), 3), np.int64)
+        L.orc_fragile_voxels(self._h, _p(out, _i64p), n)
+        return out[:n]
 
     def esdf_wavefront(self) -> dict:
         """One incremental (wavefront) ESDF update; returns its round count,
@@ -278,16 +293,25 @@ def align_multistart(A: Submap, pts, T_init, n_starts=8):
             "n": int(info[1]), "best": best.value, "starts": starts.reshape(n_starts, 4, 4)}
 
 
-def ray_walk32(o, u, s0, s1, vs) -> np.ndarray:
+def ray_walk32(o, u, s0, s1, vs, fragile=False):
     """Voxel indices (n, 3) crossed by the binary32 ray segment o + s u,
-    s in [s0, s1], in walk order."""
+    s in [s0, s1], in walk order (Amanatides-Woo with correctly rounded
+    crossing parameters).  With fragile=True also the voxels (m, 3) that
+    another faithful rounding of the crossing parameters could visit
+    instead: returns (walk, fragile_voxels)."""
     o = np.ascontiguousarray(o, np.float32)
     u = np.ascontiguousarray(u, np.float32)
     s0, s1, vs = np.float32(s0), np.float32(s1), np.float32(vs)
     cap = 3 * int(np.ceil(np.float32(s1 - s0) / vs)) + 6
     out = np.zeros((cap, 3), np.int64)
-    n = _load().orc_ray_walk32(_p(o, _fp), _p(u, _fp), s0, s1, vs, _p(out, _i64p), cap)
-    return out[:n]
+    if not fragile:
+        n = _load().orc_ray_walk32(_p(o, _fp), _p(u, _fp), s0, s1, vs, _p(out, _i64p), cap)
+        return out[:n]
+    fr = np.zeros((7 * cap, 3), np.int64)
+    nf = np.zeros(1, np.int64)
+    n = _load().orc_ray_walk32_fragile(_p(o, _fp), _p(u, _fp), s0, s1, vs, _p(out, _i64p), cap, _p(fr, _i64p),
+                                       7 * cap, _p(nf, _i64p))
+    return out[:n], fr[:int(nf[0])]
 
 
 def se3_exp(xi) -> np.ndarray:

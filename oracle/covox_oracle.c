@@ -97,6 +97,9 @@ typedef struct {
     int32_t *wpar;      /* parent site as a packed offset from the voxel, or WF_NONE */
     uint8_t *wsite;     /* site flag at the last update */
     int64_t wn;         /* blocks at the last update */
+    /* raycasting: voxels next to fragile walk steps (x, y, z triples), all frames */
+    int64_t *frag;
+    int64_t n_frag, frag_cap;
 } orc_submap;
 
 /* ------------------------------------------------------------ keys */
@@ -271,7 +274,7 @@ void orc_submap_destroy(orc_submap *s)
     free(s->keys); free(s->skeys); free(s->sidx);
     free(s->D); free(s->W); free(s->D64); free(s->W64);
     free(s->phi); free(s->phi64); free(s->ksq);
-    free(s->wk); free(s->wpar); free(s->wsite);
+    free(s->wk); free(s->wpar); free(s->wsite); free(s->frag);
     free(s);
 }
 
@@ -522,69 +525,143 @@ int orc_integrate(orc_submap *s, const float *depth, int H, int W, const float K
 
 /*
  * Voxels crossed by the segment o + s u, s in [s0, s1], of a ray with unit
- * direction u (binary32): the grid traversal of Amanatides and Woo
- * (Eurographics 1987).  The start voxel holds o + s0 u; the parameter of the
- * next boundary along axis a is computed from the voxel index itself,
- *   s_a = ((i_a + [u_a > 0]) vs - o_a) * (1 / u_a)   (infinite when u_a = 0,
- *   the reciprocal rounded once per ray),
- * the smallest s_a (x before y before z on ties) moves that axis by one, and
- * the walk ends once that smallest s_a is not below s1.  At most max_out
- * voxels (3 ceil((s1 - s0) / vs) + 6 bounds the walk) are written to out as
- * (x, y, z) triples; returns the number written.
+ * direction u: the grid traversal of Amanatides and Woo (Eurographics 1987).
+ * The walk starts in the voxel holding o + s0 u.  In voxel i the ray leaves
+ * through the boundary plane of axis a at the parameter that solves
+ * o_a + s u_a = (i_a + [u_a > 0]) vs, that is
+ *   s_a = ((i_a + [u_a > 0]) vs - o_a) / u_a
+ * (one correctly rounded division; infinite when u_a = 0).  The smallest s_a
+ * (x before y before z on ties) moves axis a by one voxel; the walk ends once
+ * that smallest s_a is not below s1.  At most max_out voxels (3 ceil((s1 -
+ * s0) / vs) + 6 bounds the walk) are written to out as (x, y, z) triples;
+ * returns the number written.
+ *
+ * Fragile steps.  A different but still faithful rounding of the crossing
+ * parameters (each within eps/2 of the exact quotient, relative) can change a
+ * step only where two candidates are that close.  With m the smallest s_a
+ * and eps = 2^-21 (binary32; 2^-50 in binary64), axis a is in doubt when
+ * s_a - m <= eps |s_a|, and the end test when |m - s1| <= eps max(|m|, |s1|).
+ * At a step where two or more axes are in doubt, or the end test is, every
+ * voxel another choice could enter next is appended to frag (nullable; at
+ * most max_frag triples, *n_frag counts them all): i moved along a subset of
+ * the axes in doubt -- the proper non-empty subsets, or all non-empty subsets
+ * when the end test is in doubt too (then the walk may stop before any).
  */
-int64_t orc_ray_walk32(const float o[3], const float u[3], float s0, float s1, float vs, int64_t *out,
-                       int64_t max_out)
+static void walk_frag(const int64_t i[3], const int step[3], const int doubt[3], int end_doubt, int64_t *frag,
+                      int64_t max_frag, int64_t *n_frag)
 {
+    int nd = doubt[0] + doubt[1] + doubt[2];
+    if (nd < 2 && !end_doubt) return;
+    for (int mask = 1; mask < 8; ++mask) {
+        int ok = 1, full = 1;
+        for (int a = 0; a < 3; ++a) {
+            if ((mask >> a) & 1) ok &= doubt[a];
+            else if (doubt[a]) full = 0;
+        }
+        if (!ok || (full && !end_doubt)) continue;
+        if (frag && *n_frag < max_frag)
+            for (int a = 0; a < 3; ++a) frag[3 * *n_frag + a] = i[a] + (((mask >> a) & 1) ? step[a] : 0);
+        ++*n_frag;
+    }
+}
+
+static int64_t ray_walk32_frag(const float o[3], const float u[3], float s0, float s1, float vs, int64_t *out,
+                               int64_t max_out, int64_t *frag, int64_t max_frag, int64_t *n_frag)
+{
+    const float eps = 0x1p-21f;
     int64_t i[3];
     int step[3];
-    float sn[3], iu[3];
+    float sn[3];
     for (int a = 0; a < 3; ++a) {
         const float e = o[a] + s0 * u[a];
         i[a] = (int64_t)floorf(e / vs);
         step[a] = u[a] > 0.0f ? 1 : (u[a] < 0.0f ? -1 : 0);
-        iu[a] = step[a] ? 1.0f / u[a] : 0.0f;
-        sn[a] = step[a] ? (((float)(i[a] + (step[a] > 0)) * vs) - o[a]) * iu[a] : INFINITY;
     }
     int64_t n = 0;
     while (n < max_out) {
         out[3 * n + 0] = i[0]; out[3 * n + 1] = i[1]; out[3 * n + 2] = i[2];
         ++n;
+        for (int a = 0; a < 3; ++a)
+            sn[a] = step[a] ? (((float)(i[a] + (step[a] > 0)) * vs) - o[a]) / u[a] : INFINITY;
         int a = 0;
         if (sn[1] < sn[a]) a = 1;
         if (sn[2] < sn[a]) a = 2;
-        if (!(sn[a] < s1)) break;
+        const float m = sn[a];
+        int doubt[3];
+        for (int b = 0; b < 3; ++b) doubt[b] = step[b] && sn[b] - m <= eps * fabsf(sn[b]);
+        const int end_doubt = fabsf(m - s1) <= eps * fmaxf(fabsf(m), fabsf(s1));
+        if (n_frag) walk_frag(i, step, doubt, end_doubt, frag, max_frag, n_frag);
+        if (!(m < s1)) break;
         i[a] += step[a];
-        sn[a] = (((float)(i[a] + (step[a] > 0)) * vs) - o[a]) * iu[a];
     }
     return n;
 }
 
+int64_t orc_ray_walk32(const float o[3], const float u[3], float s0, float s1, float vs, int64_t *out,
+                       int64_t max_out)
+{
+    return ray_walk32_frag(o, u, s0, s1, vs, out, max_out, NULL, 0, NULL);
+}
+
+/* The walk with its fragile steps (frag: max_frag triples; returns the
+ * voxel count, *n_frag the fragile voxels). */
+int64_t orc_ray_walk32_fragile(const float o[3], const float u[3], float s0, float s1, float vs, int64_t *out,
+                               int64_t max_out, int64_t *frag, int64_t max_frag, int64_t *n_frag)
+{
+    *n_frag = 0;
+    return ray_walk32_frag(o, u, s0, s1, vs, out, max_out, frag, max_frag, n_frag);
+}
+
 /* The same walk in binary64. */
 static int64_t ray_walk64(const double o[3], const double u[3], double s0, double s1, double vs, int64_t *out,
-                          int64_t max_out)
+                          int64_t max_out, int64_t *frag, int64_t max_frag, int64_t *n_frag)
 {
+    const double eps = 0x1p-50;
     int64_t i[3];
     int step[3];
-    double sn[3], iu[3];
+    double sn[3];
     for (int a = 0; a < 3; ++a) {
         const double e = o[a] + s0 * u[a];
         i[a] = (int64_t)floor(e / vs);
         step[a] = u[a] > 0.0 ? 1 : (u[a] < 0.0 ? -1 : 0);
-        iu[a] = step[a] ? 1.0 / u[a] : 0.0;
-        sn[a] = step[a] ? (((double)(i[a] + (step[a] > 0)) * vs) - o[a]) * iu[a] : INFINITY;
     }
     int64_t n = 0;
     while (n < max_out) {
         out[3 * n + 0] = i[0]; out[3 * n + 1] = i[1]; out[3 * n + 2] = i[2];
         ++n;
+        for (int a = 0; a < 3; ++a)
+            sn[a] = step[a] ? (((double)(i[a] + (step[a] > 0)) * vs) - o[a]) / u[a] : INFINITY;
         int a = 0;
         if (sn[1] < sn[a]) a = 1;
         if (sn[2] < sn[a]) a = 2;
-        if (!(sn[a] < s1)) break;
+        const double m = sn[a];
+        int doubt[3];
+        for (int b = 0; b < 3; ++b) doubt[b] = step[b] && sn[b] - m <= eps * fabs(sn[b]);
+        const int end_doubt = fabs(m - s1) <= eps * fmax(fabs(m), fabs(s1));
+        if (n_frag) walk_frag(i, step, doubt, end_doubt, frag, max_frag, n_frag);
+        if (!(m < s1)) break;
         i[a] += step[a];
-        sn[a] = (((double)(i[a] + (step[a] > 0)) * vs) - o[a]) * iu[a];
     }
     return n;
+}
+
+static void frag_append(orc_submap *s, const int64_t *v, int64_t n)
+{
+    if (n <= 0) return;
+    if (s->n_frag + n > s->frag_cap) {
+        s->frag_cap = 2 * (s->n_frag + n);
+        s->frag = (int64_t *)realloc(s->frag, sizeof(int64_t) * 3 * s->frag_cap);
+    }
+    memcpy(s->frag + 3 * s->n_frag, v, sizeof(int64_t) * 3 * n);
+    s->n_frag += n;
+}
+
+/* Voxels next to fragile walk steps of all raycast frames so far (with
+ * repeats), up to cap triples; returns the count. */
+int64_t orc_fragile_voxels(const orc_submap *s, int64_t *out, int64_t cap)
+{
+    if (out) memcpy(out, s->frag, sizeof(int64_t) * 3 * (s->n_frag < cap ? s->n_frag : cap));
+    return s->n_frag;
 }
 
 typedef struct { uint64_t bkey; int64_t lin, pix; double t, w; } ray_contrib;
@@ -609,7 +686,8 @@ static int cmp_contrib(const void *a, const void *b)
  *     d = R_sc q, r = |d|, u = d / r, origin o = t_sc (submap frame);
  *   segment s in [s0, r + tau], s0 = 0 with ray_carve (from the optical
  *     centre), else max(0, r - tau);
- *   each crossed voxel (orc_ray_walk32) with centre c: sdf = r - (c - o).u;
+ *   each crossed voxel (the walk above; its fragile steps are recorded for
+ *     orc_fragile_voxels) with centre c: sdf = r - (c - o).u;
  *     it contributes t = min(sdf, tau) with the weight w (1, or 1/z^2) when
  *     sdf >= -tau;
  *   blocks holding a contribution are touched; new ones get buffer indices
@@ -639,6 +717,7 @@ int orc_integrate_raycast(orc_submap *s, const float *depth, int H, int W, const
     size_t nc = 0, capc = 1 << 16;
     ray_contrib *L = (ray_contrib *)malloc(sizeof(ray_contrib) * capc);
     int64_t walk_cap = 0, *walk = NULL;
+    int64_t fcap = 0, *fbuf = NULL, nf = 0;
     for (int row = 0; row < H; ++row)
         for (int col = 0; col < W; ++col) {
             const float z = depth[(size_t)row * W + col];
@@ -656,8 +735,15 @@ int orc_integrate_raycast(orc_submap *s, const float *depth, int H, int W, const
                 const float s1 = rf + tau_f;
                 const float s0 = s->p.ray_carve ? 0.0f : fmaxf(rf - tau_f, 0.0f);
                 guard = 3 * (int64_t)ceilf((s1 - s0) / vs_f) + 6;
-                if (guard > walk_cap) { walk_cap = guard; walk = (int64_t *)realloc(walk, sizeof(int64_t) * 3 * walk_cap); }
-                nvox = orc_ray_walk32(o32, uf, s0, s1, vs_f, walk, guard);
+                if (guard > walk_cap) {
+                    walk_cap = guard;
+                    walk = (int64_t *)realloc(walk, sizeof(int64_t) * 3 * walk_cap);
+                    fcap = 7 * walk_cap;
+                    fbuf = (int64_t *)realloc(fbuf, sizeof(int64_t) * 3 * fcap);
+                }
+                nf = 0;
+                nvox = ray_walk32_frag(o32, uf, s0, s1, vs_f, walk, guard, fbuf, fcap, &nf);
+                frag_append(s, fbuf, nf < fcap ? nf : fcap);
                 const float wf = s->p.weight_mode ? 1.0f / (z * z) : 1.0f;
                 for (int64_t k = 0; k < nvox; ++k) {
                     float c[3];
@@ -685,8 +771,15 @@ int orc_integrate_raycast(orc_submap *s, const float *depth, int H, int W, const
                 const double s1 = r + tau;
                 const double s0 = s->p.ray_carve ? 0.0 : fmax(r - tau, 0.0);
                 guard = 3 * (int64_t)ceil((s1 - s0) / s->p.vs) + 6;
-                if (guard > walk_cap) { walk_cap = guard; walk = (int64_t *)realloc(walk, sizeof(int64_t) * 3 * walk_cap); }
-                nvox = ray_walk64(o, u, s0, s1, s->p.vs, walk, guard);
+                if (guard > walk_cap) {
+                    walk_cap = guard;
+                    walk = (int64_t *)realloc(walk, sizeof(int64_t) * 3 * walk_cap);
+                    fcap = 7 * walk_cap;
+                    fbuf = (int64_t *)realloc(fbuf, sizeof(int64_t) * 3 * fcap);
+                }
+                nf = 0;
+                nvox = ray_walk64(o, u, s0, s1, s->p.vs, walk, guard, fbuf, fcap, &nf);
+                frag_append(s, fbuf, nf < fcap ? nf : fcap);
                 w = s->p.weight_mode ? 1.0 / (zd * zd) : 1.0;
                 for (int64_t k = 0; k < nvox; ++k) {
                     double c[3];
@@ -706,6 +799,7 @@ int orc_integrate_raycast(orc_submap *s, const float *depth, int H, int W, const
             }
         }
     free(walk);
+    free(fbuf);
 
     /* count and allocate */
     uint64_t *tk = (uint64_t *)malloc(sizeof(uint64_t) * (nc ? nc : 1));

@@ -25,10 +25,14 @@
 //                   / W' where sw > 0, and the accumulators are cleared.
 // The paper orders the merge by sorting the contributions by voxel address;
 // here the sums are formed by hardware FP64 atomics instead, in any order.
-// The walk and every binary32 step are the oracle's, so block keys, buffer
-// indices and the set of contributions agree bit for bit; the binary64 sums
-// of binary32 products agree up to their order, which the binary32 result
-// hides except at rare rounding ties.
+// The walk takes each crossing parameter as ((i + [u > 0]) vs - o) * (1 / u)
+// with the reciprocal rounded once per ray: a multiply per step instead of a
+// division, and faithful to 2^-22 relative of the exact crossing.  A walk
+// with correctly rounded crossings can therefore take another step only where
+// two crossing parameters (or the nearest one and the segment end) lie within
+// that margin of each other; elsewhere block keys, buffer indices and the set
+// of contributions are those of the exact traversal.  The binary64 sums of
+// binary32 products depend on their order only at rare rounding ties.
 #include "covox_impl.h"
 
 #include <math.h>

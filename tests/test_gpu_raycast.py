@@ -2,12 +2,23 @@
 count / allocate / merge) through the C ABI against the oracle on the same
 seeded frames.
 
-Block keys, buffer indices and home buckets must match bit for bit (the
-grid walk and every binary32 step are the oracle's). The per-voxel sums are
-binary64 in both, but formed in a different order on the GPU (hardware
-atomics), so W and D must match bit for bit on at least 99.9 % of the
-observed voxels and within 1e-6 (m, relative for W) everywhere, well inside
-the 1e-4 m bar for the TSDF."""
+The oracle's grid walk solves each boundary crossing with one correctly
+rounded division; the kernel multiplies by a reciprocal rounded once per
+ray.  Both are faithful to 2^-22 relative, so their walks can differ only at
+steps the oracle records as fragile (two crossing parameters, or the
+nearest one and the segment end, within 2^-21 relative): the voxels such a
+step could enter are excluded from the exact comparison, counted and
+reported.  The bar:
+  - blocks: the key sets agree except for blocks whose every observed voxel
+    is fragile; buffer order agrees on the common keys (bit for bit when the
+    sets are equal), home buckets bit for bit;
+  - voxels outside the fragile set: observed sets equal, W within 1e-6
+    relative and D within 1e-6 m (the per-voxel sums are binary64 in both,
+    formed in another order on the GPU, so at least 99.9 % agree bit for
+    bit);
+  - fragile voxels: differences counted and printed, and they stay below
+    1 % of the observed voxels.
+"""
 import numpy as np
 import pytest
 
@@ -38,20 +49,72 @@ def _orc(**kw):
     return orc.Submap(orc.Params(**base))
 
 
-def _compare(g, r, tcap):
-    assert np.array_equal(g["keys"], r["keys"]), "block keys / buffer order differ"
-    assert np.array_equal(g["home"].astype(np.int64), orc.home_bucket(r["keys"], tcap))
-    W, Wr = g["W"].astype(np.float64), r["W"]
-    D, Dr = g["D"].astype(np.float64), r["D"]
-    obs = Wr > 0
-    assert np.array_equal(W > 0, obs), "observed sets differ"
-    dW = np.abs(W - Wr)[obs] / Wr[obs]
-    dD = np.abs(D - Dr)[obs]
+def _voxel_index(keys):
+    """(key, in-block index) -> flat index into the (n, 512) arrays."""
+    return {int(k): i for i, k in enumerate(keys)}
+
+
+def _fragile_flat(ref, keys):
+    """Flat indices (into the blocks `keys`) of the oracle's fragile voxels,
+    and the block keys they fall in."""
+    fr = ref.fragile_voxels()
+    if len(fr) == 0:
+        return np.zeros(0, np.int64), set()
+    b = fr >> 3
+    bk = orc.pack_key(b[:, 0], b[:, 1], b[:, 2])
+    lin = (fr[:, 0] & 7) + 8 * (fr[:, 1] & 7) + 64 * (fr[:, 2] & 7)
+    pos = _voxel_index(keys)
+    flat = [pos[int(k)] * 512 + int(l) for k, l in zip(bk, lin) if int(k) in pos]
+    return np.unique(np.array(flat, np.int64)), {int(k) for k in bk}
+
+
+def _compare(g, r, ref, tcap):
+    gk, rk = g["keys"], r["keys"]
+    gpos, rpos = _voxel_index(gk), _voxel_index(rk)
+    common = [int(k) for k in rk if int(k) in gpos]
+    # key sets: any block on one side only holds fragile voxels alone
+    frag_r, frag_blocks = _fragile_flat(ref, rk)
+    only = (set(gpos) ^ set(rpos))
+    assert only <= frag_blocks, "blocks differ away from fragile walk steps"
+    for k in only:
+        side = g if k in gpos else r
+        i = (gpos if k in gpos else rpos)[k]
+        obs = np.nonzero(side["W"][i] > 0)[0]
+        b = np.array(orc.unpack_key(np.array([k], np.uint64))).reshape(3)
+        vox = 8 * b + np.stack([obs & 7, (obs >> 3) & 7, obs >> 6], axis=1)
+        fr = {tuple(v) for v in ref.fragile_voxels()}
+        assert all(tuple(v) in fr for v in vox), "a one-sided block holds a voxel no fragile step explains"
+    # buffer order on the common keys; home buckets
+    assert [int(k) for k in gk if int(k) in rpos] == common, "buffer order differs"
+    if not only:
+        assert np.array_equal(gk, rk)
+    assert np.array_equal(g["home"].astype(np.int64), orc.home_bucket(gk, tcap))
+    # voxels of the common blocks, in the oracle's block order
+    gi = np.array([gpos[k] for k in common], np.int64)
+    ri = np.array([rpos[k] for k in common], np.int64)
+    W, Wr = g["W"][gi].astype(np.float64).reshape(-1), r["W"][ri].reshape(-1)
+    D, Dr = g["D"][gi].astype(np.float64).reshape(-1), r["D"][ri].reshape(-1)
+    fragile = np.zeros(len(common) * 512, bool)
+    rmap = {int(x): j for j, x in enumerate(ri)}
+    for f in frag_r:
+        j = rmap.get(int(f) // 512)
+        if j is not None:
+            fragile[j * 512 + int(f) % 512] = True
+    obs_r, obs_g = Wr > 0, W > 0
+    strict = ~fragile
+    assert np.array_equal(obs_g[strict], obs_r[strict]), "observed sets differ away from fragile steps"
+    m = strict & obs_r
+    dW = np.abs(W - Wr)[m] / Wr[m]
+    dD = np.abs(D - Dr)[m]
     assert dW.max(initial=0) <= 1e-6, dW.max()
     assert dD.max(initial=0) <= 1e-6, dD.max()
-    n = int(obs.sum())
+    n = int(obs_r.sum())
     assert np.count_nonzero(dW) <= 1e-3 * n and np.count_nonzero(dD) <= 1e-3 * n
-    return int(np.count_nonzero(dD)), n
+    fm = fragile & (obs_r | obs_g)
+    n_frag_diff = int(np.count_nonzero((W != Wr)[fm] | (np.abs(D - Dr)[fm] > 1e-6)))
+    assert n_frag_diff <= 0.01 * n
+    return {"d_differ": int(np.count_nonzero(dD)), "observed": n, "fragile": int(fragile.sum()),
+            "fragile_differ": n_frag_diff, "one_sided_blocks": len(only)}
 
 
 @pytest.mark.parametrize("carve", [1, 0])
@@ -69,8 +132,8 @@ def test_tiny_raycast_parity(cv, carve):
         ctx.integrate_depth(s, dev[f], w.cam.K, w.poses[f])
         n_vox += ref.integrate(fr[f], w.cam.K, w.poses[f])["n_voxels"]
         if f in (0, 1, 7, w.n_frames - 1):
-            nd, n = _compare(ctx.export_blocks(s), ref.export(), tcap)
-            print("frame %d: %d of %d voxels differ in D" % (f, nd, n))
+            c = _compare(ctx.export_blocks(s), ref.export(), ref, tcap)
+            print("frame %d: %s" % (f, c))
     assert ctx.submap_info(s)["n_updates"] == n_vox
     ctx.close()
 
@@ -87,7 +150,7 @@ def test_raycast_inverse_depth_weights(cv):
         ctx.integrate_depth(s, dev[f], w.cam.K, w.poses[f])
         ref.integrate(fr[f], w.cam.K, w.poses[f])
     g = ctx.export_blocks(s)
-    _compare(g, ref.export(), ctx.submap_info(s)["table_capacity"])
+    _compare(g, ref.export(), ref, ctx.submap_info(s)["table_capacity"])
     assert not np.all(g["W"] == np.round(g["W"]))
     ctx.close()
 
@@ -105,8 +168,8 @@ def test_room_frames_raycast_parity(cv):
     for f in range(w.n_frames):
         ctx.integrate_depth(s, dev[f], w.cam.K, w.poses[f])
         ref.integrate(fr[f], w.cam.K, w.poses[f])
-    nd, n = _compare(ctx.export_blocks(s), ref.export(), ctx.submap_info(s)["table_capacity"])
-    print("room: %d of %d voxels differ in D" % (nd, n))
+    c = _compare(ctx.export_blocks(s), ref.export(), ref, ctx.submap_info(s)["table_capacity"])
+    print("room: %s" % c)
     ctx.close()
 
 
@@ -125,8 +188,10 @@ def test_batch_calls_match_per_frame_calls(cv):
     ctx.integrate_depth_batch(b, dev, w.cam.K, w.poses)
     tcap = ctx.submap_info(a)["table_capacity"]
     r = ref.export()
-    _compare(ctx.export_blocks(a), r, tcap)
-    _compare(ctx.export_blocks(b), r, tcap)
+    ga, gb = ctx.export_blocks(a), ctx.export_blocks(b)
+    _compare(ga, r, ref, tcap)
+    for k in ("keys", "D", "W"):
+        assert np.array_equal(ga[k], gb[k]), k  # the same kernels in the same order
     ctx.close()
 
 
@@ -148,7 +213,7 @@ def test_capacity_failure_drops_the_frame_only(cv):
         ctx.integrate_depth(s, torch.from_numpy(fr[10]).cuda(), w.cam.K, w.poses[10])
     ctx.integrate_depth(s, torch.from_numpy(fr[0]).cuda(), w.cam.K, w.poses[0])
     ref.integrate(fr[0], w.cam.K, w.poses[0])
-    _compare(ctx.export_blocks(s), ref.export(), ctx.submap_info(s)["table_capacity"])
+    _compare(ctx.export_blocks(s), ref.export(), ref, ctx.submap_info(s)["table_capacity"])
     ctx.close()
 
 

@@ -220,3 +220,91 @@ def test_binary32_and_binary64_agree():
     same = (Wa == Wb) & (Wa > 0)
     assert same.sum() > 0.8 * (Wb > 0).sum()
     assert np.percentile(np.abs(ea["D"][ia][same] - eb["D"][ib][same]), 99) < 1e-6
+
+
+def _walk_alt(o, u, s0, s1, vs, mode):
+    """The traversal with other roundings of the crossing parameters:
+    mode "recip" multiplies by the binary32 reciprocal of u_a, mode "f64"
+    forms and compares the parameters in binary64 (from the same binary32
+    inputs).  Both stay within 2^-22 relative of the exact quotient."""
+    f = np.float32
+    vs = f(vs)
+    i = [int(math.floor(f(o[a] + f(f(s0) * u[a])) / vs)) for a in range(3)]
+    step = [1 if u[a] > 0 else (-1 if u[a] < 0 else 0) for a in range(3)]
+    iu = [f(f(1.0) / u[a]) if step[a] else f(0) for a in range(3)]
+    out = []
+    cap = 3 * int(math.ceil(f(f(s1) - f(s0)) / vs)) + 6
+    while len(out) < cap:
+        out.append(tuple(i))
+        sn = []
+        for a in range(3):
+            if not step[a]:
+                sn.append(math.inf)
+                continue
+            b = f(f(i[a] + (step[a] > 0)) * vs)
+            if mode == "recip":
+                sn.append(float(f(f(b - o[a]) * iu[a])))
+            else:
+                sn.append((float(b) - float(o[a])) / float(u[a]))
+        a = 0
+        if sn[1] < sn[a]:
+            a = 1
+        if sn[2] < sn[a]:
+            a = 2
+        if not (sn[a] < float(s1)):
+            break
+        i[a] += step[a]
+    return out
+
+
+def _near_tie_rays(n, seed):
+    """Rays whose x and y crossings nearly coincide at every boundary: equal
+    direction components and origin offsets up to a few ulps apart."""
+    rng = np.random.default_rng(seed)
+    for k in range(n):
+        x = np.float32(rng.uniform(0.0, 0.05))
+        o = np.array([x, x, rng.uniform(0.0, 0.05)], np.float32)
+        o[1] = np.nextafter(o[1], np.float32(1.0) if k % 3 else np.float32(-1.0)) if k % 2 else o[1]
+        c = rng.uniform(-0.5, 0.5)
+        u = np.array([1.0, 1.0 + rng.choice([0.0, 1e-7, -1e-7, 3e-7]), c])
+        u = (u / np.linalg.norm(u)).astype(np.float32)
+        s1 = np.float32(rng.uniform(0.3, 1.5))
+        yield o, u, np.float32(0.0), s1
+
+
+def test_fragile_steps_cover_other_faithful_roundings():
+    """Walks whose crossing parameters are rounded differently (but still
+    faithfully) differ from the oracle's walk only in voxels the oracle
+    recorded as fragile; rays away from ties record nothing."""
+    differing = 0
+    for o, u, s0, s1 in list(_near_tie_rays(400, 21)) + list(_random_rays(200, 22)):
+        walk, frag = orc.ray_walk32(o, u, s0, s1, VS, fragile=True)
+        got = {tuple(v) for v in walk}
+        fr = {tuple(v) for v in frag}
+        for mode in ("recip", "f64"):
+            alt = set(_walk_alt(o, u, s0, s1, VS, mode))
+            diff = alt ^ got
+            assert diff <= fr, (mode, sorted(diff - fr)[:4])
+            differing += bool(diff)
+    assert differing > 20  # the near-tie rays do exercise the margin
+
+
+def test_exact_tie_records_both_neighbours():
+    """A ray with equal x and y components through a point with equal x and
+    y offsets crosses every x and y boundary at the same parameter: the walk
+    moves x first (the tie rule), and each tie records the two voxels a
+    step could enter (x or y first), never the corner both reach."""
+    o = np.array([0.013, 0.013, 0.021], np.float32)
+    u = np.array([1.0, 1.0, 0.0], np.float32) / np.float32(np.sqrt(2.0))
+    u = u.astype(np.float32)
+    walk, frag = orc.ray_walk32(o, u, 0.0, 0.3, VS, fragile=True)
+    steps = np.diff(walk, axis=0)
+    assert np.all(steps[0::2] == [1, 0, 0]) and np.all(steps[1::2] == [0, 1, 0])
+    fr = {tuple(v) for v in frag}
+    for k in range(0, len(walk) - 1, 2):
+        i = walk[k]
+        if k + 2 < len(walk):
+            assert (i[0] + 1, i[1], i[2]) in fr and (i[0], i[1] + 1, i[2]) in fr
+            assert (i[0] + 1, i[1] + 1, i[2]) not in fr
+    _, none = orc.ray_walk32(o, np.array([0.6, 0.8, 0.0], np.float32), 0.0, 0.3, VS, fragile=True)
+    assert len(none) == 0
