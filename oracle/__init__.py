@@ -10,7 +10,9 @@ the GPU library never imports or links it, and it imports nothing from the
 GPU library.
 
 Build flags: gcc -O2 -ffp-contract=off (no FMA contraction, no fast-math), so
-that the binary32 mode follows the pinned operation order.
+that the binary32 mode follows the pinned operation order; -fopenmp for the
+loops over independent items (set_threads), whose results do not depend on
+the thread count.
 """
 from __future__ import annotations
 
@@ -33,7 +35,7 @@ def build(force: bool = False) -> str:
     stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in (_SRC, _SRC_NET))
     if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared", "-fPIC",
                                "-o", tmp, _SRC, _SRC_NET, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -129,6 +131,8 @@ def _load():
                                              ctypes.c_int64, _i64p, ctypes.c_int64, _i64p]
         L.orc_fragile_voxels.restype = ctypes.c_int64
         L.orc_fragile_voxels.argtypes = [_vp, _i64p, ctypes.c_int64]
+        L.orc_set_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_pose_cam_sub.restype = None
         L.orc_pose_cam_sub.argtypes = [_dp, _dp, _dp]
         _lib = L
@@ -137,6 +141,12 @@ def _load():
 
 def _p(a, t):
     return a.ctypes.data_as(t)
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops (n < 1: all cores); returns
+    the count in use.  Results do not depend on it."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def _mat(T):

@@ -44,6 +44,12 @@
  *   binary64  the same definitions in binary64 (for error statements).
  * Optional binary16 storage of distance and weight (binary32 arithmetic).
  *
+ * Threads: the loops over independent items -- the voxels of the frustum
+ * box, the valid voxels of a frame, the lines of an EDT pass, the blocks of
+ * the final values -- run under OpenMP (orc_set_threads); every item writes
+ * its own outputs and the per-thread lists are joined in sequential order,
+ * so the results are bit-identical for any thread count.
+ *
  * Every function is a direct transcription of a definition: brute-force
  * voxel enumeration over a box that contains the camera frustum, sorted key
  * arrays with binary search, the Felzenszwalb-Huttenlocher lower-envelope
@@ -51,6 +57,7 @@
  * Cholesky.  Nothing here is tuned.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -304,6 +311,13 @@ static void grow(orc_submap *s, int64_t need)
 
 int64_t orc_n_blocks(const orc_submap *s) { return s->n; }
 
+/* Threads of the parallel loops (n < 1: all cores); returns the count now in use. */
+int orc_set_threads(int n)
+{
+    omp_set_num_threads(n >= 1 ? n : omp_get_num_procs());
+    return omp_get_max_threads();
+}
+
 static int64_t floordiv8(int64_t v) { return v >= 0 ? v / 8 : -((-v + 7) / 8); }
 
 static int lin_index(int64_t ix, int64_t iy, int64_t iz)
@@ -458,30 +472,54 @@ int orc_integrate(orc_submap *s, const float *depth, int H, int W, const float K
     const double tau = s->p.trunc_vox * s->p.vs;
     const float vs_f = (float)s->p.vs, tau_f = (float)tau, maxr_f = (float)s->p.max_range;
 
-    /* 1. brute-force validity over the box */
-    size_t nv = 0, capv = 1 << 16;
-    valid_vox *vv = (valid_vox *)malloc(sizeof(valid_vox) * capv);
-    int64_t i[3];
-    for (i[0] = lo[0]; i[0] <= hi[0]; ++i[0])
-        for (i[1] = lo[1]; i[1] <= hi[1]; ++i[1])
-            for (i[2] = lo[2]; i[2] <= hi[2]; ++i[2]) {
-                int ok;
-                double sdf, dd;
-                if (s->p.fp64) {
-                    ok = valid64(R64, t64, s->p.vs, tau, s->p.max_range, K, depth, H, W, i, &sdf, &dd);
-                } else {
-                    float sf, df;
-                    ok = valid32(R32, t32, vs_f, tau_f, maxr_f, K, depth, H, W, i, &sf, &df);
-                    sdf = sf;
-                    dd = df;
+    /* 1. brute-force validity over the box: each thread scans a contiguous
+     * range of x slices into a list of its own; the lists are joined in
+     * thread order, which is the sequential (x, y, z) order */
+    const int nthr = omp_get_max_threads();
+    valid_vox **tv = (valid_vox **)calloc((size_t)nthr, sizeof(valid_vox *));
+    size_t *tn = (size_t *)calloc((size_t)nthr, sizeof(size_t));
+#pragma omp parallel num_threads(nthr)
+    {
+        const int th = omp_get_thread_num(), nt_ = omp_get_num_threads();
+        const int64_t nx = hi[0] - lo[0] + 1;
+        const int64_t x0 = lo[0] + nx * th / nt_, x1 = lo[0] + nx * (th + 1) / nt_;
+        size_t nv_t = 0, cap_t = 1 << 12;
+        valid_vox *vt = (valid_vox *)malloc(sizeof(valid_vox) * cap_t);
+        int64_t i[3];
+        for (i[0] = x0; i[0] < x1; ++i[0])
+            for (i[1] = lo[1]; i[1] <= hi[1]; ++i[1])
+                for (i[2] = lo[2]; i[2] <= hi[2]; ++i[2]) {
+                    int ok;
+                    double sdf, dd;
+                    if (s->p.fp64) {
+                        ok = valid64(R64, t64, s->p.vs, tau, s->p.max_range, K, depth, H, W, i, &sdf, &dd);
+                    } else {
+                        float sf, df;
+                        ok = valid32(R32, t32, vs_f, tau_f, maxr_f, K, depth, H, W, i, &sf, &df);
+                        sdf = sf;
+                        dd = df;
+                    }
+                    if (!ok) continue;
+                    if (nv_t == cap_t) { cap_t *= 2; vt = (valid_vox *)realloc(vt, sizeof(valid_vox) * cap_t); }
+                    vt[nv_t].i[0] = i[0]; vt[nv_t].i[1] = i[1]; vt[nv_t].i[2] = i[2];
+                    vt[nv_t].sdf = sdf;
+                    vt[nv_t].d = dd;
+                    ++nv_t;
                 }
-                if (!ok) continue;
-                if (nv == capv) { capv *= 2; vv = (valid_vox *)realloc(vv, sizeof(valid_vox) * capv); }
-                vv[nv].i[0] = i[0]; vv[nv].i[1] = i[1]; vv[nv].i[2] = i[2];
-                vv[nv].sdf = sdf;
-                vv[nv].d = dd;
-                ++nv;
-            }
+        tv[th] = vt;
+        tn[th] = nv_t;
+    }
+    size_t nv = 0;
+    for (int th = 0; th < nthr; ++th) nv += tn[th];
+    valid_vox *vv = (valid_vox *)malloc(sizeof(valid_vox) * (nv ? nv : 1));
+    size_t o = 0;
+    for (int th = 0; th < nthr; ++th) {
+        if (tn[th]) memcpy(vv + o, tv[th], sizeof(valid_vox) * tn[th]);
+        o += tn[th];
+        free(tv[th]);
+    }
+    free(tv);
+    free(tn);
 
     /* 2. touched and new blocks */
     uint64_t *tk = (uint64_t *)malloc(sizeof(uint64_t) * (nv ? nv : 1));
@@ -490,7 +528,9 @@ int orc_integrate(orc_submap *s, const float *depth, int H, int W, const float K
     size_t nt = 0;
     const int64_t n_new = allocate_touched(s, tk, nv, &nt);
 
-    /* 3. update every valid voxel */
+    /* 3. update every valid voxel (each voxel of the box appears at most
+     * once, so the updates are independent) */
+#pragma omp parallel for schedule(static)
     for (size_t j = 0; j < nv; ++j) {
         const int64_t *v = vv[j].i;
         int64_t idx = find_block(s, pack_key(floordiv8(v[0]), floordiv8(v[1]), floordiv8(v[2])));
@@ -924,6 +964,7 @@ int orc_update_esdf(orc_submap *s)
     for (size_t q = 0; q < N; ++q) g[q] = EDT_INF;
 #define GI(x, y, z) ((size_t)(((z) * dim[1] + (y)) * dim[0] + (x)))
     /* sites */
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < s->n; ++j) {
         int64_t b[3];
         unpack_key(s->keys[j], b);
@@ -939,31 +980,37 @@ int orc_update_esdf(orc_submap *s)
             g[GI(x, y, z)] = 0;
         }
     }
-    /* separable passes x, y, z */
+    /* separable passes x, y, z (the lines of a pass are independent) */
     int64_t L = dim[0] > dim[1] ? dim[0] : dim[1];
     if (dim[2] > L) L = dim[2];
-    int64_t *fin = (int64_t *)malloc(sizeof(int64_t) * L), *fout = (int64_t *)malloc(sizeof(int64_t) * L);
-    int *v = (int *)malloc(sizeof(int) * (L + 1));
-    double *zz = (double *)malloc(sizeof(double) * (L + 2));
     for (int axis = 0; axis < 3; ++axis) {
         int64_t n = dim[axis];
         int64_t a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
-        for (int64_t u = 0; u < dim[a1]; ++u)
-            for (int64_t w = 0; w < dim[a2]; ++w) {
-                for (int64_t q = 0; q < n; ++q) {
-                    int64_t c[3];
-                    c[axis] = q; c[a1] = u; c[a2] = w;
-                    fin[q] = g[GI(c[0], c[1], c[2])];
+#pragma omp parallel
+        {
+            int64_t *fin = (int64_t *)malloc(sizeof(int64_t) * L), *fout = (int64_t *)malloc(sizeof(int64_t) * L);
+            int *v = (int *)malloc(sizeof(int) * (L + 1));
+            double *zz = (double *)malloc(sizeof(double) * (L + 2));
+#pragma omp for schedule(static)
+            for (int64_t u = 0; u < dim[a1]; ++u)
+                for (int64_t w = 0; w < dim[a2]; ++w) {
+                    for (int64_t q = 0; q < n; ++q) {
+                        int64_t c[3];
+                        c[axis] = q; c[a1] = u; c[a2] = w;
+                        fin[q] = g[GI(c[0], c[1], c[2])];
+                    }
+                    edt1d(fin, fout, (int)n, v, zz);
+                    for (int64_t q = 0; q < n; ++q) {
+                        int64_t c[3];
+                        c[axis] = q; c[a1] = u; c[a2] = w;
+                        g[GI(c[0], c[1], c[2])] = fout[q] >= EDT_INF ? EDT_INF : fout[q];
+                    }
                 }
-                edt1d(fin, fout, (int)n, v, zz);
-                for (int64_t q = 0; q < n; ++q) {
-                    int64_t c[3];
-                    c[axis] = q; c[a1] = u; c[a2] = w;
-                    g[GI(c[0], c[1], c[2])] = fout[q] >= EDT_INF ? EDT_INF : fout[q];
-                }
-            }
+            free(fin); free(fout); free(v); free(zz);
+        }
     }
     /* values */
+#pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < s->n; ++j) {
         int64_t b[3];
         unpack_key(s->keys[j], b);
@@ -996,7 +1043,7 @@ int orc_update_esdf(orc_submap *s)
         }
     }
 #undef GI
-    free(g); free(fin); free(fout); free(v); free(zz);
+    free(g);
     return ORC_OK;
 }
 
