@@ -208,6 +208,7 @@ def test_context_close_before_net(cv):
     context's stream)."""
     import ctypes
     import torch
+    from paper_2410_21149_amd.covox import _lib
     ctx = _ctx(cv)
     net = cv.Net(ctx, seed=5)
     n_params = net.num_params
@@ -215,14 +216,14 @@ def test_context_close_before_net(cv):
     net.forward(x)
     h = net.handle
     # the C call order of a binding that does not close its nets: context first
-    cv._lib.covox_destroy(ctx.handle)
+    _lib.covox_destroy(ctx.handle)
     ctx.handle = None
-    assert cv._lib.covox_net_num_params(h) == n_params
+    assert _lib.covox_net_num_params(h) == n_params
     out = torch.empty((1, 5), dtype=torch.float32, device="cuda")
-    assert cv._lib.covox_net_forward(h, ctypes.c_void_p(x.data_ptr()), 1, ctypes.c_void_p(out.data_ptr())) == cv.EINVAL
+    assert _lib.covox_net_forward(h, ctypes.c_void_p(x.data_ptr()), 1, ctypes.c_void_p(out.data_ptr())) == cv.EINVAL
     buf = np.zeros(n_params, np.float32)
-    assert cv._lib.covox_net_get_params(h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n_params) == cv.EINVAL
-    cv._lib.covox_net_destroy(h)
+    assert _lib.covox_net_get_params(h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n_params) == cv.EINVAL
+    _lib.covox_net_destroy(h)
     net.handle = None
     # the binding closes a context's nets with it
     ctx2 = _ctx(cv)
