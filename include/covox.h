@@ -560,7 +560,13 @@ typedef struct {
      * cover with a grid stride, leaves CUs to the integration.  0: no
      * limit.  The results do not depend on it. */
     int64_t edt_pipe_max_workgroups;
-    int64_t reserved[3];
+    /* EDT pass layout.  0: separate x, y and z passes, one work item per
+     * block or per line (shapes by the thresholds above).  S > 0: column
+     * passes, x fused into y, each workgroup one segment of S blocks of a
+     * block column with HB = ceil(R / 8) halo blocks on each side staged
+     * once; S is clamped to 48 - 2 HB.  The results do not depend on it. */
+    int64_t edt_col_seg;
+    int64_t reserved[2];
 } covox_tuning;
 
 /* Defaults: y envelopes from 2048 segments up, z always windowed, 256

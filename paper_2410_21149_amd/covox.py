@@ -73,7 +73,8 @@ class covox_train_cfg(ctypes.Structure):
 class covox_tuning(ctypes.Structure):
     _fields_ = [("edt_y_env_min_cols", ctypes.c_int64), ("edt_z_env_min_cols", ctypes.c_int64),
                 ("align_threads", ctypes.c_int64), ("align_points_per_step", ctypes.c_int64),
-                ("edt_pipe_max_workgroups", ctypes.c_int64), ("reserved", ctypes.c_int64 * 3)]
+                ("edt_pipe_max_workgroups", ctypes.c_int64), ("edt_col_seg", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 2)]
 
 
 class covox_pose_factor(ctypes.Structure):
@@ -492,7 +493,7 @@ class Context:
     def _tuning_dict(t) -> dict:
         return {"edt_y_env_min_cols": t.edt_y_env_min_cols, "edt_z_env_min_cols": t.edt_z_env_min_cols,
                 "align_threads": t.align_threads, "align_points_per_step": t.align_points_per_step,
-                "edt_pipe_max_workgroups": t.edt_pipe_max_workgroups}
+                "edt_pipe_max_workgroups": t.edt_pipe_max_workgroups, "edt_col_seg": t.edt_col_seg}
 
     def tuning(self) -> dict:
         t = covox_tuning()
@@ -500,7 +501,7 @@ class Context:
         return self._tuning_dict(t)
 
     def set_tuning(self, edt_y_env_min_cols=None, edt_z_env_min_cols=None, align_threads=None,
-                   align_points_per_step=None, edt_pipe_max_workgroups=None):
+                   align_points_per_step=None, edt_pipe_max_workgroups=None, edt_col_seg=None):
         t = covox_tuning()
         self._check(_lib.covox_tuning_get(self.handle, ctypes.byref(t)), "tuning_get")
         if edt_y_env_min_cols is not None:
@@ -513,6 +514,8 @@ class Context:
             t.align_points_per_step = align_points_per_step
         if edt_pipe_max_workgroups is not None:
             t.edt_pipe_max_workgroups = edt_pipe_max_workgroups
+        if edt_col_seg is not None:
+            t.edt_col_seg = edt_col_seg
         self._check(_lib.covox_tuning_set(self.handle, ctypes.byref(t)), "tuning_set")
 
     def autotune_esdf(self, subs) -> dict:

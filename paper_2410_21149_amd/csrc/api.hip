@@ -439,7 +439,7 @@ void covox_destroy(covox_ctx *ctx)
                       (void *)ctx->fcount, (void *)ctx->ray_acc, (void *)ctx->wf_nk, (void *)ctx->wf_np,
                       (void *)ctx->wf_sites, (void *)ctx->wf_flag, (void *)ctx->wf_list, (void *)ctx->wf_cnt,
                       (void *)ctx->sites[1], (void *)ctx->seeds[0], (void *)ctx->seeds[1], (void *)ctx->snap[0],
-                      (void *)ctx->snap[1]})
+                      (void *)ctx->snap[1], (void *)ctx->blk[0], (void *)ctx->blk[1]})
         if (ptr) (void)hipFree(ptr);
     for (void *p : ctx->deferred) (void)hipFree(p);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -1353,6 +1353,7 @@ int covox_tuning_set(covox_ctx *ctx, const covox_tuning *t)
         return fail(ctx, COVOX_EINVAL, "tuning_set: align_points_per_step must be 1 or 2");
     if (t->edt_pipe_max_workgroups < 0)
         return fail(ctx, COVOX_EINVAL, "tuning_set: edt_pipe_max_workgroups must be >= 0");
+    if (t->edt_col_seg < 0) return fail(ctx, COVOX_EINVAL, "tuning_set: edt_col_seg must be >= 0");
     ctx->tune = *t;
     return COVOX_OK;
 }

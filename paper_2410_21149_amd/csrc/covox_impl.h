@@ -288,6 +288,8 @@ struct covox_ctx {
     int64_t sites_cap[2] = {0, 0};            // dense blocks
     float *seeds[2] = {nullptr, nullptr};     // phi seed per voxel of the dense blocks
     int64_t seeds_cap[2] = {0, 0};            // dense blocks
+    int32_t *blk[2] = {nullptr, nullptr};     // buffer index per dense block (column passes)
+    int64_t blk_cap[2] = {0, 0};              // dense blocks
     covox::EsdfSnap *snap[2] = {nullptr, nullptr};  // kEsdfMaxJobs per slot
     int esdf_slot = 0;
     uint8_t *g1 = nullptr;      // 512 per dense block

@@ -67,30 +67,36 @@ struct JobInfo {
     int32_t lo[3], dim[3];
     int64_t nd, nb;           // dense blocks of the box, allocated blocks
     int64_t od, ob, oy, oz;   // prefixes: dense, allocated, y columns, z columns
+    int64_t oxy, ozc;         // prefixes: y and z column segments of the column passes
 };
 
 struct Plan {
     JobInfo info[kMaxJobs];
     int n;
-    int64_t td, tb, ty, tz;   // totals
+    int64_t td, tb, ty, tz, txy, tzc;   // totals
 };
 
 __device__ __forceinline__ int64_t nsegments(int64_t L, int S) { return L > 0 ? (L + S - 1) / S : 0; }
+
+// Work items of the column passes (segments of Sseg blocks along the pass
+// axis; none when Sseg is 0).
+struct ColCounts {
+    int64_t cy, cz, cxy, czc;
+};
 
 // Fills the job info of one submap: from the live block count and block box
 // (SNAP = false: the page kernel, which runs in order with the integration),
 // or from the snapshot the page kernel stored (SNAP = true: the EDT passes,
 // which may run while the next frames are integrated into the same submap).
 template <bool SNAP>
-__device__ __forceinline__ void job_info(const EsdfJob &job, int C, JobInfo &ji, int64_t &cy, int64_t &cz)
+__device__ __forceinline__ void job_info(const EsdfJob &job, int C, int Sseg, JobInfo &ji, ColCounts &cc)
 {
     const SubmapMeta *m = job.meta;
     const EsdfSnap *sn = job.snap;
     for (int a = 0; a < 3; ++a) { ji.lo[a] = 0; ji.dim[a] = 0; }
     ji.nd = 0;
     ji.nb = 0;
-    cy = 0;
-    cz = 0;
+    cc.cy = cc.cz = cc.cxy = cc.czc = 0;
     const int64_t nb = SNAP ? (int64_t)sn->nb : m->n_blocks;
     if (nb <= 0) return;
     ji.nb = nb;
@@ -101,27 +107,31 @@ __device__ __forceinline__ void job_info(const EsdfJob &job, int C, JobInfo &ji,
         ji.nd *= ji.dim[a];
     }
     const int S = kWin - 2 * C;
-    cy = (int64_t)ji.dim[0] * ji.dim[2] * nsegments(8 * (int64_t)ji.dim[1], S);
-    cz = (int64_t)ji.dim[0] * ji.dim[1] * nsegments(8 * (int64_t)ji.dim[2], S);
+    cc.cy = (int64_t)ji.dim[0] * ji.dim[2] * nsegments(8 * (int64_t)ji.dim[1], S);
+    cc.cz = (int64_t)ji.dim[0] * ji.dim[1] * nsegments(8 * (int64_t)ji.dim[2], S);
+    if (Sseg > 0) {
+        cc.cxy = (int64_t)ji.dim[0] * ji.dim[2] * nsegments(ji.dim[1], Sseg);
+        cc.czc = (int64_t)ji.dim[0] * ji.dim[1] * nsegments(ji.dim[2], Sseg);
+    }
 }
 
 // The plan of a multi-submap launch: the first wave derives one submap per
 // lane with wave prefix sums, then a workgroup barrier publishes it.  A
 // single-submap launch keeps its one entry in registers instead (PlanView).
 template <bool SNAP, int NJ>
-__device__ void make_plan(const JobList<NJ> &jl, int C, Plan &pl)
+__device__ void make_plan(const JobList<NJ> &jl, int C, int Sseg, Plan &pl)
 {
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
         JobInfo ji;
-        int64_t cy = 0, cz = 0;
+        ColCounts cc = {0, 0, 0, 0};
         for (int a = 0; a < 3; ++a) { ji.lo[a] = 0; ji.dim[a] = 0; }
         ji.nd = ji.nb = 0;
-        if (lane < jl.n) job_info<SNAP>(jl.j[lane], C, ji, cy, cz);
-        const int64_t v[4] = {ji.nd, ji.nb, cy, cz};
-        int64_t incl[4];
+        if (lane < jl.n) job_info<SNAP>(jl.j[lane], C, Sseg, ji, cc);
+        const int64_t v[6] = {ji.nd, ji.nb, cc.cy, cc.cz, cc.cxy, cc.czc};
+        int64_t incl[6];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 6; ++k) {
             int64_t x = v[k];
             for (int o = 1; o < 64; o <<= 1) {
                 const int64_t y = __shfl_up(x, o, 64);
@@ -134,6 +144,8 @@ __device__ void make_plan(const JobList<NJ> &jl, int C, Plan &pl)
             ji.ob = incl[1] - v[1];
             ji.oy = incl[2] - v[2];
             ji.oz = incl[3] - v[3];
+            ji.oxy = incl[4] - v[4];
+            ji.ozc = incl[5] - v[5];
             pl.info[lane] = ji;
         }
         if (lane == 63) {
@@ -142,6 +154,8 @@ __device__ void make_plan(const JobList<NJ> &jl, int C, Plan &pl)
             pl.tb = incl[1];
             pl.ty = incl[2];
             pl.tz = incl[3];
+            pl.txy = incl[4];
+            pl.tzc = incl[5];
         }
     }
     __syncthreads();
@@ -165,26 +179,31 @@ template <int NJ, bool SNAP = true>
 struct PlanView {
     Plan *pl;
     JobInfo one;
-    int64_t t[4];  // totals: dense, allocated, y columns, z columns
+    // totals: dense, allocated, y columns, z columns, y and z column segments
+    int64_t t[6];
 
-    __device__ void init(const JobList<NJ> &jl, int C, Plan &lds)
+    __device__ void init(const JobList<NJ> &jl, int C, Plan &lds, int Sseg = 0)
     {
         if constexpr (NJ == 1) {
-            int64_t cy, cz;
-            job_info<SNAP>(jl.j[0], C, one, cy, cz);
-            one.od = one.ob = one.oy = one.oz = 0;
+            ColCounts cc;
+            job_info<SNAP>(jl.j[0], C, Sseg, one, cc);
+            one.od = one.ob = one.oy = one.oz = one.oxy = one.ozc = 0;
             t[0] = one.nd;
             t[1] = one.nb;
-            t[2] = cy;
-            t[3] = cz;
+            t[2] = cc.cy;
+            t[3] = cc.cz;
+            t[4] = cc.cxy;
+            t[5] = cc.czc;
             pl = nullptr;
         } else {
-            make_plan<SNAP>(jl, C, lds);
+            make_plan<SNAP>(jl, C, Sseg, lds);
             pl = &lds;
             t[0] = lds.td;
             t[1] = lds.tb;
             t[2] = lds.ty;
             t[3] = lds.tz;
+            t[4] = lds.txy;
+            t[5] = lds.tzc;
         }
     }
     template <int64_t JobInfo::*OFF>
@@ -212,16 +231,19 @@ __device__ __forceinline__ int64_t dom_index(const JobInfo &d, int x, int y, int
     return ((int64_t)z * d.dim[1] + y) * d.dim[0] + x;
 }
 
-// Page (dense block -> buffer index, -1 if unallocated) and site masks, one
-// wave per dense block, and the snapshot of each submap's domain (block box
-// and block count) that the later passes work on.  With SEEDS, also the phi
-// seed of every voxel of an allocated block: NaN when unobserved, D inside
-// the band, and otherwise an infinity with the sign of D.  The EDT passes then
+// Page (dense block -> buffer index, -1 if unallocated), site masks and the
+// snapshot of each submap's domain (block box and block count) that the later
+// passes work on.  Two independent loops: one lane per dense block looks its
+// key up in the hash table (64 lookups in flight per wave), writes the page
+// and, for an unallocated block, empty site masks; one wave per allocated
+// block reads its D and W and writes its site masks.  With SEEDS, that wave
+// also writes the phi seed of each voxel: NaN when unobserved, D inside the
+// band, and otherwise an infinity with the sign of D.  The EDT passes then
 // never read the TSDF or the submap's bookkeeping, so that the next frames
 // may be integrated while they run.
 template <typename S, int NJ, bool SEEDS>
 __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C, float vs, float tau,
-                                                    uint64_t *__restrict__ sites)
+                                                    uint64_t *__restrict__ sites, int32_t *__restrict__ blk)
 {
     __shared__ Plan lds;
     PlanView<NJ, false> pv;
@@ -238,40 +260,53 @@ __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C,
         m->dom_nblocks = sn->nb = (int32_t)d.nb;
         m->dom_valid = 1;
     }
-    for (int64_t g = (int64_t)blockIdx.x * 4 + wid; g < pv.t[0]; g += (int64_t)gridDim.x * 4) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < pv.t[0];
+         g += (int64_t)gridDim.x * blockDim.x) {
         const int j = pv.template job<&JobInfo::od>(g);
         const JobInfo d = pv.info(j);
         const EsdfJob &job = jl.j[j];
         const int64_t db = g - d.od;
         int x, y, z;
         dom_coords(d, db, x, y, z);
-        int64_t idx = -1;
-        if (lane == 0) idx = hash_find(job.tkeys, job.tvals, job.tmask, pack_key(d.lo[0] + x, d.lo[1] + y, d.lo[2] + z));
-        idx = __shfl(idx, 0, 64);
-        if (lane == 0) job.page[db] = (int32_t)idx;
-        uint64_t w = 0;
-        if (idx >= 0) {
-            const S *Db = (const S *)job.D + idx * 512 + lane;
-            const S *Wb = (const S *)job.W + idx * 512 + lane;
-            // all reads before the first write (the seeds), so that they overlap
-            float Dk[8], Wk[8];
+        const int64_t idx =
+            hash_find(job.tkeys, job.tvals, job.tmask, pack_key(d.lo[0] + x, d.lo[1] + y, d.lo[2] + z));
+        job.page[db] = (int32_t)idx;
+        if (blk) blk[g] = (int32_t)idx;  // the launch's own copy, read by the column passes
+        if (idx < 0) {
+            uint4 *w = (uint4 *)(sites + g * 8);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                Dk[k] = ldv(Db + 64 * k);
-                Wk[k] = ldv(Wb + 64 * k);
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const float Dv = Dk[k], Wv = Wk[k];
-                const uint64_t m = __ballot(Wv > 0.0f && fabsf(Dv) <= vs);
-                if (lane == k) w = m;
-                if constexpr (SEEDS)
-                    job.seeds[g * 512 + lane + 64 * k] =
-                        !(Wv > 0.0f) ? __builtin_nanf("")
-                                     : (fabsf(Dv) < tau ? Dv : (Dv > 0.0f ? __builtin_inff() : -__builtin_inff()));
-            }
+            for (int k = 0; k < 4; ++k) w[k] = make_uint4(0u, 0u, 0u, 0u);
         }
-        if (lane < 8) sites[g * 8 + lane] = w;
+    }
+    for (int64_t w = (int64_t)blockIdx.x * 4 + wid; w < pv.t[1]; w += (int64_t)gridDim.x * 4) {
+        const int jj = pv.template job<&JobInfo::ob>(w);
+        const JobInfo d = pv.info(jj);
+        const EsdfJob &job = jl.j[jj];
+        const int64_t idx = w - d.ob;
+        int bx, by, bz;
+        unpack_key(job.keys[idx], bx, by, bz);
+        const int64_t g = d.od + dom_index(d, bx - d.lo[0], by - d.lo[1], bz - d.lo[2]);
+        const S *Db = (const S *)job.D + idx * 512 + lane;
+        const S *Wb = (const S *)job.W + idx * 512 + lane;
+        // all reads before the first write (the seeds), so that they overlap
+        float Dk[8], Wk[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            Dk[k] = ldv(Db + 64 * k);
+            Wk[k] = ldv(Wb + 64 * k);
+        }
+        uint64_t wm = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float Dv = Dk[k], Wv = Wk[k];
+            const uint64_t m = __ballot(Wv > 0.0f && fabsf(Dv) <= vs);
+            if (lane == k) wm = m;
+            if constexpr (SEEDS)
+                job.seeds[g * 512 + lane + 64 * k] =
+                    !(Wv > 0.0f) ? __builtin_nanf("")
+                                 : (fabsf(Dv) < tau ? Dv : (Dv > 0.0f ? __builtin_inff() : -__builtin_inff()));
+        }
+        if (lane < 8) sites[g * 8 + lane] = wm;
     }
 }
 
@@ -517,6 +552,224 @@ __global__ __launch_bounds__(512) void k_edt_z_vox(const JobList<NJ> jl, const u
 }
 
 // ------------------------------------------------------------------------
+// Column passes.  Each workgroup owns a segment of Sseg blocks of one block
+// column along the pass axis and stages the segment with HB halo blocks on
+// each side once, so that no block is staged more than 1 + 2 HB / Sseg times
+// (the per-block passes above stage 2 HB + 1 blocks for every block).
+//
+// k_edt_xy fuses the x pass into the y pass: the x distances of the staged
+// blocks of a y column (bx, *, bz) come from the site masks straight into
+// LDS, in the column layout of k_edt_y_col, and g2 is written only for the
+// segment's blocks that the z pass reads (those with an allocated block
+// within HB blocks along z).  k_edt_z_col stages g2 of a z column (bx, by,
+// *) that holds an allocated block and writes phi of its allocated blocks.
+// Both passes read the launch's copy of the page (blk: buffer index per
+// dense block, -1 when unallocated), never the submap's bookkeeping.
+//
+// The searches and exit tests are those of k_edt_y_col and k_edt_z_vox, so
+// every squared distance, and phi, is the same bit for bit.
+constexpr int kColMaxStage = 48;  // staged blocks of a segment: Sseg + 2 HB
+
+template <int NJ>
+__global__ __launch_bounds__(256) void k_edt_xy(const JobList<NJ> jl, int Sseg, const uint64_t *__restrict__ sites,
+                                                const int32_t *__restrict__ blk, uint16_t *__restrict__ g2, int R,
+                                                int HB)
+{
+    __shared__ Plan lds;
+    // 64 columns (x + 8 z) of 4 * (2 nst + 3) bytes: 4 bytes of margin, then
+    // the 8 nst staged rows along y; an odd stride in dwords puts the 8 x
+    // columns a wave reads in different banks
+    __shared__ __align__(16) uint32_t colw[64 * (2 * kColMaxStage + 3)];
+    __shared__ uint64_t need_s;
+    uint8_t *colb = (uint8_t *)colw;
+    PlanView<NJ> pv;
+    pv.init(jl, 8 * HB, lds, Sseg);
+    const int tid = threadIdx.x;
+    const int x = tid & 7, y = (tid >> 3) & 7, z = tid >> 6;  // the lane's voxels: (x, y, z) and (x, y, z + 4)
+    const int R2 = R * R;
+    for (int64_t c = blockIdx.x; c < pv.t[4]; c += gridDim.x) {
+        const JobInfo d = pv.info(pv.template job<&JobInfo::oxy>(c));
+        const int nseg = (d.dim[1] + Sseg - 1) / Sseg;
+        const int64_t cl = c - d.oxy;
+        const int seg = (int)(cl % nseg);
+        const int64_t cc = cl / nseg;
+        const int bx = (int)(cc % d.dim[0]), bz = (int)(cc / d.dim[0]);
+        const int y0 = seg * Sseg, y1 = min(y0 + Sseg, d.dim[1]);
+        const int nst = (y1 - y0) + 2 * HB;  // staged blocks y0 - HB .. y1 + HB - 1
+        const int colB = 4 * (2 * nst + 3);
+        // output blocks that the z pass reads: an allocated block within HB along z
+        if (tid < 64) {
+            const int j = y0 + tid;
+            bool need = false;
+            if (j < y1) {
+                const int za = max(0, bz - HB), zb = min(d.dim[2] - 1, bz + HB);
+                for (int zz = za; zz <= zb; ++zz) need = need || blk[d.od + dom_index(d, bx, j, zz)] >= 0;
+            }
+            const uint64_t m = __ballot(need);
+            if (tid == 0) need_s = m;
+        }
+        __syncthreads();
+        const uint64_t need = need_s;
+        if (need != 0) {
+            // x distances of the staged blocks, one (y, z) row of 8 voxels per
+            // item: byte y of site word z of the 2 HB + 1 blocks along x
+            // (outside the domain: no sites; staged blocks outside it: none)
+            for (int e = tid; e < nst * 64; e += 256) {
+                const int i = e >> 6, yr = e & 7, zr = (e >> 3) & 7;
+                const int j = y0 - HB + i;
+                uint64_t out = ~0ull;
+                if (j >= 0 && j < d.dim[1]) {
+                    const int64_t g = d.od + dom_index(d, bx, j, bz);
+                    uint64_t wv[2 * kMaxHalo + 1];
+#pragma unroll
+                    for (int k = 0; k < 2 * kMaxHalo + 1; ++k) {
+                        const int nx = bx + k - HB;
+                        const bool ok = k < 2 * HB + 1 && nx >= 0 && nx < d.dim[0];
+                        const uint64_t v = sites[(ok ? g + (k - HB) : g) * 8 + zr];
+                        wv[k] = ok ? v : 0ull;
+                    }
+                    uint64_t lo = 0, hi = 0;
+#pragma unroll
+                    for (int k = 0; k < 2 * kMaxHalo + 1; ++k) {
+                        const uint64_t byte = (wv[k] >> (8 * yr)) & 0xFFull;
+                        const int pos = 8 * k;
+                        if (pos < 64) lo |= byte << pos;
+                        else hi |= byte << (pos - 64);
+                    }
+                    out = 0;
+#pragma unroll
+                    for (int xx = 0; xx < 8; ++xx) {
+                        const int dist = nearest_bit(lo, hi, 8 * HB + xx);
+                        out |= (uint64_t)(dist <= R ? dist : 255) << (8 * xx);
+                    }
+                }
+                uint8_t *dst = colb + 8 * zr * colB + 4 + 8 * i + yr;
+#pragma unroll
+                for (int xx = 0; xx < 8; ++xx) dst[xx * colB] = (uint8_t)(out >> (8 * xx));
+            }
+            __syncthreads();
+            const int c0 = x + 8 * z, c1 = x + 8 * (z + 4);
+            const uint32_t *cw0 = colw + c0 * (colB / 4), *cw1 = colw + c1 * (colB / 4);
+            for (int io = 0; io < y1 - y0; ++io) {
+                if (!((need >> io) & 1ull)) continue;  // uniform
+                const int Y = 8 * (HB + io) + y;
+                // as in k_edt_y_col: rows Y - 4m - 4 .. Y - 4m - 1 in dword (Y >> 2) - m
+                // at byte Y & 3; rows Y + 4m + 1 .. Y + 4m + 4 in dword ((Y + 5) >> 2) + m
+                // at byte (Y + 5) & 3
+                const int dn = Y >> 2, sdn = Y & 3, up = (Y + 5) >> 2, sup = (Y + 5) & 3;
+                int b0 = sq8(colb[c0 * colB + 4 + Y]), b1 = sq8(colb[c1 * colB + 4 + Y]);
+                uint32_t dhi0 = cw0[dn + 1], dhi1 = cw1[dn + 1];
+                uint32_t ulo0 = cw0[up], ulo1 = cw1[up];
+                for (int dd = 1, m = 0; dd <= R; dd += 8) {
+                    if (dd * dd >= max(b0, b1)) break;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h, ++m) {
+                        const uint32_t dlo0 = cw0[dn - m], dlo1 = cw1[dn - m];
+                        const uint32_t uhi0 = cw0[up + m + 1], uhi1 = cw1[up + m + 1];
+                        const uint32_t dv0 = __builtin_amdgcn_alignbyte(dhi0, dlo0, sdn);
+                        const uint32_t dv1 = __builtin_amdgcn_alignbyte(dhi1, dlo1, sdn);
+                        const uint32_t uv0 = __builtin_amdgcn_alignbyte(uhi0, ulo0, sup);
+                        const uint32_t uv1 = __builtin_amdgcn_alignbyte(uhi1, ulo1, sup);
+                        dhi0 = dlo0; dhi1 = dlo1;
+                        ulo0 = uhi0; ulo1 = uhi1;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int e = 4 * m + 1 + k;
+                            if (e <= R) {
+                                const int ee = e * e;
+                                b0 = min(b0, min(sq8((uint8_t)(dv0 >> (8 * (3 - k)))), sq8((uint8_t)(uv0 >> (8 * k)))) + ee);
+                                b1 = min(b1, min(sq8((uint8_t)(dv1 >> (8 * (3 - k)))), sq8((uint8_t)(uv1 >> (8 * k)))) + ee);
+                            }
+                        }
+                    }
+                }
+                const int64_t g = d.od + dom_index(d, bx, y0 + io, bz);
+                g2[g * 512 + tid] = b0 <= R2 ? (uint16_t)b0 : (uint16_t)0xFFFF;
+                g2[g * 512 + tid + 256] = b1 <= R2 ? (uint16_t)b1 : (uint16_t)0xFFFF;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int NJ>
+__global__ __launch_bounds__(512) void k_edt_z_col(const JobList<NJ> jl, int Sseg, const uint16_t *__restrict__ g2,
+                                                   const int32_t *__restrict__ blk, int R, int HB, float vs,
+                                                   float dmax)
+{
+    __shared__ Plan lds;
+    __shared__ __align__(16) uint32_t colw[kColMaxStage * 256];  // staged g2, block by block
+    __shared__ int32_t sblk[kColMaxStage + 2 * kMaxHalo];         // blk of z0 - 2 HB .. z1 + 2 HB - 1
+    __shared__ uint8_t sneed[kColMaxStage];                      // staged block read by an allocated block
+    PlanView<NJ> pv;
+    pv.init(jl, 8 * HB, lds, Sseg);
+    const uint16_t *col = (const uint16_t *)colw;
+    const int tid = threadIdx.x;
+    const int R2 = R * R;
+    const int base = tid & 63;
+    for (int64_t c = blockIdx.x; c < pv.t[5]; c += gridDim.x) {
+        const int jj = pv.template job<&JobInfo::ozc>(c);
+        const JobInfo d = pv.info(jj);
+        const EsdfJob &job = jl.j[jj];
+        const int nseg = (d.dim[2] + Sseg - 1) / Sseg;
+        const int64_t cl = c - d.ozc;
+        const int seg = (int)(cl % nseg);
+        const int64_t cc = cl / nseg;
+        const int bx = (int)(cc % d.dim[0]), by = (int)(cc / d.dim[0]);
+        const int z0 = seg * Sseg, z1 = min(z0 + Sseg, d.dim[2]);
+        const int nst = (z1 - z0) + 2 * HB;  // staged blocks z0 - HB .. z1 + HB - 1
+        for (int t = tid; t < nst + 2 * HB; t += 512) {
+            const int zz = z0 - 2 * HB + t;
+            sblk[t] = zz >= 0 && zz < d.dim[2] ? blk[d.od + dom_index(d, bx, by, zz)] : -1;
+        }
+        __syncthreads();
+        bool any = false;
+        for (int i = 0; i < z1 - z0; ++i) any = any || sblk[2 * HB + i] >= 0;
+        if (any) {  // uniform
+            // staged block i (z = z0 - HB + i) is written by k_edt_xy iff an
+            // allocated block lies within HB of it: sblk[i .. i + 2 HB]
+            for (int i = tid; i < nst; i += 512) {
+                const int zz = z0 - HB + i;
+                bool nd = false;
+                for (int t = i; t <= i + 2 * HB; ++t) nd = nd || sblk[t] >= 0;
+                sneed[i] = nd && zz >= 0 && zz < d.dim[2];
+            }
+            __syncthreads();
+            for (int e = tid; e < nst * 256; e += 512) {
+                const int i = e >> 8, q = e & 255;
+                uint32_t v = 0xFFFFFFFFu;
+                if (sneed[i]) v = ((const uint32_t *)(g2 + (d.od + dom_index(d, bx, by, z0 - HB + i)) * 512))[q];
+                colw[e] = v;
+            }
+            __syncthreads();
+            for (int io = 0; io < z1 - z0; ++io) {
+                const int32_t idx = sblk[2 * HB + io];
+                if (idx < 0) continue;  // uniform
+                const int64_t g = d.od + dom_index(d, bx, by, z0 + io);
+                const float seed = job.seeds[g * 512 + tid];  // from k_page_sites
+                float out = seed;  // unobserved (NaN) or in the band (D)
+                if (__builtin_isinf(seed)) {
+                    const int Z = 8 * (HB + io) + (tid >> 6);
+                    auto at = [&](int zz) { return col[(zz >> 3) * 512 + base + 64 * (zz & 7)]; };
+                    int best = inf16(at(Z));
+                    for (int dd = 1; dd <= R; dd += kScanStep) {  // as in k_edt_z_vox
+                        if (dd * dd >= best) break;
+#pragma unroll
+                        for (int q = 0; q < kScanStep; ++q) {
+                            const int e = dd + q;
+                            if (e <= R) best = min(best, min(inf16(at(Z - e)), inf16(at(Z + e))) + e * e);
+                        }
+                    }
+                    out = phi_value(seed, best, R2, vs, dmax);
+                }
+                job.phi[(int64_t)idx * 512 + tid] = out;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
 // Per-line passes: lower envelope of parabolas (Felzenszwalb and
 // Huttenlocher, edt_envelope.h).  One wave per block column; lane = one
 // line.  A line longer than kWin voxels is cut into output segments that each
@@ -729,8 +982,28 @@ void chunk_cols(covox_submap *const *subs, int n, int HB, int64_t &cy, int64_t &
     }
 }
 
-// force < 0: shapes by the tuning (or COVOX_EDT_MODE); else bit 0 = y
-// envelopes, bit 1 = z envelopes.
+// Column segments along axis `c` (columns spanned by the other two axes) of
+// the column passes over the host-side bound box.
+int64_t bound_segs(const covox_submap *s, int c, int S)
+{
+    if (!s->bound_valid) return 0;
+    int64_t cols = 1;
+    for (int a = 0; a < 3; ++a)
+        if (a != c) cols *= (int64_t)(s->bound_hi[a] - s->bound_lo[a] + 1);
+    const int64_t L = s->bound_hi[c] - s->bound_lo[c] + 1;
+    return cols * ((L + S - 1) / S);
+}
+
+// Segment length of the column passes for halo HB (0: per-block passes).
+int col_segment(const covox_ctx *ctx, int HB)
+{
+    const int64_t S = ctx->tune.edt_col_seg;
+    if (S <= 0) return 0;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(S, kColMaxStage - 2 * HB));
+}
+
+// force < 0: pass layout and shapes by the tuning (or COVOX_EDT_MODE); else
+// the per-block passes with bit 0 = y envelopes, bit 1 = z envelopes.
 template <int NJ>
 int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int force = -1)
 {
@@ -752,10 +1025,13 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
         nb += std::min(s->nb_upper, s->cap);
     }
     chunk_cols(subs, n, HB, cy, cz);
+    const int Sseg = force >= 0 ? 0 : col_segment(ctx, HB);
+    const bool cols = edt && Sseg > 0;
     // a buffer that grows is freed: the passes of an earlier update on the
     // other stream may still read it
     bool grows = ctx->sites_cap[slot] < nd ||
-                 (edt && (ctx->seeds_cap[slot] < nd || ctx->g1_cap < nd || ctx->g2_cap < nd));
+                 (edt && (ctx->seeds_cap[slot] < nd || (!cols && ctx->g1_cap < nd) || ctx->g2_cap < nd)) ||
+                 (cols && ctx->blk_cap[slot] < nd);
     for (int i = 0; i < n; ++i) grows = grows || subs[i]->page_cap < std::max<int64_t>(bound_blocks(subs[i]), 1);
     if (grows && edt_stream != ctx->stream && !ctx->capturing &&
         (rc = hip_check(ctx, hipStreamSynchronize(edt_stream), "esdf stream sync")))
@@ -775,28 +1051,32 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
         if ((rc = ensure_buffer(ctx, (void **)&ctx->seeds[slot], &ctx->seeds_cap[slot], nd, 512 * sizeof(float),
                                 "phi seeds")))
             return rc;
-        if ((rc = ensure_buffer(ctx, (void **)&ctx->g1, &ctx->g1_cap, nd, 512, "edt g1"))) return rc;
+        if (!cols && (rc = ensure_buffer(ctx, (void **)&ctx->g1, &ctx->g1_cap, nd, 512, "edt g1"))) return rc;
         if ((rc = ensure_buffer(ctx, (void **)&ctx->g2, &ctx->g2_cap, nd, 1024, "edt g2"))) return rc;
     }
+    if (cols && (rc = ensure_buffer(ctx, (void **)&ctx->blk[slot], &ctx->blk_cap[slot], nd, sizeof(int32_t),
+                                    "esdf block index")))
+        return rc;
+    int32_t *const blk = cols ? ctx->blk[slot] : nullptr;
     uint64_t *const sites = ctx->sites[slot];
     const JobList<NJ> jl = make_jobs<NJ>(subs, n, ctx->snap[slot], ctx->seeds[slot]);
     const float vs = (float)p.voxel_size, tau = (float)band_limit(p), dmax = (float)p.d_max;
     const bool h = p.precision == COVOX_FP16;
     {
         TimedLaunch tl(ctx, COVOX_K_ESDF_PAGE);
-        const dim3 grid(clamp_grid((nd + 3) / 4));
+        const dim3 grid(clamp_grid(std::max((nd + 255) / 256, (nb + 3) / 4)));
         if (h && edt)
             hipLaunchKernelGGL((k_page_sites<__half, NJ, true>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               sites);
+                               sites, blk);
         else if (h)
             hipLaunchKernelGGL((k_page_sites<__half, NJ, false>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               sites);
+                               sites, blk);
         else if (edt)
             hipLaunchKernelGGL((k_page_sites<float, NJ, true>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               sites);
+                               sites, blk);
         else
             hipLaunchKernelGGL((k_page_sites<float, NJ, false>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               sites);
+                               sites, blk);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "page launch"))) return rc;
     for (int i = 0; i < n; ++i) subs[i]->page_version = subs[i]->version;
@@ -811,7 +1091,7 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
         env_y = (force & 1) != 0;
         env_z = (force & 2) != 0;
     }
-    ctx->esdf_used_page = env_z;  // the z envelopes read the page
+    ctx->esdf_used_page = !cols && env_z;  // the z envelopes read the page
     // the passes read nothing the next integration writes: on their own
     // stream they wait for the page kernel only
     hipStream_t base = ctx->stream;
@@ -820,6 +1100,27 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
             (rc = hip_check(ctx, hipStreamWaitEvent(edt_stream, ctx->ev_paged, 0), "paged wait")))
             return rc;
         ctx->stream = edt_stream;  // for the launches and their timing events below
+    }
+    if (cols) {
+        int64_t sy = 0, sz = 0;
+        for (int i = 0; i < n; ++i) {
+            sy += std::max<int64_t>(bound_segs(subs[i], 1, Sseg), 1);
+            sz += std::max<int64_t>(bound_segs(subs[i], 2, Sseg), 1);
+        }
+        {
+            TimedLaunch tl(ctx, COVOX_K_EDT_Y);
+            hipLaunchKernelGGL((k_edt_xy<NJ>), dim3(cap_grid(ctx, clamp_grid(sy))), dim3(256), 0, ctx->stream, jl, Sseg,
+                               sites, blk, ctx->g2, R, HB);
+        }
+        {
+            TimedLaunch tl(ctx, COVOX_K_EDT_Z);
+            hipLaunchKernelGGL((k_edt_z_col<NJ>), dim3(cap_grid(ctx, clamp_grid(sz))), dim3(512), 0, ctx->stream, jl,
+                               Sseg, ctx->g2, blk, R, HB, vs, dmax);
+        }
+        ctx->stream = base;
+        if ((rc = hip_check(ctx, hipGetLastError(), "esdf launch"))) return rc;
+        for (int i = 0; i < n; ++i) subs[i]->esdf_version = subs[i]->version;
+        return COVOX_OK;
     }
     {
         TimedLaunch tl(ctx, COVOX_K_EDT_X);
@@ -905,28 +1206,41 @@ int autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int n)
     }
     const int32_t saved_timing = ctx->timing;
     ctx->timing = 0;  // no per-kernel events inside the measured region
-    float best_ms[4];
-    for (int combo = 0; combo < 4 && !rc; ++combo) {
-        best_ms[combo] = 1e30f;
-        rc = run(combo);  // warm-up (buffers, caches)
+    covox_tuning &t = ctx->tune;
+    const int64_t saved_seg = t.edt_col_seg;
+    // candidates: the four shapes of the per-block passes, then the column
+    // passes at five segment lengths
+    constexpr int kSegs[5] = {2, 4, 8, 16, 32};
+    constexpr int kCand = 4 + 5;
+    float best_ms[kCand];
+    for (int cand = 0; cand < kCand && !rc; ++cand) {
+        best_ms[cand] = 1e30f;
+        const int force = cand < 4 ? cand : -1;
+        if (cand >= 4) t.edt_col_seg = kSegs[cand - 4];
+        rc = run(force);  // warm-up (buffers, caches)
         for (int rep = 0; rep < 3 && !rc; ++rep) {
             rc = hip_check(ctx, hipEventRecord(e0, ctx->stream), "autotune record");
-            if (!rc) rc = run(combo);
+            if (!rc) rc = run(force);
             if (!rc) rc = hip_check(ctx, hipEventRecord(e1, ctx->stream), "autotune record");
             if (!rc) rc = hip_check(ctx, hipEventSynchronize(e1), "autotune sync");
             float ms = 0;
             if (!rc) rc = hip_check(ctx, hipEventElapsedTime(&ms, e0, e1), "autotune elapsed");
-            if (!rc) best_ms[combo] = std::min(best_ms[combo], ms);
+            if (!rc) best_ms[cand] = std::min(best_ms[cand], ms);
         }
     }
+    t.edt_col_seg = saved_seg;
     ctx->timing = saved_timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     int best = 0;
-    for (int c = 1; c < 4; ++c)
+    for (int c = 1; c < kCand; ++c)
         if (best_ms[c] < best_ms[best]) best = c;
-    covox_tuning &t = ctx->tune;
+    if (best >= 4) {
+        t.edt_col_seg = kSegs[best - 4];
+        return COVOX_OK;
+    }
+    t.edt_col_seg = 0;
     if (best & 1) t.edt_y_env_min_cols = std::min(t.edt_y_env_min_cols, cy);
     else t.edt_y_env_min_cols = std::max(t.edt_y_env_min_cols, cy + 1);
     if (best & 2) t.edt_z_env_min_cols = std::min(t.edt_z_env_min_cols, cz);

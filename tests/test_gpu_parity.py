@@ -426,6 +426,49 @@ def test_mixed_pass_shapes_and_autotune_leave_phi_unchanged(cv):
     ctx.close()
 
 
+@pytest.mark.parametrize("workload", ["tiny", "room40", "outdoor"])
+def test_column_passes_parity(cv, workload):
+    """The column passes (x fused into y, segments of S blocks staged with
+    their halos) give the oracle's phi bit for bit at every segment length,
+    including 1 (all halo), lengths that do not divide the box and lengths
+    above the clamp; the batched form over several submaps equals the
+    per-submap updates."""
+    import torch
+    if workload == "outdoor":
+        w = sg.mav(n_frames=300)
+        params = dict(voxel_size=0.1, trunc_vox=4, max_range=10.0, d_max=3.0, block_capacity=32768)
+        oparams = orc.Params(vs=0.1, trunc_vox=4, max_range=10.0, d_max=3.0)
+        starts, nf = (0, 100, 200), 30
+    else:
+        w = sg.tiny() if workload == "tiny" else sg.room(n_frames=40)
+        params = dict(block_capacity=16384)
+        oparams = _oracle_params()
+        starts, nf = (0,), w.n_frames
+    ctx = _ctx(cv, **params)
+    subs, want = [], []
+    for k, f0 in enumerate(starts):
+        T = sg.gravity_aligned(w.poses[f0]) if workload == "outdoor" else np.eye(4)
+        fr = w.frames(f0, f0 + nf)
+        s = ctx.submap_create(T)
+        ctx.integrate_depth_batch(s, torch.from_numpy(fr).cuda(), w.cam.K, w.poses[f0:f0 + nf])
+        subs.append(s)
+        r = orc.Submap(oparams, T)
+        for f in range(nf):
+            r.integrate(fr[f], w.cam.K, w.poses[f0 + f])
+        r.update_esdf()
+        want.append(r.export())
+    for seg in (1, 2, 3, 8, 64):
+        ctx.set_tuning(edt_col_seg=seg)
+        for s, r in zip(subs, want):
+            ctx.update_esdf(s)
+            assert _compare_phi(ctx.export_blocks(s), r) == 0, seg
+        if len(subs) > 1:
+            ctx.update_esdf_batch(subs[::-1])
+            for s, r in zip(subs, want):
+                assert _compare_phi(ctx.export_blocks(s), r) == 0, ("batch", seg)
+    ctx.close()
+
+
 def test_outdoor_submap_parity_and_batched_esdf(cv):
     """An outdoor submap at the large-scale configuration (0.1 m voxels,
     10 m range, ESDF to 3 m) against the oracle, and the batched ESDF of
