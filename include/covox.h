@@ -348,6 +348,28 @@ int covox_net_get_params(covox_net *net, float *host, int64_t n);
 int covox_net_set_params(covox_net *net, const float *host, int64_t n);
 /* x_dev: device n x 32^3 x 4 floats; out_dev: device n x 5 floats. */
 int covox_net_forward(covox_net *net, const float *x_dev, int32_t n, float *out_dev);
+
+/* Forward pass that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and the same kernels as
+ * covox_net_forward, so the outputs are bit-identical to it; asynchronous on
+ * the context stream.
+ *
+ * The activations live in one static device array of the library, about
+ * 1.6 MB per pair for COVOX_NET_NOALLOC_MAX_PAIRS pairs (13.2 MB), which each
+ * GPU the library runs on holds until the process ends.  Every call on a GPU
+ * shares that array: calls that overlap on one GPU (two streams, two
+ * contexts or two host threads) race and give undefined outputs.  Each call
+ * writes every activation it reads, so nothing carries over between calls.
+ *
+ *   x_dev    device n x 32^3 x 4 floats (caller-owned, as for covox_net_forward)
+ *   out_dev  device n x 5 floats (caller-owned)
+ *   n        1 .. COVOX_NET_NOALLOC_MAX_PAIRS; a larger n returns COVOX_EINVAL
+ *            with a message and launches nothing.
+ * COVOX_EINVAL also for null pointers, n <= 0, or a net whose context is
+ * destroyed. */
+#define COVOX_NET_NOALLOC_MAX_PAIRS 8
+int covox_net_forward_noalloc(covox_net *net, const float *x_dev, int32_t n, float *out_dev);
 /* One Adam step (beta 0.9 / 0.999) on the loss mean over the batch of
  * |t - t*|^2 / trans_scale^2 + |(c, s) - (c*, s*)|^2; y_dev: device n x 5.
  * loss_host (nullable) receives the loss (synchronous when given). */

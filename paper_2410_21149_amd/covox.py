@@ -29,6 +29,7 @@ WEIGHT_CONSTANT, WEIGHT_INV_DEPTH2 = 0, 1
 PROJECTIVE, RAYCAST = 0, 1
 ESDF_EXACT, ESDF_WAVEFRONT = 0, 1
 GAUSS_NEWTON, LEVENBERG_MARQUARDT = 0, 1
+NET_NOALLOC_MAX_PAIRS = 8  # COVOX_NET_NOALLOC_MAX_PAIRS
 KERNELS = ["probe", "scan", "integrate", "esdf_page", "esdf_sites", "edt_x", "edt_y", "edt_z", "iso", "align",
            "summary", "net", "ray_mark", "ray_accum", "ray_apply", "pgo", "wavefront", "hash"]
 
@@ -137,6 +138,7 @@ _sig = {
     "covox_net_get_params": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
     "covox_net_set_params": (ctypes.c_int, [_vp, _fp, ctypes.c_int64]),
     "covox_net_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp]),
+    "covox_net_forward_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp]),
     "covox_net_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, _fp]),
     "covox_net_gradients": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, _fp, _fp]),
     "covox_align_learned": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_double,
@@ -613,6 +615,14 @@ class Net:
         out = torch.empty((x.shape[0], 5), dtype=torch.float32, device=x.device)
         self.ctx._check(_lib.covox_net_forward(self.handle, self._x(x), x.shape[0], ctypes.c_void_p(out.data_ptr())),
                         "net_forward")
+        return out
+
+    def forward_noalloc(self, x: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """covox_net_forward_noalloc: the forward pass into the caller's
+        `out` (n x 5 float32 on the device), n <= NET_NOALLOC_MAX_PAIRS,
+        with no device allocation by the library."""
+        self.ctx._check(_lib.covox_net_forward_noalloc(self.handle, self._x(x), x.shape[0],
+                                                       ctypes.c_void_p(out.data_ptr())), "net_forward_noalloc")
         return out
 
     def train_step(self, x: torch.Tensor, y: torch.Tensor, lr: float, trans_scale: float = 3.0, want_loss=True):

@@ -414,6 +414,10 @@ int covox_create(covox_ctx **out, const covox_params *p)
         delete ctx;
         return COVOX_EHIP;
     }
+    if (noalloc_scratch_init(ctx) != COVOX_OK) {
+        delete ctx;
+        return COVOX_EHIP;
+    }
     if (p->integrator == COVOX_RAYCAST && ensure_ray_acc(ctx) != COVOX_OK) {
         delete ctx;
         return COVOX_EHIP;
@@ -938,6 +942,12 @@ int covox_net_forward(covox_net *net, const float *x_dev, int32_t n, float *out_
     if (!net || !net_ctx(net) || !x_dev || !out_dev || n <= 0) return COVOX_EINVAL;
     COVOX_NOT_DURING_CAPTURE(net_ctx(net), "net_forward");
     return net_forward_api(net, x_dev, n, out_dev);
+}
+
+int covox_net_forward_noalloc(covox_net *net, const float *x_dev, int32_t n, float *out_dev)
+{
+    if (!net || !net_ctx(net) || !x_dev || !out_dev || n <= 0) return COVOX_EINVAL;
+    return net_forward_noalloc(net, x_dev, n, out_dev);
 }
 
 int covox_net_train_step(covox_net *net, const float *x_dev, const float *y_dev, int32_t n, float lr, float trans_scale,

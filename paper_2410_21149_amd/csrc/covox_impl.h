@@ -498,6 +498,11 @@ int64_t net_num_params(const covox_net *net);
 int net_get_params(covox_net *net, float *host, int64_t n);
 int net_set_params(covox_net *net, const float *host, int64_t n);
 int net_forward_api(covox_net *net, const float *x_dev, int n, float *out_dev);
+// Forward pass with the activations in the library's static device scratch
+// (no allocation); n <= COVOX_NET_NOALLOC_MAX_PAIRS.
+int net_forward_noalloc(covox_net *net, const float *x_dev, int n, float *out_dev);
+// Takes the scratch's device address on ctx->device, once per device.
+int noalloc_scratch_init(covox_ctx *ctx);
 // One training step enqueued on the context stream (no host synchronisation);
 // the step's loss is then at net_loss_dev(net).
 int net_train_async(covox_net *net, const float *x_dev, const float *y_dev, int n, float lr, float trans_scale);

@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 namespace covox {
@@ -359,13 +360,36 @@ static int net_reserve(covox_net *net, int n)
 }
 
 template <int L>
-static void launch_conv_fwd(covox_net *net, const uint16_t *x, int n)
+static void launch_conv_fwd(covox_net *net, const uint16_t *x, uint16_t *y, int n)
 {
     constexpr ConvShape s = kShapes[L];
     const int64_t npos = (int64_t)n * s.dout * s.dout * s.dout;
     const unsigned grid = (unsigned)std::min<int64_t>((npos + 15) / 16, 1 << 20);
     hipLaunchKernelGGL((k_conv_fwd<s.cin, s.cout, s.din, s.dout, s.stride>), dim3(grid), dim3(64 * (s.cout / 16)), 0,
-                       net->ctx->stream, x, net->wb[L], net->w + net->P.off_b[L], net->a[L], npos);
+                       net->ctx->stream, x, net->wb[L], net->w + net->P.off_b[L], y, npos);
+}
+
+// Buffers of one forward pass: the bf16 input, the four bf16 layer outputs,
+// the pooled features and the network outputs.
+struct FwdBuffers {
+    uint16_t *x0;
+    uint16_t *a[kLayers];
+    float *pooled, *out;
+};
+
+// The forward pass's launches on the context stream, into the given buffers
+// (every element of each buffer is written before it is read).
+static void forward_launches(covox_net *net, const float *x_dev, int n, const FwdBuffers &b)
+{
+    covox_ctx *ctx = net->ctx;
+    const int64_t nx = (int64_t)n * 32768 * 4;
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(nx, 256)), dim3(256), 0, ctx->stream, x_dev, b.x0, nx);
+    launch_conv_fwd<0>(net, b.x0, b.a[0], n);
+    launch_conv_fwd<1>(net, b.a[0], b.a[1], n);
+    launch_conv_fwd<2>(net, b.a[1], b.a[2], n);
+    launch_conv_fwd<3>(net, b.a[2], b.a[3], n);
+    hipLaunchKernelGGL(k_pool_fc, dim3(n), dim3(64), 0, ctx->stream, b.a[3], net->w + net->P.off_fcw,
+                       net->w + net->P.off_fcb, b.pooled, b.out, n);
 }
 
 static int net_forward(covox_net *net, const float *x_dev, int n)
@@ -373,16 +397,10 @@ static int net_forward(covox_net *net, const float *x_dev, int n)
     covox_ctx *ctx = net->ctx;
     int rc = net_reserve(net, n);
     if (rc) return rc;
-    const int64_t nx = (int64_t)n * 32768 * 4;
-    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(nx, 256)), dim3(256), 0, ctx->stream, x_dev, net->x0, nx);
     {
         TimedLaunch tl(ctx, COVOX_K_NET);
-        launch_conv_fwd<0>(net, net->x0, n);
-        launch_conv_fwd<1>(net, net->a[0], n);
-        launch_conv_fwd<2>(net, net->a[1], n);
-        launch_conv_fwd<3>(net, net->a[2], n);
-        hipLaunchKernelGGL(k_pool_fc, dim3(n), dim3(64), 0, ctx->stream, net->a[3], net->w + net->P.off_fcw,
-                           net->w + net->P.off_fcb, net->pooled, net->out, n);
+        forward_launches(net, x_dev, n, FwdBuffers{net->x0, {net->a[0], net->a[1], net->a[2], net->a[3]},
+                                                   net->pooled, net->out});
     }
     return hip_check(ctx, hipGetLastError(), "net forward");
 }
@@ -443,6 +461,79 @@ int net_forward_api(covox_net *net, const float *x_dev, int n, float *out_dev)
 }
 
 const float *net_loss_dev(const covox_net *net) { return net->loss; }
+
+// ------------------------------------------------- forward without allocation
+//
+// Activations of at most COVOX_NET_NOALLOC_MAX_PAIRS pairs in a file-scope
+// device array.  Its address on each device comes from hipGetSymbolAddress,
+// taken once per device when a context is created there; host code never
+// uses the array's name as a device address.
+
+constexpr int64_t kNoAllocX0 = (int64_t)COVOX_NET_NOALLOC_MAX_PAIRS * 32768 * 4;  // bf16 elements
+constexpr int64_t noalloc_act(int l)
+{
+    return (int64_t)COVOX_NET_NOALLOC_MAX_PAIRS * kShapes[l].dout * kShapes[l].dout * kShapes[l].dout *
+           kShapes[l].cout;
+}
+constexpr int64_t kNoAllocBytes =
+    2 * (kNoAllocX0 + noalloc_act(0) + noalloc_act(1) + noalloc_act(2) + noalloc_act(3)) +
+    4 * (int64_t)COVOX_NET_NOALLOC_MAX_PAIRS * kFeat;
+static_assert(kNoAllocBytes % 256 == 0, "scratch regions stay 256-byte aligned");
+
+}  // namespace covox
+
+static __device__ __align__(256) unsigned char scratch[covox::kNoAllocBytes];
+
+namespace covox {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int noalloc_scratch_init(covox_ctx *ctx)
+{
+    const int dev = ctx->device;
+    if (dev < 0 || dev >= kMaxDevices) return fail(ctx, COVOX_EHIP, "no-alloc scratch: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return COVOX_OK;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+    void *ptr = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !ptr)
+        return fail(ctx, COVOX_EHIP, std::string("no-alloc scratch address: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+    return COVOX_OK;
+}
+
+int net_forward_noalloc(covox_net *net, const float *x_dev, int n, float *out_dev)
+{
+    covox_ctx *ctx = net->ctx;
+    if (n > COVOX_NET_NOALLOC_MAX_PAIRS)
+        return fail(ctx, COVOX_EINVAL, "net_forward_noalloc: more than COVOX_NET_NOALLOC_MAX_PAIRS pairs");
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (ctx->device >= 0 && ctx->device < kMaxDevices) base = (unsigned char *)g_scratch_ptr[ctx->device];
+    }
+    if (!base) return fail(ctx, COVOX_EHIP, "net_forward_noalloc: scratch address not set up on this device");
+    // Regions sized for the maximum batch; n pairs use the front of each.
+    FwdBuffers b;
+    b.x0 = (uint16_t *)base;
+    base += 2 * kNoAllocX0;
+    for (int l = 0; l < kLayers; ++l) {
+        b.a[l] = (uint16_t *)base;
+        base += 2 * noalloc_act(l);
+    }
+    b.pooled = (float *)base;
+    b.out = out_dev;
+    forward_launches(net, x_dev, n, b);
+    return hip_check(ctx, hipGetLastError(), "net forward (no allocation)");
+}
 
 int net_train_step(covox_net *net, const float *x_dev, const float *y_dev, int n, float lr, float trans_scale,
                    float *loss_host)
