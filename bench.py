@@ -13,22 +13,34 @@ with --no-graph).  value = frames per second of the faster of the two
 (config.step_mode names it; inputs already resident in device memory);
 config.eager_frames_per_s and config.graph_replay_frames_per_s give both.
 
-Also reported on the same JSON line:
-  roofline      the dominant kernel: algorithmic bytes per launch divided by
-                its mean duration from HIP events recorded around each of its
-                launches in the timed region, against 8 TB/s and against a
-                1 GiB device-to-device copy timed in the same run;
+Also reported on the same JSON line (every figure, with more, is also in the
+full record printed to stderr and, when gpurun_out/ exists, written to
+gpurun_out/bench_detail.json):
+  roofline      the dominant kernel: the algorithmic bytes of the unit its
+                launch belongs to (B_esdf per ESDF update, B_int per frame)
+                divided by its mean duration from HIP events recorded around
+                each of its launches, against 8 TB/s and against a 1 GiB
+                device-to-device copy timed in the same run; and sum of
+                bytes over sum of kernel time for the room step's ESDF and
+                integration, the outdoor batched ESDF of 30 submaps and the
+                outdoor mapping of 3000 frames;
   config.latency_per_frame  one frame integrated plus its ESDF, then a
                 host synchronisation (median, p99, max over the sequence);
-  cpu_baseline  the oracle (single-threaded C) on a bounded
-                prefix of the same workload;
-  align         ESDF alignment of overlapping room submaps: pairs/s and the
-                fraction within 1 cm / 0.1 degrees, 1 start and 8 starts;
-  mav           the outdoor workload: mapping, batched ESDF, alignment, pose
-                graph, learned proposal, and integration time against the
-                updated-voxel count at five voxel sizes (voxel_sweep);
-  hash_table    the hash-table stress test: inserts per second and probe
-                lengths at load factors 0.25 .. 0.85.
+  cpu_baseline  the oracle (plain C, OpenMP over independent items) on the
+                room workload on every host core, then on one thread over
+                the same frames, with the CPU model and thread counts;
+  aligns        ESDF alignment: room submap pairs, and outdoor pairs (every
+                pair of the 30 submaps at block overlap 0.3 .. 0.9, both
+                directions) -- pairs/s, success within 1 cm / 0.1 deg and
+                5 cm / 0.5 deg, aligns/s within 1 cm / 0.1 deg;
+  learned       learned proposal + refinement against plain 8-start on
+                held-out outdoor pairs, with raw success counts;
+  precision     FP32 and FP16 storage against the binary64 oracle on the
+                room workload: D and phi errors, validity, site and band
+                flips, the EDT alone on the same TSDF, and alignment poses.
+
+--cfg4-align runs only the batched alignment of pairs drawn from several
+outdoor scenes (and the accuracy-floor experiments) and prints that record.
 
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
 """
@@ -54,34 +66,40 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kind, census, s_dw):
-    """Compulsory bytes per launch of one kernel kind, averaged over the
-    launches of one step (census = per-frame counts of the workload).
-    s_dw = bytes of D plus W per voxel (8 in FP32, 4 in FP16)."""
-    F = len(census["n_blocks"])
+ESDF_KINDS = ("esdf_page", "edt_x", "edt_y", "edt_z")
+INTEGRATION_KINDS = ("probe", "scan", "integrate")
+
+
+def frame_bytes(census, s_dw):
+    """Algorithmic bytes per frame of the two parts of the step, from the
+    per-frame counts of the workload (s_dw = bytes of D plus W per voxel: 8
+    in FP32, 4 in FP16):
+      integration  B_int  = 4 H W (depth) + 2 s_dw N_upd (state read and
+                   written) + (s_dw 512 + 24) N_new (new blocks initialised;
+                   key, index and slot)
+      ESDF update  B_esdf = (s_dw + 4) 512 n_blocks (D and W read, phi written)
+    Returns two lists, one value per frame."""
     HW = census["H"] * census["W"]
-    nb = census["n_blocks"]          # blocks after each frame
-    new = census["n_new"]
-    upd = census["n_upd"]
-    box = census["n_box"]
-    dense = census["n_dense"]        # dense blocks of the ESDF box after each frame
-    tot = 0.0
-    for f in range(F):
-        if kind == "probe":         # depth image once + candidate flags + read-modify-write of updated voxels
-            tot += 4 * HW + 4 * box[f] + 2 * s_dw * upd[f]
-        elif kind == "scan":        # candidate flags in, touched list out
-            tot += 4 * box[f] + 12 * (census["n_touched"][f])
-        elif kind == "integrate":   # init of new blocks, activation (updates are the probe's)
-            tot += s_dw * 512 * new[f] + 24 * new[f]
-        elif kind == "esdf_page":   # D, W of every block in, page + site masks + phi seeds out
-            tot += s_dw * 512 * nb[f] + 4 * dense[f] + 64 * dense[f] + 4 * 512 * nb[f]
-        elif kind == "edt_x":       # site masks in, g1 (1 B / voxel) out
-            tot += 64 * dense[f] + 512 * dense[f]
-        elif kind == "edt_y":       # g1 in, g2 (2 B / voxel) out
-            tot += 512 * dense[f] + 1024 * dense[f]
-        elif kind == "edt_z":       # g2 of the block columns, phi seeds in, phi out
-            tot += 1024 * nb[f] + 4 * 512 * nb[f] + 4 * 512 * nb[f]
-    return tot / F
+    b_int = [4 * HW + 2 * s_dw * u + (s_dw * 512 + 24) * n for u, n in zip(census["n_upd"], census["n_new"])]
+    b_esdf = [(s_dw + 4) * 512 * nb for nb in census["n_blocks"]]
+    return b_int, b_esdf
+
+
+def unit_bytes(kind, census, s_dw):
+    """Bytes of the unit of work one launch of `kind` belongs to, averaged
+    over the frames: B_esdf for the ESDF kernels (one launch per update),
+    B_int for the integration kernels (one launch per frame)."""
+    b_int, b_esdf = frame_bytes(census, s_dw)
+    b = b_esdf if kind in ESDF_KINDS else b_int
+    return sum(b) / len(b)
+
+
+def part_fraction(bytes_total, kernel_ms, peak=HBM_PEAK_GBS):
+    """Sum of algorithmic bytes over the sum of kernel time, against peak."""
+    if not kernel_ms or kernel_ms <= 0:
+        return {"bytes": bytes_total, "kernel_ms": kernel_ms, "GBs": None, "frac": None}
+    gbs = bytes_total / (kernel_ms * 1e-3) / 1e9
+    return {"bytes": bytes_total, "kernel_ms": kernel_ms, "GBs": gbs, "frac": gbs / peak}
 
 
 def measured_traffic(kind, tuning, census):
@@ -150,22 +168,157 @@ def frustum_box_blocks(w, f, vs, np):
     return int(np.prod(hi - lo + 1))
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, frames, budget_s):
-    """The oracle on a prefix of the workload: integrate + ESDF per
-    frame until the time budget is spent (whole frames)."""
+    """The oracle on a prefix of the room workload: integrate + ESDF after
+    every frame, first with its parallel loops on every host core, then on
+    one thread over the same frames (the results are the same bit for bit
+    at any thread count).  About budget_s of CPU time in total."""
     import oracle as orc
-    ref = orc.Submap(orc.Params(vs=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max))
+
+    def run(threads, n_max, t_max):
+        used = orc.set_threads(threads)
+        ref = orc.Submap(orc.Params(vs=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max))
+        t0 = time.perf_counter()
+        n = 0
+        while n < n_max:
+            ref.integrate(frames[n], w.cam.K, w.poses[n])
+            ref.update_esdf()
+            n += 1
+            if time.perf_counter() - t0 > t_max:
+                break
+        return n, time.perf_counter() - t0, used
+
+    n_all, t_all, cores = run(0, min(w.n_frames, len(frames)), 0.4 * budget_s)
+    n_one, t_one, _ = run(1, n_all, 0.6 * budget_s)
+    orc.set_threads(0)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"value": n_all / t_all, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d of %d room frames, integrate + ESDF after every frame, %.1f s on %d threads"
+                      % (n_all, w.n_frames, t_all, cores),
+            "single_thread": {"value": n_one / t_one, "frames": n_one, "seconds": t_one},
+            "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "affinity": affinity,
+                     "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}}
+
+
+def _pose_diff(Ta, Tb, np):
+    """Translation difference (m) and rotation angle (rad) between two poses."""
+    dt = float(np.linalg.norm(Ta[:3, 3] - Tb[:3, 3]))
+    c = (np.trace(Ta[:3, :3] @ Tb[:3, :3].T) - 1) / 2
+    return dt, math.acos(max(-1.0, min(1.0, c)))
+
+
+def _field_errors(g, e64, np, vs, tau):
+    """Errors of one GPU submap (export) against the binary64 oracle's, over
+    the blocks both hold: |D - D64| and |phi - phi64| (max, RMS), validity
+    decisions that differ (voxel-frame updates, as weight differences under
+    unit weights), site flips (|D| <= vs with W > 0 on one side only) and
+    band flips."""
+    tab = {int(k): i for i, k in enumerate(e64["keys"])}
+    rows = np.array([tab.get(int(k), -1) for k in g["keys"]])
+    both = rows >= 0
+    D, W = g["D"][both].astype(np.float64).ravel(), g["W"][both].astype(np.float64).ravel()
+    P = g["phi"][both].astype(np.float64).ravel()
+    D64, W64, P64 = (e64[k].reshape(-1, 512)[rows[both]].ravel() for k in ("D", "W", "phi"))
+    obs, obs64 = W > 0, W64 > 0
+    same = obs & obs64 & (W == W64)
+    dD = np.abs(D - D64)[same]
+    m = ~np.isnan(P) & ~np.isnan(P64)
+    dP = np.abs(P - P64)[m]
+    site, site64 = obs & (np.abs(D) <= vs), obs64 & (np.abs(D64) <= vs)
+    band, band64 = obs & (np.abs(D) < tau), obs64 & (np.abs(D64) < tau)
+    inb = m & band & band64
+    return {"blocks": int(len(g["keys"])), "blocks_fp64": int(len(e64["keys"])),
+            "blocks_one_side": int(np.count_nonzero(~both) + len(e64["keys"]) - int(both.sum())),
+            "validity_flips": int(np.abs(W - W64).sum()), "observed_flips": int(np.count_nonzero(obs != obs64)),
+            "voxels_compared": int(same.sum()),
+            "D_max": float(dD.max(initial=0)), "D_rms": float(np.sqrt((dD ** 2).mean())) if dD.size else 0.0,
+            "phi_max": float(dP.max(initial=0)), "phi_rms": float(np.sqrt((dP ** 2).mean())) if dP.size else 0.0,
+            "phi_max_in_band": float(np.abs(P - P64)[inb].max(initial=0)),
+            "phi_voxels_over_1e-4": int(np.count_nonzero(dP > 1e-4)),
+            "site_flips": int(np.count_nonzero(site != site64)), "band_flips": int(np.count_nonzero(band != band64))}
+
+
+def precision_bench(cv, torch, np, w, frames, dev, per=50):
+    """Error statement of the binary32 and binary16 storage paths against the
+    binary64 oracle on the room workload: the headline map (every frame into
+    one submap, ESDF at the end) field by field, the same ESDF recomputed by
+    the binary64 oracle from the GPU's own TSDF (which separates the EDT's
+    arithmetic from the TSDF's rounding), and single-start alignment of the
+    consecutive room submaps of `per` frames against the binary64 oracle's
+    pose from the same start."""
+    import oracle as orc
+    import scenegen as sg
+    F = w.n_frames
+    P = dict(vs=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max)
+    vs, tau = w.voxel_size, 4 * w.voxel_size * (1 - 2.0 ** -10)
+    orc.set_threads(0)
     t0 = time.perf_counter()
-    n = 0
-    while n < w.n_frames:
-        ref.integrate(frames[n], w.cam.K, w.poses[n])
-        ref.update_esdf()
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d room frames, integrate + ESDF after every frame, %.1f s" % (n, w.n_frames, dt)}
+    r64 = orc.Submap(orc.Params(fp64=True, **P))
+    nsub = F // per
+    s64 = [orc.Submap(orc.Params(fp64=True, **P), w.poses[k * per]) for k in range(nsub)]
+    for f in range(F):
+        r64.integrate(frames[f], w.cam.K, w.poses[f])
+        if f // per < nsub:
+            s64[f // per].integrate(frames[f], w.cam.K, w.poses[f])
+    r64.update_esdf()
+    for sm in s64:
+        sm.update_esdf()
+    e64 = r64.export()
+    rng = np.random.default_rng(77)
+    pairs = []
+    for i in range(nsub - 1):
+        T_gt = np.linalg.inv(w.poses[i * per]) @ w.poses[(i + 1) * per]
+        dT = np.eye(4)
+        dT[:3, :3] = sg.rot_z(math.radians(rng.uniform(-5, 5)))
+        dT[:3, 3] = rng.uniform(-0.1, 0.1, size=3)
+        pairs.append((i, i + 1, T_gt @ dT))
+    pose64 = [orc.align(s64[i], s64[j].iso_points(), T0)["T"] for i, j, T0 in pairs]
+    out = {"workload": "room, %d frames: one submap (ESDF at the end); %d pairs of consecutive %d-frame submaps, "
+                       "single-start Gauss-Newton from a perturbed start" % (F, len(pairs), per)}
+    for name, prec in (("fp32", cv.FP32), ("fp16", cv.FP16)):
+        ctx = cv.Context(voxel_size=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max,
+                         block_capacity=16384, precision=prec)
+        s = ctx.submap_create()
+        ctx.map_sequence(s, dev, w.cam.K, w.poses, esdf_every=0)
+        ctx.update_esdf(s)
+        g = ctx.export_blocks(s)
+        r = _field_errors(g, e64, np, vs, tau)
+        # the binary64 oracle's ESDF of the GPU's own TSDF: what is left is
+        # the EDT's arithmetic alone
+        imp = orc.Submap(orc.Params(fp64=True, **P))
+        imp.import_blocks(g["keys"], g["D"].astype(np.float64), g["W"].astype(np.float64))
+        imp.update_esdf()
+        ei = imp.export()
+        tab = {int(k): i for i, k in enumerate(ei["keys"])}
+        rows = np.array([tab[int(k)] for k in g["keys"]])
+        Pg, Pi = g["phi"].astype(np.float64).ravel(), ei["phi"].reshape(-1, 512)[rows].ravel()
+        mm = ~np.isnan(Pg) & ~np.isnan(Pi)
+        r["phi_max_same_tsdf"] = float(np.abs(Pg - Pi)[mm].max(initial=0))
+        subs = [ctx.submap_create(w.poses[k * per]) for k in range(nsub)]
+        for k in range(nsub):
+            ctx.map_sequence(subs[k], dev[k * per:(k + 1) * per], w.cam.K, w.poses[k * per:(k + 1) * per],
+                             esdf_every=0)
+        T, _, _ = ctx.align_batch([(subs[i], subs[j], T0) for i, j, T0 in pairs], 1)
+        d = [_pose_diff(Tg, T64, np) for Tg, T64 in zip(T, pose64)]
+        r["pose_vs_fp64_max_t_m"] = max(x[0] for x in d)
+        r["pose_vs_fp64_max_rot_rad"] = max(x[1] for x in d)
+        out[name] = r
+        ctx.close()
+    out["cpu_s"] = time.perf_counter() - t0
+    return out
 
 
 def align_bench(cv, torch, np, w, dev, reps=3):
@@ -247,7 +400,7 @@ def block_overlap(keys_a, T_ws_a, keys_b, T_ws_b, vs, np):
     return hit / max(1, min(len(ba), len(bb)))
 
 
-def mav_bench(cv, torch, np, reps=3, n_pairs=256):
+def mav_bench(cv, torch, np, reps=3, n_pairs=256, roofline_only=False):
     """MAV-scale outdoor workload: 3000 frames 640x480 cut into 30 submaps of
     100 frames (0.1 m voxels, ESDF to 3 m).  Reports the batched ESDF of all
     submaps (one launch per pass) and the batched alignment of overlapping
@@ -296,15 +449,17 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
         best_map = dt if best_map is None else min(best_map, dt)
     n_upd = sum(ctx.submap_info(s)["n_updates"] for s in subs)
     n_blk = sum(ctx.submap_info(s)["n_blocks"] for s in subs)
-    # compulsory bytes: every depth frame once, D and W of every block read and
-    # written once per frame batch (2 batches per submap), new blocks initialised
-    b_map = 4 * w.cam.H * w.cam.W * w.n_frames + 2 * 8 * 512 * n_blk * 2 + 8 * 512 * n_blk
+    # B_int summed over the frames: depth once per frame, two state accesses
+    # per voxel update, new blocks initialised once (FP32 state: 8 B per voxel)
+    b_map = 4 * w.cam.H * w.cam.W * w.n_frames + 2 * 8 * n_upd + (8 * 512 + 24) * n_blk
     mapping = {"frames": w.n_frames, "frames_per_s": w.n_frames / best_map, "ms": best_map * 1e3,
                "voxel_updates": int(n_upd), "voxel_updates_per_s": n_upd / best_map, "kernel_ms": map_kernels,
-               "algorithmic_bytes": b_map, "achieved_GBs": b_map / best_map / 1e9,
-               "frac_hbm": b_map / best_map / 1e9 / HBM_PEAK_GBS}
-    large = large_submap_esdf_bench(cv, torch, np, w, frames[:600], reps)
-    sweep = voxel_sweep_bench(cv, torch, np, w, frames[:per], Tws[0])
+               "roofline": part_fraction(b_map, sum(map_kernels.values())),
+               "wall_GBs": b_map / best_map / 1e9}
+    large = sweep = None
+    if not roofline_only:
+        large = large_submap_esdf_bench(cv, torch, np, w, frames[:600], reps)
+        sweep = voxel_sweep_bench(cv, torch, np, w, frames[:per], Tws[0])
     del frames
     t_build = time.perf_counter() - t0
     nblk = [ctx.submap_info(s)["n_blocks"] for s in subs]
@@ -324,19 +479,27 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
     ctx.timing_enable([])
     kern = {k: v[0] / reps for k, v in tk.items() if v[1]}
     kms = sum(kern.values())
-    b_esdf = 12 * 512 * sum(nblk)
+    b_esdf = 12 * 512 * sum(nblk)  # B_esdf: D and W read, phi written, every voxel of every submap
     esdf = {"submaps": nsub, "blocks_total": int(sum(nblk)), "blocks_min": int(min(nblk)), "blocks_max": int(max(nblk)),
-            "ms_per_batch": wall * 1e3, "kernel_ms": kern, "algorithmic_bytes": b_esdf,
-            "achieved_GBs": b_esdf / (kms * 1e-3) / 1e9, "frac_hbm": b_esdf / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "ms_per_batch": wall * 1e3, "kernel_ms": kern, "roofline": part_fraction(b_esdf, kms),
             "voxels_per_s": 512 * sum(nblk) / (kms * 1e-3), "tuning": tuning}
+    if roofline_only:
+        ctx.close()
+        return {"workload": "outdoor 120x80 m, 3000 frames 640x480 fx=fy=380, 0.1 m voxels, 30 submaps of 100 "
+                            "frames (mapping and batched ESDF only)",
+                "build_s": t_build, "render_s": t_render, "mapping": mapping, "esdf_batch": esdf}
     # overlapping pairs
     keys = [ctx.export_blocks(s)["keys"] for s in subs]
+    # every submap pair of the trajectory (loop closures included) whose block
+    # overlap is within 0.3 .. 0.9, in both directions (points from one,
+    # field from the other)
     cand = []
     for i in range(nsub):
-        for j in range(i + 1, min(nsub, i + 4)):
+        for j in range(i + 1, nsub):
             ov = block_overlap(keys[i], Tws[i], keys[j], Tws[j], w.voxel_size, np)
             if 0.3 <= ov <= 0.9:
                 cand.append((i, j, ov))
+                cand.append((j, i, ov))
     def make_pairs(seed, tilt_deg):
         rng = np.random.default_rng(seed)
         pairs, gts = [], []
@@ -361,14 +524,16 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
             T, cost, st = ctx.align_batch(pairs, n_starts)
             dt = time.perf_counter() - t2
             best = dt if best is None else min(best, dt)
-        ok, errs = 0, []
+        ok, ok5, errs = 0, 0, []
         for Tg, Tt in zip(T, gts):
             et = np.linalg.norm(Tg[:3, 3] - Tt[:3, 3])
             c = (np.trace(Tg[:3, :3] @ Tt[:3, :3].T) - 1) / 2
             er = math.degrees(math.acos(max(-1.0, min(1.0, c))))
             ok += et <= 0.01 and er <= 0.1
+            ok5 += et <= 0.05 and er <= 0.5
             errs.append(et)
-        return {"pairs_per_s": n_pairs / best, "success": ok / n_pairs, "median_t_err_m": float(np.median(errs)),
+        return {"pairs_per_s": n_pairs / best, "success": ok / n_pairs, "success_5cm": ok5 / n_pairs,
+                "aligned_per_s": ok / best, "median_t_err_m": float(np.median(errs)),
                 "ms": best * 1e3, "mean_iterations": float(np.mean([x["iterations"] for x in st])),
                 "tuning": tuning}
 
@@ -407,6 +572,126 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256):
             "build_s": t_build, "render_s": t_render, "mapping": mapping, "esdf_batch": esdf,
             "esdf_large_submap": large, "voxel_sweep": sweep, "align": align, "pose_graph": pose_graph,
             "learned": learned}
+
+
+def _pose_errors(T, gts, np):
+    """Translation (m) and rotation (deg) error of each pose against the truth."""
+    et, er = [], []
+    for Tg, Tt in zip(T, gts):
+        et.append(float(np.linalg.norm(Tg[:3, 3] - Tt[:3, 3])))
+        c = (np.trace(Tg[:3, :3] @ Tt[:3, :3].T) - 1) / 2
+        er.append(math.degrees(math.acos(max(-1.0, min(1.0, c)))))
+    return np.array(et), np.array(er)
+
+
+def cfg4_align_bench(cv, torch, np, seeds=(40, 41, 42, 43, 44), n_pairs=256, reps=3, experiment_seeds=2):
+    """Batched alignment on submap pairs of several outdoor scenes: each seed's
+    3000-frame trajectory is cut into 30 submaps of 100 frames (0.1 m voxels,
+    ESDF to 3 m); every pair of submaps of a scene whose block overlap lies in
+    0.3 .. 0.9 enters in both directions; n_pairs distinct pairs are drawn
+    (all of them when there are fewer) and perturbed by U[-0.5, 0.5]^3 m,
+    U[-10, 10] deg yaw and U[-2, 2] deg roll and pitch.  Reports pairs/s and
+    the success fraction at 1 cm / 0.1 deg and at 5 cm / 0.5 deg, for 1 and 8
+    starts.  Two experiments on the pairs of the first experiment_seeds
+    scenes name what sets the accuracy floor: the same pairs mapped from
+    noise-free frames, and mapped from the same noisy frames by raycasting."""
+    import scenegen as sg
+    t0 = time.perf_counter()
+    per = 100
+
+    def build(ctx, w, Tws, cache=None):
+        subs = []
+        for k in range(len(Tws)):
+            fr = cache[k] if cache is not None else torch.from_numpy(w.frames(k * per, (k + 1) * per)).cuda()
+            s = ctx.submap_create(Tws[k])
+            ctx.map_sequence(s, fr, w.cam.K, w.poses[k * per:(k + 1) * per], esdf_every=0)
+            subs.append(s)
+        ctx.update_esdf_batch(subs)
+        return subs
+
+    def make_ctx(**kw):
+        return cv.Context(voxel_size=0.1, trunc_vox=4, max_range=10.0, d_max=3.0, block_capacity=16384,
+                          tol_rho=OUTDOOR_TOL_RHO, tol_theta=OUTDOOR_TOL_THETA, **kw)
+
+    ctx = make_ctx()
+    scenes = []
+    for sd in seeds:
+        w = sg.mav(seed=sd)
+        nsub = w.n_frames // per
+        Tws = [sg.gravity_aligned(w.poses[k * per]) for k in range(nsub)]
+        keep = len(scenes) < experiment_seeds
+        frames = [torch.from_numpy(w.frames(k * per, (k + 1) * per)).cuda() for k in range(nsub)] if keep else None
+        subs = build(ctx, w, Tws, frames)
+        keys = [ctx.export_blocks(s)["keys"] for s in subs]
+        cand = []
+        for i in range(nsub):
+            for j in range(i + 1, nsub):
+                ov = block_overlap(keys[i], Tws[i], keys[j], Tws[j], w.voxel_size, np)
+                if 0.3 <= ov <= 0.9:
+                    cand += [(i, j, ov), (j, i, ov)]
+        scenes.append({"seed": sd, "w": w, "Tws": Tws, "subs": subs, "cand": cand, "frames": frames})
+    t_build = time.perf_counter() - t0
+    rng = np.random.default_rng(4)
+    allc = [(si, i, j, ov) for si, sc in enumerate(scenes) for (i, j, ov) in sc["cand"]]
+    order = rng.permutation(len(allc))[:n_pairs]
+    chosen = [allc[k] for k in order]
+    items = []
+    for (si, i, j, ov) in chosen:
+        sc = scenes[si]
+        T_gt = np.linalg.inv(sc["Tws"][i]) @ sc["Tws"][j]
+        dT = np.eye(4)
+        dT[:3, :3] = sg.rot_z(math.radians(rng.uniform(-10, 10))) @ sg.rot_y(math.radians(rng.uniform(-2, 2))) \
+            @ sg.rot_x(math.radians(rng.uniform(-2, 2)))
+        dT[:3, 3] = rng.uniform(-0.5, 0.5, size=3)
+        items.append((si, i, j, T_gt, T_gt @ dT))
+
+    def run(c, subs_of, sel, n_starts):
+        pairs = [(subs_of(si)[i], subs_of(si)[j], T0) for (si, i, j, _, T0) in sel]
+        gts = [T_gt for (_, _, _, T_gt, _) in sel]
+        c.autotune_align(pairs, n_starts)
+        best, res = None, None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            res = c.align_batch(pairs, n_starts)
+            dt = time.perf_counter() - t1
+            best = dt if best is None else min(best, dt)
+        et, er = _pose_errors(res[0], gts, np)
+        n = len(sel)
+        ok1 = int(np.count_nonzero((et <= 0.01) & (er <= 0.1)))
+        ok5 = int(np.count_nonzero((et <= 0.05) & (er <= 0.5)))
+        return {"pairs": n, "pairs_per_s": n / best, "ms": best * 1e3, "success": ok1 / n, "successes": ok1,
+                "success_5cm": ok5 / n, "successes_5cm": ok5, "aligned_per_s": ok1 / best,
+                "median_t_err_m": float(np.median(et)), "median_rot_err_deg": float(np.median(er)),
+                "mean_iterations": float(np.mean([x["iterations"] for x in res[2]]))}
+
+    out = {"workload": "outdoor scenes seeds %s, 30 submaps of 100 frames each, pairs at block overlap 0.3-0.9 "
+                       "in both directions, perturbation 0.5 m / 10 deg yaw / 2 deg roll-pitch" % list(seeds),
+           "distinct_pairs_available": len(allc), "pairs": len(items),
+           "pairs_per_scene": [len(sc["cand"]) for sc in scenes],
+           "overlap_range": [float(min(c[3] for c in chosen)), float(max(c[3] for c in chosen))],
+           "build_s": t_build}
+    for n_starts in (1, 8):
+        out["starts_%d" % n_starts] = run(ctx, lambda si: scenes[si]["subs"], items, n_starts)
+    # the accuracy floor: the pairs of the first scenes, mapped three ways
+    sel = [it for it in items if it[0] < experiment_seeds]
+    exp = {"pairs": len(sel), "seeds": [sc["seed"] for sc in scenes[:experiment_seeds]]}
+    exp["noisy_projective"] = run(ctx, lambda si: scenes[si]["subs"], sel, 1)
+    cr = make_ctx(integrator=cv.RAYCAST)
+    rsubs = [build(cr, scenes[si]["w"], scenes[si]["Tws"], scenes[si]["frames"]) for si in range(experiment_seeds)]
+    exp["noisy_raycast"] = run(cr, lambda si: rsubs[si], sel, 1)
+    cr.close()
+    cn = make_ctx()
+    nsubs = []
+    for si in range(experiment_seeds):
+        wc = sg.mav(seed=scenes[si]["seed"], noise=False)
+        nsubs.append(build(cn, wc, scenes[si]["Tws"]))
+    exp["noise_free_projective"] = run(cn, lambda si: nsubs[si], sel, 1)
+    cn.close()
+    out["accuracy_floor"] = exp
+    out["total_s"] = time.perf_counter() - t0
+    ctx.close()
+    return out
 
 
 def _success(T, gts, np, bound_t, bound_deg):
@@ -683,6 +968,8 @@ def learned_bench(cv, torch, np, ctx, subs, Tws, vs, n_items=1024, reps=3):
         r = {"pairs_per_s": n_items / best, "ms": best * 1e3,
              "success_1cm_0.1deg": _success(T, gts, np, 0.01, 0.1),
              "success_5cm_0.5deg": _success(T, gts, np, 0.05, 0.5)}
+        r["successes_1cm"] = int(round(r["success_1cm_0.1deg"] * n_items))
+        r["successes_5cm"] = int(round(r["success_5cm_0.5deg"] * n_items))
         r["aligned_per_s_1cm"] = r["pairs_per_s"] * r["success_1cm_0.1deg"]
         r["aligned_per_s_5cm"] = r["pairs_per_s"] * r["success_5cm_0.5deg"]
         if name == "learned_refine":
@@ -799,6 +1086,12 @@ def main():
     ap.add_argument("--no-wavefront", action="store_true", help="skip the exact / wavefront ESDF comparison")
     ap.add_argument("--no-hash", action="store_true", help="skip the hash-table stress test")
     ap.add_argument("--no-copy", action="store_true", help="skip the stream-copy bandwidth measurement")
+    ap.add_argument("--no-precision", action="store_true", help="skip the error statement against the binary64 oracle")
+    ap.add_argument("--cfg4-align", action="store_true",
+                    help="only the batched alignment of outdoor pairs from several scenes (several minutes of "
+                         "rendering), printed as one JSON line")
+    ap.add_argument("--mav-roofline-only", action="store_true",
+                    help="outdoor workload: mapping and batched ESDF only (for counter runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -814,6 +1107,9 @@ def main():
     import paper_2410_21149_amd as cv
 
     torch.cuda.set_device(0)
+    if args.cfg4_align:
+        print(json.dumps({"cfg4_align": cfg4_align_bench(cv, torch, np)}), flush=True)
+        return
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -937,12 +1233,21 @@ def main():
     s_dw = 4 if prec == cv.FP16 else 8
     ms_k, n_k = tim[dominant]
     per_launch_ms = ms_k / max(n_k, 1)
-    bytes_launch = algorithmic_bytes(dominant, census, s_dw)
+    # the dominant kernel against the bytes of the unit it belongs to: one
+    # ESDF update (B_esdf) or one frame's integration (B_int)
+    bytes_launch = unit_bytes(dominant, census, s_dw)
     achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
+    b_int, b_esdf = frame_bytes(census, s_dw)
+    kms = {k: v[0] for k, v in prof.items() if v[1]}
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dominant, room_tuning, census),
+                "bytes_rule": ("B_esdf = (s_D + s_W + 4) 512 n_blocks per ESDF update" if dominant in ESDF_KINDS else
+                               "B_int = 4HW + 2 (s_D + s_W) N_upd + ((s_D + s_W) 512 + 24) N_new per frame"),
                 "bytes_per_launch": bytes_launch, "ms_per_launch": per_launch_ms,
-                "achievable_copy_GBs": copy_gbs, "frac_achievable": (achieved / copy_gbs) if copy_gbs else None}
+                "achievable_copy_GBs": copy_gbs, "frac_achievable": (achieved / copy_gbs) if copy_gbs else None,
+                # whole parts of the room step: sum of bytes over sum of kernel time
+                "room_esdf": part_fraction(sum(b_esdf), sum(kms.get(k, 0.0) for k in ESDF_KINDS)),
+                "room_integration": part_fraction(sum(b_int), sum(kms.get(k, 0.0) for k in INTEGRATION_KINDS))}
 
     result = {
         "metric": METRIC,
@@ -965,7 +1270,7 @@ def main():
                    "voxel_updates_per_step": int(sum(census["n_upd"])),
                    "latency_per_frame": latency},
         "roofline": roofline,
-        "kernel_ms_per_step": {k: v[0] for k, v in prof.items() if v[1]},
+        "kernel_ms_per_step": kms,
         "tuning": room_tuning,
     }
     if prec == cv.FP32 and not args.no_fp16:
@@ -998,15 +1303,71 @@ def main():
         result["align"] = align_bench(cv, torch, np, w, dev)
     if not args.no_mav:
         _log("outdoor workload: 30 submaps, batched ESDF and alignment")
-        result["mav"] = mav_bench(cv, torch, np)
+        result["mav"] = mav_bench(cv, torch, np, roofline_only=args.mav_roofline_only)
     if not args.no_hash:
         _log("hash-table stress test (2^26 slots, load 0.25 .. 0.85)")
         result["hash_table"] = hash_bench(cv, torch, np)
+    if not args.no_precision:
+        _log("precision statement (binary64 oracle)")
+        result["precision"] = precision_bench(cv, torch, np, w, frames, dev)
     if not args.no_cpu_baseline:
         _log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(w, frames, args.cpu_seconds)
     ctx.close()
-    print(json.dumps(result), flush=True)
+    detail = json.dumps(result)
+    _log("bench detail: " + detail)
+    if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
+        with open(os.path.join(ROOT, "gpurun_out", "bench_detail.json"), "w") as fh:
+            fh.write(detail + "\n")
+    print(json.dumps(summary_line(result)), flush=True)
+
+
+def _pick(d, *keys):
+    return {k: d[k] for k in keys if isinstance(d, dict) and k in d}
+
+
+def summary_line(r):
+    """The one JSON line: the room step (value), the roofline of its dominant
+    kernel and of the parts of the step and of the outdoor batches, the oracle
+    on the host cores, and compact alignment (aligns per second and success),
+    learned-proposal and precision figures.  Every figure is also in the full
+    record printed to stderr."""
+    line = {k: r[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config") if k in r}
+    roof = dict(r["roofline"])
+    mav = r.get("mav", {})
+    if "esdf_batch" in mav:
+        e = mav["esdf_batch"]
+        roof["outdoor_esdf_batch"] = dict(e["roofline"], submaps=e["submaps"], blocks=e["blocks_total"])
+    if "mapping" in mav:
+        m = mav["mapping"]
+        roof["outdoor_mapping"] = dict(m["roofline"], frames=m["frames"], frames_per_s=m["frames_per_s"])
+    line["roofline"] = roof
+    if "cpu_baseline" in r:
+        line["cpu_baseline"] = r["cpu_baseline"]
+    aligns = {}
+    if "align" in r:
+        a = r["align"]
+        aligns["room"] = {k: _pick(a.get(k, {}), "pairs_per_s", "success") for k in ("starts_1", "starts_8")}
+    if "align" in mav:
+        a = mav["align"]
+        aligns["outdoor"] = dict(_pick(a, "pairs", "distinct_pairs", "overlap_range"),
+                                 **{k: _pick(a.get(k, {}), "pairs_per_s", "success", "success_5cm",
+                                             "aligned_per_s", "median_t_err_m")
+                                    for k in ("starts_1", "starts_8") if k in a})
+    if aligns:
+        line["aligns"] = aligns
+    if "learned" in mav and "plain_8start" in mav["learned"]:
+        le = mav["learned"]
+        line["learned"] = dict(_pick(le, "held_out_pairs", "distinct_pairs", "ratio_aligned_per_s_1cm",
+                                     "ratio_aligned_per_s_5cm", "ratio_pairs_per_s",
+                                     "proposal_only_success_0.5m_10deg"),
+                               **{k: _pick(le[k], "pairs_per_s", "success_1cm_0.1deg", "success_5cm_0.5deg",
+                                           "successes_1cm", "successes_5cm", "fallback_fraction")
+                                  for k in ("plain_8start", "learned_refine")})
+    if "precision" in r:
+        line["precision"] = r["precision"]
+    return line
 
 
 if __name__ == "__main__":
