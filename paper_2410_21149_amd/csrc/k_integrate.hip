@@ -37,32 +37,27 @@ template <> __device__ __forceinline__ void st<float>(float *p, float v) { *p = 
 template <> __device__ __forceinline__ void st<__half>(__half *p, float v) { *p = __float2half_rn(v); }
 
 // Validity of the 8 voxels (ix, iy, iz0 + z), z = 0..7, of one lane under
-// a frame's projection: the voxel centre lies in front of the camera, its
+// the frame's projection: the voxel centre lies in front of the camera, its
 // nearest pixel is inside the image, the pixel's depth d is in (0, max
 // range], and the signed distance sdf = d - (voxel depth) is at least -tau.
-// Two halves: proj_issue computes every voxel's pixel and issues the 8 depth
-// reads together; proj_finish takes the tests, sets sdf and the observation
-// weight w (1, or 1 / d^2) of each valid voxel and returns the mask of valid
-// voxels.  A caller may issue the reads of the next frame between the two.
-struct ColumnProj {
-    float pz[8];
-    float d[8];
-    uint32_t in_image;  // bit z: the voxel's pixel is inside the image
-};
-
-__device__ __forceinline__ void proj_issue(const FrameArgs &f, float vs, int ix, int iy, int iz0, ColumnProj &p)
+// Sets sdf and the observation weight w (1, or 1 / d^2) of each valid voxel
+// and returns the mask of valid voxels.  The steps run in three passes (the
+// pixel of every voxel, the 8 depth reads, the tests) so that the reads are
+// in flight together; the arithmetic of each voxel is unchanged.
+__device__ __forceinline__ uint32_t proj_column(const FrameArgs &f, float vs, float tau, float maxr, int ix, int iy,
+                                                int iz0, float sdf[8], float w[8])
 {
     const float cx = ((float)ix + 0.5f) * vs;
     const float cy = ((float)iy + 0.5f) * vs;
+    float pzv[8];
     int64_t pix[8];
-    p.in_image = 0;
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
         const float cz = ((float)(iz0 + z) + 0.5f) * vs;
         const float px = ((f.R[0] * cx + f.R[1] * cy) + f.R[2] * cz) + f.t[0];
         const float py = ((f.R[3] * cx + f.R[4] * cy) + f.R[5] * cz) + f.t[1];
         const float pz = ((f.R[6] * cx + f.R[7] * cy) + f.R[8] * cz) + f.t[2];
-        p.pz[z] = pz;
+        pzv[z] = pz;
         pix[z] = -1;
         if (pz > 0.0f) {
             const float u = ((f.K[0] * px) / pz) + f.K[2];
@@ -72,35 +67,21 @@ __device__ __forceinline__ void proj_issue(const FrameArgs &f, float vs, int ix,
             if (uf >= 0.0f && uf < (float)f.W && vf >= 0.0f && vf < (float)f.H)
                 pix[z] = (int64_t)(int)vf * f.W + (int)uf;
         }
-        p.in_image |= (uint32_t)(pix[z] >= 0) << z;
     }
+    float d[8];
 #pragma unroll
-    for (int z = 0; z < 8; ++z) p.d[z] = f.depth[pix[z] >= 0 ? pix[z] : 0];  // pixel 0 stands in, unused
-}
-
-__device__ __forceinline__ uint32_t proj_finish(const FrameArgs &f, float tau, float maxr, const ColumnProj &p,
-                                                float sdf[8], float w[8])
-{
+    for (int z = 0; z < 8; ++z) d[z] = f.depth[pix[z] >= 0 ? pix[z] : 0];  // pixel 0 stands in, unused
     uint32_t okm = 0;
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
-        const float d = p.d[z];
         sdf[z] = 0.0f;
         w[z] = 0.0f;
-        if (!((p.in_image >> z) & 1u) || !(d > 0.0f && d <= maxr)) continue;
-        sdf[z] = d - p.pz[z];
-        w[z] = f.weight_mode == COVOX_WEIGHT_INV_DEPTH2 ? 1.0f / (d * d) : 1.0f;
+        if (pix[z] < 0 || !(d[z] > 0.0f && d[z] <= maxr)) continue;
+        sdf[z] = d[z] - pzv[z];
+        w[z] = f.weight_mode == COVOX_WEIGHT_INV_DEPTH2 ? 1.0f / (d[z] * d[z]) : 1.0f;
         okm |= (uint32_t)(sdf[z] >= -tau) << z;
     }
     return okm;
-}
-
-__device__ __forceinline__ uint32_t proj_column(const FrameArgs &f, float vs, float tau, float maxr, int ix, int iy,
-                                                int iz0, float sdf[8], float w[8])
-{
-    ColumnProj p;
-    proj_issue(f, vs, ix, iy, iz0, p);
-    return proj_finish(f, tau, maxr, p, sdf, w);
 }
 
 // False only if no voxel centre of block (bx, by, bz) can pass the validity
@@ -134,15 +115,18 @@ template <typename S>
 __device__ __forceinline__ int update_column(S *Db, S *Wb, const float sdf[8], const float wt[8], uint32_t okm, float tau,
                                              bool is_new)
 {
-    // The whole column is read, updated in registers and written back
-    // (unchanged voxels with their own value, a new block's with zero), in
-    // straight-line code: conditional reads or writes would make the
-    // compiler wait for each one in turn.
+    // Every read is issued in straight-line code, so that the eight are in
+    // flight together (a conditional read would make the compiler wait for
+    // each one in turn), but a voxel that is not updated reads its lane's
+    // z = 0 voxel instead: rows of the block that no lane updates are not
+    // fetched.  Only updated voxels are written, and every voxel of a new
+    // block (zero where not updated).
     float Dp[8], Wp[8];
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
-        Dp[z] = ld(Db + 64 * z);
-        Wp[z] = ld(Wb + 64 * z);
+        const int o = ((okm >> z) & 1u) ? 64 * z : 0;
+        Dp[z] = ld(Db + o);
+        Wp[z] = ld(Wb + o);
     }
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
@@ -162,8 +146,10 @@ __device__ __forceinline__ int update_column(S *Db, S *Wb, const float sdf[8], c
     }
 #pragma unroll
     for (int z = 0; z < 8; ++z) {
-        st(Db + 64 * z, Dp[z]);
-        st(Wb + 64 * z, Wp[z]);
+        if (((okm >> z) & 1u) || is_new) {
+            st(Db + 64 * z, Dp[z]);
+            st(Wb + 64 * z, Wp[z]);
+        }
     }
     return n_ok;
 }
@@ -598,25 +584,14 @@ __global__ __launch_bounds__(256) void k_integrate_batch(const FrameArgs *__rest
             dv[z] = is_new ? 0.0f : ld(Db + 64 * z);
             wv[z] = is_new ? 0.0f : ld(Wb + 64 * z);
         }
-        // The frames that may see the block, in order, two at a time: the
-        // depth reads of the next one are in flight while this one updates.
-        auto visible = [&](int fi) {
-            const FrameArgs &f = frames[fi];
-            return !(bx < f.blo[0] || bx >= f.blo[0] + f.bdim[0] || by < f.blo[1] || by >= f.blo[1] + f.bdim[1] ||
-                     bz < f.blo[2] || bz >= f.blo[2] + f.bdim[2]) &&
-                   block_may_be_visible(f, vs, bx, by, bz);
-        };
         int n_ok = 0;
-        int fa = 0;
-        while (fa < F && !visible(fa)) ++fa;  // uniform across the wave
-        ColumnProj pa, pb;
-        if (fa < F) proj_issue(frames[fa], vs, ix, iy, 8 * bz, pa);
-        while (fa < F) {
-            int fb = fa + 1;
-            while (fb < F && !visible(fb)) ++fb;
-            if (fb < F) proj_issue(frames[fb], vs, ix, iy, 8 * bz, pb);
+        for (int fi = 0; fi < F; ++fi) {
+            const FrameArgs &f = frames[fi];
+            if (bx < f.blo[0] || bx >= f.blo[0] + f.bdim[0] || by < f.blo[1] || by >= f.blo[1] + f.bdim[1] ||
+                bz < f.blo[2] || bz >= f.blo[2] + f.bdim[2] || !block_may_be_visible(f, vs, bx, by, bz))
+                continue;  // no valid voxel in this frame
             float sdf[8], w[8];
-            const uint32_t okm = proj_finish(frames[fa], tau, maxr, pa, sdf, w);
+            const uint32_t okm = proj_column(f, vs, tau, maxr, ix, iy, 8 * bz, sdf, w);
 #pragma unroll
             for (int z = 0; z < 8; ++z) {
                 const bool ok = (okm >> z) & 1u;
@@ -629,8 +604,6 @@ __global__ __launch_bounds__(256) void k_integrate_batch(const FrameArgs *__rest
                     wv[z] = stored<S>(Wn);
                 }
             }
-            pa = pb;
-            fa = fb;
         }
 #pragma unroll
         for (int z = 0; z < 8; ++z) {

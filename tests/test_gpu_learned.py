@@ -124,6 +124,7 @@ def test_network_forward_parity(cv):
     r = orc.net_forward(p, x, bf16=True)
     scale = np.abs(r).max()
     assert scale > 1e-3
+    print("forward: max |gpu - oracle| / max |oracle| = %.3g" % (np.abs(g - r).max() / scale))
     assert np.abs(g - r).max() <= 0.02 * scale, (g, r)
     # a different batch size gives the same per-sample outputs
     g1 = net.forward(torch.from_numpy(x[1:]).cuda()).cpu().numpy()

@@ -120,12 +120,18 @@ def test_pass_grid_cap_does_not_change_the_result(cv, cap):
     b.close()
 
 
-def test_captured_pipelined_sequence_replays_to_the_calls_in_order(cv, room90):
+@pytest.mark.parametrize("capacity", [16384, 1 << 21])
+def test_captured_pipelined_sequence_replays_to_the_calls_in_order(cv, room90, capacity):
+    """A captured pipelined sequence replays to the calls in order.  At 2^21
+    blocks the host's bound never reaches the capacity, so every frame of the
+    capture takes the fused probe update (existing blocks updated in the
+    probe); at 16384 the bound passes the capacity within a few frames and
+    the capture falls back to the separate update."""
     import torch
     w, fr = room90
     dev = torch.from_numpy(fr[:60]).cuda()
     base = dict(voxel_size=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max,
-                block_capacity=16384)
+                block_capacity=capacity)
     b = cv.Context(**base)
     sb = b.submap_create()
     _in_order(b, sb, dev, w.cam.K, w.poses[:60], 1)
