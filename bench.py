@@ -321,6 +321,55 @@ def precision_bench(cv, torch, np, w, frames, dev, per=50):
     return out
 
 
+def outdoor_pose_precision(cv, torch, np, w, ctx, subs, Tws, pairs, cand, n=3):
+    """Pose difference of single-start alignment from the binary64 oracle's on
+    outdoor pairs: the first n pairs of the benchmark set whose submaps are
+    all distinct, each aligned from the same perturbed start by the GPU
+    (FP32 and FP16 storage) and by the binary64 oracle (its own binary64 map
+    of the same frames)."""
+    import oracle as orc
+    import scenegen as sg
+    t0 = time.perf_counter()
+    per = w.submap_every
+    chosen, used = [], set()
+    for k, (i, j, _) in enumerate(cand):
+        if i in used or j in used:
+            continue
+        chosen.append((i, j, pairs[k][2]))
+        used |= {i, j}
+        if len(chosen) == n:
+            break
+    orc.set_threads(0)
+    P = dict(vs=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max, tol_rho=OUTDOOR_TOL_RHO,
+             tol_theta=OUTDOOR_TOL_THETA)
+    frames = {k: w.frames(k * per, (k + 1) * per) for k in used}
+    ref = {}
+    for k in used:
+        r = orc.Submap(orc.Params(fp64=True, **P), Tws[k])
+        for f in range(per):
+            r.integrate(frames[k][f], w.cam.K, w.poses[k * per + f])
+        r.update_esdf()
+        ref[k] = r
+    T64 = [orc.align(ref[i], ref[j].iso_points(), T0)["T"] for i, j, T0 in chosen]
+    out = {"pairs": [[int(i), int(j)] for i, j, _ in chosen]}
+    T32, _, _ = ctx.align_batch([(subs[i], subs[j], T0) for i, j, T0 in chosen], 1)
+    c16 = cv.Context(voxel_size=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max,
+                     block_capacity=65536, precision=cv.FP16, tol_rho=OUTDOOR_TOL_RHO, tol_theta=OUTDOOR_TOL_THETA)
+    s16 = {}
+    for k in used:
+        s16[k] = c16.submap_create(Tws[k])
+        c16.map_sequence(s16[k], torch.from_numpy(frames[k]).cuda(), w.cam.K, w.poses[k * per:(k + 1) * per],
+                         esdf_every=0)
+    c16.update_esdf_batch(list(s16.values()))
+    T16, _, _ = c16.align_batch([(s16[i], s16[j], T0) for i, j, T0 in chosen], 1)
+    c16.close()
+    for name, T in (("fp32", T32), ("fp16", T16)):
+        d = [_pose_diff(a, b, np) for a, b in zip(T, T64)]
+        out[name] = {"max_t_m": max(x[0] for x in d), "max_rot_rad": max(x[1] for x in d)}
+    out["cpu_s"] = time.perf_counter() - t0
+    return out
+
+
 def align_bench(cv, torch, np, w, dev, reps=3):
     """Room submaps of 50 frames each (frame 0 of each submap defines its
     frame); overlapping pairs with seeded perturbations of the true relative
@@ -544,6 +593,7 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256, roofline_only=False):
              "overlap_range": [float(min(c[2] for c in cand)), float(max(c[2] for c in cand))]}
     for n_starts in (1, 8):
         align["starts_%d" % n_starts] = run_pairs(pairs, gts, n_starts)
+    align["precision"] = outdoor_pose_precision(cv, torch, np, w, ctx, subs, Tws, pairs[:len(cand)], cand)
     ctx.set_params(align_solver=cv.LEVENBERG_MARQUARDT)  # the same pairs under Levenberg-Marquardt
     for n_starts in (1, 8):
         align["lm_starts_%d" % n_starts] = run_pairs(pairs, gts, n_starts)
@@ -1366,7 +1416,9 @@ def summary_line(r):
                                            "successes_1cm", "successes_5cm", "fallback_fraction")
                                   for k in ("plain_8start", "learned_refine")})
     if "precision" in r:
-        line["precision"] = r["precision"]
+        line["precision"] = dict(r["precision"])
+        if "precision" in mav.get("align", {}):
+            line["precision"]["outdoor_pose"] = mav["align"]["precision"]
     return line
 
 

@@ -247,8 +247,12 @@ typedef struct {
  * cost (host) = mean squared residual at T_out.  stats: nullable.
  * Requires covox_update_esdf(A) after A's last integration.  Synchronous.
  * Returns the alignment status (OK, NOT_CONVERGED, EDEGENERATE) or an error.
+ * The map of B is read only; the library keeps B's registration points in
+ * a buffer it owns inside B, extracted on the first call after B changes,
+ * so calls that take the same B from several host threads must not
+ * overlap (as for every call on one context).
  */
-int covox_align_submaps(covox_ctx *ctx, const covox_submap *A, covox_submap *B,
+int covox_align_submaps(covox_ctx *ctx, const covox_submap *A, const covox_submap *B,
                         const double T_init_A_B[16], double T_out[16], double *cost,
                         covox_align_stats *stats);
 
@@ -256,13 +260,13 @@ int covox_align_submaps(covox_ctx *ctx, const covox_submap *A, covox_submap *B,
  * Rz(2 pi k / n_starts) Trans(-pbar), pbar the centroid of B's points; the
  * result is the least-cost start among those with status != EDEGENERATE and
  * n_used >= max n_used / 2 (ties: smallest k).  Synchronous. */
-int covox_align_multistart(covox_ctx *ctx, const covox_submap *A, covox_submap *B,
+int covox_align_multistart(covox_ctx *ctx, const covox_submap *A, const covox_submap *B,
                            const double T_init_A_B[16], int32_t n_starts, double T_out[16],
                            double *cost, covox_align_stats *stats);
 
 typedef struct {
     const covox_submap *A;
-    covox_submap *B;
+    const covox_submap *B;
     double T_init_A_B[16];
 } covox_pair;
 
@@ -300,12 +304,12 @@ int64_t covox_export_blocks(covox_ctx *ctx, const covox_submap *s, uint64_t *key
 /* Registration points of B (3 floats each, order: block buffer index,
  * in-block index, axis) copied to host, up to cap points.  Returns the total
  * count or an error.  Synchronous. */
-int64_t covox_export_points(covox_ctx *ctx, covox_submap *B, float *pts, int64_t cap);
+int64_t covox_export_points(covox_ctx *ctx, const covox_submap *B, float *pts, int64_t cap);
 
 /* One evaluation of the normal equations of the pair at T (host, 16
  * doubles): out[0..20] upper triangle of H row by row, out[21..26] b,
  * out[27] sum r^2, out[28] n.  Synchronous. */
-int covox_normal_equations(covox_ctx *ctx, const covox_submap *A, covox_submap *B,
+int covox_normal_equations(covox_ctx *ctx, const covox_submap *A, const covox_submap *B,
                            const double T_A_B[16], double out[29]);
 
 /* ------------------------------------------------------ learned proposal */

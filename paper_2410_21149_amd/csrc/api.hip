@@ -292,7 +292,7 @@ void mat_mul4(const double *A, const double *B, double *O)
     memcpy(O, t, sizeof(t));
 }
 
-int prepare_pair(covox_ctx *ctx, const covox_submap *A, covox_submap *B)
+int prepare_pair(covox_ctx *ctx, const covox_submap *A, const covox_submap *B)
 {
     if (!A || !B) return fail(ctx, COVOX_EINVAL, "align: null submap");
     if (A->esdf_version != A->version)
@@ -698,7 +698,7 @@ int covox_update_esdf(covox_ctx *ctx, covox_submap *s)
     return update_esdf(ctx, s);
 }
 
-int covox_align_submaps(covox_ctx *ctx, const covox_submap *A, covox_submap *B, const double T_init_A_B[16],
+int covox_align_submaps(covox_ctx *ctx, const covox_submap *A, const covox_submap *B, const double T_init_A_B[16],
                         double T_out[16], double *cost, covox_align_stats *stats)
 {
     COVOX_NOT_DURING_CAPTURE(ctx, "align_submaps");
@@ -715,7 +715,7 @@ int covox_align_submaps(covox_ctx *ctx, const covox_submap *A, covox_submap *B, 
     return res.status;
 }
 
-int covox_align_multistart(covox_ctx *ctx, const covox_submap *A, covox_submap *B, const double T_init_A_B[16],
+int covox_align_multistart(covox_ctx *ctx, const covox_submap *A, const covox_submap *B, const double T_init_A_B[16],
                            int32_t n_starts, double T_out[16], double *cost, covox_align_stats *stats)
 {
     COVOX_NOT_DURING_CAPTURE(ctx, "align_multistart");
@@ -786,7 +786,7 @@ int covox_align_batch(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_
     return COVOX_OK;
 }
 
-int covox_normal_equations(covox_ctx *ctx, const covox_submap *A, covox_submap *B, const double T_A_B[16],
+int covox_normal_equations(covox_ctx *ctx, const covox_submap *A, const covox_submap *B, const double T_A_B[16],
                            double out[29])
 {
     COVOX_NOT_DURING_CAPTURE(ctx, "normal_equations");
@@ -874,7 +874,7 @@ int64_t covox_export_blocks(covox_ctx *ctx, const covox_submap *s, uint64_t *key
     return n;
 }
 
-int64_t covox_export_points(covox_ctx *ctx, covox_submap *B, float *pts, int64_t cap)
+int64_t covox_export_points(covox_ctx *ctx, const covox_submap *B, float *pts, int64_t cap)
 {
     COVOX_NOT_DURING_CAPTURE(ctx, "export_points");
     if (!ctx || !B || cap < 0) return fail(ctx, COVOX_EINVAL, "export_points: bad argument");
@@ -1006,7 +1006,7 @@ int prepare_learned(covox_ctx *ctx, const covox_pair *pairs, int n, const char *
         if ((rc = prepare_pair(ctx, pr.A, pr.B))) return rc;
         if (pr.B->esdf_version != pr.B->version)
             return fail(ctx, COVOX_EINVAL, std::string(what) + ": the ESDF of B is out of date");
-        if ((rc = extract_points(ctx, const_cast<covox_submap *>(pr.A)))) return rc;
+        if ((rc = extract_points(ctx, pr.A))) return rc;
     }
     return COVOX_OK;
 }

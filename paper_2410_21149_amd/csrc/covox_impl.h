@@ -450,7 +450,7 @@ int autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int n);
 int update_esdf_batch(covox_ctx *ctx, covox_submap *const *subs, int n);
 
 // k_align.hip
-int extract_points(covox_ctx *ctx, covox_submap *B);  // synchronous (count read back)
+int extract_points(covox_ctx *ctx, const covox_submap *B);  // synchronous (count read back)
 
 struct AlignProblem {
     const float *phi;            // field of A

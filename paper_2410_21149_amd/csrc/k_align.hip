@@ -681,8 +681,12 @@ unsigned grid_waves(int64_t waves)
 
 }  // namespace
 
-int extract_points(covox_ctx *ctx, covox_submap *B)
+int extract_points(covox_ctx *ctx, const covox_submap *Bc)
 {
+    // The registration points, the page and their versions are a cache the
+    // library keeps inside the submap; the map itself (keys, D, W) is only
+    // read here.
+    covox_submap *B = const_cast<covox_submap *>(Bc);
     if (B->pts_version == B->version) return COVOX_OK;
     int rc;
     if ((rc = build_page(ctx, B))) return rc;
