@@ -198,6 +198,14 @@ int covox_map_sequence(covox_ctx *ctx, covox_submap *s, const float *depths_dev,
  *   else sign(D) * d_max (sign = +1 for D > 0, else -1);
  *   unobserved voxels: phi = NaN.
  * Asynchronous.
+ * Dirty region: with the column passes (tuning edt_col_seg > 0) an update
+ * after an exact one writes phi only for the blocks within ceil(R / 8)
+ * blocks, along every axis, of a block whose D or W changed since (every
+ * integration path flags the blocks it changes); phi elsewhere is kept,
+ * being already exact, so the result equals a full recompute bit for bit.
+ * The first update, and the first after a reset, a wavefront update or a
+ * graph replay, recomputes everything, as does every update under the
+ * per-block passes or with tuning esdf_full_recompute = 1.
  * With esdf_mode = COVOX_ESDF_WAVEFRONT, k comes instead from an
  * incremental propagation (Sec. III-E) over the allocated blocks: every
  * voxel keeps a parent site (offset) and its squared distance (<= R^2, else
@@ -592,7 +600,14 @@ typedef struct {
      * block column with HB = ceil(R / 8) halo blocks on each side staged
      * once; S is clamped to 48 - 2 HB.  The results do not depend on it. */
     int64_t edt_col_seg;
-    int64_t reserved[2];
+    /* Exact ESDF updates with the column passes recompute only the blocks
+     * within ceil(R / 8) blocks of a block whose TSDF changed since the
+     * submap's last exact update (the rest keeps its phi, which is already
+     * exact), or everything on the first update, after a reset, a wavefront
+     * update or a graph replay.  1: every update recomputes everything (for
+     * timing full updates).  The results do not depend on it. */
+    int64_t esdf_full_recompute;
+    int64_t reserved[1];
 } covox_tuning;
 
 /* Defaults: y envelopes from 2048 segments up, z always windowed, 256

@@ -75,7 +75,7 @@ class covox_tuning(ctypes.Structure):
     _fields_ = [("edt_y_env_min_cols", ctypes.c_int64), ("edt_z_env_min_cols", ctypes.c_int64),
                 ("align_threads", ctypes.c_int64), ("align_points_per_step", ctypes.c_int64),
                 ("edt_pipe_max_workgroups", ctypes.c_int64), ("edt_col_seg", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 2)]
+                ("esdf_full_recompute", ctypes.c_int64), ("reserved", ctypes.c_int64 * 1)]
 
 
 class covox_pose_factor(ctypes.Structure):
@@ -495,7 +495,8 @@ class Context:
     def _tuning_dict(t) -> dict:
         return {"edt_y_env_min_cols": t.edt_y_env_min_cols, "edt_z_env_min_cols": t.edt_z_env_min_cols,
                 "align_threads": t.align_threads, "align_points_per_step": t.align_points_per_step,
-                "edt_pipe_max_workgroups": t.edt_pipe_max_workgroups, "edt_col_seg": t.edt_col_seg}
+                "edt_pipe_max_workgroups": t.edt_pipe_max_workgroups, "edt_col_seg": t.edt_col_seg,
+                "esdf_full_recompute": t.esdf_full_recompute}
 
     def tuning(self) -> dict:
         t = covox_tuning()
@@ -503,7 +504,8 @@ class Context:
         return self._tuning_dict(t)
 
     def set_tuning(self, edt_y_env_min_cols=None, edt_z_env_min_cols=None, align_threads=None,
-                   align_points_per_step=None, edt_pipe_max_workgroups=None, edt_col_seg=None):
+                   align_points_per_step=None, edt_pipe_max_workgroups=None, edt_col_seg=None,
+                   esdf_full_recompute=None):
         t = covox_tuning()
         self._check(_lib.covox_tuning_get(self.handle, ctypes.byref(t)), "tuning_get")
         if edt_y_env_min_cols is not None:
@@ -518,6 +520,8 @@ class Context:
             t.edt_pipe_max_workgroups = edt_pipe_max_workgroups
         if edt_col_seg is not None:
             t.edt_col_seg = edt_col_seg
+        if esdf_full_recompute is not None:
+            t.esdf_full_recompute = int(esdf_full_recompute)
         self._check(_lib.covox_tuning_set(self.handle, ctypes.byref(t)), "tuning_set")
 
     def autotune_esdf(self, subs) -> dict:

@@ -443,7 +443,8 @@ void covox_destroy(covox_ctx *ctx)
                       (void *)ctx->fcount, (void *)ctx->ray_acc, (void *)ctx->wf_nk, (void *)ctx->wf_np,
                       (void *)ctx->wf_sites, (void *)ctx->wf_flag, (void *)ctx->wf_list, (void *)ctx->wf_cnt,
                       (void *)ctx->sites[1], (void *)ctx->seeds[0], (void *)ctx->seeds[1], (void *)ctx->snap[0],
-                      (void *)ctx->snap[1], (void *)ctx->blk[0], (void *)ctx->blk[1]})
+                      (void *)ctx->snap[1], (void *)ctx->blk[0], (void *)ctx->blk[1], (void *)ctx->ddirty[0],
+                      (void *)ctx->ddirty[1]})
         if (ptr) (void)hipFree(ptr);
     for (void *p : ctx->deferred) (void)hipFree(p);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -528,6 +529,7 @@ int covox_submap_create(covox_ctx *ctx, const double T_world_submap[16], covox_s
     if (e == hipSuccess) e = hipMalloc((void **)&s->tvals, sizeof(uint32_t) * s->tcap);
     if (e == hipSuccess) e = hipMalloc((void **)&s->meta, sizeof(SubmapMeta));
     if (e == hipSuccess) e = hipMalloc((void **)&s->stamp, sizeof(uint32_t) * s->cap);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->dirty, (size_t)4 * ((s->cap + 3) / 4));
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->pin_nb, sizeof(uint64_t), hipHostMallocMapped | hipHostMallocCoherent);
     if (e == hipSuccess) {
         *s->pin_nb = 0;
@@ -539,6 +541,7 @@ int covox_submap_create(covox_ctx *ctx, const double T_world_submap[16], covox_s
     }
     submaps_of(ctx).push_back(s);
     fill_u32(ctx->stream, s->stamp, 0u, s->cap);  // frame-batch stamps (never reset)
+    fill_u32(ctx->stream, (uint32_t *)s->dirty, 0u, (s->cap + 3) / 4);
     int rc = covox_submap_reset(ctx, s);
     if (rc) {
         covox_submap_destroy(s);
@@ -560,6 +563,7 @@ void covox_submap_destroy(covox_submap *s)
                     (void *)s->page, (void *)s->pts, (void *)s->wf_k, (void *)s->wf_p, (void *)s->wf_wn})
         if (p) (void)hipFree(p);
     if (s->stamp) (void)hipFree(s->stamp);
+    if (s->dirty) (void)hipFree(s->dirty);
     if (s->pin_nb) (void)hipHostFree((void *)s->pin_nb);
     delete s;
 }
@@ -576,6 +580,7 @@ int covox_submap_reset(covox_ctx *ctx, covox_submap *s)
     s->bound_valid = false;
     s->version++;
     s->n_pts = 0;
+    s->esdf_exact = false;
     return wavefront_reset(ctx, s);
 }
 
@@ -1310,6 +1315,7 @@ int covox_graph_launch(covox_graph *g)
         s->version = v;
         if (esdf_current) s->esdf_version = v;
         if (page_current) s->page_version = v;
+        s->esdf_exact = false;  // the next eager exact update recomputes everything
     }
     return COVOX_OK;
 }
@@ -1364,6 +1370,8 @@ int covox_tuning_set(covox_ctx *ctx, const covox_tuning *t)
     if (t->edt_pipe_max_workgroups < 0)
         return fail(ctx, COVOX_EINVAL, "tuning_set: edt_pipe_max_workgroups must be >= 0");
     if (t->edt_col_seg < 0) return fail(ctx, COVOX_EINVAL, "tuning_set: edt_col_seg must be >= 0");
+    if (t->esdf_full_recompute != 0 && t->esdf_full_recompute != 1)
+        return fail(ctx, COVOX_EINVAL, "tuning_set: esdf_full_recompute must be 0 or 1");
     ctx->tune = *t;
     return COVOX_OK;
 }

@@ -199,6 +199,13 @@ struct covox_submap {
     static constexpr int kSeqRing = 256;
     int64_t box_ring[kSeqRing] = {};  // box sizes of the last calls, by sequence
     uint32_t *stamp = nullptr;       // per block: id of the last frame batch that listed it
+    // per block: 1 once an integration has changed it since the last exact
+    // ESDF update (cleared by that update's page kernel); cap bytes, padded
+    uint8_t *dirty = nullptr;
+    // the submap's phi is the exact ESDF of its TSDF at the last exact update,
+    // and the dirty flags cover every change since (else the next exact update
+    // recomputes everything)
+    bool esdf_exact = false;
     uint32_t batch_id = 0;
     bool bound_valid = false;        // box containing every allocated block
     int32_t bound_lo[3] = {0, 0, 0};
@@ -290,6 +297,8 @@ struct covox_ctx {
     int64_t seeds_cap[2] = {0, 0};            // dense blocks
     int32_t *blk[2] = {nullptr, nullptr};     // buffer index per dense block (column passes)
     int64_t blk_cap[2] = {0, 0};              // dense blocks
+    uint8_t *ddirty[2] = {nullptr, nullptr};  // dirty flag per dense block, then its dilation along x
+    int64_t ddirty_cap[2] = {0, 0};           // dense blocks (two arrays)
     covox::EsdfSnap *snap[2] = {nullptr, nullptr};  // kEsdfMaxJobs per slot
     int esdf_slot = 0;
     uint8_t *g1 = nullptr;      // 512 per dense block

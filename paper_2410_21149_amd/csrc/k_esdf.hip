@@ -51,6 +51,8 @@ struct EsdfJob {
     float *phi;
     int32_t *page;
     float *seeds;       // phi seed per voxel, by dense block index of the launch
+    uint8_t *dirty;     // the submap's per-block change flags (cleared by the page kernel with SEEDS)
+    int32_t full;       // every allocated block gets a new phi (else only those near a changed block)
 };
 
 template <int NJ>
@@ -243,7 +245,8 @@ __device__ __forceinline__ int64_t dom_index(const JobInfo &d, int x, int y, int
 // may be integrated while they run.
 template <typename S, int NJ, bool SEEDS>
 __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C, float vs, float tau,
-                                                    uint64_t *__restrict__ sites, int32_t *__restrict__ blk)
+                                                    uint64_t *__restrict__ sites, int32_t *__restrict__ blk,
+                                                    uint8_t *__restrict__ ddirty)
 {
     __shared__ Plan lds;
     PlanView<NJ, false> pv;
@@ -272,6 +275,7 @@ __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C,
             hash_find(job.tkeys, job.tvals, job.tmask, pack_key(d.lo[0] + x, d.lo[1] + y, d.lo[2] + z));
         job.page[db] = (int32_t)idx;
         if (blk) blk[g] = (int32_t)idx;  // the launch's own copy, read by the column passes
+        if (ddirty && idx < 0) ddirty[g] = 0;
         if (idx < 0) {
             uint4 *w = (uint4 *)(sites + g * 8);
 #pragma unroll
@@ -286,6 +290,13 @@ __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C,
         int bx, by, bz;
         unpack_key(job.keys[idx], bx, by, bz);
         const int64_t g = d.od + dom_index(d, bx - d.lo[0], by - d.lo[1], bz - d.lo[2]);
+        if constexpr (SEEDS) {
+            // an exact update consumes the block's change flag
+            if (lane == 0) {
+                if (ddirty) ddirty[g] = job.full ? 1 : job.dirty[idx];
+                job.dirty[idx] = 0;
+            }
+        }
         const S *Db = (const S *)job.D + idx * 512 + lane;
         const S *Wb = (const S *)job.W + idx * 512 + lane;
         // all reads before the first write (the seeds), so that they overlap
@@ -548,6 +559,54 @@ __global__ __launch_bounds__(512) void k_edt_z_vox(const JobList<NJ> jl, const u
         }
         job.phi[j * 512 + tid] = out;
         __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// The region of a partial update (jobs with full = 0): the blocks of the
+// launch's page copy (blk) whose phi can change are those within HB blocks,
+// along every axis, of a block whose TSDF changed since the last exact
+// update -- a site HB + 1 blocks away along some axis is more than 8 HB >= R
+// voxels away.  Two dilations of the change flags: k_esdf_dil_x along x into
+// dx, then k_esdf_region clears blk for allocated blocks with no flagged dx
+// within HB along y and z, which the column passes then neither write nor
+// read.  Jobs with full = 1 have every allocated block flagged.
+template <int NJ>
+__global__ __launch_bounds__(256) void k_esdf_dil_x(const JobList<NJ> jl, int HB, const uint8_t *__restrict__ ddirty,
+                                                    uint8_t *__restrict__ dx)
+{
+    __shared__ Plan lds;
+    PlanView<NJ> pv;
+    pv.init(jl, 8 * HB, lds);
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < pv.t[0];
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const JobInfo d = pv.info(pv.template job<&JobInfo::od>(g));
+        int x, y, z;
+        dom_coords(d, g - d.od, x, y, z);
+        uint8_t any = 0;
+        for (int k = max(0, x - HB); k <= min(d.dim[0] - 1, x + HB); ++k) any |= ddirty[g + (k - x)];
+        dx[g] = any;
+    }
+}
+
+template <int NJ>
+__global__ __launch_bounds__(256) void k_esdf_region(const JobList<NJ> jl, int HB, const uint8_t *__restrict__ dx,
+                                                     int32_t *__restrict__ blk)
+{
+    __shared__ Plan lds;
+    PlanView<NJ> pv;
+    pv.init(jl, 8 * HB, lds);
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < pv.t[0];
+         g += (int64_t)gridDim.x * blockDim.x) {
+        if (blk[g] < 0) continue;
+        const JobInfo d = pv.info(pv.template job<&JobInfo::od>(g));
+        int x, y, z;
+        dom_coords(d, g - d.od, x, y, z);
+        bool any = false;
+        for (int zz = max(0, z - HB); zz <= min(d.dim[2] - 1, z + HB) && !any; ++zz)
+            for (int yy = max(0, y - HB); yy <= min(d.dim[1] - 1, y + HB) && !any; ++yy)
+                any = dx[d.od + dom_index(d, x, yy, zz)] != 0;
+        if (!any) blk[g] = -1;
     }
 }
 
@@ -957,7 +1016,7 @@ int64_t bound_cols(const covox_submap *s, int a, int b, int HB)
 }
 
 template <int NJ>
-JobList<NJ> make_jobs(covox_submap *const *subs, int n, EsdfSnap *snap, float *seeds)
+JobList<NJ> make_jobs(covox_submap *const *subs, int n, EsdfSnap *snap, float *seeds, bool partial)
 {
     JobList<NJ> jl;
     memset(&jl, 0, sizeof(jl));
@@ -965,7 +1024,7 @@ JobList<NJ> make_jobs(covox_submap *const *subs, int n, EsdfSnap *snap, float *s
     for (int i = 0; i < n; ++i) {
         covox_submap *s = subs[i];
         jl.j[i] = EsdfJob{s->meta, snap + i, s->keys, s->tkeys, s->tvals, (uint64_t)s->tcap - 1, s->D, s->W,
-                          s->phi, s->page, seeds};
+                          s->phi, s->page, seeds, s->dirty, (partial && s->esdf_exact) ? 0 : 1};
     }
     return jl;
 }
@@ -1027,11 +1086,19 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
     chunk_cols(subs, n, HB, cy, cz);
     const int Sseg = force >= 0 ? 0 : col_segment(ctx, HB);
     const bool cols = edt && Sseg > 0;
+    // a partial update (column passes only, never under capture): the
+    // submaps whose phi is exact and whose changes since are all flagged
+    bool partial = cols && !ctx->capturing && !ctx->tune.esdf_full_recompute;
+    if (partial) {
+        bool any = false;
+        for (int i = 0; i < n; ++i) any = any || subs[i]->esdf_exact;
+        partial = any;
+    }
     // a buffer that grows is freed: the passes of an earlier update on the
     // other stream may still read it
     bool grows = ctx->sites_cap[slot] < nd ||
                  (edt && (ctx->seeds_cap[slot] < nd || (!cols && ctx->g1_cap < nd) || ctx->g2_cap < nd)) ||
-                 (cols && ctx->blk_cap[slot] < nd);
+                 (cols && ctx->blk_cap[slot] < nd) || (partial && ctx->ddirty_cap[slot] < 2 * nd);
     for (int i = 0; i < n; ++i) grows = grows || subs[i]->page_cap < std::max<int64_t>(bound_blocks(subs[i]), 1);
     if (grows && edt_stream != ctx->stream && !ctx->capturing &&
         (rc = hip_check(ctx, hipStreamSynchronize(edt_stream), "esdf stream sync")))
@@ -1058,8 +1125,12 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
                                     "esdf block index")))
         return rc;
     int32_t *const blk = cols ? ctx->blk[slot] : nullptr;
+    if (partial && (rc = ensure_buffer(ctx, (void **)&ctx->ddirty[slot], &ctx->ddirty_cap[slot], 2 * nd, 1,
+                                       "esdf change flags")))
+        return rc;
+    uint8_t *const ddirty = partial ? ctx->ddirty[slot] : nullptr;
     uint64_t *const sites = ctx->sites[slot];
-    const JobList<NJ> jl = make_jobs<NJ>(subs, n, ctx->snap[slot], ctx->seeds[slot]);
+    const JobList<NJ> jl = make_jobs<NJ>(subs, n, ctx->snap[slot], ctx->seeds[slot], partial);
     const float vs = (float)p.voxel_size, tau = (float)band_limit(p), dmax = (float)p.d_max;
     const bool h = p.precision == COVOX_FP16;
     {
@@ -1067,16 +1138,16 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
         const dim3 grid(clamp_grid(std::max((nd + 255) / 256, (nb + 3) / 4)));
         if (h && edt)
             hipLaunchKernelGGL((k_page_sites<__half, NJ, true>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               sites, blk);
+                               sites, blk, ddirty);
         else if (h)
             hipLaunchKernelGGL((k_page_sites<__half, NJ, false>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               sites, blk);
+                               sites, blk, ddirty);
         else if (edt)
             hipLaunchKernelGGL((k_page_sites<float, NJ, true>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               sites, blk);
+                               sites, blk, ddirty);
         else
             hipLaunchKernelGGL((k_page_sites<float, NJ, false>), grid, dim3(256), 0, ctx->stream, jl, C, vs, tau,
-                               sites, blk);
+                               sites, blk, ddirty);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "page launch"))) return rc;
     for (int i = 0; i < n; ++i) subs[i]->page_version = subs[i]->version;
@@ -1102,6 +1173,11 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
         ctx->stream = edt_stream;  // for the launches and their timing events below
     }
     if (cols) {
+        if (partial) {
+            const unsigned gd = cap_grid(ctx, clamp_grid((nd + 255) / 256));
+            hipLaunchKernelGGL((k_esdf_dil_x<NJ>), dim3(gd), dim3(256), 0, ctx->stream, jl, HB, ddirty, ddirty + nd);
+            hipLaunchKernelGGL((k_esdf_region<NJ>), dim3(gd), dim3(256), 0, ctx->stream, jl, HB, ddirty + nd, blk);
+        }
         int64_t sy = 0, sz = 0;
         for (int i = 0; i < n; ++i) {
             sy += std::max<int64_t>(bound_segs(subs[i], 1, Sseg), 1);
@@ -1119,7 +1195,10 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
         }
         ctx->stream = base;
         if ((rc = hip_check(ctx, hipGetLastError(), "esdf launch"))) return rc;
-        for (int i = 0; i < n; ++i) subs[i]->esdf_version = subs[i]->version;
+        for (int i = 0; i < n; ++i) {
+            subs[i]->esdf_version = subs[i]->version;
+            if (!ctx->capturing) subs[i]->esdf_exact = true;
+        }
         return COVOX_OK;
     }
     {
@@ -1147,7 +1226,10 @@ int esdf_chunk(covox_ctx *ctx, covox_submap *const *subs, int n, bool edt, int f
     }
     ctx->stream = base;
     if ((rc = hip_check(ctx, hipGetLastError(), "esdf launch"))) return rc;
-    for (int i = 0; i < n; ++i) subs[i]->esdf_version = subs[i]->version;
+    for (int i = 0; i < n; ++i) {
+        subs[i]->esdf_version = subs[i]->version;
+        if (!ctx->capturing) subs[i]->esdf_exact = true;
+    }
     return COVOX_OK;
 }
 
@@ -1207,7 +1289,8 @@ int autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int n)
     const int32_t saved_timing = ctx->timing;
     ctx->timing = 0;  // no per-kernel events inside the measured region
     covox_tuning &t = ctx->tune;
-    const int64_t saved_seg = t.edt_col_seg;
+    const int64_t saved_seg = t.edt_col_seg, saved_full = t.esdf_full_recompute;
+    t.esdf_full_recompute = 1;  // every candidate times a whole update
     // candidates: the four shapes of the per-block passes, then the column
     // passes at five segment lengths
     constexpr int kSegs[5] = {2, 4, 8, 16, 32};
@@ -1229,6 +1312,7 @@ int autotune_esdf(covox_ctx *ctx, covox_submap *const *subs, int n)
         }
     }
     t.edt_col_seg = saved_seg;
+    t.esdf_full_recompute = saved_full;
     ctx->timing = saved_timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256) void k_probe(FrameArgs f, float vs, float tau,
                                                const uint64_t *__restrict__ tkeys,
                                                const uint32_t *__restrict__ tvals, uint64_t tmask,
                                                uint32_t *__restrict__ cand, int64_t n_box, S *D, S *W,
-                                               SubmapMeta *meta)
+                                               SubmapMeta *meta, uint8_t *__restrict__ dirty)
 {
     const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
@@ -192,7 +192,10 @@ __global__ __launch_bounds__(256) void k_probe(FrameArgs f, float vs, float tau,
         out = idx >= 0 ? (uint32_t)idx + 1u : kNew;
         if (FUSED && idx >= 0) {
             const int n_ok = update_column(D + idx * 512 + lane, W + idx * 512 + lane, sdf, wt, okm, tau, false);
-            if (lane == 0) atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
+            if (lane == 0) {
+                atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
+                dirty[idx] = 1;
+            }
         }
     }
     if (lane == 0) cand[j] = out;
@@ -340,7 +343,8 @@ __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float 
                                                    const uint64_t *__restrict__ t_key,
                                                    const uint32_t *__restrict__ t_idx,
                                                    const uint64_t *__restrict__ t_new, uint64_t *keys, S *D, S *W,
-                                                   uint64_t *tkeys, uint32_t *tvals, uint64_t tmask)
+                                                   uint64_t *tkeys, uint32_t *tvals, uint64_t tmask,
+                                                   uint8_t *__restrict__ dirty)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -363,7 +367,10 @@ __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float 
         float sdf[8], wt[8];
         const uint32_t okm = proj_column(f, vs, tau, maxr, ix, iy, 8 * bz, sdf, wt);
         const int n_ok = update_column(D + idx * 512 + lane, W + idx * 512 + lane, sdf, wt, okm, tau, is_new);
-        if (lane == 0) atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
+        if (lane == 0) {
+            atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
+            dirty[idx] = 1;
+        }
     }
 }
 
@@ -562,7 +569,7 @@ __global__ __launch_bounds__(256) void k_integrate_batch(const FrameArgs *__rest
                                                          SubmapMeta *__restrict__ meta,
                                                          const uint32_t *__restrict__ list,
                                                          const uint64_t *__restrict__ keys, S *D, S *W, float vs,
-                                                         float tau, float maxr)
+                                                         float tau, float maxr, uint8_t *__restrict__ dirty)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -610,7 +617,10 @@ __global__ __launch_bounds__(256) void k_integrate_batch(const FrameArgs *__rest
             st(Db + 64 * z, dv[z]);
             st(Wb + 64 * z, wv[z]);
         }
-        if (lane == 0) atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
+        if (lane == 0) {
+            atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
+            dirty[idx] = 1;
+        }
     }
 }
 
@@ -668,10 +678,10 @@ void launch_frame(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, float vs,
         TimedLaunch tl(ctx, COVOX_K_PROBE);
         if (fused)
             hipLaunchKernelGGL((k_probe<S, true>), dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau, maxr, s->tkeys,
-                               s->tvals, tmask, ctx->cand, n_box, D, W, s->meta);
+                               s->tvals, tmask, ctx->cand, n_box, D, W, s->meta, s->dirty);
         else
             hipLaunchKernelGGL((k_probe<S, false>), dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau, maxr, s->tkeys,
-                               s->tvals, tmask, ctx->cand, n_box, D, W, s->meta);
+                               s->tvals, tmask, ctx->cand, n_box, D, W, s->meta, s->dirty);
     }
     {
         TimedLaunch tl(ctx, COVOX_K_SCAN);
@@ -683,11 +693,11 @@ void launch_frame(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, float vs,
         if (fused)
             hipLaunchKernelGGL((k_integrate<S, true>), dim3(std::min(grid, kNewGrid)), dim3(256), 0, ctx->stream, f, vs,
                                tau, maxr, s->meta, ctx->t_key, ctx->t_idx, ctx->t_key + n_box, s->keys, D, W,
-                               s->tkeys, s->tvals, tmask);
+                               s->tkeys, s->tvals, tmask, s->dirty);
         else
             hipLaunchKernelGGL((k_integrate<S, false>), dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau, maxr,
                                s->meta, ctx->t_key, ctx->t_idx, ctx->t_key + n_box, s->keys, D, W, s->tkeys,
-                               s->tvals, tmask);
+                               s->tvals, tmask, s->dirty);
     }
 }
 
@@ -970,10 +980,12 @@ int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_
         TimedLaunch tl(ctx, COVOX_K_INTEGRATE);
         if (p.precision == COVOX_FP16)
             hipLaunchKernelGGL(k_integrate_batch<__half>, dim3(grid), dim3(256), 0, ctx->stream, ctx->frames_dev,
-                               s->meta, ctx->blist, s->keys, (__half *)s->D, (__half *)s->W, vs, tau_f, maxr);
+                               s->meta, ctx->blist, s->keys, (__half *)s->D, (__half *)s->W, vs, tau_f, maxr,
+                               s->dirty);
         else
             hipLaunchKernelGGL(k_integrate_batch<float>, dim3(grid), dim3(256), 0, ctx->stream, ctx->frames_dev,
-                               s->meta, ctx->blist, s->keys, (float *)s->D, (float *)s->W, vs, tau_f, maxr);
+                               s->meta, ctx->blist, s->keys, (float *)s->D, (float *)s->W, vs, tau_f, maxr,
+                               s->dirty);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "integrate batch launch"))) return rc;
     s->nb_upper += box_sum;

@@ -356,7 +356,8 @@ __global__ __launch_bounds__(256) void k_ray_accum(FrameArgs f, float vs, float 
 }
 
 __global__ __launch_bounds__(256) void k_ray_apply(SubmapMeta *__restrict__ meta, const uint32_t *__restrict__ t_idx,
-                                                   float *D, float *W, double *__restrict__ acc)
+                                                   float *D, float *W, double *__restrict__ acc,
+                                                   uint8_t *__restrict__ dirty)
 {
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -381,7 +382,10 @@ __global__ __launch_bounds__(256) void k_ray_apply(SubmapMeta *__restrict__ meta
                 *a2 = make_double2(0.0, 0.0);
             }
         }
-        if (lane == 0) atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
+        if (lane == 0) {
+            atomicAdd(&meta->n_updates, (unsigned long long)n_ok);
+            dirty[idx] = 1;
+        }
     }
 }
 
@@ -459,7 +463,7 @@ int raycast_frame(covox_ctx *ctx, covox_submap *s, const float *depth, int32_t H
     {
         TimedLaunch tl(ctx, COVOX_K_RAY_APPLY);
         hipLaunchKernelGGL(k_ray_apply, dim3(wave_grid), dim3(256), 0, ctx->stream, s->meta, ctx->t_idx, Dp, Wp,
-                           ctx->ray_acc);
+                           ctx->ray_acc, s->dirty);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "raycast launch"))) return rc;
     s->nb_upper += n_box;

@@ -373,6 +373,7 @@ int update_esdf_wavefront(covox_ctx *ctx, covox_submap *s)
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "wavefront phi"))) return rc;
     s->esdf_version = s->version;
+    s->esdf_exact = false;  // phi is the wavefront's, not the exact transform
     return COVOX_OK;
 }
 
