@@ -117,9 +117,11 @@ def measured_traffic(kind, tuning, census):
             table = json.loads(line[len("traffic_json: "):])
     if not table:
         return None
+    cols = (tuning or {}).get("edt_col_seg", 0) > 0  # column passes: x fused into y
     symbols = {"probe": "k_probe<float, true>", "scan": "k_scan", "integrate": "k_integrate<float, true>",
-               "esdf_page": "k_page_sites<float, 1, true>", "edt_x": "k_edt_x<1>", "edt_y": "k_edt_y_col<1>",
-               "edt_z": "k_edt_z_vox<1>"}
+               "esdf_page": "k_page_sites<float, 1, true>", "edt_x": "k_edt_x<1>",
+               "edt_y": "k_edt_xy<1>" if cols else "k_edt_y_col<1>",
+               "edt_z": "k_edt_z_col<1>" if cols else "k_edt_z_vox<1>"}
     ent = table.get(symbols.get(kind, ""))
     if ent is None:
         return None
