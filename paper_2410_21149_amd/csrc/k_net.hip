@@ -50,7 +50,7 @@ __host__ __device__ inline float bf2f(uint16_t h)
 
 struct ConvShape {
     int cin, cout, din, dout, stride;
-    int K() const { return 27 * cin; }
+    constexpr int K() const { return 27 * cin; }
 };
 
 constexpr int kLayers = 4;
@@ -181,80 +181,120 @@ __global__ void k_fc_bwd(const float *__restrict__ dout, const float *__restrict
     }
 }
 
-// Weight gradient: gw[co][k] += sum_p x_col[p][k] dy[p][co]; bias: sum_p dy.
-// Grid: (K * COUT) threads per position chunk, accumulated with atomics.
+// Weight and bias gradients on the matrix cores (MFMA 16x16x16 bf16, FP32
+// accumulation): gw[co][kk] = sum_p dy[p][co] xcol[p][kk], kk = tap CIN +
+// ci, xcol the input activation under tap kk of output position p (zero
+// outside the grid); column kk = K of xcol is 1, which gives the bias
+// gradient sum_p dy[p][co].  One wave per tile of 16 output channels x 16
+// columns and chunk of positions (16 per MFMA, the reduction dimension); dy
+// is rounded to bf16 (the activations are bf16 already); one atomic add per
+// output and chunk.
 template <int CIN, int COUT, int DIN, int DOUT, int STRIDE>
-__global__ void k_conv_wgrad(const uint16_t *__restrict__ x, const float *__restrict__ dy, float *__restrict__ gw,
-                             float *__restrict__ gb, int64_t n_pos, int64_t chunk)
+__global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__ x, const float *__restrict__ dy,
+                                                    float *__restrict__ gw, float *__restrict__ gb, int64_t n_pos,
+                                                    int64_t chunk)
 {
     constexpr int K = 27 * CIN;
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per = (int64_t)(K + 1) * COUT;
-    const int64_t slot = id % per, part = id / per;
+    constexpr int NCT = COUT / 16;
+    constexpr int NKT = (K + 1 + 15) / 16;  // column tiles, the bias column included
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t tile = wave % (NCT * NKT), part = wave / (NCT * NKT);
     const int64_t p0 = part * chunk;
-    if (p0 >= n_pos) return;
+    if (p0 >= n_pos) return;  // uniform across the wave
     const int64_t p1 = min(n_pos, p0 + chunk);
-    const int co = (int)(slot % COUT), k = (int)(slot / COUT);
-    float s = 0.f;
-    if (k == K) {
-        for (int64_t p = p0; p < p1; ++p) s += dy[p * COUT + co];
-        atomicAdd(&gb[co], s);
-        return;
-    }
-    const int off = k / CIN, ci = k % CIN;
+    const int ct = (int)(tile % NCT), kt = (int)(tile / NCT);
+    const int co = ct * 16 + (lane & 15);  // this lane's A row
+    const int kk = kt * 16 + (lane & 15);  // this lane's B column
+    const int q4 = 4 * (lane >> 4);         // its 4 positions of a step
+    const bool is_w = kk < K, is_b = kk == K;
+    const int off = is_w ? kk / CIN : 0, ci = is_w ? kk % CIN : 0;
     const int kd = off / 9, kh = (off / 3) % 3, kw = off % 3;
-    for (int64_t p = p0; p < p1; ++p) {
-        const float g = dy[p * COUT + co];
-        if (g == 0.f) continue;
-        const int ox = (int)(p % DOUT), oy = (int)((p / DOUT) % DOUT), oz = (int)((p / (DOUT * DOUT)) % DOUT);
-        const int64_t nb = p / ((int64_t)DOUT * DOUT * DOUT);
-        const int iz = oz * STRIDE + kd - 1, iy = oy * STRIDE + kh - 1, ix = ox * STRIDE + kw - 1;
-        if (iz < 0 || iy < 0 || ix < 0 || iz >= DIN || iy >= DIN || ix >= DIN) continue;
-        s += bf2f(x[(((nb * DIN + iz) * DIN + iy) * DIN + ix) * CIN + ci]) * g;
-    }
-    atomicAdd(&gw[(int64_t)co * K + k], s);
-}
-
-// Input gradient through the convolution, masked by the ReLU of the layer
-// that produced x (x > 0): dx[p][ci] = sum over (offset, co) dy[o][co] w[co][offset, ci].
-template <int CIN, int COUT, int DIN, int DOUT, int STRIDE>
-__global__ void k_conv_dgrad(const uint16_t *__restrict__ x, const float *__restrict__ dy,
-                             const float *__restrict__ wmaster, float *__restrict__ dx, int64_t n_in)
-{
-    constexpr int K = 27 * CIN;
-    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= n_in * CIN) return;
-    const int ci = (int)(id % CIN);
-    const int64_t p = id / CIN;
-    if (!(bf2f(x[id]) > 0.f)) {
-        dx[id] = 0.f;
-        return;
-    }
-    const int ix = (int)(p % DIN), iy = (int)((p / DIN) % DIN), iz = (int)((p / (DIN * DIN)) % DIN);
-    const int64_t nb = p / ((int64_t)DIN * DIN * DIN);
-    float s = 0.f;
-    for (int kd = 0; kd < 3; ++kd) {
-        const int tz = iz + 1 - kd;
-        if (tz < 0 || tz % STRIDE) continue;
-        const int oz = tz / STRIDE;
-        if (oz >= DOUT) continue;
-        for (int kh = 0; kh < 3; ++kh) {
-            const int ty = iy + 1 - kh;
-            if (ty < 0 || ty % STRIDE) continue;
-            const int oy = ty / STRIDE;
-            if (oy >= DOUT) continue;
-            for (int kw = 0; kw < 3; ++kw) {
-                const int tx = ix + 1 - kw;
-                if (tx < 0 || tx % STRIDE) continue;
-                const int ox = tx / STRIDE;
-                if (ox >= DOUT) continue;
-                const int64_t o = ((nb * DOUT + oz) * DOUT + oy) * DOUT + ox;
-                const int k = ((kd * 3 + kh) * 3 + kw) * CIN + ci;
-                for (int co = 0; co < COUT; ++co) s += dy[o * COUT + co] * wmaster[(int64_t)co * K + k];
+    v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t pb = p0; pb < p1; pb += 16) {
+        v4i16 av = {0, 0, 0, 0}, bv = {0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t p = pb + q4 + i;
+            if (p >= p1) continue;
+            av[i] = (short)f2bf(dy[p * COUT + co]);
+            if (is_b) {
+                bv[i] = (short)0x3F80;  // bf16 1.0
+            } else if (is_w) {
+                const int ox = (int)(p % DOUT), oy = (int)((p / DOUT) % DOUT), oz = (int)((p / (DOUT * DOUT)) % DOUT);
+                const int64_t nb = p / ((int64_t)DOUT * DOUT * DOUT);
+                const int iz = oz * STRIDE + kd - 1, iy = oy * STRIDE + kh - 1, ix = ox * STRIDE + kw - 1;
+                if (iz >= 0 && iy >= 0 && ix >= 0 && iz < DIN && iy < DIN && ix < DIN)
+                    bv[i] = (short)x[(((nb * DIN + iz) * DIN + iy) * DIN + ix) * CIN + ci];
             }
         }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
     }
-    dx[id] = s;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int co_o = ct * 16 + q4 + i, kk_o = kt * 16 + (lane & 15);
+        if (kk_o < K) atomicAdd(&gw[(int64_t)co_o * K + kk_o], acc[i]);
+        else if (kk_o == K) atomicAdd(&gb[co_o], acc[i]);
+    }
+}
+
+// Input gradient through the convolution on the matrix cores, masked by the
+// ReLU of the layer that produced x (x > 0): dx[p][ci] = sum over (tap, co)
+// dy[o][co] w[co][tap CIN + ci], o the output position that tap maps onto
+// input position p (none where the stride skips it).  One wave per tile of
+// 16 input positions x 16 input channels; the reduction runs over the taps
+// and, per tap, over the output channels 16 at a time; dy is rounded to
+// bf16 and the bf16 copy of the weights is used.
+template <int CIN, int COUT, int DIN, int DOUT, int STRIDE>
+__global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t *__restrict__ x, const float *__restrict__ dy,
+                                                    const uint16_t *__restrict__ wb, float *__restrict__ dx,
+                                                    int64_t n_in)
+{
+    constexpr int K = 27 * CIN;
+    constexpr int NCI = CIN / 16;
+    static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channel counts in multiples of 16");
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (wave >= ((n_in + 15) / 16) * NCI) return;  // uniform across the wave
+    const int cit = (int)(wave % NCI);
+    const int64_t pt = wave / NCI;
+    const int64_t pm = pt * 16 + (lane & 15);  // this lane's A row: an input position
+    const bool pin = pm < n_in;
+    const int64_t pp = pin ? pm : 0;
+    const int ix = (int)(pp % DIN), iy = (int)((pp / DIN) % DIN), iz = (int)((pp / (DIN * DIN)) % DIN);
+    const int64_t nb = pp / ((int64_t)DIN * DIN * DIN);
+    const int cib = cit * 16 + (lane & 15);  // this lane's B column: an input channel
+    const int q4 = 4 * (lane >> 4);
+    v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int tap = 0; tap < 27; ++tap) {
+        const int kd = tap / 9, kh = (tap / 3) % 3, kw = tap % 3;
+        const int tz = iz + 1 - kd, ty = iy + 1 - kh, tx = ix + 1 - kw;
+        const bool ok = pin && tz >= 0 && ty >= 0 && tx >= 0 && tz % STRIDE == 0 && ty % STRIDE == 0 &&
+                        tx % STRIDE == 0 && tz / STRIDE < DOUT && ty / STRIDE < DOUT && tx / STRIDE < DOUT;
+        const int64_t o = ok ? ((nb * DOUT + tz / STRIDE) * DOUT + ty / STRIDE) * DOUT + tx / STRIDE : 0;
+#pragma unroll
+        for (int c0 = 0; c0 < COUT; c0 += 16) {
+            v4i16 av = {0, 0, 0, 0}, bv;
+            if (ok) {
+                const float4 g = *(const float4 *)(dy + o * COUT + c0 + q4);
+                av[0] = (short)f2bf(g.x);
+                av[1] = (short)f2bf(g.y);
+                av[2] = (short)f2bf(g.z);
+                av[3] = (short)f2bf(g.w);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bv[i] = (short)wb[(int64_t)(c0 + q4 + i) * K + tap * CIN + cib];
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t p = pt * 16 + q4 + i;
+        if (p < n_in) {
+            const int64_t id = p * CIN + cit * 16 + (lane & 15);
+            dx[id] = bf2f(x[id]) > 0.f ? acc[i] : 0.f;
+        }
+    }
 }
 
 // Adam (Kingma and Ba, 2015) on the FP32 master weights; refreshes the bf16
@@ -409,12 +449,13 @@ template <int L>
 static void launch_wgrad(covox_net *net, const uint16_t *x, int n)
 {
     constexpr ConvShape s = kShapes[L];
+    constexpr int64_t tiles = (int64_t)(s.cout / 16) * ((s.K() + 1 + 15) / 16);
     const int64_t npos = (int64_t)n * s.dout * s.dout * s.dout;
-    const int64_t chunk = 2048;
-    const int64_t parts = (npos + chunk - 1) / chunk;
-    const int64_t threads = parts * (int64_t)(s.K() + 1) * s.cout;
-    hipLaunchKernelGGL((k_conv_wgrad<s.cin, s.cout, s.din, s.dout, s.stride>), dim3(blocks_for(threads, 256)), dim3(256), 0,
-                       net->ctx->stream, x, net->d[L], net->g + net->P.off_w[L], net->g + net->P.off_b[L], npos, chunk);
+    const int64_t chunk = 1024;  // positions per wave (a multiple of 16)
+    const int64_t waves = tiles * ((npos + chunk - 1) / chunk);
+    hipLaunchKernelGGL((k_conv_wgrad<s.cin, s.cout, s.din, s.dout, s.stride>), dim3(blocks_for(waves * 64, 256)),
+                       dim3(256), 0, net->ctx->stream, x, net->d[L], net->g + net->P.off_w[L],
+                       net->g + net->P.off_b[L], npos, chunk);
 }
 
 template <int L>
@@ -422,8 +463,9 @@ static void launch_dgrad(covox_net *net, const uint16_t *x, float *dx, int n)
 {
     constexpr ConvShape s = kShapes[L];
     const int64_t nin = (int64_t)n * s.din * s.din * s.din;
-    hipLaunchKernelGGL((k_conv_dgrad<s.cin, s.cout, s.din, s.dout, s.stride>), dim3(blocks_for(nin * s.cin, 256)),
-                       dim3(256), 0, net->ctx->stream, x, net->d[L], net->w + net->P.off_w[L], dx, nin);
+    const int64_t waves = ((nin + 15) / 16) * (s.cin / 16);
+    hipLaunchKernelGGL((k_conv_dgrad<s.cin, s.cout, s.din, s.dout, s.stride>), dim3(blocks_for(waves * 64, 256)),
+                       dim3(256), 0, net->ctx->stream, x, net->d[L], net->wb[L], dx, nin);
 }
 
 static int net_backward(covox_net *net, int n)
