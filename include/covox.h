@@ -232,7 +232,8 @@ typedef struct {
     int32_t iterations;   /* pose updates applied (Levenberg-Marquardt: steps taken) */
     int32_t status;       /* COVOX_OK, COVOX_NOT_CONVERGED or COVOX_EDEGENERATE */
     int32_t best_start;   /* multi-start: the chosen start, else 0 */
-    int32_t reserved;
+    int32_t solves;       /* binary64 solves made, rejected Levenberg-Marquardt steps included
+                             (Gauss-Newton: = iterations) */
 } covox_align_stats;
 
 /*
@@ -249,8 +250,11 @@ typedef struct {
  * delta.H.delta) / n the decrease of the mean cost c/n that the linear model
  * predicts (fewer than n_min residuals at the trial: not taken); then
  * mu *= max(1/3, 1 - (2 rho - 1)^3), nu = 2, else mu *= nu, nu *= 2 (mu starts
- * at 1e-4, nu at 2).  A step below the tolerances ends the solve as
- * converged without being taken; max_iter caps the solves.
+ * at 1e-4, nu at 2).  A step below the tolerances, or one whose L is
+ * within the binary32 rounding noise of the cost (L n <= 2^-19 Q sqrt(c),
+ * c = n times the mean cost, Q the largest norm of a corner of A's ESDF
+ * domain in metres), ends the solve as converged without being taken;
+ * max_iter caps the solves.
  * T_init_A_B, T_out (host, 16 doubles) map B coordinates into A's frame.
  * cost (host) = mean squared residual at T_out.  stats: nullable.
  * Requires covox_update_esdf(A) after A's last integration.  Synchronous.

@@ -282,25 +282,26 @@ def align(A: Submap, pts, T_init):
     p = _pts(A, pts)
     T = np.zeros(16)
     cost = np.zeros(1)
-    info = np.zeros(2, np.int64)
+    info = np.zeros(3, np.int64)
     st = _load().orc_align_points(A._h, p.ctypes.data_as(_vp), len(p), _p(_mat(T_init), _dp), _p(T, _dp),
                                   _p(cost, _dp), _p(info, _i64p))
     return {"T": T.reshape(4, 4), "cost": float(cost[0]), "status": int(st), "iters": int(info[0]),
-            "n": int(info[1])}
+            "n": int(info[1]), "solves": int(info[2])}
 
 
 def align_multistart(A: Submap, pts, T_init, n_starts=8):
     p = _pts(A, pts)
     T = np.zeros(16)
     cost = np.zeros(1)
-    info = np.zeros(2, np.int64)
+    info = np.zeros(3, np.int64)
     best = ctypes.c_int(-1)
     starts = np.zeros(16 * n_starts)
     st = _load().orc_align_multistart(A._h, p.ctypes.data_as(_vp), len(p), _p(_mat(T_init), _dp), n_starts,
                                       _p(T, _dp), _p(cost, _dp), _p(info, _i64p), ctypes.byref(best),
                                       _p(starts, _dp))
     return {"T": T.reshape(4, 4), "cost": float(cost[0]), "status": int(st), "iters": int(info[0]),
-            "n": int(info[1]), "best": best.value, "starts": starts.reshape(n_starts, 4, 4)}
+            "n": int(info[1]), "solves": int(info[2]), "best": best.value,
+            "starts": starts.reshape(n_starts, 4, 4)}
 
 
 def ray_walk32(o, u, s0, s1, vs, fragile=False):

@@ -1616,7 +1616,17 @@ int orc_solve_xyz_yaw(const double ne[29], double d[6]) { return orc_solve_xyz_y
  * mu starts at 1e-4 (relative to diag(H), Marquardt's scaling), nu at 2
  * (the rule of Madsen, Nielsen and Tingleff, 2004).  max_iter caps the
  * solves; fewer than n_min residuals at the start is EDEGENERATE, as is a
- * damped matrix that is not positive definite.  info[0] = steps taken.
+ * damped matrix that is not positive definite.
+ * Rounding-noise floor: a residual computed in a format of unit roundoff u
+ * is off by at most about 16 u Q, Q the distance from A's origin of the
+ * farthest corner of A's block box (every point with a residual lies in
+ * it): the transform, the grid coordinate and the interpolation each add a
+ * few roundings of quantities up to Q.  Independent errors add in
+ * root-sum-square, so c = sum r^2 is uncertain by up to 2 * 16 u Q sqrt(c).
+ * A step whose predicted decrease L n is within that is converged (not
+ * taken): beyond it the gain ratio compares rounding noise.  u = 2^-24 for
+ * binary32 residuals, 2^-53 for binary64.
+ * info[0] = steps taken, info[1] = n at the returned T, info[2] = solves.
  */
 static double lm_predicted(const double *ne, const double d[6])
 {
@@ -1643,15 +1653,37 @@ static int align_lm(const orc_submap *A, const void *pts, int64_t n_pts, const d
     orc_normal_eq(A, pts, n_pts, T, ne);
     if (A->p.max_iter > 0 && ne[28] < A->p.n_min) status = ORC_EDEGENERATE;
     double mu = 1e-4, nu = 2.0;
+    /* Q from the block box of A (block edge 8 voxels) */
+    int64_t bmin[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, bmax[3] = {INT64_MIN, INT64_MIN, INT64_MIN};
+    for (int64_t j = 0; j < A->n; ++j) {
+        int64_t b[3];
+        unpack_key(A->keys[j], b);
+        for (int a = 0; a < 3; ++a) {
+            if (b[a] < bmin[a]) bmin[a] = b[a];
+            if (b[a] > bmax[a]) bmax[a] = b[a];
+        }
+    }
+    const double edge = 8.0 * (A->p.fp64 ? A->p.vs : (double)(float)A->p.vs);
+    double q2 = 0.0;
+    for (int a = 0; a < 3 && A->n > 0; ++a) {
+        const double lo = fabs(edge * (double)bmin[a]), hi = fabs(edge * (double)(bmax[a] + 1));
+        const double m = lo > hi ? lo : hi;
+        q2 += m * m;
+    }
+    const double u = A->p.fp64 ? ldexp(1.0, -53) : ldexp(1.0, -24);
+    const double noise = 2.0 * 16.0 * u * sqrt(q2);
+    int64_t solves = 0;
     for (int it = 0; it < A->p.max_iter && status == ORC_NOT_CONVERGED; ++it) {
         double d[6];
         if ((A->p.align_dof == 4 ? orc_solve_xyz_yaw_damped(ne, mu, d) : orc_solve6_damped(ne, mu, d)) != 0) {
             status = ORC_EDEGENERATE;
             break;
         }
+        ++solves;
         double nr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         double nth = sqrt(d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
         if (nr < A->p.tol_rho && nth < A->p.tol_theta) { status = ORC_OK; break; }
+        if (lm_predicted(ne, d) <= noise * sqrt(ne[27])) { status = ORC_OK; break; }
         double E[16];
         orc_se3_exp(d, E);
         rigid_mul(E, T, Tt);
@@ -1673,7 +1705,7 @@ static int align_lm(const orc_submap *A, const void *pts, int64_t n_pts, const d
     }
     *cost = ne[28] > 0 ? ne[27] / ne[28] : INFINITY;
     memcpy(T_out, T, sizeof(T));
-    if (info) { info[0] = taken; info[1] = (int64_t)ne[28]; }
+    if (info) { info[0] = taken; info[1] = (int64_t)ne[28]; info[2] = solves; }
     return status;
 }
 
@@ -1684,7 +1716,8 @@ static int align_lm(const orc_submap *A, const void *pts, int64_t n_pts, const d
  * positive definite; delta = -H^-1 b; T <- Exp(delta) T; stop when
  * |delta_rho| < 1e-7 m and |delta_theta| < 1e-8 rad (converged) or after
  * max_iter iterations.  cost = c / n at the returned T.
- * info[0] = pose updates applied, info[1] = n used at the returned T.
+ * info[0] = pose updates applied, info[1] = n used at the returned T,
+ * info[2] = solves (Gauss-Newton: = info[0]).
  */
 int orc_align_points(const orc_submap *A, const void *pts, int64_t n_pts, const double *T_init,
                      double *T_out, double *cost, int64_t *info)
@@ -1714,7 +1747,7 @@ int orc_align_points(const orc_submap *A, const void *pts, int64_t n_pts, const 
     orc_normal_eq(A, pts, n_pts, T, ne);
     *cost = ne[28] > 0 ? ne[27] / ne[28] : INFINITY;
     memcpy(T_out, T, sizeof(T));
-    if (info) { info[0] = n_upd; info[1] = (int64_t)ne[28]; }
+    if (info) { info[0] = n_upd; info[1] = (int64_t)ne[28]; info[2] = n_upd; }
     return status;
 }
 
@@ -1739,6 +1772,7 @@ int orc_align_multistart(const orc_submap *A, const void *pts, int64_t n_pts, co
     double *cs = (double *)malloc(sizeof(double) * n_starts);
     int64_t *ns = (int64_t *)malloc(sizeof(int64_t) * n_starts);
     int64_t *its = (int64_t *)malloc(sizeof(int64_t) * n_starts);
+    int64_t *sol = (int64_t *)malloc(sizeof(int64_t) * n_starts);
     int *st = (int *)malloc(sizeof(int) * n_starts);
     int64_t nmax = 0;
     for (int k = 0; k < n_starts; ++k) {
@@ -1751,10 +1785,11 @@ int orc_align_multistart(const orc_submap *A, const void *pts, int64_t n_pts, co
         rigid_mul(S, Rz, S);
         rigid_mul(S, Pm, S);
         if (starts_out) memcpy(starts_out + 16 * k, S, sizeof(S));
-        int64_t inf[2];
+        int64_t inf[3];
         st[k] = orc_align_points(A, pts, n_pts, S, Ts + 16 * k, &cs[k], inf);
         its[k] = inf[0];
         ns[k] = inf[1];
+        sol[k] = inf[2];
         if (st[k] != ORC_EDEGENERATE && ns[k] > nmax) nmax = ns[k];
     }
     int best = -1;
@@ -1767,15 +1802,15 @@ int orc_align_multistart(const orc_submap *A, const void *pts, int64_t n_pts, co
     if (best >= 0) {
         memcpy(T_out, Ts + 16 * best, sizeof(double) * 16);
         *cost = cs[best];
-        if (info) { info[0] = its[best]; info[1] = ns[best]; }
+        if (info) { info[0] = its[best]; info[1] = ns[best]; info[2] = sol[best]; }
         status = st[best];
     } else {
         memcpy(T_out, T_init, sizeof(double) * 16);
         *cost = INFINITY;
-        if (info) { info[0] = 0; info[1] = 0; }
+        if (info) { info[0] = 0; info[1] = 0; info[2] = 0; }
     }
     if (best_k) *best_k = best;
-    free(Ts); free(cs); free(ns); free(its); free(st);
+    free(Ts); free(cs); free(ns); free(its); free(sol); free(st);
     return status;
 }
 

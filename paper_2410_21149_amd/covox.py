@@ -51,7 +51,7 @@ class covox_params(ctypes.Structure):
 
 class covox_align_stats(ctypes.Structure):
     _fields_ = [("n_points", ctypes.c_int64), ("n_used", ctypes.c_int64), ("iterations", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("best_start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("best_start", ctypes.c_int32), ("solves", ctypes.c_int32)]
 
 
 class covox_pair(ctypes.Structure):
@@ -572,7 +572,7 @@ class Graph:
 
 def _stats(st: covox_align_stats) -> dict:
     return {"n_points": st.n_points, "n_used": st.n_used, "iterations": st.iterations, "status": st.status,
-            "best_start": st.best_start}
+            "best_start": st.best_start, "solves": st.solves}
 
 
 class Net:

@@ -352,7 +352,7 @@ void fill_stats(covox_align_stats *st, const covox_submap *B, const AlignResult 
     st->iterations = r.iters;
     st->status = r.status;
     st->best_start = best;
-    st->reserved = 0;
+    st->solves = r.solves;
 }
 
 }  // namespace

@@ -479,6 +479,8 @@ struct AlignResult {
     int64_t n_used;
     int32_t iters;
     int32_t status;
+    int32_t solves;  // binary64 solves made (Gauss-Newton: = iters)
+    int32_t pad;
 };
 
 int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult *res);

@@ -428,6 +428,13 @@ __device__ void se3_left_update(const double xi[6], double T[12])
 // Marquardt (the trust-region least squares Sec. III-F names): the solve is
 // damped by mu diag(H), its trial pose is evaluated, and the step is taken
 // when the mean cost falls (gain ratio > 0); max_iter then caps the solves.
+// LM also ends as converged when the decrease L that the model predicts is
+// within the cost's binary32 rounding noise, L <= 2^-19 Q sqrt(c): each
+// residual carries an error of up to 16 u Q (u = 2^-24, Q the largest norm
+// of a corner of A's ESDF domain, in metres), and over the residuals these
+// errors add in root-sum-square to at most 2 * 16 u Q sqrt(c) in c = sum r^2;
+// below that the gain ratio is rounding noise.
+constexpr double kCostNoise32 = 1.0 / 524288.0;  // 2 * 16 * 2^-24
 template <int kAlignThreads, int U, bool LM>
 __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__restrict__ probs,
                                                          const int32_t *__restrict__ order, AlignResult *res,
@@ -445,6 +452,16 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__r
     const AlignProblem &P = probs[pid];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const DomArgs d = dom_of(P.metaA);
+    double noise = 0.0;  // LM: the floor of the predicted decrease is noise sqrt(c)
+    if (LM) {
+        double q2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double lo = (8.0 * (double)vs) * (double)d.lo[a], hi = (8.0 * (double)vs) * (double)(d.lo[a] + d.dim[a]);
+            const double m = fmax(fabs(lo), fabs(hi));
+            q2 += m * m;
+        }
+        noise = kCostNoise32 * sqrt(q2);
+    }
     if (tid < 12) {
         sT[tid] = P.T[tid];
         sTf[tid] = (float)P.T[tid];
@@ -549,7 +566,7 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__r
                     s_state[1] += 1;
                     const double nr = sqrt(dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2]);
                     const double nt = sqrt(dl[3] * dl[3] + dl[4] * dl[4] + dl[5] * dl[5]);
-                    if (nr < tol_rho && nt < tol_theta) {
+                    if ((nr < tol_rho && nt < tol_theta) || lm_predicted(sPrev, dl) <= noise * sqrt(sPrev[27])) {
                         s_state[2] = COVOX_OK;  // converged; the step is not taken
                         stop = true;
                     } else {
@@ -610,6 +627,7 @@ __global__ __launch_bounds__(kAlignThreads) void k_align(const AlignProblem *__r
         R.n_used = (int64_t)ne[28];
         R.cost = ne[28] > 0 ? ne[27] / ne[28] : __builtin_inf();
         R.iters = acc ? s_lm[1] : s_state[1];
+        R.solves = s_state[1];
         R.status = s_state[2];
     }
 }
