@@ -289,6 +289,41 @@ typedef struct {
 int covox_align_batch(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_t n_starts,
                       double *T_out, double *cost, covox_align_stats *stats);
 
+/*
+ * The batch of covox_align_batch in three parts, for callers that capture
+ * their work in a HIP graph or repeat one alignment batch many times.
+ *
+ * covox_align_prepare checks the pairs as covox_align_batch does (A's ESDF
+ * current, rigid starts), extracts the registration points, and uploads the
+ * n x n_starts problems to device memory that the set owns.  The solver
+ * settings, max_iter and the launch shape of the context at this call are
+ * the set's.  Synchronous; not during capture.  *out receives the set.
+ *
+ * covox_align_launch enqueues the one persistent alignment launch of the
+ * set on the context stream; results stay in the set's device memory.  It
+ * may be called during graph capture: the launch is then recorded, and each
+ * replay of the graph recomputes the results.  EINVAL when a submap of the
+ * set changed (integration, reset, ESDF update) after covox_align_prepare;
+ * covox_graph_launch refuses a graph in that case too, and covox_graph_end
+ * refuses a capture that changes a submap that it also aligns.
+ *
+ * covox_align_collect waits for the stream, copies the results back and
+ * selects the start of each pair: T_out (n x 16), cost (n) and stats (n,
+ * nullable) as covox_align_batch returns them, bit for bit.  Synchronous.
+ *
+ * covox_align_set_destroy frees the set (after the context's pending work;
+ * while graphs of the context live, its device memory is kept until the
+ * context is destroyed).  Destroy sets and graphs that use a submap before
+ * the submap; a set outlives its context as a handle only.
+ */
+typedef struct covox_align_set covox_align_set;
+int covox_align_prepare(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_t n_starts,
+                        covox_align_set **out);
+int covox_align_launch(covox_ctx *ctx, covox_align_set *set);
+int covox_align_collect(covox_ctx *ctx, covox_align_set *set, double *T_out, double *cost,
+                        covox_align_stats *stats);
+void covox_align_set_destroy(covox_align_set *set);
+
 /* ------------------------------------------------------------ inspection */
 
 typedef struct {

@@ -127,6 +127,11 @@ _sig = {
                                               ctypes.POINTER(covox_align_stats)]),
     "covox_align_batch": (ctypes.c_int, [_vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_int32, _dp, _dp,
                                          ctypes.POINTER(covox_align_stats)]),
+    "covox_align_prepare": (ctypes.c_int, [_vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(_vp)]),
+    "covox_align_launch": (ctypes.c_int, [_vp, _vp]),
+    "covox_align_collect": (ctypes.c_int, [_vp, _vp, _dp, _dp, ctypes.POINTER(covox_align_stats)]),
+    "covox_align_set_destroy": (None, [_vp]),
     "covox_submap_info_get": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_submap_info)]),
     "covox_export_blocks": (ctypes.c_int64, [_vp, _vp, _vp, _vp, _fp, _fp, _fp, ctypes.c_int64]),
     "covox_export_points": (ctypes.c_int64, [_vp, _vp, _fp, ctypes.c_int64]),
@@ -346,6 +351,19 @@ class Context:
                     "align_batch")
         return T.reshape(-1, 4, 4)[:n], cost[:n], [_stats(st[i]) for i in range(n)]
 
+    def align_prepare(self, pairs, n_starts=1) -> "AlignSet":
+        """The problems of align_batch(pairs, n_starts) on the device, for
+        repeated or graph-captured launches (AlignSet.launch / collect)."""
+        n = len(pairs)
+        arr = (covox_pair * max(n, 1))()
+        for i, (A, B, T0) in enumerate(pairs):
+            arr[i].A = A.handle
+            arr[i].B = B.handle
+            arr[i].T_init_A_B[:] = list(_mat(T0))
+        h = _vp()
+        self._check(_lib.covox_align_prepare(self.handle, arr, n, n_starts, ctypes.byref(h)), "align_prepare")
+        return AlignSet(self, h, n)
+
     def normal_equations(self, A: Submap, B: Submap, T) -> np.ndarray:
         out = np.zeros(29)
         Tm = _mat(T)
@@ -561,6 +579,40 @@ class Graph:
     def close(self):
         if getattr(self, "handle", None):
             _lib.covox_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class AlignSet:
+    """Alignment problems prepared on the device: launch() enqueues the
+    alignment (also inside a graph capture), collect() returns what
+    align_batch returns."""
+
+    def __init__(self, ctx: Context, handle, n: int):
+        self.ctx = ctx
+        self.handle = handle
+        self.n = n
+
+    def launch(self):
+        self.ctx._check(_lib.covox_align_launch(self.ctx.handle, self.handle), "align_launch")
+
+    def collect(self):
+        n = self.n
+        T = np.zeros(16 * n)
+        cost = np.zeros(n)
+        st = (covox_align_stats * n)()
+        self.ctx._check(_lib.covox_align_collect(self.ctx.handle, self.handle, _p(T, _dp), _p(cost, _dp), st),
+                        "align_collect")
+        return T.reshape(-1, 4, 4), cost, [_stats(st[i]) for i in range(n)]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.covox_align_set_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -344,15 +344,41 @@ int select_start(const AlignResult *r, int n)
     return best;
 }
 
-void fill_stats(covox_align_stats *st, const covox_submap *B, const AlignResult &r, int best)
+void fill_stats(covox_align_stats *st, int64_t n_points, const AlignResult &r, int best)
 {
     if (!st) return;
-    st->n_points = B->n_pts;
+    st->n_points = n_points;
     st->n_used = r.n_used;
     st->iterations = r.iters;
     st->status = r.status;
     st->best_start = best;
     st->solves = r.solves;
+}
+
+// Per pair: the chosen start (least cost under select_start; one start:
+// that start unless degenerate), its pose, cost and statistics.
+void finish_pairs(int n, int n_starts, const AlignResult *res, const double *T_init, const int64_t *n_points,
+                  double *T_out, double *cost, covox_align_stats *stats)
+{
+    for (int i = 0; i < n; ++i) {
+        const AlignResult *r = &res[(size_t)i * n_starts];
+        const int best = n_starts == 1 ? (r[0].status == COVOX_EDEGENERATE ? -1 : 0) : select_start(r, n_starts);
+        if (best < 0) {
+            memcpy(T_out + 16 * i, T_init + 16 * (size_t)i, sizeof(double) * 16);
+            if (n_starts == 1) memcpy(T_out + 16 * i, r[0].T, sizeof(double) * 16);
+            cost[i] = n_starts == 1 ? r[0].cost : INFINITY;
+            if (stats) {
+                if (n_starts == 1) fill_stats(stats + i, n_points[i], r[0], 0);
+                else { memset(stats + i, 0, sizeof(*stats)); stats[i].n_points = n_points[i]; }
+                stats[i].status = COVOX_EDEGENERATE;
+                stats[i].best_start = n_starts == 1 ? 0 : -1;
+            }
+            continue;
+        }
+        memcpy(T_out + 16 * i, r[best].T, sizeof(double) * 16);
+        cost[i] = r[best].cost;
+        fill_stats(stats ? stats + i : nullptr, n_points[i], r[best], best);
+    }
 }
 
 }  // namespace
@@ -436,6 +462,15 @@ void covox_destroy(covox_ctx *ctx)
     // and their handles stay valid for covox_net_destroy alone.
     for (covox_net *net : ctx->nets) net_detach(net);
     ctx->nets.clear();
+    // Alignment sets likewise: device memory now, handles for covox_align_set_destroy.
+    for (covox_align_set *set : ctx->align_sets) {
+        for (void *p : {set->dev, (void *)set->dres})
+            if (p) (void)hipFree(p);
+        set->dev = nullptr;
+        set->dres = nullptr;
+        set->ctx = nullptr;
+    }
+    ctx->align_sets.clear();
     for (void *ptr : {(void *)ctx->cand, (void *)ctx->t_key, (void *)ctx->t_idx, (void *)ctx->sites[0], (void *)ctx->g1,
                       (void *)ctx->g2, (void *)ctx->cnt, (void *)ctx->psum, ctx->prob_dev, ctx->res_dev, ctx->sum_dev,
                       (void *)ctx->net_in, (void *)ctx->net_out, (void *)ctx->train_y, (void *)ctx->loss_hist,
@@ -716,7 +751,7 @@ int covox_align_submaps(covox_ctx *ctx, const covox_submap *A, const covox_subma
     if ((rc = run_alignment(ctx, &pr, 1, &res))) return rc;
     memcpy(T_out, res.T, sizeof(res.T));
     *cost = res.cost;
-    fill_stats(stats, B, res, 0);
+    fill_stats(stats, B->n_pts, res, 0);
     return res.status;
 }
 
@@ -745,7 +780,7 @@ int covox_align_multistart(covox_ctx *ctx, const covox_submap *A, const covox_su
     }
     memcpy(T_out, res[best].T, sizeof(double) * 16);
     *cost = res[best].cost;
-    fill_stats(stats, B, res[best], best);
+    fill_stats(stats, B->n_pts, res[best], best);
     return res[best].status;
 }
 
@@ -769,26 +804,115 @@ int covox_align_batch(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_
         }
     std::vector<AlignResult> res(prs.size());
     if ((rc = run_alignment(ctx, prs.data(), (int)prs.size(), res.data()))) return rc;
+    std::vector<double> T0((size_t)16 * n);
+    std::vector<int64_t> np(n);
     for (int i = 0; i < n; ++i) {
-        const AlignResult *r = &res[(size_t)i * n_starts];
-        const int best = n_starts == 1 ? (r[0].status == COVOX_EDEGENERATE ? -1 : 0) : select_start(r, n_starts);
-        if (best < 0) {
-            memcpy(T_out + 16 * i, pairs[i].T_init_A_B, sizeof(double) * 16);
-            if (n_starts == 1) memcpy(T_out + 16 * i, r[0].T, sizeof(double) * 16);
-            cost[i] = n_starts == 1 ? r[0].cost : INFINITY;
-            if (stats) {
-                if (n_starts == 1) fill_stats(stats + i, pairs[i].B, r[0], 0);
-                else { memset(stats + i, 0, sizeof(*stats)); stats[i].n_points = pairs[i].B->n_pts; }
-                stats[i].status = COVOX_EDEGENERATE;
-                stats[i].best_start = n_starts == 1 ? 0 : -1;
-            }
-            continue;
-        }
-        memcpy(T_out + 16 * i, r[best].T, sizeof(double) * 16);
-        cost[i] = r[best].cost;
-        fill_stats(stats ? stats + i : nullptr, pairs[i].B, r[best], best);
+        memcpy(&T0[16 * (size_t)i], pairs[i].T_init_A_B, sizeof(double) * 16);
+        np[i] = pairs[i].B->n_pts;
     }
+    finish_pairs(n, n_starts, res.data(), T0.data(), np.data(), T_out, cost, stats);
     return COVOX_OK;
+}
+
+int covox_align_prepare(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_t n_starts, covox_align_set **out)
+{
+    COVOX_NOT_DURING_CAPTURE(ctx, "align_prepare");
+    if (!ctx || !pairs || !out || n < 1 || n_starts < 1 || (int64_t)n * n_starts > INT32_MAX / 2)
+        return fail(ctx, COVOX_EINVAL, "align_prepare: bad argument");
+    *out = nullptr;
+    int rc;
+    for (int i = 0; i < n; ++i) {
+        if (!rigid_pose(pairs[i].T_init_A_B)) return fail(ctx, COVOX_EINVAL, "align_prepare: T_init is not rigid");
+        if ((rc = prepare_pair(ctx, pairs[i].A, pairs[i].B))) return rc;
+    }
+    const int m = n * n_starts;
+    const size_t pbytes = sizeof(AlignProblem) * m + sizeof(int32_t) * m;
+    std::vector<char> stage(pbytes);
+    AlignProblem *prs = (AlignProblem *)stage.data();
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n_starts; ++k) {
+            double S[16];
+            if (n_starts == 1) memcpy(S, pairs[i].T_init_A_B, sizeof(S));
+            else start_pose(pairs[i].T_init_A_B, pairs[i].B->pbar, k, n_starts, S);
+            prs[(size_t)i * n_starts + k] = make_problem(ctx, pairs[i].A, pairs[i].B, S, ctx->p.max_iter);
+        }
+    align_order(prs, m, (int32_t *)(stage.data() + sizeof(AlignProblem) * m));
+    covox_align_set *set = new covox_align_set();
+    set->ctx = ctx;
+    set->n = n;
+    set->n_starts = n_starts;
+    set->launch = align_launch_of(ctx);
+    set->T_init.resize((size_t)16 * n);
+    set->n_points.resize(n);
+    for (int i = 0; i < n; ++i) {
+        memcpy(&set->T_init[16 * (size_t)i], pairs[i].T_init_A_B, sizeof(double) * 16);
+        set->n_points[i] = pairs[i].B->n_pts;
+        for (const covox_submap *q : {pairs[i].A, pairs[i].B}) {
+            bool seen = false;
+            for (const auto &f : set->frozen) seen = seen || f.s == q;
+            if (!seen) set->frozen.push_back(AlignFrozen{q, q->version});
+        }
+    }
+    hipError_t e = hipMalloc(&set->dev, pbytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&set->dres, sizeof(AlignResult) * m);
+    if (e == hipSuccess) e = hipMemcpyAsync(set->dev, stage.data(), pbytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        if (set->dev) (void)hipFree(set->dev);
+        if (set->dres) (void)hipFree(set->dres);
+        delete set;
+        return hip_check(ctx, e, "align_prepare");
+    }
+    ctx->align_sets.push_back(set);
+    *out = set;
+    return COVOX_OK;
+}
+
+int covox_align_launch(covox_ctx *ctx, covox_align_set *set)
+{
+    if (!ctx || !set || set->ctx != ctx) return fail(ctx, COVOX_EINVAL, "align_launch: bad argument");
+    for (const auto &f : set->frozen)
+        if (f.s->version != f.version)
+            return fail(ctx, COVOX_EINVAL, "align_launch: a submap of the set changed since covox_align_prepare");
+    if (ctx->capturing)
+        for (const auto &f : set->frozen) ctx->cap_frozen.push_back(f);
+    const int m = set->n * set->n_starts;
+    return launch_alignment(ctx, (const AlignProblem *)set->dev,
+                            (const int32_t *)((const char *)set->dev + sizeof(AlignProblem) * m), m, set->dres,
+                            set->launch);
+}
+
+int covox_align_collect(covox_ctx *ctx, covox_align_set *set, double *T_out, double *cost, covox_align_stats *stats)
+{
+    COVOX_NOT_DURING_CAPTURE(ctx, "align_collect");
+    if (!ctx || !set || set->ctx != ctx || !T_out || !cost) return fail(ctx, COVOX_EINVAL, "align_collect: bad argument");
+    const int m = set->n * set->n_starts;
+    std::vector<AlignResult> res(m);
+    int rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(res.data(), set->dres, sizeof(AlignResult) * m, hipMemcpyDeviceToHost,
+                                            ctx->stream),
+                        "align_collect copy")))
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "align_collect sync"))) return rc;
+    finish_pairs(set->n, set->n_starts, res.data(), set->T_init.data(), set->n_points.data(), T_out, cost, stats);
+    return COVOX_OK;
+}
+
+void covox_align_set_destroy(covox_align_set *set)
+{
+    if (!set) return;
+    covox_ctx *ctx = set->ctx;
+    if (ctx) {
+        (void)hipStreamSynchronize(ctx->stream);
+        auto &v = ctx->align_sets;
+        v.erase(std::remove(v.begin(), v.end(), set), v.end());
+        for (void *p : {set->dev, (void *)set->dres}) {
+            if (!p) continue;
+            if (ctx->capturing || ctx->n_graphs > 0) ctx->deferred.push_back(p);  // a graph may still name it
+            else (void)hipFree(p);
+        }
+    }
+    delete set;
 }
 
 int covox_normal_equations(covox_ctx *ctx, const covox_submap *A, const covox_submap *B, const double T_A_B[16],
@@ -1218,7 +1342,7 @@ int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs,
     for (int i = 0; i < n; ++i) {
         ::memcpy(T_out + 16 * i, res[i].T, sizeof(double) * 16);
         cost[i] = res[i].cost;
-        fill_stats(stats ? stats + i : nullptr, pairs[i].B, res[i], best[i]);
+        fill_stats(stats ? stats + i : nullptr, pairs[i].B->n_pts, res[i], best[i]);
     }
     return COVOX_OK;
 }
@@ -1240,6 +1364,7 @@ int covox_graph_begin(covox_ctx *ctx)
     ctx->capture_why.clear();
     ctx->cap_subs.clear();
     ctx->cap_host.clear();
+    ctx->cap_frozen.clear();
     ctx->cap_saved_timing = ctx->timing;
     ctx->timing = 0;  // no timing events inside a graph
     return COVOX_OK;
@@ -1266,10 +1391,14 @@ int covox_graph_end(covox_ctx *ctx, covox_graph **out)
         for (void *h : ctx->cap_host) (void)hipHostFree(h);
         ctx->cap_host.clear();
         ctx->cap_subs.clear();
+        ctx->cap_frozen.clear();
         return fail(ctx, code, why);
     };
     if (e != hipSuccess) return drop(std::string("graph_end: ") + hipGetErrorString(e), COVOX_EHIP);
     if (ctx->capture_bad) return drop("graph_end: " + ctx->capture_why, COVOX_EINVAL);
+    for (const auto &f : ctx->cap_frozen)
+        for (const auto &c : ctx->cap_subs)
+            if (c.s == f.s) return drop("graph_end: a submap that the graph aligns is also changed in it", COVOX_EINVAL);
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return drop(std::string("graph_end: instantiate: ") + hipGetErrorString(e), COVOX_EHIP);
@@ -1279,8 +1408,10 @@ int covox_graph_end(covox_ctx *ctx, covox_graph **out)
     g->exec = exec;
     g->subs = ctx->cap_subs;
     g->host_bufs = ctx->cap_host;
+    g->frozen = ctx->cap_frozen;
     ctx->cap_subs.clear();
     ctx->cap_host.clear();
+    ctx->cap_frozen.clear();
     ctx->n_graphs++;
     *out = g;
     return COVOX_OK;
@@ -1301,6 +1432,9 @@ int covox_graph_launch(covox_graph *g)
             ok = s->bound_lo[a] >= c.start.bound_lo[a] && s->bound_hi[a] <= c.start.bound_hi[a];
         if (!ok) return fail(ctx, COVOX_EINVAL, "graph_launch: a submap grew beyond its bounds at capture");
     }
+    for (const auto &f : g->frozen)
+        if (f.s->version != f.version)
+            return fail(ctx, COVOX_EINVAL, "graph_launch: a submap that the graph aligns changed since its set was prepared");
     int rc = hip_check(ctx, hipGraphLaunch(g->exec, ctx->stream), "graph launch");
     if (rc) return rc;
     for (const auto &c : g->subs) {

@@ -248,6 +248,12 @@ struct CaptureEntry {
     bool integrated;
 };
 
+// A submap and its version when an alignment set was prepared.
+struct AlignFrozen {
+    const covox_submap *s;
+    uint64_t version;
+};
+
 }  // namespace covox
 
 struct covox_graph {
@@ -255,7 +261,8 @@ struct covox_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<covox::CaptureEntry> subs;
-    std::vector<void *> host_bufs;  // pinned sources of captured copies
+    std::vector<void *> host_bufs;          // pinned sources of captured copies
+    std::vector<covox::AlignFrozen> frozen;  // submaps that captured alignment sets read
 };
 
 struct covox_ctx {
@@ -362,6 +369,8 @@ struct covox_ctx {
     std::string capture_why;
     std::vector<covox::CaptureEntry> cap_subs;
     std::vector<void *> cap_host;
+    std::vector<covox::AlignFrozen> cap_frozen;  // submaps read by alignment sets launched in the capture
+    std::vector<covox_align_set *> align_sets;    // live alignment sets (detached by covox_destroy)
     int32_t cap_saved_timing = 0;
     int n_graphs = 0;                 // live graphs: scratch is never freed while > 0
     std::vector<void *> deferred;     // scratch replaced while capturing or while graphs live
@@ -485,6 +494,21 @@ struct AlignResult {
 
 int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult *res);
 
+// Solver settings and launch shape of k_align, taken from a context.
+struct AlignLaunch {
+    float vs;
+    double tol_rho, tol_theta;
+    int n_min, dof, lm, threads, pps;
+};
+AlignLaunch align_launch_of(const covox_ctx *ctx);
+// Dispatch order of n problems: longest first (stable).
+void align_order(const AlignProblem *probs, int n, int32_t *order);
+// k_align over n problems already on the device, results to dres (device);
+// enqueues on ctx->stream only, so that it may be captured.
+int launch_alignment(covox_ctx *ctx, const AlignProblem *dprob, const int32_t *dorder, int n, AlignResult *dres,
+                     const AlignLaunch &L);
+
+
 // Coarse ESDF summary request (k_align.hip): 32^3 cells of edge `cell`
 // centred on the grid origin, grid frame -> submap frame by T.
 struct SummaryReq {
@@ -524,3 +548,16 @@ int net_grads(covox_net *net, const float *x_dev, const float *y_dev, int n, flo
               float *loss_host);
 
 }  // namespace covox
+
+// Alignment problems prepared once on the device, launched any number of
+// times (also under graph capture) and read back on demand.
+struct covox_align_set {
+    covox_ctx *ctx = nullptr;  // nullptr once the context is destroyed
+    int32_t n = 0, n_starts = 1;
+    covox::AlignLaunch launch{};
+    void *dev = nullptr;                 // n n_starts problems, then their dispatch order
+    covox::AlignResult *dres = nullptr;  // n n_starts results
+    std::vector<double> T_init;          // n x 16
+    std::vector<int64_t> n_points;       // B's registration points per pair
+    std::vector<covox::AlignFrozen> frozen;
+};

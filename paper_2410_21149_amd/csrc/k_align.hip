@@ -776,39 +776,39 @@ int run_summaries(covox_ctx *ctx, const SummaryReq *reqs, int n)
     return hip_check(ctx, hipGetLastError(), "summary launch");
 }
 
-int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult *res)
+AlignLaunch align_launch_of(const covox_ctx *ctx)
+{
+    AlignLaunch L;
+    L.vs = (float)ctx->p.voxel_size;
+    L.tol_rho = ctx->p.tol_rho;
+    L.tol_theta = ctx->p.tol_theta;
+    L.n_min = ctx->p.n_min;
+    L.dof = ctx->p.align_dof;
+    L.lm = ctx->p.align_solver == COVOX_LEVENBERG_MARQUARDT;
+    L.threads = ctx->tune.align_threads == 512 ? 512 : 256;
+    L.pps = ctx->tune.align_points_per_step == 2 ? 2 : 1;
+    return L;
+}
+
+void align_order(const AlignProblem *probs, int n, int32_t *order)
+{
+    // longest problems first so that the hardware dispatches them early
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order, order + n, [&](int a, int b) { return probs[a].n_pts > probs[b].n_pts; });
+}
+
+int launch_alignment(covox_ctx *ctx, const AlignProblem *dprob, const int32_t *dorder, int n, AlignResult *dres,
+                     const AlignLaunch &L)
 {
     if (n <= 0) return COVOX_OK;
-    int rc;
-    const size_t pbytes = sizeof(AlignProblem) * n + sizeof(int32_t) * n;
-    if ((rc = ensure_buffer(ctx, &ctx->prob_dev, &ctx->prob_cap, (int64_t)pbytes, 1, "problems"))) return rc;
-    if ((rc = ensure_buffer(ctx, &ctx->res_dev, &ctx->res_cap, (int64_t)(sizeof(AlignResult) * n), 1, "results")))
-        return rc;
-    // longest problems first so that the hardware dispatches them early
-    std::vector<int32_t> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].n_pts > probs[b].n_pts; });
-    std::vector<char> stage(pbytes);
-    ::memcpy(stage.data(), probs, sizeof(AlignProblem) * n);
-    ::memcpy(stage.data() + sizeof(AlignProblem) * n, order.data(), sizeof(int32_t) * n);
-    if ((rc = hip_check(ctx, hipMemcpyAsync(ctx->prob_dev, stage.data(), pbytes, hipMemcpyHostToDevice, ctx->stream),
-                        "problem upload")))
-        return rc;
-    const AlignProblem *dprob = (const AlignProblem *)ctx->prob_dev;
-    const int32_t *dorder = (const int32_t *)((const char *)ctx->prob_dev + sizeof(AlignProblem) * n);
     {
         TimedLaunch tl(ctx, COVOX_K_ALIGN);
-        AlignResult *dres = (AlignResult *)ctx->res_dev;
-        const float vs = (float)ctx->p.voxel_size;
-        const double tr = ctx->p.tol_rho, tt = ctx->p.tol_theta;
-        const int nm = ctx->p.n_min, dof = ctx->p.align_dof, lm = ctx->p.align_solver == COVOX_LEVENBERG_MARQUARDT;
-        const bool two = ctx->tune.align_points_per_step == 2;
-        const int shape = (ctx->tune.align_threads == 512 ? 4 : 0) + (two ? 2 : 0) + (lm ? 1 : 0);
+        const int shape = (L.threads == 512 ? 4 : 0) + (L.pps == 2 ? 2 : 0) + (L.lm ? 1 : 0);
         switch (shape) {
-#define COVOX_ALIGN_LAUNCH(S, NT, U, L)                                                                          \
+#define COVOX_ALIGN_LAUNCH(S, NT, U, LM)                                                                       \
     case S:                                                                                                    \
-        hipLaunchKernelGGL((k_align<NT, U, L>), dim3(n), dim3(NT), 0, ctx->stream, dprob, dorder, dres, vs, tr, \
-                           tt, nm, dof);                                                                       \
+        hipLaunchKernelGGL((k_align<NT, U, LM>), dim3(n), dim3(NT), 0, ctx->stream, dprob, dorder, dres, L.vs, \
+                           L.tol_rho, L.tol_theta, L.n_min, L.dof);                                            \
         break;
             COVOX_ALIGN_LAUNCH(0, 256, 1, false)
             COVOX_ALIGN_LAUNCH(1, 256, 1, true)
@@ -821,7 +821,26 @@ int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult 
 #undef COVOX_ALIGN_LAUNCH
         }
     }
-    if ((rc = hip_check(ctx, hipGetLastError(), "align launch"))) return rc;
+    return hip_check(ctx, hipGetLastError(), "align launch");
+}
+
+int run_alignment(covox_ctx *ctx, const AlignProblem *probs, int n, AlignResult *res)
+{
+    if (n <= 0) return COVOX_OK;
+    int rc;
+    const size_t pbytes = sizeof(AlignProblem) * n + sizeof(int32_t) * n;
+    if ((rc = ensure_buffer(ctx, &ctx->prob_dev, &ctx->prob_cap, (int64_t)pbytes, 1, "problems"))) return rc;
+    if ((rc = ensure_buffer(ctx, &ctx->res_dev, &ctx->res_cap, (int64_t)(sizeof(AlignResult) * n), 1, "results")))
+        return rc;
+    std::vector<char> stage(pbytes);
+    ::memcpy(stage.data(), probs, sizeof(AlignProblem) * n);
+    align_order(probs, n, (int32_t *)(stage.data() + sizeof(AlignProblem) * n));
+    if ((rc = hip_check(ctx, hipMemcpyAsync(ctx->prob_dev, stage.data(), pbytes, hipMemcpyHostToDevice, ctx->stream),
+                        "problem upload")))
+        return rc;
+    const AlignProblem *dprob = (const AlignProblem *)ctx->prob_dev;
+    const int32_t *dorder = (const int32_t *)((const char *)ctx->prob_dev + sizeof(AlignProblem) * n);
+    if ((rc = launch_alignment(ctx, dprob, dorder, n, (AlignResult *)ctx->res_dev, align_launch_of(ctx)))) return rc;
     if ((rc = hip_check(ctx, hipMemcpyAsync(res, ctx->res_dev, sizeof(AlignResult) * n, hipMemcpyDeviceToHost,
                                             ctx->stream),
                         "result copy")))
