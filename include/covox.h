@@ -646,7 +646,16 @@ typedef struct {
      * update or a graph replay.  1: every update recomputes everything (for
      * timing full updates).  The results do not depend on it. */
     int64_t esdf_full_recompute;
-    int64_t reserved[1];
+    /* Work order of the kernels that gather depth pixels (the probes and the
+     * frame-batch integration).  1: workgroup w of a grid of 8 C takes work
+     * item (w mod 8) C + floor(w / 8); the dispatcher deals workgroups to
+     * the eight XCDs in turn, so each XCD covers one contiguous eighth of
+     * the blocks (or of the frame-block pairs of a batch) and the depth rows
+     * they read stay in its own L2.  0 (default): items in dispatch order;
+     * on MI355X the XCD order gained nothing (outdoor frame batches: probe
+     * 12.8 against 11.7 ms per 3000 frames; room probe unchanged).  The
+     * results do not depend on it. */
+    int64_t mapping_xcd_order;
 } covox_tuning;
 
 /* Defaults: y envelopes from 2048 segments up, z always windowed, 256

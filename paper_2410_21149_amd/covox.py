@@ -75,7 +75,7 @@ class covox_tuning(ctypes.Structure):
     _fields_ = [("edt_y_env_min_cols", ctypes.c_int64), ("edt_z_env_min_cols", ctypes.c_int64),
                 ("align_threads", ctypes.c_int64), ("align_points_per_step", ctypes.c_int64),
                 ("edt_pipe_max_workgroups", ctypes.c_int64), ("edt_col_seg", ctypes.c_int64),
-                ("esdf_full_recompute", ctypes.c_int64), ("reserved", ctypes.c_int64 * 1)]
+                ("esdf_full_recompute", ctypes.c_int64), ("mapping_xcd_order", ctypes.c_int64)]
 
 
 class covox_pose_factor(ctypes.Structure):
@@ -514,7 +514,7 @@ class Context:
         return {"edt_y_env_min_cols": t.edt_y_env_min_cols, "edt_z_env_min_cols": t.edt_z_env_min_cols,
                 "align_threads": t.align_threads, "align_points_per_step": t.align_points_per_step,
                 "edt_pipe_max_workgroups": t.edt_pipe_max_workgroups, "edt_col_seg": t.edt_col_seg,
-                "esdf_full_recompute": t.esdf_full_recompute}
+                "esdf_full_recompute": t.esdf_full_recompute, "mapping_xcd_order": t.mapping_xcd_order}
 
     def tuning(self) -> dict:
         t = covox_tuning()
@@ -523,7 +523,7 @@ class Context:
 
     def set_tuning(self, edt_y_env_min_cols=None, edt_z_env_min_cols=None, align_threads=None,
                    align_points_per_step=None, edt_pipe_max_workgroups=None, edt_col_seg=None,
-                   esdf_full_recompute=None):
+                   esdf_full_recompute=None, mapping_xcd_order=None):
         t = covox_tuning()
         self._check(_lib.covox_tuning_get(self.handle, ctypes.byref(t)), "tuning_get")
         if edt_y_env_min_cols is not None:
@@ -540,6 +540,8 @@ class Context:
             t.edt_col_seg = edt_col_seg
         if esdf_full_recompute is not None:
             t.esdf_full_recompute = int(esdf_full_recompute)
+        if mapping_xcd_order is not None:
+            t.mapping_xcd_order = int(mapping_xcd_order)
         self._check(_lib.covox_tuning_set(self.handle, ctypes.byref(t)), "tuning_set")
 
     def autotune_esdf(self, subs) -> dict:

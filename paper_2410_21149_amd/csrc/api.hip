@@ -1506,6 +1506,8 @@ int covox_tuning_set(covox_ctx *ctx, const covox_tuning *t)
     if (t->edt_col_seg < 0) return fail(ctx, COVOX_EINVAL, "tuning_set: edt_col_seg must be >= 0");
     if (t->esdf_full_recompute != 0 && t->esdf_full_recompute != 1)
         return fail(ctx, COVOX_EINVAL, "tuning_set: esdf_full_recompute must be 0 or 1");
+    if (t->mapping_xcd_order != 0 && t->mapping_xcd_order != 1)
+        return fail(ctx, COVOX_EINVAL, "tuning_set: mapping_xcd_order must be 0 or 1");
     ctx->tune = *t;
     return COVOX_OK;
 }

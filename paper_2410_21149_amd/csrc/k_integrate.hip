@@ -154,6 +154,15 @@ __device__ __forceinline__ int update_column(S *Db, S *Wb, const float sdf[8], c
     return n_ok;
 }
 
+// Work item of workgroup w in a grid of n_wg = 8 C workgroups: with XCD
+// order, item (w mod 8) C + floor(w / 8), so that the workgroups the
+// dispatcher deals to one XCD cover one contiguous eighth of the items;
+// otherwise w.
+__device__ __forceinline__ int64_t work_item(int64_t w, int64_t n_wg, bool xcd)
+{
+    return xcd ? (w & 7) * (n_wg >> 3) + (w >> 3) : w;
+}
+
 // FUSED: blocks that already exist are updated here (their buffer index is
 // known), so only new blocks are left to k_integrate.  Used only when the
 // host bound proves that this frame cannot overflow the pool or the table,
@@ -163,9 +172,9 @@ __global__ __launch_bounds__(256) void k_probe(FrameArgs f, float vs, float tau,
                                                const uint64_t *__restrict__ tkeys,
                                                const uint32_t *__restrict__ tvals, uint64_t tmask,
                                                uint32_t *__restrict__ cand, int64_t n_box, S *D, S *W,
-                                               SubmapMeta *meta, uint8_t *__restrict__ dirty)
+                                               SubmapMeta *meta, uint8_t *__restrict__ dirty, int xcd)
 {
-    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t j = work_item(blockIdx.x, gridDim.x, xcd) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (j >= n_box) return;  // uniform across the wave
     int bx, by, bz;
@@ -388,31 +397,45 @@ __global__ __launch_bounds__(256) void k_integrate(FrameArgs f, float vs, float 
 __global__ __launch_bounds__(256) void k_probe_batch(const FrameArgs *__restrict__ frames, float vs, float tau,
                                                      float maxr, const uint64_t *__restrict__ tkeys,
                                                      const uint32_t *__restrict__ tvals, uint64_t tmask,
-                                                     uint32_t *__restrict__ cand, int64_t stride)
+                                                     uint32_t *__restrict__ cand, int64_t stride, int F, int xcd)
 {
-    const FrameArgs f = frames[blockIdx.y];
-    const int64_t n_box = (int64_t)f.bdim[0] * f.bdim[1] * f.bdim[2];
-    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    if (j >= n_box) return;  // uniform across the wave
-    int bx, by, bz;
-    box_block(f, j, bx, by, bz);
-    if (!block_may_be_visible(f, vs, bx, by, bz)) {  // uniform across the wave
-        if (lane == 0) cand[(int64_t)blockIdx.y * stride + j] = 0;
-        return;
+    // work items: (frame, group of 4 box blocks), frame-major, in a grid
+    // stride; with XCD order the workgroups on XCD r (w mod 8 = r) stride
+    // over the r-th eighth of the items
+    const int64_t per_frame = (stride + 3) / 4, n_items = per_frame * F;
+    int64_t first, end, step;
+    if (xcd) {
+        const int64_t per = (n_items + 7) / 8, r = blockIdx.x & 7;
+        first = r * per + (blockIdx.x >> 3);
+        end = min(n_items, (r + 1) * per);
+        step = gridDim.x >> 3;
+    } else {
+        first = blockIdx.x;
+        end = n_items;
+        step = gridDim.x;
     }
-    const int ix = 8 * bx + (lane & 7);
-    const int iy = 8 * by + (lane >> 3);
-    float sdf[8], w[8];
-    const bool any = proj_column(f, vs, tau, maxr, ix, iy, 8 * bz, sdf, w) != 0;
-    const uint64_t m = __ballot(any);
-    if (lane == 0) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t item = first; item < end; item += step) {
+        const int fi = (int)(item / per_frame);
+        const FrameArgs f = frames[fi];
+        const int64_t n_box = (int64_t)f.bdim[0] * f.bdim[1] * f.bdim[2];
+        const int64_t j = (item % per_frame) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        if (j >= n_box) continue;  // uniform across the wave
+        int bx, by, bz;
+        box_block(f, j, bx, by, bz);
         uint32_t out = 0;
-        if (m) {
-            const int64_t idx = hash_find(tkeys, tvals, tmask, pack_key(bx, by, bz));
-            out = idx >= 0 ? (uint32_t)idx + 1u : kNew;
+        if (block_may_be_visible(f, vs, bx, by, bz)) {  // uniform across the wave
+            const int ix = 8 * bx + (lane & 7);
+            const int iy = 8 * by + (lane >> 3);
+            float sdf[8], w[8];
+            const bool any = proj_column(f, vs, tau, maxr, ix, iy, 8 * bz, sdf, w) != 0;
+            const uint64_t m = __ballot(any);
+            if (lane == 0 && m) {
+                const int64_t idx = hash_find(tkeys, tvals, tmask, pack_key(bx, by, bz));
+                out = idx >= 0 ? (uint32_t)idx + 1u : kNew;
+            }
         }
-        cand[(int64_t)blockIdx.y * stride + j] = out;
+        if (lane == 0) cand[(int64_t)fi * stride + j] = out;
     }
 }
 
@@ -569,14 +592,28 @@ __global__ __launch_bounds__(256) void k_integrate_batch(const FrameArgs *__rest
                                                          SubmapMeta *__restrict__ meta,
                                                          const uint32_t *__restrict__ list,
                                                          const uint64_t *__restrict__ keys, S *D, S *W, float vs,
-                                                         float tau, float maxr, uint8_t *__restrict__ dirty)
+                                                         float tau, float maxr, uint8_t *__restrict__ dirty, int xcd)
 {
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t n_t = meta->n_touched, n0 = meta->batch_n0;
     const int F = meta->batch_frames;
-    for (int64_t t = wave; t < n_t; t += nwaves) {
+    // the listed blocks in a grid stride; with XCD order, the workgroups on
+    // XCD r (w mod 8 = r) stride over the r-th eighth of the list
+    const int64_t wpg = blockDim.x >> 6;
+    int64_t t0, t1, step, first;
+    if (xcd) {
+        const int r = blockIdx.x & 7;
+        t0 = n_t * r / 8;
+        t1 = n_t * (r + 1) / 8;
+        step = (int64_t)(gridDim.x >> 3) * wpg;
+        first = (int64_t)(blockIdx.x >> 3) * wpg + (threadIdx.x >> 6);
+    } else {
+        t0 = 0;
+        t1 = n_t;
+        step = (int64_t)gridDim.x * wpg;
+        first = (int64_t)blockIdx.x * wpg + (threadIdx.x >> 6);
+    }
+    for (int64_t t = t0 + first; t < t1; t += step) {
         const int64_t idx = list[t];
         const bool is_new = idx >= n0;
         int bx, by, bz;
@@ -674,14 +711,16 @@ void launch_frame(covox_ctx *ctx, covox_submap *s, const FrameArgs &f, float vs,
                   int64_t table_limit, int64_t n_box, unsigned grid, bool fused)
 {
     S *D = (S *)s->D, *W = (S *)s->W;
+    const int xcd = ctx->tune.mapping_xcd_order != 0;
+    const unsigned grid8 = (grid + 7) / 8 * 8;  // a multiple of 8 for the XCD order
     {
         TimedLaunch tl(ctx, COVOX_K_PROBE);
         if (fused)
-            hipLaunchKernelGGL((k_probe<S, true>), dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau, maxr, s->tkeys,
-                               s->tvals, tmask, ctx->cand, n_box, D, W, s->meta, s->dirty);
+            hipLaunchKernelGGL((k_probe<S, true>), dim3(grid8), dim3(256), 0, ctx->stream, f, vs, tau, maxr, s->tkeys,
+                               s->tvals, tmask, ctx->cand, n_box, D, W, s->meta, s->dirty, xcd);
         else
-            hipLaunchKernelGGL((k_probe<S, false>), dim3(grid), dim3(256), 0, ctx->stream, f, vs, tau, maxr, s->tkeys,
-                               s->tvals, tmask, ctx->cand, n_box, D, W, s->meta, s->dirty);
+            hipLaunchKernelGGL((k_probe<S, false>), dim3(grid8), dim3(256), 0, ctx->stream, f, vs, tau, maxr, s->tkeys,
+                               s->tvals, tmask, ctx->cand, n_box, D, W, s->meta, s->dirty, xcd);
     }
     {
         TimedLaunch tl(ctx, COVOX_K_SCAN);
@@ -955,8 +994,11 @@ int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_
     refresh_block_bound(s, box_sum);
     {
         TimedLaunch tl(ctx, COVOX_K_PROBE);
-        hipLaunchKernelGGL(k_probe_batch, dim3((unsigned)((box_max + 3) / 4), (unsigned)F), dim3(256), 0, ctx->stream,
-                           ctx->frames_dev, vs, tau_f, maxr, s->tkeys, s->tvals, tmask, ctx->cand, box_max);
+        const int64_t items = (box_max + 3) / 4 * F;
+        const unsigned pgrid = (unsigned)((std::min<int64_t>(items, 1 << 20) + 7) / 8 * 8);
+        hipLaunchKernelGGL(k_probe_batch, dim3(pgrid), dim3(256), 0, ctx->stream,
+                           ctx->frames_dev, vs, tau_f, maxr, s->tkeys, s->tvals, tmask, ctx->cand, box_max, F,
+                           (int)(ctx->tune.mapping_xcd_order != 0));
     }
     {
         TimedLaunch tl(ctx, COVOX_K_SCAN);
@@ -976,16 +1018,17 @@ int integrate_batch(covox_ctx *ctx, covox_submap *s, const float *depths, int32_
     {
         // one wave per listed block (at most min(capacity, sum of the boxes))
         const int64_t waves = std::max<int64_t>(1, std::min(s->cap, s->nb_upper + box_sum));
-        const unsigned grid = (unsigned)std::min<int64_t>((waves + 3) / 4, 1 << 20);
+        const unsigned grid = (unsigned)std::min<int64_t>((waves + 3) / 4 + 7, 1 << 20) / 8 * 8;
+        const int xcd = ctx->tune.mapping_xcd_order != 0;
         TimedLaunch tl(ctx, COVOX_K_INTEGRATE);
         if (p.precision == COVOX_FP16)
             hipLaunchKernelGGL(k_integrate_batch<__half>, dim3(grid), dim3(256), 0, ctx->stream, ctx->frames_dev,
                                s->meta, ctx->blist, s->keys, (__half *)s->D, (__half *)s->W, vs, tau_f, maxr,
-                               s->dirty);
+                               s->dirty, xcd);
         else
             hipLaunchKernelGGL(k_integrate_batch<float>, dim3(grid), dim3(256), 0, ctx->stream, ctx->frames_dev,
                                s->meta, ctx->blist, s->keys, (float *)s->D, (float *)s->W, vs, tau_f, maxr,
-                               s->dirty);
+                               s->dirty, xcd);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "integrate batch launch"))) return rc;
     s->nb_upper += box_sum;

@@ -146,18 +146,20 @@ def test_batch_integration_equals_sequential(cv):
     ctx.close()
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16"])
-def test_batched_integration_matches_oracle_and_single_frames(cv, precision):
+@pytest.mark.parametrize("precision,xcd", [("fp32", 0), ("fp16", 0), ("fp32", 1)])
+def test_batched_integration_matches_oracle_and_single_frames(cv, precision, xcd):
     """Frame batches (one probe, one scan and one update launch per batch)
     against per-frame calls and the oracle: blocks in (first frame, key)
     order, D and W bit for bit, also in binary16 storage where every frame's
-    result is rounded to the stored precision."""
+    result is rounded to the stored precision, and with the XCD work order
+    of the depth-gathering kernels."""
     import torch
     w = sg.tiny()
     fr = w.frames()
     dev = torch.from_numpy(fr).cuda()
     fp16 = precision == "fp16"
     ctx = _ctx(cv, precision=cv.FP16 if fp16 else cv.FP32)
+    ctx.set_tuning(mapping_xcd_order=xcd)
     a, b = ctx.submap_create(), ctx.submap_create()
     for f in range(w.n_frames):
         ctx.integrate_depth(a, dev[f], w.cam.K, w.poses[f])
