@@ -619,8 +619,8 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256, roofline_only=False):
             if ov >= 0.1:
                 cand_pgo.append((i, j, ov))
     pose_graph = pgo_bench(cv, torch, np, ctx, subs, Tws, cand_pgo, reps)
-    learned = learned_bench(cv, torch, np, ctx, subs, Tws, w.voxel_size)
     ctx.close()
+    learned = learned_bench(cv, torch, np)
     return {"workload": "outdoor 120x80 m, 3000 frames 640x480 fx=fy=380, 0.1 m voxels, 30 submaps of 100 frames",
             "build_s": t_build, "render_s": t_render, "mapping": mapping, "esdf_batch": esdf,
             "esdf_large_submap": large, "voxel_sweep": sweep, "align": align, "pose_graph": pose_graph,
@@ -989,12 +989,14 @@ def pgo_bench(cv, torch, np, ctx, subs, Tws, cand, reps=2):
             "kernel_ms": {k: v[0] for k, v in tk.items() if v[1]}}
 
 
-def learned_bench(cv, torch, np, ctx, subs, Tws, vs, n_items=1024, reps=3):
-    """Learned proposal + refinement against plain 8-start on held-out pairs
-    of the outdoor scene (its seed is not among the training seeds): every
-    pair with block overlap >= 0.2 (j = i+1..i+4, both directions), re-framed
-    like the training data (+-3 m x/y, +-0.5 m z, +-180 deg yaw about the
-    summary grid centre, +-2 deg roll/pitch), n_items in total."""
+def learned_bench(cv, torch, np, n_items=1024, reps=3, min_distinct=256, seed0=4):
+    """Learned proposal + refinement against plain 8-start on held-out pairs:
+    outdoor scenes from seed seed0 on (no training or calibration seed
+    among them), built until they give at least min_distinct directed pairs
+    with block overlap >= 0.2 (j = i+1..i+4, both directions), each pair
+    re-framed like the training data (+-3 m x/y, +-0.5 m z, +-180 deg yaw
+    about the summary grid centre, +-2 deg roll/pitch); n_items items drawn
+    round-robin over the pairs."""
     import importlib.util
     path = os.path.join(ROOT, "paper_2410_21149_amd", "data", "proposal_mav.npz")
     if not os.path.exists(path):
@@ -1004,14 +1006,22 @@ def learned_bench(cv, torch, np, ctx, subs, Tws, vs, n_items=1024, reps=3):
     tp = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(tp)
     params, meta = tp.load(path)
+    t0 = time.perf_counter()
+    ctx = cv.Context(voxel_size=0.1, trunc_vox=4, max_range=10.0, d_max=3.0, block_capacity=16384,
+                     tol_rho=OUTDOOR_TOL_RHO, tol_theta=OUTDOOR_TOL_THETA)
     net = cv.Net(ctx, seed=1)
     net.set_params(params)
     cell, c_thr = float(meta["cell"]), float(meta["c_thr"])
-    base = []
-    for i, j, ov in tp.block_pairs(ctx, subs, Tws, vs, min_overlap=0.2):
-        T = np.linalg.inv(Tws[i]) @ Tws[j]
-        base.append((subs[i], subs[j], T))
-        base.append((subs[j], subs[i], np.linalg.inv(T)))
+    base, seeds, sd = [], [], seed0
+    trained = set(meta.get("seeds", [])) | set(meta.get("calibration_seeds", []))
+    while len(base) < min_distinct:
+        if sd not in trained:
+            got = tp.build_scene(cv, torch, ctx, sd)
+            if got is not None:
+                base += tp.scene_pairs(ctx, *got)
+                seeds.append(sd)
+                _log("held-out scene seed %d: %d pairs so far" % (sd, len(base)))
+        sd += 1
     cent = {}
     rng = np.random.default_rng(6)
     items, gts = [], []
@@ -1028,8 +1038,11 @@ def learned_bench(cv, torch, np, ctx, subs, Tws, vs, n_items=1024, reps=3):
         E = tp.perturbed(rng, np.eye(4), trans=0.0, yaw_deg=0.0, tilt_deg=2.0)
         items.append((A, B, G @ np.linalg.inv(C) @ np.linalg.inv(G) @ T_gt @ E))
         gts.append(T_gt)
-    out = {"held_out_pairs": n_items, "distinct_pairs": len(base), "cell_m": cell, "cost_threshold": c_thr,
-           "training": {k: meta[k] for k in ("seeds", "pairs_train", "steps", "batch", "final_loss") if k in meta}}
+    out = {"held_out_pairs": n_items, "distinct_pairs": len(base), "held_out_seeds": seeds, "cell_m": cell,
+           "cost_threshold": c_thr, "build_s": time.perf_counter() - t0,
+           "training": {k: meta[k] for k in ("pairs_train", "steps", "batch", "render_scale", "final_loss")
+                        if k in meta}}
+    out["training"]["scenes"] = len(meta.get("seeds", []))
     runs = {}
     out["tuning"] = ctx.autotune_align(items, 8)
     for name, fn in (("plain_8start", lambda: ctx.align_batch(items, 8)),
@@ -1063,6 +1076,7 @@ def learned_bench(cv, torch, np, ctx, subs, Tws, vs, n_items=1024, reps=3):
                                       if pl["aligned_per_s_5cm"] > 0 else None)
     out["ratio_pairs_per_s"] = le["pairs_per_s"] / pl["pairs_per_s"]
     net.close()
+    ctx.close()
     return out
 
 
@@ -1437,12 +1451,13 @@ def summary_line(r):
         line["aligns"] = aligns
     if "learned" in mav and "plain_8start" in mav["learned"]:
         le = mav["learned"]
-        line["learned"] = dict(_pick(le, "held_out_pairs", "distinct_pairs", "ratio_aligned_per_s_1cm",
+        line["learned"] = dict(_pick(le, "held_out_pairs", "distinct_pairs", "held_out_seeds", "ratio_aligned_per_s_1cm",
                                      "ratio_aligned_per_s_5cm", "ratio_pairs_per_s",
                                      "proposal_only_success_0.5m_10deg"),
                                **{k: _pick(le[k], "pairs_per_s", "success_1cm_0.1deg", "success_5cm_0.5deg",
                                            "successes_1cm", "successes_5cm", "fallback_fraction")
                                   for k in ("plain_8start", "learned_refine")})
+        line["learned"]["training"] = _pick(le.get("training", {}), "pairs_train", "scenes", "steps")
     if "precision" in r:
         line["precision"] = dict(r["precision"])
         if "precision" in mav.get("align", {}):

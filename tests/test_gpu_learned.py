@@ -125,7 +125,9 @@ def test_network_forward_parity(cv):
     scale = np.abs(r).max()
     assert scale > 1e-3
     print("forward: max |gpu - oracle| / max |oracle| = %.3g" % (np.abs(g - r).max() / scale))
-    assert np.abs(g - r).max() <= 0.02 * scale, (g, r)
+    # the oracle rounds activations and weights to bf16 as the kernels do; what
+    # is left is FP32 against binary64 accumulation order (measured 5.5e-5)
+    assert np.abs(g - r).max() <= 1e-3 * scale, (g, r)
     # a different batch size gives the same per-sample outputs
     g1 = net.forward(torch.from_numpy(x[1:]).cuda()).cpu().numpy()
     assert np.array_equal(g1[0], g[1].astype(np.float32))
@@ -153,7 +155,9 @@ def test_network_gradients_parity(cv):
         errs.append(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12))
         o += sz
     print("gradient rel-L2 per tensor:", " ".join(f"{e:.2e}" for e in errs))
-    assert max(errs) <= 0.03, errs
+    # the kernels also round the upstream gradient to bf16 for the matrix
+    # cores (the oracle does not): measured at most 3.6e-3
+    assert max(errs) <= 1e-2, errs
     assert o == len(p)
     ctx.close()
 
