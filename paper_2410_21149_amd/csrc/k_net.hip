@@ -154,30 +154,32 @@ __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ 
 }
 
 // FC backward: gradients of the head, then d a4 = (d pooled / 64) masked by
-// ReLU (a4 > 0).
+// ReLU (a4 > 0).  Workgroup n (64 threads) sums the head's gradients over the
+// batch; workgroup b < n writes d a4 of item b.
 __global__ void k_fc_bwd(const float *__restrict__ dout, const float *__restrict__ pooled,
                          const float *__restrict__ wfc, const uint16_t *__restrict__ a4, float *__restrict__ gwfc,
                          float *__restrict__ gbfc, float *__restrict__ da4, int n)
 {
-    const int t = threadIdx.x;  // 64 threads, one block
-    // weight and bias gradients (each thread one feature column)
-    for (int o = 0; o < kOut; ++o) {
-        float g = 0.f, gb = 0.f;
-        for (int b = 0; b < n; ++b) {
-            g += dout[b * kOut + o] * pooled[b * kFeat + t];
-            gb += dout[b * kOut + o];
+    const int t = threadIdx.x, b = blockIdx.x;
+    if (b == n) {
+        // weight and bias gradients (each thread one feature column)
+        for (int o = 0; o < kOut; ++o) {
+            float g = 0.f, gb = 0.f;
+            for (int bb = 0; bb < n; ++bb) {
+                g += dout[bb * kOut + o] * pooled[bb * kFeat + t];
+                gb += dout[bb * kOut + o];
+            }
+            gwfc[o * kFeat + t] += g;
+            if (t == 0) gbfc[o] += gb;
         }
-        gwfc[o * kFeat + t] += g;
-        if (t == 0) gbfc[o] += gb;
+        return;
     }
-    for (int b = 0; b < n; ++b) {
-        float dp = 0.f;
-        for (int o = 0; o < kOut; ++o) dp += dout[b * kOut + o] * wfc[o * kFeat + t];
-        dp *= (1.0f / 64.0f);
-        for (int p = 0; p < 64; ++p) {
-            const int64_t q = ((int64_t)b * 64 + p) * kFeat + t;
-            da4[q] = bf2f(a4[q]) > 0.f ? dp : 0.f;
-        }
+    float dp = 0.f;
+    for (int o = 0; o < kOut; ++o) dp += dout[b * kOut + o] * wfc[o * kFeat + t];
+    dp *= (1.0f / 64.0f);
+    for (int p = 0; p < 64; ++p) {
+        const int64_t q = ((int64_t)b * 64 + p) * kFeat + t;
+        da4[q] = bf2f(a4[q]) > 0.f ? dp : 0.f;
     }
 }
 
@@ -185,11 +187,12 @@ __global__ void k_fc_bwd(const float *__restrict__ dout, const float *__restrict
 // accumulation): gw[co][kk] = sum_p dy[p][co] xcol[p][kk], kk = tap CIN +
 // ci, xcol the input activation under tap kk of output position p (zero
 // outside the grid); column kk = K of xcol is 1, which gives the bias
-// gradient sum_p dy[p][co].  One wave per tile of 16 output channels x 16
-// columns and chunk of positions (16 per MFMA, the reduction dimension); dy
-// is rounded to bf16 (the activations are bf16 already); one atomic add per
-// output and chunk.
-template <int CIN, int COUT, int DIN, int DOUT, int STRIDE>
+// gradient sum_p dy[p][co].  One wave per 16 output channels, G tiles of 16
+// columns and chunk of positions (16 per MFMA, the reduction dimension):
+// dy is read and rounded to bf16 once per step for the G tiles (the
+// activations are bf16 already), and each position's coordinates are
+// computed once for them; one atomic add per output and chunk.
+template <int CIN, int COUT, int DIN, int DOUT, int STRIDE, int G>
 __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__ x, const float *__restrict__ dy,
                                                     float *__restrict__ gw, float *__restrict__ gb, int64_t n_pos,
                                                     int64_t chunk)
@@ -197,44 +200,73 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
     constexpr int K = 27 * CIN;
     constexpr int NCT = COUT / 16;
     constexpr int NKT = (K + 1 + 15) / 16;  // column tiles, the bias column included
+    constexpr int NKG = (NKT + G - 1) / G;  // groups of G tiles
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t tile = wave % (NCT * NKT), part = wave / (NCT * NKT);
+    const int64_t tile = wave % (NCT * NKG), part = wave / (NCT * NKG);
     const int64_t p0 = part * chunk;
     if (p0 >= n_pos) return;  // uniform across the wave
     const int64_t p1 = min(n_pos, p0 + chunk);
-    const int ct = (int)(tile % NCT), kt = (int)(tile / NCT);
+    const int ct = (int)(tile % NCT), kg = (int)(tile / NCT);
     const int co = ct * 16 + (lane & 15);  // this lane's A row
-    const int kk = kt * 16 + (lane & 15);  // this lane's B column
     const int q4 = 4 * (lane >> 4);         // its 4 positions of a step
-    const bool is_w = kk < K, is_b = kk == K;
-    const int off = is_w ? kk / CIN : 0, ci = is_w ? kk % CIN : 0;
-    const int kd = off / 9, kh = (off / 3) % 3, kw = off % 3;
-    v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+    int tap[G], ci[G];                      // this lane's B column of each tile: tap and channel
+    bool is_w[G], is_b[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int kk = (kg * G + g) * 16 + (lane & 15);
+        is_w[g] = kk < K;
+        is_b[g] = kk == K;
+        tap[g] = is_w[g] ? kk / CIN : 0;
+        ci[g] = is_w[g] ? kk % CIN : 0;
+    }
+    v4f32 acc[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g] = (v4f32){0.f, 0.f, 0.f, 0.f};
     for (int64_t pb = p0; pb < p1; pb += 16) {
-        v4i16 av = {0, 0, 0, 0}, bv = {0, 0, 0, 0};
+        v4i16 av = {0, 0, 0, 0};
+        int oxs[4], oys[4], ozs[4];
+        int64_t nbs[4];
+        bool pin[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int64_t p = pb + q4 + i;
-            if (p >= p1) continue;
-            av[i] = (short)f2bf(dy[p * COUT + co]);
-            if (is_b) {
-                bv[i] = (short)0x3F80;  // bf16 1.0
-            } else if (is_w) {
-                const int ox = (int)(p % DOUT), oy = (int)((p / DOUT) % DOUT), oz = (int)((p / (DOUT * DOUT)) % DOUT);
-                const int64_t nb = p / ((int64_t)DOUT * DOUT * DOUT);
-                const int iz = oz * STRIDE + kd - 1, iy = oy * STRIDE + kh - 1, ix = ox * STRIDE + kw - 1;
-                if (iz >= 0 && iy >= 0 && ix >= 0 && iz < DIN && iy < DIN && ix < DIN)
-                    bv[i] = (short)x[(((nb * DIN + iz) * DIN + iy) * DIN + ix) * CIN + ci];
-            }
+            pin[i] = p < p1;
+            const int64_t pp = pin[i] ? p : p0;
+            av[i] = pin[i] ? (short)f2bf(dy[pp * COUT + co]) : (short)0;
+            oxs[i] = (int)(pp % DOUT);
+            oys[i] = (int)((pp / DOUT) % DOUT);
+            ozs[i] = (int)((pp / (DOUT * DOUT)) % DOUT);
+            nbs[i] = pp / ((int64_t)DOUT * DOUT * DOUT);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (kg * G + g >= NKT) break;  // uniform
+            const int kd = tap[g] / 9, kh = (tap[g] / 3) % 3, kw = tap[g] % 3;
+            v4i16 bv = {0, 0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (!pin[i]) continue;
+                if (is_b[g]) {
+                    bv[i] = (short)0x3F80;  // bf16 1.0
+                } else if (is_w[g]) {
+                    const int iz = ozs[i] * STRIDE + kd - 1, iy = oys[i] * STRIDE + kh - 1, ix = oxs[i] * STRIDE + kw - 1;
+                    if (iz >= 0 && iy >= 0 && ix >= 0 && iz < DIN && iy < DIN && ix < DIN)
+                        bv[i] = (short)x[(((nbs[i] * DIN + iz) * DIN + iy) * DIN + ix) * CIN + ci[g]];
+                }
+            }
+            acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[g], 0, 0, 0);
+        }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int co_o = ct * 16 + q4 + i, kk_o = kt * 16 + (lane & 15);
-        if (kk_o < K) atomicAdd(&gw[(int64_t)co_o * K + kk_o], acc[i]);
-        else if (kk_o == K) atomicAdd(&gb[co_o], acc[i]);
+    for (int g = 0; g < G; ++g) {
+        if (kg * G + g >= NKT) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co_o = ct * 16 + q4 + i, kk_o = (kg * G + g) * 16 + (lane & 15);
+            if (kk_o < K) atomicAdd(&gw[(int64_t)co_o * K + kk_o], acc[g][i]);
+            else if (kk_o == K) atomicAdd(&gb[co_o], acc[g][i]);
+        }
     }
 }
 
@@ -243,8 +275,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
 // dy[o][co] w[co][tap CIN + ci], o the output position that tap maps onto
 // input position p (none where the stride skips it).  One wave per tile of
 // 16 input positions x 16 input channels; the reduction runs over the taps
-// and, per tap, over the output channels 16 at a time; dy is rounded to
-// bf16 and the bf16 copy of the weights is used.
+// that map some position of the tile onto an output and, per tap, over the
+// output channels 16 at a time; dy is rounded to bf16 and the bf16 copy of
+// the weights is used.
 template <int CIN, int COUT, int DIN, int DOUT, int STRIDE>
 __global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t *__restrict__ x, const float *__restrict__ dy,
                                                     const uint16_t *__restrict__ wb, float *__restrict__ dx,
@@ -271,6 +304,9 @@ __global__ __launch_bounds__(256) void k_conv_dgrad(const uint16_t *__restrict__
         const int tz = iz + 1 - kd, ty = iy + 1 - kh, tx = ix + 1 - kw;
         const bool ok = pin && tz >= 0 && ty >= 0 && tx >= 0 && tz % STRIDE == 0 && ty % STRIDE == 0 &&
                         tx % STRIDE == 0 && tz / STRIDE < DOUT && ty / STRIDE < DOUT && tx / STRIDE < DOUT;
+        // a tap that maps no position of the tile onto an output adds only
+        // zeros (with stride 2, most taps for a row of input positions)
+        if (__ballot(ok) == 0) continue;  // uniform
         const int64_t o = ok ? ((nb * DOUT + tz / STRIDE) * DOUT + ty / STRIDE) * DOUT + tx / STRIDE : 0;
 #pragma unroll
         for (int c0 = 0; c0 < COUT; c0 += 16) {
@@ -449,11 +485,16 @@ template <int L>
 static void launch_wgrad(covox_net *net, const uint16_t *x, int n)
 {
     constexpr ConvShape s = kShapes[L];
-    constexpr int64_t tiles = (int64_t)(s.cout / 16) * ((s.K() + 1 + 15) / 16);
+    // One column tile per wave: sharing dy over 4 tiles (fewer, longer waves)
+    // measured slower on every layer.
+    constexpr int G = 1;
+    constexpr int64_t tiles = (int64_t)(s.cout / 16) * (((s.K() + 1 + 15) / 16 + G - 1) / G);
     const int64_t npos = (int64_t)n * s.dout * s.dout * s.dout;
-    const int64_t chunk = 1024;  // positions per wave (a multiple of 16)
+    // positions per wave (a multiple of 16): at most 1024, fewer where the
+    // layer has few positions, so that a launch has about 12 k waves
+    const int64_t chunk = std::max<int64_t>(64, std::min<int64_t>(1024, npos * tiles / 12288 / 16 * 16));
     const int64_t waves = tiles * ((npos + chunk - 1) / chunk);
-    hipLaunchKernelGGL((k_conv_wgrad<s.cin, s.cout, s.din, s.dout, s.stride>), dim3(blocks_for(waves * 64, 256)),
+    hipLaunchKernelGGL((k_conv_wgrad<s.cin, s.cout, s.din, s.dout, s.stride, G>), dim3(blocks_for(waves * 64, 256)),
                        dim3(256), 0, net->ctx->stream, x, net->d[L], net->g + net->P.off_w[L],
                        net->g + net->P.off_b[L], npos, chunk);
 }
@@ -473,7 +514,7 @@ static int net_backward(covox_net *net, int n)
     covox_ctx *ctx = net->ctx;
     const int64_t np = net->P.total;
     hipLaunchKernelGGL(k_zero, dim3(blocks_for(np, 256)), dim3(256), 0, ctx->stream, net->g, np);
-    hipLaunchKernelGGL(k_fc_bwd, dim3(1), dim3(64), 0, ctx->stream, net->dout, net->pooled, net->w + net->P.off_fcw,
+    hipLaunchKernelGGL(k_fc_bwd, dim3(n + 1), dim3(64), 0, ctx->stream, net->dout, net->pooled, net->w + net->P.off_fcw,
                        net->a[3], net->g + net->P.off_fcw, net->g + net->P.off_fcb, net->d[3], n);
     launch_wgrad<3>(net, net->a[2], n);
     launch_dgrad<3>(net, net->a[2], net->d[2], n);
