@@ -309,7 +309,9 @@ int covox_align_batch(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int32_
  *
  * covox_align_collect waits for the stream, copies the results back and
  * selects the start of each pair: T_out (n x 16), cost (n) and stats (n,
- * nullable) as covox_align_batch returns them, bit for bit.  Synchronous.
+ * nullable) as covox_align_batch returns them, bit for bit.  Before any
+ * launch has run, every start reads as not converged, unmoved, with an
+ * infinite cost.  Synchronous.
  *
  * covox_align_set_destroy frees the set (after the context's pending work;
  * while graphs of the context live, its device memory is kept until the

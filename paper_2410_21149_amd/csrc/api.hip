@@ -853,9 +853,20 @@ int covox_align_prepare(covox_ctx *ctx, const covox_pair *pairs, int32_t n, int3
             if (!seen) set->frozen.push_back(AlignFrozen{q, q->version});
         }
     }
+    // results before the first launch (or replay): each start as given, no
+    // update made, NOT_CONVERGED
+    std::vector<AlignResult> init(m);
+    for (int q = 0; q < m; ++q) {
+        memset(&init[q], 0, sizeof(AlignResult));
+        memcpy(init[q].T, prs[q].T, sizeof(init[q].T));
+        init[q].cost = INFINITY;
+        init[q].status = COVOX_NOT_CONVERGED;
+    }
     hipError_t e = hipMalloc(&set->dev, pbytes);
     if (e == hipSuccess) e = hipMalloc((void **)&set->dres, sizeof(AlignResult) * m);
     if (e == hipSuccess) e = hipMemcpyAsync(set->dev, stage.data(), pbytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(set->dres, init.data(), sizeof(AlignResult) * m, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         if (set->dev) (void)hipFree(set->dev);

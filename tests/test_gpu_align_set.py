@@ -89,6 +89,8 @@ def test_graph_replays_equal_eager(cv):
     other = [(A, B, orc.se3_exp(np.array([0.1, 0.0, 0.0, 0.0, 0.0, math.radians(20)])))]
     ref_other = ctx.align_batch(other, 1)
     st = ctx.align_prepare(pairs, 8)  # never launched eagerly: the results come from the replays
+    T0s, c0s, s0s = st.collect()  # before any run: the starts, unmoved, not converged
+    assert np.all(np.isinf(c0s)) and all(x["status"] == cv.NOT_CONVERGED and x["iterations"] == 0 for x in s0s)
     ctx.graph_begin()
     st.launch()
     g = ctx.graph_end()
