@@ -507,6 +507,7 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256, roofline_only=False):
                "voxel_updates": int(n_upd), "voxel_updates_per_s": n_upd / best_map, "kernel_ms": map_kernels,
                "roofline": part_fraction(b_map, sum(map_kernels.values())),
                "wall_GBs": b_map / best_map / 1e9}
+    mapping["concurrent"] = concurrent_mapping(cv, torch, np, w, frames, Tws, ctx, subs, b_map, reps)
     large = sweep = None
     if not roofline_only:
         large = large_submap_esdf_bench(cv, torch, np, w, frames[:600], reps)
@@ -625,6 +626,60 @@ def mav_bench(cv, torch, np, reps=3, n_pairs=256, roofline_only=False):
             "build_s": t_build, "render_s": t_render, "mapping": mapping, "esdf_batch": esdf,
             "esdf_large_submap": large, "voxel_sweep": sweep, "align": align, "pose_graph": pose_graph,
             "learned": learned}
+
+
+def concurrent_mapping(cv, torch, np, w, frames, Tws, ctx0, subs0, b_map, reps, n_ctx=4):
+    """The same 3000 frames mapped from n_ctx contexts at once, each on a
+    stream of its own and driven by a host thread of its own (submap k on
+    context k mod n_ctx), as independent submaps may be built.  Wall time of
+    the whole mapping; the roofline fraction is the algorithmic bytes over
+    that wall time (the kernels of different streams overlap, so their sum
+    is no measure here).  Every submap's blocks, D and W equal those of the
+    single-context run."""
+    import concurrent.futures
+    per = w.submap_every
+    nsub = len(Tws)
+    ctxs = []
+    for _ in range(n_ctx):
+        c = cv.Context(voxel_size=w.voxel_size, trunc_vox=4, max_range=w.cam.max_range, d_max=w.d_max,
+                       block_capacity=65536)
+        c.set_stream(torch.cuda.Stream())
+        ctxs.append(c)
+    torch.cuda.synchronize()
+    subs = [ctxs[k % n_ctx].submap_create(Tws[k]) for k in range(nsub)]
+    pool = concurrent.futures.ThreadPoolExecutor(n_ctx)
+
+    def run(ci):
+        c = ctxs[ci]
+        for k in range(ci, nsub, n_ctx):
+            c.submap_reset(subs[k])
+            c.map_sequence(subs[k], frames[k * per:(k + 1) * per], w.cam.K, w.poses[k * per:(k + 1) * per],
+                           esdf_every=0)
+        c.sync()
+
+    def map_all():
+        list(pool.map(run, range(n_ctx)))
+
+    map_all()
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        map_all()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        best = dt if best is None else min(best, dt)
+    same = True
+    for k in range(nsub):
+        a, b = ctx0.export_blocks(subs0[k]), ctxs[k % n_ctx].export_blocks(subs[k])
+        same = same and all(np.array_equal(a[q], b[q]) for q in ("keys", "D", "W"))
+    assert same, "concurrent mapping differs from the single-context run"
+    pool.shutdown()
+    for c in ctxs:
+        c.close()
+    gbs = b_map / best / 1e9
+    return {"contexts": n_ctx, "frames_per_s": w.n_frames / best, "ms": best * 1e3, "wall_GBs": gbs,
+            "frac_wall": gbs / HBM_PEAK_GBS, "same_blocks_D_W": same}
 
 
 def _solve_counts(stats, np):
@@ -1434,6 +1489,9 @@ def summary_line(r):
     if "mapping" in mav:
         m = mav["mapping"]
         roof["outdoor_mapping"] = dict(m["roofline"], frames=m["frames"], frames_per_s=m["frames_per_s"])
+        if m.get("concurrent"):
+            roof["outdoor_mapping_concurrent"] = _pick(m["concurrent"], "contexts", "frames_per_s", "wall_GBs",
+                                                       "frac_wall")
     line["roofline"] = roof
     if "cpu_baseline" in r:
         line["cpu_baseline"] = r["cpu_baseline"]
