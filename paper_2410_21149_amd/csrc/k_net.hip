@@ -66,33 +66,45 @@ __global__ void k_to_bf16(const float *__restrict__ x, uint16_t *__restrict__ y,
         y[i] = f2bf(x[i]);
 }
 
-// One wave computes a 16 (positions) x 16 (output channels) tile; a
-// workgroup holds COUT / 16 waves over the same 16 positions.  MFMA operand
-// layout (16x16x16 bf16): lane l supplies A[m = l % 16][k = 4 (l / 16) + i]
-// and B[k = 4 (l / 16) + i][n = l % 16], i = 0..3, and receives
-// D[m = 4 (l / 16) + i][n = l % 16].
-template <int CIN, int COUT, int DIN, int DOUT, int STRIDE>
-__global__ __launch_bounds__(64 * (COUT / 16)) void k_conv_fwd(const uint16_t *__restrict__ x,
-                                                               const uint16_t *__restrict__ w,
-                                                               const float *__restrict__ bias,
-                                                               uint16_t *__restrict__ y, int64_t n_pos)
+// One wave computes a tile of 16 positions x 16 CT output channels: per K
+// chunk of 16 it loads its A fragment (the im2col row slice) once and runs
+// one MFMA per 16 output channels.  With CT = COUT / 16 a workgroup of 4
+// waves covers 64 positions; a layer with few positions takes CT = 1, so
+// that its waves split the output channels.  The K chunks are summed in
+// order for every output, whatever CT.  MFMA operand layout (16x16x16
+// bf16): lane l supplies A[m = l % 16][k = 4 (l / 16) + i] and B[k = 4 (l /
+// 16) + i][n = l % 16], i = 0..3, and receives D[m = 4 (l / 16) + i][n = l %
+// 16].
+template <int CIN, int COUT, int DIN, int DOUT, int STRIDE, int CT>
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ x, const uint16_t *__restrict__ w,
+                                                  const float *__restrict__ bias, uint16_t *__restrict__ y,
+                                                  int64_t n_pos)
 {
     constexpr int K = 27 * CIN;
-    constexpr int KC = (K + 15) / 16;  // K chunks
+    constexpr int KC = (K + 15) / 16;     // K chunks
+    constexpr int NCT = CT;               // output-channel tiles of this wave
+    constexpr int NG = COUT / (16 * CT);  // waves per position tile
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int co = wid * 16 + (lane & 15);  // this lane's B column / D column
-    const int kq = 4 * (lane >> 4);          // first of this lane's 4 k in a chunk
-    for (int64_t tile = blockIdx.x; tile * 16 < n_pos; tile += gridDim.x) {
+    const int kq = 4 * (lane >> 4);  // first of this lane's 4 k in a chunk
+    const int64_t n_items = (n_pos + 15) / 16 * NG;
+    for (int64_t item = (int64_t)blockIdx.x * 4 + wid; item < n_items; item += (int64_t)gridDim.x * 4) {
+        const int64_t tile = item / NG;
+        const int cg = (int)(item % NG);  // output channels cg 16 CT .. (cg + 1) 16 CT - 1
         // A row of this lane: output position tile * 16 + lane % 16
         const int64_t p = tile * 16 + (lane & 15);
         const bool pin = p < n_pos;
         const int64_t pp = pin ? p : 0;
         const int ox = (int)(pp % DOUT), oy = (int)((pp / DOUT) % DOUT), oz = (int)((pp / (DOUT * DOUT)) % DOUT);
         const int64_t nb = pp / ((int64_t)DOUT * DOUT * DOUT);
-        v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+        v4f32 acc[NCT];
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) acc[t] = (v4f32){0.f, 0.f, 0.f, 0.f};
         for (int c = 0; c < KC; ++c) {
             const int k0 = 16 * c + kq;  // 4 consecutive k: same kernel offset, channels ci..ci+3
-            v4i16 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+            v4i16 a = {0, 0, 0, 0};
+            v4i16 b[NCT];
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) b[t] = (v4i16){0, 0, 0, 0};
             if (k0 < K) {
                 const int off = k0 / CIN, ci = k0 % CIN;
                 const int kd = off / 9, kh = (off / 3) % 3, kw = off % 3;
@@ -101,17 +113,24 @@ __global__ __launch_bounds__(64 * (COUT / 16)) void k_conv_fwd(const uint16_t *_
                     const int64_t src = (((nb * DIN + iz) * DIN + iy) * DIN + ix) * CIN + ci;
                     a = *(const v4i16 *)(x + src);
                 }
-                b = *(const v4i16 *)(w + (int64_t)co * K + k0);
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-        }
-        const float bv = bias[co];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t q = tile * 16 + 4 * (lane >> 4) + i;
-            if (q < n_pos) {
-                const float v = fmaxf(acc[i] + bv, 0.0f);
-                y[q * COUT + co] = f2bf(v);
+                for (int t = 0; t < NCT; ++t)
+                    b[t] = *(const v4i16 *)(w + (int64_t)((cg * NCT + t) * 16 + (lane & 15)) * K + k0);
+            }
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+            const int co = (cg * NCT + t) * 16 + (lane & 15);
+            const float bv = bias[co];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t q = tile * 16 + 4 * (lane >> 4) + i;
+                if (q < n_pos) {
+                    const float v = fmaxf(acc[t][i] + bv, 0.0f);
+                    y[q * COUT + co] = f2bf(v);
+                }
             }
         }
     }
@@ -439,9 +458,12 @@ template <int L>
 static void launch_conv_fwd(covox_net *net, const uint16_t *x, uint16_t *y, int n)
 {
     constexpr ConvShape s = kShapes[L];
+    // the last layer (4^3 positions per item) splits its output channels over waves
+    constexpr int CT = s.dout >= 8 ? s.cout / 16 : 1;
     const int64_t npos = (int64_t)n * s.dout * s.dout * s.dout;
-    const unsigned grid = (unsigned)std::min<int64_t>((npos + 15) / 16, 1 << 20);
-    hipLaunchKernelGGL((k_conv_fwd<s.cin, s.cout, s.din, s.dout, s.stride>), dim3(grid), dim3(64 * (s.cout / 16)), 0,
+    const int64_t items = (npos + 15) / 16 * (s.cout / (16 * CT));
+    const unsigned grid = (unsigned)std::min<int64_t>((items + 3) / 4, 1 << 20);  // 4 waves per workgroup
+    hipLaunchKernelGGL((k_conv_fwd<s.cin, s.cout, s.din, s.dout, s.stride, CT>), dim3(grid), dim3(256), 0,
                        net->ctx->stream, x, net->wb[L], net->w + net->P.off_b[L], y, npos);
 }
 
