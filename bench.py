@@ -1101,7 +1101,8 @@ def learned_bench(cv, torch, np, n_items=1024, reps=3, min_distinct=256, seed0=4
     runs = {}
     out["tuning"] = ctx.autotune_align(items, 8)
     for name, fn in (("plain_8start", lambda: ctx.align_batch(items, 8)),
-                     ("learned_refine", lambda: ctx.align_learned(net, items, cell, c_thr, 8))):
+                     ("learned_refine", lambda: ctx.align_learned(net, items, cell, c_thr, 8)),
+                     ("learned_refine_rot4", lambda: ctx.align_learned(net, items, cell, c_thr, 8, n_rot=4))):
         fn()  # warm (buffers, registration points)
         best, res = None, None
         for _ in range(reps):
@@ -1118,13 +1119,19 @@ def learned_bench(cv, torch, np, n_items=1024, reps=3, min_distinct=256, seed0=4
         r["successes_5cm"] = int(round(r["success_5cm_0.5deg"] * n_items))
         r["aligned_per_s_1cm"] = r["pairs_per_s"] * r["success_1cm_0.1deg"]
         r["aligned_per_s_5cm"] = r["pairs_per_s"] * r["success_5cm_0.5deg"]
-        if name == "learned_refine":
+        if name.startswith("learned"):
             r["fallback_fraction"] = sum(1 for x in st if x["best_start"] >= 0) / n_items
         runs[name] = r
     out.update(runs)
-    Tp = ctx.propose(net, items, cell)
-    out["proposal_only_success_0.5m_10deg"] = _success(Tp, gts, np, 0.5, 10.0)
+    Tp = ctx.propose(net, items, cell, n_rot=4)
+    out["proposal_only_success_0.5m_10deg"] = _success(Tp[:, 0], gts, np, 0.5, 10.0)
+    out["proposal_any_of_4_turned_0.5m_10deg"] = float(np.mean(
+        [any(_success([Tp[i, k]], [gts[i]], np, 0.5, 10.0) > 0 for k in range(4)) for i in range(n_items)]))
     pl, le = runs["plain_8start"], runs["learned_refine"]
+    l4 = runs["learned_refine_rot4"]
+    for b in ("1cm", "5cm"):
+        out["ratio_rot4_aligned_per_s_" + b] = (l4["aligned_per_s_" + b] / pl["aligned_per_s_" + b]
+                                                if pl["aligned_per_s_" + b] > 0 else None)
     out["ratio_aligned_per_s_1cm"] = (le["aligned_per_s_1cm"] / pl["aligned_per_s_1cm"]
                                       if pl["aligned_per_s_1cm"] > 0 else None)
     out["ratio_aligned_per_s_5cm"] = (le["aligned_per_s_5cm"] / pl["aligned_per_s_5cm"]
@@ -1510,11 +1517,12 @@ def summary_line(r):
     if "learned" in mav and "plain_8start" in mav["learned"]:
         le = mav["learned"]
         line["learned"] = dict(_pick(le, "held_out_pairs", "distinct_pairs", "held_out_seeds", "ratio_aligned_per_s_1cm",
-                                     "ratio_aligned_per_s_5cm", "ratio_pairs_per_s",
-                                     "proposal_only_success_0.5m_10deg"),
+                                     "ratio_aligned_per_s_5cm", "ratio_rot4_aligned_per_s_1cm",
+                                     "ratio_rot4_aligned_per_s_5cm", "ratio_pairs_per_s",
+                                     "proposal_only_success_0.5m_10deg", "proposal_any_of_4_turned_0.5m_10deg"),
                                **{k: _pick(le[k], "pairs_per_s", "success_1cm_0.1deg", "success_5cm_0.5deg",
                                            "successes_1cm", "successes_5cm", "fallback_fraction")
-                                  for k in ("plain_8start", "learned_refine")})
+                                  for k in ("plain_8start", "learned_refine", "learned_refine_rot4") if k in le})
         line["learned"]["training"] = _pick(le.get("training", {}), "pairs_train", "scenes", "steps")
     if "precision" in r:
         line["precision"] = dict(r["precision"])

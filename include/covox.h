@@ -437,8 +437,14 @@ int covox_net_gradients(covox_net *net, const float *x_dev, const float *y_dev, 
  * A's registration points (T_A_grid = Trans(c_A)); B is summarised on the
  * same grid through the prior T_init (T_B_grid = T_init^-1 T_A_grid).  The
  * network's correction C = (t, Rz(yaw)) in grid coordinates gives the
- * proposal T_A_grid C T_A_grid^-1 T_init, refined by single-start alignment;
- * pairs whose refined cost exceeds cost_thr (or that are degenerate) fall
+ * proposal T_A_grid C T_A_grid^-1 T_init, refined by single-start alignment.
+ * With n_rot > 1 the network also sees the prior turned about the grid
+ * centre, T_k = T_A_grid Rz(2 pi k / n_rot) T_A_grid^-1 T_init (k = 0 ..
+ * n_rot - 1); each proposal is scored by the mean squared residual at the
+ * proposal itself (one evaluation, no update), and among the proposals with
+ * at least n_min residuals and at least half the largest count the least
+ * cost is refined (ties: smallest k).
+ * Pairs whose refined cost exceeds cost_thr (or that are degenerate) fall
  * back to n_starts-start alignment from T_init, and the refined proposal
  * competes with those starts under the multi-start selection rule (it wins
  * ties), so a fallback never returns a higher cost than the refined pose.
@@ -446,12 +452,16 @@ int covox_net_gradients(covox_net *net, const float *x_dev, const float *y_dev, 
  * chosen start.  A net whose context was destroyed is rejected (EINVAL), as
  * is a net of another context.  Synchronous. */
 int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell,
-                        double cost_thr, int32_t n_starts, double *T_out, double *cost, covox_align_stats *stats);
+                        double cost_thr, int32_t n_rot, int32_t n_starts, double *T_out, double *cost,
+                        covox_align_stats *stats);
 
-/* The network's proposal alone for n pairs (the first step of
- * covox_align_learned): T_prop = T_A_grid C T_A_grid^-1 T_init, host n x 16
- * doubles.  Synchronous. */
-int covox_propose(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell, double *T_prop);
+/* The network's proposals alone for n pairs (the first step of
+ * covox_align_learned): for each pair and k = 0 .. n_rot - 1 (1 <= n_rot <=
+ * 256), T_A_grid C_k T_A_grid^-1 T_k with T_k the prior turned by
+ * 2 pi k / n_rot about the grid centre; host n x n_rot x 16 doubles (pair
+ * major).  Synchronous. */
+int covox_propose(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell, int32_t n_rot,
+                  double *T_prop);
 
 /* Training on re-framings of ground-truth pairs.  Item b of step s draws
  * (SplitMix64 of seed and the counter s * batch + b) a pair j, a correction

@@ -147,9 +147,10 @@ _sig = {
     "covox_net_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, _fp]),
     "covox_net_gradients": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, _fp, _fp]),
     "covox_align_learned": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_double,
-                                           ctypes.c_double, ctypes.c_int32, _dp, _dp,
+                                           ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _dp, _dp,
                                            ctypes.POINTER(covox_align_stats)]),
-    "covox_propose": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_double, _dp]),
+    "covox_propose": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_pair), ctypes.c_int32, ctypes.c_double,
+                                     ctypes.c_int32, _dp]),
     "covox_train_proposal": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(covox_train_cfg), ctypes.POINTER(covox_pair),
                                             ctypes.c_int32, _fp]),
     "covox_graph_begin": (ctypes.c_int, [_vp]),
@@ -434,23 +435,26 @@ class Context:
             arr[i].channel = ch
         self._check(_lib.covox_summaries(self.handle, arr, len(reqs)), "summaries")
 
-    def align_learned(self, net: "Net", pairs, cell, cost_thr, n_starts=8):
+    def align_learned(self, net: "Net", pairs, cell, cost_thr, n_starts=8, n_rot=1):
         n = len(pairs)
         arr = self._pairs(pairs)
         T = np.zeros(16 * max(n, 1))
         cost = np.zeros(max(n, 1))
         st = (covox_align_stats * max(n, 1))()
-        self._check(_lib.covox_align_learned(self.handle, net.handle, arr, n, cell, cost_thr, n_starts, _p(T, _dp),
-                                             _p(cost, _dp), st), "align_learned")
+        self._check(_lib.covox_align_learned(self.handle, net.handle, arr, n, cell, cost_thr, n_rot, n_starts,
+                                             _p(T, _dp), _p(cost, _dp), st), "align_learned")
         return T.reshape(-1, 4, 4)[:n], cost[:n], [_stats(st[i]) for i in range(n)]
 
-    def propose(self, net: "Net", pairs, cell):
-        """The network's proposals (n x 4 x 4) for (A, B, T_init) pairs."""
+    def propose(self, net: "Net", pairs, cell, n_rot=1):
+        """The network's proposals for (A, B, T_init) pairs: n x 4 x 4, or
+        n x n_rot x 4 x 4 with the prior also turned by 2 pi k / n_rot about
+        the summary grid centre."""
         arr = self._pairs(pairs)
         n = len(pairs)
-        T = np.zeros(16 * max(n, 1))
-        self._check(_lib.covox_propose(self.handle, net.handle, arr, n, cell, _p(T, _dp)), "propose")
-        return T.reshape(-1, 4, 4)[:n]
+        T = np.zeros(16 * n_rot * max(n, 1))
+        self._check(_lib.covox_propose(self.handle, net.handle, arr, n, cell, n_rot, _p(T, _dp)), "propose")
+        T = T.reshape(-1, n_rot, 4, 4)[:n]
+        return T[:, 0] if n_rot == 1 else T
 
     def train_proposal(self, net: "Net", pairs, steps, batch=64, lr=1e-3, trans_scale=3.0, cell=1.0, trans_xy=3.0,
                        trans_z=0.5, yaw=math.pi, tilt=math.radians(2.0), seed=5):

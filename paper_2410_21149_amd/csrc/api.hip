@@ -1210,6 +1210,45 @@ int propose_chunk(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int m
 
 constexpr int kLearnChunk = 256;
 
+// The proposal of a pair to refine, from the sums at each proposal: among
+// those with at least n_min residuals and at least half the largest count,
+// the least cost (ties: smallest k); 0 when none qualifies.
+int pick_proposal(const AlignResult *r, int n, int n_min)
+{
+    int64_t nmax = 0;
+    for (int k = 0; k < n; ++k)
+        if (r[k].n_used >= n_min) nmax = std::max(nmax, r[k].n_used);
+    int best = -1;
+    for (int k = 0; k < n; ++k) {
+        if (r[k].n_used < n_min || 2 * r[k].n_used < nmax) continue;
+        if (best < 0 || r[k].cost < r[best].cost) best = k;
+    }
+    return best < 0 ? 0 : best;
+}
+
+// The pairs with their priors turned about the summary grid centre: item
+// j n_rot + k carries T_A_grid Rz(2 pi k / n_rot) T_A_grid^-1 T_init of pair
+// j (k = 0: the prior itself).
+std::vector<covox_pair> turned_pairs(const covox_pair *pairs, int m, int n_rot)
+{
+    std::vector<covox_pair> out((size_t)m * n_rot);
+    for (int j = 0; j < m; ++j)
+        for (int k = 0; k < n_rot; ++k) {
+            covox_pair &q = out[(size_t)j * n_rot + k];
+            q = pairs[j];
+            if (k == 0) continue;
+            const double a = 2.0 * M_PI * (double)k / (double)n_rot;
+            double G[16], Gi[16], R[16] = {cos(a), -sin(a), 0, 0, sin(a), cos(a), 0, 0, 0, 0, 1, 0, 0, 0, 0, 1}, M[16];
+            grid_of(pairs[j].A, G);
+            rigid_inverse_h(G, Gi);
+            mat_mul4(G, R, M);
+            mat_mul4(M, Gi, M);
+            mat_mul4(M, pairs[j].T_init_A_B, q.T_init_A_B);
+            q.T_init_A_B[12] = 0; q.T_init_A_B[13] = 0; q.T_init_A_B[14] = 0; q.T_init_A_B[15] = 1;
+        }
+    return out;
+}
+
 // Uniform draw in [0, 1) number k of item `item` (SplitMix64 of the seed
 // and a counter).
 double draw(uint64_t seed, uint64_t item, int k)
@@ -1220,16 +1259,21 @@ double draw(uint64_t seed, uint64_t item, int k)
 
 }  // namespace
 
-int covox_propose(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell, double *T_prop)
+int covox_propose(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell, int32_t n_rot,
+                  double *T_prop)
 {
     COVOX_NOT_DURING_CAPTURE(ctx, "propose");
-    if (!ctx || !net || net_ctx(net) != ctx || (!pairs && n > 0) || n < 0 || !(cell > 0) || (!T_prop && n > 0))
+    if (!ctx || !net || net_ctx(net) != ctx || (!pairs && n > 0) || n < 0 || !(cell > 0) || (!T_prop && n > 0) ||
+        n_rot < 1 || n_rot > kLearnChunk)
         return fail(ctx, COVOX_EINVAL, "propose: bad argument");
     int rc = prepare_learned(ctx, pairs, n, "propose");
     if (rc) return rc;
-    for (int i0 = 0; i0 < n; i0 += kLearnChunk)
-        if ((rc = propose_chunk(ctx, net, pairs + i0, std::min(kLearnChunk, n - i0), cell, T_prop + 16 * i0)))
-            return rc;
+    const int per = kLearnChunk / n_rot;
+    for (int i0 = 0; i0 < n; i0 += per) {
+        const int m = std::min(per, n - i0);
+        const std::vector<covox_pair> tp = turned_pairs(pairs + i0, m, n_rot);
+        if ((rc = propose_chunk(ctx, net, tp.data(), m * n_rot, cell, T_prop + (size_t)16 * n_rot * i0))) return rc;
+    }
     return COVOX_OK;
 }
 
@@ -1300,24 +1344,46 @@ int covox_train_proposal(covox_ctx *ctx, covox_net *net, const covox_train_cfg *
 }
 
 int covox_align_learned(covox_ctx *ctx, covox_net *net, const covox_pair *pairs, int32_t n, double cell,
-                        double cost_thr, int32_t n_starts, double *T_out, double *cost, covox_align_stats *stats)
+                        double cost_thr, int32_t n_rot, int32_t n_starts, double *T_out, double *cost,
+                        covox_align_stats *stats)
 {
     COVOX_NOT_DURING_CAPTURE(ctx, "align_learned");
     if (!ctx || !net || net_ctx(net) != ctx || (!pairs && n > 0) || n < 0 || !(cell > 0) || n_starts < 1 || !T_out ||
-        !cost)
+        !cost || n_rot < 1 || n_rot > kLearnChunk || (int64_t)n * n_rot > INT32_MAX / 2)
         return fail(ctx, COVOX_EINVAL, "align_learned: bad argument");
     int rc = prepare_learned(ctx, pairs, n, "align_learned");
     if (rc) return rc;
-    std::vector<AlignResult> res(n);
-    std::vector<double> Tp((size_t)16 * std::min(n, kLearnChunk));
-    for (int i0 = 0; i0 < n; i0 += kLearnChunk) {
-        const int m = std::min(kLearnChunk, n - i0);
-        if ((rc = propose_chunk(ctx, net, pairs + i0, m, cell, Tp.data()))) return rc;
-        std::vector<AlignProblem> prs(m);
-        for (int k = 0; k < m; ++k)
-            prs[k] = make_problem(ctx, pairs[i0 + k].A, pairs[i0 + k].B, &Tp[16 * k], ctx->p.max_iter);
-        if ((rc = run_alignment(ctx, prs.data(), m, res.data() + i0))) return rc;
+    // proposals in chunks of at most kLearnChunk network items, then one
+    // alignment launch for all of them (the launch lasts as long as its
+    // slowest problem, so fewer, larger launches finish sooner)
+    const int per = kLearnChunk / n_rot;
+    const int nq = n * n_rot;
+    std::vector<double> Tp((size_t)16 * nq);
+    std::vector<covox_pair> tp((size_t)nq);
+    for (int i0 = 0; i0 < n; i0 += per) {
+        const int m = std::min(per, n - i0);
+        const std::vector<covox_pair> t = turned_pairs(pairs + i0, m, n_rot);
+        std::copy(t.begin(), t.end(), tp.begin() + (size_t)i0 * n_rot);
+        if ((rc = propose_chunk(ctx, net, t.data(), m * n_rot, cell, &Tp[(size_t)16 * n_rot * i0]))) return rc;
     }
+    // with turned priors, each proposal is scored by the cost at the
+    // proposal itself (sums at the start pose, no update) and only the best
+    // one is refined
+    std::vector<int> pick(n, 0);
+    if (n_rot > 1) {
+        std::vector<AlignProblem> ev(nq);
+        for (int q = 0; q < nq; ++q) ev[q] = make_problem(ctx, tp[q].A, tp[q].B, &Tp[16 * (size_t)q], 0);
+        std::vector<AlignResult> r0(nq);
+        if ((rc = run_alignment(ctx, ev.data(), nq, r0.data()))) return rc;
+        for (int j = 0; j < n; ++j) pick[j] = pick_proposal(&r0[(size_t)j * n_rot], n_rot, ctx->p.n_min);
+    }
+    std::vector<AlignProblem> rp(n);
+    for (int j = 0; j < n; ++j) {
+        const size_t q = (size_t)j * n_rot + pick[j];
+        rp[j] = make_problem(ctx, tp[q].A, tp[q].B, &Tp[16 * q], ctx->p.max_iter);
+    }
+    std::vector<AlignResult> res(n);
+    if ((rc = run_alignment(ctx, rp.data(), n, res.data()))) return rc;
     // fallback to multi-start from the prior
     std::vector<int> fb;
     for (int i = 0; i < n; ++i)

@@ -7,12 +7,15 @@ Bars: summary values within 2e-5 (binary32 vs binary64 trilinear weights;
 values are phi / d_max in [-1, 1]) and masks equal except at cells whose
 sample lies within 1e-4 voxel of a voxel-centre plane (the binary32 map
 position can then select the neighbouring corner set); network outputs within
-2 % of the output scale (bf16 storage of every activation: a one-ulp
-difference in the accumulation order can flip a bf16 rounding, 2^-8 relative,
-and such flips compound over four layers); gradients within 3 % relative L2
-per layer against binary64 backpropagation through the oracle's bf16 forward
-pass.  The driver with a zero cost threshold must give exactly what plain
-multi-start gives (every pair falls back)."""
+1e-3 of the output scale (the oracle rounds activations and weights to bf16
+as the kernels do; a one-ulp difference in the accumulation order can still
+flip a bf16 rounding, 2^-8 relative, so the bar sits well above the FP32
+against binary64 summation difference); gradients within 1e-2 relative L2
+per tensor against binary64 backpropagation through the oracle's bf16
+forward pass (the kernels round the upstream gradient to bf16 for the matrix
+cores).  The driver with a zero cost threshold must give exactly what plain
+multi-start gives (every pair falls back); with turned priors it refines the
+proposal of least cost at the proposal."""
 import math
 
 import numpy as np
@@ -256,6 +259,36 @@ def test_propose_then_refine_equals_driver(cv):
     Tl, cl, sl = ctx.align_learned(net, pairs, 0.1, math.inf)
     Tr, cr, sr = ctx.align_batch([(a, b, Tp[k]) for k, (a, b, _) in enumerate(pairs)], n_starts=1)
     assert np.array_equal(Tl, Tr) and np.array_equal(cl, cr)
+    ctx.close()
+
+
+def test_turned_priors_pick_then_refine(cv):
+    """n_rot = 4: the prior turned by 0, 90, 180 and 270 degrees about the
+    summary grid centre gives four proposals (the first that of the prior
+    itself); with an infinite threshold the driver refines the proposal of
+    least cost at the proposal (residual counts of at least n_min and half
+    the largest), as calls of the parts in turn give it."""
+    ctx = _ctx(cv)
+    A, B, _, _ = _tiny_submaps(cv, ctx, with_oracle=False)
+    net = cv.Net(ctx, seed=4)
+    pairs = [(A, B, orc.se3_exp(np.array([0.03, -0.02, 0.0, 0.0, 0.0, 0.3]))),
+             (B, A, orc.se3_exp(np.array([-0.02, 0.01, 0.01, 0.0, 0.0, -2.2])))]
+    P4 = ctx.propose(net, pairs, 0.1, n_rot=4)
+    assert P4.shape == (2, 4, 4, 4)
+    assert np.array_equal(P4[:, 0], ctx.propose(net, pairs, 0.1))
+    Tl, cl, sl = ctx.align_learned(net, pairs, 0.1, math.inf, n_rot=4)
+    for i, (a, b, _) in enumerate(pairs):
+        ctx.set_params(max_iter=0)  # the cost at each proposal, no update
+        _, c0, s0 = ctx.align_batch([(a, b, P4[i, k]) for k in range(4)], n_starts=1)
+        ctx.set_params(max_iter=30)
+        ok = [s["n_used"] >= 100 for s in s0]
+        nmax = max([s["n_used"] for s, o in zip(s0, ok) if o], default=0)
+        cand = [k for k in range(4) if ok[k] and 2 * s0[k]["n_used"] >= nmax]
+        best = min(cand, key=lambda k: (c0[k], k)) if cand else 0
+        Tr, cr, sr = ctx.align_batch([(a, b, P4[i, best])], n_starts=1)
+        assert np.array_equal(Tl[i], Tr[0]) and cl[i] == cr[0], (i, best)
+    with pytest.raises(cv.CovoxError):
+        ctx.align_learned(net, pairs, 0.1, math.inf, n_rot=0)
     ctx.close()
 
 
