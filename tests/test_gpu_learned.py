@@ -289,6 +289,20 @@ def test_turned_priors_pick_then_refine(cv):
         assert np.array_equal(Tl[i], Tr[0]) and cl[i] == cr[0], (i, best)
     with pytest.raises(cv.CovoxError):
         ctx.align_learned(net, pairs, 0.1, math.inf, n_rot=0)
+    # 70 items cross the 64-pair chunk of four turned priors: one call equals
+    # two calls on parts of the list (every item stands alone)
+    rng = np.random.default_rng(5)
+    many = [(A, B, orc.se3_exp(np.concatenate([rng.uniform(-0.05, 0.05, 3), [0, 0], rng.uniform(-3, 3, 1)])))
+            if k % 2 == 0 else (B, A, orc.se3_exp(np.concatenate([rng.uniform(-0.05, 0.05, 3), [0, 0],
+                                                                   rng.uniform(-3, 3, 1)])))
+            for k in range(70)]
+    Pm = ctx.propose(net, many, 0.1, n_rot=4)
+    assert np.array_equal(Pm, np.concatenate([ctx.propose(net, many[:30], 0.1, n_rot=4),
+                                              ctx.propose(net, many[30:], 0.1, n_rot=4)]))
+    Tm, cm, _ = ctx.align_learned(net, many, 0.1, 0.01, n_rot=4)
+    T1, c1, _ = ctx.align_learned(net, many[:30], 0.1, 0.01, n_rot=4)
+    T2, c2, _ = ctx.align_learned(net, many[30:], 0.1, 0.01, n_rot=4)
+    assert np.array_equal(Tm, np.concatenate([T1, T2])) and np.array_equal(cm, np.concatenate([c1, c2]))
     ctx.close()
 
 
