@@ -1102,7 +1102,9 @@ def learned_bench(cv, torch, np, n_items=1024, reps=3, min_distinct=256, seed0=4
     out["tuning"] = ctx.autotune_align(items, 8)
     for name, fn in (("plain_8start", lambda: ctx.align_batch(items, 8)),
                      ("learned_refine", lambda: ctx.align_learned(net, items, cell, c_thr, 8)),
-                     ("learned_refine_rot4", lambda: ctx.align_learned(net, items, cell, c_thr, 8, n_rot=4))):
+                     ("learned_refine_rot4", lambda: ctx.align_learned(net, items, cell, c_thr, 8, n_rot=4)),
+                     ("learned_rot4_no_fallback",
+                      lambda: ctx.align_learned(net, items, cell, math.inf, 8, n_rot=4))):
         fn()  # warm (buffers, registration points)
         best, res = None, None
         for _ in range(reps):
@@ -1128,10 +1130,11 @@ def learned_bench(cv, torch, np, n_items=1024, reps=3, min_distinct=256, seed0=4
     out["proposal_any_of_4_turned_0.5m_10deg"] = float(np.mean(
         [any(_success([Tp[i, k]], [gts[i]], np, 0.5, 10.0) > 0 for k in range(4)) for i in range(n_items)]))
     pl, le = runs["plain_8start"], runs["learned_refine"]
-    l4 = runs["learned_refine_rot4"]
-    for b in ("1cm", "5cm"):
-        out["ratio_rot4_aligned_per_s_" + b] = (l4["aligned_per_s_" + b] / pl["aligned_per_s_" + b]
-                                                if pl["aligned_per_s_" + b] > 0 else None)
+    for name, key in (("learned_refine_rot4", "rot4"), ("learned_rot4_no_fallback", "rot4_no_fallback")):
+        l4 = runs[name]
+        for b in ("1cm", "5cm"):
+            out["ratio_%s_aligned_per_s_%s" % (key, b)] = (l4["aligned_per_s_" + b] / pl["aligned_per_s_" + b]
+                                                          if pl["aligned_per_s_" + b] > 0 else None)
     out["ratio_aligned_per_s_1cm"] = (le["aligned_per_s_1cm"] / pl["aligned_per_s_1cm"]
                                       if pl["aligned_per_s_1cm"] > 0 else None)
     out["ratio_aligned_per_s_5cm"] = (le["aligned_per_s_5cm"] / pl["aligned_per_s_5cm"]
@@ -1518,11 +1521,13 @@ def summary_line(r):
         le = mav["learned"]
         line["learned"] = dict(_pick(le, "held_out_pairs", "distinct_pairs", "held_out_seeds", "ratio_aligned_per_s_1cm",
                                      "ratio_aligned_per_s_5cm", "ratio_rot4_aligned_per_s_1cm",
-                                     "ratio_rot4_aligned_per_s_5cm", "ratio_pairs_per_s",
+                                     "ratio_rot4_aligned_per_s_5cm", "ratio_rot4_no_fallback_aligned_per_s_1cm",
+                                     "ratio_rot4_no_fallback_aligned_per_s_5cm", "ratio_pairs_per_s",
                                      "proposal_only_success_0.5m_10deg", "proposal_any_of_4_turned_0.5m_10deg"),
                                **{k: _pick(le[k], "pairs_per_s", "success_1cm_0.1deg", "success_5cm_0.5deg",
                                            "successes_1cm", "successes_5cm", "fallback_fraction")
-                                  for k in ("plain_8start", "learned_refine", "learned_refine_rot4") if k in le})
+                                  for k in ("plain_8start", "learned_refine", "learned_refine_rot4",
+                                            "learned_rot4_no_fallback") if k in le})
         line["learned"]["training"] = _pick(le.get("training", {}), "pairs_train", "scenes", "steps")
     if "precision" in r:
         line["precision"] = dict(r["precision"])
