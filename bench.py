@@ -14,8 +14,7 @@ with --no-graph).  value = frames per second of the faster of the two
 config.eager_frames_per_s and config.graph_replay_frames_per_s give both.
 
 Also reported on the same JSON line (every figure, with more, is also in the
-full record printed to stderr and, when gpurun_out/ exists, written to
-gpurun_out/bench_detail.json):
+full record printed to stderr and, with --detail-out PATH, written to PATH):
   roofline      the dominant kernel: the algorithmic bytes of the unit its
                 launch belongs to (B_esdf per ESDF update, B_int per frame)
                 divided by its mean duration from HIP events recorded around
@@ -1243,6 +1242,7 @@ def main():
     ap.add_argument("--no-wavefront", action="store_true", help="skip the exact / wavefront ESDF comparison")
     ap.add_argument("--no-hash", action="store_true", help="skip the hash-table stress test")
     ap.add_argument("--no-copy", action="store_true", help="skip the stream-copy bandwidth measurement")
+    ap.add_argument("--detail-out", default=None, help="also write the full record (JSON) to this file")
     ap.add_argument("--no-precision", action="store_true", help="skip the error statement against the binary64 oracle")
     ap.add_argument("--cfg4-align", action="store_true",
                     help="only the batched alignment of outdoor pairs from several scenes (several minutes of "
@@ -1473,8 +1473,8 @@ def main():
     ctx.close()
     detail = json.dumps(result)
     _log("bench detail: " + detail)
-    if os.path.isdir(os.path.join(ROOT, "gpurun_out")):
-        with open(os.path.join(ROOT, "gpurun_out", "bench_detail.json"), "w") as fh:
+    if args.detail_out:
+        with open(args.detail_out, "w") as fh:
             fh.write(detail + "\n")
     print(json.dumps(summary_line(result)), flush=True)
 
