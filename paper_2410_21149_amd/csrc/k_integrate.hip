@@ -84,6 +84,45 @@ __device__ __forceinline__ uint32_t proj_column(const FrameArgs &f, float vs, fl
     return okm;
 }
 
+// The nearest pixel of the voxel centre (cx, cy, cz) and its camera depth
+// pz, by the arithmetic of proj_column (kept written out there, where the
+// compiler schedules the eight voxels of a lane together); -1 when the
+// centre is behind the camera or projects outside the image.
+__device__ __forceinline__ int64_t proj_pixel(const FrameArgs &f, float cx, float cy, float cz, float &pz)
+{
+    const float px = ((f.R[0] * cx + f.R[1] * cy) + f.R[2] * cz) + f.t[0];
+    const float py = ((f.R[3] * cx + f.R[4] * cy) + f.R[5] * cz) + f.t[1];
+    pz = ((f.R[6] * cx + f.R[7] * cy) + f.R[8] * cz) + f.t[2];
+    if (pz > 0.0f) {
+        const float u = ((f.K[0] * px) / pz) + f.K[2];
+        const float v = ((f.K[1] * py) / pz) + f.K[3];
+        const float uf = floorf(u + 0.5f);
+        const float vf = floorf(v + 0.5f);
+        if (uf >= 0.0f && uf < (float)f.W && vf >= 0.0f && vf < (float)f.H) return (int64_t)(int)vf * f.W + (int)uf;
+    }
+    return -1;
+}
+
+// Whether some voxel (ix, iy, iz0 + z), Z0 <= z < Z1, of the lane passes the
+// validity test of proj_column (same arithmetic; the weights are not needed).
+template <int Z0, int Z1>
+__device__ __forceinline__ bool proj_any(const FrameArgs &f, float vs, float tau, float maxr, int ix, int iy, int iz0)
+{
+    const float cx = ((float)ix + 0.5f) * vs;
+    const float cy = ((float)iy + 0.5f) * vs;
+    float pzv[Z1 - Z0];
+    int64_t pix[Z1 - Z0];
+#pragma unroll
+    for (int z = Z0; z < Z1; ++z) pix[z - Z0] = proj_pixel(f, cx, cy, ((float)(iz0 + z) + 0.5f) * vs, pzv[z - Z0]);
+    float d[Z1 - Z0];
+#pragma unroll
+    for (int k = 0; k < Z1 - Z0; ++k) d[k] = f.depth[pix[k] >= 0 ? pix[k] : 0];  // pixel 0 stands in, unused
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < Z1 - Z0; ++k) any |= pix[k] >= 0 && d[k] > 0.0f && d[k] <= maxr && d[k] - pzv[k] >= -tau;
+    return any;
+}
+
 // False only if no voxel centre of block (bx, by, bz) can pass the validity
 // test in this frame: the sphere holding the centres lies behind the
 // camera, beyond the far limit, or outside a side plane of the image.
@@ -419,7 +458,9 @@ __global__ __launch_bounds__(256) void k_probe_batch(const FrameArgs *__restrict
         const int fi = (int)(item / per_frame);
         const FrameArgs f = frames[fi];
         const int64_t n_box = (int64_t)f.bdim[0] * f.bdim[1] * f.bdim[2];
-        const int64_t j = (item % per_frame) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        // the wave index is read through the scalar unit, so that the box
+        // coordinates of the wave's block are scalar arithmetic
+        const int64_t j = (item % per_frame) * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         if (j >= n_box) continue;  // uniform across the wave
         int bx, by, bz;
         box_block(f, j, bx, by, bz);
@@ -427,9 +468,11 @@ __global__ __launch_bounds__(256) void k_probe_batch(const FrameArgs *__restrict
         if (block_may_be_visible(f, vs, bx, by, bz)) {  // uniform across the wave
             const int ix = 8 * bx + (lane & 7);
             const int iy = 8 * by + (lane >> 3);
-            float sdf[8], w[8];
-            const bool any = proj_column(f, vs, tau, maxr, ix, iy, 8 * bz, sdf, w) != 0;
-            const uint64_t m = __ballot(any);
+            // only whether some voxel is valid matters here: the bottom row
+            // of 64 voxels first, which decides a block of free space or at
+            // the surface; the other seven rows only when it has none
+            uint64_t m = __ballot(proj_any<0, 1>(f, vs, tau, maxr, ix, iy, 8 * bz));
+            if (m == 0) m = __ballot(proj_any<1, 8>(f, vs, tau, maxr, ix, iy, 8 * bz));
             if (lane == 0 && m) {
                 const int64_t idx = hash_find(tkeys, tvals, tmask, pack_key(bx, by, bz));
                 out = idx >= 0 ? (uint32_t)idx + 1u : kNew;
