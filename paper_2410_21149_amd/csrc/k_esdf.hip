@@ -321,21 +321,34 @@ __global__ __launch_bounds__(256) void k_page_sites(const JobList<NJ> jl, int C,
     }
 }
 
-// Distance to the nearest set bit of the 128-bit mask (lo, hi) from bit p.
-__device__ __forceinline__ int nearest_bit(uint64_t lo, uint64_t hi, int p)
+// The x distances of the 8 voxels of one x-line of a block, as 8 bytes:
+// byte x is the distance from bit 8 HB + x of the 128-bit site window
+// (lo, hi) to its nearest set bit, or 255 when that exceeds R or the window
+// has none.  The window holds the 2 HB + 1 blocks' bytes of the line (the
+// own block's byte at bit 8 HB, in lo since HB <= 7; zero above).  The
+// nearest sites below and above the own byte are found once per line, and
+// each voxel then looks only inside its own byte.
+__device__ __forceinline__ uint64_t line_dists(uint64_t lo, uint64_t hi, int HB, int R)
 {
-    uint64_t rlo, rhi;
-    if (p == 0) { rlo = lo; rhi = hi; }
-    else if (p < 64) { rlo = (lo >> p) | (hi << (64 - p)); rhi = hi >> p; }
-    else { rlo = hi >> (p - 64); rhi = 0; }
-    const int dr = rlo ? __ffsll((long long)rlo) - 1 : (rhi ? 63 + __ffsll((long long)rhi) : 1000);
-    const int s = 127 - p;
-    uint64_t llo, lhi;
-    if (s == 0) { llo = lo; lhi = hi; }
-    else if (s < 64) { lhi = (hi << s) | (lo >> (64 - s)); llo = lo << s; }
-    else { lhi = lo << (s - 64); llo = 0; }
-    const int dl = lhi ? __clzll((long long)lhi) : (llo ? 64 + __clzll((long long)llo) : 1000);
-    return min(dl, dr);
+    constexpr int kNone = 1000;
+    const int p0 = 8 * HB;
+    const uint32_t b = (uint32_t)(lo >> p0) & 0xFFu;
+    const uint64_t below = lo & ((1ull << p0) - 1ull);  // p0 <= 56
+    const int dl0 = below ? p0 - (63 - __clzll((long long)below)) : kNone;  // from bit p0 down
+    const uint64_t above = p0 + 8 < 64 ? lo >> (p0 + 8) : 0ull;
+    const int dr7 = above ? __ffsll((long long)above)                        // from bit p0 + 7 up
+                          : (hi ? 64 - (p0 + 7) + (__ffsll((long long)hi) - 1) : kNone);
+    uint64_t out = 0;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const uint32_t ml = b & ((2u << x) - 1u);  // own sites at or below x
+        const uint32_t mr = b >> x;                // own sites at or above x
+        const int dl = ml ? x - (31 - __clz((int)ml)) : x + dl0;
+        const int dr = mr ? __ffs((int)mr) - 1 : (7 - x) + dr7;
+        const int d = min(dl, dr);
+        out |= (uint64_t)(d <= R ? d : 255) << (8 * x);
+    }
+    return out;
 }
 
 // ------------------------------------------------------------------------
@@ -392,13 +405,7 @@ __global__ __launch_bounds__(256) void k_edt_x(const JobList<NJ> jl, const uint6
             if (pos < 64) lo |= byte << pos;
             else hi |= byte << (pos - 64);
         }
-        uint64_t out = 0;
-#pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            const int dist = nearest_bit(lo, hi, 8 * HB + x);
-            out |= (uint64_t)(dist <= R ? dist : 255) << (8 * x);
-        }
-        *(uint64_t *)(g1 + g * 512 + 8 * lane) = out;
+        *(uint64_t *)(g1 + g * 512 + 8 * lane) = line_dists(lo, hi, HB, R);
     }
 }
 
@@ -695,12 +702,7 @@ __global__ __launch_bounds__(256) void k_edt_xy(const JobList<NJ> jl, int Sseg, 
                         if (pos < 64) lo |= byte << pos;
                         else hi |= byte << (pos - 64);
                     }
-                    out = 0;
-#pragma unroll
-                    for (int xx = 0; xx < 8; ++xx) {
-                        const int dist = nearest_bit(lo, hi, 8 * HB + xx);
-                        out |= (uint64_t)(dist <= R ? dist : 255) << (8 * xx);
-                    }
+                    out = line_dists(lo, hi, HB, R);
                 }
                 uint8_t *dst = colb + 8 * zr * colB + 4 + 8 * i + yr;
 #pragma unroll
