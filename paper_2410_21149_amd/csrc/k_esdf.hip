@@ -359,7 +359,13 @@ __device__ __forceinline__ uint64_t line_dists(uint64_t lo, uint64_t hi, int HB,
 // distance to the nearest site rather than the line length, which suits
 // small domains where per-line envelopes leave the GPU idle.
 
-__device__ __forceinline__ int sq8(uint8_t v) { return v == 255 ? kBig : (int)v * (int)v; }
+// The y passes' candidates g1^2 + e^2 without the test for 255 (no site
+// within R along x): 255 squares to 65025, above every candidate from a real
+// distance (at most 2 R^2), so the minimum is the same wherever it is at most
+// R^2 (the only values written), and a search still never ends early while
+// a voxel has no real candidate (the exit needs e^2 >= its best, e <= R).
+static_assert(2 * (8 * kMaxHalo) * (8 * kMaxHalo) < 255 * 255, "255 must square above every real candidate");
+__device__ __forceinline__ int cand8(uint32_t byte, int ee) { return (int)(byte * byte) + ee; }
 
 constexpr int kScanStep = 8;  // offsets per exit test of the windowed y and z passes
 // 32-bit words a lane stages into LDS per block in the z pass (512 lanes,
@@ -467,7 +473,7 @@ __global__ __launch_bounds__(256) void k_edt_y_col(const JobList<NJ> jl, const u
             }
         }
         __syncthreads();
-        int b0 = sq8(colb[c0 * kColBytes + 4 + Y]), b1 = sq8(colb[c1 * kColBytes + 4 + Y]);
+        int b0 = cand8(colb[c0 * kColBytes + 4 + Y], 0), b1 = cand8(colb[c1 * kColBytes + 4 + Y], 0);
         // sliding dword windows per direction and voxel
         uint32_t dhi0 = cw0[dn + 1], dhi1 = cw1[dn + 1];  // "-": the dword above the next one
         uint32_t ulo0 = cw0[up], ulo1 = cw1[up];          // "+": the dword below the next one
@@ -488,8 +494,8 @@ __global__ __launch_bounds__(256) void k_edt_y_col(const JobList<NJ> jl, const u
                     const int e = 4 * m + 1 + k;  // byte 3 - k going down, byte k going up
                     if (e <= R) {
                         const int ee = e * e;
-                        b0 = min(b0, min(sq8((uint8_t)(dv0 >> (8 * (3 - k)))), sq8((uint8_t)(uv0 >> (8 * k)))) + ee);
-                        b1 = min(b1, min(sq8((uint8_t)(dv1 >> (8 * (3 - k)))), sq8((uint8_t)(uv1 >> (8 * k)))) + ee);
+                        b0 = min(b0, min(cand8((dv0 >> (8 * (3 - k))) & 0xFFu, ee), cand8((uv0 >> (8 * k)) & 0xFFu, ee)));
+                        b1 = min(b1, min(cand8((dv1 >> (8 * (3 - k))) & 0xFFu, ee), cand8((uv1 >> (8 * k)) & 0xFFu, ee)));
                     }
                 }
             }
@@ -718,7 +724,7 @@ __global__ __launch_bounds__(256) void k_edt_xy(const JobList<NJ> jl, int Sseg, 
                 // at byte Y & 3; rows Y + 4m + 1 .. Y + 4m + 4 in dword ((Y + 5) >> 2) + m
                 // at byte (Y + 5) & 3
                 const int dn = Y >> 2, sdn = Y & 3, up = (Y + 5) >> 2, sup = (Y + 5) & 3;
-                int b0 = sq8(colb[c0 * colB + 4 + Y]), b1 = sq8(colb[c1 * colB + 4 + Y]);
+                int b0 = cand8(colb[c0 * colB + 4 + Y], 0), b1 = cand8(colb[c1 * colB + 4 + Y], 0);
                 uint32_t dhi0 = cw0[dn + 1], dhi1 = cw1[dn + 1];
                 uint32_t ulo0 = cw0[up], ulo1 = cw1[up];
                 for (int dd = 1, m = 0; dd <= R; dd += 8) {
@@ -738,8 +744,8 @@ __global__ __launch_bounds__(256) void k_edt_xy(const JobList<NJ> jl, int Sseg, 
                             const int e = 4 * m + 1 + k;
                             if (e <= R) {
                                 const int ee = e * e;
-                                b0 = min(b0, min(sq8((uint8_t)(dv0 >> (8 * (3 - k)))), sq8((uint8_t)(uv0 >> (8 * k)))) + ee);
-                                b1 = min(b1, min(sq8((uint8_t)(dv1 >> (8 * (3 - k)))), sq8((uint8_t)(uv1 >> (8 * k)))) + ee);
+                                b0 = min(b0, min(cand8((dv0 >> (8 * (3 - k))) & 0xFFu, ee), cand8((uv0 >> (8 * k)) & 0xFFu, ee)));
+                                b1 = min(b1, min(cand8((dv1 >> (8 * (3 - k))) & 0xFFu, ee), cand8((uv1 >> (8 * k)) & 0xFFu, ee)));
                             }
                         }
                     }
