@@ -372,7 +372,11 @@ constexpr int kScanStep = 8;  // offsets per exit test of the windowed y and z p
 // 2 HB + 1 blocks of 256 words)
 constexpr int kStageZ = ((2 * kMaxHalo + 1) * 256 + 511) / 512;
 
-__device__ __forceinline__ int inf16(uint16_t v) { return v == 0xFFFF ? kBig : (int)v; }
+// The z passes' candidates g2 + e^2, likewise without the test for 0xFFFF
+// (no site within R in the xy plane): 65535 lies above every candidate from
+// a real value (g2 <= R^2, so at most 2 R^2), so phi (which takes R^2 as the
+// limit) and the exits (e^2 >= best, e <= R) are unchanged.
+__device__ __forceinline__ int cand16(uint16_t v, int ee) { return (int)v + ee; }
 
 // x pass: one wave per dense block, lane = (y, z) line of the block.  The
 // lane gathers byte y of site word z from the 2 HB + 1 blocks along x into a
@@ -559,13 +563,13 @@ __global__ __launch_bounds__(512) void k_edt_z_vox(const JobList<NJ> jl, const u
         if (__builtin_isinf(seed)) {
             const int base = tid & 63;
             auto at = [&](int zz) { return col[(zz >> 3) * 512 + base + 64 * (zz & 7)]; };
-            int best = inf16(at(Z));
+            int best = cand16(at(Z), 0);
             for (int dd = 1; dd <= R; dd += kScanStep) {  // as in the y pass
                 if (dd * dd >= best) break;
 #pragma unroll
                 for (int q = 0; q < kScanStep; ++q) {
                     const int e = dd + q;
-                    if (e <= R) best = min(best, min(inf16(at(Z - e)), inf16(at(Z + e))) + e * e);
+                    if (e <= R) best = min(best, min(cand16(at(Z - e), e * e), cand16(at(Z + e), e * e)));
                 }
             }
             out = phi_value(seed, best, R2, vs, dmax);
@@ -818,13 +822,13 @@ __global__ __launch_bounds__(512) void k_edt_z_col(const JobList<NJ> jl, int Sse
                 if (__builtin_isinf(seed)) {
                     const int Z = 8 * (HB + io) + (tid >> 6);
                     auto at = [&](int zz) { return col[(zz >> 3) * 512 + base + 64 * (zz & 7)]; };
-                    int best = inf16(at(Z));
+                    int best = cand16(at(Z), 0);
                     for (int dd = 1; dd <= R; dd += kScanStep) {  // as in k_edt_z_vox
                         if (dd * dd >= best) break;
 #pragma unroll
                         for (int q = 0; q < kScanStep; ++q) {
                             const int e = dd + q;
-                            if (e <= R) best = min(best, min(inf16(at(Z - e)), inf16(at(Z + e))) + e * e);
+                            if (e <= R) best = min(best, min(cand16(at(Z - e), e * e), cand16(at(Z + e), e * e)));
                         }
                     }
                     out = phi_value(seed, best, R2, vs, dmax);
