@@ -471,6 +471,36 @@ def test_column_passes_parity(cv, workload):
     ctx.close()
 
 
+@pytest.mark.parametrize("R", [5, 56])
+def test_esdf_radius_extremes_parity(cv, R):
+    """The exact ESDF at the smallest halo (R = 5 voxels: one halo block) and
+    the largest radius the passes support (R = 56: seven halo blocks, the
+    site window's full 128 bits, squared candidates up to 2 R^2 = 6272), in
+    every pass shape: voxel-parallel windows, per-line envelopes and column
+    passes.  phi must equal the oracle's bit for bit."""
+    import torch
+    w = sg.tiny()
+    fr = w.frames()
+    d_max = R * 0.05
+    ctx = _ctx(cv, d_max=d_max)
+    s = ctx.submap_create()
+    ctx.integrate_depth_batch(s, torch.from_numpy(fr).cuda(), w.cam.K, w.poses)
+    ref = orc.Submap(_oracle_params(d_max=d_max))
+    for f in range(w.n_frames):
+        ref.integrate(fr[f], w.cam.K, w.poses[f])
+    ref.update_esdf()
+    want = ref.export()
+    big = 2 ** 62
+    shapes = {"windows": dict(edt_col_seg=0, edt_y_env_min_cols=big, edt_z_env_min_cols=big),
+              "envelopes": dict(edt_col_seg=0, edt_y_env_min_cols=0, edt_z_env_min_cols=0),
+              "columns": dict(edt_col_seg=2, edt_y_env_min_cols=big, edt_z_env_min_cols=big)}
+    for name, tuning in shapes.items():
+        ctx.set_tuning(esdf_full_recompute=1, **tuning)
+        ctx.update_esdf(s)
+        assert _compare_phi(ctx.export_blocks(s), want) == 0, name
+    ctx.close()
+
+
 def test_outdoor_submap_parity_and_batched_esdf(cv):
     """An outdoor submap at the large-scale configuration (0.1 m voxels,
     10 m range, ESDF to 3 m) against the oracle, and the batched ESDF of
